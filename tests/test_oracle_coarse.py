@@ -1,0 +1,88 @@
+"""Pins of the oracle's MS-GFEM coarse problem and GenEO PCG (CPU).
+
+Sec. 3.3: u^G = u^p + u_H with a(u^G, v) = b(v) on V_H.  Pinned by:
+exact recovery of the fine solution when every finite eigenpair is kept (the
+fine solution restricted to Omega_j^* minus psi_j is A-harmonic, so it lies in
+u^p + V_H), Galerkin orthogonality, monotone error in n_ev (nested spaces,
+Sec. 5.3), the partition-of-unity-weighted load, and the fine solve itself
+(the bar closed form pins it in test_oracle_material_fem).
+"""
+import numpy as np
+import pytest
+
+from oracle import coarse, decomp, fem, geneo, gevp
+from paper_2211_13893_amd import synth
+
+
+@pytest.fixture(scope="module")
+def beam():
+    p = synth.laminated_beam()
+    A = fem.assemble_global_sparse(p)
+    b = fem.traction_load(p)
+    return p, A, b, coarse.fine_solve(p, A, b)
+
+
+def test_energy_error_decreases_with_n_ev(beam):
+    p, A, b, uh = beam
+    errs = [coarse.energy_error(p, A, uh, coarse.msgfem(p, k, A, b).uG) for k in (4, 10, 20)]
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.05
+
+
+def test_galerkin_orthogonality(beam):
+    p, A, b, uh = beam
+    r = coarse.msgfem(p, 10, A, b)
+    F = coarse.free_dofs(p)
+    AF = A[F][:, F]
+    g = r.V[F].T @ (AF @ (uh - r.uG)[F])
+    assert np.abs(g).max() <= 1e-10 * np.abs(r.V[F].T @ (AF @ uh[F])).max()
+
+
+def test_all_modes_recover_fine_solution():
+    p = synth.laminated_beam(shape=(12, 3, 3), n_sub=2, overlap=1, ovs=1)
+    A = fem.assemble_global_sparse(p)
+    b = fem.traction_load(p)
+    uh = coarse.fine_solve(p, A, b)
+    locs = []
+    kec = fem.KeCache(p)
+    for j in range(p.nsd):
+        ops = gevp.local_ops(p, j, kec, b)
+        res = gevp.schur_gevp(ops, None)
+        keep = res.nu > 1e-13 * res.nu.max()
+        phi = res.phi[:, keep]
+        locs.append((phi, coarse.particular_local(ops), ops.mu, decomp.star_global_dofs(p, j), res.lam[keep]))
+    r = coarse.msgfem(p, None, A, b, locals_=locs)
+    F = coarse.free_dofs(p)
+    w, U = np.linalg.eigh(r.AH)
+    keep = w > 1e-12 * w.max()
+    c = U[:, keep] @ ((U[:, keep].T @ r.bH) / w[keep])
+    uG = r.up + r.V @ c
+    assert coarse.energy_error(p, A, uh, uG) <= 1e-8
+
+
+def test_particular_functions_and_weighted_load(beam):
+    p, A, b, uh = beam
+    total = np.zeros(p.n_dofs)
+    nonzero = []
+    for j in range(p.nsd):
+        ops = gevp.local_ops(p, j, load=b)
+        psi = coarse.particular_local(ops)
+        nonzero.append(bool(np.any(psi != 0)))
+        gd = decomp.star_global_dofs(p, j)
+        total[gd] += ops.mu * ops.b
+    # only the subdomain touching the loaded face carries a particular function
+    assert nonzero == [False, False, False, True]
+    assert np.allclose(total, b, rtol=0, atol=1e-12)
+
+
+def test_geneo_pcg_matches_direct_solve():
+    p = synth.laminated_beam(shape=(24, 3, 3), n_sub=4, overlap=1, ovs=1)
+    A = fem.assemble_global_sparse(p)
+    b = fem.traction_load(p)
+    uh = coarse.fine_solve(p, A, b)
+    u, it, rel = geneo.two_level_pcg(p, A, b, n_ev=8, rtol=1e-8)
+    assert rel <= 1e-8
+    assert coarse.energy_error(p, A, uh, u) <= 1e-6
+    # floating GenEO subdomains have six zero eigenvalues as well
+    lam, *_ = geneo.geneo_local(p, 2, 8)
+    assert np.sum(np.abs(lam) < 1e-8) == 6
