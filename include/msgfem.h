@@ -1,0 +1,175 @@
+/*
+ * msgfem.h - C ABI of the MI355X (gfx950) local spectral stage of MS-GFEM
+ * with A-harmonic local spaces (Benezech, Seelinger, Bastian, Butler,
+ * Dodwell, Ma, Scheichl: "Scalable multiscale-spectral GFEM with an
+ * application to composite aero-structures").
+ *
+ * The library computes, for a batch of oversampled subdomains Omega_j^* of a
+ * structured hexahedral laminate mesh:
+ *   - the Q1 anisotropic-elasticity stiffness a_{Omega*} (Sec. 2, eq. for a_D),
+ *     the DoF classes B1/B2/B3 (Sec. 4.3) and the smooth partition of unity
+ *     mu_j (Sec. 4.2)                                    -> msgfem_assemble_local
+ *   - the n_ev smallest eigenpairs of the A-harmonic GEVP (Sec. 3.3; matrix
+ *     form Sec. 4.3), solved through the interior Schur complement
+ *                                                        -> msgfem_local_eigs
+ *   - building blocks of the same operators (stiffness / PoU products and the
+ *     interior solves) for particular functions and checks -> msgfem_local_apply
+ *
+ * Conventions
+ *   - Units mm, N, MPa.  Mesh node id i + (nx+1)*(j + (ny+1)*k); element id
+ *     i + nx*(j + ny*k); DoF id 3*node + component.
+ *   - Every array marked "device" is a device pointer owned by the caller
+ *     (e.g. allocated by PyTorch); the library never allocates device memory
+ *     in these calls.  "host" arrays are read during the call only.
+ *   - Every compute call is asynchronous on the caller's HIP stream, passed as
+ *     `void *stream` (a hipStream_t; NULL = the default stream).  The return
+ *     value reports argument and launch errors only; device-side outcomes are
+ *     written to the caller's device `status` array (bit flags, below) and are
+ *     valid after the stream is synchronised.
+ *   - Inputs are never modified.  No exceptions cross the ABI.
+ *
+ * Return codes: MSGFEM_OK (0), MSGFEM_EARG (-1) bad argument,
+ * MSGFEM_EHIP (-2) HIP error, MSGFEM_ESIZE (-3) unsupported size.
+ * The message of the last failure of a plan: msgfem_plan_error().
+ *
+ * Status bits (device int32 per batch box): 1 = not converged within maxit
+ * (best iterate returned), 4 = a pivot of a local factorisation was not
+ * positive, 8 = non-finite value met.
+ */
+#ifndef MSGFEM_H
+#define MSGFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSGFEM_OK 0
+#define MSGFEM_EARG (-1)
+#define MSGFEM_EHIP (-2)
+#define MSGFEM_ESIZE (-3)
+
+typedef struct msgfem_plan msgfem_plan;
+
+/* Structured laminate mesh (Sec. 2, Sec. 5.1).  All pointers are device. */
+typedef struct {
+  int32_t nx, ny, nz;        /* elements per axis */
+  int32_t n_mat;             /* rows of `materials` */
+  const double *node_xyz;    /* [(nx+1)(ny+1)(nz+1)][3] node coordinates */
+  const int32_t *elem_mat;   /* [nx*ny*nz] material row of every element */
+  const double *materials;   /* [n_mat][10]: E1,E2,E3,G12,G13,G23,nu12,nu13,nu23
+                                in the material frame and the ply angle in
+                                degrees (rotation about +z, fibre axis
+                                (cos t, sin t, 0)) */
+  const uint8_t *dirichlet;  /* [3*n_nodes] 1 = DoF clamped to zero (Gamma_D) */
+} msgfem_mesh;
+
+/* Overlapping domain decomposition (Sec. 3.1, 3.3).  Host pointers.
+ * Omega_j = core grown by `overlap` element layers, Omega_j^* = Omega_j grown
+ * by ovs[j] further layers, both clipped to the mesh (the paper's o^* is
+ * overlap + ovs[j]).  Every subdomain takes part in the partition of unity;
+ * only the batch is solved. */
+typedef struct {
+  int32_t nsd;
+  const int32_t *cores;      /* [nsd][6] element box lo_x,lo_y,lo_z,hi_x,hi_y,hi_z, [lo,hi) */
+  int32_t overlap;           /* o >= 1 */
+  const int32_t *ovs;        /* [nsd] oversampling layers >= 0 */
+} msgfem_decomp;
+
+/* Eigensolver options. */
+typedef struct {
+  double shift;     /* s > 0 of the shifted pencil M x = nu (S + s M) x (default 1) */
+  double tol;       /* residual tolerance on rho (default 1e-6) */
+  int32_t maxit;    /* LOBPCG iteration cap (default 200) */
+  int32_t block;    /* block width k >= max n_ev (0: n_ev + max(4, n_ev/2) rounded up to 8) */
+  int32_t precision;/* 0 = FP64 throughout */
+  int32_t reserved;
+  uint64_t seed;    /* seed of the random start block */
+} msgfem_eig_opts;
+
+typedef struct {
+  int64_t ops_bytes;    /* device bytes of the assembled-operator buffer */
+  int64_t work_bytes;   /* device bytes of the eigensolver workspace */
+  int64_t n_eval;       /* sum over the batch of n_ev (length of evals, resid) */
+  int64_t n_evec;       /* sum over the batch of n_dof(box)*n_ev(box) */
+  int64_t n_dof;        /* sum over the batch of n_dof(box) = 3 * box nodes */
+  int32_t block;        /* block width k in use */
+  int32_t n_box;        /* batch size */
+} msgfem_sizes;
+
+/* Per-box geometry and buffer offsets, for callers that read the assembled
+ * operators (layouts documented in msgfem_plan_box). */
+typedef struct {
+  int32_t sd;                  /* subdomain id */
+  int32_t mx, my, mz;          /* box node dims (Omega_j^* node box) */
+  int32_t g0[3];               /* global node index of the box's first node */
+  int32_t n_nodes, n_dof, n_ev;
+  int32_t n1, n2, n3;          /* sizes of B1, B2, B3 (computed on the host from geometry) */
+  int64_t stencil_off;         /* byte offset in ops of the stencil:
+                                  double [27*9][n_nodes], entry
+                                  ((nb*9 + 3*cr + cc)*n_nodes + node), nb = (dx+1)+3(dy+1)+9(dz+1):
+                                  a_{Omega*}(phi_{node,cr}, phi_{node+d,cc}) */
+  int64_t cls_off;             /* byte offset of uint8 [n_dof] class 1/2/3 */
+  int64_t mu_off;              /* byte offset of double [n_dof]: mu_j on B1, 0 elsewhere */
+  int64_t vec_off;             /* element offset of this box in block vectors [n_dof][k] */
+  int64_t evec_off;            /* element offset in evecs: [n_dof][n_ev] row-major */
+  int64_t eval_off;            /* element offset in evals / resid */
+} msgfem_box_info;
+
+/* Create a plan for one mesh, one decomposition and a batch of subdomains.
+ * batch[nb] are subdomain ids, n_ev[nb] the number of eigenpairs of each
+ * (1 <= n_ev <= 32).  `opts` may be NULL (defaults).  Host-side only: reads
+ * the host arrays, keeps copies of the mesh descriptor's device pointers
+ * (which must stay valid while the plan is used).  Returns MSGFEM_EARG for
+ * inconsistent geometry (empty interior block, box thinner than 3 nodes). */
+int msgfem_plan_create(msgfem_plan **plan, int device, const msgfem_mesh *mesh,
+                       const msgfem_decomp *dec, const int32_t *batch, const int32_t *n_ev,
+                       int32_t nb, const msgfem_eig_opts *opts);
+void msgfem_plan_destroy(msgfem_plan *plan);
+const char *msgfem_plan_error(const msgfem_plan *plan);
+int msgfem_plan_sizes(const msgfem_plan *plan, msgfem_sizes *out);
+int msgfem_plan_box(const msgfem_plan *plan, int32_t b, msgfem_box_info *out);
+
+/* Assemble the local operators of every batch box into `ops` (device,
+ * ops_bytes): material tensors, partition-of-unity weight sums over all
+ * subdomains (Sec. 4.2), block-27 stencils of a_{Omega*} (Sec. 2), DoF
+ * classes (Sec. 4.3), mu_j on B1, and the banded Cholesky factors of A11
+ * (B1 block) and of A + s D A D on B1 u B2 used by msgfem_local_eigs.
+ * status: device int32[nb], overwritten (bit 4 = non-positive pivot). */
+int msgfem_assemble_local(msgfem_plan *plan, void *ops, int32_t *status, void *stream);
+
+/* The A-harmonic local GEVP (Sec. 3.3; mixed form and its matrix form Sec.
+ * 4.3), reduced exactly to S x = lambda M x on B2 with
+ * S = A22 - A21 A11^{-1} A12 and M = E^T (D A D)_{11} E, E = -A11^{-1} A12,
+ * and solved as M x = nu (S + s M) x for the n_ev largest nu by LOBPCG
+ * preconditioned with the B2 trace of (A + s D A D)^{-1}.
+ *   ops   : assembled by msgfem_assemble_local with this plan
+ *   work  : device, work_bytes
+ *   x0    : NULL (seeded random start) or device block [n_dof][k] per box at
+ *           vec_off (values on B2 DoFs are used)
+ *   evals : device double[n_eval], lambda ascending per box (eval_off)
+ *   evecs : device double[n_evec], per box [n_dof][n_ev] row-major: the
+ *           A-harmonic eigenvectors phi = (E x, x, 0) on every DoF of the box,
+ *           unit 2-norm, entry of largest magnitude positive
+ *   resid : device double[n_eval], rho = |Mx - nu T x| / (|Mx| + nu |T x|)
+ *   iters : device int32[nb] LOBPCG iterations
+ *   status: device int32[nb], bits ORed in (1 = not converged) */
+int msgfem_local_eigs(msgfem_plan *plan, const void *ops, void *work, const double *x0,
+                      double *evals, double *evecs, double *resid, int32_t *iters,
+                      int32_t *status, void *stream);
+
+/* Apply one local operator to a block of k columns (box layout [n_dof][k] at
+ * vec_off; k must equal the plan's block width, else MSGFEM_EARG):
+ *   op 0: y = A x on B1 u B2 (B3 rows/columns removed, 0 on B3)
+ *   op 1: y = D A D x (D = diag(mu_j) on B1, 0 elsewhere)
+ *   op 2: y = A11^{-1} x on B1, 0 elsewhere (interior solve)
+ *   op 3: y = (A + s D A D)^{-1} x on B1 u B2, 0 on B3
+ * Solves need `work` (work_bytes).  Reads x, writes y (distinct buffers). */
+int msgfem_local_apply(msgfem_plan *plan, const void *ops, void *work, int32_t op, int32_t k,
+                       const double *x, double *y, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSGFEM_H */

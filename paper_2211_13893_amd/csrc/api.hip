@@ -1,0 +1,683 @@
+// C ABI entry points: plans, assembly, the LOBPCG driver and operator application.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "msgfem.h"
+
+namespace msg {
+__global__ void k_materials(const double*, int, double*);
+__global__ void k_pou_total(const int32_t*, int, int, int, int, int, int32_t*);
+__global__ void k_fill_i32(int32_t*, int64_t, int32_t);
+__global__ void k_fill_f64(double*, int64_t, double);
+__global__ void k_assemble(const BoxMeta*, MeshDev, const double*, double*);
+__global__ void k_classes_mu(const BoxMeta*, MeshDev, int, const int32_t*, uint8_t*, double*);
+__global__ void k_band_build(const BoxMeta*, int, const double*, const uint8_t*, const double*, double,
+                             double*);
+__global__ void k_band_potrf(const BoxMeta*, int, double*, int32_t*);
+template <int KC>
+__global__ void k_band_solve(const BoxMeta*, int, int, int, const double*, const uint8_t*, const double*,
+                             double*, int, int, int, double*, int64_t, const int32_t*);
+__global__ void k_spmm(const BoxMeta*, const double*, const uint8_t*, const double*, const double*,
+                       double*, double*, int, int, double, const int32_t*);
+struct Blk3 { const double* p[3]; };
+struct Blk4x3 { const double* p[4][3]; };
+struct Out4 { double* p[4]; };
+__global__ void k_gram_partial(const BoxMeta*, int, Blk3, Blk3, Blk3, int, int, int, double*,
+                               const int32_t*);
+__global__ void k_gram_reduce(int, int, const double*, double*, const int32_t*);
+__global__ void k_rayleigh_ritz(int, int, int, double, const double*, double*, double*, double*,
+                                double*, const int32_t*);
+__global__ void k_update(const BoxMeta*, int, int, Blk4x3, Out4, Out4, const double*, const double*,
+                         const int32_t*);
+__global__ void k_residual(const BoxMeta*, const uint8_t*, int, double, const double*, const double*,
+                           const double*, double*, int, int, double*, const int32_t*);
+__global__ void k_converge(const BoxMeta*, int, int, int, const double*, const double*, double, double*,
+                           int32_t*, int32_t*, int32_t*, int);
+__global__ void k_random_start(const BoxMeta*, const uint8_t*, int, uint64_t, double*);
+__global__ void k_copy_start(const BoxMeta*, const uint8_t*, int, const double*, double*);
+__global__ void k_output(const BoxMeta*, int, double, const double*, const double*, const double*,
+                         double*, double*, double*);
+}  // namespace msg
+
+using namespace msg;
+
+static const int KC = 8;           // columns per solve workgroup
+static const int GRAM_ROWS = 1024; // rows per Gram / residual chunk
+
+static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+struct msgfem_plan {
+  int device = 0;
+  msgfem_mesh mesh{};
+  int32_t nsd = 0, overlap = 0;
+  std::vector<int32_t> omega;     // [nsd][6] node boxes of Omega_j
+  std::vector<BoxMeta> meta;      // batch boxes
+  msgfem_eig_opts opts{};
+  int k = 0;
+  int64_t n_nodes_global = 0;
+  // ops layout (bytes)
+  int64_t o_meta = 0, o_omega = 0, o_ctab = 0, o_wtot = 0, o_stencil = 0, o_mu = 0, o_cls = 0,
+          o_fac = 0, ops_bytes = 0;
+  int64_t nodes_total = 0, dofs_total = 0, fac_total = 0, vec_total = 0, evec_total = 0,
+          eval_total = 0;
+  int max_nodes = 0, max_dof = 0, max_nt = 0, max_bt = 0;
+  int64_t max_fac_tiles = 0;
+  int n_gchunk = 0;
+  // work layout (bytes)
+  int64_t w_vec = 0, w_part = 0, w_G = 0, w_L = 0, w_Y = 0, w_Yp = 0, w_nu = 0, w_rho = 0,
+          w_rpart = 0, w_active = 0, w_iters = 0, w_nact = 0, w_scr = 0, work_bytes = 0;
+  int64_t scr_stride = 0;
+  std::string err;
+};
+
+static int fail(msgfem_plan* p, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (p) p->err = buf;
+  return code;
+}
+
+#define HIPCHK(p, call)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(p, MSGFEM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));        \
+  } while (0)
+
+#define LAUNCHCHK(p)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = hipGetLastError();                                                     \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(p, MSGFEM_EHIP, "launch failed (line %d): %s", __LINE__,                 \
+                  hipGetErrorString(e_));                                                  \
+  } while (0)
+
+static void band_geom(int sx, int sy, int sz, int* n, int* nt, int* bt) {
+  *n = 3 * sx * sy * sz;
+  int b = 3 * (sx * sy + sx + 1) + 2;
+  *nt = (*n + 31) / 32;
+  *bt = (b + 31) / 32 + 1;
+  if (*bt > *nt) *bt = *nt;
+}
+
+extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_mesh* mesh,
+                                  const msgfem_decomp* dec, const int32_t* batch,
+                                  const int32_t* n_ev, int32_t nb,
+                                  const msgfem_eig_opts* opts) {
+  if (!out || !mesh || !dec || !batch || !n_ev || nb <= 0) return MSGFEM_EARG;
+  *out = nullptr;
+  msgfem_plan* p = new msgfem_plan();
+  *out = p;
+  p->device = device;
+  p->mesh = *mesh;
+  p->nsd = dec->nsd;
+  p->overlap = dec->overlap;
+  if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1 || mesh->n_mat < 1)
+    return fail(p, MSGFEM_EARG, "bad mesh dimensions");
+  if (!mesh->node_xyz || !mesh->elem_mat || !mesh->materials || !mesh->dirichlet)
+    return fail(p, MSGFEM_EARG, "null mesh array");
+  if (dec->nsd < 1 || !dec->cores || !dec->ovs || dec->overlap < 1)
+    return fail(p, MSGFEM_EARG, "bad decomposition (nsd >= 1, overlap >= 1 required)");
+  msgfem_eig_opts o;
+  o.shift = 1.0; o.tol = 1e-6; o.maxit = 200; o.block = 0; o.precision = 0; o.reserved = 0; o.seed = 1234;
+  if (opts) {
+    o = *opts;
+    if (!(o.shift > 0)) o.shift = 1.0;
+    if (!(o.tol > 0)) o.tol = 1e-6;
+    if (o.maxit <= 0) o.maxit = 200;
+  }
+  if (o.precision != 0) return fail(p, MSGFEM_EARG, "precision %d not supported", o.precision);
+  p->opts = o;
+  const int N[3] = {mesh->nx, mesh->ny, mesh->nz};
+  p->n_nodes_global = (int64_t)(N[0] + 1) * (N[1] + 1) * (N[2] + 1);
+  p->omega.resize(6 * (size_t)dec->nsd);
+  for (int j = 0; j < dec->nsd; ++j) {
+    const int32_t* c = dec->cores + 6 * j;
+    for (int d = 0; d < 3; ++d) {
+      if (c[d] < 0 || c[3 + d] > N[d] || c[d] >= c[3 + d])
+        return fail(p, MSGFEM_EARG, "core %d out of the mesh", j);
+      p->omega[6 * j + d] = std::max(c[d] - dec->overlap, 0);
+      p->omega[6 * j + 3 + d] = std::min(c[3 + d] + dec->overlap, N[d]);
+    }
+  }
+  int maxnev = 0;
+  for (int b = 0; b < nb; ++b) maxnev = std::max(maxnev, n_ev[b]);
+  if (maxnev < 1 || maxnev > 32) return fail(p, MSGFEM_EARG, "n_ev must be in [1, 32]");
+  int k = o.block;
+  if (k <= 0) {
+    k = maxnev + std::max(4, (maxnev + 1) / 2);
+    k = (k + 7) / 8 * 8;
+  }
+  k = std::min(k, 32);
+  if (k < maxnev) return fail(p, MSGFEM_EARG, "block %d < n_ev %d", k, maxnev);
+  if (k % 2) return fail(p, MSGFEM_EARG, "block width must be even");
+  p->k = k;
+  p->meta.resize(nb);
+  int64_t node_off = 0, dof_off = 0, vec_off = 0, fac_off = 0, evec_off = 0, eval_off = 0;
+  for (int b = 0; b < nb; ++b) {
+    int sd = batch[b];
+    if (sd < 0 || sd >= dec->nsd) return fail(p, MSGFEM_EARG, "batch[%d] = %d out of range", b, sd);
+    if (n_ev[b] < 1) return fail(p, MSGFEM_EARG, "n_ev[%d] < 1", b);
+    if (dec->ovs[sd] < 0) return fail(p, MSGFEM_EARG, "ovs[%d] < 0", sd);
+    BoxMeta m;
+    std::memset(&m, 0, sizeof m);
+    m.sd = sd;
+    const int32_t* c = dec->cores + 6 * sd;
+    int g = dec->overlap + dec->ovs[sd];
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::max(c[d] - g, 0);
+      hi[d] = std::min(c[3 + d] + g, N[d]);
+      m.g0[d] = lo[d];
+      m.olo[d] = p->omega[6 * sd + d];
+      m.ohi[d] = p->omega[6 * sd + 3 + d];
+      m.olo_int[d] = m.olo[d] > 0;
+      m.ohi_int[d] = m.ohi[d] < N[d];
+      m.iface_lo[d] = lo[d] > 0;
+      m.iface_hi[d] = hi[d] < N[d];
+    }
+    m.mx = hi[0] - lo[0] + 1;
+    m.my = hi[1] - lo[1] + 1;
+    m.mz = hi[2] - lo[2] + 1;
+    int mm[3] = {m.mx, m.my, m.mz};
+    for (int d = 0; d < 3; ++d) {
+      m.sub_lo[d] = m.iface_lo[d] ? 1 : 0;
+      m.sub_hi[d] = mm[d] - 1 - (m.iface_hi[d] ? 1 : 0);
+      if (m.sub_hi[d] < m.sub_lo[d] || mm[d] < 3)
+        return fail(p, MSGFEM_EARG, "subdomain %d: box too thin for an interior block", sd);
+    }
+    if (!(m.iface_lo[0] || m.iface_hi[0] || m.iface_lo[1] || m.iface_hi[1] || m.iface_lo[2] || m.iface_hi[2]))
+      return fail(p, MSGFEM_EARG, "subdomain %d: oversampling box covers the whole mesh (B2 empty)", sd);
+    m.n_nodes = m.mx * m.my * m.mz;
+    m.n_dof = 3 * m.n_nodes;
+    m.n_ev = n_ev[b];
+    band_geom(m.sub_hi[0] - m.sub_lo[0] + 1, m.sub_hi[1] - m.sub_lo[1] + 1,
+              m.sub_hi[2] - m.sub_lo[2] + 1, &m.n11, &m.nt11, &m.bt11);
+    band_geom(m.mx, m.my, m.mz, &m.nh, &m.nth, &m.bth);
+    m.node_off = node_off;
+    m.dof_off = dof_off;
+    m.vec_off = vec_off;
+    m.f11_off = fac_off;
+    fac_off += (int64_t)m.nt11 * m.bt11 * 1024;
+    m.f11i_off = fac_off;
+    fac_off += (int64_t)m.nt11 * 1024;
+    m.fh_off = fac_off;
+    fac_off += (int64_t)m.nth * m.bth * 1024;
+    m.fhi_off = fac_off;
+    fac_off += (int64_t)m.nth * 1024;
+    m.evec_off = evec_off;
+    m.eval_off = eval_off;
+    node_off += m.n_nodes;
+    dof_off += m.n_dof;
+    vec_off += (int64_t)m.n_dof * k;
+    evec_off += (int64_t)m.n_dof * m.n_ev;
+    eval_off += m.n_ev;
+    p->max_nodes = std::max(p->max_nodes, m.n_nodes);
+    p->max_dof = std::max(p->max_dof, m.n_dof);
+    p->max_nt = std::max(p->max_nt, std::max(m.nt11, m.nth));
+    p->max_bt = std::max(p->max_bt, std::max(m.bt11, m.bth));
+    p->max_fac_tiles = std::max(p->max_fac_tiles, (int64_t)std::max(m.nt11 * m.bt11, m.nth * m.bth));
+    p->meta[b] = m;
+  }
+  if ((int64_t)p->max_bt * 32 * KC * 8 > 140 * 1024)
+    return fail(p, MSGFEM_ESIZE, "band too wide for the LDS ring (BT=%d)", p->max_bt);
+  p->nodes_total = node_off;
+  p->dofs_total = dof_off;
+  p->fac_total = fac_off;
+  p->vec_total = vec_off;
+  p->evec_total = evec_off;
+  p->eval_total = eval_off;
+  // ops layout
+  int64_t off = 0;
+  p->o_meta = off; off = align256(off + (int64_t)nb * sizeof(BoxMeta));
+  p->o_omega = off; off = align256(off + (int64_t)dec->nsd * 6 * 4);
+  p->o_ctab = off; off = align256(off + (int64_t)mesh->n_mat * 36 * 8);
+  p->o_wtot = off; off = align256(off + p->n_nodes_global * 4);
+  p->o_stencil = off; off = align256(off + p->nodes_total * 243 * 8);
+  p->o_mu = off; off = align256(off + p->dofs_total * 8);
+  p->o_cls = off; off = align256(off + p->dofs_total);
+  p->o_fac = off; off = align256(off + p->fac_total * 8);
+  p->ops_bytes = off;
+  // work layout
+  p->n_gchunk = (p->max_dof + GRAM_ROWS - 1) / GRAM_ROWS;
+  int m3 = 3 * k;
+  int nchunk_solve = (k + KC - 1) / KC;
+  p->scr_stride = (int64_t)p->max_nt * 32 * KC;
+  off = 0;
+  p->w_vec = off; off = align256(off + 22 * p->vec_total * 8);
+  p->w_part = off; off = align256(off + (int64_t)nb * p->n_gchunk * 2 * m3 * m3 * 8);
+  p->w_G = off; off = align256(off + (int64_t)nb * 2 * m3 * m3 * 8);
+  p->w_L = off; off = align256(off + (int64_t)nb * m3 * m3 * 8);
+  p->w_Y = off; off = align256(off + (int64_t)nb * m3 * k * 8);
+  p->w_Yp = off; off = align256(off + (int64_t)nb * m3 * k * 8);
+  p->w_nu = off; off = align256(off + (int64_t)nb * k * 8);
+  p->w_rho = off; off = align256(off + (int64_t)nb * k * 8);
+  p->w_rpart = off; off = align256(off + (int64_t)nb * p->n_gchunk * 3 * 32 * 8);
+  p->w_active = off; off = align256(off + (int64_t)nb * 4);
+  p->w_iters = off; off = align256(off + (int64_t)nb * 4);
+  p->w_nact = off; off = align256(off + 4);
+  p->w_scr = off; off = align256(off + (int64_t)nb * nchunk_solve * p->scr_stride * 8);
+  p->work_bytes = off;
+  return MSGFEM_OK;
+}
+
+extern "C" void msgfem_plan_destroy(msgfem_plan* p) { delete p; }
+
+extern "C" const char* msgfem_plan_error(const msgfem_plan* p) {
+  return p ? p->err.c_str() : "null plan";
+}
+
+extern "C" int msgfem_plan_sizes(const msgfem_plan* p, msgfem_sizes* s) {
+  if (!p || !s) return MSGFEM_EARG;
+  s->ops_bytes = p->ops_bytes;
+  s->work_bytes = p->work_bytes;
+  s->n_eval = p->eval_total;
+  s->n_evec = p->evec_total;
+  s->n_dof = p->dofs_total;
+  s->block = p->k;
+  s->n_box = (int32_t)p->meta.size();
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_plan_box(const msgfem_plan* p, int32_t b, msgfem_box_info* o) {
+  if (!p || !o || b < 0 || b >= (int32_t)p->meta.size()) return MSGFEM_EARG;
+  const BoxMeta& m = p->meta[b];
+  o->sd = m.sd;
+  o->mx = m.mx; o->my = m.my; o->mz = m.mz;
+  for (int d = 0; d < 3; ++d) o->g0[d] = m.g0[d];
+  o->n_nodes = m.n_nodes;
+  o->n_dof = m.n_dof;
+  o->n_ev = m.n_ev;
+  // class counts from geometry (host): B2 = interior faces, B3 needs the Dirichlet flags
+  int n2n = 0;
+  for (int kk = 0; kk < m.mz; ++kk)
+    for (int jj = 0; jj < m.my; ++jj)
+      for (int ii = 0; ii < m.mx; ++ii) {
+        int l[3] = {ii, jj, kk}, mm[3] = {m.mx, m.my, m.mz};
+        bool b2 = false;
+        for (int d = 0; d < 3; ++d)
+          if ((m.iface_lo[d] && l[d] == 0) || (m.iface_hi[d] && l[d] == mm[d] - 1)) b2 = true;
+        n2n += b2;
+      }
+  o->n2 = 3 * n2n;   // before removing Dirichlet DoFs on the interior faces
+  o->n1 = m.n_dof - o->n2;
+  o->n3 = -1;        // needs device data (Dirichlet flags); read the class array
+  o->stencil_off = p->o_stencil + m.node_off * 243 * 8;
+  o->cls_off = p->o_cls + m.dof_off;
+  o->mu_off = p->o_mu + m.dof_off * 8;
+  o->vec_off = m.vec_off;
+  o->evec_off = m.evec_off;
+  o->eval_off = m.eval_off;
+  return MSGFEM_OK;
+}
+
+static MeshDev mesh_dev(const msgfem_plan* p) {
+  MeshDev md;
+  md.nx = p->mesh.nx; md.ny = p->mesh.ny; md.nz = p->mesh.nz; md.n_mat = p->mesh.n_mat;
+  md.xyz = p->mesh.node_xyz; md.elem_mat = p->mesh.elem_mat; md.materials = p->mesh.materials;
+  md.dirichlet = p->mesh.dirichlet;
+  return md;
+}
+
+struct OpsView {
+  const BoxMeta* meta;
+  int32_t* omega;
+  double* ctab;
+  int32_t* wtot;
+  double* stencil;
+  double* mu1;
+  uint8_t* cls;
+  double* fac;
+};
+
+static OpsView ops_view(const msgfem_plan* p, const void* ops) {
+  char* b = (char*)ops;
+  OpsView v;
+  v.meta = (const BoxMeta*)(b + p->o_meta);
+  v.omega = (int32_t*)(b + p->o_omega);
+  v.ctab = (double*)(b + p->o_ctab);
+  v.wtot = (int32_t*)(b + p->o_wtot);
+  v.stencil = (double*)(b + p->o_stencil);
+  v.mu1 = (double*)(b + p->o_mu);
+  v.cls = (uint8_t*)(b + p->o_cls);
+  v.fac = (double*)(b + p->o_fac);
+  return v;
+}
+
+static void lds_attributes();
+
+static int set_device(msgfem_plan* p) {
+  HIPCHK(p, hipSetDevice(p->device));
+  lds_attributes();
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status, void* stream) {
+  if (!p || !ops || !status) return fail(p, MSGFEM_EARG, "null argument");
+  if (set_device(p)) return MSGFEM_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  OpsView v = ops_view(p, ops);
+  const int nb = (int)p->meta.size();
+  HIPCHK(p, hipMemcpyAsync((void*)v.meta, p->meta.data(), nb * sizeof(BoxMeta), hipMemcpyHostToDevice, s));
+  HIPCHK(p, hipMemcpyAsync(v.omega, p->omega.data(), p->omega.size() * 4, hipMemcpyHostToDevice, s));
+  // the host copies must stay alive until the copies complete
+  HIPCHK(p, hipStreamSynchronize(s));
+  k_fill_i32<<<(nb + 255) / 256, 256, 0, s>>>(status, nb, 0);
+  LAUNCHCHK(p);
+  k_materials<<<(p->mesh.n_mat + 63) / 64, 64, 0, s>>>(p->mesh.materials, p->mesh.n_mat, v.ctab);
+  LAUNCHCHK(p);
+  k_fill_i32<<<1024, 256, 0, s>>>(v.wtot, p->n_nodes_global, 0);
+  LAUNCHCHK(p);
+  int maxo = 1;
+  for (int j = 0; j < p->nsd; ++j) {
+    const int32_t* o = &p->omega[6 * j];
+    maxo = std::max(maxo, (o[3] - o[0] + 1) * (o[4] - o[1] + 1) * (o[5] - o[2] + 1));
+  }
+  {
+    dim3 grid((maxo + 255) / 256, p->nsd);
+    k_pou_total<<<grid, 256, 0, s>>>(v.omega, p->nsd, p->mesh.nx, p->mesh.ny, p->mesh.nz,
+                                     2 * p->overlap, v.wtot);
+    LAUNCHCHK(p);
+  }
+  MeshDev md = mesh_dev(p);
+  {
+    dim3 grid((p->max_nodes + 3) / 4, nb);
+    k_assemble<<<grid, 256, 0, s>>>(v.meta, md, v.ctab, v.stencil);
+    LAUNCHCHK(p);
+  }
+  {
+    dim3 grid((p->max_nodes + 255) / 256, nb);
+    k_classes_mu<<<grid, 256, 0, s>>>(v.meta, md, 2 * p->overlap, v.wtot, v.cls, v.mu1);
+    LAUNCHCHK(p);
+  }
+  for (int kind = 0; kind < 2; ++kind) {
+    int64_t tot = p->max_fac_tiles * 1024;
+    int64_t blocks = std::min<int64_t>((tot + 255) / 256, 65535);
+    dim3 grid((unsigned)blocks, nb);
+    k_band_build<<<grid, 256, 0, s>>>(v.meta, kind, v.stencil, v.cls, v.mu1, p->opts.shift, v.fac);
+    LAUNCHCHK(p);
+  }
+  for (int kind = 0; kind < 2; ++kind) {
+    k_band_potrf<<<nb, 256, 0, s>>>(v.meta, kind, v.fac, status);
+    LAUNCHCHK(p);
+  }
+  return MSGFEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// LOBPCG driver
+
+namespace {
+struct Work {
+  double* vec;       // 22 block arrays of vec_total doubles
+  double* part;
+  double* G;
+  double* L;
+  double* Y;
+  double* Yp;
+  double* nu;
+  double* rho;
+  double* rpart;
+  int32_t* active;
+  int32_t* iters;
+  int32_t* nact;
+  double* scr;
+};
+}  // namespace
+
+static Work work_view(const msgfem_plan* p, void* work) {
+  char* b = (char*)work;
+  Work w;
+  w.vec = (double*)(b + p->w_vec);
+  w.part = (double*)(b + p->w_part);
+  w.G = (double*)(b + p->w_G);
+  w.L = (double*)(b + p->w_L);
+  w.Y = (double*)(b + p->w_Y);
+  w.Yp = (double*)(b + p->w_Yp);
+  w.nu = (double*)(b + p->w_nu);
+  w.rho = (double*)(b + p->w_rho);
+  w.rpart = (double*)(b + p->w_rpart);
+  w.active = (int32_t*)(b + p->w_active);
+  w.iters = (int32_t*)(b + p->w_iters);
+  w.nact = (int32_t*)(b + p->w_nact);
+  w.scr = (double*)(b + p->w_scr);
+  return w;
+}
+
+struct Ctx {
+  msgfem_plan* p;
+  OpsView v;
+  Work w;
+  hipStream_t s;
+  int nb, k;
+};
+
+// Kernels whose dynamic LDS may exceed 64 KiB declare it once per process.
+static void lds_attributes() {
+  static bool done = false;
+  if (done) return;
+  done = true;
+  (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_band_solve<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_gram_partial, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipGetLastError();
+}
+
+static int spmm(Ctx& c, const double* X, double* Y, double* Y2, int kk, int yclasses, double scale,
+                const int32_t* active) {
+  int nq = (kk + 3) / 4;
+  dim3 grid((unsigned)(((int64_t)c.p->max_nodes * nq + 255) / 256), c.nb);
+  k_spmm<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.stencil, c.v.cls, c.v.mu1, X, Y, Y2, kk, yclasses, scale,
+                                active);
+  LAUNCHCHK(c.p);
+  return 0;
+}
+
+static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int out_classes, int zero_rest,
+                 const int32_t* active) {
+  int nchunk = (kk + KC - 1) / KC;
+  dim3 grid(nchunk * c.nb);
+  size_t lds = (size_t)c.p->max_bt * 32 * KC * 8;
+  k_band_solve<KC><<<grid, 256, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, c.v.fac, c.v.cls, in, out, kk,
+                                            out_classes, zero_rest, c.w.scr, c.p->scr_stride, active);
+  LAUNCHCHK(c.p);
+  return 0;
+}
+
+// Z~ <- [E Z; Z] for a boundary block Z (B1 part written), AZ, BZ, MZ
+static int harmonic_images(Ctx& c, double* Z, double* AZ, double* BZ, double* MZ, double* tmp,
+                           const int32_t* act) {
+  const int k = c.k;
+  // extension: A11 u = -(A Z)_1
+  if (spmm(c, Z, tmp, nullptr, k, 1 << 1, -1.0, act)) return MSGFEM_EHIP;
+  if (solve(c, 0, tmp, Z, k, 1 << 1, 0, act)) return MSGFEM_EHIP;
+  // A Z~ (B1 u B2) and D A D Z~
+  if (spmm(c, Z, AZ, BZ, k, (1 << 1) | (1 << 2), 1.0, act)) return MSGFEM_EHIP;
+  // adjoint: M Z = E^T (DAD Z~)_1 = -A21 A11^{-1} (DAD Z~)_1
+  if (solve(c, 0, BZ, tmp, k, 1 << 1, 1, act)) return MSGFEM_EHIP;
+  if (spmm(c, tmp, MZ, nullptr, k, 1 << 2, -1.0, act)) return MSGFEM_EHIP;
+  return 0;
+}
+
+static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double* const* BZb,
+                const int32_t* act) {
+  const int k = c.k, m = nblk * k;
+  Blk3 Z, A, B;
+  for (int i = 0; i < 3; ++i) {
+    Z.p[i] = i < nblk ? Zb[i] : nullptr;
+    A.p[i] = i < nblk ? AZb[i] : nullptr;
+    B.p[i] = i < nblk ? BZb[i] : nullptr;
+  }
+  dim3 grid(c.p->n_gchunk, c.nb, 2);
+  size_t lds = (size_t)2 * 32 * m * 8;
+  k_gram_partial<<<grid, 256, lds, c.s>>>(c.v.meta, nblk, Z, A, B, k, GRAM_ROWS, c.p->n_gchunk, c.w.part,
+                                          act);
+  LAUNCHCHK(c.p);
+  dim3 g2((2 * m * m + 255) / 256, c.nb);
+  k_gram_reduce<<<g2, 256, 0, c.s>>>(m, c.p->n_gchunk, c.w.part, c.w.G, act);
+  LAUNCHCHK(c.p);
+  size_t lds_rr = ((size_t)2 * m * (m + 1) + 3 * m + 256 + m) * 8;
+  k_rayleigh_ritz<<<c.nb, 256, lds_rr, c.s>>>(m, k, 1, c.p->opts.shift, c.w.G, c.w.L, c.w.Y, c.w.Yp,
+                                               c.w.nu, act);
+  LAUNCHCHK(c.p);
+  return 0;
+}
+
+extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, const double* x0,
+                                 double* evals, double* evecs, double* resid, int32_t* iters,
+                                 int32_t* status, void* stream) {
+  if (!p || !ops || !work || !evals || !evecs || !resid || !iters || !status)
+    return fail(p, MSGFEM_EARG, "null argument");
+  if (set_device(p)) return MSGFEM_EHIP;
+  Ctx c;
+  c.p = p;
+  c.v = ops_view(p, ops);
+  c.w = work_view(p, work);
+  c.s = (hipStream_t)stream;
+  c.nb = (int)p->meta.size();
+  c.k = p->k;
+  const int k = c.k, nb = c.nb;
+  const int64_t VT = p->vec_total;
+  // block arrays: kind (0 Z~, 1 AZ~, 2 DAD Z~, 3 MZ) x slot (0 X, 1 W, 2 P, 3 Xn, 4 Pn)
+  double* B[4][5];
+  for (int kind = 0; kind < 4; ++kind)
+    for (int sl = 0; sl < 5; ++sl) B[kind][sl] = c.w.vec + (int64_t)(kind * 5 + sl) * VT;
+  double* tmp = c.w.vec + (int64_t)20 * VT;
+  int32_t* act = c.w.active;
+  const size_t lds_upd3 = (size_t)2 * 3 * k * k * 8;
+  k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(act, nb, 1);
+  k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(c.w.iters, nb, 0);
+  LAUNCHCHK(p);
+  // start block
+  {
+    dim3 grid((unsigned)(((int64_t)p->max_dof * k + 255) / 256), nb);
+    if (x0) k_copy_start<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, x0, B[0][0]);
+    else k_random_start<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, p->opts.seed, B[0][0]);
+    LAUNCHCHK(p);
+  }
+  if (harmonic_images(c, B[0][0], B[1][0], B[2][0], B[3][0], tmp, nullptr)) return MSGFEM_EHIP;
+  // initial Rayleigh-Ritz on X alone (T-orthonormalises the start block)
+  {
+    double* Zb[1] = {B[0][0]};
+    double* Ab[1] = {B[1][0]};
+    double* Bb[1] = {B[2][0]};
+    if (gram(c, 1, Zb, Ab, Bb, nullptr)) return MSGFEM_EHIP;
+    Blk4x3 Z;
+    Out4 OX, OP;
+    for (int kind = 0; kind < 4; ++kind) {
+      Z.p[kind][0] = B[kind][0];
+      Z.p[kind][1] = Z.p[kind][2] = nullptr;
+      OX.p[kind] = B[kind][3];
+      OP.p[kind] = nullptr;
+    }
+    int nq = (k + 3) / 4;
+    dim3 grid((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, 4);
+    k_update<<<grid, 256, (size_t)2 * k * k * 8, c.s>>>(c.v.meta, 1, k, Z, OX, OP, c.w.Y, c.w.Yp, nullptr);
+    LAUNCHCHK(p);
+    for (int kind = 0; kind < 4; ++kind) std::swap(B[kind][0], B[kind][3]);
+  }
+  int n_chunk = p->n_gchunk;
+  for (int it = 0; it <= p->opts.maxit; ++it) {
+    // residual of the current Ritz block, convergence, active set
+    {
+      dim3 grid(n_chunk, nb);
+      k_residual<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, p->opts.shift, B[1][0], B[3][0], c.w.nu,
+                                        B[0][1], GRAM_ROWS, n_chunk, c.w.rpart, act);
+      LAUNCHCHK(p);
+      k_fill_i32<<<1, 32, 0, c.s>>>(c.w.nact, 1, 0);
+      k_converge<<<(nb + 63) / 64, 64, 0, c.s>>>(c.v.meta, nb, k, n_chunk, c.w.rpart, c.w.nu,
+                                                  p->opts.tol, c.w.rho, act, c.w.iters, c.w.nact,
+                                                  it < p->opts.maxit ? 1 : 0);
+      LAUNCHCHK(p);
+      int32_t nact = 0;
+      HIPCHK(p, hipMemcpyAsync(&nact, c.w.nact, 4, hipMemcpyDeviceToHost, c.s));
+      HIPCHK(p, hipStreamSynchronize(c.s));
+      if (nact == 0 || it == p->opts.maxit) break;
+    }
+    // W = preconditioned residual: B2 trace of (A + s DAD)^{-1} [0; R]
+    if (solve(c, 1, B[0][1], B[0][1], k, 1 << 2, 1, act)) return MSGFEM_EHIP;
+    if (harmonic_images(c, B[0][1], B[1][1], B[2][1], B[3][1], tmp, act)) return MSGFEM_EHIP;
+    int nblk = (it == 0) ? 2 : 3;
+    double* Zb[3] = {B[0][0], B[0][1], B[0][2]};
+    double* Ab[3] = {B[1][0], B[1][1], B[1][2]};
+    double* Bb[3] = {B[2][0], B[2][1], B[2][2]};
+    if (gram(c, nblk, Zb, Ab, Bb, act)) return MSGFEM_EHIP;
+    Blk4x3 Z;
+    Out4 OX, OP;
+    for (int kind = 0; kind < 4; ++kind) {
+      for (int b = 0; b < 3; ++b) Z.p[kind][b] = b < nblk ? B[kind][b] : nullptr;
+      OX.p[kind] = B[kind][3];
+      OP.p[kind] = B[kind][4];
+    }
+    int nq = (k + 3) / 4;
+    dim3 grid((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, 4);
+    k_update<<<grid, 256, (size_t)2 * nblk * k * k * 8, c.s>>>(c.v.meta, nblk, k, Z, OX, OP, c.w.Y,
+                                                                c.w.Yp, act);
+    LAUNCHCHK(p);
+    (void)lds_upd3;
+    for (int kind = 0; kind < 4; ++kind) {
+      std::swap(B[kind][0], B[kind][3]);
+      std::swap(B[kind][2], B[kind][4]);
+    }
+  }
+  // boxes still active did not converge
+  {
+    k_output<<<nb, 256, 0, c.s>>>(c.v.meta, k, p->opts.shift, B[0][0], c.w.nu, c.w.rho, evals, evecs,
+                                  resid);
+    LAUNCHCHK(p);
+    HIPCHK(p, hipMemcpyAsync(iters, c.w.iters, nb * 4, hipMemcpyDeviceToDevice, c.s));
+    std::vector<int32_t> a(nb);
+    HIPCHK(p, hipMemcpyAsync(a.data(), act, nb * 4, hipMemcpyDeviceToHost, c.s));
+    HIPCHK(p, hipStreamSynchronize(c.s));
+    bool any = false;
+    for (int b = 0; b < nb; ++b) any |= a[b] != 0;
+    if (any) {
+      // status |= 1 for boxes left active
+      std::vector<int32_t> st(nb);
+      HIPCHK(p, hipMemcpyAsync(st.data(), status, nb * 4, hipMemcpyDeviceToHost, c.s));
+      HIPCHK(p, hipStreamSynchronize(c.s));
+      for (int b = 0; b < nb; ++b) st[b] |= a[b] ? 1 : 0;
+      HIPCHK(p, hipMemcpyAsync(status, st.data(), nb * 4, hipMemcpyHostToDevice, c.s));
+      HIPCHK(p, hipStreamSynchronize(c.s));
+    }
+  }
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_local_apply(msgfem_plan* p, const void* ops, void* work, int32_t op, int32_t kk,
+                                  const double* x, double* y, void* stream) {
+  if (!p || !ops || !x || !y || x == y) return fail(p, MSGFEM_EARG, "bad argument");
+  if (kk != p->k) return fail(p, MSGFEM_EARG, "k must equal the plan's block width %d", p->k);
+  if (set_device(p)) return MSGFEM_EHIP;
+  Ctx c;
+  c.p = p;
+  c.v = ops_view(p, ops);
+  c.s = (hipStream_t)stream;
+  c.nb = (int)p->meta.size();
+  c.k = p->k;
+  if (op == 0) return spmm(c, x, y, nullptr, kk, (1 << 1) | (1 << 2), 1.0, nullptr) ? MSGFEM_EHIP : 0;
+  if (op == 1) {
+    return spmm(c, x, nullptr, y, kk, 0, 1.0, nullptr) ? MSGFEM_EHIP : 0;
+  }
+  if (!work) return fail(p, MSGFEM_EARG, "solves need the work buffer");
+  c.w = work_view(p, work);
+  if (op == 2) return solve(c, 0, x, y, kk, 1 << 1, 1, nullptr) ? MSGFEM_EHIP : 0;
+  if (op == 3) return solve(c, 1, x, y, kk, (1 << 1) | (1 << 2), 1, nullptr) ? MSGFEM_EHIP : 0;
+  return fail(p, MSGFEM_EARG, "unknown op %d", op);
+}

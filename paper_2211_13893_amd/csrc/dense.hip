@@ -1,0 +1,570 @@
+// Dense block kernels of the locally optimal block preconditioned conjugate
+// gradient (LOBPCG) iteration on the shifted A-harmonic pencil
+//      M x = nu T x,   T = S + s M,   nu = 1/(lambda + s)
+// (Sec. 3.3 and 4.3: S x = lambda M x is the mixed GEVP after eliminating the
+// Lagrange multiplier and the B1 unknowns).  Basis blocks are stored as
+// full-box vectors Z~ = [E Z; Z] together with A Z~, D A D Z~ and M Z, so the
+// Gram matrices of the Rayleigh-Ritz step are Z~^T A Z~ = Z^T S Z and
+// Z~^T (D A D) Z~ = Z^T M Z.
+//
+//  k_gram_partial / k_gram_reduce : Gram matrices over row chunks, summed in a
+//                                   fixed order (bitwise reproducible).
+//  k_rayleigh_ritz                : one workgroup per box: scaled Cholesky of
+//                                   the T-Gram with dropping of near-dependent
+//                                   columns, congruence of the M-Gram, cyclic
+//                                   parallel Jacobi, top-k Ritz coefficients.
+//  k_update                       : X <- Z Y, P <- Z Yp for the four kinds.
+//  k_residual / k_converge        : R = M X - nu T X on B2, the scale-free
+//                                   residual rho = |R| / (|MX| + nu |TX|),
+//                                   convergence and iteration bookkeeping.
+#include "internal.hpp"
+
+namespace msg {
+
+struct Blk3 {
+  const double* p[3];
+};
+
+#define GR_ROWS 32
+
+// grid (n_chunk, n_box, 2): z = 0 -> Z^T (A Z), z = 1 -> Z^T (DAD Z).
+// dynamic LDS = 2 * GR_ROWS * m doubles; thread owns outputs tid + 256 u.
+__global__ __launch_bounds__(256) void k_gram_partial(const BoxMeta* __restrict__ meta, int nblk,
+                                                      Blk3 Z, Blk3 AZ, Blk3 BZ, int k,
+                                                      int rows_per_chunk, int n_chunk,
+                                                      double* __restrict__ part,
+                                                      const int32_t* __restrict__ active) {
+  extern __shared__ double sm[];
+  int box = blockIdx.y, chunk = blockIdx.x, which = blockIdx.z;
+  if (active && !active[box]) return;
+  const BoxMeta& bm = meta[box];
+  const int m = nblk * k;
+  double* z = sm;
+  double* w = sm + GR_ROWS * m;
+  const Blk3& W = which ? BZ : AZ;
+  const int tid = threadIdx.x;
+  const int mm = m * m;
+  const int U = (mm + 255) / 256;   // <= 36 for m <= 96
+  double g[36];
+#pragma unroll
+  for (int u = 0; u < 36; ++u) g[u] = 0.0;
+  int r_begin = chunk * rows_per_chunk;
+  int r_end = min(bm.n_dof, r_begin + rows_per_chunk);
+  for (int r0 = r_begin; r0 < r_end; r0 += GR_ROWS) {
+    for (int t = tid; t < GR_ROWS * m; t += 256) {
+      int rr = t / m, col = t % m;
+      int blk = col / k, cc = col % k;
+      int row = r0 + rr;
+      double vz = 0.0, vw = 0.0;
+      if (row < r_end) {
+        int64_t o = bm.vec_off + (int64_t)row * k + cc;
+        vz = Z.p[blk][o];
+        vw = W.p[blk][o];
+      }
+      z[t] = vz;
+      w[t] = vw;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < GR_ROWS; ++rr) {
+      const double* zr = z + rr * m;
+      const double* wr = w + rr * m;
+#pragma unroll
+      for (int u = 0; u < 36; ++u) {
+        int o = tid + 256 * u;
+        if (u < U && o < mm) {
+          int i = o / m, j = o - (o / m) * m;
+          g[u] += zr[i] * wr[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* out = part + ((int64_t)box * n_chunk + chunk) * 2 * mm + (int64_t)which * mm;
+#pragma unroll
+  for (int u = 0; u < 36; ++u) {
+    int o = tid + 256 * u;
+    if (u < U && o < mm) out[o] = g[u];
+  }
+}
+
+// G[box][2][m][m] = sum over chunks (fixed order)
+__global__ void k_gram_reduce(int m, int n_chunk, const double* __restrict__ part,
+                              double* __restrict__ G, const int32_t* __restrict__ active) {
+  int box = blockIdx.y;
+  if (active && !active[box]) return;
+  int mm2 = 2 * m * m;
+  int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= mm2) return;
+  const double* p = part + (int64_t)box * n_chunk * mm2 + o;
+  double s = 0.0;
+  for (int c = 0; c < n_chunk; ++c) s += p[(int64_t)c * mm2];
+  G[(int64_t)box * mm2 + o] = s;
+}
+
+// One workgroup per box.  dynamic LDS: C[m][m+1], V[m][m+1] + small arrays.
+// Lg: global scratch m*m per box for the Cholesky factor.
+__global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, int nblk_x, double shift,
+                                                       const double* __restrict__ G,
+                                                       double* __restrict__ Lg,
+                                                       double* __restrict__ Y,
+                                                       double* __restrict__ Yp,
+                                                       double* __restrict__ nu,
+                                                       const int32_t* __restrict__ active) {
+  extern __shared__ double sm[];
+  int box = blockIdx.x;
+  if (active && !active[box]) return;
+  const int ld = m + 1;
+  double* C = sm;
+  double* V = C + m * ld;
+  double* dsc = V + m * ld;          // m scale factors
+  double* ev = dsc + m;              // m eigenvalues
+  double* rc = ev + m;               // m/2 rotation cos
+  double* rs = rc + m / 2;           // m/2 rotation sin
+  double* red = rs + m / 2;          // 256 reduction slots
+  int* drop = (int*)(red + 256);     // m
+  int* order = drop + m;             // m
+  const int tid = threadIdx.x;
+  const double* GA = G + (int64_t)box * 2 * m * m;
+  const double* GB = GA + m * m;
+  double* L = Lg + (int64_t)box * m * m;
+  // 1. scaled T-Gram
+  for (int i = tid; i < m; i += 256) {
+    double t = GA[i * m + i] + shift * GB[i * m + i];
+    dsc[i] = (t > 0.0) ? 1.0 / sqrt(t) : 0.0;
+    drop[i] = (t > 0.0) ? 0 : 1;
+  }
+  __syncthreads();
+  for (int t = tid; t < m * m; t += 256) {
+    int i = t / m, j = t % m;
+    double a = 0.5 * ((GA[i * m + j] + shift * GB[i * m + j]) + (GA[j * m + i] + shift * GB[j * m + i]));
+    C[i * ld + j] = a * dsc[i] * dsc[j];
+  }
+  __syncthreads();
+  // 2. Cholesky with dropping of near-dependent columns
+  const double tau = 1e-12;
+  for (int j = 0; j < m; ++j) {
+    double piv = C[j * ld + j];
+    bool dj = drop[j] || !(piv > tau);
+    if (dj) {
+      for (int t = tid; t < m; t += 256) {
+        if (t > j) C[t * ld + j] = 0.0;
+        if (t < j) C[j * ld + t] = 0.0;
+      }
+      if (tid == 0) { C[j * ld + j] = 1.0; drop[j] = 1; }
+      __syncthreads();
+      continue;
+    }
+    double sd = sqrt(piv);
+    for (int t = tid; t < m; t += 256) {
+      if (t > j) C[t * ld + j] /= sd;
+    }
+    __syncthreads();
+    if (tid == 0) C[j * ld + j] = sd;
+    for (int t = tid; t < m * m; t += 256) {
+      int i = t / m, c = t % m;
+      if (i > j && c > j && c <= i) C[i * ld + c] -= C[i * ld + j] * C[c * ld + j];
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < m * m; t += 256) {
+    int i = t / m, c = t % m;
+    L[t] = (c <= i) ? C[i * ld + c] : 0.0;
+  }
+  __syncthreads();
+  // 3. scaled M-Gram, dropped rows/columns removed
+  for (int t = tid; t < m * m; t += 256) {
+    int i = t / m, j = t % m;
+    double b = 0.5 * (GB[i * m + j] + GB[j * m + i]) * dsc[i] * dsc[j];
+    C[i * ld + j] = (drop[i] || drop[j]) ? 0.0 : b;
+  }
+  __syncthreads();
+  // 4. C <- L^{-1} C (column-wise forward substitution), then C <- C L^{-T} (row-wise)
+  for (int j = tid; j < m; j += 256) {
+    for (int i = 0; i < m; ++i) {
+      double s = C[i * ld + j];
+      for (int q = 0; q < i; ++q) s -= L[i * m + q] * C[q * ld + j];
+      C[i * ld + j] = s / L[i * m + i];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += 256) {
+    for (int j = 0; j < m; ++j) {
+      double s = C[i * ld + j];
+      for (int q = 0; q < j; ++q) s -= C[i * ld + q] * L[j * m + q];
+      C[i * ld + j] = s / L[j * m + j];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < m * m; t += 256) {
+    int i = t / m, j = t % m;
+    if (i < j) {
+      double a = 0.5 * (C[i * ld + j] + C[j * ld + i]);
+      C[i * ld + j] = a;
+      C[j * ld + i] = a;
+    }
+    V[i * ld + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // 5. cyclic parallel Jacobi (round-robin pairing, m even)
+  const int h = m / 2;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    // convergence test: off-diagonal mass vs. total
+    double off = 0.0, tot = 0.0;
+    for (int t = tid; t < m * m; t += 256) {
+      int i = t / m, j = t % m;
+      double a = C[i * ld + j];
+      tot += a * a;
+      if (i != j) off += a * a;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    double offs = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    double tots = red[0];
+    __syncthreads();
+    if (offs <= 1e-32 * tots || tots == 0.0) break;
+    for (int r = 0; r < m - 1; ++r) {
+      for (int i = tid; i < h; i += 256) {
+        int p, q;
+        if (i == 0) { p = 0; q = 1 + (r % (m - 1)); }
+        else { p = 1 + (r + i) % (m - 1); q = 1 + (r + m - 1 - i) % (m - 1); }
+        double apq = C[p * ld + q];
+        double app = C[p * ld + p], aqq = C[q * ld + q];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
+          double th = (aqq - app) / (2.0 * apq);
+          double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+        } else if (fabs(apq) > 0.0) {
+          C[p * ld + q] = 0.0;
+          C[q * ld + p] = 0.0;
+        }
+        rc[i] = c;
+        rs[i] = s;
+      }
+      __syncthreads();
+      // rows: C <- J^T C
+      for (int t = tid; t < h * m; t += 256) {
+        int i = t / m, col = t % m;
+        int p, q;
+        if (i == 0) { p = 0; q = 1 + (r % (m - 1)); }
+        else { p = 1 + (r + i) % (m - 1); q = 1 + (r + m - 1 - i) % (m - 1); }
+        double c = rc[i], s = rs[i];
+        double xp = C[p * ld + col], xq = C[q * ld + col];
+        C[p * ld + col] = c * xp - s * xq;
+        C[q * ld + col] = s * xp + c * xq;
+      }
+      __syncthreads();
+      // columns: C <- C J, V <- V J
+      for (int t = tid; t < h * m; t += 256) {
+        int i = t / m, row = t % m;
+        int p, q;
+        if (i == 0) { p = 0; q = 1 + (r % (m - 1)); }
+        else { p = 1 + (r + i) % (m - 1); q = 1 + (r + m - 1 - i) % (m - 1); }
+        double c = rc[i], s = rs[i];
+        double xp = C[row * ld + p], xq = C[row * ld + q];
+        C[row * ld + p] = c * xp - s * xq;
+        C[row * ld + q] = s * xp + c * xq;
+        double vp = V[row * ld + p], vq = V[row * ld + q];
+        V[row * ld + p] = c * vp - s * vq;
+        V[row * ld + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  // 6. sort eigenvalues descending (dropped directions have eigenvalue 0)
+  for (int i = tid; i < m; i += 256) {
+    double e = C[i * ld + i];
+    ev[i] = (e == e) ? e : -1.0e300;   // NaN ranks last
+    order[i] = i;
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += 256) {
+    double e = ev[i];
+    int rank = 0;
+    for (int j = 0; j < m; ++j) {
+      double f = ev[j];
+      if (f > e || (f == e && j < i)) ++rank;
+    }
+    order[rank] = i;
+  }
+  __syncthreads();
+  // 7. Ritz coefficients Y[:, c] = D L^{-T} V[:, order[c]]
+  double* Yb = Y + (int64_t)box * m * k;
+  double* Ypb = Yp + (int64_t)box * m * k;
+  for (int c = tid; c < k; c += 256) {
+    int col = order[c];
+    for (int i = m - 1; i >= 0; --i) {
+      double s = V[i * ld + col];
+      for (int q = i + 1; q < m; ++q) s -= L[q * m + i] * Yb[q * k + c];
+      Yb[i * k + c] = s / L[i * m + i];
+    }
+    nu[(int64_t)box * k + c] = ev[col];
+  }
+  __syncthreads();
+  for (int t = tid; t < m * k; t += 256) {
+    int i = t / k;
+    double v = Yb[t] * dsc[i];
+    v = drop[i] ? 0.0 : v;
+    Yb[t] = v;
+    Ypb[t] = (i < nblk_x * k) ? 0.0 : v;
+  }
+}
+
+struct Blk4x3 {
+  const double* p[4][3];
+};
+struct Out4 {
+  double* p[4];
+};
+
+// X_new = Z Y, P_new = Z Yp for kind = blockIdx.z (0: Z~, 1: A Z~, 2: DAD Z~, 3: M Z)
+// thread per (row, column quad); dynamic LDS = 2*m*k doubles
+__global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta, int nblk, int k,
+                                                Blk4x3 Z, Out4 OX, Out4 OP,
+                                                const double* __restrict__ Y,
+                                                const double* __restrict__ Yp,
+                                                const int32_t* __restrict__ active) {
+  extern __shared__ double sm[];
+  int box = blockIdx.y, kind = blockIdx.z;
+  const BoxMeta& bm = meta[box];
+  if (active && !active[box]) {
+    // converged box: carry X (and P) over to the output slots, which the host
+    // swaps with the current ones for every box
+    int64_t n = (int64_t)bm.n_dof * k;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+      OX.p[kind][bm.vec_off + t] = Z.p[kind][0][bm.vec_off + t];
+      if (OP.p[kind] && nblk == 3) OP.p[kind][bm.vec_off + t] = Z.p[kind][2][bm.vec_off + t];
+    }
+    return;
+  }
+  const int m = nblk * k;
+  double* ys = sm;
+  double* yps = sm + m * k;
+  const bool wantP = OP.p[kind] != nullptr;
+  for (int t = threadIdx.x; t < m * k; t += 256) {
+    ys[t] = Y[(int64_t)box * m * k + t];
+    yps[t] = wantP ? Yp[(int64_t)box * m * k + t] : 0.0;
+  }
+  __syncthreads();
+  int nq = (k + 3) >> 2;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)bm.n_dof * nq) return;
+  int row = (int)(t / nq), c0 = 4 * (int)(t % nq);
+  double ax[4] = {}, ap[4] = {};
+  for (int b = 0; b < nblk; ++b) {
+    const double* zr = Z.p[kind][b] + bm.vec_off + (int64_t)row * k;
+    for (int cc = 0; cc < k; ++cc) {
+      double zv = zr[cc];
+      int i = b * k + cc;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (c0 + j < k) {
+          ax[j] += zv * ys[i * k + c0 + j];
+          ap[j] += zv * yps[i * k + c0 + j];
+        }
+      }
+    }
+  }
+  double* ox = OX.p[kind] + bm.vec_off + (int64_t)row * k;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (c0 + j < k) ox[c0 + j] = ax[j];
+  if (wantP) {
+    double* op = OP.p[kind] + bm.vec_off + (int64_t)row * k;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (c0 + j < k) op[c0 + j] = ap[j];
+  }
+}
+
+// R = MX - nu (SX + s MX) on B2 rows (SX = (A X~) on B2), written into R (zero
+// elsewhere); partial column sums of |R|^2, |MX|^2, |TX|^2 per row chunk.
+// grid (n_chunk, n_box); thread = (row slot tid/32, column tid%32); k <= 32
+__global__ __launch_bounds__(256) void k_residual(const BoxMeta* __restrict__ meta,
+                                                  const uint8_t* __restrict__ cls, int k,
+                                                  double shift, const double* __restrict__ AX,
+                                                  const double* __restrict__ MX,
+                                                  const double* __restrict__ nu,
+                                                  double* __restrict__ R, int rows_per_chunk,
+                                                  int n_chunk, double* __restrict__ part,
+                                                  const int32_t* __restrict__ active) {
+  __shared__ double red[3][256];
+  int box = blockIdx.y, chunk = blockIdx.x;
+  if (active && !active[box]) return;
+  const BoxMeta& bm = meta[box];
+  const int tid = threadIdx.x, col = tid & 31, slot = tid >> 5;
+  double sr = 0.0, sm_ = 0.0, st = 0.0;
+  if (col < k) {
+    double v = nu[(int64_t)box * k + col];
+    int r_begin = chunk * rows_per_chunk;
+    int r_end = min(bm.n_dof, r_begin + rows_per_chunk);
+    for (int row = r_begin + slot; row < r_end; row += 8) {
+      int64_t o = bm.vec_off + (int64_t)row * k + col;
+      double r = 0.0;
+      if (cls[bm.dof_off + row] == 2) {
+        double mx = MX[o], sx = AX[o];
+        double tx = sx + shift * mx;
+        r = mx - v * tx;
+        sr += r * r;
+        sm_ += mx * mx;
+        st += tx * tx;
+      }
+      R[o] = r;
+    }
+  }
+  red[0][tid] = sr;
+  red[1][tid] = sm_;
+  red[2][tid] = st;
+  __syncthreads();
+  if (tid < 32) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int s = 0; s < 8; ++s) {
+      a += red[0][s * 32 + tid];
+      b += red[1][s * 32 + tid];
+      c += red[2][s * 32 + tid];
+    }
+    double* out = part + (((int64_t)box * n_chunk + chunk) * 3) * 32;
+    out[tid] = a;
+    out[32 + tid] = b;
+    out[64 + tid] = c;
+  }
+}
+
+// Per box: rho from the partial sums; converged when every one of the first
+// n_ev columns has rho <= tol.  Updates active/iters and the count of boxes
+// still active.  One thread per box.
+__global__ void k_converge(const BoxMeta* __restrict__ meta, int n_box, int k, int n_chunk,
+                           const double* __restrict__ part, const double* __restrict__ nu,
+                           double tol, double* __restrict__ rho, int32_t* __restrict__ active,
+                           int32_t* __restrict__ iters, int32_t* __restrict__ n_active,
+                           int count_iter) {
+  int box = blockIdx.x * blockDim.x + threadIdx.x;
+  if (box >= n_box) return;
+  if (!active[box]) return;
+  int nev = meta[box].n_ev;
+  bool ok = true;
+  for (int c = 0; c < k; ++c) {
+    double a = 0.0, b = 0.0, d = 0.0;
+    for (int ch = 0; ch < n_chunk; ++ch) {
+      const double* p = part + (((int64_t)box * n_chunk + ch) * 3) * 32;
+      a += p[c];
+      b += p[32 + c];
+      d += p[64 + c];
+    }
+    double v = nu[(int64_t)box * k + c];
+    double den = sqrt(b) + v * sqrt(d);
+    double r = den > 0.0 ? sqrt(a) / den : 0.0;
+    rho[(int64_t)box * k + c] = r;
+    if (c < nev && !(r <= tol)) ok = false;
+  }
+  if (ok) {
+    active[box] = 0;
+  } else {
+    iters[box] += count_iter;
+    atomicAdd(n_active, 1);
+  }
+}
+
+// random start block on B2 (counter-based hash, uniform in [-1, 1)), zero elsewhere
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_random_start(const BoxMeta* __restrict__ meta, const uint8_t* __restrict__ cls,
+                               int k, uint64_t seed, double* __restrict__ X) {
+  int box = blockIdx.y;
+  const BoxMeta& bm = meta[box];
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)bm.n_dof * k) return;
+  int row = (int)(t / k), col = (int)(t % k);
+  double v = 0.0;
+  if (cls[bm.dof_off + row] == 2) {
+    uint64_t h = mix64(seed ^ mix64(((uint64_t)bm.sd << 40) ^ ((uint64_t)row << 8) ^ (uint64_t)col));
+    v = (double)(h >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+  }
+  X[bm.vec_off + t] = v;
+}
+
+// copy a caller start block (boundary values on B2 DoFs, box layout [n_dof][k]) into X
+__global__ void k_copy_start(const BoxMeta* __restrict__ meta, const uint8_t* __restrict__ cls,
+                             int k, const double* __restrict__ X0, double* __restrict__ X) {
+  int box = blockIdx.y;
+  const BoxMeta& bm = meta[box];
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)bm.n_dof * k) return;
+  int row = (int)(t / k);
+  X[bm.vec_off + t] = (cls[bm.dof_off + row] == 2) ? X0[bm.vec_off + t] : 0.0;
+}
+
+// Output: lambda ascending, unit 2-norm eigenvectors on all box DoFs (0 on B3)
+// with the entry of largest magnitude positive, rho per pair.  One workgroup per box.
+__global__ __launch_bounds__(256) void k_output(const BoxMeta* __restrict__ meta, int k,
+                                                double shift, const double* __restrict__ X,
+                                                const double* __restrict__ nu,
+                                                const double* __restrict__ rho,
+                                                double* __restrict__ evals,
+                                                double* __restrict__ evecs,
+                                                double* __restrict__ resid) {
+  __shared__ double sn[256];
+  __shared__ double sa[256];
+  __shared__ int si[256];
+  __shared__ double scale[32];
+  int box = blockIdx.x;
+  const BoxMeta& bm = meta[box];
+  const int tid = threadIdx.x, col = tid & 31, slot = tid >> 5;
+  const int nev = bm.n_ev;
+  double s2 = 0.0, amax = -1.0;
+  int imax = 0x7fffffff;
+  if (col < nev) {
+    for (int row = slot; row < bm.n_dof; row += 8) {
+      double v = X[bm.vec_off + (int64_t)row * k + col];
+      s2 += v * v;
+      double a = fabs(v);
+      if (a > amax) { amax = a; imax = row; }
+    }
+  }
+  sn[tid] = s2;
+  sa[tid] = amax;
+  si[tid] = imax;
+  __syncthreads();
+  if (tid < 32 && col < nev) {
+    double n2 = 0.0, am = -1.0;
+    int im = 0x7fffffff;
+    for (int s = 0; s < 8; ++s) {
+      n2 += sn[s * 32 + tid];
+      double a = sa[s * 32 + tid];
+      int ii = si[s * 32 + tid];
+      if (a > am || (a == am && ii < im)) { am = a; im = ii; }
+    }
+    if (im < 0 || im >= bm.n_dof) im = 0;   // all-NaN column: keep the read in bounds
+    double v = X[bm.vec_off + (int64_t)im * k + tid];
+    double sg = (v < 0.0) ? -1.0 : 1.0;
+    scale[tid] = sg / sqrt(n2);
+    double nv = nu[(int64_t)box * k + tid];
+    evals[bm.eval_off + tid] = 1.0 / nv - shift;
+    resid[bm.eval_off + tid] = rho[(int64_t)box * k + tid];
+  }
+  __syncthreads();
+  for (int64_t t = tid; t < (int64_t)bm.n_dof * nev; t += 256) {
+    int row = (int)(t / nev), c = (int)(t % nev);
+    evecs[bm.evec_off + t] = X[bm.vec_off + (int64_t)row * k + c] * scale[c];
+  }
+}
+
+}  // namespace msg

@@ -1,0 +1,61 @@
+// Internal definitions shared by the HIP translation units of libmsgfem.
+//
+// Data layout in HBM (one "plan" = one mesh, one decomposition, one batch of
+// oversampled subdomains):
+//   * every oversampled box Omega_j^* is a node grid mx*my*mz, nodes x fastest,
+//     DoF = 3*node + component;
+//   * the box stiffness is a block-27 stencil stored structure-of-arrays:
+//     stencil[(nb*9 + 3*cr + cc) * n_nodes + node], nb = (dx+1)+3(dy+1)+9(dz+1);
+//   * block vectors are row-major [n_dof][k] (k columns contiguous per DoF);
+//   * banded SPD factors are 32x32 tiles: tile (I, I-s) at
+//     ((I*BT + s) * 1024), row-major inside the tile, s = 0 the diagonal tile;
+//     the inverses of the diagonal tiles follow in a separate NT*1024 array.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MSG_TILE 32
+#define MSG_TILE2 1024
+
+namespace msg {
+
+// Per-box metadata, uploaded once per plan.
+struct BoxMeta {
+  int32_t sd;                 // subdomain id in the decomposition
+  int32_t mx, my, mz;         // box node dims
+  int32_t g0[3];              // global node index of box node (0,0,0)
+  int32_t olo[3], ohi[3];     // Omega_j node box (global, inclusive)
+  int32_t iface_lo[3];        // 1 if the low face of the box on this axis is interior boundary
+  int32_t iface_hi[3];
+  int32_t olo_int[3];         // 1 if the low face of Omega_j is interior (not on the mesh boundary)
+  int32_t ohi_int[3];
+  int32_t sub_lo[3], sub_hi[3];  // node sub-box (box-relative, inclusive) holding B1 (and B3)
+  int32_t n_nodes, n_dof;
+  int32_t n_ev;
+  // factor geometry (tiles of 32): A11 on the sub-box, Ahat on the full box
+  int32_t nt11, bt11, n11;    // tile rows, band tiles, matrix order (unpadded)
+  int32_t nth, bth, nh;
+  int32_t pad_;
+  int64_t node_off;           // offset into per-node arrays of the batch
+  int64_t dof_off;            // offset into per-dof arrays
+  int64_t vec_off;            // offset (doubles) of this box inside one block-vector array
+  int64_t f11_off, f11i_off;  // band tiles / inverse diag tiles of A11 (doubles)
+  int64_t fh_off, fhi_off;    // same for Ahat
+  int64_t evec_off;           // offset (doubles) into the eigenvector output
+  int64_t eval_off;           // offset into eigenvalue output
+};
+
+struct MeshDev {
+  int32_t nx, ny, nz;
+  int32_t n_mat;
+  const double* xyz;
+  const int32_t* elem_mat;
+  const double* materials;
+  const uint8_t* dirichlet;
+};
+
+__host__ __device__ inline int nb_index(int dx, int dy, int dz) {
+  return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+}
+
+}  // namespace msg

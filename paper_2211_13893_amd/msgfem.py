@@ -1,0 +1,260 @@
+"""Python binding of libmsgfem (the HIP library declared in include/msgfem.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  PyTorch provides device memory (the caller-owned buffers of the ABI)
+and the stream.  Loading fails loudly when the library has not been built
+(``python -m paper_2211_13893_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsgfem.so")
+
+MSGFEM_OK, MSGFEM_EARG, MSGFEM_EHIP, MSGFEM_ESIZE = 0, -1, -2, -3
+OP_A, OP_DAD, OP_A11_SOLVE, OP_AHAT_SOLVE = 0, 1, 2, 3
+STATUS_NOT_CONVERGED, STATUS_BAD_PIVOT, STATUS_NONFINITE = 1, 4, 8
+
+
+class msgfem_mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("n_mat", ctypes.c_int32), ("node_xyz", ctypes.c_void_p),
+                ("elem_mat", ctypes.c_void_p), ("materials", ctypes.c_void_p),
+                ("dirichlet", ctypes.c_void_p)]
+
+
+class msgfem_decomp(ctypes.Structure):
+    _fields_ = [("nsd", ctypes.c_int32), ("cores", ctypes.c_void_p),
+                ("overlap", ctypes.c_int32), ("ovs", ctypes.c_void_p)]
+
+
+class msgfem_eig_opts(ctypes.Structure):
+    _fields_ = [("shift", ctypes.c_double), ("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class msgfem_sizes(ctypes.Structure):
+    _fields_ = [("ops_bytes", ctypes.c_int64), ("work_bytes", ctypes.c_int64),
+                ("n_eval", ctypes.c_int64), ("n_evec", ctypes.c_int64), ("n_dof", ctypes.c_int64),
+                ("block", ctypes.c_int32), ("n_box", ctypes.c_int32)]
+
+
+class msgfem_box_info(ctypes.Structure):
+    _fields_ = [("sd", ctypes.c_int32), ("mx", ctypes.c_int32), ("my", ctypes.c_int32),
+                ("mz", ctypes.c_int32), ("g0", ctypes.c_int32 * 3), ("n_nodes", ctypes.c_int32),
+                ("n_dof", ctypes.c_int32), ("n_ev", ctypes.c_int32), ("n1", ctypes.c_int32),
+                ("n2", ctypes.c_int32), ("n3", ctypes.c_int32),
+                ("stencil_off", ctypes.c_int64), ("cls_off", ctypes.c_int64),
+                ("mu_off", ctypes.c_int64), ("vec_off", ctypes.c_int64),
+                ("evec_off", ctypes.c_int64), ("eval_off", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+SIGNATURES = {
+    "msgfem_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
+                                          ctypes.POINTER(msgfem_mesh), ctypes.POINTER(msgfem_decomp),
+                                          _P, _P, ctypes.c_int32, ctypes.POINTER(msgfem_eig_opts)]),
+    "msgfem_plan_destroy": (None, [_P]),
+    "msgfem_plan_error": (ctypes.c_char_p, [_P]),
+    "msgfem_plan_sizes": (ctypes.c_int, [_P, ctypes.POINTER(msgfem_sizes)]),
+    "msgfem_plan_box": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(msgfem_box_info)]),
+    "msgfem_assemble_local": (ctypes.c_int, [_P, _P, _P, _P]),
+    "msgfem_local_eigs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "msgfem_local_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmsgfem.so and declare its C signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2211_13893_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class MsgfemError(RuntimeError):
+    pass
+
+
+def _check(rc: int, plan=None, what: str = ""):
+    if rc != MSGFEM_OK:
+        msg = ""
+        if plan:
+            m = load().msgfem_plan_error(plan)
+            msg = m.decode() if m else ""
+        raise MsgfemError(f"{what} failed with code {rc}: {msg}")
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else 0
+
+
+def _stream_handle(torch, device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class LocalStage:
+    """One plan of the local spectral stage: a mesh, its decomposition and a batch.
+
+    ``problem`` is a :class:`paper_2211_13893_amd.synth.Problem`.  Device
+    copies of the mesh arrays are kept for the plan's lifetime.
+    """
+
+    def __init__(self, problem, batch: Optional[Sequence[int]] = None,
+                 n_ev: Optional[Sequence[int]] = None, device: str = "cuda:0", shift: float = 1.0,
+                 tol: float = 1e-6, maxit: int = 200, block: int = 0, seed: int = 1234):
+        import torch
+        self.torch = torch
+        lib = load()
+        self.lib = lib
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise MsgfemError("LocalStage needs a GPU device")
+        dev = self.device
+        p = problem
+        self.problem = p
+        self.batch = np.asarray(p.batch if batch is None else batch, dtype=np.int32)
+        nev = np.asarray([int(p.n_ev[j]) for j in self.batch] if n_ev is None else n_ev, dtype=np.int32)
+        self.n_ev = nev
+        self._xyz = torch.as_tensor(np.ascontiguousarray(p.xyz, dtype=np.float64), device=dev)
+        self._emat = torch.as_tensor(np.ascontiguousarray(p.elem_mat, dtype=np.int32), device=dev)
+        self._mats = torch.as_tensor(np.ascontiguousarray(p.materials, dtype=np.float64), device=dev)
+        self._dir = torch.as_tensor(np.ascontiguousarray(p.dirichlet, dtype=np.uint8), device=dev)
+        self.mesh = msgfem_mesh(p.nx, p.ny, p.nz, p.materials.shape[0], _ptr(self._xyz),
+                                _ptr(self._emat), _ptr(self._mats), _ptr(self._dir))
+        self._cores = np.ascontiguousarray(p.cores, dtype=np.int32)
+        self._ovs = np.ascontiguousarray(p.ovs, dtype=np.int32)
+        dec = msgfem_decomp(p.nsd, self._cores.ctypes.data, p.overlap, self._ovs.ctypes.data)
+        opts = msgfem_eig_opts(shift, tol, maxit, block, 0, 0, seed)
+        self.shift = shift
+        plan = _P()
+        idx = dev.index if dev.index is not None else torch.cuda.current_device()
+        rc = lib.msgfem_plan_create(ctypes.byref(plan), idx, ctypes.byref(self.mesh),
+                                    ctypes.byref(dec), self.batch.ctypes.data, nev.ctypes.data,
+                                    int(self.batch.size), ctypes.byref(opts))
+        self.plan = plan
+        _check(rc, plan, "msgfem_plan_create")
+        s = msgfem_sizes()
+        _check(lib.msgfem_plan_sizes(plan, ctypes.byref(s)), plan, "msgfem_plan_sizes")
+        self.sizes = s
+        self.k = s.block
+        self.boxes = []
+        for b in range(self.batch.size):
+            bi = msgfem_box_info()
+            _check(lib.msgfem_plan_box(plan, b, ctypes.byref(bi)), plan, "msgfem_plan_box")
+            self.boxes.append(bi)
+        self.ops = None
+        self.work = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "plan", None):
+                self.lib.msgfem_plan_destroy(self.plan)
+                self.plan = None
+        except Exception:
+            pass
+
+    # -- buffers -------------------------------------------------------
+    def _alloc_ops(self):
+        if self.ops is None:
+            self.ops = self.torch.empty(self.sizes.ops_bytes, dtype=self.torch.uint8, device=self.device)
+        return self.ops
+
+    def _alloc_work(self):
+        if self.work is None:
+            self.work = self.torch.empty(self.sizes.work_bytes, dtype=self.torch.uint8, device=self.device)
+        return self.work
+
+    # -- ABI calls -----------------------------------------------------
+    def msgfem_assemble_local(self, status=None):
+        torch = self.torch
+        ops = self._alloc_ops()
+        if status is None:
+            status = torch.zeros(len(self.batch), dtype=torch.int32, device=self.device)
+        rc = self.lib.msgfem_assemble_local(self.plan, _ptr(ops), _ptr(status),
+                                            _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_assemble_local")
+        self.status = status
+        return status
+
+    def msgfem_local_eigs(self, x0=None, out=None):
+        torch = self.torch
+        if self.ops is None:
+            raise MsgfemError("assemble first")
+        work = self._alloc_work()
+        s = self.sizes
+        nb = len(self.batch)
+        if out is None:
+            out = dict(evals=torch.empty(s.n_eval, dtype=torch.float64, device=self.device),
+                       evecs=torch.empty(s.n_evec, dtype=torch.float64, device=self.device),
+                       resid=torch.empty(s.n_eval, dtype=torch.float64, device=self.device),
+                       iters=torch.empty(nb, dtype=torch.int32, device=self.device))
+        rc = self.lib.msgfem_local_eigs(self.plan, _ptr(self.ops), _ptr(work), _ptr(x0),
+                                        _ptr(out["evals"]), _ptr(out["evecs"]), _ptr(out["resid"]),
+                                        _ptr(out["iters"]), _ptr(self.status),
+                                        _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_local_eigs")
+        out["status"] = self.status
+        return out
+
+    def msgfem_local_apply(self, op: int, x, k: Optional[int] = None):
+        torch = self.torch
+        k = self.k if k is None else k
+        y = torch.zeros_like(x)
+        work = self._alloc_work() if op in (OP_A11_SOLVE, OP_AHAT_SOLVE) else None
+        rc = self.lib.msgfem_local_apply(self.plan, _ptr(self.ops), _ptr(work), op, k, _ptr(x), _ptr(y),
+                                         _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_local_apply")
+        return y
+
+    # -- views ---------------------------------------------------------
+    def stencil(self, b: int):
+        bi = self.boxes[b]
+        n = bi.n_nodes * 243 * 8
+        return self.ops[bi.stencil_off:bi.stencil_off + n].view(self.torch.float64).view(243, bi.n_nodes)
+
+    def classes(self, b: int):
+        bi = self.boxes[b]
+        return self.ops[bi.cls_off:bi.cls_off + bi.n_dof]
+
+    def mu(self, b: int):
+        bi = self.boxes[b]
+        return self.ops[bi.mu_off:bi.mu_off + 8 * bi.n_dof].view(self.torch.float64)
+
+    def box_vector(self, vec, b: int, k: Optional[int] = None):
+        """View of box b inside a block vector [sum n_dof][k] (flat)."""
+        k = self.k if k is None else k
+        bi = self.boxes[b]
+        return vec[bi.vec_off:bi.vec_off + bi.n_dof * k].view(bi.n_dof, k)
+
+    def new_block(self, k: Optional[int] = None):
+        k = self.k if k is None else k
+        return self.torch.zeros(self.sizes.n_dof * k, dtype=self.torch.float64, device=self.device)
+
+    def eigvals(self, out, b: int):
+        bi = self.boxes[b]
+        return out["evals"][bi.eval_off:bi.eval_off + bi.n_ev]
+
+    def eigvecs(self, out, b: int):
+        bi = self.boxes[b]
+        return out["evecs"][bi.evec_off:bi.evec_off + bi.n_dof * bi.n_ev].view(bi.n_dof, bi.n_ev)
+
+    def resid(self, out, b: int):
+        bi = self.boxes[b]
+        return out["resid"][bi.eval_off:bi.eval_off + bi.n_ev]
