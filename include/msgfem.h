@@ -169,6 +169,27 @@ int msgfem_local_eigs(msgfem_plan *plan, const void *ops, void *work, const doub
 int msgfem_local_apply(msgfem_plan *plan, const void *ops, void *work, int32_t op, int32_t k,
                        const double *x, double *y, void *stream);
 
+/* Kernel timing.  msgfem_profile(plan, 1) clears the counters and starts
+ * recording a pair of HIP events around every launch of the library's hot
+ * kernels on the stream the kernel is launched on; msgfem_profile(plan, 0)
+ * stops recording.  msgfem_profile_stats synchronises the recorded events and
+ * returns, per kernel that ran, the launch count, the summed device time and
+ * the summed algorithmic bytes and flops of those launches (the minimal
+ * traffic of the algorithm, e.g. the band entries of a factor read once per
+ * triangular sweep, not the bytes the hardware moved).  `out` may be NULL to
+ * query the count; at most max_out records are written, *n_out is the total. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double ms;
+  double bytes;
+  double flops;
+} msgfem_kernel_stat;
+
+int msgfem_profile(msgfem_plan *plan, int32_t enable);
+int msgfem_profile_stats(msgfem_plan *plan, msgfem_kernel_stat *out, int32_t max_out,
+                         int32_t *n_out);
+
 #ifdef __cplusplus
 }
 #endif

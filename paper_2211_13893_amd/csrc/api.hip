@@ -76,6 +76,63 @@ struct msgfem_plan {
           w_rpart = 0, w_active = 0, w_iters = 0, w_nact = 0, w_scr = 0, work_bytes = 0;
   int64_t scr_stride = 0;
   std::string err;
+  // kernel timing (msgfem_profile)
+  struct ProfRec {
+    int kernel;
+    hipEvent_t b, e;
+    double bytes, flops;
+  };
+  bool prof_on = false;
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[16] = {}, prof_bytes[16] = {}, prof_flops[16] = {};
+  int64_t prof_launches[16] = {};
+  ~msgfem_plan();
+};
+
+static const char* const PROF_NAMES[] = {"assemble", "band_build", "band_potrf", "band_solve",
+                                         "spmm", "gram", "rayleigh_ritz", "update", "residual"};
+enum { PK_ASSEMBLE, PK_BUILD, PK_POTRF, PK_SOLVE, PK_SPMM, PK_GRAM, PK_RR, PK_UPDATE, PK_RESID, PK_N };
+
+msgfem_plan::~msgfem_plan() {
+  for (auto& r : prof_pending) { ev_pool.push_back(r.b); ev_pool.push_back(r.e); }
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+}
+
+static hipEvent_t prof_event(msgfem_plan* p) {
+  if (!p->ev_pool.empty()) {
+    hipEvent_t e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records HIP events around one launch on the launch stream when profiling is on.
+struct ProfScope {
+  msgfem_plan* p;
+  int kernel;
+  hipStream_t s;
+  hipEvent_t b = nullptr;
+  double bytes, flops;
+  ProfScope(msgfem_plan* p_, int kernel_, hipStream_t s_, double bytes_, double flops_)
+      : p(p_), kernel(kernel_), s(s_), bytes(bytes_), flops(flops_) {
+    if (p->prof_on) {
+      b = prof_event(p);
+      if (b) (void)hipEventRecord(b, s);
+    }
+  }
+  ~ProfScope() {
+    if (p->prof_on && b) {
+      hipEvent_t e = prof_event(p);
+      if (e) {
+        (void)hipEventRecord(e, s);
+        p->prof_pending.push_back({kernel, b, e, bytes, flops});
+      }
+    }
+  }
 };
 
 static int fail(msgfem_plan* p, int code, const char* fmt, ...) {
@@ -322,6 +379,26 @@ extern "C" int msgfem_plan_box(const msgfem_plan* p, int32_t b, msgfem_box_info*
   return MSGFEM_OK;
 }
 
+// exact number of stored entries of a lower band of order n and half-bandwidth b
+static double band_entries(double n, double b) {
+  if (b > n - 1) b = n - 1;
+  return n * (b + 1) - b * (b + 1) / 2;
+}
+
+static void band_nb(const BoxMeta& m, int kind, double* n, double* b) {
+  int sx, sy;
+  if (kind == 0) {
+    sx = m.sub_hi[0] - m.sub_lo[0] + 1;
+    sy = m.sub_hi[1] - m.sub_lo[1] + 1;
+    *n = m.n11;
+  } else {
+    sx = m.mx;
+    sy = m.my;
+    *n = m.nh;
+  }
+  *b = 3.0 * (sx * sy + sx + 1) + 2;
+}
+
 static MeshDev mesh_dev(const msgfem_plan* p) {
   MeshDev md;
   md.nx = p->mesh.nx; md.ny = p->mesh.ny; md.nz = p->mesh.nz; md.n_mat = p->mesh.n_mat;
@@ -393,6 +470,9 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
   MeshDev md = mesh_dev(p);
   {
     dim3 grid((p->max_nodes + 3) / 4, nb);
+    double by = 0;
+    for (auto& m : p->meta) by += 243.0 * 8 * m.n_nodes;
+    ProfScope ps(p, PK_ASSEMBLE, s, by, 0.0);
     k_assemble<<<grid, 256, 0, s>>>(v.meta, md, v.ctab, v.stencil);
     LAUNCHCHK(p);
   }
@@ -405,10 +485,25 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
     int64_t tot = p->max_fac_tiles * 1024;
     int64_t blocks = std::min<int64_t>((tot + 255) / 256, 65535);
     dim3 grid((unsigned)blocks, nb);
+    double by = 0;
+    for (auto& m : p->meta) {
+      double n, b;
+      band_nb(m, kind, &n, &b);
+      by += 8.0 * band_entries(n, b);
+    }
+    ProfScope ps(p, PK_BUILD, s, by, 0.0);
     k_band_build<<<grid, 256, 0, s>>>(v.meta, kind, v.stencil, v.cls, v.mu1, p->opts.shift, v.fac);
     LAUNCHCHK(p);
   }
   for (int kind = 0; kind < 2; ++kind) {
+    double by = 0, fl = 0;
+    for (auto& m : p->meta) {
+      double n, b;
+      band_nb(m, kind, &n, &b);
+      by += 2 * 8.0 * band_entries(n, b);
+      fl += n * b * b - 2.0 / 3.0 * b * b * b;
+    }
+    ProfScope ps(p, PK_POTRF, s, by, fl);
     k_band_potrf<<<nb, 256, 0, s>>>(v.meta, kind, v.fac, status);
     LAUNCHCHK(p);
   }
@@ -461,6 +556,8 @@ struct Ctx {
   Work w;
   hipStream_t s;
   int nb, k;
+  std::vector<int32_t> act_h;   // host copy of the active flags (all 1 when unknown)
+  bool counts(int b, const int32_t* act) const { return !act || act_h.empty() || act_h[b]; }
 };
 
 // Kernels whose dynamic LDS may exceed 64 KiB declare it once per process.
@@ -483,6 +580,15 @@ static int spmm(Ctx& c, const double* X, double* Y, double* Y2, int kk, int ycla
                 const int32_t* active) {
   int nq = (kk + 3) / 4;
   dim3 grid((unsigned)(((int64_t)c.p->max_nodes * nq + 255) / 256), c.nb);
+  double by = 0, fl = 0;
+  for (int b = 0; b < c.nb; ++b) {
+    if (!c.counts(b, active)) continue;
+    const BoxMeta& m = c.p->meta[b];
+    int nout = (Y ? 1 : 0) + (Y2 ? 1 : 0);
+    by += 243.0 * 8 * m.n_nodes + 8.0 * m.n_dof * kk * (1 + nout);
+    fl += 2.0 * 243 * m.n_nodes * kk * (Y2 ? 2 : 1);
+  }
+  ProfScope ps(c.p, PK_SPMM, c.s, by, fl);
   k_spmm<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.stencil, c.v.cls, c.v.mu1, X, Y, Y2, kk, yclasses, scale,
                                 active);
   LAUNCHCHK(c.p);
@@ -494,6 +600,16 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
   int nchunk = (kk + KC - 1) / KC;
   dim3 grid(nchunk * c.nb);
   size_t lds = (size_t)c.p->max_bt * 32 * KC * 8;
+  double by = 0, fl = 0;
+  for (int b = 0; b < c.nb; ++b) {
+    if (!c.counts(b, active)) continue;
+    double n, bw;
+    band_nb(c.p->meta[b], kind, &n, &bw);
+    double e = band_entries(n, bw);
+    by += 2 * 8.0 * e + 2 * 8.0 * n * kk;
+    fl += 4.0 * e * kk;
+  }
+  ProfScope ps(c.p, PK_SOLVE, c.s, by, fl);
   k_band_solve<KC><<<grid, 256, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, c.v.fac, c.v.cls, in, out, kk,
                                             out_classes, zero_rest, c.w.scr, c.p->scr_stride, active);
   LAUNCHCHK(c.p);
@@ -526,6 +642,14 @@ static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double*
   }
   dim3 grid(c.p->n_gchunk, c.nb, 2);
   size_t lds = (size_t)2 * 32 * m * 8;
+  double by = 0, fl = 0;
+  for (int b = 0; b < c.nb; ++b) {
+    if (!c.counts(b, act)) continue;
+    const BoxMeta& mt = c.p->meta[b];
+    by += 3 * 8.0 * mt.n_dof * m;
+    fl += 2 * 2.0 * mt.n_dof * m * m;
+  }
+  ProfScope ps(c.p, PK_GRAM, c.s, by, fl);
   k_gram_partial<<<grid, 256, lds, c.s>>>(c.v.meta, nblk, Z, A, B, k, GRAM_ROWS, c.p->n_gchunk, c.w.part,
                                           act);
   LAUNCHCHK(c.p);
@@ -533,6 +657,7 @@ static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double*
   k_gram_reduce<<<g2, 256, 0, c.s>>>(m, c.p->n_gchunk, c.w.part, c.w.G, act);
   LAUNCHCHK(c.p);
   size_t lds_rr = ((size_t)2 * m * (m + 1) + 3 * m + 256 + m) * 8;
+  ProfScope ps2(c.p, PK_RR, c.s, 0.0, 0.0);
   k_rayleigh_ritz<<<c.nb, 256, lds_rr, c.s>>>(m, k, 1, c.p->opts.shift, c.w.G, c.w.L, c.w.Y, c.w.Yp,
                                                c.w.nu, act);
   LAUNCHCHK(c.p);
@@ -605,9 +730,11 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
                                                   p->opts.tol, c.w.rho, act, c.w.iters, c.w.nact,
                                                   it < p->opts.maxit ? 1 : 0);
       LAUNCHCHK(p);
-      int32_t nact = 0;
-      HIPCHK(p, hipMemcpyAsync(&nact, c.w.nact, 4, hipMemcpyDeviceToHost, c.s));
+      c.act_h.resize(nb);
+      HIPCHK(p, hipMemcpyAsync(c.act_h.data(), act, nb * 4, hipMemcpyDeviceToHost, c.s));
       HIPCHK(p, hipStreamSynchronize(c.s));
+      int nact = 0;
+      for (int b = 0; b < nb; ++b) nact += c.act_h[b] != 0;
       if (nact == 0 || it == p->opts.maxit) break;
     }
     // W = preconditioned residual: B2 trace of (A + s DAD)^{-1} [0; R]
@@ -627,6 +754,14 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
     }
     int nq = (k + 3) / 4;
     dim3 grid((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, 4);
+    double by = 0, fl = 0;
+    for (int b = 0; b < nb; ++b) {
+      if (!c.counts(b, act)) continue;
+      const BoxMeta& mt = p->meta[b];
+      by += 4 * 8.0 * mt.n_dof * k * (nblk + 2);
+      fl += 4 * 2 * 2.0 * mt.n_dof * (nblk * k) * k;
+    }
+    ProfScope ps(p, PK_UPDATE, c.s, by, fl);
     k_update<<<grid, 256, (size_t)2 * nblk * k * k * 8, c.s>>>(c.v.meta, nblk, k, Z, OX, OP, c.w.Y,
                                                                 c.w.Yp, act);
     LAUNCHCHK(p);
@@ -680,4 +815,50 @@ extern "C" int msgfem_local_apply(msgfem_plan* p, const void* ops, void* work, i
   if (op == 2) return solve(c, 0, x, y, kk, 1 << 1, 1, nullptr) ? MSGFEM_EHIP : 0;
   if (op == 3) return solve(c, 1, x, y, kk, (1 << 1) | (1 << 2), 1, nullptr) ? MSGFEM_EHIP : 0;
   return fail(p, MSGFEM_EARG, "unknown op %d", op);
+}
+
+extern "C" int msgfem_profile(msgfem_plan* p, int32_t enable) {
+  if (!p) return MSGFEM_EARG;
+  if (enable) {
+    for (auto& r : p->prof_pending) { p->ev_pool.push_back(r.b); p->ev_pool.push_back(r.e); }
+    p->prof_pending.clear();
+    for (int i = 0; i < PK_N; ++i) {
+      p->prof_ms[i] = p->prof_bytes[i] = p->prof_flops[i] = 0.0;
+      p->prof_launches[i] = 0;
+    }
+  }
+  p->prof_on = enable != 0;
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_profile_stats(msgfem_plan* p, msgfem_kernel_stat* out, int32_t max_out,
+                                    int32_t* n_out) {
+  if (!p || !n_out) return MSGFEM_EARG;
+  for (auto& r : p->prof_pending) {
+    HIPCHK(p, hipEventSynchronize(r.e));
+    float ms = 0.f;
+    HIPCHK(p, hipEventElapsedTime(&ms, r.b, r.e));
+    p->prof_ms[r.kernel] += ms;
+    p->prof_bytes[r.kernel] += r.bytes;
+    p->prof_flops[r.kernel] += r.flops;
+    p->prof_launches[r.kernel] += 1;
+    p->ev_pool.push_back(r.b);
+    p->ev_pool.push_back(r.e);
+  }
+  p->prof_pending.clear();
+  int n = 0;
+  for (int i = 0; i < PK_N; ++i) {
+    if (!p->prof_launches[i]) continue;
+    if (out && n < max_out) {
+      std::memset(&out[n], 0, sizeof(msgfem_kernel_stat));
+      std::strncpy(out[n].name, PROF_NAMES[i], sizeof(out[n].name) - 1);
+      out[n].launches = p->prof_launches[i];
+      out[n].ms = p->prof_ms[i];
+      out[n].bytes = p->prof_bytes[i];
+      out[n].flops = p->prof_flops[i];
+    }
+    ++n;
+  }
+  *n_out = n;
+  return MSGFEM_OK;
 }

@@ -55,6 +55,11 @@ class msgfem_box_info(ctypes.Structure):
                 ("evec_off", ctypes.c_int64), ("eval_off", ctypes.c_int64)]
 
 
+class msgfem_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 SIGNATURES = {
     "msgfem_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
@@ -67,6 +72,9 @@ SIGNATURES = {
     "msgfem_assemble_local": (ctypes.c_int, [_P, _P, _P, _P]),
     "msgfem_local_eigs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "msgfem_local_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    "msgfem_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "msgfem_profile_stats": (ctypes.c_int, [_P, ctypes.POINTER(msgfem_kernel_stat), ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None
@@ -222,6 +230,18 @@ class LocalStage:
                                          _stream_handle(torch, self.device))
         _check(rc, self.plan, "msgfem_local_apply")
         return y
+
+    def msgfem_profile(self, enable: bool):
+        _check(self.lib.msgfem_profile(self.plan, 1 if enable else 0), self.plan, "msgfem_profile")
+
+    def msgfem_profile_stats(self):
+        n = ctypes.c_int32()
+        arr = (msgfem_kernel_stat * 16)()
+        _check(self.lib.msgfem_profile_stats(self.plan, arr, 16, ctypes.byref(n)), self.plan,
+               "msgfem_profile_stats")
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms,
+                                           bytes=arr[i].bytes, flops=arr[i].flops)
+                for i in range(min(n.value, 16))}
 
     # -- views ---------------------------------------------------------
     def stencil(self, b: int):
