@@ -21,7 +21,9 @@ __global__ void k_assemble(const BoxMeta*, MeshDev, const double*, double*);
 __global__ void k_classes_mu(const BoxMeta*, MeshDev, int, const int32_t*, uint8_t*, double*);
 __global__ void k_band_build(const BoxMeta*, int, const double*, const uint8_t*, const double*, double,
                              double*);
-__global__ void k_band_potrf(const BoxMeta*, int, double*, int32_t*);
+__global__ void k_chol_update(const BoxMeta*, int, double*, int32_t*);
+__global__ void k_chol_panel(const BoxMeta*, int, double*);
+__global__ void k_chol_unit(const BoxMeta*, double*);
 template <int KC>
 __global__ void k_band_solve(const BoxMeta*, int, int, int, const double*, const uint8_t*, const double*,
                              double*, int, int, int, double*, int64_t, const int32_t*);
@@ -287,7 +289,7 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     p->max_fac_tiles = std::max(p->max_fac_tiles, (int64_t)std::max(m.nt11 * m.bt11, m.nth * m.bth));
     p->meta[b] = m;
   }
-  if ((int64_t)p->max_bt * 32 * KC * 8 > 140 * 1024)
+  if ((int64_t)p->max_bt * 32 * KC * 8 > 108 * 1024)
     return fail(p, MSGFEM_ESIZE, "band too wide for the LDS ring (BT=%d)", p->max_bt);
   p->nodes_total = node_off;
   p->dofs_total = dof_off;
@@ -495,16 +497,30 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
     k_band_build<<<grid, 256, 0, s>>>(v.meta, kind, v.stencil, v.cls, v.mu1, p->opts.shift, v.fac);
     LAUNCHCHK(p);
   }
-  for (int kind = 0; kind < 2; ++kind) {
+  {
+    // tile Cholesky of both matrices of every box: one update launch and one
+    // panel launch per tile column
     double by = 0, fl = 0;
+    int max_nt = 0, max_bt = 0;
     for (auto& m : p->meta) {
-      double n, b;
-      band_nb(m, kind, &n, &b);
-      by += 2 * 8.0 * band_entries(n, b);
-      fl += n * b * b - 2.0 / 3.0 * b * b * b;
+      for (int kind = 0; kind < 2; ++kind) {
+        double n, b;
+        band_nb(m, kind, &n, &b);
+        by += 2 * 8.0 * band_entries(n, b);
+        fl += n * b * b - 2.0 / 3.0 * b * b * b;
+      }
+      max_nt = std::max(max_nt, std::max(m.nt11, m.nth));
+      max_bt = std::max(max_bt, std::max(m.bt11, m.bth));
     }
     ProfScope ps(p, PK_POTRF, s, by, fl);
-    k_band_potrf<<<nb, 256, 0, s>>>(v.meta, kind, v.fac, status);
+    const int mmax = max_bt - 1;
+    const int upd_wg = std::max(1, (mmax * (mmax + 1) / 2 + 3) / 4);
+    const int pan_wg = std::max(1, (mmax + 3) / 4);
+    for (int K = -1; K < max_nt - 1; ++K) {
+      k_chol_update<<<dim3(K < 0 ? 1 : upd_wg, nb, 2), 256, 0, s>>>(v.meta, K, v.fac, status);
+      k_chol_panel<<<dim3(pan_wg, nb, 2), 256, 0, s>>>(v.meta, K + 1, v.fac);
+    }
+    k_chol_unit<<<dim3((unsigned)((int64_t)max_nt * max_bt + 3) / 4, nb, 2), 256, 0, s>>>(v.meta, v.fac);
     LAUNCHCHK(p);
   }
   return MSGFEM_OK;
@@ -598,7 +614,7 @@ static int spmm(Ctx& c, const double* X, double* Y, double* Y2, int kk, int ycla
 static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int out_classes, int zero_rest,
                  const int32_t* active) {
   int nchunk = (kk + KC - 1) / KC;
-  dim3 grid(nchunk * c.nb);
+  dim3 grid(8 * nchunk * ((c.nb + 7) / 8));
   size_t lds = (size_t)c.p->max_bt * 32 * KC * 8;
   double by = 0, fl = 0;
   for (int b = 0; b < c.nb; ++b) {
@@ -610,7 +626,7 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
     fl += 4.0 * e * kk;
   }
   ProfScope ps(c.p, PK_SOLVE, c.s, by, fl);
-  k_band_solve<KC><<<grid, 256, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, c.v.fac, c.v.cls, in, out, kk,
+  k_band_solve<KC><<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, c.v.fac, c.v.cls, in, out, kk,
                                             out_classes, zero_rest, c.w.scr, c.p->scr_stride, active);
   LAUNCHCHK(c.p);
   return 0;
@@ -641,7 +657,7 @@ static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double*
     B.p[i] = i < nblk ? BZb[i] : nullptr;
   }
   dim3 grid(c.p->n_gchunk, c.nb, 2);
-  size_t lds = (size_t)2 * 32 * m * 8;
+  size_t lds = 0;
   double by = 0, fl = 0;
   for (int b = 0; b < c.nb; ++b) {
     if (!c.counts(b, act)) continue;

@@ -94,213 +94,429 @@ __global__ void k_band_build(const BoxMeta* __restrict__ meta, int kind,
   }
 }
 
-// Right-looking tile Cholesky, one workgroup (256 threads) per (box, kind).
-// grid.x = box.  status[box] gets bit 2 set if a pivot is not positive.
-__global__ __launch_bounds__(256) void k_band_potrf(const BoxMeta* __restrict__ meta, int kind,
-                                                    double* __restrict__ fac,
-                                                    int32_t* __restrict__ status) {
-  __shared__ double D[32][33];
-  __shared__ double Di[32][33];
-  __shared__ double Pa[4][32][33];
-  __shared__ double Pb[4][32][33];
-  __shared__ int bad;
-  const BoxMeta& bm = meta[blockIdx.x];
-  BandView v = band_view(bm, kind);
-  double* L = fac + v.off;
-  double* Li = fac + v.ioff;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (tid == 0) bad = 0;
-  for (int K = 0; K < v.NT; ++K) {
-    double* TKK = L + (int64_t)K * v.BT * MSG_TILE2;
-    for (int t = tid; t < 1024; t += 256) D[t >> 5][t & 31] = TKK[t];
-    __syncthreads();
-    // unblocked Cholesky of the diagonal tile
-    for (int j = 0; j < 32; ++j) {
-      if (tid >= j && tid < 32) {
-        double d = D[j][j];
-        if (!(d > 0.0)) {
-          d = 1.0;
-          bad = 1;
-        }
-        double sd = sqrt(d);
-        if (tid == j) D[j][j] = sd;
-        else D[tid][j] = D[tid][j] / sd;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// 32x32 tile product on one wavefront with the FP64 matrix cores:
+// acc (2x2 blocks of 16x16) += sa * A B^T for row-major 32x32 tiles A, B.
+// v_mfma_f64_16x16x4f64 lane layout: A operand A[l&15][l>>4], B operand
+// B[l>>4][l&15], accumulator item v of lane l = D[(l>>4) + 4v][l&15].
+__device__ inline void tile_mfma_abt(const double* __restrict__ A, const double* __restrict__ B,
+                                     double sa, dbl4 acc[2][2], int lane) {
+  const int i = lane & 15, k = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    double a0 = sa * A[i * 32 + 4 * kk + k];
+    double a1 = sa * A[(16 + i) * 32 + 4 * kk + k];
+    double b0 = B[i * 32 + 4 * kk + k];
+    double b1 = B[(16 + i) * 32 + 4 * kk + k];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+// acc += A B for row-major 32x32 tiles (B operand B[k][j] read along rows).
+__device__ inline void tile_mfma_ab(const double* __restrict__ A, const double* __restrict__ B,
+                                    dbl4 acc[2][2], int lane) {
+  const int i = lane & 15, k = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    double a0 = A[i * 32 + 4 * kk + k];
+    double a1 = A[(16 + i) * 32 + 4 * kk + k];
+    double b0 = B[(4 * kk + k) * 32 + i];
+    double b1 = B[(4 * kk + k) * 32 + 16 + i];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+// acc += A^T B for row-major 32x32 tiles.
+__device__ inline void tile_mfma_atb(const double* __restrict__ A, const double* __restrict__ B,
+                                     dbl4 acc[2][2], int lane) {
+  const int i = lane & 15, k = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    double a0 = A[(4 * kk + k) * 32 + i];
+    double a1 = A[(4 * kk + k) * 32 + 16 + i];
+    double b0 = B[(4 * kk + k) * 32 + i];
+    double b1 = B[(4 * kk + k) * 32 + 16 + i];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+__device__ inline void tile_load_acc(const double* __restrict__ C, dbl4 acc[2][2], int lane) {
+  const int j = lane & 15, r = lane >> 4;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[bi][bj][v] = C[(16 * bi + r + 4 * v) * 32 + 16 * bj + j];
+}
+
+__device__ inline void tile_store_acc(double* __restrict__ C, const dbl4 acc[2][2], int lane) {
+  const int j = lane & 15, r = lane >> 4;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) C[(16 * bi + r + 4 * v) * 32 + 16 * bj + j] = acc[bi][bj][v];
+}
+
+// Cholesky of the diagonal tile T (in place, lower) and the inverse of its
+// factor into Ti, by one whole workgroup through LDS.
+__device__ void diag_tile_factor(double* __restrict__ T, double* __restrict__ Ti, double (*D)[33],
+                                 double (*Di)[33], int* bad) {
+  const int tid = threadIdx.x;
+  for (int t = tid; t < 1024; t += 256) D[t >> 5][t & 31] = T[t];
+  __syncthreads();
+  for (int j = 0; j < 32; ++j) {
+    if (tid >= j && tid < 32) {
+      double d = D[j][j];
+      if (!(d > 0.0)) {
+        d = 1.0;
+        *bad = 1;
       }
-      __syncthreads();
-      for (int t = tid; t < 1024; t += 256) {
-        int i = t >> 5, c = t & 31;
-        if (i > j && c > j && c <= i) D[i][c] -= D[i][j] * D[c][j];
-      }
-      __syncthreads();
-    }
-    // inverse of the lower-triangular diagonal tile, column by column
-    if (tid < 32) {
-      int c = tid;
-      for (int i = 0; i < 32; ++i) {
-        if (i < c) { Di[i][c] = 0.0; continue; }
-        double s = (i == c) ? 1.0 : 0.0;
-        for (int q = c; q < i; ++q) s -= D[i][q] * Di[q][c];
-        Di[i][c] = s / D[i][i];
-      }
+      double sd = sqrt(d);
+      if (tid == j) D[j][j] = sd;
+      else D[tid][j] = D[tid][j] / sd;
     }
     __syncthreads();
     for (int t = tid; t < 1024; t += 256) {
       int i = t >> 5, c = t & 31;
-      TKK[t] = (c <= i) ? D[i][c] : 0.0;
-      Li[(int64_t)K * 1024 + t] = Di[i][c];
+      if (i > j && c > j && c <= i) D[i][c] -= D[i][j] * D[c][j];
     }
-    // panel: L(I,K) = A(I,K) * L_KK^{-T}, tile by tile through LDS:
-    // x[r][c] = sum_{q<=c} a[r][q] Di[c][q]
-    int m = min(v.BT - 1, v.NT - 1 - K);
-    for (int s = 1; s <= m; ++s) {
-      double* T = L + ((int64_t)(K + s) * v.BT + s) * MSG_TILE2;
-      for (int t = tid; t < 1024; t += 256) Pa[0][t >> 5][t & 31] = T[t];
-      __syncthreads();
-      for (int t = tid; t < 1024; t += 256) {
-        int r = t >> 5, c = t & 31;
-        double x = 0.0;
-        for (int q = 0; q <= c; ++q) x += Pa[0][r][q] * Di[c][q];
-        T[t] = x;
-      }
-      __syncthreads();
-    }
-    // trailing update A(I,J) -= L(I,K) L(J,K)^T, K < J <= I < K+BT
-    int npairs = m * (m + 1) / 2;
-    int rounds = (npairs + 3) / 4;
-    for (int rd = 0; rd < rounds; ++rd) {
-      int p = rd * 4 + wave;
-      int sI = 0, sJ = 0;
-      bool act = p < npairs;
-      if (act) {
-        // invert p -> (sI, sJ) with 1 <= sJ <= sI <= m, p = (sI-1)sI/2 + (sJ-1)
-        sI = 1;
-        while ((sI * (sI + 1)) / 2 <= p) ++sI;
-        sJ = p - (sI - 1) * sI / 2 + 1;
-        const double* A1 = L + ((int64_t)(K + sI) * v.BT + sI) * MSG_TILE2;
-        const double* B1 = L + ((int64_t)(K + sJ) * v.BT + sJ) * MSG_TILE2;
-        for (int t = lane; t < 1024; t += 64) {
-          Pa[wave][t >> 5][t & 31] = A1[t];
-          Pb[wave][t >> 5][t & 31] = B1[t];
-        }
-      }
-      __syncthreads();
-      if (act) {
-        int r0 = (lane >> 3) * 4, c0 = (lane & 7) * 4;
-        double acc[4][4] = {};
-        for (int q = 0; q < 32; ++q) {
-          double av[4], bv[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) av[i] = Pa[wave][r0 + i][q];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) bv[j] = Pb[wave][c0 + j][q];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
-        }
-        double* Tt = L + ((int64_t)(K + sI) * v.BT + (sI - sJ)) * MSG_TILE2;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) Tt[(r0 + i) * 32 + c0 + j] -= acc[i][j];
-      }
-      __syncthreads();
+    __syncthreads();
+  }
+  if (tid < 32) {
+    int c = tid;
+    for (int i = 0; i < 32; ++i) {
+      if (i < c) { Di[i][c] = 0.0; continue; }
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int q = c; q < i; ++q) s -= D[i][q] * Di[q][c];
+      Di[i][c] = s / D[i][i];
     }
   }
   __syncthreads();
-  if (tid == 0 && bad) atomicOr(&status[blockIdx.x], 4);
+  for (int t = tid; t < 1024; t += 256) {
+    int i = t >> 5, c = t & 31;
+    T[t] = (c <= i) ? D[i][c] : 0.0;
+    Ti[t] = Di[i][c];
+  }
 }
 
-// Block solve (L L^T) x = f for KC columns [c0, c0+KC) of a box block vector.
-// Reads `in` (box layout [n_dof][ldk]) on the matrix's DoFs, writes `out` on
-// the DoFs whose class bit is set in out_classes (bit c for class c); with
-// zero_rest, every other DoF of the box gets 0 in these columns.  Scratch
-// holds the forward result, NT*32*KC doubles per (box, chunk).
-// grid.x = n_chunks * n_boxes (chunk fastest inside an XCD-friendly order),
-// dynamic LDS = BT*32*KC doubles.
+// Right-looking tile Cholesky, one launch per tile column K (K = -1 first):
+// the trailing update with panel K, A(K+sI, K+sJ) -= L(K+sI,K) L(K+sJ,K)^T
+// for 1 <= sJ <= sI <= m, one tile per wavefront on the matrix cores, spread
+// over workgroups; workgroup 0 also owns pair (1,1), whose target is the next
+// diagonal tile, and factors that tile (and inverts it) right after its update.
+// grid (n_wg, n_box, 2 kinds), 256 threads.
+__global__ __launch_bounds__(256) void k_chol_update(const BoxMeta* __restrict__ meta, int K,
+                                                     double* __restrict__ fac,
+                                                     int32_t* __restrict__ status) {
+  __shared__ double D[32][33];
+  __shared__ double Di[32][33];
+  __shared__ int bad;
+  const int box = blockIdx.y, kind = blockIdx.z;
+  const BoxMeta& bm = meta[box];
+  BandView v = band_view(bm, kind);
+  if (K >= v.NT - 1) return;
+  const int m = (K < 0) ? 0 : min(v.BT - 1, v.NT - 1 - K);
+  const int npairs = m * (m + 1) / 2;
+  const bool owner = blockIdx.x == 0;
+  if (!owner && (int)blockIdx.x * 4 >= npairs) return;
+  double* L = fac + v.off;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int p = blockIdx.x * 4 + wave;
+  if (p < npairs) {
+    int sI = 1;
+    while ((sI * (sI + 1)) / 2 <= p) ++sI;
+    int sJ = p - (sI - 1) * sI / 2 + 1;
+    const double* Ta = L + ((int64_t)(K + sI) * v.BT + sI) * MSG_TILE2;
+    const double* Tb = L + ((int64_t)(K + sJ) * v.BT + sJ) * MSG_TILE2;
+    double* Tc = L + ((int64_t)(K + sI) * v.BT + (sI - sJ)) * MSG_TILE2;
+    dbl4 acc[2][2];
+    tile_load_acc(Tc, acc, lane);
+    tile_mfma_abt(Ta, Tb, -1.0, acc, lane);
+    tile_store_acc(Tc, acc, lane);
+  }
+  if (owner) {
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    double* T = L + (int64_t)(K + 1) * v.BT * MSG_TILE2;
+    diag_tile_factor(T, fac + v.ioff + (int64_t)(K + 1) * MSG_TILE2, D, Di, &bad);
+    __syncthreads();
+    if (tid == 0 && bad) atomicOr(&status[box], 4);
+  }
+}
+
+// Panel of column K: L(K+s, K) = A(K+s, K) L_KK^{-T} = A Linv_KK^T, one tile per
+// wavefront on the matrix cores.  grid (ceil(max(BT-1)/4), n_box, 2 kinds).
+__global__ __launch_bounds__(256) void k_chol_panel(const BoxMeta* __restrict__ meta, int K,
+                                                    double* __restrict__ fac) {
+  const int box = blockIdx.y, kind = blockIdx.z;
+  const BoxMeta& bm = meta[box];
+  BandView v = band_view(bm, kind);
+  if (K >= v.NT) return;
+  const int m = min(v.BT - 1, v.NT - 1 - K);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + wave + 1;
+  if (s > m) return;
+  double* T = fac + v.off + ((int64_t)(K + s) * v.BT + s) * MSG_TILE2;
+  const double* Ti = fac + v.ioff + (int64_t)K * MSG_TILE2;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
+  tile_mfma_abt(T, Ti, 1.0, acc, lane);
+  tile_store_acc(T, acc, lane);
+}
+
+// After the factorisation A = L L^T: rewrite the factor in block unit-lower
+// form A = Lu D Lu^T with Lu(I,J) = L(I,J) L_JJ^{-1} (off-diagonal tiles, in
+// place) and D^{-1}_II = L_II^{-T} L_II^{-1} stored in the diagonal tile slot,
+// so that the block triangular sweeps need no diagonal solve.
+// grid (ceil(max NT*BT / 4), n_box, 2 kinds), one tile per wavefront.
+__global__ __launch_bounds__(256) void k_chol_unit(const BoxMeta* __restrict__ meta,
+                                                   double* __restrict__ fac) {
+  const int box = blockIdx.y, kind = blockIdx.z;
+  const BoxMeta& bm = meta[box];
+  BandView v = band_view(bm, kind);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + wave;
+  if (t >= (int64_t)v.NT * v.BT) return;
+  const int I = (int)(t / v.BT), s = (int)(t % v.BT);
+  if (s > I) return;
+  double* T = fac + v.off + ((int64_t)I * v.BT + s) * MSG_TILE2;
+  const double* Ti = fac + v.ioff + (int64_t)(I - s) * MSG_TILE2;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
+  if (s == 0) tile_mfma_atb(Ti, Ti, acc, lane);
+  else tile_mfma_ab(T, Ti, acc, lane);
+  tile_store_acc(T, acc, lane);
+}
+
+// Block solve A x = f with A = Lu D Lu^T for KC columns [chunk*KC, +KC) of a
+// box block vector.  Reads `in` (box layout [n_dof][ldk]) on the matrix's
+// DoFs, writes `out` on the DoFs whose class bit is set in out_classes (bit c
+// for class c); with zero_rest, every other DoF of the box gets 0 in these
+// columns.  Scratch holds w = D^{-1} y of the forward sweep, NT*32*KC doubles
+// per (box, chunk).
+//
+// Forward sweep  y_I = f_I - sum_s Lu(I,I-s) y_{I-s}; backward sweep
+// x_I = w_I - sum_s Lu(I+s,I)^T x_{I+s}.  A step's work items are
+// (band tile s, row quad, half of the inner index): thread t handles tile
+// s = 1 + (t >> 4), rows 4*((t >> 1) & 7) .. +3 and inner indices
+// 16*(t & 1) .. +15, for all KC columns, so every solution row read from the
+// LDS ring feeds four factor rows.  The two halves are combined with a lane
+// shuffle, the per-tile partial sums are reduced through LDS, and the factor
+// fragment of the next step is requested as soon as the current one has been
+// used, so its memory latency overlaps the reduction and the barriers.  The
+// diagonal block D^{-1} of the previous forward step is applied in the same
+// shadow.  The column chunks of one box share an XCD (block id mod 8) so the
+// factor they stream is read from HBM once and then hit in that XCD's L2.
+// grid.x = 8 * n_chunk * ceil(n_box/8), 512 threads; dynamic LDS = BT*32*KC doubles.
+#define SOLVE_THREADS 512
+#define SOLVE_TILES 32      // band tiles covered by the thread layout (bands up to 33 tiles)
+
+// f[i][q]: forward  = T[4rq+i][16h+q] of tile (I, I-s);
+//          backward = T[16h+q][4rq+i] of tile (I+s, I)  (row i of its transpose)
 template <int KC>
-__global__ __launch_bounds__(256) void k_band_solve(const BoxMeta* __restrict__ meta, int n_box,
-                                                    int n_chunk, int kind,
-                                                    const double* __restrict__ fac,
-                                                    const uint8_t* __restrict__ cls,
-                                                    const double* in, double* out, int ldk,
-                                                    int out_classes, int zero_rest,
-                                                    double* __restrict__ scratch,
-                                                    int64_t scratch_stride,
-                                                    const int32_t* __restrict__ active) {
+__device__ inline void frag_load(const double* __restrict__ L, int I, int BT, int smax, int dir,
+                                 int s, int rq, int h, double (&f)[4][16]) {
+  if (s > smax) return;
+  if (dir < 0) {
+    const double* p = L + ((int64_t)I * BT + s) * MSG_TILE2 + (4 * rq) * 32 + 16 * h;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        double2 a = ((const double2*)(p + i * 32))[q];
+        f[i][2 * q] = a.x;
+        f[i][2 * q + 1] = a.y;
+      }
+  } else {
+    const double* p = L + ((int64_t)(I + s) * BT + s) * MSG_TILE2 + (16 * h) * 32 + 4 * rq;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      double2 a = ((const double2*)(p + q * 32))[0];
+      double2 b = ((const double2*)(p + q * 32))[1];
+      f[0][q] = a.x;
+      f[1][q] = a.y;
+      f[2][q] = b.x;
+      f[3][q] = b.y;
+    }
+  }
+}
+
+template <int KC>
+__global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
+    const BoxMeta* __restrict__ meta, int n_box, int n_chunk, int kind,
+    const double* __restrict__ fac, const uint8_t* __restrict__ cls, const double* in, double* out,
+    int ldk, int out_classes, int zero_rest, double* __restrict__ scratch, int64_t scratch_stride,
+    const int32_t* __restrict__ active) {
   extern __shared__ double ring[];   // [BT][32][KC]
-  __shared__ double T[32][KC + 1];
-  int chunk = blockIdx.x % n_chunk;
-  int box = blockIdx.x / n_chunk;
+  __shared__ double part[SOLVE_TILES][32][KC + 1];
+  __shared__ double Dl[32][33];      // D^{-1} tile of the current forward step
+  const int x = blockIdx.x;
+  const int xcd = x & 7, rest = x >> 3;
+  const int chunk = rest % n_chunk;
+  const int box = (rest / n_chunk) * 8 + xcd;
   if (box >= n_box) return;
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
   BandView v = band_view(bm, kind);
   const double* L = fac + v.off;
-  const double* Li = fac + v.ioff;
   const uint8_t* cl = cls + bm.dof_off;
   const int tid = threadIdx.x;
-  const int r = tid / KC, c = tid % KC;   // 32 x KC outputs per tile row (256 = 32*8)
-  const int col = chunk * KC + c;
+  const int h = tid & 1, rq = (tid >> 1) & 7, sg = tid >> 4;  // item of the thread
+  const int s = 1 + sg;
+  const bool red = tid < 32 * KC;
+  const int rr = tid / KC, cc = tid % KC;                     // reduction mapping
+  const int col = chunk * KC + cc;
   const bool colok = col < ldk;
   const double* vin = in + bm.vec_off;
   double* vout = out + bm.vec_off;
-  double* y = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
-  // forward: L y = f
-  for (int I = 0; I < v.NT; ++I) {
-    int row = I * 32 + r;
-    int dof = band_to_dof(v, bm, row);
-    double acc = 0.0;
-    if (dof >= 0 && colok && dof_active(kind, cl[dof])) acc = vin[(int64_t)dof * ldk + col];
-    int smax = min(v.BT - 1, I);
-    for (int s = 1; s <= smax; ++s) {
-      const double* Lt = L + ((int64_t)I * v.BT + s) * MSG_TILE2 + r * 32;
-      const double* yp = ring + (int64_t)((I - s) % v.BT) * 32 * KC;
-#pragma unroll 8
-      for (int q = 0; q < 32; ++q) acc -= Lt[q] * yp[q * KC + c];
-    }
-    T[r][c] = acc;
-    __syncthreads();
-    const double* Di = Li + (int64_t)I * MSG_TILE2 + r * 32;
-    double yv = 0.0;
-    for (int q = 0; q <= r; ++q) yv += Di[q] * T[q][c];
-    ring[(int64_t)(I % v.BT) * 32 * KC + r * KC + c] = yv;
-    y[(int64_t)row * KC + c] = yv;
-    __syncthreads();
-  }
-  // backward: L^T x = y
-  for (int I = v.NT - 1; I >= 0; --I) {
-    int row = I * 32 + r;
-    double acc = y[(int64_t)row * KC + c];
-    int smax = min(v.BT - 1, v.NT - 1 - I);
-    for (int s = 1; s <= smax; ++s) {
-      const double* Lt = L + ((int64_t)(I + s) * v.BT + s) * MSG_TILE2 + r;
-      const double* xp = ring + (int64_t)((I + s) % v.BT) * 32 * KC;
-#pragma unroll 8
-      for (int q = 0; q < 32; ++q) acc -= Lt[q * 32] * xp[q * KC + c];
-    }
-    T[r][c] = acc;
-    __syncthreads();
-    const double* Di = Li + (int64_t)I * MSG_TILE2 + r;
-    double xv = 0.0;
-    for (int q = r; q < 32; ++q) xv += Di[q * 32] * T[q][c];
-    ring[(int64_t)(I % v.BT) * 32 * KC + r * KC + c] = xv;
-    int dof = band_to_dof(v, bm, row);
-    if (dof >= 0 && colok) {
-      uint8_t k = cl[dof];
-      if (dof_active(kind, k) && ((out_classes >> k) & 1)) vout[(int64_t)dof * ldk + col] = xv;
-    }
-    __syncthreads();
-  }
-  if (zero_rest && colok) {
-    // zero the DoFs of this box (this chunk's columns) that were not written
-    for (int d = tid / KC; d < bm.n_dof; d += 256 / KC) {
-      uint8_t k = cl[d];
-      bool written = false;
-      if (dof_active(kind, k) && ((out_classes >> k) & 1)) {
-        // A11 orders only the sub-box: B1 DoFs always lie in it
-        written = true;
+  double* w = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
+  const int BT = v.BT, NT = v.NT;
+  double f[4][16];
+
+  // partial sums of this thread's item over its half of the inner index
+  auto accumulate = [&](const double* yp, double (&acc)[4][KC]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < KC; ++c) acc[i][c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const double* y0 = yp + (16 * h + q) * KC;
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        const double a = y0[c];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][c] += f[i][q] * a;
       }
+    }
+  };
+  auto store_part = [&](bool has, double (&acc)[4][KC]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        double o = __shfl_xor(acc[i][c], 1);
+        acc[i][c] += o;
+      }
+    if (h == 0 && sg < SOLVE_TILES) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < KC; ++c) part[sg][4 * rq + i][c] = has ? acc[i][c] : 0.0;
+    }
+  };
+
+  // ---- forward: Lu y = f
+  frag_load<KC>(L, 0, BT, 0, -1, s, rq, h, f);
+  for (int I = 0; I < NT; ++I) {
+    const int smax = min(BT - 1, I);
+    double fv = 0.0;
+    if (red) {
+      const int dof = band_to_dof(v, bm, I * 32 + rr);
+      if (dof >= 0 && colok && dof_active(kind, cl[dof])) fv = vin[(int64_t)dof * ldk + col];
+    }
+    const double2* dp = (const double2*)(L + (int64_t)I * BT * MSG_TILE2);
+    const double2 d0 = red ? dp[2 * tid] : make_double2(0.0, 0.0);
+    const double2 d1 = red ? dp[2 * tid + 1] : make_double2(0.0, 0.0);
+    // w_{I-1} = D^{-1}_{I-1} y_{I-1} (Dl and its ring slot were completed last step)
+    if (red && I >= 1) {
+      const double* yp = ring + (int64_t)((I - 1) % BT) * 32 * KC;
+      double wv = 0.0;
+#pragma unroll
+      for (int q = 0; q < 32; ++q) wv += Dl[rr][q] * yp[q * KC + cc];
+      w[(int64_t)((I - 1) * 32 + rr) * KC + cc] = wv;
+    }
+    double acc[4][KC];
+    const bool has = s <= smax;
+    if (has) accumulate(ring + (int64_t)((I - s) % BT) * 32 * KC, acc);
+    store_part(has, acc);
+    // fragment of the next step, in flight during the reduction
+    if (I + 1 < NT) frag_load<KC>(L, I + 1, BT, min(BT - 1, I + 1), -1, s, rq, h, f);
+    __syncthreads();
+    if (red) {
+      const int e = 4 * tid;
+      Dl[e >> 5][e & 31] = d0.x;
+      Dl[(e + 1) >> 5][(e + 1) & 31] = d0.y;
+      Dl[(e + 2) >> 5][(e + 2) & 31] = d1.x;
+      Dl[(e + 3) >> 5][(e + 3) & 31] = d1.y;
+      double sum = 0.0;
+      const int ns = min(smax, SOLVE_TILES);
+      for (int q = 0; q < ns; ++q) sum += part[q][rr][cc];
+      // bands wider than 33 tiles: remaining tiles directly
+      for (int s2 = SOLVE_TILES + 1; s2 <= smax; ++s2) {
+        const double* p = L + ((int64_t)I * BT + s2) * MSG_TILE2 + rr * 32;
+        const double* yp = ring + (int64_t)((I - s2) % BT) * 32 * KC;
+        for (int q = 0; q < 32; ++q) sum += p[q] * yp[q * KC + cc];
+      }
+      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = fv - sum;
+    }
+    __syncthreads();
+  }
+  if (red) {
+    const int I = NT - 1;
+    const double* yp = ring + (int64_t)(I % BT) * 32 * KC;
+    double wv = 0.0;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) wv += Dl[rr][q] * yp[q * KC + cc];
+    w[(int64_t)(I * 32 + rr) * KC + cc] = wv;
+  }
+  __syncthreads();
+
+  // ---- backward: Lu^T x = w
+  frag_load<KC>(L, NT - 1, BT, 0, +1, s, rq, h, f);
+  for (int I = NT - 1; I >= 0; --I) {
+    const int smax = min(BT - 1, NT - 1 - I);
+    const int row = I * 32 + rr;
+    const double fv = red ? w[(int64_t)row * KC + cc] : 0.0;
+    double acc[4][KC];
+    const bool has = s <= smax;
+    if (has) accumulate(ring + (int64_t)((I + s) % BT) * 32 * KC, acc);
+    store_part(has, acc);
+    if (I - 1 >= 0) frag_load<KC>(L, I - 1, BT, min(BT - 1, NT - I), +1, s, rq, h, f);
+    __syncthreads();
+    if (red) {
+      double sum = 0.0;
+      const int ns = min(smax, SOLVE_TILES);
+      for (int q = 0; q < ns; ++q) sum += part[q][rr][cc];
+      for (int s2 = SOLVE_TILES + 1; s2 <= smax; ++s2) {
+        const double* p = L + ((int64_t)(I + s2) * BT + s2) * MSG_TILE2 + rr;
+        const double* xp = ring + (int64_t)((I + s2) % BT) * 32 * KC;
+        for (int q = 0; q < 32; ++q) sum += p[q * 32] * xp[q * KC + cc];
+      }
+      const double xv = fv - sum;
+      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = xv;
+      const int dof = band_to_dof(v, bm, row);
+      if (dof >= 0 && colok) {
+        uint8_t k = cl[dof];
+        if (dof_active(kind, k) && ((out_classes >> k) & 1)) vout[(int64_t)dof * ldk + col] = xv;
+      }
+    }
+    __syncthreads();
+  }
+  if (zero_rest && colok && red) {
+    // zero the DoFs of this box (this chunk's columns) that were not written
+    for (int d = rr; d < bm.n_dof; d += 256 / KC) {
+      uint8_t k = cl[d];
+      bool written = dof_active(kind, k) && ((out_classes >> k) & 1);
       if (!written) vout[(int64_t)d * ldk + col] = 0.0;
     }
   }

@@ -27,75 +27,105 @@ struct Blk3 {
 
 #define GR_ROWS 32
 
-// grid (n_chunk, n_box, 2): z = 0 -> Z^T (A Z), z = 1 -> Z^T (DAD Z).
-// dynamic LDS = 2 * GR_ROWS * m doubles; thread owns outputs tid + 256 u.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Gram matrices on the FP64 matrix cores: G = Z^T W over a chunk of rows with
+// W = A Z~ (grid z = 0) or W = D A D Z~ (z = 1).  The m columns are padded to
+// 16-wide blocks; only blocks bi <= bj are formed (the matrices are
+// symmetric; k_gram_reduce mirrors them).  Wave w owns the output blocks
+// t = w, w+4, ... and walks all rows of the chunk four at a time; the operands
+// are read straight from the row-major block vectors (A operand lane l:
+// Z[row l>>4][col l&15], B operand W[row l>>4][col l&15]).
+// grid (n_chunk, n_box, 2), 256 threads.
 __global__ __launch_bounds__(256) void k_gram_partial(const BoxMeta* __restrict__ meta, int nblk,
                                                       Blk3 Z, Blk3 AZ, Blk3 BZ, int k,
                                                       int rows_per_chunk, int n_chunk,
                                                       double* __restrict__ part,
                                                       const int32_t* __restrict__ active) {
-  extern __shared__ double sm[];
   int box = blockIdx.y, chunk = blockIdx.x, which = blockIdx.z;
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
   const int m = nblk * k;
-  double* z = sm;
-  double* w = sm + GR_ROWS * m;
+  const int nb16 = (m + 15) >> 4;
+  const int ntile = nb16 * (nb16 + 1) / 2;
   const Blk3& W = which ? BZ : AZ;
-  const int tid = threadIdx.x;
-  const int mm = m * m;
-  const int U = (mm + 255) / 256;   // <= 36 for m <= 96
-  double g[36];
-#pragma unroll
-  for (int u = 0; u < 36; ++u) g[u] = 0.0;
-  int r_begin = chunk * rows_per_chunk;
-  int r_end = min(bm.n_dof, r_begin + rows_per_chunk);
-  for (int r0 = r_begin; r0 < r_end; r0 += GR_ROWS) {
-    for (int t = tid; t < GR_ROWS * m; t += 256) {
-      int rr = t / m, col = t % m;
-      int blk = col / k, cc = col % k;
-      int row = r0 + rr;
-      double vz = 0.0, vw = 0.0;
-      if (row < r_end) {
-        int64_t o = bm.vec_off + (int64_t)row * k + cc;
-        vz = Z.p[blk][o];
-        vw = W.p[blk][o];
-      }
-      z[t] = vz;
-      w[t] = vw;
-    }
-    __syncthreads();
-    for (int rr = 0; rr < GR_ROWS; ++rr) {
-      const double* zr = z + rr * m;
-      const double* wr = w + rr * m;
-#pragma unroll
-      for (int u = 0; u < 36; ++u) {
-        int o = tid + 256 * u;
-        if (u < U && o < mm) {
-          int i = o / m, j = o - (o / m) * m;
-          g[u] += zr[i] * wr[j];
-        }
-      }
-    }
-    __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r_begin = chunk * rows_per_chunk;
+  const int r_end = min(bm.n_dof, r_begin + rows_per_chunk);
+  // this wave's tiles (at most 6 of the <= 21 upper blocks of m <= 96)
+  int tbi[6], tbj[6];
+  int nt = 0;
+  {
+    int t = 0;
+    for (int bi = 0; bi < nb16; ++bi)
+      for (int bj = bi; bj < nb16; ++bj, ++t)
+        if ((t & 3) == wave && nt < 6) { tbi[nt] = bi; tbj[nt] = bj; ++nt; }
   }
+  dbl4 acc[6];
+#pragma unroll
+  for (int u = 0; u < 6; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // column of this lane in every 16-block: (block of the basis, column inside it)
+  const int lc = lane & 15, lr = lane >> 4;
+  int cblk[6], ccol[6];
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    int c = 16 * b + lc;
+    cblk[b] = (c < m) ? c / k : -1;
+    ccol[b] = (c < m) ? c % k : 0;
+  }
+  for (int r0 = r_begin; r0 < r_end; r0 += 4) {
+    const int row = r0 + lr;
+    const bool rok = row < r_end;
+    double zf[6], wf[6];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      zf[b] = 0.0;
+      wf[b] = 0.0;
+      if (b < nb16 && rok && cblk[b] >= 0) {
+        int64_t o = bm.vec_off + (int64_t)row * k + ccol[b];
+        zf[b] = Z.p[cblk[b]][o];
+        wf[b] = W.p[cblk[b]][o];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      if (u < nt) {
+        double a = 0.0, bb = 0.0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+          if (b == tbi[u]) a = zf[b];
+          if (b == tbj[u]) bb = wf[b];
+        }
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[u], 0, 0, 0);
+      }
+    }
+  }
+  const int mm = m * m;
   double* out = part + ((int64_t)box * n_chunk + chunk) * 2 * mm + (int64_t)which * mm;
 #pragma unroll
-  for (int u = 0; u < 36; ++u) {
-    int o = tid + 256 * u;
-    if (u < U && o < mm) out[o] = g[u];
+  for (int u = 0; u < 6; ++u) {
+    if (u < nt) {
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        int i = 16 * tbi[u] + lr + 4 * vv, j = 16 * tbj[u] + lc;
+        if (i < m && j < m) out[i * m + j] = acc[u][vv];
+      }
+    }
   }
+  (void)ntile;
 }
 
-// G[box][2][m][m] = sum over chunks (fixed order)
+// G[box][2][m][m] = sum over chunks (fixed order); lower 16-blocks mirrored.
 __global__ void k_gram_reduce(int m, int n_chunk, const double* __restrict__ part,
                               double* __restrict__ G, const int32_t* __restrict__ active) {
   int box = blockIdx.y;
   if (active && !active[box]) return;
-  int mm2 = 2 * m * m;
+  const int mm = m * m, mm2 = 2 * mm;
   int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= mm2) return;
-  const double* p = part + (int64_t)box * n_chunk * mm2 + o;
+  int which = o / mm, e = o % mm, i = e / m, j = e % m;
+  int src = ((i >> 4) <= (j >> 4)) ? e : j * m + i;
+  const double* p = part + (int64_t)box * n_chunk * mm2 + which * mm + src;
   double s = 0.0;
   for (int c = 0; c < n_chunk; ++c) s += p[(int64_t)c * mm2];
   G[(int64_t)box * mm2 + o] = s;
@@ -166,9 +196,12 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, int nblk_x,
     }
     __syncthreads();
   }
+  // keep L in LDS (V's space, free until the Jacobi sweeps) and in global
   for (int t = tid; t < m * m; t += 256) {
     int i = t / m, c = t % m;
-    L[t] = (c <= i) ? C[i * ld + c] : 0.0;
+    double l = (c <= i) ? C[i * ld + c] : 0.0;
+    L[t] = l;
+    V[i * ld + c] = l;
   }
   __syncthreads();
   // 3. scaled M-Gram, dropped rows/columns removed
@@ -182,16 +215,16 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, int nblk_x,
   for (int j = tid; j < m; j += 256) {
     for (int i = 0; i < m; ++i) {
       double s = C[i * ld + j];
-      for (int q = 0; q < i; ++q) s -= L[i * m + q] * C[q * ld + j];
-      C[i * ld + j] = s / L[i * m + i];
+      for (int q = 0; q < i; ++q) s -= V[i * ld + q] * C[q * ld + j];
+      C[i * ld + j] = s / V[i * ld + i];
     }
   }
   __syncthreads();
   for (int i = tid; i < m; i += 256) {
     for (int j = 0; j < m; ++j) {
       double s = C[i * ld + j];
-      for (int q = 0; q < j; ++q) s -= C[i * ld + q] * L[j * m + q];
-      C[i * ld + j] = s / L[j * m + j];
+      for (int q = 0; q < j; ++q) s -= C[i * ld + q] * V[j * ld + q];
+      C[i * ld + j] = s / V[j * ld + j];
     }
   }
   __syncthreads();
@@ -232,7 +265,8 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, int nblk_x,
     }
     double tots = red[0];
     __syncthreads();
-    if (offs <= 1e-32 * tots || tots == 0.0) break;
+    // relative off-diagonal norm 1e-13: Ritz values then carry errors ~1e-26
+    if (offs <= 1e-26 * tots || tots == 0.0) break;
     for (int r = 0; r < m - 1; ++r) {
       for (int i = tid; i < h; i += 256) {
         int p, q;
@@ -300,16 +334,23 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, int nblk_x,
     order[rank] = i;
   }
   __syncthreads();
-  // 7. Ritz coefficients Y[:, c] = D L^{-T} V[:, order[c]]
+  // 7. Ritz coefficients Y[:, c] = D L^{-T} V[:, order[c]] (L back in LDS, C's space;
+  //    the back substitution runs in place in the column of V owned by c)
+  for (int t = tid; t < m * m; t += 256) {
+    int i = t / m, q = t % m;
+    C[i * ld + q] = L[t];
+  }
+  __syncthreads();
   double* Yb = Y + (int64_t)box * m * k;
   double* Ypb = Yp + (int64_t)box * m * k;
   for (int c = tid; c < k; c += 256) {
     int col = order[c];
     for (int i = m - 1; i >= 0; --i) {
       double s = V[i * ld + col];
-      for (int q = i + 1; q < m; ++q) s -= L[q * m + i] * Yb[q * k + c];
-      Yb[i * k + c] = s / L[i * m + i];
+      for (int q = i + 1; q < m; ++q) s -= C[q * ld + i] * V[q * ld + col];
+      V[i * ld + col] = s / C[i * ld + i];
     }
+    for (int i = 0; i < m; ++i) Yb[i * k + c] = V[i * ld + col];
     nu[(int64_t)box * k + c] = ev[col];
   }
   __syncthreads();
