@@ -169,6 +169,47 @@ int msgfem_local_eigs(msgfem_plan *plan, const void *ops, void *work, const doub
 int msgfem_local_apply(msgfem_plan *plan, const void *ops, void *work, int32_t op, int32_t k,
                        const double *x, double *y, void *stream);
 
+/* Uniform tractions on the mesh faces (Sec. 2: b(v) = integral of g.v over
+ * Gamma_N; the body force is zero).  Host arrays: face[n] with 0..5 =
+ * x-, x+, y-, y+, z-, z+ and g[n][3] in MPa. */
+typedef struct {
+  int32_t n;
+  const int32_t *face;
+  const double *g;
+} msgfem_load;
+
+/* Size of the caller's coarse buffer and the number N_H of coarse functions
+ * (the sum of n_ev over the batch).  The coarse problem needs a batch that
+ * lists every subdomain of the decomposition exactly once (MSGFEM_EARG
+ * otherwise). */
+int msgfem_coarse_sizes(msgfem_plan *plan, int64_t *coarse_bytes, int32_t *n_coarse);
+
+/* MS-GFEM coarse problem (Sec. 3.3; coarse basis of Sec. 4.3).  From the local
+ * eigenvectors `evecs` (msgfem_local_eigs) it forms, on every box:
+ *   b_{Omega*}: consistent nodal loads of `load` on the box's mesh faces,
+ *   psi_j: the particular function, A11 psi = b on B1, 0 on B2 and B3 (zero
+ *          Dirichlet data, so the Dirichlet part vanishes),
+ *   V_j: mu_j phi_{j,k}, orthonormalised by two Cholesky-QR passes that drop
+ *        columns whose orthogonal part is below 1e-12 of the largest norm,
+ * and writes the Galerkin system of u^G = u^p + V c (u^p = sum_j mu_j psi_j
+ * lifted to the right-hand side):
+ *   AH (device, N_H x N_H row-major) = V^T A V over the free DoFs
+ *   bH (device, N_H)                 = V^T (b - A u^p)
+ * A dropped coarse function gives a unit diagonal entry and a zero right-hand
+ * side.  ops/work as for msgfem_local_eigs; coarse: device, coarse_bytes, kept
+ * for msgfem_coarse_solve. */
+int msgfem_coarse_assemble(msgfem_plan *plan, const void *ops, void *work, const msgfem_load *load,
+                           const double *evecs, void *coarse, double *AH, double *bH,
+                           int32_t *status, void *stream);
+
+/* Coarse solve: FP64 tile Cholesky of AH, c = AH^{-1} bH (device, N_H), and the
+ * MS-GFEM solution on the global mesh uG = u^p + V c (device, 3 * n_nodes,
+ * zero on the Dirichlet DoFs); up (nullable, device, 3 * n_nodes) receives
+ * u^p.  status[0] gets bit 4 if AH is not numerically positive definite. */
+int msgfem_coarse_solve(msgfem_plan *plan, const void *ops, void *work, void *coarse,
+                        const double *AH, const double *bH, double *c, double *uG, double *up,
+                        int32_t *status, void *stream);
+
 /* Kernel timing.  msgfem_profile(plan, 1) clears the counters and starts
  * recording a pair of HIP events around every launch of the library's hot
  * kernels on the stream the kernel is launched on; msgfem_profile(plan, 0)

@@ -21,9 +21,9 @@ __global__ void k_assemble(const BoxMeta*, MeshDev, const double*, double*);
 __global__ void k_classes_mu(const BoxMeta*, MeshDev, int, const int32_t*, uint8_t*, double*);
 __global__ void k_band_build(const BoxMeta*, int, const double*, const uint8_t*, const double*, double,
                              double*);
-__global__ void k_chol_update(const BoxMeta*, int, double*, int32_t*);
-__global__ void k_chol_panel(const BoxMeta*, int, double*);
-__global__ void k_chol_unit(const BoxMeta*, double*);
+__global__ void k_chol_update(const MatDesc*, int, double*, int32_t*);
+__global__ void k_chol_panel(const MatDesc*, int, double*);
+__global__ void k_chol_unit(const MatDesc*, double*);
 template <int KC>
 __global__ void k_band_solve(const BoxMeta*, int, int, int, const double*, const uint8_t*, const double*,
                              double*, int, int, int, double*, int64_t, const int32_t*);
@@ -47,6 +47,27 @@ __global__ void k_random_start(const BoxMeta*, const uint8_t*, int, uint64_t, do
 __global__ void k_copy_start(const BoxMeta*, const uint8_t*, int, const double*, double*);
 __global__ void k_output(const BoxMeta*, int, double, const double*, const double*, const double*,
                          double*, double*, double*);
+struct FaceLoad {
+  int32_t axis, side;
+  double g[3];
+};
+struct CoarsePair {
+  int32_t i, j;
+  int32_t lo[3], hi[3];
+  int32_t row_off, col_off;
+};
+__global__ void k_box_load(const BoxMeta*, MeshDev, const FaceLoad*, int, double*);
+__global__ void k_coarse_basis(const BoxMeta*, int, const double*, const double*, const double*, double*,
+                               double*);
+__global__ void k_cholqr_coef(int, const double*, double*);
+__global__ void k_coarse_pairs(const BoxMeta*, const CoarsePair*, int, const double*, const double*,
+                               const double*, int, double*, double*);
+__global__ void k_coarse_rhs(const BoxMeta*, int, const double*, const double*, const int32_t*,
+                             const int32_t*, int, const double*, double*, double*);
+__global__ void k_dense_tiles(const double*, int, int, double*);
+__global__ void k_dense_tile_solve(const double*, int, int, const double*, double*, double*);
+__global__ void k_prolong(const BoxMeta*, MeshDev, int, const double*, const double*, const double*,
+                          const int32_t*, double*, double*);
 }  // namespace msg
 
 using namespace msg;
@@ -62,12 +83,13 @@ struct msgfem_plan {
   int32_t nsd = 0, overlap = 0;
   std::vector<int32_t> omega;     // [nsd][6] node boxes of Omega_j
   std::vector<BoxMeta> meta;      // batch boxes
+  std::vector<MatDesc> mats;      // the two banded matrices of every box (A11, Ahat)
   msgfem_eig_opts opts{};
   int k = 0;
   int64_t n_nodes_global = 0;
   // ops layout (bytes)
-  int64_t o_meta = 0, o_omega = 0, o_ctab = 0, o_wtot = 0, o_stencil = 0, o_mu = 0, o_cls = 0,
-          o_fac = 0, ops_bytes = 0;
+  int64_t o_meta = 0, o_mats = 0, o_omega = 0, o_ctab = 0, o_wtot = 0, o_stencil = 0, o_mu = 0,
+          o_cls = 0, o_fac = 0, ops_bytes = 0;
   int64_t nodes_total = 0, dofs_total = 0, fac_total = 0, vec_total = 0, evec_total = 0,
           eval_total = 0;
   int max_nodes = 0, max_dof = 0, max_nt = 0, max_bt = 0;
@@ -77,6 +99,14 @@ struct msgfem_plan {
   int64_t w_vec = 0, w_part = 0, w_G = 0, w_L = 0, w_Y = 0, w_Yp = 0, w_nu = 0, w_rho = 0,
           w_rpart = 0, w_active = 0, w_iters = 0, w_nact = 0, w_scr = 0, work_bytes = 0;
   int64_t scr_stride = 0;
+  // coarse problem (built on the first coarse call)
+  bool coarse_ready = false;
+  int NH = 0, NTc = 0;
+  std::vector<CoarsePair> pairs;
+  std::vector<int32_t> pair_start, row_off;
+  int64_t c_faces = 0, c_pairs = 0, c_pstart = 0, c_roff = 0, c_mat = 0, c_bload = 0, c_psi = 0,
+          c_pv = 0, c_V = 0, c_Vn = 0, c_AV = 0, c_Ap = 0, c_rpart = 0, c_tiles = 0, c_y = 0,
+          coarse_bytes = 0;
   std::string err;
   // kernel timing (msgfem_profile)
   struct ProfRec {
@@ -291,6 +321,13 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   }
   if ((int64_t)p->max_bt * 32 * KC * 8 > 108 * 1024)
     return fail(p, MSGFEM_ESIZE, "band too wide for the LDS ring (BT=%d)", p->max_bt);
+  for (int b = 0; b < nb; ++b) {
+    const BoxMeta& m = p->meta[b];
+    MatDesc a11{m.nt11, m.bt11, b, 0, m.f11_off, m.f11i_off};
+    MatDesc ah{m.nth, m.bth, b, 0, m.fh_off, m.fhi_off};
+    p->mats.push_back(a11);
+    p->mats.push_back(ah);
+  }
   p->nodes_total = node_off;
   p->dofs_total = dof_off;
   p->fac_total = fac_off;
@@ -300,6 +337,7 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   // ops layout
   int64_t off = 0;
   p->o_meta = off; off = align256(off + (int64_t)nb * sizeof(BoxMeta));
+  p->o_mats = off; off = align256(off + (int64_t)p->mats.size() * sizeof(MatDesc));
   p->o_omega = off; off = align256(off + (int64_t)dec->nsd * 6 * 4);
   p->o_ctab = off; off = align256(off + (int64_t)mesh->n_mat * 36 * 8);
   p->o_wtot = off; off = align256(off + p->n_nodes_global * 4);
@@ -411,6 +449,7 @@ static MeshDev mesh_dev(const msgfem_plan* p) {
 
 struct OpsView {
   const BoxMeta* meta;
+  MatDesc* mats;
   int32_t* omega;
   double* ctab;
   int32_t* wtot;
@@ -424,6 +463,7 @@ static OpsView ops_view(const msgfem_plan* p, const void* ops) {
   char* b = (char*)ops;
   OpsView v;
   v.meta = (const BoxMeta*)(b + p->o_meta);
+  v.mats = (MatDesc*)(b + p->o_mats);
   v.omega = (int32_t*)(b + p->o_omega);
   v.ctab = (double*)(b + p->o_ctab);
   v.wtot = (int32_t*)(b + p->o_wtot);
@@ -442,6 +482,23 @@ static int set_device(msgfem_plan* p) {
   return MSGFEM_OK;
 }
 
+// Tile Cholesky of a list of SPD matrices in tile-band storage: per tile column
+// one update launch (which also factors the next diagonal tile) and one panel
+// launch, then the block unit-lower rewrite A = Lu D Lu^T.
+static int tile_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_nt, int max_bt,
+                         double* fac, int32_t* status, hipStream_t s) {
+  const int mmax = max_bt - 1;
+  const int upd_wg = std::max(1, (mmax * (mmax + 1) / 2 + 3) / 4);
+  const int pan_wg = std::max(1, (mmax + 3) / 4);
+  for (int K = -1; K < max_nt - 1; ++K) {
+    k_chol_update<<<dim3(K < 0 ? 1 : upd_wg, nmat), 256, 0, s>>>(mats, K, fac, status);
+    k_chol_panel<<<dim3(pan_wg, nmat), 256, 0, s>>>(mats, K + 1, fac);
+  }
+  k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
+  LAUNCHCHK(p);
+  return 0;
+}
+
 extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status, void* stream) {
   if (!p || !ops || !status) return fail(p, MSGFEM_EARG, "null argument");
   if (set_device(p)) return MSGFEM_EHIP;
@@ -450,6 +507,8 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
   const int nb = (int)p->meta.size();
   HIPCHK(p, hipMemcpyAsync((void*)v.meta, p->meta.data(), nb * sizeof(BoxMeta), hipMemcpyHostToDevice, s));
   HIPCHK(p, hipMemcpyAsync(v.omega, p->omega.data(), p->omega.size() * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(p, hipMemcpyAsync(v.mats, p->mats.data(), p->mats.size() * sizeof(MatDesc),
+                           hipMemcpyHostToDevice, s));
   // the host copies must stay alive until the copies complete
   HIPCHK(p, hipStreamSynchronize(s));
   k_fill_i32<<<(nb + 255) / 256, 256, 0, s>>>(status, nb, 0);
@@ -498,8 +557,6 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
     LAUNCHCHK(p);
   }
   {
-    // tile Cholesky of both matrices of every box: one update launch and one
-    // panel launch per tile column
     double by = 0, fl = 0;
     int max_nt = 0, max_bt = 0;
     for (auto& m : p->meta) {
@@ -513,15 +570,7 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
       max_bt = std::max(max_bt, std::max(m.bt11, m.bth));
     }
     ProfScope ps(p, PK_POTRF, s, by, fl);
-    const int mmax = max_bt - 1;
-    const int upd_wg = std::max(1, (mmax * (mmax + 1) / 2 + 3) / 4);
-    const int pan_wg = std::max(1, (mmax + 3) / 4);
-    for (int K = -1; K < max_nt - 1; ++K) {
-      k_chol_update<<<dim3(K < 0 ? 1 : upd_wg, nb, 2), 256, 0, s>>>(v.meta, K, v.fac, status);
-      k_chol_panel<<<dim3(pan_wg, nb, 2), 256, 0, s>>>(v.meta, K + 1, v.fac);
-    }
-    k_chol_unit<<<dim3((unsigned)((int64_t)max_nt * max_bt + 3) / 4, nb, 2), 256, 0, s>>>(v.meta, v.fac);
-    LAUNCHCHK(p);
+    if (tile_cholesky(p, v.mats, (int)p->mats.size(), max_nt, max_bt, v.fac, status, s)) return MSGFEM_EHIP;
   }
   return MSGFEM_OK;
 }
@@ -876,5 +925,214 @@ extern "C" int msgfem_profile_stats(msgfem_plan* p, msgfem_kernel_stat* out, int
     ++n;
   }
   *n_out = n;
+  return MSGFEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Coarse problem
+
+static int coarse_plan(msgfem_plan* p) {
+  if (p->coarse_ready) return MSGFEM_OK;
+  const int nb = (int)p->meta.size();
+  if (nb != p->nsd) return fail(p, MSGFEM_EARG, "the coarse problem needs every subdomain in the batch");
+  std::vector<int> seen(p->nsd, 0);
+  for (auto& m : p->meta) seen[m.sd]++;
+  for (int j = 0; j < p->nsd; ++j)
+    if (seen[j] != 1) return fail(p, MSGFEM_EARG, "batch must list each subdomain once");
+  p->row_off.assign(nb, 0);
+  int NH = 0;
+  for (int b = 0; b < nb; ++b) {
+    p->row_off[b] = NH;
+    NH += p->meta[b].n_ev;
+  }
+  p->NH = NH;
+  p->NTc = (NH + 31) / 32;
+  p->pairs.clear();
+  p->pair_start.assign(nb + 1, 0);
+  for (int i = 0; i < nb; ++i) {
+    p->pair_start[i] = (int)p->pairs.size();
+    const BoxMeta& bi = p->meta[i];
+    for (int j = 0; j < nb; ++j) {
+      const BoxMeta& bj = p->meta[j];
+      CoarsePair pr;
+      bool ok = true;
+      for (int d = 0; d < 3; ++d) {
+        int jlo = bj.g0[d], jhi = bj.g0[d] + (d == 0 ? bj.mx : d == 1 ? bj.my : bj.mz) - 1;
+        pr.lo[d] = std::max(bi.olo[d], jlo);
+        pr.hi[d] = std::min(bi.ohi[d], jhi);
+        if (pr.lo[d] > pr.hi[d]) ok = false;
+      }
+      if (!ok) continue;
+      pr.i = i;
+      pr.j = j;
+      pr.row_off = p->row_off[i];
+      pr.col_off = p->row_off[j];
+      p->pairs.push_back(pr);
+    }
+  }
+  p->pair_start[nb] = (int)p->pairs.size();
+  const int64_t k = p->k, nd = p->dofs_total, np = (int64_t)p->pairs.size();
+  int64_t off = 0;
+  p->c_faces = off; off = align256(off + 6 * sizeof(FaceLoad));
+  p->c_pairs = off; off = align256(off + np * sizeof(CoarsePair));
+  p->c_pstart = off; off = align256(off + (nb + 1) * 4);
+  p->c_roff = off; off = align256(off + nb * 4);
+  p->c_mat = off; off = align256(off + sizeof(MatDesc));
+  p->c_bload = off; off = align256(off + nd * 8);
+  p->c_psi = off; off = align256(off + nd * 8);
+  p->c_pv = off; off = align256(off + nd * 8);
+  p->c_V = off; off = align256(off + nd * k * 8);
+  p->c_Vn = off; off = align256(off + nd * k * 8);
+  p->c_AV = off; off = align256(off + nd * k * 8);
+  p->c_Ap = off; off = align256(off + nd * 8);
+  p->c_rpart = off; off = align256(off + np * 32 * 8);
+  p->c_tiles = off; off = align256(off + ((int64_t)p->NTc * p->NTc + p->NTc) * 1024 * 8);
+  p->c_y = off; off = align256(off + 2 * (int64_t)p->NTc * 32 * 8);
+  p->coarse_bytes = off;
+  p->coarse_ready = true;
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_coarse_sizes(msgfem_plan* p, int64_t* coarse_bytes, int32_t* n_coarse) {
+  if (!p || !coarse_bytes || !n_coarse) return MSGFEM_EARG;
+  int rc = coarse_plan(p);
+  if (rc) return rc;
+  *coarse_bytes = p->coarse_bytes;
+  *n_coarse = p->NH;
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_coarse_assemble(msgfem_plan* p, const void* ops, void* work, const msgfem_load* load,
+                                      const double* evecs, void* coarse, double* AH, double* bH,
+                                      int32_t* status, void* stream) {
+  if (!p || !ops || !work || !evecs || !coarse || !AH || !bH || !status)
+    return fail(p, MSGFEM_EARG, "null argument");
+  int rc = coarse_plan(p);
+  if (rc) return rc;
+  if (set_device(p)) return MSGFEM_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  OpsView v = ops_view(p, ops);
+  char* cb = (char*)coarse;
+  const int nb = (int)p->meta.size(), k = p->k, NH = p->NH;
+  // load description and pair tables
+  std::vector<FaceLoad> faces;
+  if (load) {
+    if (load->n < 0 || load->n > 6 || (load->n > 0 && (!load->face || !load->g)))
+      return fail(p, MSGFEM_EARG, "bad load description");
+    for (int f = 0; f < load->n; ++f) {
+      int fc = load->face[f];
+      if (fc < 0 || fc > 5) return fail(p, MSGFEM_EARG, "face id %d out of range", fc);
+      FaceLoad fl;
+      fl.axis = fc / 2;
+      fl.side = fc % 2;
+      for (int c = 0; c < 3; ++c) fl.g[c] = load->g[3 * f + c];
+      faces.push_back(fl);
+    }
+  }
+  MatDesc md{p->NTc, p->NTc, 0, 0, 0, (int64_t)p->NTc * p->NTc * 1024};
+  if (!faces.empty())
+    HIPCHK(p, hipMemcpyAsync(cb + p->c_faces, faces.data(), faces.size() * sizeof(FaceLoad),
+                             hipMemcpyHostToDevice, s));
+  if (!p->pairs.empty())
+    HIPCHK(p, hipMemcpyAsync(cb + p->c_pairs, p->pairs.data(), p->pairs.size() * sizeof(CoarsePair),
+                             hipMemcpyHostToDevice, s));
+  HIPCHK(p, hipMemcpyAsync(cb + p->c_pstart, p->pair_start.data(), (nb + 1) * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(p, hipMemcpyAsync(cb + p->c_roff, p->row_off.data(), nb * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(p, hipMemcpyAsync(cb + p->c_mat, &md, sizeof(MatDesc), hipMemcpyHostToDevice, s));
+  HIPCHK(p, hipStreamSynchronize(s));
+  double* bload = (double*)(cb + p->c_bload);
+  double* psi = (double*)(cb + p->c_psi);
+  double* pv = (double*)(cb + p->c_pv);
+  double* V = (double*)(cb + p->c_V);
+  double* Vn = (double*)(cb + p->c_Vn);
+  double* AV = (double*)(cb + p->c_AV);
+  double* Ap = (double*)(cb + p->c_Ap);
+  double* rpart = (double*)(cb + p->c_rpart);
+  MeshDev mdv = mesh_dev(p);
+  Ctx c;
+  c.p = p;
+  c.v = v;
+  c.w = work_view(p, work);
+  c.s = s;
+  c.nb = nb;
+  c.k = k;
+  // loads on the boxes and particular functions psi = A11^{-1} b on B1
+  k_box_load<<<dim3((p->max_nodes + 255) / 256, nb), 256, 0, s>>>(v.meta, mdv, (const FaceLoad*)(cb + p->c_faces),
+                                                                 (int)faces.size(), bload);
+  LAUNCHCHK(p);
+  if (solve(c, 0, bload, psi, 1, 1 << 1, 1, nullptr)) return MSGFEM_EHIP;
+  // PoU-weighted bases and their CholQR2 orthonormalisation
+  k_coarse_basis<<<dim3((unsigned)(((int64_t)p->max_dof * k + 255) / 256), nb), 256, 0, s>>>(
+      v.meta, k, v.mu1, evecs, psi, V, pv);
+  LAUNCHCHK(p);
+  for (int pass = 0; pass < 2; ++pass) {
+    double* Zb[1] = {V};
+    Blk3 Z, A, B;
+    Z.p[0] = A.p[0] = B.p[0] = V;
+    Z.p[1] = Z.p[2] = A.p[1] = A.p[2] = B.p[1] = B.p[2] = nullptr;
+    (void)Zb;
+    k_gram_partial<<<dim3(p->n_gchunk, nb, 2), 256, 0, s>>>(v.meta, 1, Z, A, B, k, GRAM_ROWS, p->n_gchunk,
+                                                            c.w.part, nullptr);
+    k_gram_reduce<<<dim3((2 * k * k + 255) / 256, nb), 256, 0, s>>>(k, p->n_gchunk, c.w.part, c.w.G, nullptr);
+    k_cholqr_coef<<<nb, 256, (size_t)(k * (k + 1) + k) * 8, s>>>(k, c.w.G, c.w.Y);
+    Blk4x3 Zu;
+    Out4 OX, OP;
+    for (int kind = 0; kind < 4; ++kind) {
+      Zu.p[kind][0] = Zu.p[kind][1] = Zu.p[kind][2] = nullptr;
+      OX.p[kind] = OP.p[kind] = nullptr;
+    }
+    Zu.p[0][0] = V;
+    OX.p[0] = Vn;
+    int nq = (k + 3) / 4;
+    k_update<<<dim3((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, 1), 256, (size_t)2 * k * k * 8, s>>>(
+        v.meta, 1, k, Zu, OX, OP, c.w.Y, c.w.Yp, nullptr);
+    LAUNCHCHK(p);
+    std::swap(V, Vn);
+  }
+  // A V_j and A (mu_j psi_j) on the boxes (B3 rows removed)
+  if (spmm(c, V, AV, nullptr, k, (1 << 1) | (1 << 2), 1.0, nullptr)) return MSGFEM_EHIP;
+  if (spmm(c, pv, Ap, nullptr, 1, (1 << 1) | (1 << 2), 1.0, nullptr)) return MSGFEM_EHIP;
+  // Galerkin blocks and right-hand side
+  k_fill_f64<<<1024, 256, 0, s>>>(AH, (int64_t)NH * NH, 0.0);
+  if (!p->pairs.empty())
+    k_coarse_pairs<<<(unsigned)p->pairs.size(), 256, 0, s>>>(v.meta, (const CoarsePair*)(cb + p->c_pairs), k, V, AV,
+                                                            Ap, NH, AH, rpart);
+  k_coarse_rhs<<<nb, 256, 0, s>>>(v.meta, k, V, bload, (const int32_t*)(cb + p->c_pstart),
+                                  (const int32_t*)(cb + p->c_roff), NH, rpart, AH, bH);
+  LAUNCHCHK(p);
+  (void)status;
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_coarse_solve(msgfem_plan* p, const void* ops, void* work, void* coarse,
+                                   const double* AH, const double* bH, double* cvec, double* uG,
+                                   double* up, int32_t* status, void* stream) {
+  if (!p || !ops || !coarse || !AH || !bH || !cvec || !uG || !status)
+    return fail(p, MSGFEM_EARG, "null argument");
+  if (!p->coarse_ready) return fail(p, MSGFEM_EARG, "msgfem_coarse_assemble first");
+  if (set_device(p)) return MSGFEM_EHIP;
+  (void)work;
+  hipStream_t s = (hipStream_t)stream;
+  OpsView v = ops_view(p, ops);
+  char* cb = (char*)coarse;
+  const int NT = p->NTc, NH = p->NH, k = p->k;
+  double* tiles = (double*)(cb + p->c_tiles);
+  k_fill_i32<<<1, 32, 0, s>>>(status, 1, 0);
+  k_dense_tiles<<<2048, 256, 0, s>>>(AH, NH, NT, tiles);
+  LAUNCHCHK(p);
+  if (tile_cholesky(p, (const MatDesc*)(cb + p->c_mat), 1, NT, NT, tiles, status, s)) return MSGFEM_EHIP;
+  double* ysc = (double*)(cb + p->c_y);
+  double* xsc = ysc + (int64_t)NT * 32;
+  k_dense_tile_solve<<<1, 256, 0, s>>>(tiles, NT, NH, bH, ysc, xsc);
+  LAUNCHCHK(p);
+  HIPCHK(p, hipMemcpyAsync(cvec, xsc, (size_t)NH * 8, hipMemcpyDeviceToDevice, s));
+  // u^G = u^p + V c on the global mesh
+  const int64_t ng = 3 * p->n_nodes_global;
+  k_fill_f64<<<1024, 256, 0, s>>>(uG, ng, 0.0);
+  if (up) k_fill_f64<<<1024, 256, 0, s>>>(up, ng, 0.0);
+  k_prolong<<<dim3((p->max_dof + 255) / 256, (unsigned)p->meta.size()), 256, 0, s>>>(
+      v.meta, mesh_dev(p), k, (const double*)(cb + p->c_V), (const double*)(cb + p->c_pv), cvec,
+      (const int32_t*)(cb + p->c_roff), uG, up);
+  LAUNCHCHK(p);
   return MSGFEM_OK;
 }

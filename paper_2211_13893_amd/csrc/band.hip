@@ -217,16 +217,14 @@ __device__ void diag_tile_factor(double* __restrict__ T, double* __restrict__ Ti
 // for 1 <= sJ <= sI <= m, one tile per wavefront on the matrix cores, spread
 // over workgroups; workgroup 0 also owns pair (1,1), whose target is the next
 // diagonal tile, and factors that tile (and inverts it) right after its update.
-// grid (n_wg, n_box, 2 kinds), 256 threads.
-__global__ __launch_bounds__(256) void k_chol_update(const BoxMeta* __restrict__ meta, int K,
+// grid (n_wg, n_mat), 256 threads.
+__global__ __launch_bounds__(256) void k_chol_update(const MatDesc* __restrict__ mats, int K,
                                                      double* __restrict__ fac,
                                                      int32_t* __restrict__ status) {
   __shared__ double D[32][33];
   __shared__ double Di[32][33];
   __shared__ int bad;
-  const int box = blockIdx.y, kind = blockIdx.z;
-  const BoxMeta& bm = meta[box];
-  BandView v = band_view(bm, kind);
+  const MatDesc v = mats[blockIdx.y];
   if (K >= v.NT - 1) return;
   const int m = (K < 0) ? 0 : min(v.BT - 1, v.NT - 1 - K);
   const int npairs = m * (m + 1) / 2;
@@ -253,17 +251,15 @@ __global__ __launch_bounds__(256) void k_chol_update(const BoxMeta* __restrict__
     double* T = L + (int64_t)(K + 1) * v.BT * MSG_TILE2;
     diag_tile_factor(T, fac + v.ioff + (int64_t)(K + 1) * MSG_TILE2, D, Di, &bad);
     __syncthreads();
-    if (tid == 0 && bad) atomicOr(&status[box], 4);
+    if (tid == 0 && bad) atomicOr(&status[v.status_idx], 4);
   }
 }
 
 // Panel of column K: L(K+s, K) = A(K+s, K) L_KK^{-T} = A Linv_KK^T, one tile per
-// wavefront on the matrix cores.  grid (ceil(max(BT-1)/4), n_box, 2 kinds).
-__global__ __launch_bounds__(256) void k_chol_panel(const BoxMeta* __restrict__ meta, int K,
+// wavefront on the matrix cores.  grid (ceil(max(BT-1)/4), n_mat).
+__global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* __restrict__ mats, int K,
                                                     double* __restrict__ fac) {
-  const int box = blockIdx.y, kind = blockIdx.z;
-  const BoxMeta& bm = meta[box];
-  BandView v = band_view(bm, kind);
+  const MatDesc v = mats[blockIdx.y];
   if (K >= v.NT) return;
   const int m = min(v.BT - 1, v.NT - 1 - K);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -284,12 +280,10 @@ __global__ __launch_bounds__(256) void k_chol_panel(const BoxMeta* __restrict__ 
 // form A = Lu D Lu^T with Lu(I,J) = L(I,J) L_JJ^{-1} (off-diagonal tiles, in
 // place) and D^{-1}_II = L_II^{-T} L_II^{-1} stored in the diagonal tile slot,
 // so that the block triangular sweeps need no diagonal solve.
-// grid (ceil(max NT*BT / 4), n_box, 2 kinds), one tile per wavefront.
-__global__ __launch_bounds__(256) void k_chol_unit(const BoxMeta* __restrict__ meta,
+// grid (ceil(max NT*BT / 4), n_mat), one tile per wavefront.
+__global__ __launch_bounds__(256) void k_chol_unit(const MatDesc* __restrict__ mats,
                                                    double* __restrict__ fac) {
-  const int box = blockIdx.y, kind = blockIdx.z;
-  const BoxMeta& bm = meta[box];
-  BandView v = band_view(bm, kind);
+  const MatDesc v = mats[blockIdx.y];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * 4 + wave;
   if (t >= (int64_t)v.NT * v.BT) return;
@@ -386,8 +380,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   const int rr = tid / KC, cc = tid % KC;                     // reduction mapping
   const int col = chunk * KC + cc;
   const bool colok = col < ldk;
-  const double* vin = in + bm.vec_off;
-  double* vout = out + bm.vec_off;
+  const double* vin = in + bm.dof_off * ldk;
+  double* vout = out + bm.dof_off * ldk;
   double* w = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
   const int BT = v.BT, NT = v.NT;
   double f[4][16];

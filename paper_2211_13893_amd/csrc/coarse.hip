@@ -1,0 +1,330 @@
+// The MS-GFEM coarse problem from the local spectral stage (Sec. 3.3, 4.3, 4.4).
+//
+//  k_box_load      : consistent nodal loads b_{Omega*}(phi_i) of the uniform
+//                    tractions on the mesh faces that lie in the box (2x2 Gauss on
+//                    the bilinear face quads).
+//  k_coarse_basis  : V_j = Xi_j(phi_{j,k}) = mu_j phi_{j,k} and the weighted
+//                    particular function mu_j psi_j on the box grid.
+//  k_cholqr_coef   : Cholesky of V_j^T V_j with dropping of columns whose
+//                    orthogonal part is below 1e-12 of the largest column norm,
+//                    and the coefficients R^{-1} of the orthonormalised basis
+//                    (applied twice: CholQR2, the Gram-Schmidt step of Sec. 4.3).
+//  k_coarse_pairs  : Galerkin blocks A^H_{ij} = V_i^T (A V_j) over the node
+//                    intersection of Omega_i with the box of Omega_j^*, and
+//                    V_i^T A (mu_j psi_j) for the right-hand side.
+//  k_coarse_rhs    : b^H_i = V_i^T b - sum_j V_i^T A (mu_j psi_j).
+//  k_dense_tiles / k_dense_tile_solve : the coarse matrix in dense tile form for
+//                    the tile Cholesky, and the single-RHS block solve.
+//  k_prolong       : u^G = sum_j R_j^T (mu_j psi_j + V_j c_j).
+#include "internal.hpp"
+
+namespace msg {
+
+// face descriptor: axis (0..2), side (0: low, 1: high), traction g (3)
+struct FaceLoad {
+  int32_t axis, side;
+  double g[3];
+};
+
+// Coarse pair: rows of box i, columns of box j, over the global node range [lo, hi]
+struct CoarsePair {
+  int32_t i, j;
+  int32_t lo[3], hi[3];
+  int32_t row_off, col_off;   // offsets in the coarse numbering
+};
+
+__global__ void k_box_load(const BoxMeta* __restrict__ meta, MeshDev mesh,
+                           const FaceLoad* __restrict__ faces, int n_faces,
+                           double* __restrict__ b) {
+  const BoxMeta& bm = meta[blockIdx.y];
+  int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= bm.n_nodes) return;
+  int l[3] = {node % bm.mx, (node / bm.mx) % bm.my, node / (bm.mx * bm.my)};
+  int gidx[3] = {bm.g0[0] + l[0], bm.g0[1] + l[1], bm.g0[2] + l[2]};
+  int m[3] = {bm.mx, bm.my, bm.mz};
+  int N[3] = {mesh.nx, mesh.ny, mesh.nz};
+  double acc[3] = {0.0, 0.0, 0.0};
+  const double gp = 0.57735026918962576451;
+  for (int f = 0; f < n_faces; ++f) {
+    const int ax = faces[f].axis, side = faces[f].side;
+    if (gidx[ax] != (side ? N[ax] : 0)) continue;
+    const int e1 = (ax + 1) % 3, e2 = (ax + 2) % 3;
+    // quads with lower in-face corner (u0, v0), u0 in {l-1, l}, inside the box
+    for (int du = -1; du <= 0; ++du)
+      for (int dv = -1; dv <= 0; ++dv) {
+        int u0 = l[e1] + du, v0 = l[e2] + dv;
+        if (u0 < 0 || v0 < 0 || u0 >= m[e1] - 1 || v0 >= m[e2] - 1) continue;
+        // corner coordinates of the quad (global nodes)
+        double X[2][2][3];
+        for (int a1 = 0; a1 < 2; ++a1)
+          for (int a2 = 0; a2 < 2; ++a2) {
+            int gi[3];
+            gi[ax] = gidx[ax];
+            gi[e1] = bm.g0[e1] + u0 + a1;
+            gi[e2] = bm.g0[e2] + v0 + a2;
+            int64_t gn = gi[0] + (int64_t)(mesh.nx + 1) * (gi[1] + (int64_t)(mesh.ny + 1) * gi[2]);
+            for (int c = 0; c < 3; ++c) X[a1][a2][c] = mesh.xyz[3 * gn + c];
+          }
+        const int c1 = l[e1] - u0, c2 = l[e2] - v0;  // this node's corner
+        const double r1 = 2 * c1 - 1, r2 = 2 * c2 - 1;
+        for (int q1 = 0; q1 < 2; ++q1)
+          for (int q2 = 0; q2 < 2; ++q2) {
+            double s1 = q1 ? gp : -gp, s2 = q2 ? gp : -gp;
+            double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0};
+            for (int a1 = 0; a1 < 2; ++a1)
+              for (int a2 = 0; a2 < 2; ++a2) {
+                double p1 = 2 * a1 - 1, p2 = 2 * a2 - 1;
+                double d1 = 0.25 * p1 * (1 + p2 * s2), d2 = 0.25 * (1 + p1 * s1) * p2;
+                for (int c = 0; c < 3; ++c) {
+                  t1[c] += d1 * X[a1][a2][c];
+                  t2[c] += d2 * X[a1][a2][c];
+                }
+              }
+            double nx_ = t1[1] * t2[2] - t1[2] * t2[1];
+            double ny_ = t1[2] * t2[0] - t1[0] * t2[2];
+            double nz_ = t1[0] * t2[1] - t1[1] * t2[0];
+            double dA = sqrt(nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
+            double Nn = 0.25 * (1 + r1 * s1) * (1 + r2 * s2);
+            for (int c = 0; c < 3; ++c) acc[c] += Nn * faces[f].g[c] * dA;
+          }
+      }
+  }
+  for (int c = 0; c < 3; ++c) b[bm.dof_off + 3 * node + c] = acc[c];
+}
+
+// V[dof][c] = mu1[dof] * phi[dof][c] (c < n_ev, 0 above), pv[dof] = mu1[dof] * psi[dof]
+__global__ void k_coarse_basis(const BoxMeta* __restrict__ meta, int k, const double* __restrict__ mu1,
+                               const double* __restrict__ evecs, const double* __restrict__ psi,
+                               double* __restrict__ V, double* __restrict__ pv) {
+  const BoxMeta& bm = meta[blockIdx.y];
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)bm.n_dof * k) return;
+  int dof = (int)(t / k), c = (int)(t % k);
+  double mu = mu1[bm.dof_off + dof];
+  V[bm.dof_off * k + t] = (c < bm.n_ev) ? mu * evecs[bm.evec_off + (int64_t)dof * bm.n_ev + c] : 0.0;
+  if (c == 0) pv[bm.dof_off + dof] = mu * psi[bm.dof_off + dof];
+}
+
+// One workgroup per box: Y = R^{-1} of the Cholesky factor R^T R = V^T V with
+// dropped columns zeroed.  G is [box][2][k][k] (the first copy is used).
+__global__ __launch_bounds__(256) void k_cholqr_coef(int k, const double* __restrict__ G,
+                                                     double* __restrict__ Y) {
+  extern __shared__ double sm[];
+  const int box = blockIdx.x, ld = k + 1, tid = threadIdx.x;
+  double* C = sm;            // k x (k+1)
+  int* drop = (int*)(C + k * ld);
+  const double* g = G + (int64_t)box * 2 * k * k;
+  double gmax = 0.0;
+  for (int i = 0; i < k; ++i) gmax = fmax(gmax, g[i * k + i]);
+  const double thr = 1e-24 * gmax;   // (1e-12 of the largest column norm)^2
+  for (int t = tid; t < k * k; t += 256) {
+    int i = t / k, j = t % k;
+    C[i * ld + j] = 0.5 * (g[i * k + j] + g[j * k + i]);
+  }
+  for (int t = tid; t < k; t += 256) drop[t] = 0;
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    double piv = C[j * ld + j];
+    bool dj = !(piv > thr) || gmax == 0.0;
+    if (dj) {
+      for (int t = tid; t < k; t += 256) {
+        if (t > j) C[t * ld + j] = 0.0;
+        if (t < j) C[j * ld + t] = 0.0;
+      }
+      if (tid == 0) { C[j * ld + j] = 1.0; drop[j] = 1; }
+      __syncthreads();
+      continue;
+    }
+    double sd = sqrt(piv);
+    for (int t = tid; t < k; t += 256)
+      if (t > j) C[t * ld + j] /= sd;
+    __syncthreads();
+    if (tid == 0) C[j * ld + j] = sd;
+    for (int t = tid; t < k * k; t += 256) {
+      int i = t / k, c = t % k;
+      if (i > j && c > j && c <= i) C[i * ld + c] -= C[i * ld + j] * C[c * ld + j];
+    }
+    __syncthreads();
+  }
+  // Y = L^{-T} (upper triangular), column c by back substitution: L^T y = e_c
+  double* Yb = Y + (int64_t)box * k * k;
+  for (int c = tid; c < k; c += 256) {
+    for (int i = k - 1; i >= 0; --i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int q = i + 1; q < k; ++q) s -= C[q * ld + i] * Yb[q * k + c];
+      Yb[i * k + c] = s / C[i * ld + i];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < k * k; t += 256) {
+    int i = t / k, c = t % k;
+    if (drop[i] || drop[c]) Yb[t] = 0.0;
+  }
+}
+
+// One workgroup per pair.  outputs (a, b), a < n_ev(i), b <= n_ev(j) (b = n_ev(j)
+// is the particular column); AH row-major NH x NH; rpart[pair][32].
+__global__ __launch_bounds__(256) void k_coarse_pairs(const BoxMeta* __restrict__ meta,
+                                                      const CoarsePair* __restrict__ pairs, int k,
+                                                      const double* __restrict__ V,
+                                                      const double* __restrict__ AV,
+                                                      const double* __restrict__ Ap, int NH,
+                                                      double* __restrict__ AH,
+                                                      double* __restrict__ rpart) {
+  const CoarsePair pr = pairs[blockIdx.x];
+  const BoxMeta& bi = meta[pr.i];
+  const BoxMeta& bj = meta[pr.j];
+  const int na = bi.n_ev, nbc = bj.n_ev + 1;
+  const int sx = pr.hi[0] - pr.lo[0] + 1, sy = pr.hi[1] - pr.lo[1] + 1, sz = pr.hi[2] - pr.lo[2] + 1;
+  const int64_t nn = (int64_t)sx * sy * sz;
+  const double* Vi = V + bi.dof_off * k;
+  const double* AVj = AV + bj.dof_off * k;
+  const double* Apj = Ap + bj.dof_off;
+  for (int o = threadIdx.x; o < na * nbc; o += 256) {
+    const int a = o / nbc, b = o % nbc;
+    double acc = 0.0;
+    for (int64_t t = 0; t < nn; ++t) {
+      int gx = pr.lo[0] + (int)(t % sx), gy = pr.lo[1] + (int)((t / sx) % sy), gz = pr.lo[2] + (int)(t / ((int64_t)sx * sy));
+      int ni = (gx - bi.g0[0]) + bi.mx * ((gy - bi.g0[1]) + bi.my * (gz - bi.g0[2]));
+      int nj = (gx - bj.g0[0]) + bj.mx * ((gy - bj.g0[1]) + bj.my * (gz - bj.g0[2]));
+      for (int c = 0; c < 3; ++c) {
+        double vi = Vi[(int64_t)(3 * ni + c) * k + a];
+        double w = (b < bj.n_ev) ? AVj[(int64_t)(3 * nj + c) * k + b] : Apj[3 * nj + c];
+        acc += vi * w;
+      }
+    }
+    if (b < bj.n_ev) AH[(int64_t)(pr.row_off + a) * NH + pr.col_off + b] = acc;
+    else rpart[(int64_t)blockIdx.x * 32 + a] = acc;
+  }
+}
+
+// b^H_i[a] = V_i[:,a]^T b_i - sum over the pairs of row box i of rpart; a unit
+// diagonal for dropped (zero) coarse functions.  One workgroup per box.
+__global__ __launch_bounds__(256) void k_coarse_rhs(const BoxMeta* __restrict__ meta, int k,
+                                                    const double* __restrict__ V,
+                                                    const double* __restrict__ bload,
+                                                    const int32_t* __restrict__ pair_start,
+                                                    const int32_t* __restrict__ row_off, int NH,
+                                                    const double* __restrict__ rpart,
+                                                    double* __restrict__ AH,
+                                                    double* __restrict__ bH) {
+  __shared__ double red[256];
+  const int box = blockIdx.x;
+  const BoxMeta& bm = meta[box];
+  const double* Vb = V + bm.dof_off * k;
+  const double* bb = bload + bm.dof_off;
+  for (int a = 0; a < bm.n_ev; ++a) {
+    double s = 0.0;
+    for (int d = threadIdx.x; d < bm.n_dof; d += 256) s += Vb[(int64_t)d * k + a] * bb[d];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double r = red[0];
+      for (int p = pair_start[box]; p < pair_start[box + 1]; ++p) r -= rpart[(int64_t)p * 32 + a];
+      const int64_t l = row_off[box] + a;
+      bH[l] = r;
+      if (AH[l * NH + l] == 0.0) AH[l * NH + l] = 1.0;
+    }
+    __syncthreads();
+  }
+}
+
+// dense NH x NH (row-major) -> tile-band storage with BT = NT (lower tiles, identity padding)
+__global__ void k_dense_tiles(const double* __restrict__ AH, int NH, int NT, double* __restrict__ T) {
+  int64_t total = (int64_t)NT * NT * MSG_TILE2;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int e = (int)(t & 1023);
+    int64_t tile = t >> 10;
+    int I = (int)(tile / NT), s = (int)(tile % NT);
+    int row = I * 32 + (e >> 5), col = (I - s) * 32 + (e & 31);
+    double v = 0.0;
+    if (col >= 0 && col <= row) {
+      if (row < NH && col < NH) v = AH[(int64_t)row * NH + col];
+      else v = (row == col) ? 1.0 : 0.0;
+    }
+    T[t] = v;
+  }
+}
+
+// Single-RHS solve with the unit-lower tile factor A = Lu D Lu^T of a dense
+// matrix (BT = NT).  One workgroup of 256 threads; y, w in global scratch.
+__global__ __launch_bounds__(256) void k_dense_tile_solve(const double* __restrict__ T, int NT,
+                                                          int NH, const double* __restrict__ b,
+                                                          double* __restrict__ y,
+                                                          double* __restrict__ x) {
+  __shared__ double part[8][33];
+  const int tid = threadIdx.x, r = tid & 31, g = tid >> 5;
+  const int BT = NT;
+  // forward Lu y = b
+  for (int I = 0; I < NT; ++I) {
+    double acc = 0.0;
+    for (int s = 1 + g; s <= I; s += 8) {
+      const double* Lr = T + ((int64_t)I * BT + s) * MSG_TILE2 + r * 32;
+      const double* yp = y + (int64_t)(I - s) * 32;
+      for (int q = 0; q < 32; ++q) acc += Lr[q] * yp[q];
+    }
+    part[g][r] = acc;
+    __syncthreads();
+    if (tid < 32) {
+      double sum = 0.0;
+      for (int q = 0; q < 8; ++q) sum += part[q][tid];
+      int row = I * 32 + tid;
+      y[row] = (row < NH ? b[row] : 0.0) - sum;
+    }
+    __syncthreads();
+  }
+  // w = D^{-1} y (diagonal tile slot holds D^{-1}), stored in x
+  for (int I = g; I < NT; I += 8) {
+    const double* Dr = T + ((int64_t)I * BT) * MSG_TILE2 + r * 32;
+    double s = 0.0;
+    for (int q = 0; q < 32; ++q) s += Dr[q] * y[I * 32 + q];
+    x[I * 32 + r] = s;
+  }
+  __syncthreads();
+  // backward Lu^T x = w (in place: x_I final once all later blocks are final)
+  for (int I = NT - 1; I >= 0; --I) {
+    double acc = 0.0;
+    for (int s = 1 + g; s <= NT - 1 - I; s += 8) {
+      const double* Lc = T + ((int64_t)(I + s) * BT + s) * MSG_TILE2 + r;
+      const double* xp = x + (int64_t)(I + s) * 32;
+      for (int q = 0; q < 32; ++q) acc += Lc[q * 32] * xp[q];
+    }
+    part[g][r] = acc;
+    __syncthreads();
+    if (tid < 32) {
+      double sum = 0.0;
+      for (int q = 0; q < 8; ++q) sum += part[q][tid];
+      x[I * 32 + tid] -= sum;
+    }
+    __syncthreads();
+  }
+}
+
+// u^G[global dof] += mu_j psi_j + V_j c_j (atomic over the boxes sharing a node)
+__global__ void k_prolong(const BoxMeta* __restrict__ meta, MeshDev mesh, int k,
+                          const double* __restrict__ V, const double* __restrict__ pv,
+                          const double* __restrict__ c, const int32_t* __restrict__ row_off,
+                          double* __restrict__ uG, double* __restrict__ up) {
+  const int box = blockIdx.y;
+  const BoxMeta& bm = meta[box];
+  int dof = blockIdx.x * blockDim.x + threadIdx.x;
+  if (dof >= bm.n_dof) return;
+  int node = dof / 3, comp = dof % 3;
+  int gi = bm.g0[0] + node % bm.mx, gj = bm.g0[1] + (node / bm.mx) % bm.my,
+      gk = bm.g0[2] + node / (bm.mx * bm.my);
+  int64_t gd = 3 * (gi + (int64_t)(mesh.nx + 1) * (gj + (int64_t)(mesh.ny + 1) * gk)) + comp;
+  const double* Vr = V + (bm.dof_off + dof) * k;
+  const double* cb = c + row_off[box];
+  double p = pv[bm.dof_off + dof];
+  double s = p;
+  for (int a = 0; a < bm.n_ev; ++a) s += Vr[a] * cb[a];
+  if (s != 0.0) atomicAdd(&uG[gd], s);
+  if (up && p != 0.0) atomicAdd(&up[gd], p);
+}
+
+}  // namespace msg

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(const BoxMeta* __restrict_
       zf[b] = 0.0;
       wf[b] = 0.0;
       if (b < nb16 && rok && cblk[b] >= 0) {
-        int64_t o = bm.vec_off + (int64_t)row * k + ccol[b];
+        int64_t o = (bm.dof_off * k) + (int64_t)row * k + ccol[b];
         zf[b] = Z.p[cblk[b]][o];
         wf[b] = W.p[cblk[b]][o];
       }
@@ -386,8 +386,8 @@ __global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta
     int64_t n = (int64_t)bm.n_dof * k;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
-      OX.p[kind][bm.vec_off + t] = Z.p[kind][0][bm.vec_off + t];
-      if (OP.p[kind] && nblk == 3) OP.p[kind][bm.vec_off + t] = Z.p[kind][2][bm.vec_off + t];
+      OX.p[kind][(bm.dof_off * k) + t] = Z.p[kind][0][(bm.dof_off * k) + t];
+      if (OP.p[kind] && nblk == 3) OP.p[kind][(bm.dof_off * k) + t] = Z.p[kind][2][(bm.dof_off * k) + t];
     }
     return;
   }
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta
   int row = (int)(t / nq), c0 = 4 * (int)(t % nq);
   double ax[4] = {}, ap[4] = {};
   for (int b = 0; b < nblk; ++b) {
-    const double* zr = Z.p[kind][b] + bm.vec_off + (int64_t)row * k;
+    const double* zr = Z.p[kind][b] + (bm.dof_off * k) + (int64_t)row * k;
     for (int cc = 0; cc < k; ++cc) {
       double zv = zr[cc];
       int i = b * k + cc;
@@ -419,12 +419,12 @@ __global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta
       }
     }
   }
-  double* ox = OX.p[kind] + bm.vec_off + (int64_t)row * k;
+  double* ox = OX.p[kind] + (bm.dof_off * k) + (int64_t)row * k;
 #pragma unroll
   for (int j = 0; j < 4; ++j)
     if (c0 + j < k) ox[c0 + j] = ax[j];
   if (wantP) {
-    double* op = OP.p[kind] + bm.vec_off + (int64_t)row * k;
+    double* op = OP.p[kind] + (bm.dof_off * k) + (int64_t)row * k;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       if (c0 + j < k) op[c0 + j] = ap[j];
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256) void k_residual(const BoxMeta* __restrict__ me
     int r_begin = chunk * rows_per_chunk;
     int r_end = min(bm.n_dof, r_begin + rows_per_chunk);
     for (int row = r_begin + slot; row < r_end; row += 8) {
-      int64_t o = bm.vec_off + (int64_t)row * k + col;
+      int64_t o = (bm.dof_off * k) + (int64_t)row * k + col;
       double r = 0.0;
       if (cls[bm.dof_off + row] == 2) {
         double mx = MX[o], sx = AX[o];
@@ -539,7 +539,7 @@ __global__ void k_random_start(const BoxMeta* __restrict__ meta, const uint8_t* 
     uint64_t h = mix64(seed ^ mix64(((uint64_t)bm.sd << 40) ^ ((uint64_t)row << 8) ^ (uint64_t)col));
     v = (double)(h >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
   }
-  X[bm.vec_off + t] = v;
+  X[(bm.dof_off * k) + t] = v;
 }
 
 // copy a caller start block (boundary values on B2 DoFs, box layout [n_dof][k]) into X
@@ -550,7 +550,7 @@ __global__ void k_copy_start(const BoxMeta* __restrict__ meta, const uint8_t* __
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)bm.n_dof * k) return;
   int row = (int)(t / k);
-  X[bm.vec_off + t] = (cls[bm.dof_off + row] == 2) ? X0[bm.vec_off + t] : 0.0;
+  X[(bm.dof_off * k) + t] = (cls[bm.dof_off + row] == 2) ? X0[(bm.dof_off * k) + t] : 0.0;
 }
 
 // Output: lambda ascending, unit 2-norm eigenvectors on all box DoFs (0 on B3)
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(256) void k_output(const BoxMeta* __restrict__ meta
   int imax = 0x7fffffff;
   if (col < nev) {
     for (int row = slot; row < bm.n_dof; row += 8) {
-      double v = X[bm.vec_off + (int64_t)row * k + col];
+      double v = X[(bm.dof_off * k) + (int64_t)row * k + col];
       s2 += v * v;
       double a = fabs(v);
       if (a > amax) { amax = a; imax = row; }
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(256) void k_output(const BoxMeta* __restrict__ meta
       if (a > am || (a == am && ii < im)) { am = a; im = ii; }
     }
     if (im < 0 || im >= bm.n_dof) im = 0;   // all-NaN column: keep the read in bounds
-    double v = X[bm.vec_off + (int64_t)im * k + tid];
+    double v = X[(bm.dof_off * k) + (int64_t)im * k + tid];
     double sg = (v < 0.0) ? -1.0 : 1.0;
     scale[tid] = sg / sqrt(n2);
     double nv = nu[(int64_t)box * k + tid];
@@ -604,7 +604,7 @@ __global__ __launch_bounds__(256) void k_output(const BoxMeta* __restrict__ meta
   __syncthreads();
   for (int64_t t = tid; t < (int64_t)bm.n_dof * nev; t += 256) {
     int row = (int)(t / nev), c = (int)(t % nev);
-    evecs[bm.evec_off + t] = X[bm.vec_off + (int64_t)row * k + c] * scale[c];
+    evecs[bm.evec_off + t] = X[(bm.dof_off * k) + (int64_t)row * k + c] * scale[c];
   }
 }
 

@@ -45,6 +45,15 @@ struct BoxMeta {
   int64_t eval_off;           // offset into eigenvalue output
 };
 
+// One SPD matrix in 32x32 tile-band storage (tiles at fac + off, inverse
+// diagonal tiles at fac + ioff); BT == NT is a dense matrix.
+struct MatDesc {
+  int32_t NT, BT;
+  int32_t status_idx;   // index into the status array for pivot failures
+  int32_t pad_;
+  int64_t off, ioff;
+};
+
 struct MeshDev {
   int32_t nx, ny, nz;
   int32_t n_mat;

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_spmm(const BoxMeta* __restrict__ meta,
   const double* st = stencil + bm.node_off * 243;
   const uint8_t* cl = cls + bm.dof_off;
   const double* m1 = mu1 + bm.dof_off;
-  const double* x = X + bm.vec_off;
+  const double* x = X + (bm.dof_off * k);
   double acc[3][4] = {}, acc2[3][4] = {};
   const bool two = Y2 != nullptr;
   for (int dz = -1; dz <= 1; ++dz) {
@@ -72,8 +72,8 @@ __global__ __launch_bounds__(256) void k_spmm(const BoxMeta* __restrict__ meta,
       }
     }
   }
-  double* y = Y ? Y + bm.vec_off : nullptr;
-  double* y2 = two ? Y2 + bm.vec_off : nullptr;
+  double* y = Y ? Y + (bm.dof_off * k) : nullptr;
+  double* y2 = two ? Y2 + (bm.dof_off * k) : nullptr;
 #pragma unroll
   for (int cr = 0; cr < 3; ++cr) {
     int d = 3 * node + cr;

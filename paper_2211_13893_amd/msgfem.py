@@ -55,6 +55,10 @@ class msgfem_box_info(ctypes.Structure):
                 ("evec_off", ctypes.c_int64), ("eval_off", ctypes.c_int64)]
 
 
+class msgfem_load(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("face", ctypes.c_void_p), ("g", ctypes.c_void_p)]
+
+
 class msgfem_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
@@ -72,6 +76,11 @@ SIGNATURES = {
     "msgfem_assemble_local": (ctypes.c_int, [_P, _P, _P, _P]),
     "msgfem_local_eigs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "msgfem_local_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    "msgfem_coarse_sizes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_int32)]),
+    "msgfem_coarse_assemble": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(msgfem_load), _P, _P, _P, _P,
+                                              _P, _P]),
+    "msgfem_coarse_solve": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "msgfem_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "msgfem_profile_stats": (ctypes.c_int, [_P, ctypes.POINTER(msgfem_kernel_stat), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
@@ -230,6 +239,47 @@ class LocalStage:
                                          _stream_handle(torch, self.device))
         _check(rc, self.plan, "msgfem_local_apply")
         return y
+
+    def msgfem_coarse_sizes(self):
+        nb = ctypes.c_int64()
+        nh = ctypes.c_int32()
+        _check(self.lib.msgfem_coarse_sizes(self.plan, ctypes.byref(nb), ctypes.byref(nh)), self.plan,
+               "msgfem_coarse_sizes")
+        return nb.value, nh.value
+
+    def msgfem_coarse_assemble(self, eig_out):
+        torch = self.torch
+        nbytes, nh = self.msgfem_coarse_sizes()
+        if getattr(self, "coarse", None) is None or self.coarse.numel() < nbytes:
+            self.coarse = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        faces = {"x-": 0, "x+": 1, "y-": 2, "y+": 3, "z-": 4, "z+": 5}
+        tr = self.problem.tractions
+        self._face = np.asarray([faces[f] for f, _ in tr], dtype=np.int32)
+        self._g = np.ascontiguousarray(np.asarray([g for _, g in tr], dtype=np.float64).reshape(-1, 3))
+        ld = msgfem_load(len(tr), self._face.ctypes.data if len(tr) else 0,
+                         self._g.ctypes.data if len(tr) else 0)
+        AH = torch.empty((nh, nh), dtype=torch.float64, device=self.device)
+        bH = torch.empty(nh, dtype=torch.float64, device=self.device)
+        rc = self.lib.msgfem_coarse_assemble(self.plan, _ptr(self.ops), _ptr(self._alloc_work()),
+                                             ctypes.byref(ld), _ptr(eig_out["evecs"]), _ptr(self.coarse),
+                                             _ptr(AH), _ptr(bH), _ptr(self.status),
+                                             _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_coarse_assemble")
+        return AH, bH
+
+    def msgfem_coarse_solve(self, AH, bH):
+        torch = self.torch
+        nh = AH.shape[0]
+        c = torch.empty(nh, dtype=torch.float64, device=self.device)
+        ng = self.problem.n_dofs
+        uG = torch.empty(ng, dtype=torch.float64, device=self.device)
+        up = torch.empty(ng, dtype=torch.float64, device=self.device)
+        st = torch.zeros(1, dtype=torch.int32, device=self.device)
+        rc = self.lib.msgfem_coarse_solve(self.plan, _ptr(self.ops), _ptr(self._alloc_work()),
+                                          _ptr(self.coarse), _ptr(AH), _ptr(bH), _ptr(c), _ptr(uG), _ptr(up),
+                                          _ptr(st), _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_coarse_solve")
+        return dict(c=c, uG=uG, up=up, status=st)
 
     def msgfem_profile(self, enable: bool):
         _check(self.lib.msgfem_profile(self.plan, 1 if enable else 0), self.plan, "msgfem_profile")
