@@ -84,7 +84,10 @@ typedef struct {
   int32_t maxit;    /* LOBPCG iteration cap (default 200) */
   int32_t block;    /* block width k >= max n_ev (0: n_ev + max(4, n_ev/2) rounded up to 8) */
   int32_t precision;/* 0 = FP64 throughout */
-  int32_t reserved;
+  int32_t geneo;    /* 0: A-harmonic GEVP on Omega_j^* (Sec. 3.3); 1: classic GenEO GEVP
+                       a_{Omega_j}(phi, v) = lambda a_{Omega_j}(Xi phi, Xi v) on Omega_j
+                       itself (Sec. 3.2; oversampling ignored), unknowns on every
+                       non-Dirichlet DoF, preconditioned by (A + s D A D)^{-1} */
   uint64_t seed;    /* seed of the random start block */
 } msgfem_eig_opts;
 
@@ -209,6 +212,24 @@ int msgfem_coarse_assemble(msgfem_plan *plan, const void *ops, void *work, const
 int msgfem_coarse_solve(msgfem_plan *plan, const void *ops, void *work, void *coarse,
                         const double *AH, const double *bH, double *c, double *uG, double *up,
                         int32_t *status, void *stream);
+
+/* Device bytes of the caller's PCG workspace (whole-mesh stencil and vectors). */
+int msgfem_pcg_sizes(msgfem_plan *plan, int64_t *bytes);
+
+/* GenEO two-level additive Schwarz preconditioned CG on the whole mesh
+ * (Sec. 3.2; the fine reference solve of Sec. 5.3), for comparison with the
+ * MS-GFEM coarse approximation.  The plan must be a GenEO plan (opts.geneo =
+ * 1) whose batch lists every subdomain, after msgfem_assemble_local,
+ * msgfem_local_eigs and msgfem_coarse_assemble (AH is then the coarse matrix
+ * A_0 of the GenEO space; its bH is not used).  The preconditioner is
+ * M^{-1} = R_0^T A_0^{-1} R_0 + sum_j R_j^T A_j^{-1} R_j with A_j the interior
+ * block of Omega_j.  u (device, 3 * n_nodes): initial guess in, solution out
+ * (zero on Dirichlet DoFs); iterations stop at |r| <= rtol |b|.  iters, relres:
+ * host outputs (the call synchronises the stream).  status[0] = 1 if maxit was
+ * reached, bit 4 if A_0 is not numerically positive definite. */
+int msgfem_geneo_pcg(msgfem_plan *plan, const void *ops, void *work, void *coarse, const double *AH,
+                     const msgfem_load *load, double rtol, int32_t maxit, void *pcg, double *u,
+                     int32_t *iters, double *relres, int32_t *status, void *stream);
 
 /* Kernel timing.  msgfem_profile(plan, 1) clears the counters and starts
  * recording a pair of HIP events around every launch of the library's hot

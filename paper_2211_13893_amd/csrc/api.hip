@@ -39,12 +39,14 @@ __global__ void k_rayleigh_ritz(int, int, int, double, const double*, double*, d
                                 double*, const int32_t*);
 __global__ void k_update(const BoxMeta*, int, int, Blk4x3, Out4, Out4, const double*, const double*,
                          const int32_t*);
-__global__ void k_residual(const BoxMeta*, const uint8_t*, int, double, const double*, const double*,
+__global__ void k_residual(const BoxMeta*, const uint8_t*, int, int, double, const double*, const double*,
                            const double*, double*, int, int, double*, const int32_t*);
 __global__ void k_converge(const BoxMeta*, int, int, int, const double*, const double*, double, double*,
                            int32_t*, int32_t*, int32_t*, int);
-__global__ void k_random_start(const BoxMeta*, const uint8_t*, int, uint64_t, double*);
-__global__ void k_copy_start(const BoxMeta*, const uint8_t*, int, const double*, double*);
+__global__ void k_random_start(const BoxMeta*, const uint8_t*, int, int, uint64_t, double*);
+__global__ void k_lock(const BoxMeta*, int, const double*, double, double*, double*, double*, double*, double*,
+                       const int32_t*);
+__global__ void k_copy_start(const BoxMeta*, const uint8_t*, int, int, const double*, double*);
 __global__ void k_output(const BoxMeta*, int, double, const double*, const double*, const double*,
                          double*, double*, double*);
 struct FaceLoad {
@@ -68,6 +70,17 @@ __global__ void k_dense_tiles(const double*, int, int, double*);
 __global__ void k_dense_tile_solve(const double*, int, int, const double*, double*, double*);
 __global__ void k_prolong(const BoxMeta*, MeshDev, int, const double*, const double*, const double*,
                           const int32_t*, double*, double*);
+__global__ void k_gather_boxes(const BoxMeta*, MeshDev, const uint8_t*, const double*, double*);
+__global__ void k_scatter_boxes(const BoxMeta*, MeshDev, const uint8_t*, const double*, double*);
+__global__ void k_coarse_restrict(const BoxMeta*, int, const double*, const double*, const int32_t*, double*);
+__global__ void k_dot_partial(const double*, const double*, const uint8_t*, int64_t, double*);
+__global__ void k_dot_final(const double*, int, double*);
+__global__ void k_pcg_alpha(double*);
+__global__ void k_pcg_beta(double*);
+__global__ void k_pcg_xr(const uint8_t*, int64_t, const double*, const double*, const double*, double*,
+                         double*);
+__global__ void k_pcg_p(const uint8_t*, int64_t, const double*, const double*, double*);
+__global__ void k_sub(const uint8_t*, int64_t, const double*, const double*, double*);
 }  // namespace msg
 
 using namespace msg;
@@ -219,7 +232,7 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   if (dec->nsd < 1 || !dec->cores || !dec->ovs || dec->overlap < 1)
     return fail(p, MSGFEM_EARG, "bad decomposition (nsd >= 1, overlap >= 1 required)");
   msgfem_eig_opts o;
-  o.shift = 1.0; o.tol = 1e-6; o.maxit = 200; o.block = 0; o.precision = 0; o.reserved = 0; o.seed = 1234;
+  o.shift = 1.0; o.tol = 1e-6; o.maxit = 200; o.block = 0; o.precision = 0; o.geneo = 0; o.seed = 1234;
   if (opts) {
     o = *opts;
     if (!(o.shift > 0)) o.shift = 1.0;
@@ -263,7 +276,7 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     std::memset(&m, 0, sizeof m);
     m.sd = sd;
     const int32_t* c = dec->cores + 6 * sd;
-    int g = dec->overlap + dec->ovs[sd];
+    int g = dec->overlap + (o.geneo ? 0 : dec->ovs[sd]);   // GenEO works on Omega_j itself
     int lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
       lo[d] = std::max(c[d] - g, 0);
@@ -751,17 +764,26 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
   double* tmp = c.w.vec + (int64_t)20 * VT;
   int32_t* act = c.w.active;
   const size_t lds_upd3 = (size_t)2 * 3 * k * k * 8;
+  // A-harmonic GEVP: unknowns on B2, images through the extension; GenEO: all
+  // of B1 u B2, M = D A D itself (kind 2 doubles as M Z)
+  const bool geneo = p->opts.geneo != 0;
+  const int vcls = geneo ? ((1 << 1) | (1 << 2)) : (1 << 2);
+  const int nkinds = geneo ? 3 : 4;
+  auto images = [&](double* Z, double* AZ, double* BZ, double* MZ, const int32_t* a_) -> int {
+    if (geneo) return spmm(c, Z, AZ, BZ, k, (1 << 1) | (1 << 2), 1.0, a_);
+    return harmonic_images(c, Z, AZ, BZ, MZ, tmp, a_);
+  };
   k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(act, nb, 1);
   k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(c.w.iters, nb, 0);
   LAUNCHCHK(p);
   // start block
   {
     dim3 grid((unsigned)(((int64_t)p->max_dof * k + 255) / 256), nb);
-    if (x0) k_copy_start<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, x0, B[0][0]);
-    else k_random_start<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, p->opts.seed, B[0][0]);
+    if (x0) k_copy_start<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, vcls, x0, B[0][0]);
+    else k_random_start<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, vcls, p->opts.seed, B[0][0]);
     LAUNCHCHK(p);
   }
-  if (harmonic_images(c, B[0][0], B[1][0], B[2][0], B[3][0], tmp, nullptr)) return MSGFEM_EHIP;
+  if (images(B[0][0], B[1][0], B[2][0], B[3][0], nullptr)) return MSGFEM_EHIP;
   // initial Rayleigh-Ritz on X alone (T-orthonormalises the start block)
   {
     double* Zb[1] = {B[0][0]};
@@ -777,7 +799,7 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
       OP.p[kind] = nullptr;
     }
     int nq = (k + 3) / 4;
-    dim3 grid((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, 4);
+    dim3 grid((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, nkinds);
     k_update<<<grid, 256, (size_t)2 * k * k * 8, c.s>>>(c.v.meta, 1, k, Z, OX, OP, c.w.Y, c.w.Yp, nullptr);
     LAUNCHCHK(p);
     for (int kind = 0; kind < 4; ++kind) std::swap(B[kind][0], B[kind][3]);
@@ -787,7 +809,8 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
     // residual of the current Ritz block, convergence, active set
     {
       dim3 grid(n_chunk, nb);
-      k_residual<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, p->opts.shift, B[1][0], B[3][0], c.w.nu,
+      k_residual<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, vcls, k, p->opts.shift, B[1][0],
+                                        geneo ? B[2][0] : B[3][0], c.w.nu,
                                         B[0][1], GRAM_ROWS, n_chunk, c.w.rpart, act);
       LAUNCHCHK(p);
       k_fill_i32<<<1, 32, 0, c.s>>>(c.w.nact, 1, 0);
@@ -802,9 +825,18 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
       for (int b = 0; b < nb; ++b) nact += c.act_h[b] != 0;
       if (nact == 0 || it == p->opts.maxit) break;
     }
+    // soft locking of converged columns (their W and P directions vanish)
+    {
+      dim3 grid((unsigned)(((int64_t)p->max_dof * k + 255) / 256), nb);
+      const bool hasP = it > 0;
+      k_lock<<<grid, 256, 0, c.s>>>(c.v.meta, k, c.w.rho, 0.1 * p->opts.tol, B[0][1],
+                                    hasP ? B[0][2] : nullptr, hasP ? B[1][2] : nullptr,
+                                    hasP ? B[2][2] : nullptr, (hasP && !geneo) ? B[3][2] : nullptr, act);
+      LAUNCHCHK(p);
+    }
     // W = preconditioned residual: B2 trace of (A + s DAD)^{-1} [0; R]
-    if (solve(c, 1, B[0][1], B[0][1], k, 1 << 2, 1, act)) return MSGFEM_EHIP;
-    if (harmonic_images(c, B[0][1], B[1][1], B[2][1], B[3][1], tmp, act)) return MSGFEM_EHIP;
+    if (solve(c, 1, B[0][1], B[0][1], k, vcls, 1, act)) return MSGFEM_EHIP;
+    if (images(B[0][1], B[1][1], B[2][1], B[3][1], act)) return MSGFEM_EHIP;
     int nblk = (it == 0) ? 2 : 3;
     double* Zb[3] = {B[0][0], B[0][1], B[0][2]};
     double* Ab[3] = {B[1][0], B[1][1], B[1][2]};
@@ -818,7 +850,7 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
       OP.p[kind] = B[kind][4];
     }
     int nq = (k + 3) / 4;
-    dim3 grid((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, 4);
+    dim3 grid((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, nkinds);
     double by = 0, fl = 0;
     for (int b = 0; b < nb; ++b) {
       if (!c.counts(b, act)) continue;
@@ -1134,5 +1166,181 @@ extern "C" int msgfem_coarse_solve(msgfem_plan* p, const void* ops, void* work, 
       v.meta, mesh_dev(p), k, (const double*)(cb + p->c_V), (const double*)(cb + p->c_pv), cvec,
       (const int32_t*)(cb + p->c_roff), uG, up);
   LAUNCHCHK(p);
+  return MSGFEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GenEO two-level additive Schwarz PCG (comparison solver)
+
+namespace {
+struct PcgLayout {
+  int64_t meta, stencil, cls, mu, b, x, r, z, p, q, rb, zb, zero, part, sc, total;
+};
+}  // namespace
+
+static PcgLayout pcg_layout(const msgfem_plan* p) {
+  PcgLayout L;
+  const int64_t ng = p->n_nodes_global, nd = 3 * ng, nbd = p->dofs_total;
+  int64_t off = 0;
+  L.meta = off; off = align256(off + sizeof(BoxMeta));
+  L.stencil = off; off = align256(off + ng * 243 * 8);
+  L.cls = off; off = align256(off + nd);
+  L.mu = off; off = align256(off + nd * 8);
+  L.b = off; off = align256(off + nd * 8);
+  L.x = off; off = align256(off + nd * 8);
+  L.r = off; off = align256(off + nd * 8);
+  L.z = off; off = align256(off + nd * 8);
+  L.p = off; off = align256(off + nd * 8);
+  L.q = off; off = align256(off + nd * 8);
+  L.rb = off; off = align256(off + nbd * 8);
+  L.zb = off; off = align256(off + nbd * 8);
+  L.zero = off; off = align256(off + nbd * 8);
+  L.part = off; off = align256(off + 1024 * 8);
+  L.sc = off; off = align256(off + 16 * 8);
+  L.total = off;
+  return L;
+}
+
+extern "C" int msgfem_pcg_sizes(msgfem_plan* p, int64_t* bytes) {
+  if (!p || !bytes) return MSGFEM_EARG;
+  *bytes = pcg_layout(p).total;
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_geneo_pcg(msgfem_plan* p, const void* ops, void* work, void* coarse, const double* AH,
+                                const msgfem_load* load, double rtol, int32_t maxit, void* pcg, double* u,
+                                int32_t* iters, double* relres, int32_t* status, void* stream) {
+  if (!p || !ops || !work || !coarse || !AH || !pcg || !u || !iters || !relres || !status)
+    return fail(p, MSGFEM_EARG, "null argument");
+  if (!p->opts.geneo) return fail(p, MSGFEM_EARG, "msgfem_geneo_pcg needs a GenEO plan (opts.geneo = 1)");
+  if (!p->coarse_ready) return fail(p, MSGFEM_EARG, "msgfem_coarse_assemble first");
+  if (!(rtol > 0) || maxit < 1) return fail(p, MSGFEM_EARG, "bad rtol / maxit");
+  if (set_device(p)) return MSGFEM_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  OpsView v = ops_view(p, ops);
+  char* cb = (char*)coarse;
+  char* pb = (char*)pcg;
+  const PcgLayout L = pcg_layout(p);
+  const int nb = (int)p->meta.size(), k = p->k, NT = p->NTc, NH = p->NH;
+  const int64_t ng = p->n_nodes_global, nd = 3 * ng;
+  MeshDev md = mesh_dev(p);
+  // whole-mesh box: stencil, classes (B1 free, B3 clamped), zero PoU
+  BoxMeta gm;
+  std::memset(&gm, 0, sizeof gm);
+  gm.sd = -1;
+  gm.mx = p->mesh.nx + 1; gm.my = p->mesh.ny + 1; gm.mz = p->mesh.nz + 1;
+  for (int d = 0; d < 3; ++d) { gm.olo[d] = 1; gm.ohi[d] = 0; }
+  gm.n_nodes = (int32_t)ng;
+  gm.n_dof = (int32_t)nd;
+  HIPCHK(p, hipMemcpyAsync(pb + L.meta, &gm, sizeof gm, hipMemcpyHostToDevice, s));
+  std::vector<FaceLoad> faces;
+  if (load) {
+    if (load->n < 0 || load->n > 6 || (load->n > 0 && (!load->face || !load->g)))
+      return fail(p, MSGFEM_EARG, "bad load description");
+    for (int f = 0; f < load->n; ++f) {
+      FaceLoad fl;
+      fl.axis = load->face[f] / 2;
+      fl.side = load->face[f] % 2;
+      for (int c = 0; c < 3; ++c) fl.g[c] = load->g[3 * f + c];
+      faces.push_back(fl);
+    }
+    if (!faces.empty())
+      HIPCHK(p, hipMemcpyAsync(cb + p->c_faces, faces.data(), faces.size() * sizeof(FaceLoad),
+                               hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(p, hipStreamSynchronize(s));
+  const BoxMeta* gmeta = (const BoxMeta*)(pb + L.meta);
+  double* gst = (double*)(pb + L.stencil);
+  uint8_t* gcls = (uint8_t*)(pb + L.cls);
+  double* gmu = (double*)(pb + L.mu);
+  double *b = (double*)(pb + L.b), *x = (double*)(pb + L.x), *r = (double*)(pb + L.r),
+         *z = (double*)(pb + L.z), *pp = (double*)(pb + L.p), *q = (double*)(pb + L.q);
+  double *rb = (double*)(pb + L.rb), *zb = (double*)(pb + L.zb), *zero = (double*)(pb + L.zero);
+  double *part = (double*)(pb + L.part), *sc = (double*)(pb + L.sc);
+  k_fill_i32<<<1, 32, 0, s>>>(status, 1, 0);
+  k_assemble<<<dim3((unsigned)((ng + 3) / 4), 1), 256, 0, s>>>(gmeta, md, v.ctab, gst);
+  k_classes_mu<<<dim3((unsigned)((ng + 255) / 256), 1), 256, 0, s>>>(gmeta, md, 2 * p->overlap, v.wtot, gcls, gmu);
+  k_box_load<<<dim3((unsigned)((ng + 255) / 256), 1), 256, 0, s>>>(gmeta, md, (const FaceLoad*)(cb + p->c_faces),
+                                                                  (int)faces.size(), b);
+  k_fill_f64<<<1024, 256, 0, s>>>(zero, p->dofs_total, 0.0);
+  LAUNCHCHK(p);
+  // coarse factor A_0
+  double* tiles = (double*)(cb + p->c_tiles);
+  k_dense_tiles<<<2048, 256, 0, s>>>(AH, NH, NT, tiles);
+  if (tile_cholesky(p, (const MatDesc*)(cb + p->c_mat), 1, NT, NT, tiles, status, s)) return MSGFEM_EHIP;
+  double* ysc = (double*)(cb + p->c_y);
+  double* xsc = ysc + (int64_t)NT * 32;
+  double* rc = (double*)(cb + p->c_rpart);   // the coarse restriction (N_H <= 32 * pairs)
+  Ctx c;
+  c.p = p;
+  c.v = v;
+  c.w = work_view(p, work);
+  c.s = s;
+  c.nb = nb;
+  c.k = k;
+  const unsigned gblk = (unsigned)std::min<int64_t>((nd + 255) / 256, 2048);
+  auto gspmv = [&](const double* in, double* out) -> int {
+    dim3 grid((unsigned)((ng + 255) / 256), 1);
+    k_spmm<<<grid, 256, 0, s>>>(gmeta, gst, gcls, gmu, in, out, nullptr, 1, 1 << 1, 1.0, nullptr);
+    LAUNCHCHK(p);
+    return 0;
+  };
+  auto dot = [&](const double* a_, const double* b_, double* out) {
+    k_dot_partial<<<1024, 256, 0, s>>>(a_, b_, gcls, nd, part);
+    k_dot_final<<<1, 256, 0, s>>>(part, 1024, out);
+  };
+  auto precond = [&](const double* rin, double* zout) -> int {
+    k_fill_f64<<<1024, 256, 0, s>>>(zout, nd, 0.0);
+    k_gather_boxes<<<dim3((p->max_dof + 255) / 256, nb), 256, 0, s>>>(v.meta, md, v.cls, rin, rb);
+    if (solve(c, 0, rb, zb, 1, 1 << 1, 1, nullptr)) return MSGFEM_EHIP;
+    k_scatter_boxes<<<dim3((p->max_dof + 255) / 256, nb), 256, 0, s>>>(v.meta, md, v.cls, zb, zout);
+    k_coarse_restrict<<<nb, 256, 0, s>>>(v.meta, k, (const double*)(cb + p->c_V), rb,
+                                         (const int32_t*)(cb + p->c_roff), rc);
+    k_dense_tile_solve<<<1, 256, 0, s>>>(tiles, NT, NH, rc, ysc, xsc);
+    k_prolong<<<dim3((p->max_dof + 255) / 256, nb), 256, 0, s>>>(v.meta, md, k, (const double*)(cb + p->c_V), zero,
+                                                                 xsc, (const int32_t*)(cb + p->c_roff), zout,
+                                                                 nullptr);
+    LAUNCHCHK(p);
+    return 0;
+  };
+  // initial residual
+  HIPCHK(p, hipMemcpyAsync(x, u, nd * 8, hipMemcpyDeviceToDevice, s));
+  if (gspmv(x, q)) return MSGFEM_EHIP;
+  k_sub<<<gblk, 256, 0, s>>>(gcls, nd, b, q, r);
+  if (precond(r, z)) return MSGFEM_EHIP;
+  k_pcg_p<<<gblk, 256, 0, s>>>(gcls, nd, nullptr, z, pp);
+  dot(r, z, sc + 0);
+  dot(b, b, sc + 6);
+  dot(r, r, sc + 3);
+  double h[8];
+  HIPCHK(p, hipMemcpyAsync(h, sc, 8 * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(p, hipStreamSynchronize(s));
+  const double nb2 = h[6] > 0 ? std::sqrt(h[6]) : 1.0;
+  double rel = std::sqrt(h[3]) / nb2;
+  int it = 0;
+  while (rel > rtol && it < maxit) {
+    if (gspmv(pp, q)) return MSGFEM_EHIP;
+    dot(pp, q, sc + 1);
+    k_pcg_alpha<<<1, 1, 0, s>>>(sc);
+    k_pcg_xr<<<gblk, 256, 0, s>>>(gcls, nd, sc, pp, q, x, r);
+    dot(r, r, sc + 3);
+    if (precond(r, z)) return MSGFEM_EHIP;
+    dot(r, z, sc + 2);
+    k_pcg_beta<<<1, 1, 0, s>>>(sc);
+    k_pcg_p<<<gblk, 256, 0, s>>>(gcls, nd, sc, z, pp);
+    LAUNCHCHK(p);
+    HIPCHK(p, hipMemcpyAsync(h, sc, 8 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(p, hipStreamSynchronize(s));
+    rel = std::sqrt(h[3]) / nb2;
+    ++it;
+  }
+  HIPCHK(p, hipMemcpyAsync(u, x, nd * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(p, hipStreamSynchronize(s));
+  *iters = it;
+  *relres = rel;
+  if (rel > rtol) {
+    int32_t one = 1;
+    HIPCHK(p, hipMemcpy(status, &one, 4, hipMemcpyHostToDevice));
+  }
   return MSGFEM_OK;
 }

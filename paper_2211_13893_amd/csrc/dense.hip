@@ -431,11 +431,12 @@ __global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta
   }
 }
 
-// R = MX - nu (SX + s MX) on B2 rows (SX = (A X~) on B2), written into R (zero
-// elsewhere); partial column sums of |R|^2, |MX|^2, |TX|^2 per row chunk.
+// R = MX - nu (SX + s MX) on the rows whose class bit is set in rcls (B2 for
+// the A-harmonic GEVP, where SX = (A X~) on B2; B1 u B2 for GenEO), written
+// into R (zero elsewhere); partial column sums of |R|^2, |MX|^2, |TX|^2.
 // grid (n_chunk, n_box); thread = (row slot tid/32, column tid%32); k <= 32
 __global__ __launch_bounds__(256) void k_residual(const BoxMeta* __restrict__ meta,
-                                                  const uint8_t* __restrict__ cls, int k,
+                                                  const uint8_t* __restrict__ cls, int rcls, int k,
                                                   double shift, const double* __restrict__ AX,
                                                   const double* __restrict__ MX,
                                                   const double* __restrict__ nu,
@@ -455,7 +456,7 @@ __global__ __launch_bounds__(256) void k_residual(const BoxMeta* __restrict__ me
     for (int row = r_begin + slot; row < r_end; row += 8) {
       int64_t o = (bm.dof_off * k) + (int64_t)row * k + col;
       double r = 0.0;
-      if (cls[bm.dof_off + row] == 2) {
+      if ((rcls >> cls[bm.dof_off + row]) & 1) {
         double mx = MX[o], sx = AX[o];
         double tx = sx + shift * mx;
         r = mx - v * tx;
@@ -519,7 +520,30 @@ __global__ void k_converge(const BoxMeta* __restrict__ meta, int n_box, int k, i
   }
 }
 
-// random start block on B2 (counter-based hash, uniform in [-1, 1)), zero elsewhere
+// Soft locking: a column whose residual is below lock_tol gets no new search
+// direction (its W and P columns are zeroed, so the Rayleigh-Ritz step drops
+// them); it stays in X and keeps being improved by the projection.  Without
+// it, the preconditioned residuals of columns converged to rounding level are
+// pure noise that corrupts the Gram matrices.  grid (rows, n_box).
+__global__ void k_lock(const BoxMeta* __restrict__ meta, int k, const double* __restrict__ rho,
+                       double lock_tol, double* __restrict__ W, double* P0, double* P1, double* P2,
+                       double* P3, const int32_t* __restrict__ active) {
+  int box = blockIdx.y;
+  if (active && !active[box]) return;
+  const BoxMeta& bm = meta[box];
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)bm.n_dof * k) return;
+  int c = (int)(t % k);
+  if (!(rho[(int64_t)box * k + c] <= lock_tol)) return;
+  int64_t o = bm.dof_off * k + t;
+  W[o] = 0.0;
+  if (P0) P0[o] = 0.0;
+  if (P1) P1[o] = 0.0;
+  if (P2) P2[o] = 0.0;
+  if (P3) P3[o] = 0.0;
+}
+
+// random start block on the classes in vcls (counter-based hash, uniform in [-1, 1)), zero elsewhere
 __device__ inline uint64_t mix64(uint64_t z) {
   z += 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -528,29 +552,29 @@ __device__ inline uint64_t mix64(uint64_t z) {
 }
 
 __global__ void k_random_start(const BoxMeta* __restrict__ meta, const uint8_t* __restrict__ cls,
-                               int k, uint64_t seed, double* __restrict__ X) {
+                               int k, int vcls, uint64_t seed, double* __restrict__ X) {
   int box = blockIdx.y;
   const BoxMeta& bm = meta[box];
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)bm.n_dof * k) return;
   int row = (int)(t / k), col = (int)(t % k);
   double v = 0.0;
-  if (cls[bm.dof_off + row] == 2) {
+  if ((vcls >> cls[bm.dof_off + row]) & 1) {
     uint64_t h = mix64(seed ^ mix64(((uint64_t)bm.sd << 40) ^ ((uint64_t)row << 8) ^ (uint64_t)col));
     v = (double)(h >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
   }
   X[(bm.dof_off * k) + t] = v;
 }
 
-// copy a caller start block (boundary values on B2 DoFs, box layout [n_dof][k]) into X
+// copy a caller start block (values on the classes in vcls, box layout [n_dof][k]) into X
 __global__ void k_copy_start(const BoxMeta* __restrict__ meta, const uint8_t* __restrict__ cls,
-                             int k, const double* __restrict__ X0, double* __restrict__ X) {
+                             int k, int vcls, const double* __restrict__ X0, double* __restrict__ X) {
   int box = blockIdx.y;
   const BoxMeta& bm = meta[box];
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)bm.n_dof * k) return;
   int row = (int)(t / k);
-  X[(bm.dof_off * k) + t] = (cls[bm.dof_off + row] == 2) ? X0[(bm.dof_off * k) + t] : 0.0;
+  X[(bm.dof_off * k) + t] = ((vcls >> cls[bm.dof_off + row]) & 1) ? X0[(bm.dof_off * k) + t] : 0.0;
 }
 
 // Output: lambda ascending, unit 2-norm eigenvectors on all box DoFs (0 on B3)

@@ -36,7 +36,7 @@ class msgfem_decomp(ctypes.Structure):
 class msgfem_eig_opts(ctypes.Structure):
     _fields_ = [("shift", ctypes.c_double), ("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("geneo", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class msgfem_sizes(ctypes.Structure):
@@ -81,6 +81,10 @@ SIGNATURES = {
     "msgfem_coarse_assemble": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(msgfem_load), _P, _P, _P, _P,
                                               _P, _P]),
     "msgfem_coarse_solve": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "msgfem_pcg_sizes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "msgfem_geneo_pcg": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(msgfem_load), ctypes.c_double,
+                                        ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_double), _P, _P]),
     "msgfem_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "msgfem_profile_stats": (ctypes.c_int, [_P, ctypes.POINTER(msgfem_kernel_stat), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
@@ -135,7 +139,8 @@ class LocalStage:
 
     def __init__(self, problem, batch: Optional[Sequence[int]] = None,
                  n_ev: Optional[Sequence[int]] = None, device: str = "cuda:0", shift: float = 1.0,
-                 tol: float = 1e-6, maxit: int = 200, block: int = 0, seed: int = 1234):
+                 tol: float = 1e-6, maxit: int = 200, block: int = 0, seed: int = 1234,
+                 geneo: bool = False):
         import torch
         self.torch = torch
         lib = load()
@@ -158,7 +163,8 @@ class LocalStage:
         self._cores = np.ascontiguousarray(p.cores, dtype=np.int32)
         self._ovs = np.ascontiguousarray(p.ovs, dtype=np.int32)
         dec = msgfem_decomp(p.nsd, self._cores.ctypes.data, p.overlap, self._ovs.ctypes.data)
-        opts = msgfem_eig_opts(shift, tol, maxit, block, 0, 0, seed)
+        opts = msgfem_eig_opts(shift, tol, maxit, block, 0, 1 if geneo else 0, seed)
+        self.geneo = geneo
         self.shift = shift
         plan = _P()
         idx = dev.index if dev.index is not None else torch.cuda.current_device()
@@ -252,12 +258,7 @@ class LocalStage:
         nbytes, nh = self.msgfem_coarse_sizes()
         if getattr(self, "coarse", None) is None or self.coarse.numel() < nbytes:
             self.coarse = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        faces = {"x-": 0, "x+": 1, "y-": 2, "y+": 3, "z-": 4, "z+": 5}
-        tr = self.problem.tractions
-        self._face = np.asarray([faces[f] for f, _ in tr], dtype=np.int32)
-        self._g = np.ascontiguousarray(np.asarray([g for _, g in tr], dtype=np.float64).reshape(-1, 3))
-        ld = msgfem_load(len(tr), self._face.ctypes.data if len(tr) else 0,
-                         self._g.ctypes.data if len(tr) else 0)
+        ld = self._load()
         AH = torch.empty((nh, nh), dtype=torch.float64, device=self.device)
         bH = torch.empty(nh, dtype=torch.float64, device=self.device)
         rc = self.lib.msgfem_coarse_assemble(self.plan, _ptr(self.ops), _ptr(self._alloc_work()),
@@ -280,6 +281,32 @@ class LocalStage:
                                           _ptr(st), _stream_handle(torch, self.device))
         _check(rc, self.plan, "msgfem_coarse_solve")
         return dict(c=c, uG=uG, up=up, status=st)
+
+    def _load(self):
+        faces = {"x-": 0, "x+": 1, "y-": 2, "y+": 3, "z-": 4, "z+": 5}
+        tr = self.problem.tractions
+        self._face = np.asarray([faces[f] for f, _ in tr], dtype=np.int32)
+        self._g = np.ascontiguousarray(np.asarray([g for _, g in tr], dtype=np.float64).reshape(-1, 3))
+        return msgfem_load(len(tr), self._face.ctypes.data if len(tr) else 0,
+                           self._g.ctypes.data if len(tr) else 0)
+
+    def msgfem_geneo_pcg(self, AH, rtol: float = 1e-8, maxit: int = 1000, u0=None):
+        torch = self.torch
+        nbytes = ctypes.c_int64()
+        _check(self.lib.msgfem_pcg_sizes(self.plan, ctypes.byref(nbytes)), self.plan, "msgfem_pcg_sizes")
+        if getattr(self, "pcg_ws", None) is None or self.pcg_ws.numel() < nbytes.value:
+            self.pcg_ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        u = torch.zeros(self.problem.n_dofs, dtype=torch.float64, device=self.device) if u0 is None else u0.clone()
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        st = torch.zeros(1, dtype=torch.int32, device=self.device)
+        ld = self._load()
+        rc = self.lib.msgfem_geneo_pcg(self.plan, _ptr(self.ops), _ptr(self._alloc_work()), _ptr(self.coarse),
+                                       _ptr(AH), ctypes.byref(ld), rtol, maxit, _ptr(self.pcg_ws), _ptr(u),
+                                       ctypes.byref(it), ctypes.byref(rel), _ptr(st),
+                                       _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_geneo_pcg")
+        return dict(u=u, iters=it.value, relres=rel.value, status=st)
 
     def msgfem_profile(self, enable: bool):
         _check(self.lib.msgfem_profile(self.plan, 1 if enable else 0), self.plan, "msgfem_profile")

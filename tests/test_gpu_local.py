@@ -5,7 +5,7 @@ stencil entries relative 1e-12 of the largest entry (FP64 element integration
 in a different summation order), classes exact, partition of unity 1e-15,
 eigenvalues nu = 1/(lambda + s) relative 1e-8 (FP64 path), residual
 rho <= 1e-6, A-harmonic residual <= 1e-10, eigenvector subspaces within
-1e-6 radians outside clusters cut by the n_ev boundary.
+10 rho / (relative spectral gap) radians at cuts with a relative gap > 1e-3.
 """
 import sys
 
@@ -156,14 +156,16 @@ def _check_eigs(torch, prob, batch, n_ev, tol_nu=1e-8):
         for c in range(n_ev):
             assert gevp.harmonic_residual(ops, phi[:, c]) <= 1e-10
         assert np.all(phi[ops.cls == 3] == 0.0)
-        # subspace of well-separated leading groups
-        gaps = ref.nu[:n_ev] - ref.nu[1:n_ev + 1]
-        cut = [c + 1 for c in range(n_ev) if gaps[c] > 1e-3 * ref.nu[c]]
+        # subspace of well-separated leading groups: with residuals rho the
+        # angle is bounded by ~rho / (relative gap at the cut)
+        gaps = (ref.nu[:n_ev] - ref.nu[1:n_ev + 1]) / ref.nu[:n_ev]
+        cut = [c + 1 for c in range(n_ev) if gaps[c] > 1e-3]
         if cut:
             q = max(cut)
             ang = gevp.subspace_angle(phi[:, :q], ref.phi[:, :q])
-            say(f"    subspace angle of the first {q}: {ang:.2e}")
-            assert ang <= 1e-6
+            bound = 10 * max(rho.max(), 1e-12) / gaps[q - 1]
+            say(f"    subspace angle of the first {q}: {ang:.2e} (bound {bound:.1e})")
+            assert ang <= bound
 
 
 def test_eigs_parity_beam(torch):
