@@ -24,6 +24,7 @@ __global__ void k_band_build(const BoxMeta*, int, const double*, const uint8_t*,
 __global__ void k_chol_update(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_panel(const MatDesc*, int, double*);
 __global__ void k_chol_unit(const MatDesc*, double*);
+__global__ void k_band_relayout(const BoxMeta*, int, double*);
 template <int KC>
 __global__ void k_band_solve(const BoxMeta*, int, int, int, const double*, const uint8_t*, const double*,
                              double*, int, int, int, double*, int64_t, const int32_t*);
@@ -318,6 +319,14 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     fac_off += (int64_t)m.nth * m.bth * 1024;
     m.fhi_off = fac_off;
     fac_off += (int64_t)m.nth * 1024;
+    m.f11_fw = fac_off;
+    fac_off += (int64_t)m.nt11 * 64 * solve_nthr(m.bt11);
+    m.f11_bw = fac_off;
+    fac_off += (int64_t)m.nt11 * 64 * solve_nthr(m.bt11);
+    m.fh_fw = fac_off;
+    fac_off += (int64_t)m.nth * 64 * solve_nthr(m.bth);
+    m.fh_bw = fac_off;
+    fac_off += (int64_t)m.nth * 64 * solve_nthr(m.bth);
     m.evec_off = evec_off;
     m.eval_off = eval_off;
     node_off += m.n_nodes;
@@ -332,8 +341,9 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     p->max_fac_tiles = std::max(p->max_fac_tiles, (int64_t)std::max(m.nt11 * m.bt11, m.nth * m.bth));
     p->meta[b] = m;
   }
-  if ((int64_t)p->max_bt * 32 * KC * 8 > 108 * 1024)
-    return fail(p, MSGFEM_ESIZE, "band too wide for the LDS ring (BT=%d)", p->max_bt);
+  // LDS of the block solve: partial sums, the D^{-1} tile and a ring of BT solution tiles
+  if ((int64_t)(SOLVE_TILES * 32 * (KC + 1) + 32 * 33 + p->max_bt * 32 * KC) * 8 > 160 * 1024)
+    return fail(p, MSGFEM_ESIZE, "band of %d tiles too wide for the block solve", p->max_bt);
   for (int b = 0; b < nb; ++b) {
     const BoxMeta& m = p->meta[b];
     MatDesc a11{m.nt11, m.bt11, b, 0, m.f11_off, m.f11i_off};
@@ -585,6 +595,20 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
     ProfScope ps(p, PK_POTRF, s, by, fl);
     if (tile_cholesky(p, v.mats, (int)p->mats.size(), max_nt, max_bt, v.fac, status, s)) return MSGFEM_EHIP;
   }
+  for (int kind = 0; kind < 2; ++kind) {
+    int64_t tot = 0;
+    double by = 0;
+    for (auto& m : p->meta) {
+      int nt = kind == 0 ? m.nt11 : m.nth, bt = kind == 0 ? m.bt11 : m.bth;
+      int64_t e = (int64_t)nt * 32 * solve_nthr(bt);
+      tot = std::max(tot, e);
+      by += 3 * 16.0 * e;
+    }
+    int64_t blocks = std::min<int64_t>((tot + 255) / 256, 65535);
+    ProfScope ps(p, PK_BUILD, s, by, 0.0);
+    k_band_relayout<<<dim3((unsigned)std::max<int64_t>(blocks, 1), nb), 256, 0, s>>>(v.meta, kind, v.fac);
+    LAUNCHCHK(p);
+  }
   return MSGFEM_OK;
 }
 
@@ -719,7 +743,7 @@ static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double*
     B.p[i] = i < nblk ? BZb[i] : nullptr;
   }
   dim3 grid(c.p->n_gchunk, c.nb, 2);
-  size_t lds = 0;
+  size_t lds = (size_t)m * m * 8;
   double by = 0, fl = 0;
   for (int b = 0; b < c.nb; ++b) {
     if (!c.counts(b, act)) continue;
@@ -727,16 +751,18 @@ static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double*
     by += 3 * 8.0 * mt.n_dof * m;
     fl += 2 * 2.0 * mt.n_dof * m * m;
   }
-  ProfScope ps(c.p, PK_GRAM, c.s, by, fl);
-  k_gram_partial<<<grid, 256, lds, c.s>>>(c.v.meta, nblk, Z, A, B, k, GRAM_ROWS, c.p->n_gchunk, c.w.part,
-                                          act);
-  LAUNCHCHK(c.p);
-  dim3 g2((2 * m * m + 255) / 256, c.nb);
-  k_gram_reduce<<<g2, 256, 0, c.s>>>(m, c.p->n_gchunk, c.w.part, c.w.G, act);
-  LAUNCHCHK(c.p);
+  {
+    ProfScope ps(c.p, PK_GRAM, c.s, by, fl);
+    k_gram_partial<<<grid, 256, lds, c.s>>>(c.v.meta, nblk, Z, A, B, k, GRAM_ROWS, c.p->n_gchunk, c.w.part,
+                                            act);
+    LAUNCHCHK(c.p);
+    dim3 g2((2 * m * m + 255) / 256, c.nb);
+    k_gram_reduce<<<g2, 256, 0, c.s>>>(m, c.p->n_gchunk, c.w.part, c.w.G, act);
+    LAUNCHCHK(c.p);
+  }
   size_t lds_rr = ((size_t)2 * m * (m + 1) + 3 * m + 256 + m) * 8;
   ProfScope ps2(c.p, PK_RR, c.s, 0.0, 0.0);
-  k_rayleigh_ritz<<<c.nb, 256, lds_rr, c.s>>>(m, k, 1, c.p->opts.shift, c.w.G, c.w.L, c.w.Y, c.w.Yp,
+  k_rayleigh_ritz<<<c.nb, 1024, lds_rr, c.s>>>(m, k, 1, c.p->opts.shift, c.w.G, c.w.L, c.w.Y, c.w.Yp,
                                                c.w.nu, act);
   LAUNCHCHK(c.p);
   return 0;
@@ -1103,7 +1129,8 @@ extern "C" int msgfem_coarse_assemble(msgfem_plan* p, const void* ops, void* wor
     Z.p[0] = A.p[0] = B.p[0] = V;
     Z.p[1] = Z.p[2] = A.p[1] = A.p[2] = B.p[1] = B.p[2] = nullptr;
     (void)Zb;
-    k_gram_partial<<<dim3(p->n_gchunk, nb, 2), 256, 0, s>>>(v.meta, 1, Z, A, B, k, GRAM_ROWS, p->n_gchunk,
+    k_gram_partial<<<dim3(p->n_gchunk, nb, 2), 256, (size_t)k * k * 8, s>>>(v.meta, 1, Z, A, B, k, GRAM_ROWS,
+                                                                            p->n_gchunk,
                                                             c.w.part, nullptr);
     k_gram_reduce<<<dim3((2 * k * k + 255) / 256, nb), 256, 0, s>>>(k, p->n_gchunk, c.w.part, c.w.G, nullptr);
     k_cholqr_coef<<<nb, 256, (size_t)(k * (k + 1) + k) * 8, s>>>(k, c.w.G, c.w.Y);

@@ -18,6 +18,7 @@ namespace msg {
 struct BandView {
   int NT, BT, n;
   int64_t off, ioff;
+  int64_t fw, bw;   // solve-ordered band copies (forward / backward sweep)
   int sx, sy, sz;   // (sub-)box node dims of the ordering
   int ox, oy, oz;   // offset of the ordering's node (0,0,0) inside the box
 };
@@ -26,12 +27,14 @@ __device__ inline BandView band_view(const BoxMeta& bm, int kind) {
   BandView v;
   if (kind == 0) {
     v.NT = bm.nt11; v.BT = bm.bt11; v.n = bm.n11; v.off = bm.f11_off; v.ioff = bm.f11i_off;
+    v.fw = bm.f11_fw; v.bw = bm.f11_bw;
     v.sx = bm.sub_hi[0] - bm.sub_lo[0] + 1;
     v.sy = bm.sub_hi[1] - bm.sub_lo[1] + 1;
     v.sz = bm.sub_hi[2] - bm.sub_lo[2] + 1;
     v.ox = bm.sub_lo[0]; v.oy = bm.sub_lo[1]; v.oz = bm.sub_lo[2];
   } else {
     v.NT = bm.nth; v.BT = bm.bth; v.n = bm.nh; v.off = bm.fh_off; v.ioff = bm.fhi_off;
+    v.fw = bm.fh_fw; v.bw = bm.fh_bw;
     v.sx = bm.mx; v.sy = bm.my; v.sz = bm.mz;
     v.ox = v.oy = v.oz = 0;
   }
@@ -170,46 +173,55 @@ __device__ inline void tile_store_acc(double* __restrict__ C, const dbl4 acc[2][
       for (int v = 0; v < 4; ++v) C[(16 * bi + r + 4 * v) * 32 + 16 * bj + j] = acc[bi][bj][v];
 }
 
+// Value of v in lane j of the wavefront (j uniform).
+__device__ inline double lane_value(double v, int j) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), j);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Cholesky of the diagonal tile T (in place, lower) and the inverse of its
-// factor into Ti, by one whole workgroup through LDS.
-__device__ void diag_tile_factor(double* __restrict__ T, double* __restrict__ Ti, double (*D)[33],
-                                 double (*Di)[33], int* bad) {
-  const int tid = threadIdx.x;
-  for (int t = tid; t < 1024; t += 256) D[t >> 5][t & 31] = T[t];
-  __syncthreads();
+// factor into Ti, by one wavefront without barriers: lane i (mod 32) keeps row
+// i of the tile in registers and takes the entries of other rows from their
+// lanes (readlane with a compile-time lane index).  Left-looking:
+//   L[i][j] = (A[i][j] - sum_{q<j} L[i][q] L[j][q]) / L[j][j];
+// then lane c forms column c of L^{-1} by forward substitution.  Returns 1
+// if a pivot was not positive (it is replaced by 1).
+__device__ int diag_tile_factor(double* __restrict__ T, double* __restrict__ Ti) {
+  const int lane = threadIdx.x & 63, i = lane & 31;
+  double r[32];
+#pragma unroll
+  for (int q = 0; q < 32; ++q) r[q] = T[i * 32 + q];
+  int bad = 0;
+#pragma unroll
   for (int j = 0; j < 32; ++j) {
-    if (tid >= j && tid < 32) {
-      double d = D[j][j];
-      if (!(d > 0.0)) {
-        d = 1.0;
-        *bad = 1;
-      }
-      double sd = sqrt(d);
-      if (tid == j) D[j][j] = sd;
-      else D[tid][j] = D[tid][j] / sd;
+    double s = r[j];
+#pragma unroll
+    for (int q = 0; q < j; ++q) s -= r[q] * lane_value(r[q], j);
+    double d = lane_value(s, j);
+    if (!(d > 0.0)) {
+      d = 1.0;
+      bad = 1;
     }
-    __syncthreads();
-    for (int t = tid; t < 1024; t += 256) {
-      int i = t >> 5, c = t & 31;
-      if (i > j && c > j && c <= i) D[i][c] -= D[i][j] * D[c][j];
-    }
-    __syncthreads();
+    const double sd = sqrt(d);
+    r[j] = (i == j) ? sd : (i > j ? s / sd : 0.0);
   }
-  if (tid < 32) {
-    int c = tid;
-    for (int i = 0; i < 32; ++i) {
-      if (i < c) { Di[i][c] = 0.0; continue; }
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int q = c; q < i; ++q) s -= D[i][q] * Di[q][c];
-      Di[i][c] = s / D[i][i];
-    }
+  double x[32];
+#pragma unroll
+  for (int ii = 0; ii < 32; ++ii) {
+    double s = (ii == i) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < ii; ++q) s -= lane_value(r[q], ii) * x[q];
+    x[ii] = s / lane_value(r[ii], ii);
   }
-  __syncthreads();
-  for (int t = tid; t < 1024; t += 256) {
-    int i = t >> 5, c = t & 31;
-    T[t] = (c <= i) ? D[i][c] : 0.0;
-    Ti[t] = Di[i][c];
+  if (lane < 32) {
+#pragma unroll
+    for (int q = 0; q < 32; ++q) T[i * 32 + q] = r[q];
+#pragma unroll
+    for (int ii = 0; ii < 32; ++ii) Ti[ii * 32 + i] = x[ii];
   }
+  return bad;
 }
 
 // Right-looking tile Cholesky, one launch per tile column K (K = -1 first):
@@ -221,9 +233,6 @@ __device__ void diag_tile_factor(double* __restrict__ T, double* __restrict__ Ti
 __global__ __launch_bounds__(256) void k_chol_update(const MatDesc* __restrict__ mats, int K,
                                                      double* __restrict__ fac,
                                                      int32_t* __restrict__ status) {
-  __shared__ double D[32][33];
-  __shared__ double Di[32][33];
-  __shared__ int bad;
   const MatDesc v = mats[blockIdx.y];
   if (K >= v.NT - 1) return;
   const int m = (K < 0) ? 0 : min(v.BT - 1, v.NT - 1 - K);
@@ -246,12 +255,14 @@ __global__ __launch_bounds__(256) void k_chol_update(const MatDesc* __restrict__
     tile_store_acc(Tc, acc, lane);
   }
   if (owner) {
-    if (tid == 0) bad = 0;
-    __syncthreads();
-    double* T = L + (int64_t)(K + 1) * v.BT * MSG_TILE2;
-    diag_tile_factor(T, fac + v.ioff + (int64_t)(K + 1) * MSG_TILE2, D, Di, &bad);
-    __syncthreads();
-    if (tid == 0 && bad) atomicOr(&status[v.status_idx], 4);
+    // the next diagonal tile was updated above by wavefront 0 (pair 0); the
+    // same wavefront factors it
+    if (wave == 0) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's tile stores are complete
+      double* T = L + (int64_t)(K + 1) * v.BT * MSG_TILE2;
+      const int bad = diag_tile_factor(T, fac + v.ioff + (int64_t)(K + 1) * MSG_TILE2);
+      if (lane == 0 && bad) atomicOr(&status[v.status_idx], 4);
+    }
   }
 }
 
@@ -301,6 +312,43 @@ __global__ __launch_bounds__(256) void k_chol_unit(const MatDesc* __restrict__ m
   tile_store_acc(T, acc, lane);
 }
 
+// Copies of the unit-lower band in the order the block solve reads it.  Solve
+// thread t (tile s = 1 + t/16, row quad rq = (t/2)%8, half h = t%2) of tile
+// row I holds 64 factor values as 32 double2 j:
+//   forward  (tile (I, I-s)):     j = 8i + q2 -> Lu[4rq+i][16h+2q2 .. +1]
+//   backward (tile (I+s, I)^T):   j = 2q + e  -> Lu[16h+q][4rq+2e .. +1]
+// stored at ((I*32 + j) * nthr + t); tiles outside the matrix are zero.
+// grid.x strides over NT*32*nthr, grid.y = box.
+__global__ void k_band_relayout(const BoxMeta* __restrict__ meta, int kind, double* __restrict__ fac) {
+  const BoxMeta& bm = meta[blockIdx.y];
+  BandView v = band_view(bm, kind);
+  const int nthr = solve_nthr(v.BT);
+  const int64_t total = (int64_t)v.NT * 32 * nthr;
+  const double* L = fac + v.off;
+  double2* fw = (double2*)(fac + v.fw);
+  double2* bw = (double2*)(fac + v.bw);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e % nthr);
+    const int j = (int)((e / nthr) & 31);
+    const int I = (int)(e / ((int64_t)nthr * 32));
+    const int sidx = 1 + (t >> 4), rq = (t >> 1) & 7, h = t & 1;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (sidx <= I) {
+      const double* T = L + ((int64_t)I * v.BT + sidx) * MSG_TILE2;
+      const int i = j >> 3, q2 = j & 7;
+      a = *(const double2*)(T + (4 * rq + i) * 32 + 16 * h + 2 * q2);
+    }
+    if (I + sidx < v.NT) {
+      const double* T = L + ((int64_t)(I + sidx) * v.BT + sidx) * MSG_TILE2;
+      const int q = j >> 1, c = j & 1;
+      b = *(const double2*)(T + (16 * h + q) * 32 + 4 * rq + 2 * c);
+    }
+    fw[e] = a;
+    bw[e] = b;
+  }
+}
+
 // Block solve A x = f with A = Lu D Lu^T for KC columns [chunk*KC, +KC) of a
 // box block vector.  Reads `in` (box layout [n_dof][ldk]) on the matrix's
 // DoFs, writes `out` on the DoFs whose class bit is set in out_classes (bit c
@@ -322,30 +370,29 @@ __global__ __launch_bounds__(256) void k_chol_unit(const MatDesc* __restrict__ m
 // factor they stream is read from HBM once and then hit in that XCD's L2.
 // grid.x = 8 * n_chunk * ceil(n_box/8), 512 threads; dynamic LDS = BT*32*KC doubles.
 #define SOLVE_THREADS 512
-#define SOLVE_TILES 32      // band tiles covered by the thread layout (bands up to 33 tiles)
 
-// f[i][q]: forward  = T[4rq+i][16h+q] of tile (I, I-s);
-//          backward = T[16h+q][4rq+i] of tile (I+s, I)  (row i of its transpose)
-template <int KC>
-__device__ inline void frag_load(const double* __restrict__ L, int I, int BT, int smax, int dir,
-                                 int s, int rq, int h, double (&f)[4][16]) {
+// f[i][q]: forward  = Lu[4rq+i][16h+q] of tile (I, I-s);
+//          backward = Lu[16h+q][4rq+i] of tile (I+s, I)  (row i of its transpose)
+// read from the solve-ordered copy F (fw or bw) of the band: consecutive
+// threads read consecutive 16-byte pieces.
+__device__ inline void frag_load(const double2* __restrict__ F, int I, int nthr, int smax, int dir,
+                                 int s, int tid, double (&f)[4][16]) {
   if (s > smax) return;
+  const double2* p = F + (int64_t)I * 32 * nthr + tid;
   if (dir < 0) {
-    const double* p = L + ((int64_t)I * BT + s) * MSG_TILE2 + (4 * rq) * 32 + 16 * h;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        double2 a = ((const double2*)(p + i * 32))[q];
+        double2 a = p[(int64_t)(8 * i + q) * nthr];
         f[i][2 * q] = a.x;
         f[i][2 * q + 1] = a.y;
       }
   } else {
-    const double* p = L + ((int64_t)(I + s) * BT + s) * MSG_TILE2 + (16 * h) * 32 + 4 * rq;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      double2 a = ((const double2*)(p + q * 32))[0];
-      double2 b = ((const double2*)(p + q * 32))[1];
+      double2 a = p[(int64_t)(2 * q) * nthr];
+      double2 b = p[(int64_t)(2 * q + 1) * nthr];
       f[0][q] = a.x;
       f[1][q] = a.y;
       f[2][q] = b.x;
@@ -384,6 +431,9 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   double* vout = out + bm.dof_off * ldk;
   double* w = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
   const int BT = v.BT, NT = v.NT;
+  const int nthr = solve_nthr(BT);
+  const double2* Ffw = (const double2*)(fac + v.fw);
+  const double2* Fbw = (const double2*)(fac + v.bw);
   double f[4][16];
 
   // partial sums of this thread's item over its half of the inner index
@@ -420,7 +470,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   };
 
   // ---- forward: Lu y = f
-  frag_load<KC>(L, 0, BT, 0, -1, s, rq, h, f);
+  frag_load(Ffw, 0, nthr, 0, -1, s, tid, f);
   for (int I = 0; I < NT; ++I) {
     const int smax = min(BT - 1, I);
     double fv = 0.0;
@@ -444,7 +494,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     if (has) accumulate(ring + (int64_t)((I - s) % BT) * 32 * KC, acc);
     store_part(has, acc);
     // fragment of the next step, in flight during the reduction
-    if (I + 1 < NT) frag_load<KC>(L, I + 1, BT, min(BT - 1, I + 1), -1, s, rq, h, f);
+    if (I + 1 < NT) frag_load(Ffw, I + 1, nthr, min(BT - 1, I + 1), -1, s, tid, f);
     __syncthreads();
     if (red) {
       const int e = 4 * tid;
@@ -476,7 +526,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   __syncthreads();
 
   // ---- backward: Lu^T x = w
-  frag_load<KC>(L, NT - 1, BT, 0, +1, s, rq, h, f);
+  frag_load(Fbw, NT - 1, nthr, 0, +1, s, tid, f);
   for (int I = NT - 1; I >= 0; --I) {
     const int smax = min(BT - 1, NT - 1 - I);
     const int row = I * 32 + rr;
@@ -485,7 +535,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     const bool has = s <= smax;
     if (has) accumulate(ring + (int64_t)((I + s) % BT) * 32 * KC, acc);
     store_part(has, acc);
-    if (I - 1 >= 0) frag_load<KC>(L, I - 1, BT, min(BT - 1, NT - I), +1, s, rq, h, f);
+    if (I - 1 >= 0) frag_load(Fbw, I - 1, nthr, min(BT - 1, NT - I), +1, s, tid, f);
     __syncthreads();
     if (red) {
       double sum = 0.0;

@@ -29,90 +29,94 @@ struct Blk3 {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// Gram matrices on the FP64 matrix cores: G = Z^T W over a chunk of rows with
-// W = A Z~ (grid z = 0) or W = D A D Z~ (z = 1).  The m columns are padded to
-// 16-wide blocks; only blocks bi <= bj are formed (the matrices are
-// symmetric; k_gram_reduce mirrors them).  Wave w owns the output blocks
-// t = w, w+4, ... and walks all rows of the chunk four at a time; the operands
-// are read straight from the row-major block vectors (A operand lane l:
-// Z[row l>>4][col l&15], B operand W[row l>>4][col l&15]).
-// grid (n_chunk, n_box, 2), 256 threads.
+// Partial Gram matrices of one row chunk of one box:
+//   part[box][chunk][0] = Z^T (A Z),  part[box][chunk][1] = Z^T (B Z)
+// (upper 16x16 blocks only; blockIdx.z selects the product), Z = [Z_0 .. Z_{nblk-1}]
+// of m = nblk*k columns.  Each wave takes every fourth group of 4 rows and
+// accumulates all upper blocks of the m x m result with the FP64 matrix cores
+// (16x16x4: one group of 4 rows is one inner step), two groups per iteration
+// so that the next rows are in flight during the products.  The four waves'
+// sums are added in a fixed order through LDS (dynamic LDS: m*m doubles).
 __global__ __launch_bounds__(256) void k_gram_partial(const BoxMeta* __restrict__ meta, int nblk,
                                                       Blk3 Z, Blk3 AZ, Blk3 BZ, int k,
                                                       int rows_per_chunk, int n_chunk,
                                                       double* __restrict__ part,
                                                       const int32_t* __restrict__ active) {
-  int box = blockIdx.y, chunk = blockIdx.x, which = blockIdx.z;
+  extern __shared__ double gsum[];   // [m][m]
+  const int box = blockIdx.y, chunk = blockIdx.x, which = blockIdx.z;
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
   const int m = nblk * k;
-  const int nb16 = (m + 15) >> 4;
-  const int ntile = nb16 * (nb16 + 1) / 2;
+  const int nb16 = (m + 15) >> 4;      // <= 6
   const Blk3& W = which ? BZ : AZ;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r_begin = chunk * rows_per_chunk;
   const int r_end = min(bm.n_dof, r_begin + rows_per_chunk);
-  // this wave's tiles (at most 6 of the <= 21 upper blocks of m <= 96)
-  int tbi[6], tbj[6];
-  int nt = 0;
-  {
-    int t = 0;
-    for (int bi = 0; bi < nb16; ++bi)
-      for (int bj = bi; bj < nb16; ++bj, ++t)
-        if ((t & 3) == wave && nt < 6) { tbi[nt] = bi; tbj[nt] = bj; ++nt; }
-  }
-  dbl4 acc[6];
-#pragma unroll
-  for (int u = 0; u < 6; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
-  // column of this lane in every 16-block: (block of the basis, column inside it)
   const int lc = lane & 15, lr = lane >> 4;
+  // the column of this lane in every 16-block: block of the basis and column in it
   int cblk[6], ccol[6];
 #pragma unroll
   for (int b = 0; b < 6; ++b) {
-    int c = 16 * b + lc;
+    const int c = 16 * b + lc;
     cblk[b] = (c < m) ? c / k : -1;
     ccol[b] = (c < m) ? c % k : 0;
   }
-  for (int r0 = r_begin; r0 < r_end; r0 += 4) {
-    const int row = r0 + lr;
+  dbl4 acc[6][6];
+#pragma unroll
+  for (int bi = 0; bi < 6; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 6; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int64_t base = bm.dof_off * k;
+  auto load = [&](int row, double (&zf)[6], double (&wf)[6]) {
     const bool rok = row < r_end;
-    double zf[6], wf[6];
 #pragma unroll
     for (int b = 0; b < 6; ++b) {
-      zf[b] = 0.0;
-      wf[b] = 0.0;
-      if (b < nb16 && rok && cblk[b] >= 0) {
-        int64_t o = (bm.dof_off * k) + (int64_t)row * k + ccol[b];
-        zf[b] = Z.p[cblk[b]][o];
-        wf[b] = W.p[cblk[b]][o];
-      }
+      const bool ok = b < nb16 && rok && cblk[b] >= 0;
+      const int64_t o = base + (int64_t)(rok ? row : r_begin) * k + ccol[b];
+      const int cb = cblk[b] >= 0 ? cblk[b] : 0;
+      zf[b] = ok ? Z.p[cb][o] : 0.0;
+      wf[b] = ok ? W.p[cb][o] : 0.0;
     }
+  };
+  auto mma = [&](const double (&zf)[6], const double (&wf)[6]) {
 #pragma unroll
-    for (int u = 0; u < 6; ++u) {
-      if (u < nt) {
-        double a = 0.0, bb = 0.0;
+    for (int bi = 0; bi < 6; ++bi)
 #pragma unroll
-        for (int b = 0; b < 6; ++b) {
-          if (b == tbi[u]) a = zf[b];
-          if (b == tbj[u]) bb = wf[b];
+      for (int bj = bi; bj < 6; ++bj)
+        if (bj < nb16) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(zf[bi], wf[bj], acc[bi][bj], 0, 0, 0);
+  };
+  // row groups g = wave, wave + 4, ... (4 rows each), two per iteration
+  const int n_groups = (r_end - r_begin + 3) >> 2;
+  for (int g0 = wave; g0 < n_groups; g0 += 8) {
+    double z0[6], w0[6], z1[6], w1[6];
+    load(r_begin + 4 * g0 + lr, z0, w0);
+    load(r_begin + 4 * (g0 + 4) + lr, z1, w1);   // beyond r_end: zeros
+    mma(z0, w0);
+    mma(z1, w1);
+  }
+  // fixed-order sum of the four waves' blocks
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int bi = 0; bi < 6; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < 6; ++bj) {
+          if (bj >= nb16) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * bi + lr + 4 * v, j = 16 * bj + lc;
+            if (i < m && j < m) gsum[i * m + j] = (w == 0 ? 0.0 : gsum[i * m + j]) + acc[bi][bj][v];
+          }
         }
-        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[u], 0, 0, 0);
-      }
     }
+    __syncthreads();
   }
   const int mm = m * m;
   double* out = part + ((int64_t)box * n_chunk + chunk) * 2 * mm + (int64_t)which * mm;
-#pragma unroll
-  for (int u = 0; u < 6; ++u) {
-    if (u < nt) {
-#pragma unroll
-      for (int vv = 0; vv < 4; ++vv) {
-        int i = 16 * tbi[u] + lr + 4 * vv, j = 16 * tbj[u] + lc;
-        if (i < m && j < m) out[i * m + j] = acc[u][vv];
-      }
-    }
+  for (int e = threadIdx.x; e < mm; e += 256) {
+    const int i = e / m, j = e % m;
+    if ((i >> 4) <= (j >> 4)) out[e] = gsum[e];
   }
-  (void)ntile;
 }
 
 // G[box][2][m][m] = sum over chunks (fixed order); lower 16-blocks mirrored.
@@ -133,7 +137,32 @@ __global__ void k_gram_reduce(int m, int n_chunk, const double* __restrict__ par
 
 // One workgroup per box.  dynamic LDS: C[m][m+1], V[m][m+1] + small arrays.
 // Lg: global scratch m*m per box for the Cholesky factor.
-__global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, int nblk_x, double shift,
+#define RR_THREADS 1024
+
+// In-place triangular solve with the lower-triangular Lm (LDS, leading
+// dimension ld) for one right-hand side x_i = X[base + i*stride] by a group of
+// 8 consecutive lanes (gl = lane in the group): forward L x = b, or backward
+// L^T x = b.  Each dot product is split over the 8 lanes and summed with lane
+// shuffles; the group's first lane writes x_i.
+__device__ inline void tri_solve_group(const double* Lm, int ld, int m, double* X, int base, int stride,
+                                       bool backward, int gl) {
+  for (int step = 0; step < m; ++step) {
+    const int i = backward ? m - 1 - step : step;
+    double s = 0.0;
+    if (!backward) {
+      for (int q = gl; q < i; q += 8) s += Lm[i * ld + q] * X[base + q * stride];
+    } else {
+      for (int q = i + 1 + gl; q < m; q += 8) s += Lm[q * ld + i] * X[base + q * stride];
+    }
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 4);
+    if (gl == 0) X[base + i * stride] = (X[base + i * stride] - s) / Lm[i * ld + i];
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x, double shift,
                                                        const double* __restrict__ G,
                                                        double* __restrict__ Lg,
                                                        double* __restrict__ Y,
@@ -158,46 +187,55 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, int nblk_x,
   const double* GB = GA + m * m;
   double* L = Lg + (int64_t)box * m * m;
   // 1. scaled T-Gram
-  for (int i = tid; i < m; i += 256) {
+  for (int i = tid; i < m; i += RR_THREADS) {
     double t = GA[i * m + i] + shift * GB[i * m + i];
     dsc[i] = (t > 0.0) ? 1.0 / sqrt(t) : 0.0;
     drop[i] = (t > 0.0) ? 0 : 1;
   }
   __syncthreads();
-  for (int t = tid; t < m * m; t += 256) {
+  for (int t = tid; t < m * m; t += RR_THREADS) {
     int i = t / m, j = t % m;
     double a = 0.5 * ((GA[i * m + j] + shift * GB[i * m + j]) + (GA[j * m + i] + shift * GB[j * m + i]));
     C[i * ld + j] = a * dsc[i] * dsc[j];
   }
   __syncthreads();
-  // 2. Cholesky with dropping of near-dependent columns
+  // 2. Cholesky with dropping of near-dependent columns (pivot <= tau: the
+  //    column becomes e_j and row j of L is cleared), left-looking on one
+  //    wavefront: L[i][j] = (C[i][j] - sum_{q<j} L[i][q] L[j][q]) / L[j][j]
   const double tau = 1e-12;
-  for (int j = 0; j < m; ++j) {
-    double piv = C[j * ld + j];
-    bool dj = drop[j] || !(piv > tau);
-    if (dj) {
-      for (int t = tid; t < m; t += 256) {
-        if (t > j) C[t * ld + j] = 0.0;
-        if (t < j) C[j * ld + t] = 0.0;
+  if (tid < 64) {
+    const int ln = tid;
+    for (int j = 0; j < m; ++j) {
+      double pp = 0.0;
+      for (int q = ln; q < j; q += 64) pp += C[j * ld + q] * C[j * ld + q];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) pp += __shfl_xor(pp, o);
+      const double piv = C[j * ld + j] - pp;
+      const bool dj = drop[j] || !(piv > tau);
+      if (dj) {
+        for (int t = ln; t < m; t += 64) {
+          if (t > j) C[t * ld + j] = 0.0;
+          if (t < j) C[j * ld + t] = 0.0;
+        }
+        if (ln == 0) {
+          C[j * ld + j] = 1.0;
+          drop[j] = 1;
+        }
+      } else {
+        const double sd = sqrt(piv);
+        for (int i = j + 1 + ln; i < m; i += 64) {
+          double t = C[i * ld + j];
+          for (int q = 0; q < j; ++q) t -= C[i * ld + q] * C[j * ld + q];
+          C[i * ld + j] = t / sd;
+        }
+        if (ln == 0) C[j * ld + j] = sd;
       }
-      if (tid == 0) { C[j * ld + j] = 1.0; drop[j] = 1; }
-      __syncthreads();
-      continue;
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     }
-    double sd = sqrt(piv);
-    for (int t = tid; t < m; t += 256) {
-      if (t > j) C[t * ld + j] /= sd;
-    }
-    __syncthreads();
-    if (tid == 0) C[j * ld + j] = sd;
-    for (int t = tid; t < m * m; t += 256) {
-      int i = t / m, c = t % m;
-      if (i > j && c > j && c <= i) C[i * ld + c] -= C[i * ld + j] * C[c * ld + j];
-    }
-    __syncthreads();
   }
+  __syncthreads();
   // keep L in LDS (V's space, free until the Jacobi sweeps) and in global
-  for (int t = tid; t < m * m; t += 256) {
+  for (int t = tid; t < m * m; t += RR_THREADS) {
     int i = t / m, c = t % m;
     double l = (c <= i) ? C[i * ld + c] : 0.0;
     L[t] = l;
@@ -205,30 +243,21 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, int nblk_x,
   }
   __syncthreads();
   // 3. scaled M-Gram, dropped rows/columns removed
-  for (int t = tid; t < m * m; t += 256) {
+  for (int t = tid; t < m * m; t += RR_THREADS) {
     int i = t / m, j = t % m;
     double b = 0.5 * (GB[i * m + j] + GB[j * m + i]) * dsc[i] * dsc[j];
     C[i * ld + j] = (drop[i] || drop[j]) ? 0.0 : b;
   }
   __syncthreads();
-  // 4. C <- L^{-1} C (column-wise forward substitution), then C <- C L^{-T} (row-wise)
-  for (int j = tid; j < m; j += 256) {
-    for (int i = 0; i < m; ++i) {
-      double s = C[i * ld + j];
-      for (int q = 0; q < i; ++q) s -= V[i * ld + q] * C[q * ld + j];
-      C[i * ld + j] = s / V[i * ld + i];
-    }
+  // 4. C <- L^{-1} C (columns as right-hand sides), then C <- C L^{-T} (rows)
+  {
+    const int grp = tid >> 3, gl = tid & 7;
+    if (grp < m) tri_solve_group(V, ld, m, C, grp, ld, false, gl);
+    __syncthreads();
+    if (grp < m) tri_solve_group(V, ld, m, C, grp * ld, 1, false, gl);
+    __syncthreads();
   }
-  __syncthreads();
-  for (int i = tid; i < m; i += 256) {
-    for (int j = 0; j < m; ++j) {
-      double s = C[i * ld + j];
-      for (int q = 0; q < j; ++q) s -= C[i * ld + q] * V[j * ld + q];
-      C[i * ld + j] = s / V[j * ld + j];
-    }
-  }
-  __syncthreads();
-  for (int t = tid; t < m * m; t += 256) {
+  for (int t = tid; t < m * m; t += RR_THREADS) {
     int i = t / m, j = t % m;
     if (i < j) {
       double a = 0.5 * (C[i * ld + j] + C[j * ld + i]);
@@ -238,93 +267,123 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, int nblk_x,
     V[i * ld + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // 5. cyclic parallel Jacobi (round-robin pairing, m even)
-  const int h = m / 2;
+  // 5. cyclic parallel Jacobi (round-robin pairing, m even).  Round r pairs
+  //    (0, 1 + r mod (m-1)) and (1 + (r+i) mod (m-1), 1 + (r-i) mod (m-1)),
+  //    i = 1..m/2-1; all m/2 rotations of a round commute.  A round computes
+  //    the rotations, then applies them to C from both sides in one pass over
+  //    the 2x2 blocks C[{p_a,q_a},{p_b,q_b}] <- R_a B R_b^T, R = [[c,-s],[s,c]],
+  //    and to the columns of V (V <- V R^T).
+  const int h = m / 2, m1 = m - 1;
+  auto pair_of = [&](int r, int i, int& p, int& q) {
+    if (i == 0) {
+      p = 0;
+      q = 1 + (r % m1);
+    } else {
+      int a1 = r + i;
+      if (a1 >= m1) a1 -= m1;
+      int a2 = r + m1 - i;
+      if (a2 >= m1) a2 -= m1;
+      if (a2 >= m1) a2 -= m1;
+      p = 1 + a1;
+      q = 1 + a2;
+    }
+  };
+  int* zero_pq = order;   // scratch flags per pair (reused: order is set in step 6)
   for (int sweep = 0; sweep < 30; ++sweep) {
-    // convergence test: off-diagonal mass vs. total
+    // convergence test: off-diagonal mass vs. total (one barrier)
     double off = 0.0, tot = 0.0;
-    for (int t = tid; t < m * m; t += 256) {
-      int i = t / m, j = t % m;
-      double a = C[i * ld + j];
+    for (int t = tid; t < m * m; t += RR_THREADS) {
+      const int i = t / m, j = t - (t / m) * m;
+      const double a = C[i * ld + j];
       tot += a * a;
       if (i != j) off += a * a;
     }
-    red[tid] = off;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      tot += __shfl_xor(tot, o);
     }
-    double offs = red[0];
-    __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
+    if ((tid & 63) == 0) {
+      red[tid >> 6] = off;
+      red[16 + (tid >> 6)] = tot;
     }
-    double tots = red[0];
+    __syncthreads();
+    double offs = 0.0, tots = 0.0;
+    for (int w = 0; w < RR_THREADS / 64; ++w) {
+      offs += red[w];
+      tots += red[16 + w];
+    }
     __syncthreads();
     // relative off-diagonal norm 1e-13: Ritz values then carry errors ~1e-26
     if (offs <= 1e-26 * tots || tots == 0.0) break;
-    for (int r = 0; r < m - 1; ++r) {
-      for (int i = tid; i < h; i += 256) {
+    for (int r = 0; r < m1; ++r) {
+      for (int i = tid; i < h; i += RR_THREADS) {
         int p, q;
-        if (i == 0) { p = 0; q = 1 + (r % (m - 1)); }
-        else { p = 1 + (r + i) % (m - 1); q = 1 + (r + m - 1 - i) % (m - 1); }
-        double apq = C[p * ld + q];
-        double app = C[p * ld + p], aqq = C[q * ld + q];
-        double c = 1.0, s = 0.0;
+        pair_of(r, i, p, q);
+        const double apq = C[p * ld + q];
+        const double app = C[p * ld + p], aqq = C[q * ld + q];
+        double c = 1.0, sn = 0.0;
+        int z = 0;
         if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
-          double th = (aqq - app) / (2.0 * apq);
-          double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+          const double th = (aqq - app) / (2.0 * apq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
           c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
+          sn = t * c;
+          z = 1;
         } else if (fabs(apq) > 0.0) {
-          C[p * ld + q] = 0.0;
-          C[q * ld + p] = 0.0;
+          z = 1;
         }
         rc[i] = c;
-        rs[i] = s;
+        rs[i] = sn;
+        zero_pq[i] = z;
       }
       __syncthreads();
-      // rows: C <- J^T C
-      for (int t = tid; t < h * m; t += 256) {
-        int i = t / m, col = t % m;
-        int p, q;
-        if (i == 0) { p = 0; q = 1 + (r % (m - 1)); }
-        else { p = 1 + (r + i) % (m - 1); q = 1 + (r + m - 1 - i) % (m - 1); }
-        double c = rc[i], s = rs[i];
-        double xp = C[p * ld + col], xq = C[q * ld + col];
-        C[p * ld + col] = c * xp - s * xq;
-        C[q * ld + col] = s * xp + c * xq;
-      }
-      __syncthreads();
-      // columns: C <- C J, V <- V J
-      for (int t = tid; t < h * m; t += 256) {
-        int i = t / m, row = t % m;
-        int p, q;
-        if (i == 0) { p = 0; q = 1 + (r % (m - 1)); }
-        else { p = 1 + (r + i) % (m - 1); q = 1 + (r + m - 1 - i) % (m - 1); }
-        double c = rc[i], s = rs[i];
-        double xp = C[row * ld + p], xq = C[row * ld + q];
-        C[row * ld + p] = c * xp - s * xq;
-        C[row * ld + q] = s * xp + c * xq;
-        double vp = V[row * ld + p], vq = V[row * ld + q];
-        V[row * ld + p] = c * vp - s * vq;
-        V[row * ld + q] = s * vp + c * vq;
+      // C <- R C R^T over 2x2 blocks; V <- V R^T over (row, pair)
+      for (int t = tid; t < h * h + m * h; t += RR_THREADS) {
+        if (t < h * h) {
+          const int ia = t / h, ib = t - (t / h) * h;
+          int pa, qa, pb, qb;
+          pair_of(r, ia, pa, qa);
+          pair_of(r, ib, pb, qb);
+          const double ca = rc[ia], sa = rs[ia], cb = rc[ib], sb = rs[ib];
+          const double b00 = C[pa * ld + pb], b01 = C[pa * ld + qb];
+          const double b10 = C[qa * ld + pb], b11 = C[qa * ld + qb];
+          // rows: R_a B
+          const double r00 = ca * b00 - sa * b10, r01 = ca * b01 - sa * b11;
+          const double r10 = sa * b00 + ca * b10, r11 = sa * b01 + ca * b11;
+          // columns: (R_a B) R_b^T
+          double n00 = cb * r00 - sb * r01, n01 = sb * r00 + cb * r01;
+          double n10 = cb * r10 - sb * r11, n11 = sb * r10 + cb * r11;
+          if (ia == ib && zero_pq[ia]) {
+            n01 = 0.0;
+            n10 = 0.0;
+          }
+          C[pa * ld + pb] = n00;
+          C[pa * ld + qb] = n01;
+          C[qa * ld + pb] = n10;
+          C[qa * ld + qb] = n11;
+        } else {
+          const int u = t - h * h;
+          const int row = u / h, i = u - (u / h) * h;
+          int p, q;
+          pair_of(r, i, p, q);
+          const double c = rc[i], sn = rs[i];
+          const double vp = V[row * ld + p], vq = V[row * ld + q];
+          V[row * ld + p] = c * vp - sn * vq;
+          V[row * ld + q] = sn * vp + c * vq;
+        }
       }
       __syncthreads();
     }
   }
   // 6. sort eigenvalues descending (dropped directions have eigenvalue 0)
-  for (int i = tid; i < m; i += 256) {
+  for (int i = tid; i < m; i += RR_THREADS) {
     double e = C[i * ld + i];
     ev[i] = (e == e) ? e : -1.0e300;   // NaN ranks last
     order[i] = i;
   }
   __syncthreads();
-  for (int i = tid; i < m; i += 256) {
+  for (int i = tid; i < m; i += RR_THREADS) {
     double e = ev[i];
     int rank = 0;
     for (int j = 0; j < m; ++j) {
@@ -336,25 +395,25 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int m, int k, int nblk_x,
   __syncthreads();
   // 7. Ritz coefficients Y[:, c] = D L^{-T} V[:, order[c]] (L back in LDS, C's space;
   //    the back substitution runs in place in the column of V owned by c)
-  for (int t = tid; t < m * m; t += 256) {
+  for (int t = tid; t < m * m; t += RR_THREADS) {
     int i = t / m, q = t % m;
     C[i * ld + q] = L[t];
   }
   __syncthreads();
   double* Yb = Y + (int64_t)box * m * k;
   double* Ypb = Yp + (int64_t)box * m * k;
-  for (int c = tid; c < k; c += 256) {
-    int col = order[c];
-    for (int i = m - 1; i >= 0; --i) {
-      double s = V[i * ld + col];
-      for (int q = i + 1; q < m; ++q) s -= C[q * ld + i] * V[q * ld + col];
-      V[i * ld + col] = s / C[i * ld + i];
-    }
-    for (int i = 0; i < m; ++i) Yb[i * k + c] = V[i * ld + col];
-    nu[(int64_t)box * k + c] = ev[col];
+  {
+    const int grp = tid >> 3, gl = tid & 7;
+    if (grp < k) tri_solve_group(C, ld, m, V, order[grp], ld, true, gl);
   }
   __syncthreads();
-  for (int t = tid; t < m * k; t += 256) {
+  for (int t = tid; t < m * k; t += RR_THREADS) {
+    const int i = t / k, c = t - (t / k) * k;
+    Yb[t] = V[i * ld + order[c]];
+  }
+  for (int c = tid; c < k; c += RR_THREADS) nu[(int64_t)box * k + c] = ev[order[c]];
+  __syncthreads();
+  for (int t = tid; t < m * k; t += RR_THREADS) {
     int i = t / k;
     double v = Yb[t] * dsc[i];
     v = drop[i] ? 0.0 : v;

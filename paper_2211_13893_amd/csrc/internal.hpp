@@ -9,13 +9,19 @@
 //   * block vectors are row-major [n_dof][k] (k columns contiguous per DoF);
 //   * banded SPD factors are 32x32 tiles: tile (I, I-s) at
 //     ((I*BT + s) * 1024), row-major inside the tile, s = 0 the diagonal tile;
-//     the inverses of the diagonal tiles follow in a separate NT*1024 array.
+//     the inverses of the diagonal tiles follow in a separate NT*1024 array;
+//   * after factorisation the off-diagonal band of every box matrix is copied
+//     twice more, once per sweep direction of the block solve, in the order
+//     the solve's threads read it: fragment double2 j (0..31) of solve thread
+//     t (0..nthr-1) of tile row I at ((I*32 + j) * nthr + t) * 2, so that a
+//     wavefront's load instruction reads 1 KB of consecutive memory.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #define MSG_TILE 32
 #define MSG_TILE2 1024
+#define SOLVE_TILES 32      // off-diagonal band tiles covered by the solve's thread layout
 
 namespace msg {
 
@@ -43,7 +49,15 @@ struct BoxMeta {
   int64_t fh_off, fhi_off;    // same for Ahat
   int64_t evec_off;           // offset (doubles) into the eigenvector output
   int64_t eval_off;           // offset into eigenvalue output
+  int64_t f11_fw, f11_bw;     // solve-ordered copies of the A11 band (forward / backward sweep)
+  int64_t fh_fw, fh_bw;       // same for Ahat
 };
+
+// solve threads that hold a band fragment: 16 per off-diagonal tile
+__host__ __device__ inline int solve_nthr(int BT) {
+  int t = BT - 1 < SOLVE_TILES ? BT - 1 : SOLVE_TILES;
+  return 16 * (t > 0 ? t : 0);
+}
 
 // One SPD matrix in 32x32 tile-band storage (tiles at fac + off, inverse
 // diagonal tiles at fac + ioff); BT == NT is a dense matrix.
