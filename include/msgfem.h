@@ -168,7 +168,9 @@ int msgfem_local_eigs(msgfem_plan *plan, const void *ops, void *work, const doub
  *   op 1: y = D A D x (D = diag(mu_j) on B1, 0 elsewhere)
  *   op 2: y = A11^{-1} x on B1, 0 elsewhere (interior solve)
  *   op 3: y = (A + s D A D)^{-1} x on B1 u B2, 0 on B3
- * Solves need `work` (work_bytes).  Reads x, writes y (distinct buffers). */
+ * Entries of x on B3 DoFs are ignored.  Every op uses `work` (device,
+ * work_bytes, the same buffer as msgfem_local_eigs; its contents are
+ * overwritten).  Reads x, writes y (distinct buffers). */
 int msgfem_local_apply(msgfem_plan *plan, const void *ops, void *work, int32_t op, int32_t k,
                        const double *x, double *y, void *stream);
 

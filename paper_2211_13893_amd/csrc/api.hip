@@ -28,8 +28,10 @@ __global__ void k_band_relayout(const BoxMeta*, int, double*);
 template <int KC>
 __global__ void k_band_solve(const BoxMeta*, int, int, int, const double*, const uint8_t*, const double*,
                              double*, int, int, int, double*, int64_t, const int32_t*);
-__global__ void k_spmm(const BoxMeta*, const double*, const uint8_t*, const double*, const double*,
+template <bool TWO, int CW>
+__global__ void k_spmm(const BoxMeta*, int, int, const double*, const uint8_t*, const double*, const double*,
                        double*, double*, int, int, double, const int32_t*);
+__global__ void k_mask_b3(const uint8_t*, const double*, int, int64_t, double*);
 struct Blk3 { const double* p[3]; };
 struct Blk4x3 { const double* p[4][3]; };
 struct Out4 { double* p[4]; };
@@ -680,8 +682,10 @@ static void lds_attributes() {
 
 static int spmm(Ctx& c, const double* X, double* Y, double* Y2, int kk, int yclasses, double scale,
                 const int32_t* active) {
-  int nq = (kk + 3) / 4;
-  dim3 grid((unsigned)(((int64_t)c.p->max_nodes * nq + 255) / 256), c.nb);
+  const int cw = Y2 ? 4 : (kk == 1 ? 1 : 8);
+  const int nq = (kk + cw - 1) / cw;
+  const int bpb = (int)(((int64_t)c.p->max_nodes * nq + 255) / 256);
+  dim3 grid((unsigned)(c.nb == 1 ? bpb : 8 * ((c.nb + 7) / 8) * bpb));
   double by = 0, fl = 0;
   for (int b = 0; b < c.nb; ++b) {
     if (!c.counts(b, active)) continue;
@@ -691,8 +695,15 @@ static int spmm(Ctx& c, const double* X, double* Y, double* Y2, int kk, int ycla
     fl += 2.0 * 243 * m.n_nodes * kk * (Y2 ? 2 : 1);
   }
   ProfScope ps(c.p, PK_SPMM, c.s, by, fl);
-  k_spmm<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.stencil, c.v.cls, c.v.mu1, X, Y, Y2, kk, yclasses, scale,
-                                active);
+  if (Y2)
+    k_spmm<true, 4><<<grid, 256, 0, c.s>>>(c.v.meta, c.nb, bpb, c.v.stencil, c.v.cls, c.v.mu1, X, Y, Y2, kk,
+                                           yclasses, scale, active);
+  else if (kk == 1)
+    k_spmm<false, 1><<<grid, 256, 0, c.s>>>(c.v.meta, c.nb, bpb, c.v.stencil, c.v.cls, c.v.mu1, X, Y, Y2, kk,
+                                            yclasses, scale, active);
+  else
+    k_spmm<false, 8><<<grid, 256, 0, c.s>>>(c.v.meta, c.nb, bpb, c.v.stencil, c.v.cls, c.v.mu1, X, Y, Y2, kk,
+                                            yclasses, scale, active);
   LAUNCHCHK(c.p);
   return 0;
 }
@@ -929,12 +940,17 @@ extern "C" int msgfem_local_apply(msgfem_plan* p, const void* ops, void* work, i
   c.s = (hipStream_t)stream;
   c.nb = (int)p->meta.size();
   c.k = p->k;
-  if (op == 0) return spmm(c, x, y, nullptr, kk, (1 << 1) | (1 << 2), 1.0, nullptr) ? MSGFEM_EHIP : 0;
-  if (op == 1) {
-    return spmm(c, x, nullptr, y, kk, 0, 1.0, nullptr) ? MSGFEM_EHIP : 0;
-  }
-  if (!work) return fail(p, MSGFEM_EARG, "solves need the work buffer");
+  if (!work) return fail(p, MSGFEM_EARG, "null work buffer");
   c.w = work_view(p, work);
+  if (op == 0 || op == 1) {
+    // B3 columns are removed from A: clear the caller's block there first
+    double* xm = c.w.vec + (int64_t)20 * p->vec_total;
+    const int64_t n = p->dofs_total * kk;
+    k_mask_b3<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, c.s>>>(c.v.cls, x, kk, n, xm);
+    LAUNCHCHK(p);
+    if (op == 0) return spmm(c, xm, y, nullptr, kk, (1 << 1) | (1 << 2), 1.0, nullptr) ? MSGFEM_EHIP : 0;
+    return spmm(c, xm, nullptr, y, kk, 0, 1.0, nullptr) ? MSGFEM_EHIP : 0;
+  }
   if (op == 2) return solve(c, 0, x, y, kk, 1 << 1, 1, nullptr) ? MSGFEM_EHIP : 0;
   if (op == 3) return solve(c, 1, x, y, kk, (1 << 1) | (1 << 2), 1, nullptr) ? MSGFEM_EHIP : 0;
   return fail(p, MSGFEM_EARG, "unknown op %d", op);
@@ -1307,8 +1323,9 @@ extern "C" int msgfem_geneo_pcg(msgfem_plan* p, const void* ops, void* work, voi
   c.k = k;
   const unsigned gblk = (unsigned)std::min<int64_t>((nd + 255) / 256, 2048);
   auto gspmv = [&](const double* in, double* out) -> int {
-    dim3 grid((unsigned)((ng + 255) / 256), 1);
-    k_spmm<<<grid, 256, 0, s>>>(gmeta, gst, gcls, gmu, in, out, nullptr, 1, 1 << 1, 1.0, nullptr);
+    const int gb = (int)((ng + 255) / 256);
+    k_spmm<false, 1><<<dim3((unsigned)gb), 256, 0, s>>>(gmeta, 1, gb, gst, gcls, gmu, in, out, nullptr, 1,
+                                                        1 << 1, 1.0, nullptr);
     LAUNCHCHK(p);
     return 0;
   };

@@ -1,93 +1,144 @@
 // Block SpMM with the block-27 box stencil (Sec. 2: a_{Omega*} assembled).
 //
 //   Y  = scale * A X       on the DoFs whose class bit is set in y_classes
-//                          (0 on the others); B3 inputs are ignored (B3
-//                          rows/columns are removed from A, Sec. 4.3)
+//                          (0 on the others)
 //   Y2 = D A D X           (optional) with D = diag(mu_j on B1, 0 elsewhere):
 //                          the partition-of-unity form B of Sec. 4.3.
-// One thread per (node, group of 4 columns); grid.y = box.  The stencil is
-// read once per node (structure of arrays, coalesced across nodes); the
-// column groups of a node share it through the cache.
+// B3 rows and columns are removed from A (Sec. 4.3): the output is masked by
+// class, and X must be zero on B3 (every block the library forms is; the
+// C entry point masks a caller's block first, k_mask_b3).
+//
+// One thread per (node, CW consecutive columns): the 243 stencil values of a
+// node are read once per CW columns (structure of arrays, coalesced across
+// nodes), the rows of X in 16-byte pieces.  With Y2, mu of the neighbour DoF
+// is folded into the stencil value.  Blocks are ordered box-major per XCD
+// (block x runs on XCD x mod 8): XCD c takes every block of box c, then of
+// box c + 8, ..., so the 27-point neighbourhoods of a box come from that
+// XCD's L2 while it works on the box.
+// grid.x = 8 * ceil(n_box/8) * blocks_per_box (n_box = 1: blocks_per_box).
 #include "internal.hpp"
 
 namespace msg {
 
-__global__ __launch_bounds__(256) void k_spmm(const BoxMeta* __restrict__ meta,
+// CW columns of row d starting at c0 (zero beyond k); pairs when k is even
+template <int CW>
+__device__ inline void load_cols(const double* __restrict__ x, int64_t d, int k, int c0, double (&v)[CW]) {
+  const double* p = x + d * k + c0;
+  if ((k & 1) == 0) {
+#pragma unroll
+    for (int j = 0; j < CW; j += 2) {
+      if (c0 + j < k) {
+        const double2 a = *(const double2*)(p + j);
+        v[j] = a.x;
+        v[j + 1] = a.y;
+      } else {
+        v[j] = 0.0;
+        v[j + 1] = 0.0;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < CW; ++j) v[j] = (c0 + j < k) ? p[j] : 0.0;
+  }
+}
+
+template <bool TWO, int CW>
+__global__ __launch_bounds__(256) void k_spmm(const BoxMeta* __restrict__ meta, int n_box,
+                                              int blocks_per_box,
                                               const double* __restrict__ stencil,
                                               const uint8_t* __restrict__ cls,
                                               const double* __restrict__ mu1,
                                               const double* __restrict__ X, double* Y,
                                               double* Y2, int k, int y_classes,
                                               double scale, const int32_t* __restrict__ active) {
-  int box = blockIdx.y;
+  // a single box (the whole-mesh operator) is spread over all XCDs instead
+  const int xb = blockIdx.x, r = xb >> 3;
+  const int box = n_box == 1 ? 0 : (r / blocks_per_box) * 8 + (xb & 7);
+  const int blk = n_box == 1 ? xb : r % blocks_per_box;
+  if (box >= n_box) return;
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
-  int nq = (k + 3) >> 2;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nq = (k + CW - 1) / CW;
+  const int64_t t = (int64_t)blk * blockDim.x + threadIdx.x;
   if (t >= (int64_t)bm.n_nodes * nq) return;
-  int node = (int)(t / nq), q = (int)(t % nq);
-  int c0 = 4 * q;
-  int li = node % bm.mx, lj = (node / bm.mx) % bm.my, lk = node / (bm.mx * bm.my);
-  const double* st = stencil + bm.node_off * 243;
+  const int node = (int)(t / nq), q = (int)(t % nq);
+  const int c0 = CW * q;
+  const int li = node % bm.mx, lj = (node / bm.mx) % bm.my, lk = node / (bm.mx * bm.my);
+  const double* st = stencil + bm.node_off * 243 + node;
   const uint8_t* cl = cls + bm.dof_off;
   const double* m1 = mu1 + bm.dof_off;
   const double* x = X + (bm.dof_off * k);
-  double acc[3][4] = {}, acc2[3][4] = {};
-  const bool two = Y2 != nullptr;
+  double acc[3][CW], acc2[3][CW];
+#pragma unroll
+  for (int cr = 0; cr < 3; ++cr)
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      acc[cr][j] = 0.0;
+      acc2[cr][j] = 0.0;
+    }
   for (int dz = -1; dz <= 1; ++dz) {
-    int kk = lk + dz;
+    const int kk = lk + dz;
     if (kk < 0 || kk >= bm.mz) continue;
     for (int dy = -1; dy <= 1; ++dy) {
-      int jj = lj + dy;
+      const int jj = lj + dy;
       if (jj < 0 || jj >= bm.my) continue;
+#pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        int ii = li + dx;
+        const int ii = li + dx;
         if (ii < 0 || ii >= bm.mx) continue;
-        int nn = ii + bm.mx * (jj + bm.my * kk);
-        int nb = nb_index(dx, dy, dz);
-        double xv[3][4], xm[3][4];
+        const int nn = ii + bm.mx * (jj + bm.my * kk);
+        const int nb = nb_index(dx, dy, dz);
+        double xv[3][CW];
+        double mu[3];
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
-          int d = 3 * nn + cc;
-          bool ok = cl[d] != 3;
-          double mu = m1[d];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            double v = (ok && c0 + j < k) ? x[(int64_t)d * k + c0 + j] : 0.0;
-            xv[cc][j] = v;
-            xm[cc][j] = mu * v;
-          }
+          load_cols<CW>(x, 3 * nn + cc, k, c0, xv[cc]);
+          mu[cc] = TWO ? m1[3 * nn + cc] : 0.0;
         }
 #pragma unroll
         for (int cr = 0; cr < 3; ++cr)
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc) {
-            double a = st[(int64_t)(nb * 9 + 3 * cr + cc) * bm.n_nodes + node];
+            const double a = st[(int64_t)(nb * 9 + 3 * cr + cc) * bm.n_nodes];
+            const double am = a * mu[cc];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < CW; ++j) {
               acc[cr][j] += a * xv[cc][j];
-              if (two) acc2[cr][j] += a * xm[cc][j];
+              if (TWO) acc2[cr][j] += am * xv[cc][j];
             }
           }
       }
     }
   }
   double* y = Y ? Y + (bm.dof_off * k) : nullptr;
-  double* y2 = two ? Y2 + (bm.dof_off * k) : nullptr;
+  double* y2 = TWO ? Y2 + (bm.dof_off * k) : nullptr;
 #pragma unroll
   for (int cr = 0; cr < 3; ++cr) {
-    int d = 3 * node + cr;
-    uint8_t kc = cl[d];
-    bool w = (y_classes >> kc) & 1;
-    double mu = m1[d];
+    const int d = 3 * node + cr;
+    const bool w = (y_classes >> cl[d]) & 1;
+    const double mo = TWO ? m1[d] : 0.0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < CW; ++j) {
       if (c0 + j < k) {
         if (y) y[(int64_t)d * k + c0 + j] = w ? scale * acc[cr][j] : 0.0;
-        if (two) y2[(int64_t)d * k + c0 + j] = mu * acc2[cr][j];
+        if (TWO) y2[(int64_t)d * k + c0 + j] = mo * acc2[cr][j];
       }
     }
   }
+}
+
+template __global__ void k_spmm<false, 8>(const BoxMeta*, int, int, const double*, const uint8_t*, const double*,
+                                          const double*, double*, double*, int, int, double, const int32_t*);
+template __global__ void k_spmm<false, 1>(const BoxMeta*, int, int, const double*, const uint8_t*, const double*,
+                                          const double*, double*, double*, int, int, double, const int32_t*);
+template __global__ void k_spmm<true, 4>(const BoxMeta*, int, int, const double*, const uint8_t*, const double*,
+                                         const double*, double*, double*, int, int, double, const int32_t*);
+
+// out = X with the rows of B3 DoFs cleared (flat over all boxes' [n_dof][k] blocks)
+__global__ void k_mask_b3(const uint8_t* __restrict__ cls, const double* __restrict__ X, int k, int64_t n,
+                          double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = cls[e / k] == 3 ? 0.0 : X[e];
 }
 
 }  // namespace msg

@@ -240,7 +240,7 @@ class LocalStage:
         torch = self.torch
         k = self.k if k is None else k
         y = torch.zeros_like(x)
-        work = self._alloc_work() if op in (OP_A11_SOLVE, OP_AHAT_SOLVE) else None
+        work = self._alloc_work()
         rc = self.lib.msgfem_local_apply(self.plan, _ptr(self.ops), _ptr(work), op, k, _ptr(x), _ptr(y),
                                          _stream_handle(torch, self.device))
         _check(rc, self.plan, "msgfem_local_apply")
