@@ -11,9 +11,12 @@ Workload (default): the uniform batch of 64 interior 14^3-element oversampled
 boxes (10125 DoF each) of a ply/resin laminate, n_ev = 16, block 24, FP64.
 
 Prints one JSON line: GEVPs/s (boxes whose n_ev pairs all reach
-rho <= 1e-6, per second), the roofline of the dominant kernel (HIP events
-around each launch on its stream, algorithmic bytes/flops from the library)
-and the FP64 CPU oracle timed on a bounded sample of the same boxes.
+rho <= 1e-6, per second) of the FP64 path, the roofline of its dominant
+kernel (HIP events around each launch on its stream, algorithmic
+bytes/flops from the library), the same workload on the mixed-precision path
+(FP32 operator copies first, FP64 finish; its residuals are FP64 residuals)
+with its ratio to the FP64 path, and the FP64 CPU oracle timed on a bounded
+sample of the same boxes.
 """
 from __future__ import annotations
 
@@ -59,6 +62,7 @@ def main():
     ap.add_argument("--boxes", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision path")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the local GEVPs of a batch "
@@ -69,33 +73,53 @@ def main():
     from paper_2211_13893_amd import msgfem, synth
 
     prob = synth.uniform_batch(n_boxes=args.boxes)
-    stage = msgfem.LocalStage(prob, tol=1e-6)
 
-    def step():
-        stage.msgfem_assemble_local()
-        return stage.msgfem_local_eigs()
+    def run(precision: int):
+        """Time `steps` full local stages (assembly + factorisation + LOBPCG)."""
+        stage = msgfem.LocalStage(prob, tol=1e-6, precision=precision)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stage.msgfem_profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stage.msgfem_profile(False)
-    stats = stage.msgfem_profile_stats()
-    ms_step = (t1 - t0) / args.steps * 1e3
-    resid = out["resid"].cpu().numpy()
-    status = out["status"].cpu().numpy()
-    iters = out["iters"].cpu().numpy()
-    conv = 0
-    for b in range(len(stage.batch)):
-        r = stage.resid(out, b).cpu().numpy()
-        conv += int(np.all(r <= 1e-6) and status[b] == 0)
-    value = conv / (ms_step / 1e3)
+        def step():
+            stage.msgfem_assemble_local()
+            return stage.msgfem_local_eigs()
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        stage.msgfem_profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stage.msgfem_profile(False)
+        stats = stage.msgfem_profile_stats()
+        ms_step = (t1 - t0) / args.steps * 1e3
+        status = out["status"].cpu().numpy()
+        iters = out["iters"].cpu().numpy()
+        conv = 0
+        for b in range(len(stage.batch)):
+            r = stage.resid(out, b).cpu().numpy()
+            conv += int(np.all(r <= 1e-6) and status[b] == 0)
+        res = {"stage": stage, "stats": stats, "ms_step": ms_step, "conv": conv, "iters": iters,
+               "value": conv / (ms_step / 1e3), "nu": out["evals"].cpu().numpy()}
+        return res
+
+    fp = run(0)
+    stage, stats, ms_step, conv, iters, value = (fp["stage"], fp["stats"], fp["ms_step"], fp["conv"],
+                                                 fp["iters"], fp["value"])
+    mixed = None
+    if not args.no_mixed:
+        mx = run(1)
+        lam64, lam32 = fp["nu"], mx["nu"]
+        dnu = np.abs(1.0 / (lam32 + 1.0) - 1.0 / (lam64 + 1.0)) * (lam64 + 1.0)
+        mixed = {"value": mx["value"], "unit": "GEVP/s", "ms_per_step": mx["ms_step"],
+                 "converged": f"{mx['conv']}/{len(stage.batch)}",
+                 "lobpcg_iters_mean": float(mx["iters"].mean()),
+                 "vs_fp64_path": mx["value"] / value if value > 0 else None,
+                 "max_nu_rel_diff_vs_fp64_path": float(dnu.max()),
+                 "kernels_ms_per_step": {n: v["ms"] / args.steps for n, v in mx["stats"].items()}}
+        del mx
 
     # dominant kernel and its roofline
     tot_ms = sum(v["ms"] for v in stats.values()) or 1.0
@@ -147,6 +171,7 @@ def main():
         "spmm_hbm_GBs": (spmm["bytes"] / (spmm["ms"] / 1e3) / 1e9) if spmm else None,
         "roofline": roof,
         "kernels": kernels,
+        "mixed_path": mixed,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline and args.cpu_sample > 0:

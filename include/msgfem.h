@@ -83,7 +83,15 @@ typedef struct {
   double tol;       /* residual tolerance on rho (default 1e-6) */
   int32_t maxit;    /* LOBPCG iteration cap (default 200) */
   int32_t block;    /* block width k >= max n_ev (0: n_ev + max(4, n_ev/2) rounded up to 8) */
-  int32_t precision;/* 0 = FP64 throughout */
+  int32_t precision;/* 0 = FP64 throughout.  1 = mixed (A-harmonic GEVP only): the
+                       assembly also keeps FP32 copies of the stencil and of the
+                       factors' solve data (ops_bytes grows accordingly); LOBPCG
+                       first runs its SpMM and block solves on those copies (FP64
+                       arithmetic, FP64 Gram / Rayleigh-Ritz / update / residual)
+                       until every active box has rho <= max(1e-4, 100 tol) (or
+                       the largest rho stops halving over two iterations), then
+                       re-forms the block with the FP64 operators and finishes in
+                       FP64, so the returned residuals are FP64 residuals */
   int32_t geneo;    /* 0: A-harmonic GEVP on Omega_j^* (Sec. 3.3); 1: classic GenEO GEVP
                        a_{Omega_j}(phi, v) = lambda a_{Omega_j}(Xi phi, Xi v) on Omega_j
                        itself (Sec. 3.2; oversampling ignored), unknowns on every

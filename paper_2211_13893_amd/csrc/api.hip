@@ -25,13 +25,15 @@ __global__ void k_chol_update(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_panel(const MatDesc*, int, double*);
 __global__ void k_chol_unit(const MatDesc*, double*);
 __global__ void k_band_relayout(const BoxMeta*, int, double*);
-template <int KC>
-__global__ void k_band_solve(const BoxMeta*, int, int, int, const double*, const uint8_t*, const double*,
-                             double*, int, int, int, double*, int64_t, const int32_t*);
-template <bool TWO, int CW>
-__global__ void k_spmm(const BoxMeta*, int, int, const double*, const uint8_t*, const double*, const double*,
+template <int KC, typename T>
+__global__ void k_band_solve(const BoxMeta*, int, int, int, const double*, const T*, const uint8_t*,
+                             const double*, double*, int, int, int, double*, int64_t, const int32_t*);
+template <bool TWO, int CW, typename ST>
+__global__ void k_spmm(const BoxMeta*, int, int, const ST*, const uint8_t*, const double*, const double*,
                        double*, double*, int, int, double, const int32_t*);
+__global__ void k_mixed_copies(const BoxMeta*, const double*, float*, const double*, float*);
 __global__ void k_mask_b3(const uint8_t*, const double*, int, int64_t, double*);
+__global__ void k_keep_classes(const uint8_t*, int, int, int64_t, double*);
 struct Blk3 { const double* p[3]; };
 struct Blk4x3 { const double* p[4][3]; };
 struct Out4 { double* p[4]; };
@@ -105,7 +107,7 @@ struct msgfem_plan {
   int64_t n_nodes_global = 0;
   // ops layout (bytes)
   int64_t o_meta = 0, o_mats = 0, o_omega = 0, o_ctab = 0, o_wtot = 0, o_stencil = 0, o_mu = 0,
-          o_cls = 0, o_fac = 0, ops_bytes = 0;
+          o_cls = 0, o_fac = 0, o_fac32 = 0, o_st32 = 0, ops_bytes = 0;
   int64_t nodes_total = 0, dofs_total = 0, fac_total = 0, vec_total = 0, evec_total = 0,
           eval_total = 0;
   int max_nodes = 0, max_dof = 0, max_nt = 0, max_bt = 0;
@@ -242,7 +244,8 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     if (!(o.tol > 0)) o.tol = 1e-6;
     if (o.maxit <= 0) o.maxit = 200;
   }
-  if (o.precision != 0) return fail(p, MSGFEM_EARG, "precision %d not supported", o.precision);
+  if (o.precision != 0 && o.precision != 1) return fail(p, MSGFEM_EARG, "precision %d not supported", o.precision);
+  if (o.precision == 1 && o.geneo) return fail(p, MSGFEM_EARG, "the mixed path is for the A-harmonic GEVP only");
   p->opts = o;
   const int N[3] = {mesh->nx, mesh->ny, mesh->nz};
   p->n_nodes_global = (int64_t)(N[0] + 1) * (N[1] + 1) * (N[2] + 1);
@@ -370,6 +373,11 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   p->o_mu = off; off = align256(off + p->dofs_total * 8);
   p->o_cls = off; off = align256(off + p->dofs_total);
   p->o_fac = off; off = align256(off + p->fac_total * 8);
+  if (o.precision == 1) {
+    // FP32 copies of the stencil and of the factors' solve data (mixed path)
+    p->o_fac32 = off; off = align256(off + p->fac_total * 4);
+    p->o_st32 = off; off = align256(off + p->nodes_total * 243 * 4);
+  }
   p->ops_bytes = off;
   // work layout
   p->n_gchunk = (p->max_dof + GRAM_ROWS - 1) / GRAM_ROWS;
@@ -482,6 +490,8 @@ struct OpsView {
   double* mu1;
   uint8_t* cls;
   double* fac;
+  float* fac32;      // mixed path only
+  float* stencil32;  // mixed path only
 };
 
 static OpsView ops_view(const msgfem_plan* p, const void* ops) {
@@ -496,6 +506,8 @@ static OpsView ops_view(const msgfem_plan* p, const void* ops) {
   v.mu1 = (double*)(b + p->o_mu);
   v.cls = (uint8_t*)(b + p->o_cls);
   v.fac = (double*)(b + p->o_fac);
+  v.fac32 = p->o_fac32 ? (float*)(b + p->o_fac32) : nullptr;
+  v.stencil32 = p->o_st32 ? (float*)(b + p->o_st32) : nullptr;
   return v;
 }
 
@@ -611,6 +623,11 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
     k_band_relayout<<<dim3((unsigned)std::max<int64_t>(blocks, 1), nb), 256, 0, s>>>(v.meta, kind, v.fac);
     LAUNCHCHK(p);
   }
+  if (p->opts.precision == 1) {
+    ProfScope ps(p, PK_BUILD, s, 0.0, 0.0);
+    k_mixed_copies<<<dim3(1024, nb, 3), 256, 0, s>>>(v.meta, v.fac, v.fac32, v.stencil, v.stencil32);
+    LAUNCHCHK(p);
+  }
   return MSGFEM_OK;
 }
 
@@ -660,6 +677,7 @@ struct Ctx {
   Work w;
   hipStream_t s;
   int nb, k;
+  bool use32 = false;           // FP32 operator copies (mixed path, first phase)
   std::vector<int32_t> act_h;   // host copy of the active flags (all 1 when unknown)
   bool counts(int b, const int32_t* act) const { return !act || act_h.empty() || act_h[b]; }
 };
@@ -671,7 +689,9 @@ static void lds_attributes() {
   done = true;
   (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
-  (void)hipFuncSetAttribute((const void*)k_band_solve<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)k_band_solve<8, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_band_solve<8, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
@@ -695,15 +715,19 @@ static int spmm(Ctx& c, const double* X, double* Y, double* Y2, int kk, int ycla
     fl += 2.0 * 243 * m.n_nodes * kk * (Y2 ? 2 : 1);
   }
   ProfScope ps(c.p, PK_SPMM, c.s, by, fl);
-  if (Y2)
-    k_spmm<true, 4><<<grid, 256, 0, c.s>>>(c.v.meta, c.nb, bpb, c.v.stencil, c.v.cls, c.v.mu1, X, Y, Y2, kk,
-                                           yclasses, scale, active);
-  else if (kk == 1)
-    k_spmm<false, 1><<<grid, 256, 0, c.s>>>(c.v.meta, c.nb, bpb, c.v.stencil, c.v.cls, c.v.mu1, X, Y, Y2, kk,
-                                            yclasses, scale, active);
-  else
-    k_spmm<false, 8><<<grid, 256, 0, c.s>>>(c.v.meta, c.nb, bpb, c.v.stencil, c.v.cls, c.v.mu1, X, Y, Y2, kk,
-                                            yclasses, scale, active);
+  auto launch = [&](auto st) {
+    if (Y2)
+      k_spmm<true, 4><<<grid, 256, 0, c.s>>>(c.v.meta, c.nb, bpb, st, c.v.cls, c.v.mu1, X, Y, Y2, kk, yclasses,
+                                             scale, active);
+    else if (kk == 1)
+      k_spmm<false, 1><<<grid, 256, 0, c.s>>>(c.v.meta, c.nb, bpb, st, c.v.cls, c.v.mu1, X, Y, Y2, kk, yclasses,
+                                              scale, active);
+    else
+      k_spmm<false, 8><<<grid, 256, 0, c.s>>>(c.v.meta, c.nb, bpb, st, c.v.cls, c.v.mu1, X, Y, Y2, kk, yclasses,
+                                              scale, active);
+  };
+  if (c.use32) launch((const float*)c.v.stencil32);
+  else launch((const double*)c.v.stencil);
   LAUNCHCHK(c.p);
   return 0;
 }
@@ -723,8 +747,14 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
     fl += 4.0 * e * kk;
   }
   ProfScope ps(c.p, PK_SOLVE, c.s, by, fl);
-  k_band_solve<KC><<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, c.v.fac, c.v.cls, in, out, kk,
-                                            out_classes, zero_rest, c.w.scr, c.p->scr_stride, active);
+  if (c.use32)
+    k_band_solve<KC, float><<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, c.v.fac, c.v.fac32, c.v.cls,
+                                                     in, out, kk, out_classes, zero_rest, c.w.scr, c.p->scr_stride,
+                                                     active);
+  else
+    k_band_solve<KC, double><<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, c.v.fac, c.v.fac, c.v.cls,
+                                                      in, out, kk, out_classes, zero_rest, c.w.scr,
+                                                      c.p->scr_stride, active);
   LAUNCHCHK(c.p);
   return 0;
 }
@@ -820,13 +850,13 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
     else k_random_start<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, vcls, p->opts.seed, B[0][0]);
     LAUNCHCHK(p);
   }
-  if (images(B[0][0], B[1][0], B[2][0], B[3][0], nullptr)) return MSGFEM_EHIP;
-  // initial Rayleigh-Ritz on X alone (T-orthonormalises the start block)
-  {
+  // Rayleigh-Ritz on X alone (T-orthonormalises the block; also used when the
+  // mixed path moves to the FP64 operators)
+  auto rr_x = [&](const int32_t* a_) -> int {
     double* Zb[1] = {B[0][0]};
     double* Ab[1] = {B[1][0]};
     double* Bb[1] = {B[2][0]};
-    if (gram(c, 1, Zb, Ab, Bb, nullptr)) return MSGFEM_EHIP;
+    if (gram(c, 1, Zb, Ab, Bb, a_)) return MSGFEM_EHIP;
     Blk4x3 Z;
     Out4 OX, OP;
     for (int kind = 0; kind < 4; ++kind) {
@@ -837,11 +867,28 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
     }
     int nq = (k + 3) / 4;
     dim3 grid((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, nkinds);
-    k_update<<<grid, 256, (size_t)2 * k * k * 8, c.s>>>(c.v.meta, 1, k, Z, OX, OP, c.w.Y, c.w.Yp, nullptr);
+    k_update<<<grid, 256, (size_t)2 * k * k * 8, c.s>>>(c.v.meta, 1, k, Z, OX, OP, c.w.Y, c.w.Yp, a_);
     LAUNCHCHK(p);
     for (int kind = 0; kind < 4; ++kind) std::swap(B[kind][0], B[kind][3]);
-  }
+    return 0;
+  };
+  if (images(B[0][0], B[1][0], B[2][0], B[3][0], nullptr)) return MSGFEM_EHIP;
+  if (rr_x(nullptr)) return MSGFEM_EHIP;
   int n_chunk = p->n_gchunk;
+  // Mixed path: the first phase runs the SpMM and the block solves with FP32
+  // operator copies (FP64 arithmetic and FP64 dense steps); once every active
+  // box has rho <= switch_tol (or the FP32 phase stagnates, or after fp32_cap
+  // iterations) the block X is
+  // re-imaged with the FP64 operators, re-orthonormalised, and the iteration
+  // continues in FP64 (without the P block once) to the requested tolerance,
+  // so the final residual check is FP64.
+  const bool mixed = p->opts.precision == 1;
+  c.use32 = mixed;
+  const double switch_tol = std::max(1e-4, 100.0 * p->opts.tol);
+  const int fp32_cap = 30;
+  int fp32_iters = 0;
+  bool restart = false;
+  std::vector<double> rho_h, rhist;
   for (int it = 0; it <= p->opts.maxit; ++it) {
     // residual of the current Ritz block, convergence, active set
     {
@@ -851,21 +898,52 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
                                         B[0][1], GRAM_ROWS, n_chunk, c.w.rpart, act);
       LAUNCHCHK(p);
       k_fill_i32<<<1, 32, 0, c.s>>>(c.w.nact, 1, 0);
+      // FP32 phase: residuals are estimates, no box is retired
       k_converge<<<(nb + 63) / 64, 64, 0, c.s>>>(c.v.meta, nb, k, n_chunk, c.w.rpart, c.w.nu,
-                                                  p->opts.tol, c.w.rho, act, c.w.iters, c.w.nact,
-                                                  it < p->opts.maxit ? 1 : 0);
+                                                  c.use32 ? 0.0 : p->opts.tol, c.w.rho, act, c.w.iters,
+                                                  c.w.nact, it < p->opts.maxit ? 1 : 0);
       LAUNCHCHK(p);
       c.act_h.resize(nb);
       HIPCHK(p, hipMemcpyAsync(c.act_h.data(), act, nb * 4, hipMemcpyDeviceToHost, c.s));
+      if (c.use32) {
+        rho_h.resize((size_t)nb * k);
+        HIPCHK(p, hipMemcpyAsync(rho_h.data(), c.w.rho, (size_t)nb * k * 8, hipMemcpyDeviceToHost, c.s));
+      }
       HIPCHK(p, hipStreamSynchronize(c.s));
       int nact = 0;
       for (int b = 0; b < nb; ++b) nact += c.act_h[b] != 0;
       if (nact == 0 || it == p->opts.maxit) break;
+      if (c.use32) {
+        double rmax = 0.0;
+        for (int b = 0; b < nb; ++b) {
+          if (!c.act_h[b]) continue;
+          for (int cc = 0; cc < p->meta[b].n_ev; ++cc) rmax = std::max(rmax, rho_h[(size_t)b * k + cc]);
+        }
+        // leave the FP32 phase when it has done its part (rho <= switch_tol),
+        // when it stagnates at the FP32 operators' accuracy (rho not halved
+        // over two iterations) or at the iteration cap
+        rhist.push_back(rmax);
+        const size_t nh = rhist.size();
+        const bool stalled = nh >= 3 && !(rhist[nh - 1] <= 0.5 * rhist[nh - 3]);
+        if (!(rmax <= switch_tol) && !stalled && ++fp32_iters < fp32_cap) {
+          // stay in the FP32 phase
+        } else {
+          c.use32 = false;
+          const int64_t n = p->dofs_total * k;
+          k_keep_classes<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, c.s>>>(c.v.cls, vcls, k, n,
+                                                                                               B[0][0]);
+          LAUNCHCHK(p);
+          if (images(B[0][0], B[1][0], B[2][0], B[3][0], act)) return MSGFEM_EHIP;
+          if (rr_x(act)) return MSGFEM_EHIP;
+          restart = true;
+          continue;
+        }
+      }
     }
     // soft locking of converged columns (their W and P directions vanish)
     {
       dim3 grid((unsigned)(((int64_t)p->max_dof * k + 255) / 256), nb);
-      const bool hasP = it > 0;
+      const bool hasP = it > 0 && !restart;
       k_lock<<<grid, 256, 0, c.s>>>(c.v.meta, k, c.w.rho, 0.1 * p->opts.tol, B[0][1],
                                     hasP ? B[0][2] : nullptr, hasP ? B[1][2] : nullptr,
                                     hasP ? B[2][2] : nullptr, (hasP && !geneo) ? B[3][2] : nullptr, act);
@@ -874,7 +952,8 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
     // W = preconditioned residual: B2 trace of (A + s DAD)^{-1} [0; R]
     if (solve(c, 1, B[0][1], B[0][1], k, vcls, 1, act)) return MSGFEM_EHIP;
     if (images(B[0][1], B[1][1], B[2][1], B[3][1], act)) return MSGFEM_EHIP;
-    int nblk = (it == 0) ? 2 : 3;
+    int nblk = (it == 0 || restart) ? 2 : 3;
+    restart = false;
     double* Zb[3] = {B[0][0], B[0][1], B[0][2]};
     double* Ab[3] = {B[1][0], B[1][1], B[1][2]};
     double* Bb[3] = {B[2][0], B[2][1], B[2][2]};
@@ -1324,8 +1403,8 @@ extern "C" int msgfem_geneo_pcg(msgfem_plan* p, const void* ops, void* work, voi
   const unsigned gblk = (unsigned)std::min<int64_t>((nd + 255) / 256, 2048);
   auto gspmv = [&](const double* in, double* out) -> int {
     const int gb = (int)((ng + 255) / 256);
-    k_spmm<false, 1><<<dim3((unsigned)gb), 256, 0, s>>>(gmeta, 1, gb, gst, gcls, gmu, in, out, nullptr, 1,
-                                                        1 << 1, 1.0, nullptr);
+    k_spmm<false, 1><<<dim3((unsigned)gb), 256, 0, s>>>(gmeta, 1, gb, (const double*)gst, gcls, gmu, in, out,
+                                                        nullptr, 1, 1 << 1, 1.0, nullptr);
     LAUNCHCHK(p);
     return 0;
   };

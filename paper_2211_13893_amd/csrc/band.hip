@@ -375,24 +375,29 @@ __global__ void k_band_relayout(const BoxMeta* __restrict__ meta, int kind, doub
 //          backward = Lu[16h+q][4rq+i] of tile (I+s, I)  (row i of its transpose)
 // read from the solve-ordered copy F (fw or bw) of the band: consecutive
 // threads read consecutive 16-byte pieces.
-__device__ inline void frag_load(const double2* __restrict__ F, int I, int nthr, int smax, int dir,
-                                 int s, int tid, double (&f)[4][16]) {
+template <typename T> struct vec2_of;
+template <> struct vec2_of<double> { typedef double2 type; };
+template <> struct vec2_of<float> { typedef float2 type; };
+
+template <typename T>
+__device__ inline void frag_load(const typename vec2_of<T>::type* __restrict__ F, int I, int nthr, int smax,
+                                 int dir, int s, int tid, double (&f)[4][16]) {
   if (s > smax) return;
-  const double2* p = F + (int64_t)I * 32 * nthr + tid;
+  const typename vec2_of<T>::type* p = F + (int64_t)I * 32 * nthr + tid;
   if (dir < 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        double2 a = p[(int64_t)(8 * i + q) * nthr];
+        const auto a = p[(int64_t)(8 * i + q) * nthr];
         f[i][2 * q] = a.x;
         f[i][2 * q + 1] = a.y;
       }
   } else {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      double2 a = p[(int64_t)(2 * q) * nthr];
-      double2 b = p[(int64_t)(2 * q + 1) * nthr];
+      const auto a = p[(int64_t)(2 * q) * nthr];
+      const auto b = p[(int64_t)(2 * q + 1) * nthr];
       f[0][q] = a.x;
       f[1][q] = a.y;
       f[2][q] = b.x;
@@ -401,10 +406,14 @@ __device__ inline void frag_load(const double2* __restrict__ F, int I, int nthr,
   }
 }
 
-template <int KC>
+// T: precision of the factor copies read by the sweeps (double, or float in
+// the mixed path; ft = the factor array in that precision, same offsets as
+// fac).  Arithmetic, right-hand sides and solutions are FP64 in both cases.
+template <int KC, typename T>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     const BoxMeta* __restrict__ meta, int n_box, int n_chunk, int kind,
-    const double* __restrict__ fac, const uint8_t* __restrict__ cls, const double* in, double* out,
+    const double* __restrict__ fac, const T* __restrict__ ft, const uint8_t* __restrict__ cls,
+    const double* in, double* out,
     int ldk, int out_classes, int zero_rest, double* __restrict__ scratch, int64_t scratch_stride,
     const int32_t* __restrict__ active) {
   extern __shared__ double ring[];   // [BT][32][KC]
@@ -432,8 +441,9 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   double* w = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
   const int BT = v.BT, NT = v.NT;
   const int nthr = solve_nthr(BT);
-  const double2* Ffw = (const double2*)(fac + v.fw);
-  const double2* Fbw = (const double2*)(fac + v.bw);
+  typedef typename vec2_of<T>::type V2;
+  const V2* Ffw = (const V2*)(ft + v.fw);
+  const V2* Fbw = (const V2*)(ft + v.bw);
   double f[4][16];
 
   // partial sums of this thread's item over its half of the inner index
@@ -470,7 +480,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   };
 
   // ---- forward: Lu y = f
-  frag_load(Ffw, 0, nthr, 0, -1, s, tid, f);
+  frag_load<T>(Ffw, 0, nthr, 0, -1, s, tid, f);
   for (int I = 0; I < NT; ++I) {
     const int smax = min(BT - 1, I);
     double fv = 0.0;
@@ -478,9 +488,13 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
       const int dof = band_to_dof(v, bm, I * 32 + rr);
       if (dof >= 0 && colok && dof_active(kind, cl[dof])) fv = vin[(int64_t)dof * ldk + col];
     }
-    const double2* dp = (const double2*)(L + (int64_t)I * BT * MSG_TILE2);
-    const double2 d0 = red ? dp[2 * tid] : make_double2(0.0, 0.0);
-    const double2 d1 = red ? dp[2 * tid + 1] : make_double2(0.0, 0.0);
+    const V2* dp = (const V2*)(ft + v.off + (int64_t)I * BT * MSG_TILE2);
+    double2 d0 = make_double2(0.0, 0.0), d1 = make_double2(0.0, 0.0);
+    if (red) {
+      const V2 a = dp[2 * tid], b = dp[2 * tid + 1];
+      d0 = make_double2(a.x, a.y);
+      d1 = make_double2(b.x, b.y);
+    }
     // w_{I-1} = D^{-1}_{I-1} y_{I-1} (Dl and its ring slot were completed last step)
     if (red && I >= 1) {
       const double* yp = ring + (int64_t)((I - 1) % BT) * 32 * KC;
@@ -494,7 +508,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     if (has) accumulate(ring + (int64_t)((I - s) % BT) * 32 * KC, acc);
     store_part(has, acc);
     // fragment of the next step, in flight during the reduction
-    if (I + 1 < NT) frag_load(Ffw, I + 1, nthr, min(BT - 1, I + 1), -1, s, tid, f);
+    if (I + 1 < NT) frag_load<T>(Ffw, I + 1, nthr, min(BT - 1, I + 1), -1, s, tid, f);
     __syncthreads();
     if (red) {
       const int e = 4 * tid;
@@ -526,7 +540,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   __syncthreads();
 
   // ---- backward: Lu^T x = w
-  frag_load(Fbw, NT - 1, nthr, 0, +1, s, tid, f);
+  frag_load<T>(Fbw, NT - 1, nthr, 0, +1, s, tid, f);
   for (int I = NT - 1; I >= 0; --I) {
     const int smax = min(BT - 1, NT - 1 - I);
     const int row = I * 32 + rr;
@@ -535,7 +549,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     const bool has = s <= smax;
     if (has) accumulate(ring + (int64_t)((I + s) % BT) * 32 * KC, acc);
     store_part(has, acc);
-    if (I - 1 >= 0) frag_load(Fbw, I - 1, nthr, min(BT - 1, NT - I), +1, s, tid, f);
+    if (I - 1 >= 0) frag_load<T>(Fbw, I - 1, nthr, min(BT - 1, NT - I), +1, s, tid, f);
     __syncthreads();
     if (red) {
       double sum = 0.0;
@@ -566,8 +580,38 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   }
 }
 
-template __global__ void k_band_solve<8>(const BoxMeta*, int, int, int, const double*, const uint8_t*,
-                                         const double*, double*, int, int, int, double*, int64_t,
-                                         const int32_t*);
+template __global__ void k_band_solve<8, double>(const BoxMeta*, int, int, int, const double*, const double*,
+                                                 const uint8_t*, const double*, double*, int, int, int, double*,
+                                                 int64_t, const int32_t*);
+template __global__ void k_band_solve<8, float>(const BoxMeta*, int, int, int, const double*, const float*,
+                                                const uint8_t*, const double*, double*, int, int, int, double*,
+                                                int64_t, const int32_t*);
+
+// FP32 copies for the mixed path (same element offsets as the FP64 arrays):
+// the two solve-ordered band copies and the D^{-1} diagonal tiles of both box
+// matrices (grid.y = box, grid.z = matrix kind), and the stencil
+// (grid.z = 2).
+__global__ void k_mixed_copies(const BoxMeta* __restrict__ meta, const double* __restrict__ fac,
+                               float* __restrict__ fac32, const double* __restrict__ stencil,
+                               float* __restrict__ stencil32) {
+  const BoxMeta& bm = meta[blockIdx.y];
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, st = (int64_t)gridDim.x * blockDim.x;
+  if (blockIdx.z == 2) {
+    const int64_t o = bm.node_off * 243, n = (int64_t)bm.n_nodes * 243;
+    for (int64_t e = t0; e < n; e += st) stencil32[o + e] = (float)stencil[o + e];
+    return;
+  }
+  BandView v = band_view(bm, blockIdx.z);
+  const int64_t nb = (int64_t)v.NT * 64 * solve_nthr(v.BT);
+  for (int64_t e = t0; e < nb; e += st) {
+    fac32[v.fw + e] = (float)fac[v.fw + e];
+    fac32[v.bw + e] = (float)fac[v.bw + e];
+  }
+  const int64_t nd = (int64_t)v.NT * MSG_TILE2;
+  for (int64_t e = t0; e < nd; e += st) {
+    const int64_t o = v.off + (e >> 10) * v.BT * MSG_TILE2 + (e & 1023);
+    fac32[o] = (float)fac[o];
+  }
+}
 
 }  // namespace msg

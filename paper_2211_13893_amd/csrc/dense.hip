@@ -691,4 +691,12 @@ __global__ __launch_bounds__(256) void k_output(const BoxMeta* __restrict__ meta
   }
 }
 
+// X <- X on the DoFs whose class bit is set in classes, 0 elsewhere
+// (flat over all boxes' [n_dof][k] blocks)
+__global__ void k_keep_classes(const uint8_t* __restrict__ cls, int classes, int k, int64_t n,
+                               double* __restrict__ X) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    if (!((classes >> cls[e / k]) & 1)) X[e] = 0.0;
+}
+
 }  // namespace msg

@@ -11,7 +11,8 @@
 // One thread per (node, CW consecutive columns): the 243 stencil values of a
 // node are read once per CW columns (structure of arrays, coalesced across
 // nodes), the rows of X in 16-byte pieces.  With Y2, mu of the neighbour DoF
-// is folded into the stencil value.  Blocks are ordered box-major per XCD
+// is folded into the stencil value.  ST is the stencil's storage precision
+// (double, or float in the mixed path); arithmetic is FP64.  Blocks are ordered box-major per XCD
 // (block x runs on XCD x mod 8): XCD c takes every block of box c, then of
 // box c + 8, ..., so the 27-point neighbourhoods of a box come from that
 // XCD's L2 while it works on the box.
@@ -42,10 +43,10 @@ __device__ inline void load_cols(const double* __restrict__ x, int64_t d, int k,
   }
 }
 
-template <bool TWO, int CW>
+template <bool TWO, int CW, typename ST>
 __global__ __launch_bounds__(256) void k_spmm(const BoxMeta* __restrict__ meta, int n_box,
                                               int blocks_per_box,
-                                              const double* __restrict__ stencil,
+                                              const ST* __restrict__ stencil,
                                               const uint8_t* __restrict__ cls,
                                               const double* __restrict__ mu1,
                                               const double* __restrict__ X, double* Y,
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(256) void k_spmm(const BoxMeta* __restrict__ meta, 
   const int node = (int)(t / nq), q = (int)(t % nq);
   const int c0 = CW * q;
   const int li = node % bm.mx, lj = (node / bm.mx) % bm.my, lk = node / (bm.mx * bm.my);
-  const double* st = stencil + bm.node_off * 243 + node;
+  const ST* st = stencil + bm.node_off * 243 + node;
   const uint8_t* cl = cls + bm.dof_off;
   const double* m1 = mu1 + bm.dof_off;
   const double* x = X + (bm.dof_off * k);
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void k_spmm(const BoxMeta* __restrict__ meta, 
         for (int cr = 0; cr < 3; ++cr)
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc) {
-            const double a = st[(int64_t)(nb * 9 + 3 * cr + cc) * bm.n_nodes];
+            const double a = (double)st[(int64_t)(nb * 9 + 3 * cr + cc) * bm.n_nodes];
             const double am = a * mu[cc];
 #pragma unroll
             for (int j = 0; j < CW; ++j) {
@@ -127,12 +128,24 @@ __global__ __launch_bounds__(256) void k_spmm(const BoxMeta* __restrict__ meta, 
   }
 }
 
-template __global__ void k_spmm<false, 8>(const BoxMeta*, int, int, const double*, const uint8_t*, const double*,
-                                          const double*, double*, double*, int, int, double, const int32_t*);
-template __global__ void k_spmm<false, 1>(const BoxMeta*, int, int, const double*, const uint8_t*, const double*,
-                                          const double*, double*, double*, int, int, double, const int32_t*);
-template __global__ void k_spmm<true, 4>(const BoxMeta*, int, int, const double*, const uint8_t*, const double*,
-                                         const double*, double*, double*, int, int, double, const int32_t*);
+template __global__ void k_spmm<false, 8, double>(const BoxMeta*, int, int, const double*, const uint8_t*,
+                                                   const double*, const double*, double*, double*, int, int, double,
+                                                   const int32_t*);
+template __global__ void k_spmm<false, 8, float>(const BoxMeta*, int, int, const float*, const uint8_t*,
+                                                   const double*, const double*, double*, double*, int, int, double,
+                                                   const int32_t*);
+template __global__ void k_spmm<false, 1, double>(const BoxMeta*, int, int, const double*, const uint8_t*,
+                                                   const double*, const double*, double*, double*, int, int, double,
+                                                   const int32_t*);
+template __global__ void k_spmm<false, 1, float>(const BoxMeta*, int, int, const float*, const uint8_t*,
+                                                   const double*, const double*, double*, double*, int, int, double,
+                                                   const int32_t*);
+template __global__ void k_spmm<true, 4, double>(const BoxMeta*, int, int, const double*, const uint8_t*,
+                                                   const double*, const double*, double*, double*, int, int, double,
+                                                   const int32_t*);
+template __global__ void k_spmm<true, 4, float>(const BoxMeta*, int, int, const float*, const uint8_t*,
+                                                   const double*, const double*, double*, double*, int, int, double,
+                                                   const int32_t*);
 
 // out = X with the rows of B3 DoFs cleared (flat over all boxes' [n_dof][k] blocks)
 __global__ void k_mask_b3(const uint8_t* __restrict__ cls, const double* __restrict__ X, int k, int64_t n,

@@ -140,7 +140,7 @@ class LocalStage:
     def __init__(self, problem, batch: Optional[Sequence[int]] = None,
                  n_ev: Optional[Sequence[int]] = None, device: str = "cuda:0", shift: float = 1.0,
                  tol: float = 1e-6, maxit: int = 200, block: int = 0, seed: int = 1234,
-                 geneo: bool = False):
+                 geneo: bool = False, precision: int = 0):
         import torch
         self.torch = torch
         lib = load()
@@ -163,7 +163,8 @@ class LocalStage:
         self._cores = np.ascontiguousarray(p.cores, dtype=np.int32)
         self._ovs = np.ascontiguousarray(p.ovs, dtype=np.int32)
         dec = msgfem_decomp(p.nsd, self._cores.ctypes.data, p.overlap, self._ovs.ctypes.data)
-        opts = msgfem_eig_opts(shift, tol, maxit, block, 0, 1 if geneo else 0, seed)
+        opts = msgfem_eig_opts(shift, tol, maxit, block, precision, 1 if geneo else 0, seed)
+        self.precision = precision
         self.geneo = geneo
         self.shift = shift
         plan = _P()

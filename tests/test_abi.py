@@ -89,3 +89,10 @@ def test_plan_rejects_bad_arguments():
     lib, plan, rc, _ = _plan(prob, precision=5)
     assert rc == msgfem.MSGFEM_EARG
     lib.msgfem_plan_destroy(plan)
+    # an empty batch and an odd block width are refused
+    lib, plan, rc, _ = _plan(prob, batch=[], n_ev=[])
+    assert rc == msgfem.MSGFEM_EARG
+    lib.msgfem_plan_destroy(plan)
+    lib, plan, rc, _ = _plan(prob, block=13)
+    assert rc == msgfem.MSGFEM_EARG
+    lib.msgfem_plan_destroy(plan)
