@@ -251,6 +251,39 @@ def uniform_batch(n_boxes: int = 64, core: int = 8, overlap: int = 1, ovs: int =
                    cores, overlap, np.full(nsd, ovs, np.int32), np.full(nsd, n_ev, np.int32), batch)
 
 
+def warm_start_batch(n_boxes: int = 64, seed: int = 0, wrinkle_max: float = 0.8,
+                     modulus_spread: float = 0.2, homogeneous: bool = False, core: int = 8,
+                     overlap: int = 1, ovs: int = 2, n_ev: int = 16, h_xy: float = 0.25) -> Problem:
+    """Training / held-out boxes of the learned warm start: the uniform batch's
+    14^3 interior boxes of a ply/resin laminate, plus a Gaussian ply wrinkle of
+    amplitude U[0, wrinkle_max] ply thicknesses (sigma 8 elements, random
+    centre) and one log-uniform modulus factor in [1/(1+spread), 1+spread] per
+    layer.  With ``homogeneous`` every element is one isotropic material on
+    the same node grid (the reference box of the coefficient basis)."""
+    rng = _rng(4, seed)
+    nx = ny = 3 * core
+    nz = (n_boxes + 2) * core
+    kinds, angles, zs = _ply_resin_stack(rng, nz, 0.25, 0.05)
+    xyz = _grid_xyz(h_xy * np.arange(nx + 1), h_xy * np.arange(ny + 1), zs)
+    lo, hi = np.log(1.0 / (1.0 + modulus_spread)), np.log(1.0 + modulus_spread)
+    scale = np.exp(rng.uniform(lo, hi, size=nz))
+    amp = float(rng.uniform(0.0, wrinkle_max)) * 0.25
+    xc, yc = rng.uniform(0.0, nx * h_xy), rng.uniform(0.0, ny * h_xy)
+    _apply_wrinkle(xyz, amp, 8.0 * h_xy, xc, yc)
+    if homogeneous:
+        mats = np.asarray([list(isotropic_constants(10000.0, 0.3)) + [0.0]], dtype=np.float64)
+        elem_mat = np.zeros(nx * ny * nz, dtype=np.int32)
+    else:
+        mats = _layered_materials(kinds, angles, scale)
+        elem_mat = _elem_mat_by_layer(nx, ny, nz)
+    cores = _tiles(nx, ny, nz, (core, core, core))
+    batch = np.asarray([1 + 3 * (1 + 3 * t) for t in range(1, n_boxes + 1)], dtype=np.int32)
+    nsd = cores.shape[0]
+    return Problem("warm_start_batch", nx, ny, nz, xyz, elem_mat, mats,
+                   np.zeros(3 * (nx + 1) * (ny + 1) * (nz + 1), np.uint8), [],
+                   cores, overlap, np.full(nsd, ovs, np.int32), np.full(nsd, n_ev, np.int32), batch)
+
+
 def _random_cuts(rng: np.random.Generator, n: int, lo: int, hi: int) -> List[int]:
     cuts = [0]
     while cuts[-1] < n:
