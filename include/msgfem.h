@@ -262,6 +262,93 @@ int msgfem_profile(msgfem_plan *plan, int32_t enable);
 int msgfem_profile_stats(msgfem_plan *plan, msgfem_kernel_stat *out, int32_t max_out,
                          int32_t *n_out);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start of msgfem_local_eigs (an addition to the method: the
+ * paper starts its local eigensolves without prior information).  A small
+ * 3D CNN maps the element field of an oversampled box to coefficients C
+ * (ng x ne, row-major) of its first ne start vectors in a basis G of ng
+ * vectors on B2, the lowest A-harmonic eigenvectors of a homogeneous
+ * isotropic reference box of the same node grid (Sec. 4.3 GEVP) made
+ * orthonormal on B2.  The start block is X0[:, e] = G C[:, e] on B2 for
+ * e < ne and seeded Gaussian columns for e >= ne.  Every call here needs a
+ * batch whose boxes share one node grid (MSGFEM_EARG otherwise), ops
+ * assembled by msgfem_assemble_local, and is asynchronous on `stream`.
+ * ------------------------------------------------------------------------ */
+
+/* Network input of every box: feat (device float[n_box][6][ez][ey][ex],
+ * ex = mx - 1 elements along x, ...) with channels, per element, cos 2 theta,
+ * sin 2 theta (ply angle), 1 for a ply and 0 for resin (E1 != E2),
+ * (ln E1 - ln 1e4) / 2.5 with E1 in MPa, and 2.5 times the mean slopes
+ * dz/dx and dz/dy of the element's edges along x and y. */
+int msgfem_warm_features(msgfem_plan *plan, const void *ops, float *feat, void *stream);
+
+/* Basis G (device double[n_dof][ng], n_dof of box 0) from the eigenvectors
+ * `evecs` that msgfem_local_eigs returned for this plan: the B2 parts of the
+ * first ng eigenvectors of box 0 (lambda ascending), orthonormalised over
+ * B2 by Gram-Schmidt applied twice; zero rows off B2.  1 <= ng <= n_ev of
+ * box 0. */
+int msgfem_warm_basis(msgfem_plan *plan, const void *ops, const double *evecs, int32_t ng, double *G,
+                      void *stream);
+
+/* Training labels: P (device float[n_box][ng][ng]) = Q Q^T with Q an
+ * orthonormal basis (Gram-Schmidt, twice) of G^T X_b, X_b the B2 parts of
+ * the first ne eigenvectors of box b in `evecs` (msgfem_local_eigs of this
+ * plan); the projector onto the best ne-dimensional approximation of the
+ * box's eigenspace in span(G).  G: from msgfem_warm_basis of a box with
+ * n_dof_g DoFs, which every box here must have.  Needs ne <= ng,
+ * ne <= n_ev and ng * ne <= 8192. */
+int msgfem_warm_labels(msgfem_plan *plan, const void *ops, const double *evecs, const double *G,
+                       int32_t n_dof_g, int32_t ng, int32_t ne, float *P, void *stream);
+
+/* Start block for msgfem_local_eigs: x0 (device double, box layout
+ * [n_dof][k] at vec_off, k the plan's block width) = G coef on B2 for the
+ * first ne columns, Gaussian columns from (seed, box, DoF, column)
+ * otherwise, 0 off B2.  coef: device float[n_box][ng][ne] (network output).
+ * A predicted column that is zero or not finite is replaced by a Gaussian
+ * column (the fallback to the random start).  0 <= ne <= k. */
+int msgfem_warm_start(msgfem_plan *plan, const void *ops, const float *coef, const double *G,
+                      int32_t n_dof_g, int32_t ng, int32_t ne, uint64_t seed, double *x0, void *stream);
+
+/* The network: four 3x3x3 convolutions (zero padding 1, strides 1, 1, 2, 2,
+ * each followed by ReLU; cin -> width -> width -> width -> width channels)
+ * on a d^3 grid, a mean over the last grid, and an affine map to n_out
+ * values.  params (device float, n_params): conv weights [width][c_in][27]
+ * (tap 9p + 3q + r for the offsets (p-1, q-1, r-1) along z, y, x) and
+ * biases of the four layers in order, then the affine weights
+ * [n_out][width] and biases [n_out].  Activations and conv weights are held
+ * in BF16 (bf16 != 0, rounded to nearest even) or FP32; every sum is FP32.
+ * work: device, work_bytes (from msgfem_cnn_sizes for this batch size),
+ * holds the activations between msgfem_cnn_forward and msgfem_cnn_backward
+ * (same params, batch and bf16). */
+int msgfem_cnn_sizes(int32_t cin, int32_t width, int32_t n_out, int32_t d, int32_t batch,
+                     int64_t *n_params, int64_t *work_bytes);
+
+/* out (device float[batch][n_out]) for x (device float[batch][cin][d][d][d]). */
+int msgfem_cnn_forward(const float *params, int32_t cin, int32_t width, int32_t n_out, int32_t d,
+                       int32_t batch, int32_t bf16, const float *x, float *out, void *work,
+                       void *stream);
+
+/* grads (device float, n_params, overwritten) of sum(gout * out) with
+ * respect to params, from the activations the last msgfem_cnn_forward left
+ * in work; the sums over the batch run in a fixed order. */
+int msgfem_cnn_backward(const float *params, int32_t cin, int32_t width, int32_t n_out, int32_t d,
+                        int32_t batch, int32_t bf16, const float *gout, float *grads, void *work,
+                        void *stream);
+
+/* Subspace loss of out viewed as c_b (ng x ne) against the label projectors
+ * P_b: loss[b] = |c_b c_b^T - P_b|_F^2 and gout[b] = gscale * 4 (c_b c_b^T -
+ * P_b) c_b, its gradient times gscale (1/batch for the mean loss; device
+ * float arrays).  It depends on c_b only through c_b c_b^T, so any
+ * orthonormal basis of the label subspace has zero loss.  Needs
+ * (ng*ne + ng*ng + 256) * 4 <= 65536. */
+int msgfem_cnn_loss(const float *out, const float *labels, int32_t ng, int32_t ne, int32_t batch,
+                    float gscale, float *loss, float *gout, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1)
+ * on params with gradient grads and moments m, v (device float, n). */
+int msgfem_cnn_adam(float *params, const float *grads, float *m, float *v, int64_t n, int32_t step,
+                    float lr, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,13 @@ Layouts (all float64 NumPy):
   lin  w [n_out, C_last], b [n_out]
 Output size of a stride-s convolution with padding 1: (D - 1) // s + 1.
 
+BF16 storage (``bf16=True``): the input, the convolution weights and every
+stored activation are rounded to bfloat16 (8 significant bits, round to
+nearest, ties to even) and the sums are exact (FP64); biases, the pooled
+vector and the affine map stay unrounded.  The gradient is the one of that
+rounded network with respect to the unrounded parameters (the rounding is
+passed straight through).
+
 Only tests/, __graft_entry__.smoke() and bench.py's CPU baseline use this
 module; the library never calls it.
 """
@@ -27,6 +34,14 @@ STRIDES = (1, 1, 2, 2)
 
 def out_size(d: int, stride: int) -> int:
     return (d - 1) // stride + 1
+
+
+def bf16(x: np.ndarray) -> np.ndarray:
+    """Round to the nearest bfloat16 value (ties to even), as float64.
+    x = m 2^e with 0.5 <= |m| < 1; bfloat16 keeps 8 significant bits of m."""
+    x = np.asarray(x, dtype=np.float64)
+    m, e = np.frexp(x)
+    return np.ldexp(np.rint(m * 256.0) / 256.0, e)
 
 
 def conv3d(x: np.ndarray, w: np.ndarray, b: np.ndarray, stride: int) -> np.ndarray:
@@ -83,20 +98,31 @@ def init_params(c_in: int, width: int, n_out: int, seed: int) -> Dict[str, np.nd
     return p
 
 
-def forward(p: Dict[str, np.ndarray], x: np.ndarray) -> Tuple[np.ndarray, List[np.ndarray]]:
+def _stored(p: Dict[str, np.ndarray], use_bf16: bool) -> Dict[str, np.ndarray]:
+    if not use_bf16:
+        return p
+    return {k: (bf16(v) if k in ("w0", "w1", "w2", "w3") else v) for k, v in p.items()}
+
+
+def forward(p: Dict[str, np.ndarray], x: np.ndarray, use_bf16: bool = False
+            ) -> Tuple[np.ndarray, List[np.ndarray]]:
     """Network output [B, n_out] and the activations needed by backward."""
-    acts = [x]
-    h = x
+    q = _stored(p, use_bf16)
+    rnd = bf16 if use_bf16 else (lambda a: a)
+    h = rnd(x)
+    acts = [h]
     for l, s in enumerate(STRIDES):
-        h = np.maximum(conv3d(h, p[f"w{l}"], p[f"b{l}"], s), 0.0)
+        h = rnd(np.maximum(conv3d(h, q[f"w{l}"], q[f"b{l}"], s), 0.0))
         acts.append(h)
     g = h.mean(axis=(2, 3, 4))
     acts.append(g)
     return g @ p["wl"].T + p["bl"], acts
 
 
-def backward(p: Dict[str, np.ndarray], acts: Sequence[np.ndarray], gout: np.ndarray) -> Dict[str, np.ndarray]:
+def backward(p: Dict[str, np.ndarray], acts: Sequence[np.ndarray], gout: np.ndarray,
+             use_bf16: bool = False) -> Dict[str, np.ndarray]:
     """Gradients of sum(gout * forward(p, x)) with respect to every parameter."""
+    p = _stored(p, use_bf16)
     grads: Dict[str, np.ndarray] = {}
     g = acts[-1]
     grads["wl"] = gout.T @ g

@@ -86,6 +86,11 @@ __global__ void k_pcg_xr(const uint8_t*, int64_t, const double*, const double*, 
                          double*);
 __global__ void k_pcg_p(const uint8_t*, int64_t, const double*, const double*, double*);
 __global__ void k_sub(const uint8_t*, int64_t, const double*, const double*, double*);
+__global__ void k_warm_features(const BoxMeta*, MeshDev, float*);
+__global__ void k_warm_basis(const BoxMeta*, const uint8_t*, const double*, int, int, double*);
+__global__ void k_warm_labels(const BoxMeta*, const uint8_t*, const double*, const double*, int, int, float*);
+__global__ void k_warm_start(const BoxMeta*, const uint8_t*, const float*, const double*, int, int, int, uint64_t,
+                             double*);
 }  // namespace msg
 
 using namespace msg;
@@ -1465,5 +1470,71 @@ extern "C" int msgfem_geneo_pcg(msgfem_plan* p, const void* ops, void* work, voi
     int32_t one = 1;
     HIPCHK(p, hipMemcpy(status, &one, 4, hipMemcpyHostToDevice));
   }
+  return MSGFEM_OK;
+}
+
+// ------------------------------------------------------------ warm start
+// every box of the batch has the node grid of box 0 (and so its DoF count)
+static bool same_boxes(const msgfem_plan* p) {
+  const BoxMeta& a = p->meta[0];
+  for (const BoxMeta& b : p->meta)
+    if (b.mx != a.mx || b.my != a.my || b.mz != a.mz) return false;
+  return true;
+}
+
+extern "C" int msgfem_warm_features(msgfem_plan* p, const void* ops, float* feat, void* stream) {
+  if (!p || !ops || !feat) return fail(p, MSGFEM_EARG, "null argument");
+  if (!same_boxes(p)) return fail(p, MSGFEM_EARG, "warm start needs boxes of one node grid");
+  if (set_device(p)) return MSGFEM_EHIP;
+  OpsView v = ops_view(p, ops);
+  const BoxMeta& a = p->meta[0];
+  const int ne = (a.mx - 1) * (a.my - 1) * (a.mz - 1);
+  k_warm_features<<<dim3((ne + 255) / 256, (unsigned)p->meta.size()), 256, 0, (hipStream_t)stream>>>(
+      v.meta, mesh_dev(p), feat);
+  LAUNCHCHK(p);
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_warm_basis(msgfem_plan* p, const void* ops, const double* evecs, int32_t ng, double* G,
+                                 void* stream) {
+  if (!p || !ops || !evecs || !G) return fail(p, MSGFEM_EARG, "null argument");
+  const BoxMeta& a = p->meta[0];
+  if (ng < 1 || ng > a.n_ev) return fail(p, MSGFEM_EARG, "ng must be in [1, n_ev of box 0 = %d]", a.n_ev);
+  if (set_device(p)) return MSGFEM_EHIP;
+  OpsView v = ops_view(p, ops);
+  k_warm_basis<<<1, 1024, 0, (hipStream_t)stream>>>(v.meta, v.cls, evecs + a.evec_off, a.n_ev, ng, G);
+  LAUNCHCHK(p);
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_warm_labels(msgfem_plan* p, const void* ops, const double* evecs, const double* G,
+                                  int32_t n_dof_g, int32_t ng, int32_t ne, float* P, void* stream) {
+  if (!p || !ops || !evecs || !G || !P) return fail(p, MSGFEM_EARG, "null argument");
+  if (!same_boxes(p) || p->meta[0].n_dof != n_dof_g)
+    return fail(p, MSGFEM_EARG, "every box must have the %d DoFs of the basis", n_dof_g);
+  for (const BoxMeta& b : p->meta)
+    if (ne < 1 || ne > b.n_ev) return fail(p, MSGFEM_EARG, "ne must be in [1, n_ev]");
+  if (ng < ne || (int64_t)ng * ne * 8 > 64 * 1024) return fail(p, MSGFEM_EARG, "need ne <= ng, ng*ne <= 8192");
+  if (set_device(p)) return MSGFEM_EHIP;
+  OpsView v = ops_view(p, ops);
+  k_warm_labels<<<(unsigned)p->meta.size(), 256, (size_t)ng * ne * 8, (hipStream_t)stream>>>(v.meta, v.cls, evecs,
+                                                                                            G, ng, ne, P);
+  LAUNCHCHK(p);
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_warm_start(msgfem_plan* p, const void* ops, const float* coef, const double* G,
+                                 int32_t n_dof_g, int32_t ng, int32_t ne, uint64_t seed, double* x0,
+                                 void* stream) {
+  if (!p || !ops || !coef || !G || !x0) return fail(p, MSGFEM_EARG, "null argument");
+  if (!same_boxes(p) || p->meta[0].n_dof != n_dof_g)
+    return fail(p, MSGFEM_EARG, "every box must have the %d DoFs of the basis", n_dof_g);
+  if (ng < 1 || ne < 0 || ne > p->k) return fail(p, MSGFEM_EARG, "need ng >= 1 and 0 <= ne <= block %d", p->k);
+  if (set_device(p)) return MSGFEM_EHIP;
+  OpsView v = ops_view(p, ops);
+  const int64_t n = (int64_t)n_dof_g * p->k;
+  k_warm_start<<<dim3((unsigned)((n + 255) / 256), (unsigned)p->meta.size()), 256, 0, (hipStream_t)stream>>>(
+      v.meta, v.cls, coef, G, ng, ne, p->k, seed, x0);
+  LAUNCHCHK(p);
   return MSGFEM_OK;
 }

@@ -88,6 +88,18 @@ SIGNATURES = {
     "msgfem_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "msgfem_profile_stats": (ctypes.c_int, [_P, ctypes.POINTER(msgfem_kernel_stat), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
+    "msgfem_warm_features": (ctypes.c_int, [_P, _P, _P, _P]),
+    "msgfem_warm_basis": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P]),
+    "msgfem_warm_labels": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          _P, _P]),
+    "msgfem_warm_start": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_uint64, _P, _P]),
+    "msgfem_cnn_sizes": (ctypes.c_int, [ctypes.c_int32] * 5 + [ctypes.POINTER(ctypes.c_int64)] * 2),
+    "msgfem_cnn_forward": (ctypes.c_int, [_P] + [ctypes.c_int32] * 6 + [_P, _P, _P, _P]),
+    "msgfem_cnn_backward": (ctypes.c_int, [_P] + [ctypes.c_int32] * 6 + [_P, _P, _P, _P]),
+    "msgfem_cnn_loss": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                       _P, _P, _P]),
+    "msgfem_cnn_adam": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, _P]),
 }
 
 _lib = None
@@ -321,6 +333,47 @@ class LocalStage:
                                            bytes=arr[i].bytes, flops=arr[i].flops)
                 for i in range(min(n.value, 16))}
 
+    # -- learned warm start ---------------------------------------------
+    def msgfem_warm_features(self):
+        """Network input [n_box, 6, ez, ey, ex] (float32) of every box."""
+        torch = self.torch
+        bi = self.boxes[0]
+        feat = torch.empty((len(self.batch), 6, bi.mz - 1, bi.my - 1, bi.mx - 1), dtype=torch.float32,
+                           device=self.device)
+        rc = self.lib.msgfem_warm_features(self.plan, _ptr(self.ops), _ptr(feat),
+                                           _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_warm_features")
+        return feat
+
+    def msgfem_warm_basis(self, eig_out, ng: int):
+        """Basis G [n_dof, ng] (float64) from box 0's eigenvectors."""
+        torch = self.torch
+        G = torch.empty((self.boxes[0].n_dof, ng), dtype=torch.float64, device=self.device)
+        rc = self.lib.msgfem_warm_basis(self.plan, _ptr(self.ops), _ptr(eig_out["evecs"]), ng, _ptr(G),
+                                        _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_warm_basis")
+        return G
+
+    def msgfem_warm_labels(self, eig_out, G, ne: int):
+        """Label projectors [n_box, ng, ng] (float32)."""
+        torch = self.torch
+        ng = G.shape[1]
+        P = torch.empty((len(self.batch), ng, ng), dtype=torch.float32, device=self.device)
+        rc = self.lib.msgfem_warm_labels(self.plan, _ptr(self.ops), _ptr(eig_out["evecs"]), _ptr(G.contiguous()),
+                                         G.shape[0], ng, ne, _ptr(P), _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_warm_labels")
+        return P
+
+    def msgfem_warm_start(self, coef, G, ne: int, seed: int = 0):
+        """Start block (flat [sum n_dof * k], float64) for msgfem_local_eigs."""
+        torch = self.torch
+        x0 = self.new_block()
+        rc = self.lib.msgfem_warm_start(self.plan, _ptr(self.ops), _ptr(coef.contiguous()), _ptr(G.contiguous()),
+                                        G.shape[0], G.shape[1], ne, seed, _ptr(x0),
+                                        _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_warm_start")
+        return x0
+
     # -- views ---------------------------------------------------------
     def stencil(self, b: int):
         bi = self.boxes[b]
@@ -356,3 +409,58 @@ class LocalStage:
     def resid(self, out, b: int):
         bi = self.boxes[b]
         return out["resid"][bi.eval_off:bi.eval_off + bi.n_ev]
+
+
+# -- the warm-start network (plan-independent) ---------------------------------
+def msgfem_cnn_sizes(cin: int, width: int, n_out: int, d: int, batch: int):
+    """(n_params, work_bytes) of the network for this batch size."""
+    n = ctypes.c_int64()
+    w = ctypes.c_int64()
+    _check(load().msgfem_cnn_sizes(cin, width, n_out, d, batch, ctypes.byref(n), ctypes.byref(w)), None,
+           "msgfem_cnn_sizes")
+    return n.value, w.value
+
+
+def _dev_stream(t):
+    import torch
+    return _stream_handle(torch, t.device)
+
+
+def msgfem_cnn_forward(params, cin: int, width: int, n_out: int, x, bf16: bool, work):
+    """Network output [batch, n_out] (float32) for x [batch, cin, d, d, d]."""
+    import torch
+    b, d = x.shape[0], x.shape[2]
+    out = torch.empty((b, n_out), dtype=torch.float32, device=x.device)
+    rc = load().msgfem_cnn_forward(_ptr(params), cin, width, n_out, d, b, 1 if bf16 else 0,
+                                   _ptr(x.contiguous()), _ptr(out), _ptr(work), _dev_stream(x))
+    _check(rc, None, "msgfem_cnn_forward")
+    return out
+
+
+def msgfem_cnn_backward(params, cin: int, width: int, n_out: int, d: int, gout, bf16: bool, work):
+    """Parameter gradient (float32, n_params) of sum(gout * out)."""
+    import torch
+    grads = torch.empty_like(params)
+    rc = load().msgfem_cnn_backward(_ptr(params), cin, width, n_out, d, gout.shape[0], 1 if bf16 else 0,
+                                    _ptr(gout.contiguous()), _ptr(grads), _ptr(work), _dev_stream(gout))
+    _check(rc, None, "msgfem_cnn_backward")
+    return grads
+
+
+def msgfem_cnn_loss(out, labels, ng: int, ne: int, gscale: float = 1.0):
+    """(loss per sample [batch], gscale * its gradient [batch, ng*ne])."""
+    import torch
+    b = out.shape[0]
+    loss = torch.empty(b, dtype=torch.float32, device=out.device)
+    gout = torch.empty_like(out)
+    rc = load().msgfem_cnn_loss(_ptr(out.contiguous()), _ptr(labels.contiguous()), ng, ne, b, gscale,
+                                _ptr(loss), _ptr(gout), _dev_stream(out))
+    _check(rc, None, "msgfem_cnn_loss")
+    return loss, gout
+
+
+def msgfem_cnn_adam(params, grads, m, v, step: int, lr: float):
+    """One Adam step, in place on params, m and v."""
+    rc = load().msgfem_cnn_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(), step, lr,
+                                _dev_stream(params))
+    _check(rc, None, "msgfem_cnn_adam")

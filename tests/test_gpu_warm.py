@@ -1,0 +1,231 @@
+"""GPU checks of the learned warm start (through the C ABI).
+
+Network kernels against the FP64 reference network of oracle/cnn.py on the
+same parameters and inputs:
+  * FP32 storage: outputs and every parameter gradient within 1e-5 relative
+    (L2 over a parameter group; FP32 sums of at most ~2e4 terms, unit
+    roundoff 6e-8);
+  * BF16 storage, against the reference with the same BF16 rounding points:
+    relative 2e-3 (the sums differ in FP32 rounding only, except where a
+    stored value sits on a BF16 rounding boundary and the two sides round it
+    to neighbours 2^-8 apart).
+Loss and Adam against their definitions.  Basis, labels and start block
+against NumPy on copies of the library's own eigenvectors (properties that
+fix them: orthonormality, projector identities, the formula of the block).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cnn
+from paper_2211_13893_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a GPU"
+    return T
+
+
+def _unflatten(flat, cin, width, n_out):
+    p, off, c = {}, 0, cin
+    for l in range(4):
+        n = width * c * 27
+        p[f"w{l}"] = flat[off:off + n].reshape(width, c, 3, 3, 3)
+        off += n
+        p[f"b{l}"] = flat[off:off + width]
+        off += width
+        c = width
+    p["wl"] = flat[off:off + n_out * width].reshape(n_out, width)
+    off += n_out * width
+    p["bl"] = flat[off:off + n_out]
+    off += n_out
+    assert off == flat.size
+    return p
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+@pytest.mark.parametrize("d", [6, 9])
+def test_cnn_matches_oracle(torch, bf16, d):
+    from paper_2211_13893_amd import msgfem, warm
+    say(f"[cnn] bf16={bf16} d={d}")
+    cin, width, n_out, B = 6, 8, 12, 3
+    rng = np.random.default_rng(10 + d)
+    flat = warm.init_params(cin, width, n_out, seed=d).astype(np.float64)
+    flat += 0.05 * rng.standard_normal(flat.size)        # nonzero biases
+    flat = flat.astype(np.float32)
+    x = rng.standard_normal((B, cin, d, d, d)).astype(np.float32)
+    gout = rng.standard_normal((B, n_out)).astype(np.float32)
+    n_params, wb = msgfem.msgfem_cnn_sizes(cin, width, n_out, d, B)
+    assert n_params == flat.size
+    dev = torch.device("cuda:0")
+    P = torch.as_tensor(flat, device=dev)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    out = msgfem.msgfem_cnn_forward(P, cin, width, n_out, torch.as_tensor(x, device=dev), bf16, work)
+    grads = msgfem.msgfem_cnn_backward(P, cin, width, n_out, d, torch.as_tensor(gout, device=dev), bf16, work)
+    torch.cuda.synchronize()
+    p = _unflatten(flat.astype(np.float64), cin, width, n_out)
+    ref, acts = cnn.forward(p, x.astype(np.float64), use_bf16=bf16)
+    gref = cnn.backward(p, acts, gout.astype(np.float64), use_bf16=bf16)
+    tol = 2e-3 if bf16 else 1e-5
+    e = _rel(out.cpu().numpy().astype(np.float64), ref)
+    say(f"  out rel {e:.2e}")
+    assert e <= tol
+    g = _unflatten(grads.cpu().numpy().astype(np.float64), cin, width, n_out)
+    for k in gref:
+        e = _rel(g[k], gref[k])
+        say(f"  grad {k} rel {e:.2e}")
+        assert e <= tol, k
+
+
+def test_cnn_loss_and_adam(torch):
+    from paper_2211_13893_amd import msgfem
+    say("[cnn] loss + adam")
+    rng = np.random.default_rng(3)
+    ng, ne, B = 32, 16, 5
+    c = rng.standard_normal((B, ng * ne)).astype(np.float32) * 0.2
+    cs = np.stack([np.linalg.qr(rng.standard_normal((ng, ne)))[0] for _ in range(B)])
+    Pm = np.einsum("bij,bkj->bik", cs, cs).astype(np.float32)
+    dev = torch.device("cuda:0")
+    loss, g = msgfem.msgfem_cnn_loss(torch.as_tensor(c, device=dev), torch.as_tensor(Pm, device=dev), ng, ne, 0.5)
+    torch.cuda.synchronize()
+    for b in range(B):
+        lr_, gr_ = cnn.projector_loss(c[b:b + 1].reshape(1, ng, ne).astype(np.float64), cs[b:b + 1])
+        assert abs(float(loss[b]) - lr_) <= 1e-5 * lr_
+        assert _rel(g[b].cpu().numpy().reshape(ng, ne).astype(np.float64), 0.5 * gr_[0]) <= 1e-5
+    # Adam: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, p -= lr mhat / (sqrt(vhat) + eps)
+    n = 1000
+    p0 = rng.standard_normal(n).astype(np.float32)
+    p = torch.as_tensor(p0.copy(), device=dev)
+    m = torch.zeros(n, device=dev)
+    v = torch.zeros(n, device=dev)
+    pr, mr, vr = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in (1, 2, 3):
+        gr = rng.standard_normal(n).astype(np.float32)
+        msgfem.msgfem_cnn_adam(p, torch.as_tensor(gr, device=dev), m, v, t, 1e-2)
+        mr = 0.9 * mr + 0.1 * gr
+        vr = 0.999 * vr + 0.001 * gr.astype(np.float64) ** 2
+        pr = pr - 1e-2 * (mr / (1 - 0.9 ** t)) / (np.sqrt(vr / (1 - 0.999 ** t)) + 1e-8)
+    torch.cuda.synchronize()
+    assert np.abs(p.cpu().numpy() - pr).max() <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def reference(torch):
+    from paper_2211_13893_amd import warm
+    say("[warm] reference basis ng=32")
+    G, st, out = warm.reference_basis(ng=32)
+    torch.cuda.synchronize()
+    return G, st, out
+
+
+def test_warm_basis(torch, reference):
+    G, st, out = reference
+    say("[warm] basis checks")
+    Gh = G.cpu().numpy()
+    cls = st.classes(0).cpu().numpy()
+    assert np.abs(Gh[cls != 2]).max() == 0.0
+    assert np.abs(Gh.T @ Gh - np.eye(32)).max() <= 1e-12
+    # span(G) = span of the B2 parts of the reference box's first 32 eigenvectors
+    X = st.eigvecs(out, 0).cpu().numpy()[cls == 2]
+    R = X - Gh[cls == 2] @ (Gh[cls == 2].T @ X)
+    assert np.linalg.norm(R) <= 1e-10 * np.linalg.norm(X)
+    # six rigid modes on a floating box
+    lam = st.eigvals(out, 0).cpu().numpy()
+    assert np.all(np.abs(lam[:6]) <= 1e-8) and lam[6] > 1e-3
+
+
+def test_warm_labels_features_and_start(torch, reference):
+    from paper_2211_13893_amd import msgfem, warm
+    G, _, _ = reference
+    say("[warm] labels / features / start, 3 boxes")
+    p = synth.warm_start_batch(n_boxes=3, seed=5)
+    st = msgfem.LocalStage(p)
+    st.msgfem_assemble_local()
+    out = st.msgfem_local_eigs()
+    ne = 16
+    P = st.msgfem_warm_labels(out, G, ne)
+    feat = st.msgfem_warm_features()
+    torch.cuda.synchronize()
+    assert tuple(feat.shape) == (3, 6, 14, 14, 14)
+    Gh = G.cpu().numpy()
+    for b in range(3):
+        cls = st.classes(b).cpu().numpy()
+        X = st.eigvecs(out, b).cpu().numpy()[:, :ne]
+        Q, _ = np.linalg.qr(Gh.T @ X)
+        assert np.abs(P[b].cpu().numpy() - Q @ Q.T).max() <= 1e-6
+        # features: the channels are what the header states
+        f = feat[b].cpu().numpy()
+        bi = st.boxes[b]
+        lo = np.array([bi.g0[0], bi.g0[1], bi.g0[2]])
+        k, j, i = 3, 7, 11
+        ge = (lo[0] + i) + p.nx * ((lo[1] + j) + p.ny * (lo[2] + k))
+        m = p.materials[p.elem_mat[ge]]
+        th = np.deg2rad(m[9])
+        assert abs(f[0, k, j, i] - np.cos(2 * th)) <= 1e-6 and abs(f[1, k, j, i] - np.sin(2 * th)) <= 1e-6
+        assert f[2, k, j, i] == (1.0 if m[0] != m[1] else 0.0)
+        assert abs(f[3, k, j, i] - (np.log(m[0]) - np.log(1e4)) / 2.5) <= 1e-6
+    # start block: G C on B2 for the first ne columns, Gaussian elsewhere on B2,
+    # zero off B2; a NaN column and a zero column fall back to Gaussian ones
+    rng = np.random.default_rng(0)
+    coef = rng.standard_normal((3, 32, ne)).astype(np.float32)
+    coef[1, :, 2] = np.nan
+    coef[2, :, 5] = 0.0
+    x0 = st.msgfem_warm_start(torch.as_tensor(coef, device="cuda:0"), G, ne, seed=9)
+    torch.cuda.synchronize()
+    for b in range(3):
+        cls = st.classes(b).cpu().numpy()
+        xb = st.box_vector(x0, b).cpu().numpy()
+        assert np.abs(xb[cls != 2]).max() == 0.0
+        ref = Gh @ coef[b].astype(np.float64)
+        ok = [e for e in range(ne) if not (b == 1 and e == 2) and not (b == 2 and e == 5)]
+        assert np.abs(xb[cls == 2][:, ok] - ref[cls == 2][:, ok]).max() <= 1e-12 * np.abs(ref[cls == 2][:, ok]).max()
+        rnd = xb[cls == 2][:, ne:]
+        assert np.all(np.isfinite(rnd)) and abs(rnd.mean()) < 0.05 and abs(rnd.std() - 1) < 0.05
+    for b, e in ((1, 2), (2, 5)):
+        col = st.box_vector(x0, b).cpu().numpy()[:, e][st.classes(b).cpu().numpy() == 2]
+        assert np.all(np.isfinite(col)) and abs(col.std() - 1) < 0.1
+
+
+def test_warm_start_gain_on_held_out_boxes(torch, reference):
+    """Train on 4 x 64 boxes, then start 64 held-out boxes from the network:
+    the same eigenpairs (nu within 1e-8), every box converged, fewer LOBPCG
+    iterations on average than the random start, and a held-out loss below
+    that of the fixed start from the reference box's first ne modes."""
+    from paper_2211_13893_amd import msgfem, warm
+    G, _, _ = reference
+    say("[warm] training 300 steps on seeds 0-3")
+    net, losses = warm.fit(G, seeds=range(4), steps=300)
+    say(f"  final train loss {losses[-1]:.3f}")
+    feat, P, out_r, st = warm.training_set(1000, G)
+    lh, _ = msgfem.msgfem_cnn_loss(net.forward(feat), P, 32, 16)
+    fixed = torch.zeros((64, 32, 16), dtype=torch.float32, device="cuda:0")
+    fixed[:, :16, :] = torch.eye(16, device="cuda:0")
+    lf, _ = msgfem.msgfem_cnn_loss(fixed.view(64, -1), P, 32, 16)
+    lam_r = out_r["evals"].cpu().numpy()
+    it_r = out_r["iters"].cpu().numpy()
+    say("[warm] held-out seed 1000, warm start")
+    out_w = st.msgfem_local_eigs(x0=net.start_block(st, G))
+    torch.cuda.synchronize()
+    lam_w = out_w["evals"].cpu().numpy()
+    it_w = out_w["iters"].cpu().numpy()
+    say(f"  iterations random {it_r.mean():.3f} warm {it_w.mean():.3f}; held-out loss "
+        f"{lh.cpu().numpy().mean():.3f} vs fixed start {lf.cpu().numpy().mean():.3f}")
+    assert int(out_w["status"].max()) == 0
+    nu_r, nu_w = 1.0 / (lam_r + 1.0), 1.0 / (lam_w + 1.0)
+    assert np.abs(nu_w - nu_r).max() <= 1e-8 * nu_r.max()
+    assert it_w.mean() <= it_r.mean()
+    assert lh.cpu().numpy().mean() < lf.cpu().numpy().mean()

@@ -94,3 +94,37 @@ def test_projector_loss_gradient_and_rotation_invariance():
     # an orthonormal basis of the same subspace has zero loss
     l0, g0 = cnn.projector_loss((cs @ q)[None], cs[None])
     assert l0 <= 1e-24 and np.abs(g0).max() <= 1e-12
+
+
+def test_bf16_rounding_ties_to_even_and_matches_torch():
+    u = 2.0 ** -7                               # bfloat16 spacing on [1, 2)
+    assert cnn.bf16(np.array([1 + u / 2]))[0] == 1.0            # tie, even neighbour 1
+    assert cnn.bf16(np.array([1 + 1.5 * u]))[0] == 1 + 2 * u    # tie, even neighbour 1 + 2u
+    assert cnn.bf16(np.array([1 + 0.51 * u]))[0] == 1 + u
+    assert cnn.bf16(np.array([-3.0]))[0] == -3.0 and cnn.bf16(np.array([0.0]))[0] == 0.0
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal(4096) * np.exp(rng.uniform(-20, 20, 4096))).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(cnn.bf16(x.astype(np.float64)), ref)
+
+
+def test_bf16_network_rounds_only_the_stored_values():
+    rng = np.random.default_rng(6)
+    p = cnn.init_params(c_in=2, width=3, n_out=4, seed=8)
+    x = rng.standard_normal((2, 2, 5, 5, 5))
+    out, acts = cnn.forward(p, x, use_bf16=True)
+    for a in acts[:5]:
+        assert np.array_equal(cnn.bf16(a), a)
+    # weights that are already bfloat16 values and a bfloat16 input: the
+    # rounded network differs from the exact one only by the rounding of the
+    # stored activations, a relative 2^-9 per layer
+    q = {k: (cnn.bf16(v) if k in ("w0", "w1", "w2", "w3") else v) for k, v in p.items()}
+    ref, _ = cnn.forward(q, cnn.bf16(x))
+    assert np.linalg.norm(out - ref) <= 4 * 5 * 2.0 ** -9 * np.linalg.norm(ref)
+    # the BF16 backward equals the FP64 backward of the network with rounded weights at the rounded activations
+    gout = rng.standard_normal((2, 4))
+    g1 = cnn.backward(p, acts, gout, use_bf16=True)
+    g2 = cnn.backward(q, acts, gout)
+    for k in g1:
+        assert np.array_equal(g1[k], g2[k])
