@@ -33,6 +33,9 @@ sys.path.insert(0, ROOT)
 METRIC = "local GEVPs/sec (n_ev pairs, resid≤1e-6), mixed vs FP64 path; SpMM HBM GB/s"
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
+# rocprofv3 summary of the FP64 path on this workload (kernel times and the
+# FETCH_SIZE / WRITE_SIZE traffic of its kernels)
+PROFILE = "local_stage_uniform_batch64_fp64.md"
 
 
 def cpu_baseline(prob, n_sample: int):
@@ -163,6 +166,13 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
                 "avg_launch_ms": avg_s * 1e3}
+    from paper_2211_13893_amd import profiling
+    lib_kernel = {"band_solve": "k_band_solve", "spmm": "k_spmm"}.get(dom)
+    if lib_kernel:
+        t = profiling.recorded_traffic(os.path.join(ROOT, "profiles", PROFILE), lib_kernel)
+        roof["traffic"] = t
+        if t:
+            roof["traffic_vs_algorithmic"] = t / per_launch_bytes
     kernels = {}
     for n, v in stats.items():
         sec = v["ms"] / 1e3

@@ -388,7 +388,8 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   p->n_gchunk = (p->max_dof + GRAM_ROWS - 1) / GRAM_ROWS;
   int m3 = 3 * k;
   int nchunk_solve = (k + KC - 1) / KC;
-  p->scr_stride = (int64_t)p->max_nt * 32 * KC;
+  // w rows of the solve plus one row that absorbs stores without a target
+  p->scr_stride = (int64_t)(p->max_nt + 1) * 32 * KC;
   off = 0;
   p->w_vec = off; off = align256(off + 22 * p->vec_total * 8);
   p->w_part = off; off = align256(off + (int64_t)nb * p->n_gchunk * 2 * m3 * m3 * 8);
@@ -694,9 +695,9 @@ static void lds_attributes() {
   done = true;
   (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
-  (void)hipFuncSetAttribute((const void*)k_band_solve<8, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)k_band_solve<KC, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
-  (void)hipFuncSetAttribute((const void*)k_band_solve<8, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)k_band_solve<KC, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);

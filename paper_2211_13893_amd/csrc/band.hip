@@ -354,41 +354,64 @@ __global__ void k_band_relayout(const BoxMeta* __restrict__ meta, int kind, doub
 // DoFs, writes `out` on the DoFs whose class bit is set in out_classes (bit c
 // for class c); with zero_rest, every other DoF of the box gets 0 in these
 // columns.  Scratch holds w = D^{-1} y of the forward sweep, NT*32*KC doubles
-// per (box, chunk).
+// per (box, chunk), and one more row (index NT) that takes stores without a
+// target; scratch_stride >= (NT + 1)*32*KC.
 //
 // Forward sweep  y_I = f_I - sum_s Lu(I,I-s) y_{I-s}; backward sweep
 // x_I = w_I - sum_s Lu(I+s,I)^T x_{I+s}.  A step's work items are
 // (band tile s, row quad, half of the inner index): thread t handles tile
 // s = 1 + (t >> 4), rows 4*((t >> 1) & 7) .. +3 and inner indices
 // 16*(t & 1) .. +15, for all KC columns, so every solution row read from the
-// LDS ring feeds four factor rows.  The two halves are combined with a lane
-// shuffle, the per-tile partial sums are reduced through LDS, and the factor
-// fragment of the next step is requested as soon as the current one has been
-// used, so its memory latency overlaps the reduction and the barriers.  The
-// diagonal block D^{-1} of the previous forward step is applied in the same
-// shadow.  The column chunks of one box share an XCD (block id mod 8) so the
-// factor they stream is read from HBM once and then hit in that XCD's L2.
+// LDS ring feeds four factor rows.  The two halves are combined by a DPP lane
+// exchange that leaves each lane of the pair with two of the four rows
+// (reduce-scatter), the per-tile partial sums go through LDS and are added in
+// a fixed order by the first 32*KC threads.  The product w = D^{-1} y of the
+// previous forward step is formed by the last two wavefronts, which hold no
+// band tiles unless the band is wider than 25 tiles.
+//
+// Latency: the factor fragment of the next step is requested piece by piece
+// while the current one is used, so the loads stream during the arithmetic,
+// and stays in flight across the LDS-only barriers while the step is reduced.  For the compiler to wait for each
+// global load only where its own value is needed, every global load and
+// store of a step is issued by every thread, unconditionally and in the same
+// order: out-of-range work items read a valid address and discard the
+// value, and stores without a target write the spare scratch row.
+//
+// The column chunks of one box share an XCD (block id mod 8) so the factor
+// they stream is read from HBM once and then hit in that XCD's L2.
 // grid.x = 8 * n_chunk * ceil(n_box/8), 512 threads; dynamic LDS = BT*32*KC doubles.
 #define SOLVE_THREADS 512
+// Barrier for LDS traffic only (__syncthreads would also wait for every
+// global load).  Inside the sweeps no thread reads global memory that
+// another thread of the block wrote, so they need no global-memory barrier.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// value of the partner lane (lane ^ 1) through a DPP quad permutation
+__device__ inline double dpp_xor1(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
 
 // f[i][q]: forward  = Lu[4rq+i][16h+q] of tile (I, I-s);
 //          backward = Lu[16h+q][4rq+i] of tile (I+s, I)  (row i of its transpose)
 // read from the solve-ordered copy F (fw or bw) of the band: consecutive
-// threads read consecutive 16-byte pieces.
+// threads read consecutive 16-byte pieces.  tc < max(nthr, 1) is the
+// (clamped) thread slot; with nthr == 0 (no off-diagonal tiles) F points at
+// any valid 32 pieces and the values are not used.
 template <typename T> struct vec2_of;
 template <> struct vec2_of<double> { typedef double2 type; };
 template <> struct vec2_of<float> { typedef float2 type; };
 
 template <typename T>
-__device__ inline void frag_load(const typename vec2_of<T>::type* __restrict__ F, int I, int nthr, int smax,
-                                 int dir, int s, int tid, double (&f)[4][16]) {
-  if (s > smax) return;
-  const typename vec2_of<T>::type* p = F + (int64_t)I * 32 * nthr + tid;
+__device__ inline void frag_load(const typename vec2_of<T>::type* __restrict__ F, int I, int nthr, int dir,
+                                 int tc, double (&f)[4][16]) {
+  const typename vec2_of<T>::type* p = F + (int64_t)I * 32 * nthr + tc;
   if (dir < 0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int q = 0; q < 8; ++q)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int i = 0; i < 4; ++i) {
         const auto a = p[(int64_t)(8 * i + q) * nthr];
         f[i][2 * q] = a.x;
         f[i][2 * q + 1] = a.y;
@@ -416,9 +439,12 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     const double* in, double* out,
     int ldk, int out_classes, int zero_rest, double* __restrict__ scratch, int64_t scratch_stride,
     const int32_t* __restrict__ active) {
+  static_assert(32 * KC == 256, "reduction threads = the first 256, w threads = the last 128");
+  static_assert(SOLVE_THREADS / 16 <= SOLVE_TILES, "one part slot per tile group");
   extern __shared__ double ring[];   // [BT][32][KC]
   __shared__ double part[SOLVE_TILES][32][KC + 1];
   __shared__ double Dl[32][33];      // D^{-1} tile of the current forward step
+  __shared__ double Wl[32 * KC];     // w of the previous forward step
   const int x = blockIdx.x;
   const int xcd = x & 7, rest = x >> 3;
   const int chunk = rest % n_chunk;
@@ -433,146 +459,194 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   const int h = tid & 1, rq = (tid >> 1) & 7, sg = tid >> 4;  // item of the thread
   const int s = 1 + sg;
   const bool red = tid < 32 * KC;
-  const int rr = tid / KC, cc = tid % KC;                     // reduction mapping
+  const int t8 = tid & (32 * KC - 1);                         // reduction slot (duplicated above 256)
+  const int rr = t8 / KC, cc = t8 % KC;
   const int col = chunk * KC + cc;
   const bool colok = col < ldk;
+  const int colc = colok ? col : ldk - 1;
+  const bool wthr = tid >= SOLVE_THREADS - 128;               // forms w = D^{-1} y
   const double* vin = in + bm.dof_off * ldk;
   double* vout = out + bm.dof_off * ldk;
   double* w = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
   const int BT = v.BT, NT = v.NT;
   const int nthr = solve_nthr(BT);
+  const int tc = nthr ? min(tid, nthr - 1) : 0;
+  // wavefronts without band tiles (uniform: the wave's first thread decides)
+  const bool wave_tiles = __builtin_amdgcn_readfirstlane(tid) < nthr;
   typedef typename vec2_of<T>::type V2;
-  const V2* Ffw = (const V2*)(ft + v.fw);
-  const V2* Fbw = (const V2*)(ft + v.bw);
+  const V2* Ffw = nthr ? (const V2*)(ft + v.fw) : (const V2*)(ft + v.off);
+  const V2* Fbw = nthr ? (const V2*)(ft + v.bw) : (const V2*)(ft + v.off);
   double f[4][16];
 
-  // partial sums of this thread's item over its half of the inner index
-  auto accumulate = [&](const double* yp, double (&acc)[4][KC]) {
+  // partial sums of this thread's item over its half of the inner index,
+  // with the factor fragment of the next step requested piece by piece as
+  // the current pieces are used (the loads are issued whether or not the
+  // thread has a tile this step, so every step issues the same loads)
+  auto accumulate = [&](bool has, const double* yp, double (&acc)[4][KC], const V2* Fn, int dir) {
+    if (!wave_tiles) return;
+#pragma unroll
+    for (int qq = 0; qq < 8; ++qq) {
+      if (has) {
+#pragma unroll
+        for (int q = 2 * qq; q < 2 * qq + 2; ++q) {
+          const double* y0 = yp + (16 * h + q) * KC;
+#pragma unroll
+          for (int c = 0; c < KC; ++c) {
+            const double a = y0[c];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i][c] += f[i][q] * a;
+          }
+        }
+      }
+      if (dir < 0) {
+        // pieces 8i + qq hold f[i][2qq], f[i][2qq+1]
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const V2 a = Fn[(int64_t)(8 * i + qq) * nthr];
+          f[i][2 * qq] = a.x;
+          f[i][2 * qq + 1] = a.y;
+        }
+      } else {
+        // pieces 2q, 2q+1 hold f[0..3][q]
+#pragma unroll
+        for (int q = 2 * qq; q < 2 * qq + 2; ++q) {
+          const V2 a = Fn[(int64_t)(2 * q) * nthr];
+          const V2 b = Fn[(int64_t)(2 * q + 1) * nthr];
+          f[0][q] = a.x;
+          f[1][q] = a.y;
+          f[2][q] = b.x;
+          f[3][q] = b.y;
+        }
+      }
+    }
+  };
+  // lane pair (h = 0, 1): lane h keeps rows 2h, 2h+1 of the quad and adds the
+  // partner's sums of those rows; every part slot is written each step
+  auto store_part = [&](bool has, double (&acc)[4][KC]) {
+#pragma unroll
+    for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        const double keep = h ? acc[2 + i2][c] : acc[i2][c];
+        const double send = h ? acc[i2][c] : acc[2 + i2][c];
+        const double sum = keep + dpp_xor1(send);
+        part[sg][4 * rq + 2 * h + i2][c] = has ? sum : 0.0;
+      }
+  };
+  // sum over the SOLVE_TILES slots in a fixed order, four independent chains
+  auto part_sum = [&]() {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+    for (int q = 0; q < SOLVE_TILES; q += 4) {
+      a0 += part[q][rr][cc];
+      a1 += part[q + 1][rr][cc];
+      a2 += part[q + 2][rr][cc];
+      a3 += part[q + 3][rr][cc];
+    }
+    return (a0 + a1) + (a2 + a3);
+  };
+  // Wl = D^{-1}_J y_J (D^{-1}_J in Dl, y_J in its ring slot), by the w threads
+  auto form_w = [&](int J) {
+    const int u = tid - (SOLVE_THREADS - 128);
+    const double* yp = ring + (int64_t)(J % BT) * 32 * KC;
+#pragma unroll
+    for (int o = u; o < 32 * KC; o += 128) {
+      const int r = o / KC, c = o % KC;
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < 32; q += 2) {
+        a0 += Dl[r][q] * yp[q * KC + c];
+        a1 += Dl[r][q + 1] * yp[(q + 1) * KC + c];
+      }
+      Wl[o] = a0 + a1;
+    }
+  };
+  auto zero_acc = [&](double (&acc)[4][KC]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int c = 0; c < KC; ++c) acc[i][c] = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const double* y0 = yp + (16 * h + q) * KC;
-#pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        const double a = y0[c];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i][c] += f[i][q] * a;
-      }
-    }
-  };
-  auto store_part = [&](bool has, double (&acc)[4][KC]) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        double o = __shfl_xor(acc[i][c], 1);
-        acc[i][c] += o;
-      }
-    if (h == 0 && sg < SOLVE_TILES) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < KC; ++c) part[sg][4 * rq + i][c] = has ? acc[i][c] : 0.0;
-    }
   };
 
   // ---- forward: Lu y = f
-  frag_load<T>(Ffw, 0, nthr, 0, -1, s, tid, f);
+  frag_load<T>(Ffw, 0, nthr, -1, tc, f);
   for (int I = 0; I < NT; ++I) {
     const int smax = min(BT - 1, I);
-    double fv = 0.0;
-    if (red) {
-      const int dof = band_to_dof(v, bm, I * 32 + rr);
-      if (dof >= 0 && colok && dof_active(kind, cl[dof])) fv = vin[(int64_t)dof * ldk + col];
-    }
-    const V2* dp = (const V2*)(ft + v.off + (int64_t)I * BT * MSG_TILE2);
-    double2 d0 = make_double2(0.0, 0.0), d1 = make_double2(0.0, 0.0);
-    if (red) {
-      const V2 a = dp[2 * tid], b = dp[2 * tid + 1];
-      d0 = make_double2(a.x, a.y);
-      d1 = make_double2(b.x, b.y);
-    }
-    // w_{I-1} = D^{-1}_{I-1} y_{I-1} (Dl and its ring slot were completed last step)
-    if (red && I >= 1) {
-      const double* yp = ring + (int64_t)((I - 1) % BT) * 32 * KC;
-      double wv = 0.0;
-#pragma unroll
-      for (int q = 0; q < 32; ++q) wv += Dl[rr][q] * yp[q * KC + cc];
-      w[(int64_t)((I - 1) * 32 + rr) * KC + cc] = wv;
-    }
+    // right-hand side and D^{-1} tile of this step (used after the first barrier)
+    // (the class byte is tested after the barrier, so no wait is forced here)
+    const int dof = band_to_dof(v, bm, I * 32 + rr);
+    const int dofc = dof >= 0 ? dof : 0;
+    const double fraw = vin[(int64_t)dofc * ldk + colc];
+    const uint8_t cb = cl[dofc];
+    const V2* dp = (const V2*)(ft + v.off + (int64_t)I * BT * MSG_TILE2) + 2 * t8;
+    const V2 da = dp[0], db = dp[1];
+    // w_{I-1} (Dl and its ring slot were completed last step)
+    if (wthr && I >= 1) form_w(I - 1);
     double acc[4][KC];
+    zero_acc(acc);
     const bool has = s <= smax;
-    if (has) accumulate(ring + (int64_t)((I - s) % BT) * 32 * KC, acc);
+    accumulate(has, ring + (int64_t)((has ? I - s : 0) % BT) * 32 * KC, acc,
+               Ffw + (int64_t)min(I + 1, NT - 1) * 32 * nthr + tc, -1);
     store_part(has, acc);
-    // fragment of the next step, in flight during the reduction
-    if (I + 1 < NT) frag_load<T>(Ffw, I + 1, nthr, min(BT - 1, I + 1), -1, s, tid, f);
-    __syncthreads();
+    lds_barrier();
+    w[(int64_t)((I >= 1 ? I - 1 : NT) * 32 + rr) * KC + cc] = Wl[t8];
     if (red) {
       const int e = 4 * tid;
-      Dl[e >> 5][e & 31] = d0.x;
-      Dl[(e + 1) >> 5][(e + 1) & 31] = d0.y;
-      Dl[(e + 2) >> 5][(e + 2) & 31] = d1.x;
-      Dl[(e + 3) >> 5][(e + 3) & 31] = d1.y;
-      double sum = 0.0;
-      const int ns = min(smax, SOLVE_TILES);
-      for (int q = 0; q < ns; ++q) sum += part[q][rr][cc];
+      Dl[e >> 5][e & 31] = da.x;
+      Dl[(e + 1) >> 5][(e + 1) & 31] = da.y;
+      Dl[(e + 2) >> 5][(e + 2) & 31] = db.x;
+      Dl[(e + 3) >> 5][(e + 3) & 31] = db.y;
+      double sum = part_sum();
       // bands wider than 33 tiles: remaining tiles directly
       for (int s2 = SOLVE_TILES + 1; s2 <= smax; ++s2) {
         const double* p = L + ((int64_t)I * BT + s2) * MSG_TILE2 + rr * 32;
         const double* yp = ring + (int64_t)((I - s2) % BT) * 32 * KC;
         for (int q = 0; q < 32; ++q) sum += p[q] * yp[q * KC + cc];
       }
-      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = fv - sum;
+      const bool fok = (dof >= 0) & colok & dof_active(kind, cb);
+      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = (fok ? fraw : 0.0) - sum;
     }
-    __syncthreads();
+    lds_barrier();
   }
-  if (red) {
-    const int I = NT - 1;
-    const double* yp = ring + (int64_t)(I % BT) * 32 * KC;
-    double wv = 0.0;
-#pragma unroll
-    for (int q = 0; q < 32; ++q) wv += Dl[rr][q] * yp[q * KC + cc];
-    w[(int64_t)(I * 32 + rr) * KC + cc] = wv;
-  }
+  if (wthr) form_w(NT - 1);
+  lds_barrier();
+  w[(int64_t)((NT - 1) * 32 + rr) * KC + cc] = Wl[t8];
   __syncthreads();
 
   // ---- backward: Lu^T x = w
-  frag_load<T>(Fbw, NT - 1, nthr, 0, +1, s, tid, f);
+  frag_load<T>(Fbw, NT - 1, nthr, +1, tc, f);
   for (int I = NT - 1; I >= 0; --I) {
     const int smax = min(BT - 1, NT - 1 - I);
     const int row = I * 32 + rr;
-    const double fv = red ? w[(int64_t)row * KC + cc] : 0.0;
+    const double fv = w[(int64_t)row * KC + cc];
+    const int dof = band_to_dof(v, bm, row);
+    const uint8_t cb = cl[dof >= 0 ? dof : 0];
     double acc[4][KC];
+    zero_acc(acc);
     const bool has = s <= smax;
-    if (has) accumulate(ring + (int64_t)((I + s) % BT) * 32 * KC, acc);
+    accumulate(has, ring + (int64_t)((has ? I + s : 0) % BT) * 32 * KC, acc,
+               Fbw + (int64_t)max(I - 1, 0) * 32 * nthr + tc, +1);
     store_part(has, acc);
-    if (I - 1 >= 0) frag_load<T>(Fbw, I - 1, nthr, min(BT - 1, NT - I), +1, s, tid, f);
-    __syncthreads();
+    lds_barrier();
+    double xv = 0.0;
     if (red) {
-      double sum = 0.0;
-      const int ns = min(smax, SOLVE_TILES);
-      for (int q = 0; q < ns; ++q) sum += part[q][rr][cc];
+      double sum = part_sum();
       for (int s2 = SOLVE_TILES + 1; s2 <= smax; ++s2) {
         const double* p = L + ((int64_t)(I + s2) * BT + s2) * MSG_TILE2 + rr;
         const double* xp = ring + (int64_t)((I + s2) % BT) * 32 * KC;
         for (int q = 0; q < 32; ++q) sum += p[q * 32] * xp[q * KC + cc];
       }
-      const double xv = fv - sum;
+      xv = fv - sum;
       ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = xv;
-      const int dof = band_to_dof(v, bm, row);
-      if (dof >= 0 && colok) {
-        uint8_t k = cl[dof];
-        if (dof_active(kind, k) && ((out_classes >> k) & 1)) vout[(int64_t)dof * ldk + col] = xv;
-      }
     }
-    __syncthreads();
+    // the solution goes to `out` where it belongs, else to the spare row
+    const bool wr = red & (dof >= 0) & colok & dof_active(kind, cb) & (((out_classes >> cb) & 1) != 0);
+    *(wr ? vout + (int64_t)dof * ldk + col : w + (int64_t)(NT * 32 + rr) * KC + cc) = xv;
+    lds_barrier();
   }
   if (zero_rest && colok && red) {
     // zero the DoFs of this box (this chunk's columns) that were not written
-    for (int d = rr; d < bm.n_dof; d += 256 / KC) {
+    for (int d = rr; d < bm.n_dof; d += 32) {
       uint8_t k = cl[d];
       bool written = dof_active(kind, k) && ((out_classes >> k) & 1);
       if (!written) vout[(int64_t)d * ldk + col] = 0.0;
@@ -586,6 +660,7 @@ template __global__ void k_band_solve<8, double>(const BoxMeta*, int, int, int, 
 template __global__ void k_band_solve<8, float>(const BoxMeta*, int, int, int, const double*, const float*,
                                                 const uint8_t*, const double*, double*, int, int, int, double*,
                                                 int64_t, const int32_t*);
+
 
 // FP32 copies for the mixed path (same element offsets as the FP64 arrays):
 // the two solve-ordered band copies and the D^{-1} diagonal tiles of both box

@@ -1,0 +1,180 @@
+"""Kernel-time and HBM-traffic summaries of the local stage from rocprofv3 output.
+
+    python -m paper_2211_13893_amd.profiling run [--boxes 64] [--steps 1]
+        the profiled workload: one 256 MiB device-to-device copy (the
+        calibration of the traffic counters), then `steps` FP64 local stages
+        (assembly + factorisation + LOBPCG) of the uniform batch;
+    python -m paper_2211_13893_amd.profiling summarize --trace D --fetch D --write D --out F.md
+        a markdown summary of the kernel statistics of a `--kernel-trace
+        --stats` run (directory D) and, per kernel, the HBM bytes per launch
+        from a `--pmc FETCH_SIZE` and a `--pmc WRITE_SIZE` run of the same
+        workload.  Each counter is scaled by the factor that makes it read
+        256 MiB for the calibration copy (read 256 MiB, written 256 MiB).
+
+The summary records a SHA-256 of the kernel sources; bench.py reports the
+measured traffic only while those sources are unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import re
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 256 * 1024 * 1024
+# kernel (name prefix in the trace) -> sources it is built from
+KERNEL_SOURCES = {
+    "k_band_solve": ["csrc/band.hip", "csrc/internal.hpp"],
+    "k_spmm": ["csrc/spmm.hip", "csrc/internal.hpp"],
+}
+
+
+def sources_sha256(kernel: str) -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def short_name(name: str) -> str:
+    n = re.sub(r"\(.*$", "", name.strip().strip('"'))
+    n = re.sub(r"^void ", "", n)
+    return n.replace("msg::", "")
+
+
+def _csv(d: str, suffix: str):
+    files = glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    with open(files[0], newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def counter_per_dispatch(d: str, counter: str):
+    """{dispatch id: (kernel name, grid size, summed counter value in KiB)}."""
+    out = {}
+    for r in _csv(d, "counter_collection.csv"):
+        if not r["Counter_Name"].startswith(counter):
+            continue
+        k = int(r["Dispatch_Id"])
+        name, grid, v = out.get(k, (r["Kernel_Name"], int(r["Grid_Size"]), 0.0))
+        out[k] = (name, grid, v + float(r["Counter_Value"]))
+    return out
+
+
+def calibration(per_dispatch) -> float:
+    """Bytes per counter unit: the 256 MiB copy is the copy dispatch with the largest value."""
+    copies = [v for (n, g, v) in per_dispatch.values() if "copyBuffer" in n or "copy" in n.lower()]
+    if not copies:
+        raise RuntimeError("no copy kernel in the counter run")
+    return COPY_BYTES / max(copies)
+
+
+def traffic_per_launch(fetch_dir: str, write_dir: str):
+    """{kernel: (launches, mean HBM bytes read, mean bytes written)} and the two factors."""
+    f = counter_per_dispatch(fetch_dir, "FETCH_SIZE")
+    w = counter_per_dispatch(write_dir, "WRITE_SIZE")
+    cf, cw = calibration(f), calibration(w)
+    acc = defaultdict(lambda: [0, 0.0, 0.0])
+    for k, (n, g, v) in f.items():
+        a = acc[short_name(n)]
+        a[0] += 1
+        a[1] += v * cf
+    for k, (n, g, v) in w.items():
+        acc[short_name(n)][2] += v * cw
+    return {n: (a[0], a[1] / a[0], a[2] / a[0]) for n, a in acc.items() if a[0]}, cf, cw
+
+
+def summarize(trace: str, fetch: str, write: str, out: str, title: str, commands: str):
+    stats = _csv(trace, "kernel_stats.csv")
+    tot = sum(float(r["TotalDurationNs"]) for r in stats)
+    rows = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))
+    traffic, cf, cw = traffic_per_launch(fetch, write) if fetch and write else ({}, None, None)
+    lines = [f"# {title}", "", "Commands (from the repository root, one MI355X):", "", "```", commands.strip(),
+             "```", "", "## Kernel time (`--kernel-trace --stats`)", "",
+             "| kernel | calls | total ms | avg us | min us | max us | share % |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows[:20]:
+        lines.append(f"| {short_name(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {100 * float(r['TotalDurationNs']) / tot:.2f} |")
+    if traffic:
+        lines += ["", "## HBM traffic per launch (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`)", "",
+                  f"Calibration on the 256 MiB copy: bytes = FETCH_SIZE x {cf / 1024:.3f} KiB, "
+                  f"WRITE_SIZE x {cw / 1024:.3f} KiB.", "",
+                  "| kernel | launches | read MB/launch | written MB/launch |", "|---|---:|---:|---:|"]
+        for n, (c, r_, w_) in sorted(traffic.items(), key=lambda t: -(t[1][1] + t[1][2]) * t[1][0])[:12]:
+            lines.append(f"| {n} | {c} | {r_ / 1e6:.3f} | {w_ / 1e6:.3f} |")
+        lines += ["", "Machine-readable (bench.py reads these while the sources are unchanged):", ""]
+        for kern in KERNEL_SOURCES:
+            hit = [(n, v) for n, v in traffic.items() if n.startswith(kern)]
+            if not hit:
+                continue
+            c = sum(v[0] for _, v in hit)
+            b = sum(v[0] * (v[1] + v[2]) for _, v in hit) / c
+            lines.append(f"    traffic_bytes_per_launch {kern} {b:.0f} sources_sha256 {sources_sha256(kern)}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out)
+
+
+def recorded_traffic(md_path: str, kernel: str):
+    """HBM bytes per launch of `kernel` recorded in a summary, or None when
+    the file is absent or the kernel's sources changed since."""
+    if not os.path.exists(md_path):
+        return None
+    pat = re.compile(rf"traffic_bytes_per_launch {re.escape(kernel)} ([0-9.e+]+) sources_sha256 ([0-9a-f]+)")
+    with open(md_path) as f:
+        for line in f:
+            m = pat.search(line)
+            if m:
+                return float(m.group(1)) if m.group(2) == sources_sha256(kernel) else None
+    return None
+
+
+def run_workload(boxes: int, steps: int):
+    import torch
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_2211_13893_amd import msgfem, synth
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("calibration copy done", flush=True)
+    del a, b
+    st = msgfem.LocalStage(synth.uniform_batch(n_boxes=boxes), tol=1e-6)
+    for i in range(steps):
+        st.msgfem_assemble_local()
+        out = st.msgfem_local_eigs()
+        torch.cuda.synchronize()
+        print(f"step {i} done, iterations {out['iters'].cpu().numpy().mean():.2f}", flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    r = sub.add_parser("run")
+    r.add_argument("--boxes", type=int, default=64)
+    r.add_argument("--steps", type=int, default=1)
+    s = sub.add_parser("summarize")
+    s.add_argument("--trace", required=True)
+    s.add_argument("--fetch")
+    s.add_argument("--write")
+    s.add_argument("--out", required=True)
+    s.add_argument("--title", default="Kernel trace")
+    s.add_argument("--commands", default="")
+    a = ap.parse_args(argv)
+    if a.cmd == "run":
+        run_workload(a.boxes, a.steps)
+    else:
+        summarize(a.trace, a.fetch, a.write, a.out, a.title, a.commands)
+
+
+if __name__ == "__main__":
+    main()
