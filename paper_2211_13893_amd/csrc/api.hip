@@ -25,9 +25,9 @@ __global__ void k_chol_update(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_panel(const MatDesc*, int, double*);
 __global__ void k_chol_unit(const MatDesc*, double*);
 __global__ void k_band_relayout(const BoxMeta*, int, double*);
-template <int KC, typename T>
-__global__ void k_band_solve(const BoxMeta*, int, int, int, const double*, const T*, const uint8_t*,
-                             const double*, double*, int, int, int, double*, int64_t, const int32_t*);
+template <int KC, int NS, typename T>
+__global__ void k_band_solve(const BoxMeta*, int, int, int, const T*, const uint8_t*, const double*, double*, int,
+                             int, int, double*, int64_t, const int32_t*);
 template <bool TWO, int CW, typename ST>
 __global__ void k_spmm(const BoxMeta*, int, int, const ST*, const uint8_t*, const double*, const double*,
                        double*, double*, int, int, double, const int32_t*);
@@ -330,13 +330,13 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     m.fhi_off = fac_off;
     fac_off += (int64_t)m.nth * 1024;
     m.f11_fw = fac_off;
-    fac_off += (int64_t)m.nt11 * 64 * solve_nthr(m.bt11);
+    fac_off += solve_copy_doubles(m.nt11, m.bt11);
     m.f11_bw = fac_off;
-    fac_off += (int64_t)m.nt11 * 64 * solve_nthr(m.bt11);
+    fac_off += solve_copy_doubles(m.nt11, m.bt11);
     m.fh_fw = fac_off;
-    fac_off += (int64_t)m.nth * 64 * solve_nthr(m.bth);
+    fac_off += solve_copy_doubles(m.nth, m.bth);
     m.fh_bw = fac_off;
-    fac_off += (int64_t)m.nth * 64 * solve_nthr(m.bth);
+    fac_off += solve_copy_doubles(m.nth, m.bth);
     m.evec_off = evec_off;
     m.eval_off = eval_off;
     node_off += m.n_nodes;
@@ -352,8 +352,11 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     p->meta[b] = m;
   }
   // LDS of the block solve: partial sums, the D^{-1} tile and a ring of BT solution tiles
-  if ((int64_t)(SOLVE_TILES * 32 * (KC + 1) + 32 * 33 + p->max_bt * 32 * KC) * 8 > 160 * 1024)
-    return fail(p, MSGFEM_ESIZE, "band of %d tiles too wide for the block solve", p->max_bt);
+  // block solve LDS: per-wavefront partial sums, D^{-1} tile, w row, ring of BT solution rows
+  if (p->max_bt > SOLVE_MAX_BT ||
+      (int64_t)(8 * 32 * (KC + 1) + 32 * 33 + 32 * KC + p->max_bt * 32 * KC) * 8 > 160 * 1024)
+    return fail(p, MSGFEM_ESIZE, "band of %d tiles too wide for the block solve (at most %d)", p->max_bt,
+                SOLVE_MAX_BT);
   for (int b = 0; b < nb; ++b) {
     const BoxMeta& m = p->meta[b];
     MatDesc a11{m.nt11, m.bt11, b, 0, m.f11_off, m.f11i_off};
@@ -620,7 +623,7 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
     double by = 0;
     for (auto& m : p->meta) {
       int nt = kind == 0 ? m.nt11 : m.nth, bt = kind == 0 ? m.bt11 : m.bth;
-      int64_t e = (int64_t)nt * 32 * solve_nthr(bt);
+      int64_t e = solve_copy_doubles(nt, bt) / 2;
       tot = std::max(tot, e);
       by += 3 * 16.0 * e;
     }
@@ -695,10 +698,9 @@ static void lds_attributes() {
   done = true;
   (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
-  (void)hipFuncSetAttribute((const void*)k_band_solve<KC, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-  (void)hipFuncSetAttribute((const void*)k_band_solve<KC, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
+  const void* solves[4] = {(const void*)k_band_solve<KC, 1, double>, (const void*)k_band_solve<KC, 2, double>,
+                           (const void*)k_band_solve<KC, 1, float>, (const void*)k_band_solve<KC, 2, float>};
+  for (const void* f : solves) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_gram_partial, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -753,14 +755,19 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
     fl += 4.0 * e * kk;
   }
   ProfScope ps(c.p, PK_SOLVE, c.s, by, fl);
-  if (c.use32)
-    k_band_solve<KC, float><<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, c.v.fac, c.v.fac32, c.v.cls,
-                                                     in, out, kk, out_classes, zero_rest, c.w.scr, c.p->scr_stride,
-                                                     active);
-  else
-    k_band_solve<KC, double><<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, c.v.fac, c.v.fac, c.v.cls,
-                                                      in, out, kk, out_classes, zero_rest, c.w.scr,
-                                                      c.p->scr_stride, active);
+  // bands wider than SOLVE_TILES + 1 tiles take two tile sets per step
+  const bool two = c.p->max_bt - 1 > SOLVE_TILES;
+  auto launch = [&](auto kern, auto ft) {
+    kern<<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, ft, c.v.cls, in, out, kk, out_classes, zero_rest,
+                                  c.w.scr, c.p->scr_stride, active);
+  };
+  if (c.use32) {
+    if (two) launch(k_band_solve<KC, 2, float>, (const float*)c.v.fac32);
+    else launch(k_band_solve<KC, 1, float>, (const float*)c.v.fac32);
+  } else {
+    if (two) launch(k_band_solve<KC, 2, double>, (const double*)c.v.fac);
+    else launch(k_band_solve<KC, 1, double>, (const double*)c.v.fac);
+  }
   LAUNCHCHK(c.p);
   return 0;
 }

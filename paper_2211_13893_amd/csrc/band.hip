@@ -313,17 +313,17 @@ __global__ __launch_bounds__(256) void k_chol_unit(const MatDesc* __restrict__ m
 }
 
 // Copies of the unit-lower band in the order the block solve reads it.  Solve
-// thread t (tile s = 1 + t/16, row quad rq = (t/2)%8, half h = t%2) of tile
-// row I holds 64 factor values as 32 double2 j:
+// thread t (tile s = 1 + 32p + t/16 of set p, row quad rq = (t/2)%8, half
+// h = t%2) of tile row I holds 64 factor values as 32 double2 j:
 //   forward  (tile (I, I-s)):     j = 8i + q2 -> Lu[4rq+i][16h+2q2 .. +1]
 //   backward (tile (I+s, I)^T):   j = 2q + e  -> Lu[16h+q][4rq+2e .. +1]
-// stored at ((I*32 + j) * nthr + t); tiles outside the matrix are zero.
-// grid.x strides over NT*32*nthr, grid.y = box.
+// stored at (((I*nsets + p)*32 + j) * nthr + t); tiles outside the matrix or
+// the band are zero.  grid.x strides over the copy, grid.y = box.
 __global__ void k_band_relayout(const BoxMeta* __restrict__ meta, int kind, double* __restrict__ fac) {
   const BoxMeta& bm = meta[blockIdx.y];
   BandView v = band_view(bm, kind);
-  const int nthr = solve_nthr(v.BT);
-  const int64_t total = (int64_t)v.NT * 32 * nthr;
+  const int nthr = solve_nthr(v.BT), nsets = solve_sets(v.BT);
+  const int64_t total = solve_copy_doubles(v.NT, v.BT) / 2;
   const double* L = fac + v.off;
   double2* fw = (double2*)(fac + v.fw);
   double2* bw = (double2*)(fac + v.bw);
@@ -331,15 +331,16 @@ __global__ void k_band_relayout(const BoxMeta* __restrict__ meta, int kind, doub
        e += (int64_t)gridDim.x * blockDim.x) {
     const int t = (int)(e % nthr);
     const int j = (int)((e / nthr) & 31);
-    const int I = (int)(e / ((int64_t)nthr * 32));
-    const int sidx = 1 + (t >> 4), rq = (t >> 1) & 7, h = t & 1;
+    const int64_t ip = e / ((int64_t)nthr * 32);
+    const int I = (int)(ip / nsets), set = (int)(ip % nsets);
+    const int sidx = 1 + SOLVE_TILES * set + (t >> 4), rq = (t >> 1) & 7, h = t & 1;
     double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-    if (sidx <= I) {
+    if (sidx < v.BT && sidx <= I) {
       const double* T = L + ((int64_t)I * v.BT + sidx) * MSG_TILE2;
       const int i = j >> 3, q2 = j & 7;
       a = *(const double2*)(T + (4 * rq + i) * 32 + 16 * h + 2 * q2);
     }
-    if (I + sidx < v.NT) {
+    if (sidx < v.BT && I + sidx < v.NT) {
       const double* T = L + ((int64_t)(I + sidx) * v.BT + sidx) * MSG_TILE2;
       const int q = j >> 1, c = j & 1;
       b = *(const double2*)(T + (16 * h + q) * 32 + 4 * rq + 2 * c);
@@ -360,27 +361,30 @@ __global__ void k_band_relayout(const BoxMeta* __restrict__ meta, int kind, doub
 // Forward sweep  y_I = f_I - sum_s Lu(I,I-s) y_{I-s}; backward sweep
 // x_I = w_I - sum_s Lu(I+s,I)^T x_{I+s}.  A step's work items are
 // (band tile s, row quad, half of the inner index): thread t handles tile
-// s = 1 + (t >> 4), rows 4*((t >> 1) & 7) .. +3 and inner indices
-// 16*(t & 1) .. +15, for all KC columns, so every solution row read from the
-// LDS ring feeds four factor rows.  The two halves are combined by a DPP lane
-// exchange that leaves each lane of the pair with two of the four rows
-// (reduce-scatter), the per-tile partial sums go through LDS and are added in
-// a fixed order by the first 32*KC threads.  The product w = D^{-1} y of the
-// previous forward step is formed by the last two wavefronts, which hold no
-// band tiles unless the band is wider than 25 tiles.
+// s = 1 + 32p + (t >> 4) of tile set p (NS sets, bands up to 32*NS + 1
+// tiles), rows 4*((t >> 1) & 7) .. +3 and inner indices 16*(t & 1) .. +15,
+// for all KC columns, so every solution row read from the LDS ring feeds four
+// factor rows.  The partial sums of a wavefront's 4 tile groups and 2 halves
+// are combined in registers by a reduce-scatter over lane ^ 1 (DPP), lane ^ 16
+// and lane ^ 32 (permlane swaps), leaving 4 of the 32 x KC sums per lane; the
+// 8 wavefronts' sums go through LDS and are added in a fixed order by the
+// first 32*KC threads.  The product w = D^{-1} y of the previous forward step
+// is formed by the last two wavefronts.
 //
-// Latency: the factor fragment of the next step is requested piece by piece
-// while the current one is used, so the loads stream during the arithmetic,
-// and stays in flight across the LDS-only barriers while the step is reduced.  For the compiler to wait for each
-// global load only where its own value is needed, every global load and
-// store of a step is issued by every thread, unconditionally and in the same
-// order: out-of-range work items read a valid address and discard the
+// Latency: the factor fragment of the next tile set or step is requested
+// piece by piece while the current one is used, so the loads stream during
+// the arithmetic, and stays in flight across the LDS-only barriers while the
+// step is reduced.  For the compiler to wait for each global load only where
+// its own value is needed, every global load and store of a step is issued by
+// every thread of a wavefront that holds tiles, unconditionally and in the
+// same order: out-of-range work items read a valid address and discard the
 // value, and stores without a target write the spare scratch row.
 //
 // The column chunks of one box share an XCD (block id mod 8) so the factor
 // they stream is read from HBM once and then hit in that XCD's L2.
 // grid.x = 8 * n_chunk * ceil(n_box/8), 512 threads; dynamic LDS = BT*32*KC doubles.
 #define SOLVE_THREADS 512
+#define SOLVE_WAVES (SOLVE_THREADS / 64)
 // Barrier for LDS traffic only (__syncthreads would also wait for every
 // global load).  Inside the sweeps no thread reads global memory that
 // another thread of the block wrote, so they need no global-memory barrier.
@@ -392,35 +396,45 @@ __device__ inline double dpp_xor1(double v) {
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+// a + a(lane ^ 16) on lanes with bit 4 clear, b + b(lane ^ 16) on the others
+__device__ inline double swap16_sum(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+// a + a(lane ^ 32) on lanes 0..31, b + b(lane ^ 32) on lanes 32..63
+__device__ inline double swap32_sum(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
 
 // f[i][q]: forward  = Lu[4rq+i][16h+q] of tile (I, I-s);
 //          backward = Lu[16h+q][4rq+i] of tile (I+s, I)  (row i of its transpose)
-// read from the solve-ordered copy F (fw or bw) of the band: consecutive
-// threads read consecutive 16-byte pieces.  tc < max(nthr, 1) is the
-// (clamped) thread slot; with nthr == 0 (no off-diagonal tiles) F points at
-// any valid 32 pieces and the values are not used.
+// read from the solve-ordered copy (fw or bw) of the band; consecutive
+// threads read consecutive 16-byte pieces.  P points at piece 0 of this
+// thread's slot of one (row, set); piece j is at P + j*nthr.
 template <typename T> struct vec2_of;
 template <> struct vec2_of<double> { typedef double2 type; };
 template <> struct vec2_of<float> { typedef float2 type; };
 
 template <typename T>
-__device__ inline void frag_load(const typename vec2_of<T>::type* __restrict__ F, int I, int nthr, int dir,
-                                 int tc, double (&f)[4][16]) {
-  const typename vec2_of<T>::type* p = F + (int64_t)I * 32 * nthr + tc;
+__device__ inline void frag_load(const typename vec2_of<T>::type* __restrict__ P, int nthr, int dir,
+                                 double (&f)[4][16]) {
   if (dir < 0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const auto a = p[(int64_t)(8 * i + q) * nthr];
+        const auto a = P[(int64_t)(8 * i + q) * nthr];
         f[i][2 * q] = a.x;
         f[i][2 * q + 1] = a.y;
       }
   } else {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const auto a = p[(int64_t)(2 * q) * nthr];
-      const auto b = p[(int64_t)(2 * q + 1) * nthr];
+      const auto a = P[(int64_t)(2 * q) * nthr];
+      const auto b = P[(int64_t)(2 * q + 1) * nthr];
       f[0][q] = a.x;
       f[1][q] = a.y;
       f[2][q] = b.x;
@@ -432,17 +446,18 @@ __device__ inline void frag_load(const typename vec2_of<T>::type* __restrict__ F
 // T: precision of the factor copies read by the sweeps (double, or float in
 // the mixed path; ft = the factor array in that precision, same offsets as
 // fac).  Arithmetic, right-hand sides and solutions are FP64 in both cases.
-template <int KC, typename T>
+template <int KC, int NS, typename T>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     const BoxMeta* __restrict__ meta, int n_box, int n_chunk, int kind,
-    const double* __restrict__ fac, const T* __restrict__ ft, const uint8_t* __restrict__ cls,
+    const T* __restrict__ ft, const uint8_t* __restrict__ cls,
     const double* in, double* out,
     int ldk, int out_classes, int zero_rest, double* __restrict__ scratch, int64_t scratch_stride,
     const int32_t* __restrict__ active) {
   static_assert(32 * KC == 256, "reduction threads = the first 256, w threads = the last 128");
-  static_assert(SOLVE_THREADS / 16 <= SOLVE_TILES, "one part slot per tile group");
+  static_assert(KC == 8, "the register reduce-scatter splits 8 columns over 4 tile groups");
+  static_assert(SOLVE_THREADS / 16 == SOLVE_TILES, "one tile group of 16 threads per tile of a set");
   extern __shared__ double ring[];   // [BT][32][KC]
-  __shared__ double part[SOLVE_TILES][32][KC + 1];
+  __shared__ double part[SOLVE_WAVES][32][KC + 1];
   __shared__ double Dl[32][33];      // D^{-1} tile of the current forward step
   __shared__ double Wl[32 * KC];     // w of the previous forward step
   const int x = blockIdx.x;
@@ -453,11 +468,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
   BandView v = band_view(bm, kind);
-  const double* L = fac + v.off;
   const uint8_t* cl = cls + bm.dof_off;
   const int tid = threadIdx.x;
   const int h = tid & 1, rq = (tid >> 1) & 7, sg = tid >> 4;  // item of the thread
-  const int s = 1 + sg;
+  const int g = sg & 3, wave = tid >> 6;                      // tile group inside the wavefront
   const bool red = tid < 32 * KC;
   const int t8 = tid & (32 * KC - 1);                         // reduction slot (duplicated above 256)
   const int rr = t8 / KC, cc = t8 % KC;
@@ -470,18 +484,20 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   double* w = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
   const int BT = v.BT, NT = v.NT;
   const int nthr = solve_nthr(BT);
+  const int nsets = NS == 1 ? 1 : solve_sets(BT);
   const int tc = nthr ? min(tid, nthr - 1) : 0;
-  // wavefronts without band tiles (uniform: the wave's first thread decides)
+  // wavefronts that hold band tiles (in set 0, which is full when set 1 is used)
   const bool wave_tiles = __builtin_amdgcn_readfirstlane(tid) < nthr;
   typedef typename vec2_of<T>::type V2;
-  const V2* Ffw = nthr ? (const V2*)(ft + v.fw) : (const V2*)(ft + v.off);
-  const V2* Fbw = nthr ? (const V2*)(ft + v.bw) : (const V2*)(ft + v.off);
+  const V2* Ffw = nthr ? (const V2*)(ft + v.fw) + tc : (const V2*)(ft + v.off);
+  const V2* Fbw = nthr ? (const V2*)(ft + v.bw) + tc : (const V2*)(ft + v.off);
+  auto slot = [&](const V2* F, int I, int p) { return F + (int64_t)(I * nsets + p) * 32 * nthr; };
   double f[4][16];
 
   // partial sums of this thread's item over its half of the inner index,
-  // with the factor fragment of the next step requested piece by piece as
-  // the current pieces are used (the loads are issued whether or not the
-  // thread has a tile this step, so every step issues the same loads)
+  // with the next fragment (Fn) requested piece by piece as the current
+  // pieces are used (the loads are issued whether or not the thread has a
+  // tile, so every step issues the same loads)
   auto accumulate = [&](bool has, const double* yp, double (&acc)[4][KC], const V2* Fn, int dir) {
     if (!wave_tiles) return;
 #pragma unroll
@@ -520,30 +536,39 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
       }
     }
   };
-  // lane pair (h = 0, 1): lane h keeps rows 2h, 2h+1 of the quad and adds the
-  // partner's sums of those rows; every part slot is written each step
-  auto store_part = [&](bool has, double (&acc)[4][KC]) {
+  // reduce-scatter of the wavefront's partial sums: after the three exchanges
+  // lane (g, rq, h) holds the wavefront total of rows 4rq+2h+i2 (i2 = 0, 1)
+  // and columns c + 2(g>>1) + 4(g&1) (c = 0, 1); every slot is written each step
+  auto store_part = [&](double (&acc)[4][KC]) {
+    double v1[2][KC];
 #pragma unroll
     for (int i2 = 0; i2 < 2; ++i2)
 #pragma unroll
       for (int c = 0; c < KC; ++c) {
         const double keep = h ? acc[2 + i2][c] : acc[i2][c];
         const double send = h ? acc[i2][c] : acc[2 + i2][c];
-        const double sum = keep + dpp_xor1(send);
-        part[sg][4 * rq + 2 * h + i2][c] = has ? sum : 0.0;
+        v1[i2][c] = keep + dpp_xor1(send);
       }
-  };
-  // sum over the SOLVE_TILES slots in a fixed order, four independent chains
-  auto part_sum = [&]() {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double v2[2][4];
 #pragma unroll
-    for (int q = 0; q < SOLVE_TILES; q += 4) {
+    for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v2[i2][c] = swap16_sum(v1[i2][c], v1[i2][c + 4]);
+#pragma unroll
+    for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        part[wave][4 * rq + 2 * h + i2][c + 2 * (g >> 1) + 4 * (g & 1)] = swap32_sum(v2[i2][c], v2[i2][c + 2]);
+  };
+  // sum over the wavefronts in a fixed order
+  auto part_sum = [&]() {
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < SOLVE_WAVES; q += 2) {
       a0 += part[q][rr][cc];
       a1 += part[q + 1][rr][cc];
-      a2 += part[q + 2][rr][cc];
-      a3 += part[q + 3][rr][cc];
     }
-    return (a0 + a1) + (a2 + a3);
+    return a0 + a1;
   };
   // Wl = D^{-1}_J y_J (D^{-1}_J in Dl, y_J in its ring slot), by the w threads
   auto form_w = [&](int J) {
@@ -569,11 +594,11 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   };
 
   // ---- forward: Lu y = f
-  frag_load<T>(Ffw, 0, nthr, -1, tc, f);
+  if (wave_tiles) frag_load<T>(slot(Ffw, 0, 0), nthr, -1, f);
   for (int I = 0; I < NT; ++I) {
     const int smax = min(BT - 1, I);
-    // right-hand side and D^{-1} tile of this step (used after the first barrier)
-    // (the class byte is tested after the barrier, so no wait is forced here)
+    // right-hand side and D^{-1} tile of this step (used after the first
+    // barrier; the class byte is tested there too, so no wait is forced here)
     const int dof = band_to_dof(v, bm, I * 32 + rr);
     const int dofc = dof >= 0 ? dof : 0;
     const double fraw = vin[(int64_t)dofc * ldk + colc];
@@ -584,10 +609,18 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     if (wthr && I >= 1) form_w(I - 1);
     double acc[4][KC];
     zero_acc(acc);
-    const bool has = s <= smax;
-    accumulate(has, ring + (int64_t)((has ? I - s : 0) % BT) * 32 * KC, acc,
-               Ffw + (int64_t)min(I + 1, NT - 1) * 32 * nthr + tc, -1);
-    store_part(has, acc);
+    const int In = min(I + 1, NT - 1);
+    const int s0 = 1 + sg;
+    const bool has0 = s0 <= smax;
+    const bool two = NS == 2 && nsets == 2;
+    accumulate(has0, ring + (int64_t)((has0 ? I - s0 : 0) % BT) * 32 * KC, acc,
+               two ? slot(Ffw, I, 1) : slot(Ffw, In, 0), -1);
+    if (two) {
+      const int s1 = 1 + SOLVE_TILES + sg;
+      const bool has1 = s1 <= smax;
+      accumulate(has1, ring + (int64_t)((has1 ? I - s1 : 0) % BT) * 32 * KC, acc, slot(Ffw, In, 0), -1);
+    }
+    store_part(acc);
     lds_barrier();
     w[(int64_t)((I >= 1 ? I - 1 : NT) * 32 + rr) * KC + cc] = Wl[t8];
     if (red) {
@@ -596,15 +629,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
       Dl[(e + 1) >> 5][(e + 1) & 31] = da.y;
       Dl[(e + 2) >> 5][(e + 2) & 31] = db.x;
       Dl[(e + 3) >> 5][(e + 3) & 31] = db.y;
-      double sum = part_sum();
-      // bands wider than 33 tiles: remaining tiles directly
-      for (int s2 = SOLVE_TILES + 1; s2 <= smax; ++s2) {
-        const double* p = L + ((int64_t)I * BT + s2) * MSG_TILE2 + rr * 32;
-        const double* yp = ring + (int64_t)((I - s2) % BT) * 32 * KC;
-        for (int q = 0; q < 32; ++q) sum += p[q] * yp[q * KC + cc];
-      }
       const bool fok = (dof >= 0) & colok & dof_active(kind, cb);
-      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = (fok ? fraw : 0.0) - sum;
+      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = (fok ? fraw : 0.0) - part_sum();
     }
     lds_barrier();
   }
@@ -614,7 +640,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   __syncthreads();
 
   // ---- backward: Lu^T x = w
-  frag_load<T>(Fbw, NT - 1, nthr, +1, tc, f);
+  if (wave_tiles) frag_load<T>(slot(Fbw, NT - 1, 0), nthr, +1, f);
   for (int I = NT - 1; I >= 0; --I) {
     const int smax = min(BT - 1, NT - 1 - I);
     const int row = I * 32 + rr;
@@ -623,20 +649,22 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     const uint8_t cb = cl[dof >= 0 ? dof : 0];
     double acc[4][KC];
     zero_acc(acc);
-    const bool has = s <= smax;
-    accumulate(has, ring + (int64_t)((has ? I + s : 0) % BT) * 32 * KC, acc,
-               Fbw + (int64_t)max(I - 1, 0) * 32 * nthr + tc, +1);
-    store_part(has, acc);
+    const int In = max(I - 1, 0);
+    const int s0 = 1 + sg;
+    const bool has0 = s0 <= smax;
+    const bool two = NS == 2 && nsets == 2;
+    accumulate(has0, ring + (int64_t)((has0 ? I + s0 : 0) % BT) * 32 * KC, acc,
+               two ? slot(Fbw, I, 1) : slot(Fbw, In, 0), +1);
+    if (two) {
+      const int s1 = 1 + SOLVE_TILES + sg;
+      const bool has1 = s1 <= smax;
+      accumulate(has1, ring + (int64_t)((has1 ? I + s1 : 0) % BT) * 32 * KC, acc, slot(Fbw, In, 0), +1);
+    }
+    store_part(acc);
     lds_barrier();
     double xv = 0.0;
     if (red) {
-      double sum = part_sum();
-      for (int s2 = SOLVE_TILES + 1; s2 <= smax; ++s2) {
-        const double* p = L + ((int64_t)(I + s2) * BT + s2) * MSG_TILE2 + rr;
-        const double* xp = ring + (int64_t)((I + s2) % BT) * 32 * KC;
-        for (int q = 0; q < 32; ++q) sum += p[q * 32] * xp[q * KC + cc];
-      }
-      xv = fv - sum;
+      xv = fv - part_sum();
       ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = xv;
     }
     // the solution goes to `out` where it belongs, else to the spare row
@@ -654,12 +682,14 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   }
 }
 
-template __global__ void k_band_solve<8, double>(const BoxMeta*, int, int, int, const double*, const double*,
-                                                 const uint8_t*, const double*, double*, int, int, int, double*,
-                                                 int64_t, const int32_t*);
-template __global__ void k_band_solve<8, float>(const BoxMeta*, int, int, int, const double*, const float*,
-                                                const uint8_t*, const double*, double*, int, int, int, double*,
-                                                int64_t, const int32_t*);
+#define SOLVE_INST(NS, T)                                                                                     \
+  template __global__ void k_band_solve<8, NS, T>(const BoxMeta*, int, int, int, const T*, const uint8_t*,   \
+                                                  const double*, double*, int, int, int, double*, int64_t,     \
+                                                  const int32_t*);
+SOLVE_INST(1, double)
+SOLVE_INST(2, double)
+SOLVE_INST(1, float)
+SOLVE_INST(2, float)
 
 
 // FP32 copies for the mixed path (same element offsets as the FP64 arrays):
@@ -677,7 +707,7 @@ __global__ void k_mixed_copies(const BoxMeta* __restrict__ meta, const double* _
     return;
   }
   BandView v = band_view(bm, blockIdx.z);
-  const int64_t nb = (int64_t)v.NT * 64 * solve_nthr(v.BT);
+  const int64_t nb = solve_copy_doubles(v.NT, v.BT);
   for (int64_t e = t0; e < nb; e += st) {
     fac32[v.fw + e] = (float)fac[v.fw + e];
     fac32[v.bw + e] = (float)fac[v.bw + e];

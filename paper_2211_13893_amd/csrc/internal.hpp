@@ -13,8 +13,9 @@
 //   * after factorisation the off-diagonal band of every box matrix is copied
 //     twice more, once per sweep direction of the block solve, in the order
 //     the solve's threads read it: fragment double2 j (0..31) of solve thread
-//     t (0..nthr-1) of tile row I at ((I*32 + j) * nthr + t) * 2, so that a
-//     wavefront's load instruction reads 1 KB of consecutive memory.
+//     t (0..nthr-1) for tile set p (tiles 1+32p .. 32+32p) of tile row I at
+//     (((I*nsets + p)*32 + j) * nthr + t) * 2, so that a wavefront's load
+//     instruction reads 1 KB of consecutive memory.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -53,10 +54,18 @@ struct BoxMeta {
   int64_t fh_fw, fh_bw;       // same for Ahat
 };
 
-// solve threads that hold a band fragment: 16 per off-diagonal tile
+// solve threads that hold a band fragment: 16 per off-diagonal tile of a set
 __host__ __device__ inline int solve_nthr(int BT) {
   int t = BT - 1 < SOLVE_TILES ? BT - 1 : SOLVE_TILES;
   return 16 * (t > 0 ? t : 0);
+}
+// tile sets of SOLVE_TILES off-diagonal tiles the solve walks per step (1 or 2;
+// bands up to 2*SOLVE_TILES + 1 tiles)
+#define SOLVE_MAX_BT (2 * SOLVE_TILES + 1)
+__host__ __device__ inline int solve_sets(int BT) { return BT - 1 > SOLVE_TILES ? 2 : 1; }
+// doubles of one solve-ordered copy of a band
+__host__ __device__ inline int64_t solve_copy_doubles(int NT, int BT) {
+  return (int64_t)NT * solve_sets(BT) * 64 * solve_nthr(BT);
 }
 
 // One SPD matrix in 32x32 tile-band storage (tiles at fac + off, inverse

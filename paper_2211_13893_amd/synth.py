@@ -368,6 +368,28 @@ def small_box(n: int = 4, core: int = 2, overlap: int = 1, ovs: int = 1, n_ev: i
                    np.arange(nsd, dtype=np.int32))
 
 
+def slab(nxy: int = 40, nz: int = 4, core: int = 20, overlap: int = 1, ovs: int = 1, n_ev: int = 8,
+         seed: int = 0) -> Problem:
+    """Thin laminate slab of unit elements (``nxy x nxy x nz``, one random ply
+    angle per element layer) tiled by ``core x core x nz`` cores.  Its
+    oversampled boxes have wide node planes (about ``(core+3)^2`` nodes), so
+    their banded matrices span more than 33 tiles of 32 rows: the wide-band
+    test problem.  Every core is in the batch."""
+    rng = _rng(8, seed)
+    nx = ny = nxy
+    xyz = _grid_xyz(np.arange(nx + 1, dtype=float), np.arange(ny + 1, dtype=float),
+                    np.arange(nz + 1, dtype=float))
+    kinds = ["ply" if rng.random() < 0.75 else "resin" for _ in range(nz)]
+    angles = [float(rng.choice([0.0, 45.0, -45.0, 90.0])) for _ in range(nz)]
+    mats = _layered_materials(kinds, angles)
+    elem_mat = _elem_mat_by_layer(nx, ny, nz)
+    cores = _tiles(nx, ny, nz, (core, core, nz))
+    nsd = cores.shape[0]
+    return Problem("slab", nx, ny, nz, xyz, elem_mat, mats,
+                   np.zeros(3 * (nx + 1) * (ny + 1) * (nz + 1), np.uint8), [], cores, overlap,
+                   np.full(nsd, ovs, np.int32), np.full(nsd, n_ev, np.int32), np.arange(nsd, dtype=np.int32))
+
+
 def start_block(n2: int, k: int, seed: int, item: int) -> np.ndarray:
     """Seeded Gaussian start block ``[n2, k]`` for iterative eigensolvers."""
     return _rng(11, seed * 1000003 + item).standard_normal((n2, k))

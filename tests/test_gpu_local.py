@@ -168,6 +168,15 @@ def _check_eigs(torch, prob, batch, n_ev, tol_nu=1e-8):
             assert ang <= bound
 
 
+def test_eigs_parity_wide_band(torch):
+    # boxes of 22 x 22 x 4 elements: the banded matrix of B1 u B2 spans
+    # 3 (23*23 + 23 + 1) + 2 = 1661 rows, more than 33 tiles of 32, so the
+    # block solve walks two tile sets per step
+    say("[eigs] wide-band slab, 4 boxes of 23 x 23 x 5 nodes, n_ev 8")
+    prob = synth.slab()
+    _check_eigs(torch, prob, [0, 1, 2, 3], 8)
+
+
 def test_eigs_parity_beam(torch):
     say("[eigs] beam, 4 subdomains, n_ev 10")
     prob = synth.laminated_beam()
