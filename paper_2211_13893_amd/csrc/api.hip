@@ -23,6 +23,8 @@ __global__ void k_band_build(const BoxMeta*, int, const double*, const uint8_t*,
                              double*);
 __global__ void k_chol_update(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_panel(const MatDesc*, int, double*);
+__global__ void k_chol_diag(const MatDesc*, int, double*, int32_t*);
+__global__ void k_chol_col(const MatDesc*, int, double*);
 __global__ void k_chol_unit(const MatDesc*, double*);
 __global__ void k_band_relayout(const BoxMeta*, int, double*);
 template <int KC, int NS, typename T>
@@ -545,6 +547,20 @@ static int tile_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_
   return 0;
 }
 
+// Left-looking tile Cholesky of banded SPD matrices (each factor tile is
+// written once): per tile column the diagonal tile, then the tiles below it;
+// then the block unit-lower rewrite.
+static int band_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_nt, int max_bt, double* fac,
+                         int32_t* status, hipStream_t s) {
+  for (int J = 0; J < max_nt; ++J) {
+    k_chol_diag<<<nmat, 256, 0, s>>>(mats, J, fac, status);
+    if (max_bt > 1 && J < max_nt - 1) k_chol_col<<<dim3(max_bt - 1, nmat), 256, 0, s>>>(mats, J, fac);
+  }
+  k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
+  LAUNCHCHK(p);
+  return 0;
+}
+
 extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status, void* stream) {
   if (!p || !ops || !status) return fail(p, MSGFEM_EARG, "null argument");
   if (set_device(p)) return MSGFEM_EHIP;
@@ -616,7 +632,7 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
       max_bt = std::max(max_bt, std::max(m.bt11, m.bth));
     }
     ProfScope ps(p, PK_POTRF, s, by, fl);
-    if (tile_cholesky(p, v.mats, (int)p->mats.size(), max_nt, max_bt, v.fac, status, s)) return MSGFEM_EHIP;
+    if (band_cholesky(p, v.mats, (int)p->mats.size(), max_nt, max_bt, v.fac, status, s)) return MSGFEM_EHIP;
   }
   for (int kind = 0; kind < 2; ++kind) {
     int64_t tot = 0;

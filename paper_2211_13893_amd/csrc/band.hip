@@ -287,6 +287,117 @@ __global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* __restrict__ 
   tile_store_acc(T, acc, lane);
 }
 
+// Left-looking tile Cholesky of banded matrices, two launches per tile column
+// J (the entries of A are read where they are stored and never updated in
+// place, so each factor tile is written once):
+//   k_chol_diag: C = A(J,J) - sum_t L(J,J-t) L(J,J-t)^T over 1 <= t <= min(J, BT-1),
+//                then L_JJ = chol(C) and its inverse;
+//   k_chol_col:  L(J+s,J) = (A(J+s,J) - sum_K L(J+s,K) L(J,K)^T) L_JJ^{-T}
+//                over max(0, J+s-BT+1) <= K <= J-1, for 1 <= s <= min(BT-1, NT-1-J).
+// One workgroup (4 wavefronts) per target tile; the tile products of a sum
+// are dealt round-robin to the wavefronts (matrix cores) and the four partial
+// sums are added in a fixed order through LDS.  (Folding the next diagonal
+// tile into the column launch lengthens the launch's critical path and was
+// slower.)
+
+// acc (per wavefront) -> sum of the 4 wavefronts' accumulators in wavefront 0
+__device__ inline void reduce_acc4(dbl4 acc[2][2], double* red, int wave, int lane) {
+  if (wave > 0) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[((wave - 1) * 16 + b * 4 + e) * 64 + lane] = acc[b >> 1][b & 1][e];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[b >> 1][b & 1][e] += red[(w * 16 + b * 4 + e) * 64 + lane];
+  }
+  __syncthreads();
+}
+
+__device__ inline void zero_acc4(dbl4 acc[2][2]) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
+}
+
+// diagonal tile D of tile row R (all of row R's off-diagonal tiles final)
+__device__ inline void chol_diag_tile(const MatDesc& v, int R, double* __restrict__ fac, double* red,
+                                     int32_t* __restrict__ status, int wave, int lane) {
+  double* L = fac + v.off;
+  dbl4 acc[2][2];
+  zero_acc4(acc);
+  const int m = min(R, v.BT - 1);
+  for (int t = 1 + wave; t <= m; t += 4) {
+    const double* T = L + ((int64_t)R * v.BT + t) * MSG_TILE2;
+    tile_mfma_abt(T, T, 1.0, acc, lane);
+  }
+  reduce_acc4(acc, red, wave, lane);
+  if (wave == 0) {
+    double* T = L + (int64_t)R * v.BT * MSG_TILE2;
+    dbl4 a[2][2];
+    tile_load_acc(T, a, lane);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) a[bi][bj] -= acc[bi][bj];
+    tile_store_acc(T, a, lane);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's tile stores are complete
+    const int bad = diag_tile_factor(T, fac + v.ioff + (int64_t)R * MSG_TILE2);
+    if (lane == 0 && bad) atomicOr(&status[v.status_idx], 4);
+  }
+}
+
+// grid (n_mat), 256 threads
+__global__ __launch_bounds__(256) void k_chol_diag(const MatDesc* __restrict__ mats, int J,
+                                                   double* __restrict__ fac, int32_t* __restrict__ status) {
+  __shared__ double red[3 * 16 * 64];
+  const MatDesc v = mats[blockIdx.x];
+  if (J >= v.NT) return;
+  chol_diag_tile(v, J, fac, red, status, threadIdx.x >> 6, threadIdx.x & 63);
+}
+
+// grid (max BT - 1, n_mat), 256 threads; block x = target s - 1 (this order
+// measured faster than dispatching the s = 1 targets of all matrices first)
+__global__ __launch_bounds__(256) void k_chol_col(const MatDesc* __restrict__ mats, int J,
+                                                  double* __restrict__ fac) {
+  __shared__ double red[3 * 16 * 64];
+  __shared__ double C[32 * 32];
+  const MatDesc v = mats[blockIdx.y];
+  const int s = 1 + blockIdx.x;
+  if (J >= v.NT || s > min(v.BT - 1, v.NT - 1 - J)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* L = fac + v.off;
+  dbl4 acc[2][2];
+  zero_acc4(acc);
+  const int kmin = max(0, J + s - (v.BT - 1));
+  for (int K = J - 1 - wave; K >= kmin; K -= 4) {
+    const double* Ta = L + ((int64_t)(J + s) * v.BT + (J + s - K)) * MSG_TILE2;   // L(J+s, K)
+    const double* Tb = L + ((int64_t)J * v.BT + (J - K)) * MSG_TILE2;             // L(J, K)
+    tile_mfma_abt(Ta, Tb, 1.0, acc, lane);
+  }
+  reduce_acc4(acc, red, wave, lane);
+  if (wave == 0) {
+    double* T = L + ((int64_t)(J + s) * v.BT + s) * MSG_TILE2;                   // A(J+s, J) -> L(J+s, J)
+    dbl4 a[2][2];
+    tile_load_acc(T, a, lane);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) a[bi][bj] -= acc[bi][bj];
+    tile_store_acc(C, a, lane);
+    zero_acc4(acc);
+    tile_mfma_abt(C, fac + v.ioff + (int64_t)J * MSG_TILE2, 1.0, acc, lane);
+    tile_store_acc(T, acc, lane);
+  }
+}
+
 // After the factorisation A = L L^T: rewrite the factor in block unit-lower
 // form A = Lu D Lu^T with Lu(I,J) = L(I,J) L_JJ^{-1} (off-diagonal tiles, in
 // place) and D^{-1}_II = L_II^{-T} L_II^{-1} stored in the diagonal tile slot,

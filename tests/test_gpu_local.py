@@ -177,6 +177,41 @@ def test_eigs_parity_wide_band(torch):
     _check_eigs(torch, prob, [0, 1, 2, 3], 8)
 
 
+def test_eigs_uneven_laminate_sampled(torch):
+    """The uneven batch: 168 boxes of 4.6k-25k DoF (bands of up to 48 tiles)
+    in one plan.  Every box: converged, rho <= 1e-6, lambda ascending, unit
+    eigenvectors that vanish on B3; the two smallest boxes against the oracle."""
+    say("[eigs] uneven laminate, 168 boxes")
+    prob = synth.uneven_laminate()
+    st = _stage(torch, prob, tol=1e-6)
+    st.msgfem_assemble_local()
+    out = st.msgfem_local_eigs()
+    torch.cuda.synchronize()
+    status = out["status"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()
+    say(f"  iterations min/mean/max {iters.min()}/{iters.mean():.2f}/{iters.max()}, status {sorted(set(status.tolist()))}")
+    assert np.all(status == 0)
+    dofs = np.array([b.n_dof for b in st.boxes])
+    for b in range(len(st.boxes)):
+        lam = st.eigvals(out, b).cpu().numpy()
+        assert st.resid(out, b).cpu().numpy().max() <= 1e-6
+        assert np.all(np.diff(lam) >= -1e-12 * max(1.0, abs(lam).max()))
+    kec = fem.KeCache(prob)
+    for b in np.argsort(dofs)[:2]:
+        j = int(prob.batch[b])
+        ops = gevp.local_ops(prob, j, kec)
+        n_ev = int(prob.n_ev[j])
+        ref = gevp.schur_gevp(ops, n_ev + 4)
+        lam = st.eigvals(out, int(b)).cpu().numpy()
+        phi = st.eigvecs(out, int(b)).cpu().numpy()
+        err = np.max(np.abs(1.0 / (lam + 1.0) - ref.nu[:n_ev]) / ref.nu[:n_ev])
+        hr = max(gevp.harmonic_residual(ops, phi[:, c]) for c in range(n_ev))
+        say(f"  box {b} (sd {j}, {dofs[b]} DoF, n_ev {n_ev}): nu rel err {err:.2e}, harmonic residual {hr:.2e}")
+        assert err <= 1e-8 and hr <= 1e-10
+        assert np.allclose(np.linalg.norm(phi, axis=0), 1.0, atol=1e-12)
+        assert np.all(phi[ops.cls == 3] == 0.0)
+
+
 def test_eigs_parity_beam(torch):
     say("[eigs] beam, 4 subdomains, n_ev 10")
     prob = synth.laminated_beam()
