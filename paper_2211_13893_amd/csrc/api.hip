@@ -635,17 +635,16 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
     if (band_cholesky(p, v.mats, (int)p->mats.size(), max_nt, max_bt, v.fac, status, s)) return MSGFEM_EHIP;
   }
   for (int kind = 0; kind < 2; ++kind) {
-    int64_t tot = 0;
+    int max_nt = 1, max_sets = 1;
     double by = 0;
     for (auto& m : p->meta) {
       int nt = kind == 0 ? m.nt11 : m.nth, bt = kind == 0 ? m.bt11 : m.bth;
-      int64_t e = solve_copy_doubles(nt, bt) / 2;
-      tot = std::max(tot, e);
-      by += 3 * 16.0 * e;
+      max_nt = std::max(max_nt, nt);
+      max_sets = std::max(max_sets, solve_sets(bt));
+      by += 3 * 8.0 * solve_copy_doubles(nt, bt);
     }
-    int64_t blocks = std::min<int64_t>((tot + 255) / 256, 65535);
     ProfScope ps(p, PK_BUILD, s, by, 0.0);
-    k_band_relayout<<<dim3((unsigned)std::max<int64_t>(blocks, 1), nb), 256, 0, s>>>(v.meta, kind, v.fac);
+    k_band_relayout<<<dim3(SOLVE_TILES * max_sets, max_nt, nb), 256, 0, s>>>(v.meta, kind, v.fac);
     LAUNCHCHK(p);
   }
   if (p->opts.precision == 1) {

@@ -429,35 +429,48 @@ __global__ __launch_bounds__(256) void k_chol_unit(const MatDesc* __restrict__ m
 //   forward  (tile (I, I-s)):     j = 8i + q2 -> Lu[4rq+i][16h+2q2 .. +1]
 //   backward (tile (I+s, I)^T):   j = 2q + e  -> Lu[16h+q][4rq+2e .. +1]
 // stored at (((I*nsets + p)*32 + j) * nthr + t); tiles outside the matrix or
-// the band are zero.  grid.x strides over the copy, grid.y = box.
-__global__ void k_band_relayout(const BoxMeta* __restrict__ meta, int kind, double* __restrict__ fac) {
-  const BoxMeta& bm = meta[blockIdx.y];
+// the band are zero.  One workgroup per (tile slot s, tile row I, box): it
+// stages the forward source tile (I, s) and the backward source tile
+// (I+s, s) in LDS with coalesced loads and writes the 16 threads' pieces of
+// each, 256 contiguous bytes per j.  grid (32*max nsets, max NT, n_box).
+__global__ __launch_bounds__(256) void k_band_relayout(const BoxMeta* __restrict__ meta, int kind,
+                                                       double* __restrict__ fac) {
+  __shared__ double Tf[MSG_TILE2], Tb[MSG_TILE2];
+  const BoxMeta& bm = meta[blockIdx.z];
   BandView v = band_view(bm, kind);
   const int nthr = solve_nthr(v.BT), nsets = solve_sets(v.BT);
-  const int64_t total = solve_copy_doubles(v.NT, v.BT) / 2;
+  const int s = 1 + blockIdx.x, I = blockIdx.y;
+  if (I >= v.NT || s > SOLVE_TILES * nsets || (nsets == 1 && s > v.BT - 1)) return;
+  const int p = (s - 1) / SOLVE_TILES, tbase = 16 * ((s - 1) % SOLVE_TILES);
   const double* L = fac + v.off;
+  const bool fok = s < v.BT && s <= I, bok = s < v.BT && I + s < v.NT;
+  const int u = threadIdx.x;
+  {
+    const double2* src = (const double2*)(L + ((int64_t)I * v.BT + (fok ? s : 0)) * MSG_TILE2);
+    const double2* srb = (const double2*)(L + ((int64_t)(bok ? I + s : I) * v.BT + (bok ? s : 0)) * MSG_TILE2);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const double2 a = fok ? src[u + 256 * r] : make_double2(0.0, 0.0);
+      const double2 b = bok ? srb[u + 256 * r] : make_double2(0.0, 0.0);
+      Tf[2 * (u + 256 * r)] = a.x;
+      Tf[2 * (u + 256 * r) + 1] = a.y;
+      Tb[2 * (u + 256 * r)] = b.x;
+      Tb[2 * (u + 256 * r) + 1] = b.y;
+    }
+  }
+  __syncthreads();
   double2* fw = (double2*)(fac + v.fw);
   double2* bw = (double2*)(fac + v.bw);
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int t = (int)(e % nthr);
-    const int j = (int)((e / nthr) & 31);
-    const int64_t ip = e / ((int64_t)nthr * 32);
-    const int I = (int)(ip / nsets), set = (int)(ip % nsets);
-    const int sidx = 1 + SOLVE_TILES * set + (t >> 4), rq = (t >> 1) & 7, h = t & 1;
-    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-    if (sidx < v.BT && sidx <= I) {
-      const double* T = L + ((int64_t)I * v.BT + sidx) * MSG_TILE2;
-      const int i = j >> 3, q2 = j & 7;
-      a = *(const double2*)(T + (4 * rq + i) * 32 + 16 * h + 2 * q2);
-    }
-    if (sidx < v.BT && I + sidx < v.NT) {
-      const double* T = L + ((int64_t)(I + sidx) * v.BT + sidx) * MSG_TILE2;
-      const int q = j >> 1, c = j & 1;
-      b = *(const double2*)(T + (16 * h + q) * 32 + 4 * rq + 2 * c);
-    }
-    fw[e] = a;
-    bw[e] = b;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int q = u + 256 * r;                 // piece: j = q / 16, thread slot tbase + q % 16
+    const int j = q >> 4, tl = q & 15;
+    const int rq = (tl >> 1) & 7, h = tl & 1;
+    const int64_t e = ((int64_t)(I * nsets + p) * 32 + j) * nthr + tbase + tl;
+    const int i = j >> 3, q2 = j & 7;
+    fw[e] = make_double2(Tf[(4 * rq + i) * 32 + 16 * h + 2 * q2], Tf[(4 * rq + i) * 32 + 16 * h + 2 * q2 + 1]);
+    const int qq = j >> 1, c = j & 1;
+    bw[e] = make_double2(Tb[(16 * h + qq) * 32 + 4 * rq + 2 * c], Tb[(16 * h + qq) * 32 + 4 * rq + 2 * c + 1]);
   }
 }
 
