@@ -893,8 +893,7 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
       OX.p[kind] = B[kind][3];
       OP.p[kind] = nullptr;
     }
-    int nq = (k + 3) / 4;
-    dim3 grid((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, nkinds);
+    dim3 grid((unsigned)((p->max_dof + 255) / 256), nb, nkinds);
     k_update<<<grid, 256, (size_t)2 * k * k * 8, c.s>>>(c.v.meta, 1, k, Z, OX, OP, c.w.Y, c.w.Yp, a_);
     LAUNCHCHK(p);
     for (int kind = 0; kind < 4; ++kind) std::swap(B[kind][0], B[kind][3]);
@@ -993,8 +992,7 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
       OX.p[kind] = B[kind][3];
       OP.p[kind] = B[kind][4];
     }
-    int nq = (k + 3) / 4;
-    dim3 grid((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, nkinds);
+    dim3 grid((unsigned)((p->max_dof + 255) / 256), nb, nkinds);
     double by = 0, fl = 0;
     for (int b = 0; b < nb; ++b) {
       if (!c.counts(b, act)) continue;
@@ -1265,8 +1263,7 @@ extern "C" int msgfem_coarse_assemble(msgfem_plan* p, const void* ops, void* wor
     }
     Zu.p[0][0] = V;
     OX.p[0] = Vn;
-    int nq = (k + 3) / 4;
-    k_update<<<dim3((unsigned)(((int64_t)p->max_dof * nq + 255) / 256), nb, 1), 256, (size_t)2 * k * k * 8, s>>>(
+    k_update<<<dim3((unsigned)((p->max_dof + 255) / 256), nb, 1), 256, (size_t)2 * k * k * 8, s>>>(
         v.meta, 1, k, Zu, OX, OP, c.w.Y, c.w.Yp, nullptr);
     LAUNCHCHK(p);
     std::swap(V, Vn);

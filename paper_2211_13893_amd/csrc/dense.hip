@@ -26,6 +26,7 @@ struct Blk3 {
 };
 
 #define GR_ROWS 32
+#define UPD_ROWS 256   // rows per k_update workgroup (4 wavefronts x 4 blocks of 16)
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -429,8 +430,13 @@ struct Out4 {
   double* p[4];
 };
 
-// X_new = Z Y, P_new = Z Yp for kind = blockIdx.z (0: Z~, 1: A Z~, 2: DAD Z~, 3: M Z)
-// thread per (row, column quad); dynamic LDS = 2*m*k doubles
+// X_new = Z Y, P_new = Z Yp for kind = blockIdx.z (0: Z~, 1: A Z~, 2: DAD Z~, 3: M Z),
+// Z = [Z_0 .. Z_{nblk-1}] of m = nblk*k columns, Y and Yp m x k per box.
+// FP64 matrix cores (16x16x4): a wavefront takes 16 rows at a time (4 blocks
+// of 16 rows per wavefront, UPD_ROWS rows per workgroup); the inner index
+// runs over the m columns of Z in steps of 4, the output columns in blocks
+// of 16 (k <= 32); Y and Yp are staged in LDS once per workgroup.
+// grid (ceil(max n_dof / UPD_ROWS), n_box, kinds); dynamic LDS = 2*m*k doubles
 __global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta, int nblk, int k,
                                                 Blk4x3 Z, Out4 OX, Out4 OP,
                                                 const double* __restrict__ Y,
@@ -450,6 +456,8 @@ __global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta
     }
     return;
   }
+  const int r_wg = blockIdx.x * UPD_ROWS;
+  if (r_wg >= bm.n_dof) return;
   const int m = nblk * k;
   double* ys = sm;
   double* yps = sm + m * k;
@@ -459,34 +467,54 @@ __global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta
     yps[t] = wantP ? Yp[(int64_t)box * m * k + t] : 0.0;
   }
   __syncthreads();
-  int nq = (k + 3) >> 2;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)bm.n_dof * nq) return;
-  int row = (int)(t / nq), c0 = 4 * (int)(t % nq);
-  double ax[4] = {}, ap[4] = {};
-  for (int b = 0; b < nblk; ++b) {
-    const double* zr = Z.p[kind][b] + (bm.dof_off * k) + (int64_t)row * k;
-    for (int cc = 0; cc < k; ++cc) {
-      double zv = zr[cc];
-      int i = b * k + cc;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nsteps = (m + 3) >> 2;
+  const int64_t base = bm.dof_off * k;
+  for (int rb = 0; rb < UPD_ROWS / 64; ++rb) {
+    const int r0 = r_wg + (wave * (UPD_ROWS / 64) + rb) * 16;
+    if (r0 >= bm.n_dof) break;
+    const int row = r0 + li;
+    const bool rok = row < bm.n_dof;
+    dbl4 ax[2], ap[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (c0 + j < k) {
-          ax[j] += zv * ys[i * k + c0 + j];
-          ap[j] += zv * yps[i * k + c0 + j];
+    for (int cb = 0; cb < 2; ++cb) {
+      ax[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+      ap[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+    int b = 0, cc = lk;                      // block and column of inner index 4 s + lk
+    for (int st = 0; st < nsteps; ++st) {
+      const int i = 4 * st + lk;
+      const double a = (rok && i < m) ? Z.p[kind][b][base + (int64_t)row * k + cc] : 0.0;
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        const int col = 16 * cb + li;
+        const bool ok = i < m && col < k;
+        ax[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ok ? ys[i * k + col] : 0.0, ax[cb], 0, 0, 0);
+        if (wantP) ap[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ok ? yps[i * k + col] : 0.0, ap[cb], 0, 0, 0);
+      }
+      cc += 4;
+      while (cc >= k && b < nblk) {
+        cc -= k;
+        ++b;
+      }
+      if (b >= nblk) b = nblk - 1;
+    }
+    // accumulator item v of lane l: row r0 + (l >> 4) + 4 v, column 16 cb + (l & 15)
+    double* ox = OX.p[kind] + base;
+    double* op = wantP ? OP.p[kind] + base : nullptr;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int col = 16 * cb + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ro = r0 + lk + 4 * v;
+        if (ro < bm.n_dof && col < k) {
+          ox[(int64_t)ro * k + col] = ax[cb][v];
+          if (wantP) op[(int64_t)ro * k + col] = ap[cb][v];
         }
       }
     }
-  }
-  double* ox = OX.p[kind] + (bm.dof_off * k) + (int64_t)row * k;
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (c0 + j < k) ox[c0 + j] = ax[j];
-  if (wantP) {
-    double* op = OP.p[kind] + (bm.dof_off * k) + (int64_t)row * k;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (c0 + j < k) op[c0 + j] = ap[j];
   }
 }
 
