@@ -30,6 +30,7 @@ __global__ void k_band_relayout(const BoxMeta*, int, double*);
 template <int KC, int NS, typename T>
 __global__ void k_band_solve(const BoxMeta*, int, int, int, const T*, const uint8_t*, const double*, double*, int,
                              int, int, double*, int64_t, const int32_t*);
+
 template <bool TWO, int CW, typename ST>
 __global__ void k_spmm(const BoxMeta*, int, int, const ST*, const uint8_t*, const double*, const double*,
                        double*, double*, int, int, double, const int32_t*);
@@ -118,6 +119,7 @@ struct msgfem_plan {
   int64_t nodes_total = 0, dofs_total = 0, fac_total = 0, vec_total = 0, evec_total = 0,
           eval_total = 0;
   int max_nodes = 0, max_dof = 0, max_nt = 0, max_bt = 0;
+  int max_bt_kind[2] = {0, 0};   // per matrix kind (A11, Ahat)
   int64_t max_fac_tiles = 0;
   int n_gchunk = 0;
   // work layout (bytes)
@@ -350,6 +352,8 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     p->max_dof = std::max(p->max_dof, m.n_dof);
     p->max_nt = std::max(p->max_nt, std::max(m.nt11, m.nth));
     p->max_bt = std::max(p->max_bt, std::max(m.bt11, m.bth));
+    p->max_bt_kind[0] = std::max(p->max_bt_kind[0], m.bt11);
+    p->max_bt_kind[1] = std::max(p->max_bt_kind[1], m.bth);
     p->max_fac_tiles = std::max(p->max_fac_tiles, (int64_t)std::max(m.nt11 * m.bt11, m.nth * m.bth));
     p->meta[b] = m;
   }
@@ -554,7 +558,7 @@ static int band_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_
                          int32_t* status, hipStream_t s) {
   for (int J = 0; J < max_nt; ++J) {
     k_chol_diag<<<nmat, 256, 0, s>>>(mats, J, fac, status);
-    if (max_bt > 1 && J < max_nt - 1) k_chol_col<<<dim3(max_bt - 1, nmat), 256, 0, s>>>(mats, J, fac);
+    if (J < max_nt - 1) k_chol_col<<<dim3(max_bt, nmat), 256, 0, s>>>(mats, J, fac);
   }
   k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
   LAUNCHCHK(p);
@@ -759,7 +763,7 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
                  const int32_t* active) {
   int nchunk = (kk + KC - 1) / KC;
   dim3 grid(8 * nchunk * ((c.nb + 7) / 8));
-  size_t lds = (size_t)c.p->max_bt * 32 * KC * 8;
+  size_t lds = (size_t)c.p->max_bt_kind[kind] * 32 * KC * 8;
   double by = 0, fl = 0;
   for (int b = 0; b < c.nb; ++b) {
     if (!c.counts(b, active)) continue;
@@ -771,7 +775,7 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
   }
   ProfScope ps(c.p, PK_SOLVE, c.s, by, fl);
   // bands wider than SOLVE_TILES + 1 tiles take two tile sets per step
-  const bool two = c.p->max_bt - 1 > SOLVE_TILES;
+  const bool two = c.p->max_bt_kind[kind] - 1 > SOLVE_TILES;
   auto launch = [&](auto kern, auto ft) {
     kern<<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, ft, c.v.cls, in, out, kk, out_classes, zero_rest,
                                   c.w.scr, c.p->scr_stride, active);

@@ -291,7 +291,8 @@ __global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* __restrict__ 
 // J (the entries of A are read where they are stored and never updated in
 // place, so each factor tile is written once):
 //   k_chol_diag: C = A(J,J) - sum_t L(J,J-t) L(J,J-t)^T over 1 <= t <= min(J, BT-1),
-//                then L_JJ = chol(C) and its inverse;
+//                then L_JJ = chol(C) and its inverse (the terms t >= 2 are
+//                subtracted ahead, by the column launch J-1);
 //   k_chol_col:  L(J+s,J) = (A(J+s,J) - sum_K L(J+s,K) L(J,K)^T) L_JJ^{-T}
 //                over max(0, J+s-BT+1) <= K <= J-1, for 1 <= s <= min(BT-1, NT-1-J).
 // One workgroup (4 wavefronts) per target tile; the tile products of a sum
@@ -327,16 +328,22 @@ __device__ inline void zero_acc4(dbl4 acc[2][2]) {
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
 }
 
-// diagonal tile D of tile row R (all of row R's off-diagonal tiles final)
-__device__ inline void chol_diag_tile(const MatDesc& v, int R, double* __restrict__ fac, double* red,
-                                     int32_t* __restrict__ status, int wave, int lane) {
+// Sum over t in [t0, t1] of L(R,R-t) L(R,R-t)^T subtracted from the diagonal
+// tile of row R.  factor != 0: then L_RR = chol and its inverse (all of row
+// R's off-diagonal tiles final); factor == 0: the partial result is stored
+// back for a later call.
+__device__ inline void chol_diag_tile(const MatDesc& v, int R, int t0, int t1, int factor,
+                                     double* __restrict__ fac, double* red, int32_t* __restrict__ status,
+                                     int wave, int lane) {
   double* L = fac + v.off;
   dbl4 acc[2][2];
   zero_acc4(acc);
-  const int m = min(R, v.BT - 1);
-  for (int t = 1 + wave; t <= m; t += 4) {
-    const double* T = L + ((int64_t)R * v.BT + t) * MSG_TILE2;
-    tile_mfma_abt(T, T, 1.0, acc, lane);
+  const int m = t1;
+  {
+    for (int t = t0 + wave; t <= m; t += 4) {
+      const double* T = L + ((int64_t)R * v.BT + t) * MSG_TILE2;
+      tile_mfma_abt(T, T, 1.0, acc, lane);
+    }
   }
   reduce_acc4(acc, red, wave, lane);
   if (wave == 0) {
@@ -348,9 +355,11 @@ __device__ inline void chol_diag_tile(const MatDesc& v, int R, double* __restric
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) a[bi][bj] -= acc[bi][bj];
     tile_store_acc(T, a, lane);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's tile stores are complete
-    const int bad = diag_tile_factor(T, fac + v.ioff + (int64_t)R * MSG_TILE2);
-    if (lane == 0 && bad) atomicOr(&status[v.status_idx], 4);
+    if (factor) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's tile stores are complete
+      const int bad = diag_tile_factor(T, fac + v.ioff + (int64_t)R * MSG_TILE2);
+      if (lane == 0 && bad) atomicOr(&status[v.status_idx], 4);
+    }
   }
 }
 
@@ -360,27 +369,35 @@ __global__ __launch_bounds__(256) void k_chol_diag(const MatDesc* __restrict__ m
   __shared__ double red[3 * 16 * 64];
   const MatDesc v = mats[blockIdx.x];
   if (J >= v.NT) return;
-  chol_diag_tile(v, J, fac, red, status, threadIdx.x >> 6, threadIdx.x & 63);
+  // the terms t >= 2 were subtracted by the previous column launch
+  chol_diag_tile(v, J, 1, min(J, min(1, v.BT - 1)), 1, fac, red, status, threadIdx.x >> 6, threadIdx.x & 63);
 }
 
-// grid (max BT - 1, n_mat), 256 threads; block x = target s - 1 (this order
-// measured faster than dispatching the s = 1 targets of all matrices first)
+// grid (max BT, n_mat), 256 threads; block x = target s (1 .. BT-1; this order
+// measured faster than dispatching the s = 1 targets of all matrices first);
+// block x = 0 subtracts the terms t >= 2 from the next diagonal tile, which
+// need no tile of column J, so that k_chol_diag(J+1) is left with t = 1.
 __global__ __launch_bounds__(256) void k_chol_col(const MatDesc* __restrict__ mats, int J,
                                                   double* __restrict__ fac) {
   __shared__ double red[3 * 16 * 64];
   __shared__ double C[32 * 32];
   const MatDesc v = mats[blockIdx.y];
-  const int s = 1 + blockIdx.x;
-  if (J >= v.NT || s > min(v.BT - 1, v.NT - 1 - J)) return;
+  const int s = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (s == 0) {
+    if (J + 1 < v.NT) chol_diag_tile(v, J + 1, 2, min(J + 1, v.BT - 1), 0, fac, red, nullptr, wave, lane);
+    return;
+  }
+  if (J >= v.NT || s > min(v.BT - 1, v.NT - 1 - J)) return;
   double* L = fac + v.off;
   dbl4 acc[2][2];
   zero_acc4(acc);
   const int kmin = max(0, J + s - (v.BT - 1));
-  for (int K = J - 1 - wave; K >= kmin; K -= 4) {
-    const double* Ta = L + ((int64_t)(J + s) * v.BT + (J + s - K)) * MSG_TILE2;   // L(J+s, K)
-    const double* Tb = L + ((int64_t)J * v.BT + (J - K)) * MSG_TILE2;             // L(J, K)
-    tile_mfma_abt(Ta, Tb, 1.0, acc, lane);
+  {
+    // L(J+s, K) L(J, K)^T over this wavefront's K
+    auto Ta = [&](int K) { return L + ((int64_t)(J + s) * v.BT + (J + s - K)) * MSG_TILE2; };
+    auto Tb = [&](int K) { return L + ((int64_t)J * v.BT + (J - K)) * MSG_TILE2; };
+    for (int K = J - 1 - wave; K >= kmin; K -= 4) tile_mfma_abt(Ta(K), Tb(K), 1.0, acc, lane);
   }
   reduce_acc4(acc, red, wave, lane);
   if (wave == 0) {
@@ -814,6 +831,7 @@ SOLVE_INST(1, double)
 SOLVE_INST(2, double)
 SOLVE_INST(1, float)
 SOLVE_INST(2, float)
+
 
 
 // FP32 copies for the mixed path (same element offsets as the FP64 arrays):

@@ -77,16 +77,18 @@ __global__ __launch_bounds__(256) void k_spmm(const BoxMeta* __restrict__ meta, 
       acc[cr][j] = 0.0;
       acc2[cr][j] = 0.0;
     }
+  // Neighbours outside the box have zero stencil blocks (the assembly writes
+  // all 27 blocks of every node), so their index is clamped into the box and
+  // the 27-point loop runs without branches.
+#pragma unroll 1
   for (int dz = -1; dz <= 1; ++dz) {
-    const int kk = lk + dz;
-    if (kk < 0 || kk >= bm.mz) continue;
+    const int kk = min(max(lk + dz, 0), bm.mz - 1);
+#pragma unroll 1
     for (int dy = -1; dy <= 1; ++dy) {
-      const int jj = lj + dy;
-      if (jj < 0 || jj >= bm.my) continue;
+      const int jj = min(max(lj + dy, 0), bm.my - 1);
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const int ii = li + dx;
-        if (ii < 0 || ii >= bm.mx) continue;
+        const int ii = min(max(li + dx, 0), bm.mx - 1);
         const int nn = ii + bm.mx * (jj + bm.my * kk);
         const int nb = nb_index(dx, dy, dz);
         double xv[3][CW];
