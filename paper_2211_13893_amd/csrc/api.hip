@@ -609,7 +609,7 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
     LAUNCHCHK(p);
   }
   for (int kind = 0; kind < 2; ++kind) {
-    int64_t tot = p->max_fac_tiles * 1024;
+    int64_t tot = p->max_fac_tiles * 128;
     int64_t blocks = std::min<int64_t>((tot + 255) / 256, 65535);
     dim3 grid((unsigned)blocks, nb);
     double by = 0;

@@ -54,46 +54,80 @@ __device__ inline bool dof_active(int kind, uint8_t c) {
   return kind == 0 ? (c == 1) : (c == 1 || c == 2);
 }
 
-// One thread per tile entry; grid.x over NT*BT*1024 of the largest box, grid.y = box.
+// One thread per 8 consecutive entries of a tile row (the row is decoded
+// once, the columns by increments); grid.x strides over NT*BT*128 of the
+// largest box, grid.y = box.  Entries beyond the matrix are identity rows,
+// entries between inactive DoFs identity or zero, the rest the stencil value
+// (times 1 + s mu_r mu_c for Ahat).
 __global__ void k_band_build(const BoxMeta* __restrict__ meta, int kind,
                              const double* __restrict__ stencil, const uint8_t* __restrict__ cls,
                              const double* __restrict__ mu1, double shift, double* __restrict__ fac) {
   const BoxMeta& bm = meta[blockIdx.y];
   BandView v = band_view(bm, kind);
-  int64_t total = (int64_t)v.NT * v.BT * MSG_TILE2;
+  const int64_t total = (int64_t)v.NT * v.BT * (MSG_TILE2 / 8);
   const double* st = stencil + bm.node_off * 243;
   const uint8_t* cl = cls + bm.dof_off;
   const double* m1 = mu1 + bm.dof_off;
+  double* out = fac + (kind == 0 ? bm.f11_off : bm.fh_off);
+  const int sxy = v.sx * v.sy;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
-    int e = (int)(t & 1023);
-    int64_t tile = t >> 10;
-    int I = (int)(tile / v.BT), s = (int)(tile % v.BT);
-    int r = e >> 5, c = e & 31;
-    int row = I * MSG_TILE + r, col = (I - s) * MSG_TILE + c;
-    double val = 0.0;
-    if (col < 0 || col > row) {
-      val = 0.0;
-    } else if (row >= v.n) {
-      val = (row == col) ? 1.0 : 0.0;
-    } else {
-      int dr = band_to_dof(v, bm, row), dc = band_to_dof(v, bm, col);
-      bool ar = dof_active(kind, cl[dr]), ac = dof_active(kind, cl[dc]);
-      if (!ar || !ac) {
-        val = (row == col) ? 1.0 : 0.0;
-      } else {
-        int nr = dr / 3, nc = dc / 3;
-        int ir = nr % bm.mx, jr = (nr / bm.mx) % bm.my, kr = nr / (bm.mx * bm.my);
-        int ic = nc % bm.mx, jc = (nc / bm.mx) % bm.my, kc = nc / (bm.mx * bm.my);
-        int dx = ic - ir, dy = jc - jr, dz = kc - kr;
-        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
-          int nb = nb_index(dx, dy, dz);
-          double a = st[(int64_t)(nb * 9 + 3 * (dr % 3) + (dc % 3)) * bm.n_nodes + nr];
-          val = (kind == 1) ? a * (1.0 + shift * m1[dr] * m1[dc]) : a;
+    const int g = (int)(t & 127);               // 8-entry group of the tile: row g/4, columns 8(g%4) ..
+    const int64_t tile = t >> 7;
+    const int I = (int)(tile / v.BT), s = (int)(tile % v.BT);
+    const int row = I * MSG_TILE + (g >> 2), col0 = (I - s) * MSG_TILE + 8 * (g & 3);
+    double val[8];
+    // row: sub-box node coordinates, component, DoF, class
+    const bool rin = row < v.n;
+    const int rnode = rin ? row / 3 : 0, rc = rin ? row - 3 * (row / 3) : 0;
+    const int ri = rnode % v.sx, rj = (rnode / v.sx) % v.sy, rk = rnode / sxy;
+    const int dr = 3 * ((ri + v.ox) + bm.mx * ((rj + v.oy) + bm.my * (rk + v.oz))) + rc;
+    const bool ar = rin && dof_active(kind, cl[dr]);
+    const double mr = (kind == 1 && rin) ? m1[dr] : 0.0;
+    // first column, then increments
+    const int c0 = max(col0, 0);
+    int cnode = c0 / 3, cc = c0 - 3 * cnode;
+    int ci = cnode % v.sx, cj = (cnode / v.sx) % v.sy, ck = cnode / sxy;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int col = col0 + q;
+      double x = 0.0;
+      if (col >= 0 && col <= row) {
+        if (!rin) {
+          x = (row == col) ? 1.0 : 0.0;
+        } else {
+          const int dc = 3 * ((ci + v.ox) + bm.mx * ((cj + v.oy) + bm.my * (ck + v.oz))) + cc;
+          const bool ac = dof_active(kind, cl[dc]);
+          if (!ar || !ac) {
+            x = (row == col) ? 1.0 : 0.0;
+          } else {
+            const int dx = ci - ri, dy = cj - rj, dz = ck - rk;
+            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
+              const int nr = dr / 3;
+              const double a = st[(int64_t)(nb_index(dx, dy, dz) * 9 + 3 * rc + cc) * bm.n_nodes + nr];
+              x = (kind == 1) ? a * (1.0 + shift * mr * m1[dc]) : a;
+            }
+          }
+        }
+      }
+      val[q] = x;
+      if (col >= 0) {
+        // next column: component, then node in the sub-box
+        if (++cc == 3) {
+          cc = 0;
+          if (++ci == v.sx) {
+            ci = 0;
+            if (++cj == v.sy) {
+              cj = 0;
+              ++ck;
+            }
+          }
         }
       }
     }
-    fac[(kind == 0 ? bm.f11_off : bm.fh_off) + t] = val;
+    double2* o = (double2*)(out + (tile << 10) + (g >> 2) * 32 + 8 * (g & 3));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = make_double2(val[2 * q], val[2 * q + 1]);
   }
 }
 
