@@ -8,7 +8,7 @@ residuals resident in HBM at the end.  The mesh, materials and decomposition
 are resident on the device before timing starts.
 
 Workload (default): the uniform batch of 64 interior 14^3-element oversampled
-boxes (10125 DoF each) of a ply/resin laminate, n_ev = 16, block 24, FP64.
+boxes (10125 DoF each) of a ply/resin laminate, n_ev = 16, block 32, FP64.
 
 Prints one JSON line: GEVPs/s (boxes whose n_ev pairs all reach
 rho <= 1e-6, per second) of the FP64 path, the roofline of its dominant
@@ -70,6 +70,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision path")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start path")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch workload")
+    ap.add_argument("--block", type=int, default=0, help="LOBPCG block width (0: the library's rule)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the local GEVPs of a batch "
@@ -84,7 +85,7 @@ def main():
     def run(precision: int, net=None, G=None, problem=None, steps=None, warmup=None):
         """Time `steps` full local stages (assembly + factorisation + LOBPCG;
         with a warm-start network also its features, inference and start block)."""
-        stage = msgfem.LocalStage(problem or prob, tol=1e-6, precision=precision)
+        stage = msgfem.LocalStage(problem or prob, tol=1e-6, precision=precision, block=args.block)
         steps = args.steps if steps is None else steps
         warmup = args.warmup if warmup is None else warmup
 
@@ -215,7 +216,7 @@ def main():
         "config": {"workload": "uniform_batch",
                    "description": f"{args.boxes} interior oversampled boxes of 14^3 Q1 elements "
                                   "(10125 DoF), 0.25 mm plies / 0.05 mm resin, core 8^3, overlap 1, "
-                                  "oversampling 2, n_ev 16, LOBPCG block 24, rho <= 1e-6, FP64 path",
+                                  f"oversampling 2, n_ev 16, LOBPCG block {int(stage.k)}, rho <= 1e-6, FP64 path",
                    "boxes": args.boxes, "n_ev": 16, "block": int(stage.k), "tol": 1e-6,
                    "path": "fp64", "parallelism": "subdomain batch on one GPU"},
         "converged": f"{conv}/{len(stage.batch)}",

@@ -82,7 +82,7 @@ typedef struct {
   double shift;     /* s > 0 of the shifted pencil M x = nu (S + s M) x (default 1) */
   double tol;       /* residual tolerance on rho (default 1e-6) */
   int32_t maxit;    /* LOBPCG iteration cap (default 200) */
-  int32_t block;    /* block width k >= max n_ev (0: n_ev + max(4, n_ev/2) rounded up to 8) */
+  int32_t block;    /* block width k >= max n_ev (0: max(2 n_ev, n_ev + 8) rounded up to 8); at most 32 */
   int32_t precision;/* 0 = FP64 throughout.  1 = mixed (A-harmonic GEVP only): the
                        assembly also keeps FP32 copies of the stencil and of the
                        factors' solve data (ops_bytes grows accordingly); LOBPCG

@@ -273,7 +273,10 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   if (maxnev < 1 || maxnev > 32) return fail(p, MSGFEM_EARG, "n_ev must be in [1, 32]");
   int k = o.block;
   if (k <= 0) {
-    k = maxnev + std::max(4, (maxnev + 1) / 2);
+    // twice n_ev, at least n_ev + 8: the block solves of 8-column chunks run
+    // side by side, so wider blocks cost little per iteration and cut the
+    // iteration count (uniform batch: 6.9 iterations at k = 32, 8.6 at 24)
+    k = std::max(2 * maxnev, maxnev + 8);
     k = (k + 7) / 8 * 8;
   }
   k = std::min(k, 32);

@@ -231,13 +231,13 @@ def test_eigs_parity_uniform_batch(torch):
 
 
 def test_eigs_full_uniform_batch_sampled(torch):
-    """The benchmark configuration itself: 64 interior 14^3 boxes, block 24,
+    """The benchmark configuration itself: 64 interior 14^3 boxes, block 32,
     rho <= 1e-6, one launch sequence as bench.py times it.  Three boxes are
     compared with the oracle's dense solve; every box is checked for what
     holds at any size: convergence, ascending eigenvalues, unit vectors with
     the sign convention, and the six rigid-body zeros of a floating box
     (Sec. 5.2) well separated from the seventh eigenvalue."""
-    say("[eigs] uniform batch at full size: 64 boxes, n_ev 16, block 24 (sampled boxes 0, 37, 63)")
+    say("[eigs] uniform batch at full size: 64 boxes, n_ev 16, block 32 (sampled boxes 0, 37, 63)")
     prob = synth.uniform_batch(n_boxes=64)
     st = _stage(torch, prob, tol=1e-6)
     st.msgfem_assemble_local()
@@ -246,7 +246,7 @@ def test_eigs_full_uniform_batch_sampled(torch):
     status = out["status"].cpu().numpy()
     iters = out["iters"].cpu().numpy()
     say(f"  iterations min/mean/max {iters.min()}/{iters.mean():.2f}/{iters.max()}, status {np.unique(status)}")
-    assert st.k == 24
+    assert st.k == 32
     assert np.all(status == 0)
     for b in range(len(st.batch)):
         lam = st.eigvals(out, b).cpu().numpy()
