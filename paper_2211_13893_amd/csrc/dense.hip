@@ -183,6 +183,8 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
   double* red = rs + m / 2;          // 256 reduction slots
   int* drop = (int*)(red + 256);     // m
   int* order = drop + m;             // m
+  int* pp = order + m;               // m/2: rotation pairs of the current round
+  int* qq = pp + m / 2;              // m/2
   const int tid = threadIdx.x;
   const double* GA = G + (int64_t)box * 2 * m * m;
   const double* GB = GA + m * m;
@@ -321,6 +323,8 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
       for (int i = tid; i < h; i += RR_THREADS) {
         int p, q;
         pair_of(r, i, p, q);
+        pp[i] = p;
+        qq[i] = q;
         const double apq = C[p * ld + q];
         const double app = C[p * ld + p], aqq = C[q * ld + q];
         double c = 1.0, sn = 0.0;
@@ -343,9 +347,7 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
       for (int t = tid; t < h * h + m * h; t += RR_THREADS) {
         if (t < h * h) {
           const int ia = t / h, ib = t - (t / h) * h;
-          int pa, qa, pb, qb;
-          pair_of(r, ia, pa, qa);
-          pair_of(r, ib, pb, qb);
+          const int pa = pp[ia], qa = qq[ia], pb = pp[ib], qb = qq[ib];
           const double ca = rc[ia], sa = rs[ia], cb = rc[ib], sb = rs[ib];
           const double b00 = C[pa * ld + pb], b01 = C[pa * ld + qb];
           const double b10 = C[qa * ld + pb], b11 = C[qa * ld + qb];
@@ -366,8 +368,7 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
         } else {
           const int u = t - h * h;
           const int row = u / h, i = u - (u / h) * h;
-          int p, q;
-          pair_of(r, i, p, q);
+          const int p = pp[i], q = qq[i];
           const double c = rc[i], sn = rs[i];
           const double vp = V[row * ld + p], vq = V[row * ld + q];
           V[row * ld + p] = c * vp - sn * vq;
