@@ -185,6 +185,8 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
   int* order = drop + m;             // m
   int* pp = order + m;               // m/2: rotation pairs of the current round
   int* qq = pp + m / 2;              // m/2
+  int* perm = qq + m / 2;            // m: active directions first (Jacobi on those only)
+  int* nj = perm + m;                // 1: size of the Jacobi block
   const int tid = threadIdx.x;
   const double* GA = G + (int64_t)box * 2 * m * m;
   const double* GB = GA + m * m;
@@ -267,16 +269,42 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
       C[i * ld + j] = a;
       C[j * ld + i] = a;
     }
+  }
+  __syncthreads();
+  // 4b. Directions dropped by the Cholesky (zero rows and columns of C, e.g.
+  //     the W and P columns of converged pairs) need no rotations: C is
+  //     permuted to P C P^T with the active directions first, and Jacobi runs
+  //     on the leading mj x mj block (mj = their count, made even with one
+  //     dropped direction if needed).
+  if (tid == 0) {
+    int a = 0;
+    for (int i = 0; i < m; ++i)
+      if (!drop[i]) perm[a++] = i;
+    const int na = a;
+    for (int i = 0; i < m; ++i)
+      if (drop[i]) perm[a++] = i;
+    nj[0] = min(m, max(2, na + (na & 1)));
+  }
+  __syncthreads();
+  for (int t = tid; t < m * m; t += RR_THREADS) {
+    const int i = t / m, j = t % m;
+    V[i * ld + j] = C[perm[i] * ld + perm[j]];
+  }
+  __syncthreads();
+  for (int t = tid; t < m * m; t += RR_THREADS) {
+    const int i = t / m, j = t % m;
+    C[i * ld + j] = V[i * ld + j];
     V[i * ld + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // 5. cyclic parallel Jacobi (round-robin pairing, m even).  Round r pairs
+  const int mj = nj[0];
+  // 5. cyclic parallel Jacobi (round-robin pairing, mj even).  Round r pairs
   //    (0, 1 + r mod (m-1)) and (1 + (r+i) mod (m-1), 1 + (r-i) mod (m-1)),
   //    i = 1..m/2-1; all m/2 rotations of a round commute.  A round computes
   //    the rotations, then applies them to C from both sides in one pass over
   //    the 2x2 blocks C[{p_a,q_a},{p_b,q_b}] <- R_a B R_b^T, R = [[c,-s],[s,c]],
   //    and to the columns of V (V <- V R^T).
-  const int h = m / 2, m1 = m - 1;
+  const int h = mj / 2, m1 = mj - 1;
   auto pair_of = [&](int r, int i, int& p, int& q) {
     if (i == 0) {
       p = 0;
@@ -295,8 +323,8 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
   for (int sweep = 0; sweep < 30; ++sweep) {
     // convergence test: off-diagonal mass vs. total (one barrier)
     double off = 0.0, tot = 0.0;
-    for (int t = tid; t < m * m; t += RR_THREADS) {
-      const int i = t / m, j = t - (t / m) * m;
+    for (int t = tid; t < mj * mj; t += RR_THREADS) {
+      const int i = t / mj, j = t - (t / mj) * mj;
       const double a = C[i * ld + j];
       tot += a * a;
       if (i != j) off += a * a;
@@ -344,7 +372,7 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
       }
       __syncthreads();
       // C <- R C R^T over 2x2 blocks; V <- V R^T over (row, pair)
-      for (int t = tid; t < h * h + m * h; t += RR_THREADS) {
+      for (int t = tid; t < h * h + mj * h; t += RR_THREADS) {
         if (t < h * h) {
           const int ia = t / h, ib = t - (t / h) * h;
           const int pa = pp[ia], qa = qq[ia], pb = pp[ib], qb = qq[ib];
@@ -378,11 +406,22 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
       __syncthreads();
     }
   }
-  // 6. sort eigenvalues descending (dropped directions have eigenvalue 0)
+  // 6. sort eigenvalues descending (dropped directions have eigenvalue 0);
+  //    eigenvector c is column c of V, its rows back in the original order
   for (int i = tid; i < m; i += RR_THREADS) {
     double e = C[i * ld + i];
     ev[i] = (e == e) ? e : -1.0e300;   // NaN ranks last
     order[i] = i;
+  }
+  __syncthreads();
+  for (int t = tid; t < m * m; t += RR_THREADS) {
+    const int i = t / m, c = t % m;
+    C[perm[i] * ld + c] = V[i * ld + c];
+  }
+  __syncthreads();
+  for (int t = tid; t < m * m; t += RR_THREADS) {
+    const int i = t / m, c = t % m;
+    V[i * ld + c] = C[i * ld + c];
   }
   __syncthreads();
   for (int i = tid; i < m; i += RR_THREADS) {
