@@ -411,7 +411,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(const MatDesc* __restrict__ m
 // measured faster than dispatching the s = 1 targets of all matrices first);
 // block x = 0 subtracts the terms t >= 2 from the next diagonal tile, which
 // need no tile of column J, so that k_chol_diag(J+1) is left with t = 1.
-__global__ __launch_bounds__(256) void k_chol_col(const MatDesc* __restrict__ mats, int J,
+__global__ __launch_bounds__(256, 4) void k_chol_col(const MatDesc* __restrict__ mats, int J,
                                                   double* __restrict__ fac) {
   __shared__ double red[3 * 16 * 64];
   __shared__ double C[32 * 32];
