@@ -23,8 +23,7 @@ __global__ void k_band_build(const BoxMeta*, int, const double*, const uint8_t*,
                              double*);
 __global__ void k_chol_update(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_panel(const MatDesc*, int, double*);
-__global__ void k_chol_diag(const MatDesc*, int, double*, int32_t*);
-__global__ void k_chol_col(const MatDesc*, int, double*);
+__global__ void k_chol_step(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_unit(const MatDesc*, double*);
 __global__ void k_band_relayout(const BoxMeta*, int, double*);
 template <int KC, int NS, typename T>
@@ -554,15 +553,13 @@ static int tile_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_
   return 0;
 }
 
-// Left-looking tile Cholesky of banded SPD matrices (each factor tile is
-// written once): per tile column the diagonal tile, then the tiles below it;
-// then the block unit-lower rewrite.
+// Left-looking tile Cholesky of banded SPD matrices, one launch per tile
+// column (which also factors the next diagonal tile), then the block
+// unit-lower rewrite.
 static int band_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_nt, int max_bt, double* fac,
                          int32_t* status, hipStream_t s) {
-  for (int J = 0; J < max_nt; ++J) {
-    k_chol_diag<<<nmat, 256, 0, s>>>(mats, J, fac, status);
-    if (J < max_nt - 1) k_chol_col<<<dim3(max_bt, nmat), 256, 0, s>>>(mats, J, fac);
-  }
+  for (int J = -1; J <= max_nt - 2; ++J)
+    k_chol_step<<<dim3(nmat, std::max(2, max_bt)), 256, 0, s>>>(mats, J, fac, status);
   k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
   LAUNCHCHK(p);
   return 0;

@@ -321,132 +321,264 @@ __global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* __restrict__ 
   tile_store_acc(T, acc, lane);
 }
 
-// Left-looking tile Cholesky of banded matrices, two launches per tile column
-// J (the entries of A are read where they are stored and never updated in
-// place, so each factor tile is written once):
-//   k_chol_diag: C = A(J,J) - sum_t L(J,J-t) L(J,J-t)^T over 1 <= t <= min(J, BT-1),
-//                then L_JJ = chol(C) and its inverse (the terms t >= 2 are
-//                subtracted ahead, by the column launch J-1);
-//   k_chol_col:  L(J+s,J) = (A(J+s,J) - sum_K L(J+s,K) L(J,K)^T) L_JJ^{-T}
-//                over max(0, J+s-BT+1) <= K <= J-1, for 1 <= s <= min(BT-1, NT-1-J).
-// One workgroup (4 wavefronts) per target tile; the tile products of a sum
-// are dealt round-robin to the wavefronts (matrix cores) and the four partial
-// sums are added in a fixed order through LDS.  (Folding the next diagonal
-// tile into the column launch lengthens the launch's critical path and was
-// slower.)
+// Left-looking tile Cholesky of banded matrices, one launch per step J
+// (J = -1 .. NT-2).  Invariant before step J: every tile of the columns
+// K <= J-1 is final; the diagonal tile J is factored and its inverse stored;
+// the tiles (I, J), I > J, and the diagonal tile J+1 hold A minus the
+// products with the columns K <= J-2.  Step J then computes, on disjoint
+// tiles, with blockIdx.y the role:
+//   role 0 (the step's chain): L(J+1,J) = (A(J+1,J) - L(J+1,J-1) L(J,J-1)^T) L_JJ^{-T},
+//          then C = A(J+1,J+1) - L(J+1,J-1) L(J+1,J-1)^T - L(J+1,J) L(J+1,J)^T,
+//          L_{J+1,J+1} = chol(C) and its inverse;
+//   role 1: the diagonal tile J+2 loses its products with K <= J-1;
+//   role s = 2 .. BT-1, row I = J+s:
+//          L(I,J) = (A(I,J) - L(I,J-1) L(J,J-1)^T) L_JJ^{-T}, and the tile
+//          (I,J+1) loses its products with K <= J-1 (all of which read only
+//          final tiles).
+// So the diagonal factor of a column is computed by the launch before the
+// one that needs it, next to the bulk of the tile products.  Each wavefront
+// owns one 16x16 quadrant of its workgroup's target tiles on the FP64
+// matrix cores (no cross-wavefront sums); the tile pair of the next product
+// is requested before the current one is multiplied.
+#define CH_LD 34   // LDS row stride (doubles) of staged tiles
 
-// acc (per wavefront) -> sum of the 4 wavefronts' accumulators in wavefront 0
-__device__ inline void reduce_acc4(dbl4 acc[2][2], double* red, int wave, int lane) {
-  if (wave > 0) {
+struct QuadOps {
+  double2 a[4], b[4];
+};
+
+// Operands of quadrant (bi, bj) of A B^T for row-major 32-column tiles A, B
+// (leading dimensions lda, ldb): lane (i = l&15, k = l>>4) supplies inner
+// index 8m + 2k + e at MFMA step 2m + e, i.e. 16 contiguous bytes per load.
+__device__ inline void quad_load(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
+                                 int bi, int bj, int lane, QuadOps& o) {
+  const int i = lane & 15, k = lane >> 4;
+  const double2* pa = reinterpret_cast<const double2*>(A + (16 * bi + i) * lda + 2 * k);
+  const double2* pb = reinterpret_cast<const double2*>(B + (16 * bj + i) * ldb + 2 * k);
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) red[((wave - 1) * 16 + b * 4 + e) * 64 + lane] = acc[b >> 1][b & 1][e];
+  for (int m = 0; m < 4; ++m) {
+    o.a[m] = pa[4 * m];
+    o.b[m] = pb[4 * m];
   }
-  __syncthreads();
-  if (wave == 0) {
-#pragma unroll
-    for (int w = 0; w < 3; ++w)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[b >> 1][b & 1][e] += red[(w * 16 + b * 4 + e) * 64 + lane];
-  }
-  __syncthreads();
 }
 
-__device__ inline void zero_acc4(dbl4 acc[2][2]) {
+__device__ inline void quad_mfma(const double2 a[4], const double2 b[4], dbl4& acc) {
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int m = 0; m < 4; ++m) {
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].x, b[m].x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].y, b[m].y, acc, 0, 0, 0);
+  }
 }
 
-// Sum over t in [t0, t1] of L(R,R-t) L(R,R-t)^T subtracted from the diagonal
-// tile of row R.  factor != 0: then L_RR = chol and its inverse (all of row
-// R's off-diagonal tiles final); factor == 0: the partial result is stored
-// back for a later call.
-__device__ inline void chol_diag_tile(const MatDesc& v, int R, int t0, int t1, int factor,
-                                     double* __restrict__ fac, double* red, int32_t* __restrict__ status,
-                                     int wave, int lane) {
-  double* L = fac + v.off;
-  dbl4 acc[2][2];
-  zero_acc4(acc);
-  const int m = t1;
-  {
-    for (int t = t0 + wave; t <= m; t += 4) {
-      const double* T = L + ((int64_t)R * v.BT + t) * MSG_TILE2;
-      tile_mfma_abt(T, T, 1.0, acc, lane);
+// quadrant (bi, bj) of a tile with leading dimension ld <-> accumulator layout
+// (item v of lane l = row (l>>4) + 4v, column l&15 of the quadrant)
+__device__ inline dbl4 quad_get(const double* __restrict__ C, int ld, int bi, int bj, int lane) {
+  const double* p = C + (16 * bi + (lane >> 4)) * ld + 16 * bj + (lane & 15);
+  return dbl4{p[0], p[4 * ld], p[8 * ld], p[12 * ld]};
+}
+
+__device__ inline void quad_put(double* __restrict__ C, int ld, int bi, int bj, int lane, dbl4 x) {
+  double* p = C + (16 * bi + (lane >> 4)) * ld + 16 * bj + (lane & 15);
+  p[0] = x[0];
+  p[4 * ld] = x[1];
+  p[8 * ld] = x[2];
+  p[12 * ld] = x[3];
+}
+
+// acc += sum over K = k1 down to k0 of L(ra,K)[bi] L(rb,K)[bj]^T (band tiles of
+// the matrix at L with BT tiles per row); with xb != nullptr, acc2 also gets
+// L(ra,k1)[bi] xb[bj]^T from the same A operand.  Two register sets: the next
+// K's operands are requested before the current product; all loads are
+// unconditional (the last request repeats k0).
+__device__ inline void quad_band_sum(const double* __restrict__ L, int BT, int ra, int rb, int k0, int k1,
+                                     const double* __restrict__ xb, int bi, int bj, int lane, dbl4& acc,
+                                     dbl4& acc2) {
+  if (k0 > k1) return;
+  auto ta = [&](int K) { return L + ((int64_t)ra * BT + (ra - K)) * MSG_TILE2; };
+  auto tb = [&](int K) { return L + ((int64_t)rb * BT + (rb - K)) * MSG_TILE2; };
+  QuadOps p, q;
+  quad_load(ta(k1), 32, tb(k1), 32, bi, bj, lane, p);
+  if (xb) {
+    const double2* pb = reinterpret_cast<const double2*>(xb + (16 * bj + (lane & 15)) * 32 + 2 * (lane >> 4));
+    double2 b[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) b[m] = pb[4 * m];
+    quad_mfma(p.a, b, acc2);
+  }
+  int K = k1;
+  for (;;) {
+    const int n1 = max(K - 1, k0);
+    quad_load(ta(n1), 32, tb(n1), 32, bi, bj, lane, q);
+    quad_mfma(p.a, p.b, acc);
+    if (--K < k0) break;
+    const int n2 = max(K - 1, k0);
+    quad_load(ta(n2), 32, tb(n2), 32, bi, bj, lane, p);
+    quad_mfma(q.a, q.b, acc);
+    if (--K < k0) break;
+  }
+}
+
+// One wavefront: C = L L^T for the 32x32 SPD tile C in LDS (stride CH_LD,
+// lower triangle read).  Writes L to Lg (row-major, zero above the diagonal)
+// and L^{-1} to Ig (row-major).  Lane (i, h) = (l&31, l>>5) holds columns
+// 16h .. 16h+15 of row i.  Right-looking: at step j the lanes holding column
+// j scale it, publish it in LDS (vec) and every lane updates its trailing
+// entries with its own row's multiplier and the broadcast column.  The
+// inverse is then formed by forward substitution, lane (c, h) holding rows
+// 16h .. 16h+15 of column c, the columns of L read from Lt (LDS, L^T).
+// dinv (32), vec (32), Lt (32 x CH_LD) are LDS scratch.  Returns 1 if a
+// pivot was not positive (it is replaced by 1).
+__device__ int factor_tile32(const double* __restrict__ C, double* __restrict__ Lt, double* __restrict__ dinv,
+                             double* __restrict__ vec, double* __restrict__ Lg, double* __restrict__ Ig) {
+  const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+  double a[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) a[c] = (16 * h + c <= i) ? C[i * CH_LD + 16 * h + c] : 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const int jh = j >> 4, jc = j & 15;
+    asm volatile("" ::: "memory");   // keep each step's LDS reads in their step (register pressure)
+    double d = lane_value(a[jc], j + 32 * jh);
+    if (!(d > 0.0)) {
+      d = 1.0;
+      bad = 1;
     }
+    const double sd = sqrt(d), inv = 1.0 / sd;
+    if (h == jh) {
+      const double l = (i == j) ? sd : (i > j ? a[jc] * inv : 0.0);
+      a[jc] = l;
+      vec[i] = l;
+    }
+    if (lane == 0) dinv[j] = inv;
+    // the other half's lanes read what these lanes wrote: no load may move above
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    const double li = vec[i];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const double m = vec[16 * h + c];
+      // column j itself is final; earlier columns see m = 0
+      if (c != jc || h != jh) a[c] -= li * m;
+    }
+    // keep the update in its step (deferring it keeps every multiplier live)
+#pragma unroll
+    for (int c = 0; c < 16; ++c) asm volatile("" : "+v"(a[c]));
   }
-  reduce_acc4(acc, red, wave, lane);
-  if (wave == 0) {
-    double* T = L + (int64_t)R * v.BT * MSG_TILE2;
-    dbl4 a[2][2];
-    tile_load_acc(T, a, lane);
+  // rows of L to global memory, columns to Lt
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+  for (int c = 0; c < 16; ++c) {
+    const int q = 16 * h + c;
+    const double w = (q <= i) ? a[c] : 0.0;
+    Lg[i * 32 + q] = w;
+    Lt[q * CH_LD + i] = w;
+  }
+  double x[16];
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) a[bi][bj] -= acc[bi][bj];
-    tile_store_acc(T, a, lane);
-    if (factor) {
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's tile stores are complete
-      const int bad = diag_tile_factor(T, fac + v.ioff + (int64_t)R * MSG_TILE2);
+  for (int r = 0; r < 16; ++r) x[r] = (16 * h + r == i) ? 1.0 : 0.0;
+#pragma unroll
+  for (int jj = 0; jj < 32; ++jj) {
+    const int jh = jj >> 4, jr = jj & 15;
+    asm volatile("" ::: "memory");
+    if (h == jh) {
+      x[jr] *= dinv[jj];
+      vec[i] = x[jr];
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    const double xj = vec[i];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const double m = Lt[jj * CH_LD + 16 * h + r];   // L(16h+r, jj): zero above the diagonal
+      if (r != jr || h != jh) x[r] -= m * xj;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) asm volatile("" : "+v"(x[r]));
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) Ig[(16 * h + r) * 32 + i] = x[r];
+  return bad;
+}
+
+// grid (n_mat, max(2, max BT)), 256 threads; blockIdx.x is the matrix, so the
+// role-0 workgroups of all matrices are dispatched first.
+__global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict__ mats, int J,
+                                                      double* __restrict__ fac, int32_t* __restrict__ status) {
+  __shared__ __align__(16) double X[32 * CH_LD];
+  __shared__ __align__(16) double Y[32 * CH_LD];
+  __shared__ double dinv[32], vec[32];
+  const MatDesc v = mats[blockIdx.x];
+  const int role = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int bi = wave >> 1, bj = wave & 1;
+  const int BT = v.BT, NT = v.NT;
+  double* L = fac + v.off;
+  auto tile = [&](int I, int K) { return L + ((int64_t)I * BT + (I - K)) * MSG_TILE2; };
+  const double* LinvJ = fac + v.ioff + (int64_t)(J < 0 ? 0 : J) * MSG_TILE2;
+  const dbl4 zero = {0.0, 0.0, 0.0, 0.0};
+
+  if (role == 0) {
+    const int R = J + 1;
+    if (R > NT - 1) return;
+    const bool has_x = J >= 0 && BT >= 2;    // tile (R, J) exists
+    const bool has_k = J >= 1 && BT >= 3;    // tiles (R, J-1), (J, J-1) exist
+    dbl4 accx = zero, accd = zero;
+    if (has_k) {
+      QuadOps o;
+      quad_load(tile(R, J - 1), 32, tile(J, J - 1), 32, bi, bj, lane, o);
+      QuadOps d;
+      quad_load(tile(R, J - 1), 32, tile(R, J - 1), 32, bi, bj, lane, d);
+      quad_mfma(o.a, o.b, accx);
+      quad_mfma(d.a, d.b, accd);
+    }
+    if (has_x) {
+      quad_put(X, CH_LD, bi, bj, lane, quad_get(tile(R, J), 32, bi, bj, lane) - accx);
+      __syncthreads();
+      QuadOps o;
+      quad_load(X, CH_LD, LinvJ, 32, bi, bj, lane, o);
+      dbl4 l = zero;
+      quad_mfma(o.a, o.b, l);
+      quad_put(tile(R, J), 32, bi, bj, lane, l);
+      quad_put(Y, CH_LD, bi, bj, lane, l);
+      __syncthreads();
+      quad_load(Y, CH_LD, Y, CH_LD, bi, bj, lane, o);
+      quad_mfma(o.a, o.b, accd);
+    }
+    quad_put(X, CH_LD, bi, bj, lane, quad_get(tile(R, R), 32, bi, bj, lane) - accd);
+    __syncthreads();
+    if (wave == 0) {
+      const int bad = factor_tile32(X, Y, dinv, vec, tile(R, R), fac + v.ioff + (int64_t)R * MSG_TILE2);
       if (lane == 0 && bad) atomicOr(&status[v.status_idx], 4);
     }
-  }
-}
-
-// grid (n_mat), 256 threads
-__global__ __launch_bounds__(256) void k_chol_diag(const MatDesc* __restrict__ mats, int J,
-                                                   double* __restrict__ fac, int32_t* __restrict__ status) {
-  __shared__ double red[3 * 16 * 64];
-  const MatDesc v = mats[blockIdx.x];
-  if (J >= v.NT) return;
-  // the terms t >= 2 were subtracted by the previous column launch
-  chol_diag_tile(v, J, 1, min(J, min(1, v.BT - 1)), 1, fac, red, status, threadIdx.x >> 6, threadIdx.x & 63);
-}
-
-// grid (max BT, n_mat), 256 threads; block x = target s (1 .. BT-1; this order
-// measured faster than dispatching the s = 1 targets of all matrices first);
-// block x = 0 subtracts the terms t >= 2 from the next diagonal tile, which
-// need no tile of column J, so that k_chol_diag(J+1) is left with t = 1.
-__global__ __launch_bounds__(256, 4) void k_chol_col(const MatDesc* __restrict__ mats, int J,
-                                                  double* __restrict__ fac) {
-  __shared__ double red[3 * 16 * 64];
-  __shared__ double C[32 * 32];
-  const MatDesc v = mats[blockIdx.y];
-  const int s = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (s == 0) {
-    if (J + 1 < v.NT) chol_diag_tile(v, J + 1, 2, min(J + 1, v.BT - 1), 0, fac, red, nullptr, wave, lane);
     return;
   }
-  if (J >= v.NT || s > min(v.BT - 1, v.NT - 1 - J)) return;
-  double* L = fac + v.off;
-  dbl4 acc[2][2];
-  zero_acc4(acc);
-  const int kmin = max(0, J + s - (v.BT - 1));
-  {
-    // L(J+s, K) L(J, K)^T over this wavefront's K
-    auto Ta = [&](int K) { return L + ((int64_t)(J + s) * v.BT + (J + s - K)) * MSG_TILE2; };
-    auto Tb = [&](int K) { return L + ((int64_t)J * v.BT + (J - K)) * MSG_TILE2; };
-    for (int K = J - 1 - wave; K >= kmin; K -= 4) tile_mfma_abt(Ta(K), Tb(K), 1.0, acc, lane);
+  if (role == 1) {
+    const int R = J + 2;
+    if (R > NT - 1 || bi < bj) return;       // the upper quadrant of a diagonal tile is not read
+    const int k0 = max(0, R - (BT - 1)), k1 = J - 1;
+    if (k0 > k1) return;
+    dbl4 acc = zero, unused = zero;
+    quad_band_sum(L, BT, R, R, k0, k1, nullptr, bi, bj, lane, acc, unused);
+    double* T = tile(R, R);
+    quad_put(T, 32, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - acc);
+    return;
   }
-  reduce_acc4(acc, red, wave, lane);
-  if (wave == 0) {
-    double* T = L + ((int64_t)(J + s) * v.BT + s) * MSG_TILE2;                   // A(J+s, J) -> L(J+s, J)
-    dbl4 a[2][2];
-    tile_load_acc(T, a, lane);
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) a[bi][bj] -= acc[bi][bj];
-    tile_store_acc(C, a, lane);
-    zero_acc4(acc);
-    tile_mfma_abt(C, fac + v.ioff + (int64_t)J * MSG_TILE2, 1.0, acc, lane);
-    tile_store_acc(T, acc, lane);
+  const int s = role, I = J + s;
+  if (J < 0 || s > BT - 1 || I > NT - 1) return;
+  // (I, J+1): products with K in [k0, J-1]; the first of them (K = J-1) shares
+  // its A operand L(I, J-1) with the product of the (I, J) target
+  const int k0 = max(0, I - (BT - 1)), k1 = J - 1;
+  dbl4 accb = zero, acca = zero;
+  quad_band_sum(L, BT, I, J + 1, k0, k1, k0 <= k1 ? tile(J, J - 1) : nullptr, bi, bj, lane, accb, acca);
+  if (k0 <= k1) {
+    double* T = tile(I, J + 1);
+    quad_put(T, 32, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - accb);
   }
+  double* T = tile(I, J);
+  quad_put(X, CH_LD, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - acca);
+  __syncthreads();
+  QuadOps o;
+  quad_load(X, CH_LD, LinvJ, 32, bi, bj, lane, o);
+  dbl4 l = zero;
+  quad_mfma(o.a, o.b, l);
+  quad_put(T, 32, bi, bj, lane, l);
 }
 
 // After the factorisation A = L L^T: rewrite the factor in block unit-lower
