@@ -417,6 +417,48 @@ __device__ inline void quad_band_sum(const double* __restrict__ L, int BT, int r
   }
 }
 
+// Two targets sharing the A operand: acc1 += sum_K L(ra,K)[bi] L(rb1,K)[bj]^T
+// and acc2 += sum_K L(ra,K)[bi] L(rb2,K)[bj]^T over K = k1 down to k0, and
+// accx += L(ra,k1)[bi] xb[bj]^T.  The next K's A operand and first B operand
+// are requested before the current products.
+__device__ inline void quad_band_sum2(const double* __restrict__ L, int BT, int ra, int rb1, int rb2, int k0,
+                                      int k1, const double* __restrict__ xb, int bi, int bj, int lane,
+                                      dbl4& acc1, dbl4& acc2, dbl4& accx) {
+  if (k0 > k1) return;
+  auto ta = [&](int K) { return L + ((int64_t)ra * BT + (ra - K)) * MSG_TILE2; };
+  auto tb1 = [&](int K) { return L + ((int64_t)rb1 * BT + (rb1 - K)) * MSG_TILE2; };
+  auto tb2 = [&](int K) { return L + ((int64_t)rb2 * BT + (rb2 - K)) * MSG_TILE2; };
+  const int i = lane & 15, k = lane >> 4;
+  auto ld4 = [&](const double* T, int b, double2 o[4]) {
+    const double2* p = reinterpret_cast<const double2*>(T + (16 * b + i) * 32 + 2 * k);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) o[m] = p[4 * m];
+  };
+  double2 a[4], b1[4], b2[4], an[4], b1n[4];
+  ld4(ta(k1), bi, a);
+  ld4(tb1(k1), bj, b1);
+  ld4(tb2(k1), bj, b2);
+  {
+    double2 bx[4];
+    ld4(xb, bj, bx);
+    quad_mfma(a, bx, accx);
+  }
+  for (int K = k1;; --K) {
+    const int n = max(K - 1, k0);
+    ld4(ta(n), bi, an);
+    ld4(tb1(n), bj, b1n);
+    quad_mfma(a, b1, acc1);
+    quad_mfma(a, b2, acc2);
+    if (K == k0) break;
+    ld4(tb2(n), bj, b2);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      a[m] = an[m];
+      b1[m] = b1n[m];
+    }
+  }
+}
+
 // One wavefront: C = L L^T for the 32x32 SPD tile C in LDS (stride CH_LD,
 // lower triangle read).  Writes L to Lg (row-major, zero above the diagonal)
 // and L^{-1} to Ig (row-major).  Lane (i, h) = (l&31, l>>5) holds columns
@@ -497,8 +539,16 @@ __device__ int factor_tile32(const double* __restrict__ C, double* __restrict__ 
   return bad;
 }
 
-// grid (n_mat, max(2, max BT)), 256 threads; blockIdx.x is the matrix, so the
-// role-0 workgroups of all matrices are dispatched first.
+// Column pairs: the products that read only final tiles are taken two columns
+// at a time, so each band tile is read once per pair.  At odd J ("pair
+// steps") the rows pre-subtract their products with K <= J-1 from both
+// (I,J+1) and (I,J+2), and the diagonal tiles J+2, J+3 lose theirs; at even J
+// the rows only subtract L(I,J-1) L(J+1,J-1)^T from (I,J+1).  The diagonal
+// tile J+1 factored at step J then still needs the products with K from J-1
+// (J even) or J-2 (J odd) up to J.
+// grid (n_mat, max(2, max BT) + 1), 256 threads; blockIdx.x is the matrix, so
+// the role-0 workgroups of all matrices are dispatched first; the last role
+// is the diagonal tile J+3.
 __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict__ mats, int J,
                                                       double* __restrict__ fac, int32_t* __restrict__ status) {
   __shared__ __align__(16) double X[32 * CH_LD];
@@ -513,19 +563,24 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
   auto tile = [&](int I, int K) { return L + ((int64_t)I * BT + (I - K)) * MSG_TILE2; };
   const double* LinvJ = fac + v.ioff + (int64_t)(J < 0 ? 0 : J) * MSG_TILE2;
   const dbl4 zero = {0.0, 0.0, 0.0, 0.0};
+  const bool pair = (J & 1) != 0;
 
   if (role == 0) {
     const int R = J + 1;
     if (R > NT - 1) return;
     const bool has_x = J >= 0 && BT >= 2;    // tile (R, J) exists
     const bool has_k = J >= 1 && BT >= 3;    // tiles (R, J-1), (J, J-1) exist
+    // first K of the diagonal tile's remaining products
+    const int kd = max(max(0, R - (BT - 1)), pair ? J - 2 : J - 1);
     dbl4 accx = zero, accd = zero;
     if (has_k) {
       QuadOps o;
       quad_load(tile(R, J - 1), 32, tile(J, J - 1), 32, bi, bj, lane, o);
-      QuadOps d;
-      quad_load(tile(R, J - 1), 32, tile(R, J - 1), 32, bi, bj, lane, d);
       quad_mfma(o.a, o.b, accx);
+    }
+    for (int K = kd; K <= J - 1; ++K) {
+      QuadOps d;
+      quad_load(tile(R, K), 32, tile(R, K), 32, bi, bj, lane, d);
       quad_mfma(d.a, d.b, accd);
     }
     if (has_x) {
@@ -549,9 +604,9 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
     }
     return;
   }
-  if (role == 1) {
-    const int R = J + 2;
-    if (R > NT - 1 || bi < bj) return;       // the upper quadrant of a diagonal tile is not read
+  if (role == 1 || role == (int)gridDim.y - 1) {
+    const int R = role == 1 ? J + 2 : J + 3;
+    if (!pair || R > NT - 1 || bi < bj) return;   // the upper quadrant of a diagonal tile is not read
     const int k0 = max(0, R - (BT - 1)), k1 = J - 1;
     if (k0 > k1) return;
     dbl4 acc = zero, unused = zero;
@@ -562,11 +617,19 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
   }
   const int s = role, I = J + s;
   if (J < 0 || s > BT - 1 || I > NT - 1) return;
-  // (I, J+1): products with K in [k0, J-1]; the first of them (K = J-1) shares
-  // its A operand L(I, J-1) with the product of the (I, J) target
-  const int k0 = max(0, I - (BT - 1)), k1 = J - 1;
+  // (I, J+1) (and at pair steps (I, J+2)): products with K in [k0, J-1] (at
+  // other steps K = J-1 only); the one with K = J-1 shares its A operand
+  // L(I, J-1) with the product of the (I, J) target
+  const int k1 = J - 1, k0 = pair ? max(0, I - (BT - 1)) : max(max(0, I - (BT - 1)), k1);
   dbl4 accb = zero, acca = zero;
-  quad_band_sum(L, BT, I, J + 1, k0, k1, k0 <= k1 ? tile(J, J - 1) : nullptr, bi, bj, lane, accb, acca);
+  if (pair && s >= 3 && k0 <= k1) {
+    dbl4 accc = zero;
+    quad_band_sum2(L, BT, I, J + 1, J + 2, k0, k1, tile(J, J - 1), bi, bj, lane, accb, accc, acca);
+    double* T2 = tile(I, J + 2);
+    quad_put(T2, 32, bi, bj, lane, quad_get(T2, 32, bi, bj, lane) - accc);
+  } else {
+    quad_band_sum(L, BT, I, J + 1, k0, k1, k0 <= k1 ? tile(J, J - 1) : nullptr, bi, bj, lane, accb, acca);
+  }
   if (k0 <= k1) {
     double* T = tile(I, J + 1);
     quad_put(T, 32, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - accb);
