@@ -559,7 +559,7 @@ static int tile_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_
 static int band_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_nt, int max_bt, double* fac,
                          int32_t* status, hipStream_t s) {
   for (int J = -1; J <= max_nt - 2; ++J)
-    k_chol_step<<<dim3(nmat, std::max(2, max_bt) + 1), 256, 0, s>>>(mats, J, fac, status);
+    k_chol_step<<<dim3(nmat, (max_bt + 1 + 3) / 4), 256, 0, s>>>(mats, J, fac, status);
   k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
   LAUNCHCHK(p);
   return 0;

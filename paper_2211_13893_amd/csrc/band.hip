@@ -322,55 +322,71 @@ __global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* __restrict__ 
 }
 
 // Left-looking tile Cholesky of banded matrices, one launch per step J
-// (J = -1 .. NT-2).  Invariant before step J: every tile of the columns
-// K <= J-1 is final; the diagonal tile J is factored and its inverse stored;
-// the tiles (I, J), I > J, and the diagonal tile J+1 hold A minus the
-// products with the columns K <= J-2.  Step J then computes, on disjoint
-// tiles, with blockIdx.y the role:
-//   role 0 (the step's chain): L(J+1,J) = (A(J+1,J) - L(J+1,J-1) L(J,J-1)^T) L_JJ^{-T},
-//          then C = A(J+1,J+1) - L(J+1,J-1) L(J+1,J-1)^T - L(J+1,J) L(J+1,J)^T,
-//          L_{J+1,J+1} = chol(C) and its inverse;
-//   role 1: the diagonal tile J+2 loses its products with K <= J-1;
-//   role s = 2 .. BT-1, row I = J+s:
-//          L(I,J) = (A(I,J) - L(I,J-1) L(J,J-1)^T) L_JJ^{-T}, and the tile
-//          (I,J+1) loses its products with K <= J-1 (all of which read only
-//          final tiles).
+// (J = -1 .. NT-2), with the products that read only final tiles taken two
+// columns at a time, so that each band tile is read once per column pair.
+// Invariant before step J: every tile of the columns K <= J-1 is final; the
+// diagonal tile J is factored and its inverse stored; the tiles (I, J),
+// I > J, hold A minus the products with K <= J-2.  Step J computes, on
+// disjoint tiles, one job per wavefront:
+//   job 0 (the step's chain): L(J+1,J) = (A(J+1,J) - L(J+1,J-1) L(J,J-1)^T) L_JJ^{-T},
+//          then C = A(J+1,J+1) minus its remaining products (K from J-1 for
+//          even J, from J-2 for odd J, up to J), L_{J+1,J+1} = chol(C) and
+//          its inverse;
+//   jobs 1, 2 (odd J only): the diagonal tiles J+2, J+3 lose their products
+//          with K <= J-1;
+//   job s+1, s = 2 .. BT-1, row I = J+s:
+//          L(I,J) = (A(I,J) - L(I,J-1) L(J,J-1)^T) L_JJ^{-T}; then for odd J
+//          the tiles (I,J+1) and (I,J+2) (if s >= 3) lose their products with
+//          K <= J-1, for even J the tile (I,J+1) loses L(I,J-1) L(J+1,J-1)^T.
 // So the diagonal factor of a column is computed by the launch before the
-// one that needs it, next to the bulk of the tile products.  Each wavefront
-// owns one 16x16 quadrant of its workgroup's target tiles on the FP64
-// matrix cores (no cross-wavefront sums); the tile pair of the next product
-// is requested before the current one is multiplied.
+// one that needs it, next to the bulk of the tile products.  A wavefront
+// owns whole 32x32 target tiles (each loaded operand feeds two or four
+// MFMAs) on the FP64 matrix cores; no job shares data with another wavefront.
 #define CH_LD 34   // LDS row stride (doubles) of staged tiles
 
-struct QuadOps {
-  double2 a[4], b[4];
+// A 32x32 row-major tile in the MFMA operand layout: lane (i = l&15, k = l>>4)
+// holds, for row block b (rows 16b + i) and step 2m + e, inner index
+// 8m + 2k + e (16 contiguous bytes per load).  The same registers serve as
+// the A operand of A B^T and as the B operand (rows of B).
+struct TileOps {
+  double2 v[2][4];
 };
 
-// Operands of quadrant (bi, bj) of A B^T for row-major 32-column tiles A, B
-// (leading dimensions lda, ldb): lane (i = l&15, k = l>>4) supplies inner
-// index 8m + 2k + e at MFMA step 2m + e, i.e. 16 contiguous bytes per load.
-__device__ inline void quad_load(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
-                                 int bi, int bj, int lane, QuadOps& o) {
+__device__ inline void tops_load(const double* __restrict__ T, int lane, TileOps& o) {
   const int i = lane & 15, k = lane >> 4;
-  const double2* pa = reinterpret_cast<const double2*>(A + (16 * bi + i) * lda + 2 * k);
-  const double2* pb = reinterpret_cast<const double2*>(B + (16 * bj + i) * ldb + 2 * k);
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    o.a[m] = pa[4 * m];
-    o.b[m] = pb[4 * m];
+  for (int b = 0; b < 2; ++b) {
+    const double2* p = reinterpret_cast<const double2*>(T + (16 * b + i) * 32 + 2 * k);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) o.v[b][m] = p[4 * m];
   }
 }
 
-__device__ inline void quad_mfma(const double2 a[4], const double2 b[4], dbl4& acc) {
+// acc[bi][bj] += A[bi] B[bj]^T; lower = blocks with bi >= bj only
+template <bool LOWER = false>
+__device__ inline void tops_abt(const TileOps& A, const TileOps& B, dbl4 acc[2][2]) {
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].x, b[m].x, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].y, b[m].y, acc, 0, 0, 0);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        if (LOWER && bi < bj) continue;
+        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.v[bi][m].x, B.v[bj][m].x, acc[bi][bj], 0, 0, 0);
+      }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        if (LOWER && bi < bj) continue;
+        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.v[bi][m].y, B.v[bj][m].y, acc[bi][bj], 0, 0, 0);
+      }
   }
 }
 
-// quadrant (bi, bj) of a tile with leading dimension ld <-> accumulator layout
-// (item v of lane l = row (l>>4) + 4v, column l&15 of the quadrant)
+// Accumulator layout of a 16x16 block (item v of lane l = row (l>>4) + 4v,
+// column l&15): block (bi, bj) of a tile with leading dimension ld, or of its
+// transpose (quadT_*: item v of lane l = C[16bj + (l&15)][16bi + (l>>4) + 4v]).
 __device__ inline dbl4 quad_get(const double* __restrict__ C, int ld, int bi, int bj, int lane) {
   const double* p = C + (16 * bi + (lane >> 4)) * ld + 16 * bj + (lane & 15);
   return dbl4{p[0], p[4 * ld], p[8 * ld], p[12 * ld]};
@@ -384,79 +400,46 @@ __device__ inline void quad_put(double* __restrict__ C, int ld, int bi, int bj, 
   p[12 * ld] = x[3];
 }
 
-// acc += sum over K = k1 down to k0 of L(ra,K)[bi] L(rb,K)[bj]^T (band tiles of
-// the matrix at L with BT tiles per row); with xb != nullptr, acc2 also gets
-// L(ra,k1)[bi] xb[bj]^T from the same A operand.  Two register sets: the next
-// K's operands are requested before the current product; all loads are
-// unconditional (the last request repeats k0).
-__device__ inline void quad_band_sum(const double* __restrict__ L, int BT, int ra, int rb, int k0, int k1,
-                                     const double* __restrict__ xb, int bi, int bj, int lane, dbl4& acc,
-                                     dbl4& acc2) {
-  if (k0 > k1) return;
-  auto ta = [&](int K) { return L + ((int64_t)ra * BT + (ra - K)) * MSG_TILE2; };
-  auto tb = [&](int K) { return L + ((int64_t)rb * BT + (rb - K)) * MSG_TILE2; };
-  QuadOps p, q;
-  quad_load(ta(k1), 32, tb(k1), 32, bi, bj, lane, p);
-  if (xb) {
-    const double2* pb = reinterpret_cast<const double2*>(xb + (16 * bj + (lane & 15)) * 32 + 2 * (lane >> 4));
-    double2 b[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) b[m] = pb[4 * m];
-    quad_mfma(p.a, b, acc2);
-  }
-  int K = k1;
-  for (;;) {
-    const int n1 = max(K - 1, k0);
-    quad_load(ta(n1), 32, tb(n1), 32, bi, bj, lane, q);
-    quad_mfma(p.a, p.b, acc);
-    if (--K < k0) break;
-    const int n2 = max(K - 1, k0);
-    quad_load(ta(n2), 32, tb(n2), 32, bi, bj, lane, p);
-    quad_mfma(q.a, q.b, acc);
-    if (--K < k0) break;
-  }
+__device__ inline dbl4 quadT_get(const double* __restrict__ C, int bi, int bj, int lane) {
+  const double* p = C + (16 * bj + (lane & 15)) * 32 + 16 * bi + (lane >> 4);
+  return dbl4{p[0], p[4], p[8], p[12]};
 }
 
-// Two targets sharing the A operand: acc1 += sum_K L(ra,K)[bi] L(rb1,K)[bj]^T
-// and acc2 += sum_K L(ra,K)[bi] L(rb2,K)[bj]^T over K = k1 down to k0, and
-// accx += L(ra,k1)[bi] xb[bj]^T.  The next K's A operand and first B operand
-// are requested before the current products.
-__device__ inline void quad_band_sum2(const double* __restrict__ L, int BT, int ra, int rb1, int rb2, int k0,
-                                      int k1, const double* __restrict__ xb, int bi, int bj, int lane,
-                                      dbl4& acc1, dbl4& acc2, dbl4& accx) {
-  if (k0 > k1) return;
-  auto ta = [&](int K) { return L + ((int64_t)ra * BT + (ra - K)) * MSG_TILE2; };
-  auto tb1 = [&](int K) { return L + ((int64_t)rb1 * BT + (rb1 - K)) * MSG_TILE2; };
-  auto tb2 = [&](int K) { return L + ((int64_t)rb2 * BT + (rb2 - K)) * MSG_TILE2; };
+__device__ inline void quadT_put(double* __restrict__ C, int bi, int bj, int lane, dbl4 x) {
+  double* p = C + (16 * bj + (lane & 15)) * 32 + 16 * bi + (lane >> 4);
+  p[0] = x[0];
+  p[4] = x[1];
+  p[8] = x[2];
+  p[12] = x[3];
+}
+
+// L(I,J) = X L_JJ^{-T} from X^T in accumulator layout (XT[bk][bb] = block of
+// X^T): L^T = L_JJ^{-1} X^T on the matrix cores, the accumulators of X^T used
+// directly as B operands (item v of block bk is inner index 16bk + (l>>4) + 4v).
+// Stores L(I,J) (row-major) and returns L^T in accumulator layout.
+__device__ inline void trsm_from_xt(const double* __restrict__ Linv, const dbl4 XT[2][2], double* __restrict__ out,
+                                    dbl4 LT[2][2], int lane) {
   const int i = lane & 15, k = lane >> 4;
-  auto ld4 = [&](const double* T, int b, double2 o[4]) {
-    const double2* p = reinterpret_cast<const double2*>(T + (16 * b + i) * 32 + 2 * k);
+  const dbl4 zero = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < 4; ++m) o[m] = p[4 * m];
-  };
-  double2 a[4], b1[4], b2[4], an[4], b1n[4];
-  ld4(ta(k1), bi, a);
-  ld4(tb1(k1), bj, b1);
-  ld4(tb2(k1), bj, b2);
-  {
-    double2 bx[4];
-    ld4(xb, bj, bx);
-    quad_mfma(a, bx, accx);
-  }
-  for (int K = k1;; --K) {
-    const int n = max(K - 1, k0);
-    ld4(ta(n), bi, an);
-    ld4(tb1(n), bj, b1n);
-    quad_mfma(a, b1, acc1);
-    quad_mfma(a, b2, acc2);
-    if (K == k0) break;
-    ld4(tb2(n), bj, b2);
+  for (int ba = 0; ba < 2; ++ba)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      a[m] = an[m];
-      b1[m] = b1n[m];
-    }
-  }
+    for (int bb = 0; bb < 2; ++bb) LT[ba][bb] = zero;
+#pragma unroll
+  for (int bk = 0; bk < 2; ++bk)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int ba = 0; ba < 2; ++ba) {
+        const double a = Linv[(16 * ba + i) * 32 + 16 * bk + k + 4 * v];
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+          LT[ba][bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, XT[bk][bb][v], LT[ba][bb], 0, 0, 0);
+      }
+#pragma unroll
+  for (int ba = 0; ba < 2; ++ba)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) quadT_put(out, ba, bb, lane, LT[ba][bb]);
 }
 
 // One wavefront: C = L L^T for the 32x32 SPD tile C in LDS (stride CH_LD,
@@ -539,109 +522,163 @@ __device__ int factor_tile32(const double* __restrict__ C, double* __restrict__ 
   return bad;
 }
 
-// Column pairs: the products that read only final tiles are taken two columns
-// at a time, so each band tile is read once per pair.  At odd J ("pair
-// steps") the rows pre-subtract their products with K <= J-1 from both
-// (I,J+1) and (I,J+2), and the diagonal tiles J+2, J+3 lose theirs; at even J
-// the rows only subtract L(I,J-1) L(J+1,J-1)^T from (I,J+1).  The diagonal
-// tile J+1 factored at step J then still needs the products with K from J-1
-// (J even) or J-2 (J odd) up to J.
-// grid (n_mat, max(2, max BT) + 1), 256 threads; blockIdx.x is the matrix, so
-// the role-0 workgroups of all matrices are dispatched first; the last role
-// is the diagonal tile J+3.
+// grid (n_mat, ceil((max BT + 1) / 4)), 256 threads: job = 4 blockIdx.y +
+// wavefront; blockIdx.x is the matrix, so the step's chain (job 0) of every
+// matrix and the longest rows are dispatched first.
 __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict__ mats, int J,
                                                       double* __restrict__ fac, int32_t* __restrict__ status) {
   __shared__ __align__(16) double X[32 * CH_LD];
   __shared__ __align__(16) double Y[32 * CH_LD];
   __shared__ double dinv[32], vec[32];
   const MatDesc v = mats[blockIdx.x];
-  const int role = blockIdx.y;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int bi = wave >> 1, bj = wave & 1;
+  const int lane = threadIdx.x & 63;
+  const int job = (int)blockIdx.y * 4 + (threadIdx.x >> 6);
   const int BT = v.BT, NT = v.NT;
   double* L = fac + v.off;
   auto tile = [&](int I, int K) { return L + ((int64_t)I * BT + (I - K)) * MSG_TILE2; };
   const double* LinvJ = fac + v.ioff + (int64_t)(J < 0 ? 0 : J) * MSG_TILE2;
   const dbl4 zero = {0.0, 0.0, 0.0, 0.0};
   const bool pair = (J & 1) != 0;
+  dbl4 acc[2][2], xt[2][2], lt[2][2];
 
-  if (role == 0) {
+  if (job == 0) {
     const int R = J + 1;
     if (R > NT - 1) return;
     const bool has_x = J >= 0 && BT >= 2;    // tile (R, J) exists
     const bool has_k = J >= 1 && BT >= 3;    // tiles (R, J-1), (J, J-1) exist
     // first K of the diagonal tile's remaining products
     const int kd = max(max(0, R - (BT - 1)), pair ? J - 2 : J - 1);
-    dbl4 accx = zero, accd = zero;
-    if (has_k) {
-      QuadOps o;
-      quad_load(tile(R, J - 1), 32, tile(J, J - 1), 32, bi, bj, lane, o);
-      quad_mfma(o.a, o.b, accx);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = zero;
+    if (has_x) {
+      // X^T = A(R,J)^T - L(J,J-1) L(R,J-1)^T
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) xt[bi][bj] = zero;
+      if (has_k) {
+        TileOps a, b;
+        tops_load(tile(J, J - 1), lane, a);
+        tops_load(tile(R, J - 1), lane, b);
+        tops_abt(a, b, xt);
+      }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) xt[bi][bj] = quadT_get(tile(R, J), bi, bj, lane) - xt[bi][bj];
+      trsm_from_xt(LinvJ, xt, tile(R, J), lt, lane);
+      // + L(R,J) L(R,J)^T: the accumulators of L^T serve as both operands
+#pragma unroll
+      for (int bk = 0; bk < 2; ++bk)
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+              acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(lt[bk][bi][w], lt[bk][bj][w], acc[bi][bj], 0, 0, 0);
     }
     for (int K = kd; K <= J - 1; ++K) {
-      QuadOps d;
-      quad_load(tile(R, K), 32, tile(R, K), 32, bi, bj, lane, d);
-      quad_mfma(d.a, d.b, accd);
+      TileOps a;
+      tops_load(tile(R, K), lane, a);
+      tops_abt<true>(a, a, acc);
     }
-    if (has_x) {
-      quad_put(X, CH_LD, bi, bj, lane, quad_get(tile(R, J), 32, bi, bj, lane) - accx);
-      __syncthreads();
-      QuadOps o;
-      quad_load(X, CH_LD, LinvJ, 32, bi, bj, lane, o);
-      dbl4 l = zero;
-      quad_mfma(o.a, o.b, l);
-      quad_put(tile(R, J), 32, bi, bj, lane, l);
-      quad_put(Y, CH_LD, bi, bj, lane, l);
-      __syncthreads();
-      quad_load(Y, CH_LD, Y, CH_LD, bi, bj, lane, o);
-      quad_mfma(o.a, o.b, accd);
-    }
-    quad_put(X, CH_LD, bi, bj, lane, quad_get(tile(R, R), 32, bi, bj, lane) - accd);
-    __syncthreads();
-    if (wave == 0) {
-      const int bad = factor_tile32(X, Y, dinv, vec, tile(R, R), fac + v.ioff + (int64_t)R * MSG_TILE2);
-      if (lane == 0 && bad) atomicOr(&status[v.status_idx], 4);
-    }
+    double* T = tile(R, R);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        if (bi >= bj) quad_put(X, CH_LD, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - acc[bi][bj]);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // the tile is read by other lanes below
+    const int bad = factor_tile32(X, Y, dinv, vec, T, fac + v.ioff + (int64_t)R * MSG_TILE2);
+    if (lane == 0 && bad) atomicOr(&status[v.status_idx], 4);
     return;
   }
-  if (role == 1 || role == (int)gridDim.y - 1) {
-    const int R = role == 1 ? J + 2 : J + 3;
-    if (!pair || R > NT - 1 || bi < bj) return;   // the upper quadrant of a diagonal tile is not read
+  if (job <= 2) {
+    const int R = J + 1 + job;
+    if (!pair || R > NT - 1) return;
     const int k0 = max(0, R - (BT - 1)), k1 = J - 1;
     if (k0 > k1) return;
-    dbl4 acc = zero, unused = zero;
-    quad_band_sum(L, BT, R, R, k0, k1, nullptr, bi, bj, lane, acc, unused);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = zero;
+    for (int K = k1; K >= k0; --K) {
+      TileOps a;
+      tops_load(tile(R, K), lane, a);
+      tops_abt<true>(a, a, acc);   // the upper block of a diagonal tile is not read
+    }
     double* T = tile(R, R);
-    quad_put(T, 32, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - acc);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        if (bi >= bj) quad_put(T, 32, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - acc[bi][bj]);
     return;
   }
-  const int s = role, I = J + s;
+  const int s = job - 1, I = J + s;
   if (J < 0 || s > BT - 1 || I > NT - 1) return;
-  // (I, J+1) (and at pair steps (I, J+2)): products with K in [k0, J-1] (at
-  // other steps K = J-1 only); the one with K = J-1 shares its A operand
-  // L(I, J-1) with the product of the (I, J) target
-  const int k1 = J - 1, k0 = pair ? max(0, I - (BT - 1)) : max(max(0, I - (BT - 1)), k1);
-  dbl4 accb = zero, acca = zero;
-  if (pair && s >= 3 && k0 <= k1) {
-    dbl4 accc = zero;
-    quad_band_sum2(L, BT, I, J + 1, J + 2, k0, k1, tile(J, J - 1), bi, bj, lane, accb, accc, acca);
+  const int k1 = J - 1, kb = max(0, I - (BT - 1));   // K range of row I's final tiles: [kb, J-1]
+  // L(I,J) from X^T = A(I,J)^T - L(J,J-1) L(I,J-1)^T
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) xt[bi][bj] = zero;
+  if (kb <= k1) {
+    TileOps a, b;
+    tops_load(tile(J, J - 1), lane, a);
+    tops_load(tile(I, J - 1), lane, b);
+    tops_abt(a, b, xt);
+  }
+  {
+    double* T = tile(I, J);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) xt[bi][bj] = quadT_get(T, bi, bj, lane) - xt[bi][bj];
+    trsm_from_xt(LinvJ, xt, T, lt, lane);
+  }
+  if (kb > k1) return;
+  // the next column(s): odd J all final products, even J the one with K = J-1
+  const int k0 = pair ? kb : k1;
+  const bool two = pair && s >= 3;
+  dbl4 acc2[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      acc[bi][bj] = zero;
+      acc2[bi][bj] = zero;
+    }
+  if (two) {
+    for (int K = k1; K >= k0; --K) {
+      TileOps a, b, c;
+      tops_load(tile(I, K), lane, a);
+      tops_load(tile(J + 1, K), lane, b);
+      tops_load(tile(J + 2, K), lane, c);
+      tops_abt(a, b, acc);
+      tops_abt(a, c, acc2);
+    }
     double* T2 = tile(I, J + 2);
-    quad_put(T2, 32, bi, bj, lane, quad_get(T2, 32, bi, bj, lane) - accc);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) quad_put(T2, 32, bi, bj, lane, quad_get(T2, 32, bi, bj, lane) - acc2[bi][bj]);
   } else {
-    quad_band_sum(L, BT, I, J + 1, k0, k1, k0 <= k1 ? tile(J, J - 1) : nullptr, bi, bj, lane, accb, acca);
+    for (int K = k1; K >= k0; --K) {
+      TileOps a, b;
+      tops_load(tile(I, K), lane, a);
+      tops_load(tile(J + 1, K), lane, b);
+      tops_abt(a, b, acc);
+    }
   }
-  if (k0 <= k1) {
-    double* T = tile(I, J + 1);
-    quad_put(T, 32, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - accb);
-  }
-  double* T = tile(I, J);
-  quad_put(X, CH_LD, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - acca);
-  __syncthreads();
-  QuadOps o;
-  quad_load(X, CH_LD, LinvJ, 32, bi, bj, lane, o);
-  dbl4 l = zero;
-  quad_mfma(o.a, o.b, l);
-  quad_put(T, 32, bi, bj, lane, l);
+  double* T1 = tile(I, J + 1);
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) quad_put(T1, 32, bi, bj, lane, quad_get(T1, 32, bi, bj, lane) - acc[bi][bj]);
 }
 
 // After the factorisation A = L L^T: rewrite the factor in block unit-lower
