@@ -1,4 +1,5 @@
-// Banded SPD factorisations and block solves on the oversampled boxes.
+// Banded SPD factorisations on the oversampled boxes (the block solves that
+// use them are in solve.hip).
 //
 // Two matrices per box are factorised once and reused by every eigensolver
 // iteration:
@@ -11,48 +12,9 @@
 // so the band structure of the lexicographic node order is kept.  Storage is
 // 32x32 tiles in band form (see internal.hpp); the Cholesky factor overwrites
 // the tiles and the inverses of the diagonal tiles are kept for the solves.
-#include "internal.hpp"
+#include "band_view.hpp"
 
 namespace msg {
-
-struct BandView {
-  int NT, BT, n;
-  int64_t off, ioff;
-  int64_t fw, bw;   // solve-ordered band copies (forward / backward sweep)
-  int sx, sy, sz;   // (sub-)box node dims of the ordering
-  int ox, oy, oz;   // offset of the ordering's node (0,0,0) inside the box
-};
-
-__device__ inline BandView band_view(const BoxMeta& bm, int kind) {
-  BandView v;
-  if (kind == 0) {
-    v.NT = bm.nt11; v.BT = bm.bt11; v.n = bm.n11; v.off = bm.f11_off; v.ioff = bm.f11i_off;
-    v.fw = bm.f11_fw; v.bw = bm.f11_bw;
-    v.sx = bm.sub_hi[0] - bm.sub_lo[0] + 1;
-    v.sy = bm.sub_hi[1] - bm.sub_lo[1] + 1;
-    v.sz = bm.sub_hi[2] - bm.sub_lo[2] + 1;
-    v.ox = bm.sub_lo[0]; v.oy = bm.sub_lo[1]; v.oz = bm.sub_lo[2];
-  } else {
-    v.NT = bm.nth; v.BT = bm.bth; v.n = bm.nh; v.off = bm.fh_off; v.ioff = bm.fhi_off;
-    v.fw = bm.fh_fw; v.bw = bm.fh_bw;
-    v.sx = bm.mx; v.sy = bm.my; v.sz = bm.mz;
-    v.ox = v.oy = v.oz = 0;
-  }
-  return v;
-}
-
-// band row -> box DoF (or -1 for padding rows)
-__device__ inline int band_to_dof(const BandView& v, const BoxMeta& bm, int r) {
-  if (r >= v.n) return -1;
-  int node = r / 3, c = r - 3 * node;
-  int i = node % v.sx, j = (node / v.sx) % v.sy, k = node / (v.sx * v.sy);
-  int bn = (i + v.ox) + bm.mx * ((j + v.oy) + bm.my * (k + v.oz));
-  return 3 * bn + c;
-}
-
-__device__ inline bool dof_active(int kind, uint8_t c) {
-  return kind == 0 ? (c == 1) : (c == 1 || c == 2);
-}
 
 // One thread per 8 consecutive entries of a tile row (the row is decoded
 // once, the columns by increments); grid.x strides over NT*BT*128 of the
@@ -757,346 +719,6 @@ __global__ __launch_bounds__(256) void k_band_relayout(const BoxMeta* __restrict
   }
 }
 
-// Block solve A x = f with A = Lu D Lu^T for KC columns [chunk*KC, +KC) of a
-// box block vector.  Reads `in` (box layout [n_dof][ldk]) on the matrix's
-// DoFs, writes `out` on the DoFs whose class bit is set in out_classes (bit c
-// for class c); with zero_rest, every other DoF of the box gets 0 in these
-// columns.  Scratch holds w = D^{-1} y of the forward sweep, NT*32*KC doubles
-// per (box, chunk), and one more row (index NT) that takes stores without a
-// target; scratch_stride >= (NT + 1)*32*KC.
-//
-// Forward sweep  y_I = f_I - sum_s Lu(I,I-s) y_{I-s}; backward sweep
-// x_I = w_I - sum_s Lu(I+s,I)^T x_{I+s}.  A step's work items are
-// (band tile s, row quad, half of the inner index): thread t handles tile
-// s = 1 + 32p + (t >> 4) of tile set p (NS sets, bands up to 32*NS + 1
-// tiles), rows 4*((t >> 1) & 7) .. +3 and inner indices 16*(t & 1) .. +15,
-// for all KC columns, so every solution row read from the LDS ring feeds four
-// factor rows.  The partial sums of a wavefront's 4 tile groups and 2 halves
-// are combined in registers by a reduce-scatter over lane ^ 1 (DPP), lane ^ 16
-// and lane ^ 32 (permlane swaps), leaving 4 of the 32 x KC sums per lane; the
-// 8 wavefronts' sums go through LDS and are added in a fixed order by the
-// first 32*KC threads.  The product w = D^{-1} y of the previous forward step
-// is formed by the last two wavefronts.
-//
-// Latency: the factor fragment of the next tile set or step is requested
-// piece by piece while the current one is used, so the loads stream during
-// the arithmetic, and stays in flight across the LDS-only barriers while the
-// step is reduced.  For the compiler to wait for each global load only where
-// its own value is needed, every global load and store of a step is issued by
-// every thread of a wavefront that holds tiles, unconditionally and in the
-// same order: out-of-range work items read a valid address and discard the
-// value, and stores without a target write the spare scratch row.
-//
-// The column chunks of one box share an XCD (block id mod 8) so the factor
-// they stream is read from HBM once and then hit in that XCD's L2.
-// grid.x = 8 * n_chunk * ceil(n_box/8), 512 threads; dynamic LDS = BT*32*KC doubles.
-#define SOLVE_THREADS 512
-#define SOLVE_WAVES (SOLVE_THREADS / 64)
-// Barrier for LDS traffic only (__syncthreads would also wait for every
-// global load).  Inside the sweeps no thread reads global memory that
-// another thread of the block wrote, so they need no global-memory barrier.
-__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
-// value of the partner lane (lane ^ 1) through a DPP quad permutation
-__device__ inline double dpp_xor1(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-// a + a(lane ^ 16) on lanes with bit 4 clear, b + b(lane ^ 16) on the others
-__device__ inline double swap16_sum(double a, double b) {
-  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
-  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
-  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
-}
-// a + a(lane ^ 32) on lanes 0..31, b + b(lane ^ 32) on lanes 32..63
-__device__ inline double swap32_sum(double a, double b) {
-  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
-  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
-}
-
-// f[i][q]: forward  = Lu[4rq+i][16h+q] of tile (I, I-s);
-//          backward = Lu[16h+q][4rq+i] of tile (I+s, I)  (row i of its transpose)
-// read from the solve-ordered copy (fw or bw) of the band; consecutive
-// threads read consecutive 16-byte pieces.  P points at piece 0 of this
-// thread's slot of one (row, set); piece j is at P + j*nthr.
-template <typename T> struct vec2_of;
-template <> struct vec2_of<double> { typedef double2 type; };
-template <> struct vec2_of<float> { typedef float2 type; };
-
-template <typename T>
-__device__ inline void frag_load(const typename vec2_of<T>::type* __restrict__ P, int nthr, int dir,
-                                 double (&f)[4][16]) {
-  if (dir < 0) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const auto a = P[(int64_t)(8 * i + q) * nthr];
-        f[i][2 * q] = a.x;
-        f[i][2 * q + 1] = a.y;
-      }
-  } else {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const auto a = P[(int64_t)(2 * q) * nthr];
-      const auto b = P[(int64_t)(2 * q + 1) * nthr];
-      f[0][q] = a.x;
-      f[1][q] = a.y;
-      f[2][q] = b.x;
-      f[3][q] = b.y;
-    }
-  }
-}
-
-// T: precision of the factor copies read by the sweeps (double, or float in
-// the mixed path; ft = the factor array in that precision, same offsets as
-// fac).  Arithmetic, right-hand sides and solutions are FP64 in both cases.
-template <int KC, int NS, typename T>
-__global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
-    const BoxMeta* __restrict__ meta, int n_box, int n_chunk, int kind,
-    const T* __restrict__ ft, const uint8_t* __restrict__ cls,
-    const double* in, double* out,
-    int ldk, int out_classes, int zero_rest, double* __restrict__ scratch, int64_t scratch_stride,
-    const int32_t* __restrict__ active) {
-  static_assert(32 * KC == 256, "reduction threads = the first 256, w threads = the last 128");
-  static_assert(KC == 8, "the register reduce-scatter splits 8 columns over 4 tile groups");
-  static_assert(SOLVE_THREADS / 16 == SOLVE_TILES, "one tile group of 16 threads per tile of a set");
-  extern __shared__ double ring[];   // [BT][32][KC]
-  __shared__ double part[SOLVE_WAVES][32][KC + 1];
-  __shared__ double Dl[32][33];      // D^{-1} tile of the current forward step
-  __shared__ double Wl[32 * KC];     // w of the previous forward step
-  const int x = blockIdx.x;
-  const int xcd = x & 7, rest = x >> 3;
-  const int chunk = rest % n_chunk;
-  const int box = (rest / n_chunk) * 8 + xcd;
-  if (box >= n_box) return;
-  if (active && !active[box]) return;
-  const BoxMeta& bm = meta[box];
-  BandView v = band_view(bm, kind);
-  const uint8_t* cl = cls + bm.dof_off;
-  const int tid = threadIdx.x;
-  const int h = tid & 1, rq = (tid >> 1) & 7, sg = tid >> 4;  // item of the thread
-  const int g = sg & 3, wave = tid >> 6;                      // tile group inside the wavefront
-  const bool red = tid < 32 * KC;
-  const int t8 = tid & (32 * KC - 1);                         // reduction slot (duplicated above 256)
-  const int rr = t8 / KC, cc = t8 % KC;
-  const int col = chunk * KC + cc;
-  const bool colok = col < ldk;
-  const int colc = colok ? col : ldk - 1;
-  const bool wthr = tid >= SOLVE_THREADS - 128;               // forms w = D^{-1} y
-  const double* vin = in + bm.dof_off * ldk;
-  double* vout = out + bm.dof_off * ldk;
-  double* w = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
-  const int BT = v.BT, NT = v.NT;
-  const int nthr = solve_nthr(BT);
-  const int nsets = NS == 1 ? 1 : solve_sets(BT);
-  const int tc = nthr ? min(tid, nthr - 1) : 0;
-  // wavefronts that hold band tiles (in set 0, which is full when set 1 is used)
-  const bool wave_tiles = __builtin_amdgcn_readfirstlane(tid) < nthr;
-  typedef typename vec2_of<T>::type V2;
-  const V2* Ffw = nthr ? (const V2*)(ft + v.fw) + tc : (const V2*)(ft + v.off);
-  const V2* Fbw = nthr ? (const V2*)(ft + v.bw) + tc : (const V2*)(ft + v.off);
-  auto slot = [&](const V2* F, int I, int p) { return F + (int64_t)(I * nsets + p) * 32 * nthr; };
-  double f[4][16];
-
-  // partial sums of this thread's item over its half of the inner index,
-  // with the next fragment (Fn) requested piece by piece as the current
-  // pieces are used (the loads are issued whether or not the thread has a
-  // tile, so every step issues the same loads)
-  auto accumulate = [&](bool has, const double* yp, double (&acc)[4][KC], const V2* Fn, int dir) {
-    if (!wave_tiles) return;
-#pragma unroll
-    for (int qq = 0; qq < 8; ++qq) {
-      if (has) {
-#pragma unroll
-        for (int q = 2 * qq; q < 2 * qq + 2; ++q) {
-          const double* y0 = yp + (16 * h + q) * KC;
-#pragma unroll
-          for (int c = 0; c < KC; ++c) {
-            const double a = y0[c];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i][c] += f[i][q] * a;
-          }
-        }
-      }
-      if (dir < 0) {
-        // pieces 8i + qq hold f[i][2qq], f[i][2qq+1]
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const V2 a = Fn[(int64_t)(8 * i + qq) * nthr];
-          f[i][2 * qq] = a.x;
-          f[i][2 * qq + 1] = a.y;
-        }
-      } else {
-        // pieces 2q, 2q+1 hold f[0..3][q]
-#pragma unroll
-        for (int q = 2 * qq; q < 2 * qq + 2; ++q) {
-          const V2 a = Fn[(int64_t)(2 * q) * nthr];
-          const V2 b = Fn[(int64_t)(2 * q + 1) * nthr];
-          f[0][q] = a.x;
-          f[1][q] = a.y;
-          f[2][q] = b.x;
-          f[3][q] = b.y;
-        }
-      }
-    }
-  };
-  // reduce-scatter of the wavefront's partial sums: after the three exchanges
-  // lane (g, rq, h) holds the wavefront total of rows 4rq+2h+i2 (i2 = 0, 1)
-  // and columns c + 2(g>>1) + 4(g&1) (c = 0, 1); every slot is written each step
-  auto store_part = [&](double (&acc)[4][KC]) {
-    double v1[2][KC];
-#pragma unroll
-    for (int i2 = 0; i2 < 2; ++i2)
-#pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        const double keep = h ? acc[2 + i2][c] : acc[i2][c];
-        const double send = h ? acc[i2][c] : acc[2 + i2][c];
-        v1[i2][c] = keep + dpp_xor1(send);
-      }
-    double v2[2][4];
-#pragma unroll
-    for (int i2 = 0; i2 < 2; ++i2)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) v2[i2][c] = swap16_sum(v1[i2][c], v1[i2][c + 4]);
-#pragma unroll
-    for (int i2 = 0; i2 < 2; ++i2)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-        part[wave][4 * rq + 2 * h + i2][c + 2 * (g >> 1) + 4 * (g & 1)] = swap32_sum(v2[i2][c], v2[i2][c + 2]);
-  };
-  // sum over the wavefronts in a fixed order
-  auto part_sum = [&]() {
-    double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-    for (int q = 0; q < SOLVE_WAVES; q += 2) {
-      a0 += part[q][rr][cc];
-      a1 += part[q + 1][rr][cc];
-    }
-    return a0 + a1;
-  };
-  // Wl = D^{-1}_J y_J (D^{-1}_J in Dl, y_J in its ring slot), by the w threads
-  auto form_w = [&](int J) {
-    const int u = tid - (SOLVE_THREADS - 128);
-    const double* yp = ring + (int64_t)(J % BT) * 32 * KC;
-#pragma unroll
-    for (int o = u; o < 32 * KC; o += 128) {
-      const int r = o / KC, c = o % KC;
-      double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-      for (int q = 0; q < 32; q += 2) {
-        a0 += Dl[r][q] * yp[q * KC + c];
-        a1 += Dl[r][q + 1] * yp[(q + 1) * KC + c];
-      }
-      Wl[o] = a0 + a1;
-    }
-  };
-  auto zero_acc = [&](double (&acc)[4][KC]) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int c = 0; c < KC; ++c) acc[i][c] = 0.0;
-  };
-
-  // ---- forward: Lu y = f
-  if (wave_tiles) frag_load<T>(slot(Ffw, 0, 0), nthr, -1, f);
-  for (int I = 0; I < NT; ++I) {
-    const int smax = min(BT - 1, I);
-    // right-hand side and D^{-1} tile of this step (used after the first
-    // barrier; the class byte is tested there too, so no wait is forced here)
-    const int dof = band_to_dof(v, bm, I * 32 + rr);
-    const int dofc = dof >= 0 ? dof : 0;
-    const double fraw = vin[(int64_t)dofc * ldk + colc];
-    const uint8_t cb = cl[dofc];
-    const V2* dp = (const V2*)(ft + v.off + (int64_t)I * BT * MSG_TILE2) + 2 * t8;
-    const V2 da = dp[0], db = dp[1];
-    // w_{I-1} (Dl and its ring slot were completed last step)
-    if (wthr && I >= 1) form_w(I - 1);
-    double acc[4][KC];
-    zero_acc(acc);
-    const int In = min(I + 1, NT - 1);
-    const int s0 = 1 + sg;
-    const bool has0 = s0 <= smax;
-    const bool two = NS == 2 && nsets == 2;
-    accumulate(has0, ring + (int64_t)((has0 ? I - s0 : 0) % BT) * 32 * KC, acc,
-               two ? slot(Ffw, I, 1) : slot(Ffw, In, 0), -1);
-    if (two) {
-      const int s1 = 1 + SOLVE_TILES + sg;
-      const bool has1 = s1 <= smax;
-      accumulate(has1, ring + (int64_t)((has1 ? I - s1 : 0) % BT) * 32 * KC, acc, slot(Ffw, In, 0), -1);
-    }
-    store_part(acc);
-    lds_barrier();
-    w[(int64_t)((I >= 1 ? I - 1 : NT) * 32 + rr) * KC + cc] = Wl[t8];
-    if (red) {
-      const int e = 4 * tid;
-      Dl[e >> 5][e & 31] = da.x;
-      Dl[(e + 1) >> 5][(e + 1) & 31] = da.y;
-      Dl[(e + 2) >> 5][(e + 2) & 31] = db.x;
-      Dl[(e + 3) >> 5][(e + 3) & 31] = db.y;
-      const bool fok = (dof >= 0) & colok & dof_active(kind, cb);
-      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = (fok ? fraw : 0.0) - part_sum();
-    }
-    lds_barrier();
-  }
-  if (wthr) form_w(NT - 1);
-  lds_barrier();
-  w[(int64_t)((NT - 1) * 32 + rr) * KC + cc] = Wl[t8];
-  __syncthreads();
-
-  // ---- backward: Lu^T x = w
-  if (wave_tiles) frag_load<T>(slot(Fbw, NT - 1, 0), nthr, +1, f);
-  for (int I = NT - 1; I >= 0; --I) {
-    const int smax = min(BT - 1, NT - 1 - I);
-    const int row = I * 32 + rr;
-    const double fv = w[(int64_t)row * KC + cc];
-    const int dof = band_to_dof(v, bm, row);
-    const uint8_t cb = cl[dof >= 0 ? dof : 0];
-    double acc[4][KC];
-    zero_acc(acc);
-    const int In = max(I - 1, 0);
-    const int s0 = 1 + sg;
-    const bool has0 = s0 <= smax;
-    const bool two = NS == 2 && nsets == 2;
-    accumulate(has0, ring + (int64_t)((has0 ? I + s0 : 0) % BT) * 32 * KC, acc,
-               two ? slot(Fbw, I, 1) : slot(Fbw, In, 0), +1);
-    if (two) {
-      const int s1 = 1 + SOLVE_TILES + sg;
-      const bool has1 = s1 <= smax;
-      accumulate(has1, ring + (int64_t)((has1 ? I + s1 : 0) % BT) * 32 * KC, acc, slot(Fbw, In, 0), +1);
-    }
-    store_part(acc);
-    lds_barrier();
-    double xv = 0.0;
-    if (red) {
-      xv = fv - part_sum();
-      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = xv;
-    }
-    // the solution goes to `out` where it belongs, else to the spare row
-    const bool wr = red & (dof >= 0) & colok & dof_active(kind, cb) & (((out_classes >> cb) & 1) != 0);
-    *(wr ? vout + (int64_t)dof * ldk + col : w + (int64_t)(NT * 32 + rr) * KC + cc) = xv;
-    lds_barrier();
-  }
-  if (zero_rest && colok && red) {
-    // zero the DoFs of this box (this chunk's columns) that were not written
-    for (int d = rr; d < bm.n_dof; d += 32) {
-      uint8_t k = cl[d];
-      bool written = dof_active(kind, k) && ((out_classes >> k) & 1);
-      if (!written) vout[(int64_t)d * ldk + col] = 0.0;
-    }
-  }
-}
-
-#define SOLVE_INST(NS, T)                                                                                     \
-  template __global__ void k_band_solve<8, NS, T>(const BoxMeta*, int, int, int, const T*, const uint8_t*,   \
-                                                  const double*, double*, int, int, int, double*, int64_t,     \
-                                                  const int32_t*);
-SOLVE_INST(1, double)
-SOLVE_INST(2, double)
-SOLVE_INST(1, float)
-SOLVE_INST(2, float)
 
 
 

@@ -29,7 +29,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 256 * 1024 * 1024
 # kernel (name prefix in the trace) -> sources it is built from
 KERNEL_SOURCES = {
-    "k_band_solve": ["csrc/band.hip", "csrc/internal.hpp"],
+    "k_band_solve": ["csrc/solve.hip", "csrc/band_view.hpp", "csrc/internal.hpp"],
     "k_spmm": ["csrc/spmm.hip", "csrc/internal.hpp"],
 }
 
