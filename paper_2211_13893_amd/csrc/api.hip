@@ -897,8 +897,8 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
       OX.p[kind] = B[kind][3];
       OP.p[kind] = nullptr;
     }
-    dim3 grid((unsigned)((p->max_dof + 255) / 256), nb, nkinds);
-    k_update<<<grid, 256, (size_t)2 * k * k * 8, c.s>>>(c.v.meta, 1, k, Z, OX, OP, c.w.Y, c.w.Yp, a_);
+    dim3 grid((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, nkinds);
+    k_update<<<grid, UPD_THREADS, (size_t)2 * k * k * 8, c.s>>>(c.v.meta, 1, k, Z, OX, OP, c.w.Y, c.w.Yp, a_);
     LAUNCHCHK(p);
     for (int kind = 0; kind < 4; ++kind) std::swap(B[kind][0], B[kind][3]);
     return 0;
@@ -996,7 +996,7 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
       OX.p[kind] = B[kind][3];
       OP.p[kind] = B[kind][4];
     }
-    dim3 grid((unsigned)((p->max_dof + 255) / 256), nb, nkinds);
+    dim3 grid((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, nkinds);
     double by = 0, fl = 0;
     for (int b = 0; b < nb; ++b) {
       if (!c.counts(b, act)) continue;
@@ -1005,7 +1005,7 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
       fl += 4 * 2 * 2.0 * mt.n_dof * (nblk * k) * k;
     }
     ProfScope ps(p, PK_UPDATE, c.s, by, fl);
-    k_update<<<grid, 256, (size_t)2 * nblk * k * k * 8, c.s>>>(c.v.meta, nblk, k, Z, OX, OP, c.w.Y,
+    k_update<<<grid, UPD_THREADS, (size_t)2 * nblk * k * k * 8, c.s>>>(c.v.meta, nblk, k, Z, OX, OP, c.w.Y,
                                                                 c.w.Yp, act);
     LAUNCHCHK(p);
     (void)lds_upd3;
@@ -1267,7 +1267,7 @@ extern "C" int msgfem_coarse_assemble(msgfem_plan* p, const void* ops, void* wor
     }
     Zu.p[0][0] = V;
     OX.p[0] = Vn;
-    k_update<<<dim3((unsigned)((p->max_dof + 255) / 256), nb, 1), 256, (size_t)2 * k * k * 8, s>>>(
+    k_update<<<dim3((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, 1), UPD_THREADS, (size_t)2 * k * k * 8, s>>>(
         v.meta, 1, k, Zu, OX, OP, c.w.Y, c.w.Yp, nullptr);
     LAUNCHCHK(p);
     std::swap(V, Vn);

@@ -26,7 +26,7 @@ struct Blk3 {
 };
 
 #define GR_ROWS 32
-#define UPD_ROWS 256   // rows per k_update workgroup (4 wavefronts x 4 blocks of 16)
+#define UPD_DEPTH 4    // MFMA steps (4 inner indices each) whose A operands are requested ahead
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -477,7 +477,7 @@ struct Out4 {
 // runs over the m columns of Z in steps of 4, the output columns in blocks
 // of 16 (k <= 32); Y and Yp are staged in LDS once per workgroup.
 // grid (ceil(max n_dof / UPD_ROWS), n_box, kinds); dynamic LDS = 2*m*k doubles
-__global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta, int nblk, int k,
+__global__ __launch_bounds__(UPD_THREADS, 3) void k_update(const BoxMeta* __restrict__ meta, int nblk, int k,
                                                 Blk4x3 Z, Out4 OX, Out4 OP,
                                                 const double* __restrict__ Y,
                                                 const double* __restrict__ Yp,
@@ -502,7 +502,7 @@ __global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta
   double* ys = sm;
   double* yps = sm + m * k;
   const bool wantP = OP.p[kind] != nullptr;
-  for (int t = threadIdx.x; t < m * k; t += 256) {
+  for (int t = threadIdx.x; t < m * k; t += UPD_THREADS) {
     ys[t] = Y[(int64_t)box * m * k + t];
     yps[t] = wantP ? Yp[(int64_t)box * m * k + t] : 0.0;
   }
@@ -511,8 +511,8 @@ __global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta
   const int li = lane & 15, lk = lane >> 4;
   const int nsteps = (m + 3) >> 2;
   const int64_t base = bm.dof_off * k;
-  for (int rb = 0; rb < UPD_ROWS / 64; ++rb) {
-    const int r0 = r_wg + (wave * (UPD_ROWS / 64) + rb) * 16;
+  for (int rb = 0; rb < 4; ++rb) {
+    const int r0 = r_wg + (wave * 4 + rb) * 16;
     if (r0 >= bm.n_dof) break;
     const int row = r0 + li;
     const bool rok = row < bm.n_dof;
@@ -522,23 +522,42 @@ __global__ __launch_bounds__(256) void k_update(const BoxMeta* __restrict__ meta
       ax[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
       ap[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
     }
-    int b = 0, cc = lk;                      // block and column of inner index 4 s + lk
-    for (int st = 0; st < nsteps; ++st) {
+    // A operand of step st (inner index i = 4 st + lk: block i / k, column
+    // i % k; k is a multiple of 8).  Two register sets of UPD_DEPTH steps: the
+    // next set is requested before the current one is multiplied.
+    auto load_a = [&](int st) {
       const int i = 4 * st + lk;
-      const double a = (rok && i < m) ? Z.p[kind][b][base + (int64_t)row * k + cc] : 0.0;
+      double a = 0.0;
+      if (st < nsteps && rok && i < m) {
+        const int b = i / k;
+        a = Z.p[kind][b][base + (int64_t)row * k + (i - b * k)];
+      }
+      return a;
+    };
+    auto mma = [&](int st, double a) {
+      if (st < nsteps) {
+        const int i = 4 * st + lk;
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        const int col = 16 * cb + li;
-        const bool ok = i < m && col < k;
-        ax[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ok ? ys[i * k + col] : 0.0, ax[cb], 0, 0, 0);
-        if (wantP) ap[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ok ? yps[i * k + col] : 0.0, ap[cb], 0, 0, 0);
+        for (int cb = 0; cb < 2; ++cb) {
+          const int col = 16 * cb + li;
+          const bool ok = i < m && col < k;
+          ax[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ok ? ys[i * k + col] : 0.0, ax[cb], 0, 0, 0);
+          if (wantP) ap[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ok ? yps[i * k + col] : 0.0, ap[cb], 0, 0, 0);
+        }
       }
-      cc += 4;
-      while (cc >= k && b < nblk) {
-        cc -= k;
-        ++b;
-      }
-      if (b >= nblk) b = nblk - 1;
+    };
+    double pa[UPD_DEPTH], pb[UPD_DEPTH];
+#pragma unroll
+    for (int j = 0; j < UPD_DEPTH; ++j) pa[j] = load_a(j);
+    for (int st = 0; st < nsteps; st += 2 * UPD_DEPTH) {
+#pragma unroll
+      for (int j = 0; j < UPD_DEPTH; ++j) pb[j] = load_a(st + UPD_DEPTH + j);
+#pragma unroll
+      for (int j = 0; j < UPD_DEPTH; ++j) mma(st + j, pa[j]);
+#pragma unroll
+      for (int j = 0; j < UPD_DEPTH; ++j) pa[j] = load_a(st + 2 * UPD_DEPTH + j);
+#pragma unroll
+      for (int j = 0; j < UPD_DEPTH; ++j) mma(st + UPD_DEPTH + j, pb[j]);
     }
     // accumulator item v of lane l: row r0 + (l >> 4) + 4 v, column 16 cb + (l & 15)
     double* ox = OX.p[kind] + base;

@@ -23,6 +23,8 @@
 #define MSG_TILE 32
 #define MSG_TILE2 1024
 #define SOLVE_TILES 32      // off-diagonal band tiles covered by the solve's thread layout
+#define UPD_THREADS 512     // k_update workgroup: 8 wavefronts x 4 row blocks of 16
+#define UPD_ROWS (UPD_THREADS)
 
 namespace msg {
 
