@@ -303,8 +303,12 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
   //    i = 1..m/2-1; all m/2 rotations of a round commute.  A round computes
   //    the rotations, then applies them to C from both sides in one pass over
   //    the 2x2 blocks C[{p_a,q_a},{p_b,q_b}] <- R_a B R_b^T, R = [[c,-s],[s,c]],
-  //    and to the columns of V (V <- V R^T).
+  //    and to the columns of V (V <- V R^T).  Only the upper triangle of C is
+  //    kept (entry (x, y) at C[min][max]), so a round updates the blocks with
+  //    a <= b; a thread applies one rotation to several rows of V.  Both halve
+  //    the LDS traffic of a round, which bounds it.
   const int h = mj / 2, m1 = mj - 1;
+  auto cix = [&](int x, int y) { return x < y ? x * ld + y : y * ld + x; };
   auto pair_of = [&](int r, int i, int& p, int& q) {
     if (i == 0) {
       p = 0;
@@ -325,9 +329,14 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
     double off = 0.0, tot = 0.0;
     for (int t = tid; t < mj * mj; t += RR_THREADS) {
       const int i = t / mj, j = t - (t / mj) * mj;
+      if (i > j) continue;
       const double a = C[i * ld + j];
-      tot += a * a;
-      if (i != j) off += a * a;
+      if (i == j) {
+        tot += a * a;
+      } else {
+        off += 2.0 * a * a;
+        tot += 2.0 * a * a;
+      }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -353,7 +362,7 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
         pair_of(r, i, p, q);
         pp[i] = p;
         qq[i] = q;
-        const double apq = C[p * ld + q];
+        const double apq = C[cix(p, q)];
         const double app = C[p * ld + p], aqq = C[q * ld + q];
         double c = 1.0, sn = 0.0;
         int z = 0;
@@ -371,36 +380,48 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
         zero_pq[i] = z;
       }
       __syncthreads();
-      // C <- R C R^T over 2x2 blocks; V <- V R^T over (row, pair)
-      for (int t = tid; t < h * h + mj * h; t += RR_THREADS) {
-        if (t < h * h) {
-          const int ia = t / h, ib = t - (t / h) * h;
-          const int pa = pp[ia], qa = qq[ia], pb = pp[ib], qb = qq[ib];
-          const double ca = rc[ia], sa = rs[ia], cb = rc[ib], sb = rs[ib];
-          const double b00 = C[pa * ld + pb], b01 = C[pa * ld + qb];
-          const double b10 = C[qa * ld + pb], b11 = C[qa * ld + qb];
+      // C <- R C R^T over the 2x2 blocks (a <= b) of the upper triangle
+      for (int t = tid; t < h * h; t += RR_THREADS) {
+        const int ia = t / h, ib = t - (t / h) * h;
+        if (ia > ib) continue;
+        const int pa = pp[ia], qa = qq[ia], pb = pp[ib], qb = qq[ib];
+        const double ca = rc[ia], sa = rs[ia], cb = rc[ib], sb = rs[ib];
+        if (ia == ib) {
+          const int e01 = cix(pa, qa);
+          const double b00 = C[pa * ld + pa], b01 = C[e01], b11 = C[qa * ld + qa];
+          const double r00 = ca * b00 - sa * b01, r01 = ca * b01 - sa * b11;
+          const double r10 = sa * b00 + ca * b01, r11 = sa * b01 + ca * b11;
+          const double n00 = ca * r00 - sa * r01, n11 = sa * r10 + ca * r11;
+          // (pa, qa) is the entry the rotation annihilates
+          const double n01 = zero_pq[ia] ? 0.0 : sa * r00 + ca * r01;
+          C[pa * ld + pa] = n00;
+          C[e01] = (pa < qa) ? n01 : (zero_pq[ia] ? 0.0 : ca * r10 - sa * r11);
+          C[qa * ld + qa] = n11;
+        } else {
+          const int e00 = cix(pa, pb), e01 = cix(pa, qb), e10 = cix(qa, pb), e11 = cix(qa, qb);
+          const double b00 = C[e00], b01 = C[e01], b10 = C[e10], b11 = C[e11];
           // rows: R_a B
           const double r00 = ca * b00 - sa * b10, r01 = ca * b01 - sa * b11;
           const double r10 = sa * b00 + ca * b10, r11 = sa * b01 + ca * b11;
           // columns: (R_a B) R_b^T
-          double n00 = cb * r00 - sb * r01, n01 = sb * r00 + cb * r01;
-          double n10 = cb * r10 - sb * r11, n11 = sb * r10 + cb * r11;
-          if (ia == ib && zero_pq[ia]) {
-            n01 = 0.0;
-            n10 = 0.0;
-          }
-          C[pa * ld + pb] = n00;
-          C[pa * ld + qb] = n01;
-          C[qa * ld + pb] = n10;
-          C[qa * ld + qb] = n11;
-        } else {
-          const int u = t - h * h;
-          const int row = u / h, i = u - (u / h) * h;
+          C[e00] = cb * r00 - sb * r01;
+          C[e01] = sb * r00 + cb * r01;
+          C[e10] = cb * r10 - sb * r11;
+          C[e11] = sb * r10 + cb * r11;
+        }
+      }
+      // V <- V R^T: thread (pair i, row group g) takes rows g, g + G, ...
+      {
+        const int G = RR_THREADS / h;
+        const int i = tid % h, g = tid / h;
+        if (g < G) {
           const int p = pp[i], q = qq[i];
           const double c = rc[i], sn = rs[i];
-          const double vp = V[row * ld + p], vq = V[row * ld + q];
-          V[row * ld + p] = c * vp - sn * vq;
-          V[row * ld + q] = sn * vp + c * vq;
+          for (int row = g; row < mj; row += G) {
+            const double vp = V[row * ld + p], vq = V[row * ld + q];
+            V[row * ld + p] = c * vp - sn * vq;
+            V[row * ld + q] = sn * vp + c * vq;
+          }
         }
       }
       __syncthreads();
