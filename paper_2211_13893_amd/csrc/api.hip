@@ -26,9 +26,13 @@ __global__ void k_chol_panel(const MatDesc*, int, double*);
 __global__ void k_chol_step(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_unit(const MatDesc*, double*);
 __global__ void k_band_relayout(const BoxMeta*, int, double*);
+__global__ void k_band_relayout4(const BoxMeta*, int, double*);
 template <int KC, int NS, typename T>
 __global__ void k_band_solve(const BoxMeta*, int, int, int, const T*, const uint8_t*, const double*, double*, int,
                              int, int, double*, int64_t, const int32_t*);
+template <int NSLOT, typename T>
+__global__ void k_band_solve4(const BoxMeta*, int, int, int, const T*, const uint8_t*, const double*, double*, int,
+                              int, int, double*, int64_t, const int32_t*);
 
 template <bool TWO, int CW, typename ST>
 __global__ void k_spmm(const BoxMeta*, int, int, const ST*, const uint8_t*, const double*, const double*,
@@ -530,6 +534,11 @@ static OpsView ops_view(const msgfem_plan* p, const void* ops) {
 
 static void lds_attributes();
 
+// the matrix-core block solve serves a matrix kind whose bands all fit its slots
+static bool solve4_kind(const msgfem_plan* p, int kind) {
+  return p->max_bt_kind[kind] - 1 <= 8 * SOLVE4_MAX_SLOTS;
+}
+
 static int set_device(msgfem_plan* p) {
   HIPCHK(p, hipSetDevice(p->device));
   lds_attributes();
@@ -648,7 +657,10 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
       by += 3 * 8.0 * solve_copy_doubles(nt, bt);
     }
     ProfScope ps(p, PK_BUILD, s, by, 0.0);
-    k_band_relayout<<<dim3(SOLVE_TILES * max_sets, max_nt, nb), 256, 0, s>>>(v.meta, kind, v.fac);
+    if (solve4_kind(p, kind))
+      k_band_relayout4<<<dim3(solve4_slots(p->max_bt_kind[kind]), max_nt, nb), 256, 0, s>>>(v.meta, kind, v.fac);
+    else
+      k_band_relayout<<<dim3(SOLVE_TILES * max_sets, max_nt, nb), 256, 0, s>>>(v.meta, kind, v.fac);
     LAUNCHCHK(p);
   }
   if (p->opts.precision == 1) {
@@ -720,6 +732,11 @@ static void lds_attributes() {
   const void* solves[4] = {(const void*)k_band_solve<KC, 1, double>, (const void*)k_band_solve<KC, 2, double>,
                            (const void*)k_band_solve<KC, 1, float>, (const void*)k_band_solve<KC, 2, float>};
   for (const void* f : solves) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  const void* solves4[8] = {(const void*)k_band_solve4<1, double>, (const void*)k_band_solve4<2, double>,
+                            (const void*)k_band_solve4<3, double>, (const void*)k_band_solve4<4, double>,
+                            (const void*)k_band_solve4<1, float>,  (const void*)k_band_solve4<2, float>,
+                            (const void*)k_band_solve4<3, float>,  (const void*)k_band_solve4<4, float>};
+  for (const void* f : solves4) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_gram_partial, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -780,7 +797,23 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
     kern<<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, ft, c.v.cls, in, out, kk, out_classes, zero_rest,
                                   c.w.scr, c.p->scr_stride, active);
   };
-  if (c.use32) {
+  if (solve4_kind(c.p, kind)) {
+    // bands of at most 33 tiles: the matrix-core solve, 1..4 tile slots per wavefront
+    const int ns = solve4_nslot(c.p->max_bt_kind[kind]);
+    if (c.use32) {
+      const float* f = (const float*)c.v.fac32;
+      if (ns <= 1) launch(k_band_solve4<1, float>, f);
+      else if (ns == 2) launch(k_band_solve4<2, float>, f);
+      else if (ns == 3) launch(k_band_solve4<3, float>, f);
+      else launch(k_band_solve4<4, float>, f);
+    } else {
+      const double* f = (const double*)c.v.fac;
+      if (ns <= 1) launch(k_band_solve4<1, double>, f);
+      else if (ns == 2) launch(k_band_solve4<2, double>, f);
+      else if (ns == 3) launch(k_band_solve4<3, double>, f);
+      else launch(k_band_solve4<4, double>, f);
+    }
+  } else if (c.use32) {
     if (two) launch(k_band_solve<KC, 2, float>, (const float*)c.v.fac32);
     else launch(k_band_solve<KC, 1, float>, (const float*)c.v.fac32);
   } else {

@@ -722,6 +722,57 @@ __global__ __launch_bounds__(256) void k_band_relayout(const BoxMeta* __restrict
 
 
 
+// Copies of the unit-lower band in the operand order of the matrix-core block
+// solve (k_band_solve4; bands of at most 33 tiles).  Tile row I has 1 + 8
+// nslot slots of 8 KB: slot 0 of the forward copy is D^{-1}_I, slot s >= 1 the
+// tile (I, I-s) (forward) or (I+s, I)^T (backward); tiles outside the matrix
+// or the band are zero.  Inside a slot, double2 pp (0..7) of lane l = 16 kk +
+// 4 o + i holds A[16 rh + 4 o + i][4 ss + kk] for rh = pp >> 2 and ss = 2 (pp
+// & 3) + e, e = 0, 1 (the A operand of v_mfma_f64_4x4x4f64 for 4x4 blocks o),
+// at ((I S + slot) 8 + pp) 64 + l, S = solve4_slots(BT).  One workgroup per
+// (slot, tile row, box) stages the source tiles in LDS and writes 1 KB per pp.
+// grid (1 + 8 max nslot, max NT, n_box).
+__global__ __launch_bounds__(256) void k_band_relayout4(const BoxMeta* __restrict__ meta, int kind,
+                                                        double* __restrict__ fac) {
+  __shared__ double Tf[MSG_TILE2], Tb[MSG_TILE2];
+  const BoxMeta& bm = meta[blockIdx.z];
+  BandView v = band_view(bm, kind);
+  const int S = solve4_slots(v.BT);
+  const int slot = blockIdx.x, I = blockIdx.y;
+  if (I >= v.NT || slot >= S) return;
+  const double* L = fac + v.off;
+  // forward source: D^{-1}_I (the diagonal slot after the unit-lower rewrite) or tile (I, I-s)
+  const bool fok = slot == 0 || (slot < v.BT && slot <= I);
+  const bool bok = slot >= 1 && slot < v.BT && I + slot < v.NT;
+  const int u = threadIdx.x;
+  {
+    const double2* src = (const double2*)(L + ((int64_t)I * v.BT + (fok ? slot : 0)) * MSG_TILE2);
+    const double2* srb = (const double2*)(L + ((int64_t)(bok ? I + slot : I) * v.BT + (bok ? slot : 0)) * MSG_TILE2);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const double2 a = fok ? src[u + 256 * r] : make_double2(0.0, 0.0);
+      const double2 b = bok ? srb[u + 256 * r] : make_double2(0.0, 0.0);
+      Tf[2 * (u + 256 * r)] = a.x;
+      Tf[2 * (u + 256 * r) + 1] = a.y;
+      Tb[2 * (u + 256 * r)] = b.x;
+      Tb[2 * (u + 256 * r) + 1] = b.y;
+    }
+  }
+  __syncthreads();
+  double2* fw = (double2*)(fac + v.fw) + ((int64_t)I * S + slot) * 8 * 64;
+  double2* bw = (double2*)(fac + v.bw) + ((int64_t)I * S + slot) * 8 * 64;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int q = u + 256 * r;                 // (pp, lane)
+    const int pp = q >> 6, l = q & 63;
+    const int kk = l >> 4, o = (l >> 2) & 3, i = l & 3;
+    const int row = 16 * (pp >> 2) + 4 * o + i, c0 = 4 * (2 * (pp & 3)) + kk;   // inner index of e = 0; e = 1 adds 4
+    fw[q] = make_double2(Tf[row * 32 + c0], Tf[row * 32 + c0 + 4]);
+    bw[q] = make_double2(Tb[c0 * 32 + row], Tb[(c0 + 4) * 32 + row]);
+  }
+}
+
+
 // FP32 copies for the mixed path (same element offsets as the FP64 arrays):
 // the two solve-ordered band copies and the D^{-1} diagonal tiles of both box
 // matrices (grid.y = box, grid.z = matrix kind), and the stencil

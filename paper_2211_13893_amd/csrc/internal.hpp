@@ -65,9 +65,16 @@ __host__ __device__ inline int solve_nthr(int BT) {
 // bands up to 2*SOLVE_TILES + 1 tiles)
 #define SOLVE_MAX_BT (2 * SOLVE_TILES + 1)
 __host__ __device__ inline int solve_sets(int BT) { return BT - 1 > SOLVE_TILES ? 2 : 1; }
-// doubles of one solve-ordered copy of a band
+// the matrix-core block solve (k_band_solve4) takes bands of at most
+// 1 + 8 * SOLVE4_MAX_SLOTS tiles; its copies hold 1 + 8 nslot tiles per row
+#define SOLVE4_MAX_SLOTS 4
+__host__ __device__ inline int solve4_nslot(int BT) { return (BT - 1 + 7) / 8; }
+__host__ __device__ inline int solve4_slots(int BT) { return 1 + 8 * solve4_nslot(BT); }
+// doubles of one solve-ordered copy of a band (room for either layout)
 __host__ __device__ inline int64_t solve_copy_doubles(int NT, int BT) {
-  return (int64_t)NT * solve_sets(BT) * 64 * solve_nthr(BT);
+  const int64_t a = (int64_t)NT * solve_sets(BT) * 64 * solve_nthr(BT);
+  const int64_t b = (int64_t)NT * solve4_slots(BT) * MSG_TILE2;
+  return a > b ? a : b;
 }
 
 // One SPD matrix in 32x32 tile-band storage (tiles at fac + off, inverse

@@ -345,4 +345,235 @@ SOLVE_INST(2, double)
 SOLVE_INST(1, float)
 SOLVE_INST(2, float)
 
+
+// The same block solve on the FP64 matrix cores, for bands of at most
+// 1 + 8 NSLOT tiles (k_band_relayout4 writes the operand copies).  One step
+// y_I = f_I - sum_s Lu(I,I-s) y_{I-s} (backward: x_I = w_I - sum_s
+// Lu(I+s,I)^T x_{I+s}) is a 32 x 8 block product per tile, done as
+// v_mfma_f64_4x4x4f64: lane l = 16 kk + 4 o + i supplies A[16 rh + 4 o + i][4 ss + kk]
+// (the factor, streamed from the copy) and B[4 ss + kk][4 ch + j] (j = l & 3,
+// the solution row from the LDS ring), and accumulates C[16 rh + 4 o + i][4 ch + j]
+// at lane 16 i + 4 o + j, four 4x4 blocks o per instruction, 8 instructions
+// (ss) per (rh, ch) and tile.  Wavefront w takes tiles s = 1 + w + 8u,
+// u < nslot; all tiles of a wavefront add into the same 4 accumulators, so
+// the wavefront's partial sum of the step leaves in 4 LDS stores.  The
+// wavefront of 4x4x4 products is FP64-FMA work that the matrix cores run at
+// close to their rate with two wavefronts per SIMD (the vector unit does not),
+// and a ring value read from LDS feeds four factor rows.  Wavefront 7 also
+// forms w_{I-1} = D^{-1}_{I-1} y_{I-1} (slot 0 of the forward copy) and
+// stores it.  The factor pieces of the next row are requested one by one as
+// the current ones are used; every load of a step is issued by every
+// wavefront in the same order (a slot without a tile reads a valid address
+// and its products are skipped), so the compiler waits for a load only where
+// its value is needed.  The ring is cleared before each sweep, so rows outside
+// the matrix read zeros.  Scratch as for k_band_solve.
+// grid.x = 8 * n_chunk * ceil(n_box/8), 512 threads; dynamic LDS = BT*32*KC doubles.
+template <int NSLOT, typename T>
+__global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
+    const BoxMeta* __restrict__ meta, int n_box, int n_chunk, int kind,
+    const T* __restrict__ ft, const uint8_t* __restrict__ cls,
+    const double* in, double* out,
+    int ldk, int out_classes, int zero_rest, double* __restrict__ scratch, int64_t scratch_stride,
+    const int32_t* __restrict__ active) {
+  constexpr int KC = 8;
+  static_assert(SOLVE_THREADS == 512, "8 wavefronts: tiles 1 + w + 8u");
+  extern __shared__ double ring[];   // [BT][32][KC]
+  __shared__ double part[SOLVE_WAVES][32][KC + 1];
+  const int x = blockIdx.x;
+  const int xcd = x & 7, rest = x >> 3;
+  const int chunk = rest % n_chunk;
+  const int box = (rest / n_chunk) * 8 + xcd;
+  if (box >= n_box) return;
+  if (active && !active[box]) return;
+  const BoxMeta& bm = meta[box];
+  BandView v = band_view(bm, kind);
+  const uint8_t* cl = cls + bm.dof_off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kk = lane >> 4, ob = (lane >> 2) & 3, jl = lane & 3;   // operand roles of the lane
+  const int oi = lane >> 4;                                        // accumulator row i of the lane
+  const bool red = tid < 32 * KC;
+  const int t8 = tid & (32 * KC - 1);
+  const int rr = t8 / KC, cc = t8 % KC;
+  const int col = chunk * KC + cc;
+  const bool colok = col < ldk;
+  const int colc = colok ? col : ldk - 1;
+  const double* vin = in + bm.dof_off * ldk;
+  double* vout = out + bm.dof_off * ldk;
+  double* w = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
+  const int BT = v.BT, NT = v.NT;
+  const int S = solve4_slots(BT), nslot = solve4_nslot(BT);
+  typedef typename vec2_of<T>::type V2;
+  // piece pair pp of slot `sl` of row I, this lane
+  auto piece = [&](const T* base, int I, int sl, int pp) {
+    return (const V2*)(base) + (((int64_t)I * S + sl) * 8 + pp) * 64 + lane;
+  };
+  const T* Ffw = ft + v.fw;
+  const T* Fbw = ft + v.bw;
+  const bool wforms = wave == SOLVE_WAVES - 1;
+  // factor pieces of this wavefront's slots (and of D^{-1} for wavefront 7)
+  double A[NSLOT][16], Aw[16];
+  auto slot_of = [&](int u) {
+    const int s = 1 + wave + 8 * u;
+    return u < nslot ? s : 0;   // no tile: a valid address, products skipped
+  };
+  auto load_slot = [&](double (&a)[16], const T* base, int I, int sl) {
+#pragma unroll
+    for (int pp = 0; pp < 8; ++pp) {
+      const V2 t = *piece(base, I, sl, pp);
+      a[2 * pp] = (double)t.x;
+      a[2 * pp + 1] = (double)t.y;
+    }
+  };
+  // acc += the tile's 32x8 product with the ring row yp; the next row's
+  // pieces of the slot are requested as the current ones are used
+  auto tile_step = [&](bool has, double (&a)[16], const double* yp, double (&acc)[2][2], const T* base, int In,
+                       int sl) {
+#pragma unroll
+    for (int pp = 0; pp < 8; ++pp) {
+      const int rh = pp >> 2;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int ss = 2 * (pp & 3) + e;
+        if (has) {
+#pragma unroll
+          for (int ch = 0; ch < 2; ++ch) {
+            const double b = yp[(4 * ss + kk) * KC + 4 * ch + jl];
+            acc[rh][ch] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[2 * pp + e], b, acc[rh][ch], 0, 0, 0);
+          }
+        }
+      }
+      const V2 t = *piece(base, In, sl, pp);
+      a[2 * pp] = (double)t.x;
+      a[2 * pp + 1] = (double)t.y;
+    }
+  };
+  auto store_part = [&](const double (&acc)[2][2]) {
+#pragma unroll
+    for (int rh = 0; rh < 2; ++rh)
+#pragma unroll
+      for (int ch = 0; ch < 2; ++ch) part[wave][16 * rh + 4 * ob + oi][4 * ch + jl] = acc[rh][ch];
+  };
+  auto part_sum = [&]() {
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < SOLVE_WAVES; q += 2) {
+      a0 += part[q][rr][cc];
+      a1 += part[q + 1][rr][cc];
+    }
+    return a0 + a1;
+  };
+  auto clear_ring = [&]() {
+    for (int e = tid; e < BT * 32 * KC; e += SOLVE_THREADS) ring[e] = 0.0;
+  };
+  // w_J = D^{-1}_J y_J by wavefront 7 into row `dst` of the scratch (the spare row NT when J < 0)
+  auto form_w = [&](int J, int dst) {
+    double accw[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    const double* yp = ring + (int64_t)((J < 0 ? 0 : J) % BT) * 32 * KC;
+#pragma unroll
+    for (int pp = 0; pp < 8; ++pp) {
+      const int rh = pp >> 2;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int ss = 2 * (pp & 3) + e;
+#pragma unroll
+        for (int ch = 0; ch < 2; ++ch) {
+          const double b = yp[(4 * ss + kk) * KC + 4 * ch + jl];
+          accw[rh][ch] = __builtin_amdgcn_mfma_f64_4x4x4f64(Aw[2 * pp + e], b, accw[rh][ch], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int rh = 0; rh < 2; ++rh)
+#pragma unroll
+      for (int ch = 0; ch < 2; ++ch)
+        w[(int64_t)(dst * 32 + 16 * rh + 4 * ob + oi) * KC + 4 * ch + jl] = accw[rh][ch];
+  };
+
+  // ---- forward: Lu y = f
+  clear_ring();
+#pragma unroll
+  for (int u = 0; u < NSLOT; ++u) load_slot(A[u], Ffw, 0, slot_of(u));
+  if (wforms) load_slot(Aw, Ffw, 0, 0);
+  lds_barrier();
+  for (int I = 0; I < NT; ++I) {
+    const int dof = band_to_dof(v, bm, I * 32 + rr);
+    const int dofc = dof >= 0 ? dof : 0;
+    const double fraw = vin[(int64_t)dofc * ldk + colc];
+    const uint8_t cb = cl[dofc];
+    const int In = min(I + 1, NT - 1);
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+    for (int u = 0; u < NSLOT; ++u) {
+      const int s = 1 + wave + 8 * u;
+      // row I-s (zero before row 0; slots past the band have zero tiles)
+      const double* yp = ring + (int64_t)(((I - s) % BT + BT) % BT) * 32 * KC;
+      tile_step(u < nslot, A[u], yp, acc, Ffw, In, slot_of(u));
+    }
+    store_part(acc);
+    // w_{I-1} (its ring row was completed last step); D^{-1} of row I next
+    if (wforms) {
+      form_w(I - 1, I >= 1 ? I - 1 : NT);
+      load_slot(Aw, Ffw, I, 0);
+    }
+    lds_barrier();
+    if (red) {
+      const bool fok = (dof >= 0) & colok & dof_active(kind, cb);
+      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = (fok ? fraw : 0.0) - part_sum();
+    }
+    lds_barrier();
+  }
+  if (wforms) form_w(NT - 1, NT - 1);
+  __syncthreads();
+  clear_ring();
+
+  // ---- backward: Lu^T x = w
+#pragma unroll
+  for (int u = 0; u < NSLOT; ++u) load_slot(A[u], Fbw, NT - 1, slot_of(u));
+  __syncthreads();
+  for (int I = NT - 1; I >= 0; --I) {
+    const int row = I * 32 + rr;
+    const double fv = w[(int64_t)row * KC + cc];
+    const int dof = band_to_dof(v, bm, row);
+    const uint8_t cb = cl[dof >= 0 ? dof : 0];
+    const int In = max(I - 1, 0);
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+    for (int u = 0; u < NSLOT; ++u) {
+      const int s = 1 + wave + 8 * u;
+      const double* yp = ring + (int64_t)((I + s) % BT) * 32 * KC;   // zero beyond row NT-1
+      tile_step(u < nslot, A[u], yp, acc, Fbw, In, slot_of(u));
+    }
+    store_part(acc);
+    lds_barrier();
+    double xv = 0.0;
+    if (red) {
+      xv = fv - part_sum();
+      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = xv;
+    }
+    const bool wr = red & (dof >= 0) & colok & dof_active(kind, cb) & (((out_classes >> cb) & 1) != 0);
+    *(wr ? vout + (int64_t)dof * ldk + col : w + (int64_t)(NT * 32 + rr) * KC + cc) = xv;
+    lds_barrier();
+  }
+  if (zero_rest && colok && red) {
+    for (int d = rr; d < bm.n_dof; d += 32) {
+      uint8_t k = cl[d];
+      bool written = dof_active(kind, k) && ((out_classes >> k) & 1);
+      if (!written) vout[(int64_t)d * ldk + col] = 0.0;
+    }
+  }
+}
+
+#define SOLVE4_INST(NSL, T)                                                                                     \
+  template __global__ void k_band_solve4<NSL, T>(const BoxMeta*, int, int, int, const T*, const uint8_t*,      \
+                                                 const double*, double*, int, int, int, double*, int64_t,       \
+                                                 const int32_t*);
+SOLVE4_INST(1, double)
+SOLVE4_INST(2, double)
+SOLVE4_INST(3, double)
+SOLVE4_INST(4, double)
+SOLVE4_INST(1, float)
+SOLVE4_INST(2, float)
+SOLVE4_INST(3, float)
+SOLVE4_INST(4, float)
+
 }  // namespace msg
