@@ -425,26 +425,34 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
     }
   };
   // acc += the tile's 32x8 product with the ring row yp; the next row's
-  // pieces of the slot are requested as the current ones are used
+  // pieces of the slot are requested as the current ones are used.  Per inner
+  // step ss the two ring values of the lane feed both row halves, so the four
+  // accumulators are updated in turn (independent MFMA chains); a slot
+  // without a tile multiplies zeros (no branch, so the LDS reads can be
+  // scheduled ahead).
   auto tile_step = [&](bool has, double (&a)[16], const double* yp, double (&acc)[2][2], const T* base, int In,
                        int sl) {
 #pragma unroll
-    for (int pp = 0; pp < 8; ++pp) {
-      const int rh = pp >> 2;
+    for (int ss2 = 0; ss2 < 4; ++ss2) {
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
-        const int ss = 2 * (pp & 3) + e;
-        if (has) {
+        const int ss = 2 * ss2 + e;
+        const double b0 = has ? yp[(4 * ss + kk) * KC + jl] : 0.0;
+        const double b1 = has ? yp[(4 * ss + kk) * KC + 4 + jl] : 0.0;
 #pragma unroll
-          for (int ch = 0; ch < 2; ++ch) {
-            const double b = yp[(4 * ss + kk) * KC + 4 * ch + jl];
-            acc[rh][ch] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[2 * pp + e], b, acc[rh][ch], 0, 0, 0);
-          }
+        for (int rh = 0; rh < 2; ++rh) {
+          const double av = a[2 * (4 * rh + ss2) + e];
+          acc[rh][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b0, acc[rh][0], 0, 0, 0);
+          acc[rh][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b1, acc[rh][1], 0, 0, 0);
         }
       }
-      const V2 t = *piece(base, In, sl, pp);
-      a[2 * pp] = (double)t.x;
-      a[2 * pp + 1] = (double)t.y;
+#pragma unroll
+      for (int rh = 0; rh < 2; ++rh) {
+        const int pp = 4 * rh + ss2;
+        const V2 t = *piece(base, In, sl, pp);
+        a[2 * pp] = (double)t.x;
+        a[2 * pp + 1] = (double)t.y;
+      }
     }
   };
   auto store_part = [&](const double (&acc)[2][2]) {
@@ -470,16 +478,14 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
     double accw[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
     const double* yp = ring + (int64_t)((J < 0 ? 0 : J) % BT) * 32 * KC;
 #pragma unroll
-    for (int pp = 0; pp < 8; ++pp) {
-      const int rh = pp >> 2;
+    for (int ss = 0; ss < 8; ++ss) {
+      const double b0 = yp[(4 * ss + kk) * KC + jl];
+      const double b1 = yp[(4 * ss + kk) * KC + 4 + jl];
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int ss = 2 * (pp & 3) + e;
-#pragma unroll
-        for (int ch = 0; ch < 2; ++ch) {
-          const double b = yp[(4 * ss + kk) * KC + 4 * ch + jl];
-          accw[rh][ch] = __builtin_amdgcn_mfma_f64_4x4x4f64(Aw[2 * pp + e], b, accw[rh][ch], 0, 0, 0);
-        }
+      for (int rh = 0; rh < 2; ++rh) {
+        const double av = Aw[2 * (4 * rh + (ss >> 1)) + (ss & 1)];
+        accw[rh][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b0, accw[rh][0], 0, 0, 0);
+        accw[rh][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b1, accw[rh][1], 0, 0, 0);
       }
     }
 #pragma unroll
