@@ -355,17 +355,15 @@ SOLVE_INST(2, float)
 // the solution row from the LDS ring), and accumulates C[16 rh + 4 o + i][4 ch + j]
 // at lane 16 i + 4 o + j, four 4x4 blocks o per instruction, 8 instructions
 // (ss) per (rh, ch) and tile.  Wavefront w takes tiles s = 1 + w + 8u,
-// u < nslot; all tiles of a wavefront add into the same 4 accumulators, so
+// s <= BT-1 (a wavefront skips its slots past the band: loads and products);
+// all tiles of a wavefront add into the same 4 accumulators, so
 // the wavefront's partial sum of the step leaves in 4 LDS stores.  The
 // wavefront of 4x4x4 products is FP64-FMA work that the matrix cores run at
 // close to their rate with two wavefronts per SIMD (the vector unit does not),
 // and a ring value read from LDS feeds four factor rows.  Wavefront 7 also
 // forms w_{I-1} = D^{-1}_{I-1} y_{I-1} (slot 0 of the forward copy) and
 // stores it.  The factor pieces of the next row are requested one by one as
-// the current ones are used; every load of a step is issued by every
-// wavefront in the same order (a slot without a tile reads a valid address
-// and its products are skipped), so the compiler waits for a load only where
-// its value is needed.  The ring is cleared before each sweep, so rows outside
+// the current ones are used.  The ring is cleared before each sweep, so rows outside
 // the matrix read zeros.  Scratch as for k_band_solve.
 // grid.x = 8 * n_chunk * ceil(n_box/8), 512 threads; dynamic LDS = BT*32*KC doubles.
 template <int NSLOT, typename T>
@@ -401,7 +399,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
   double* vout = out + bm.dof_off * ldk;
   double* w = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
   const int BT = v.BT, NT = v.NT;
-  const int S = solve4_slots(BT), nslot = solve4_nslot(BT);
+  const int S = solve4_slots(BT);
   typedef typename vec2_of<T>::type V2;
   // piece pair pp of slot `sl` of row I, this lane
   auto piece = [&](const T* base, int I, int sl, int pp) {
@@ -412,10 +410,6 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
   const bool wforms = wave == SOLVE_WAVES - 1;
   // factor pieces of this wavefront's slots (and of D^{-1} for wavefront 7)
   double A[NSLOT][16], Aw[16];
-  auto slot_of = [&](int u) {
-    const int s = 1 + wave + 8 * u;
-    return u < nslot ? s : 0;   // no tile: a valid address, products skipped
-  };
   auto load_slot = [&](double (&a)[16], const T* base, int I, int sl) {
 #pragma unroll
     for (int pp = 0; pp < 8; ++pp) {
@@ -427,18 +421,15 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
   // acc += the tile's 32x8 product with the ring row yp; the next row's
   // pieces of the slot are requested as the current ones are used.  Per inner
   // step ss the two ring values of the lane feed both row halves, so the four
-  // accumulators are updated in turn (independent MFMA chains); a slot
-  // without a tile multiplies zeros (no branch, so the LDS reads can be
-  // scheduled ahead).
-  auto tile_step = [&](bool has, double (&a)[16], const double* yp, double (&acc)[2][2], const T* base, int In,
-                       int sl) {
+  // accumulators are updated in turn (independent MFMA chains).
+  auto tile_step = [&](double (&a)[16], const double* yp, double (&acc)[2][2], const T* base, int In, int sl) {
 #pragma unroll
     for (int ss2 = 0; ss2 < 4; ++ss2) {
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int ss = 2 * ss2 + e;
-        const double b0 = has ? yp[(4 * ss + kk) * KC + jl] : 0.0;
-        const double b1 = has ? yp[(4 * ss + kk) * KC + 4 + jl] : 0.0;
+        const double b0 = yp[(4 * ss + kk) * KC + jl];
+        const double b1 = yp[(4 * ss + kk) * KC + 4 + jl];
 #pragma unroll
         for (int rh = 0; rh < 2; ++rh) {
           const double av = a[2 * (4 * rh + ss2) + e];
@@ -498,7 +489,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
   // ---- forward: Lu y = f
   clear_ring();
 #pragma unroll
-  for (int u = 0; u < NSLOT; ++u) load_slot(A[u], Ffw, 0, slot_of(u));
+  for (int u = 0; u < NSLOT; ++u)
+    if (1 + wave + 8 * u <= BT - 1) load_slot(A[u], Ffw, 0, 1 + wave + 8 * u);
   if (wforms) load_slot(Aw, Ffw, 0, 0);
   lds_barrier();
   for (int I = 0; I < NT; ++I) {
@@ -511,9 +503,9 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
 #pragma unroll
     for (int u = 0; u < NSLOT; ++u) {
       const int s = 1 + wave + 8 * u;
-      // row I-s (zero before row 0; slots past the band have zero tiles)
+      // row I-s (zero before row 0); tiles past the band are skipped (wave-uniform)
       const double* yp = ring + (int64_t)(((I - s) % BT + BT) % BT) * 32 * KC;
-      tile_step(u < nslot, A[u], yp, acc, Ffw, In, slot_of(u));
+      if (s <= BT - 1) tile_step(A[u], yp, acc, Ffw, In, s);
     }
     store_part(acc);
     // w_{I-1} (its ring row was completed last step); D^{-1} of row I next
@@ -534,7 +526,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
 
   // ---- backward: Lu^T x = w
 #pragma unroll
-  for (int u = 0; u < NSLOT; ++u) load_slot(A[u], Fbw, NT - 1, slot_of(u));
+  for (int u = 0; u < NSLOT; ++u)
+    if (1 + wave + 8 * u <= BT - 1) load_slot(A[u], Fbw, NT - 1, 1 + wave + 8 * u);
   __syncthreads();
   for (int I = NT - 1; I >= 0; --I) {
     const int row = I * 32 + rr;
@@ -547,7 +540,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
     for (int u = 0; u < NSLOT; ++u) {
       const int s = 1 + wave + 8 * u;
       const double* yp = ring + (int64_t)((I + s) % BT) * 32 * KC;   // zero beyond row NT-1
-      tile_step(u < nslot, A[u], yp, acc, Fbw, In, slot_of(u));
+      if (s <= BT - 1) tile_step(A[u], yp, acc, Fbw, In, s);
     }
     store_part(acc);
     lds_barrier();
