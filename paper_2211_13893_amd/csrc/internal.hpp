@@ -12,10 +12,13 @@
 //     the inverses of the diagonal tiles follow in a separate NT*1024 array;
 //   * after factorisation the off-diagonal band of every box matrix is copied
 //     twice more, once per sweep direction of the block solve, in the order
-//     the solve's threads read it: fragment double2 j (0..31) of solve thread
-//     t (0..nthr-1) for tile set p (tiles 1+32p .. 32+32p) of tile row I at
-//     (((I*nsets + p)*32 + j) * nthr + t) * 2, so that a wavefront's load
-//     instruction reads 1 KB of consecutive memory.
+//     the solve reads it, so that a wavefront's load instruction reads 1 KB of
+//     consecutive memory.  Bands of at most 33 tiles (matrix-core solve):
+//     1 + 8 nslot slots of 8 KB per tile row (slot 0 = D^{-1} in the forward
+//     copy, slot s = tile s), double2 pp of lane l at ((I*S + slot)*8 + pp)*64
+//     + l (see k_band_relayout4).  Wider bands (vector-FMA solve): fragment
+//     double2 j (0..31) of solve thread t (0..nthr-1) for tile set p (tiles
+//     1+32p .. 32+32p) of tile row I at (((I*nsets + p)*32 + j) * nthr + t) * 2.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
