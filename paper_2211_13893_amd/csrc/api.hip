@@ -43,6 +43,7 @@ __global__ void k_keep_classes(const uint8_t*, int, int, int64_t, double*);
 struct Blk3 { const double* p[3]; };
 struct Blk4x3 { const double* p[4][3]; };
 struct Out4 { double* p[4]; };
+template <int NB>
 __global__ void k_gram_partial(const BoxMeta*, int, Blk3, Blk3, Blk3, int, int, int, double*,
                                const int32_t*);
 __global__ void k_gram_reduce(int, int, const double*, double*, const int32_t*);
@@ -739,7 +740,11 @@ static void lds_attributes() {
   for (const void* f : solves4) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
-  (void)hipFuncSetAttribute((const void*)k_gram_partial, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)k_gram_partial<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_gram_partial<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_gram_partial<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   (void)hipGetLastError();
 }
@@ -859,7 +864,10 @@ static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double*
   }
   {
     ProfScope ps(c.p, PK_GRAM, c.s, by, fl);
-    k_gram_partial<<<grid, 256, lds, c.s>>>(c.v.meta, nblk, Z, A, B, k, GRAM_ROWS, c.p->n_gchunk, c.w.part,
+    // 16x16 blocks of the m x m result per side: 2, 4 or 6
+    const int nb16 = (m + 15) / 16;
+    auto kern = nb16 <= 2 ? k_gram_partial<2> : (nb16 <= 4 ? k_gram_partial<4> : k_gram_partial<6>);
+    kern<<<grid, 256, lds, c.s>>>(c.v.meta, nblk, Z, A, B, k, GRAM_ROWS, c.p->n_gchunk, c.w.part,
                                             act);
     LAUNCHCHK(c.p);
     dim3 g2((2 * m * m + 255) / 256, c.nb);
@@ -1287,7 +1295,8 @@ extern "C" int msgfem_coarse_assemble(msgfem_plan* p, const void* ops, void* wor
     Z.p[0] = A.p[0] = B.p[0] = V;
     Z.p[1] = Z.p[2] = A.p[1] = A.p[2] = B.p[1] = B.p[2] = nullptr;
     (void)Zb;
-    k_gram_partial<<<dim3(p->n_gchunk, nb, 2), 256, (size_t)k * k * 8, s>>>(v.meta, 1, Z, A, B, k, GRAM_ROWS,
+    auto kern = k <= 32 ? k_gram_partial<2> : (k <= 64 ? k_gram_partial<4> : k_gram_partial<6>);
+    kern<<<dim3(p->n_gchunk, nb, 2), 256, (size_t)k * k * 8, s>>>(v.meta, 1, Z, A, B, k, GRAM_ROWS,
                                                                             p->n_gchunk,
                                                             c.w.part, nullptr);
     k_gram_reduce<<<dim3((2 * k * k + 255) / 256, nb), 256, 0, s>>>(k, p->n_gchunk, c.w.part, c.w.G, nullptr);

@@ -38,6 +38,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // (16x16x4: one group of 4 rows is one inner step), two groups per iteration
 // so that the next rows are in flight during the products.  The four waves'
 // sums are added in a fixed order through LDS (dynamic LDS: m*m doubles).
+template <int NB>
 __global__ __launch_bounds__(256) void k_gram_partial(const BoxMeta* __restrict__ meta, int nblk,
                                                       Blk3 Z, Blk3 AZ, Blk3 BZ, int k,
                                                       int rows_per_chunk, int n_chunk,
@@ -48,43 +49,51 @@ __global__ __launch_bounds__(256) void k_gram_partial(const BoxMeta* __restrict_
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
   const int m = nblk * k;
-  const int nb16 = (m + 15) >> 4;      // <= 6
-  const Blk3& W = which ? BZ : AZ;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r_begin = chunk * rows_per_chunk;
   const int r_end = min(bm.n_dof, r_begin + rows_per_chunk);
   const int lc = lane & 15, lr = lane >> 4;
-  // the column of this lane in every 16-block: block of the basis and column in it
-  int cblk[6], ccol[6];
-#pragma unroll
-  for (int b = 0; b < 6; ++b) {
-    const int c = 16 * b + lc;
-    cblk[b] = (c < m) ? c / k : -1;
-    ccol[b] = (c < m) ? c % k : 0;
-  }
-  dbl4 acc[6][6];
-#pragma unroll
-  for (int bi = 0; bi < 6; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 6; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
   const int64_t base = bm.dof_off * k;
+  // per-lane column pointers of every 16-block (block of the basis selected
+  // from the kernel arguments without indexing them); columns past m read
+  // nothing and give zeros
+  const double* zp[NB];
+  const double* wp[NB];
+  bool cok[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int c = 16 * b + lc;
+    cok[b] = c < m;
+    const int cb = cok[b] ? c / k : 0, cc = cok[b] ? c % k : 0;
+    const double* z = cb == 0 ? Z.p[0] : (cb == 1 ? Z.p[1] : Z.p[2]);
+    const double* wa = cb == 0 ? AZ.p[0] : (cb == 1 ? AZ.p[1] : AZ.p[2]);
+    const double* wb = cb == 0 ? BZ.p[0] : (cb == 1 ? BZ.p[1] : BZ.p[2]);
+    zp[b] = z + base + cc;
+    wp[b] = (which ? wb : wa) + base + cc;
+  }
+  dbl4 acc[NB][NB];
+#pragma unroll
+  for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NB; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
   auto load = [&](int row, double (&zf)[6], double (&wf)[6]) {
     const bool rok = row < r_end;
+    const int64_t o = (int64_t)(rok ? row : r_begin) * k;
 #pragma unroll
-    for (int b = 0; b < 6; ++b) {
-      const bool ok = b < nb16 && rok && cblk[b] >= 0;
-      const int64_t o = base + (int64_t)(rok ? row : r_begin) * k + ccol[b];
-      const int cb = cblk[b] >= 0 ? cblk[b] : 0;
-      zf[b] = ok ? Z.p[cb][o] : 0.0;
-      wf[b] = ok ? W.p[cb][o] : 0.0;
+    for (int b = 0; b < NB; ++b) {
+      // every lane loads (a valid address), then drops what is outside
+      const bool ok = rok && cok[b];
+      const double zv = zp[b][o], wv = wp[b][o];
+      zf[b] = ok ? zv : 0.0;
+      wf[b] = ok ? wv : 0.0;
     }
   };
   auto mma = [&](const double (&zf)[6], const double (&wf)[6]) {
 #pragma unroll
-    for (int bi = 0; bi < 6; ++bi)
+    for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-      for (int bj = bi; bj < 6; ++bj)
-        if (bj < nb16) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(zf[bi], wf[bj], acc[bi][bj], 0, 0, 0);
+      for (int bj = bi; bj < NB; ++bj)
+        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(zf[bi], wf[bj], acc[bi][bj], 0, 0, 0);
   };
   // row groups g = wave, wave + 4, ... (4 rows each), two per iteration
   const int n_groups = (r_end - r_begin + 3) >> 2;
@@ -99,10 +108,9 @@ __global__ __launch_bounds__(256) void k_gram_partial(const BoxMeta* __restrict_
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
 #pragma unroll
-      for (int bi = 0; bi < 6; ++bi)
+      for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-        for (int bj = bi; bj < 6; ++bj) {
-          if (bj >= nb16) continue;
+        for (int bj = bi; bj < NB; ++bj) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int i = 16 * bi + lr + 4 * v, j = 16 * bj + lc;
@@ -121,6 +129,14 @@ __global__ __launch_bounds__(256) void k_gram_partial(const BoxMeta* __restrict_
 }
 
 // G[box][2][m][m] = sum over chunks (fixed order); lower 16-blocks mirrored.
+
+template __global__ void k_gram_partial<2>(const BoxMeta*, int, Blk3, Blk3, Blk3, int, int, int, double*,
+                                           const int32_t*);
+template __global__ void k_gram_partial<4>(const BoxMeta*, int, Blk3, Blk3, Blk3, int, int, int, double*,
+                                           const int32_t*);
+template __global__ void k_gram_partial<6>(const BoxMeta*, int, Blk3, Blk3, Blk3, int, int, int, double*,
+                                           const int32_t*);
+
 __global__ void k_gram_reduce(int m, int n_chunk, const double* __restrict__ part,
                               double* __restrict__ G, const int32_t* __restrict__ active) {
   int box = blockIdx.y;
