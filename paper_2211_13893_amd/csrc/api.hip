@@ -25,6 +25,7 @@ __global__ void k_chol_update(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_panel(const MatDesc*, int, double*);
 __global__ void k_chol_step(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_unit(const MatDesc*, double*);
+__global__ void k_band_unit_relayout4(const BoxMeta*, int, double*);
 __global__ void k_band_relayout(const BoxMeta*, int, double*);
 __global__ void k_band_relayout4(const BoxMeta*, int, double*);
 template <int KC, int NS, typename T>
@@ -564,13 +565,13 @@ static int tile_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_
 }
 
 // Left-looking tile Cholesky of banded SPD matrices, one launch per tile
-// column (which also factors the next diagonal tile), then the block
+// column (which also factors the next diagonal tile), then (unit) the block
 // unit-lower rewrite.
 static int band_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_nt, int max_bt, double* fac,
-                         int32_t* status, hipStream_t s) {
+                         int32_t* status, bool unit, hipStream_t s) {
   for (int J = -1; J <= max_nt - 2; ++J)
     k_chol_step<<<dim3(nmat, (max_bt + 1 + 3) / 4), 256, 0, s>>>(mats, J, fac, status);
-  k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
+  if (unit) k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
   LAUNCHCHK(p);
   return 0;
 }
@@ -618,6 +619,9 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
     k_classes_mu<<<grid, 256, 0, s>>>(v.meta, md, 2 * p->overlap, v.wtot, v.cls, v.mu1);
     LAUNCHCHK(p);
   }
+  // batches whose bands all fit the matrix-core solve take the unit-lower
+  // rewrite inside the copies (k_band_unit_relayout4)
+  const bool fused_unit = solve4_kind(p, 0) && solve4_kind(p, 1);
   for (int kind = 0; kind < 2; ++kind) {
     int64_t tot = p->max_fac_tiles * 128;
     int64_t blocks = std::min<int64_t>((tot + 255) / 256, 65535);
@@ -646,7 +650,8 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
       max_bt = std::max(max_bt, std::max(m.bt11, m.bth));
     }
     ProfScope ps(p, PK_POTRF, s, by, fl);
-    if (band_cholesky(p, v.mats, (int)p->mats.size(), max_nt, max_bt, v.fac, status, s)) return MSGFEM_EHIP;
+    if (band_cholesky(p, v.mats, (int)p->mats.size(), max_nt, max_bt, v.fac, status, !fused_unit, s))
+      return MSGFEM_EHIP;
   }
   for (int kind = 0; kind < 2; ++kind) {
     int max_nt = 1, max_sets = 1;
@@ -658,7 +663,10 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
       by += 3 * 8.0 * solve_copy_doubles(nt, bt);
     }
     ProfScope ps(p, PK_BUILD, s, by, 0.0);
-    if (solve4_kind(p, kind))
+    if (fused_unit)
+      k_band_unit_relayout4<<<dim3((solve4_slots(p->max_bt_kind[kind]) + 3) / 4, max_nt, nb), 256, 0, s>>>(
+          v.meta, kind, v.fac);
+    else if (solve4_kind(p, kind))
       k_band_relayout4<<<dim3(solve4_slots(p->max_bt_kind[kind]), max_nt, nb), 256, 0, s>>>(v.meta, kind, v.fac);
     else
       k_band_relayout<<<dim3(SOLVE_TILES * max_sets, max_nt, nb), 256, 0, s>>>(v.meta, kind, v.fac);

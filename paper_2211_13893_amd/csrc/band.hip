@@ -772,6 +772,63 @@ __global__ __launch_bounds__(256) void k_band_relayout4(const BoxMeta* __restric
   }
 }
 
+// The block unit-lower rewrite (as k_chol_unit) fused with the copies of
+// k_band_relayout4, for batches whose bands all fit the matrix-core solve:
+// each tile Lu(I, I-s) = L(I, I-s) L_{I-s}^{-1}, and D^{-1}_I = L_I^{-T} L_I^{-1},
+// is formed once and written straight into the forward copy (row I, slot s)
+// and the backward copy (row I-s, slot s, transposed); D^{-1}_I also replaces
+// the band's diagonal tile, while the off-diagonal tiles of the band keep L
+// (only the copies are read afterwards).  The band is read once and the
+// copies written once, instead of reading the band, rewriting it and reading
+// it again.  Slots outside the matrix or the band are zero: a forward slot
+// with s > I or s >= BT, a backward slot with s = 0, s >= BT or I + s >= NT.
+// One wavefront per slot s = 4 blockIdx.x + wave of tile row I = blockIdx.y;
+// grid (ceil(S / 4), max NT, n_box), 256 threads.
+__global__ __launch_bounds__(256) void k_band_unit_relayout4(const BoxMeta* __restrict__ meta, int kind,
+                                                             double* __restrict__ fac) {
+  __shared__ double Tl[4][MSG_TILE2];
+  const BoxMeta& bm = meta[blockIdx.z];
+  BandView v = band_view(bm, kind);
+  const int S = solve4_slots(v.BT);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s = 4 * blockIdx.x + wave, I = blockIdx.y;
+  if (I >= v.NT || s >= S) return;
+  double* L = fac + v.off;
+  const double* Linv = fac + v.ioff;
+  double2* fw = (double2*)(fac + v.fw) + ((int64_t)I * S + s) * 8 * 64;
+  // operand order of the lane (see k_band_relayout4): row and inner index of e = 0
+  const int kk = lane >> 4, o = (lane >> 2) & 3, i = lane & 3;
+  if (s == 0 || (s < v.BT && s <= I)) {
+    double* T = Tl[wave];
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
+    if (s == 0) tile_mfma_atb(Linv + (int64_t)I * MSG_TILE2, Linv + (int64_t)I * MSG_TILE2, acc, lane);
+    else tile_mfma_ab(L + ((int64_t)I * v.BT + s) * MSG_TILE2, Linv + (int64_t)(I - s) * MSG_TILE2, acc, lane);
+    tile_store_acc(T, acc, lane);
+    if (s == 0) tile_store_acc(L + (int64_t)I * v.BT * MSG_TILE2, acc, lane);
+    // other lanes' entries of T are read next
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    double2* bw = (double2*)(fac + v.bw) + ((int64_t)(I - s) * S + s) * 8 * 64;
+#pragma unroll
+    for (int pp = 0; pp < 8; ++pp) {
+      const int row = 16 * (pp >> 2) + 4 * o + i, c0 = 8 * (pp & 3) + kk;
+      fw[pp * 64 + lane] = make_double2(T[row * 32 + c0], T[row * 32 + c0 + 4]);
+      if (s >= 1) bw[pp * 64 + lane] = make_double2(T[c0 * 32 + row], T[(c0 + 4) * 32 + row]);
+    }
+  } else {
+#pragma unroll
+    for (int pp = 0; pp < 8; ++pp) fw[pp * 64 + lane] = make_double2(0.0, 0.0);
+  }
+  if (s == 0 || s >= v.BT || I + s >= v.NT) {
+    double2* bz = (double2*)(fac + v.bw) + ((int64_t)I * S + s) * 8 * 64;
+#pragma unroll
+    for (int pp = 0; pp < 8; ++pp) bz[pp * 64 + lane] = make_double2(0.0, 0.0);
+  }
+}
+
 
 // FP32 copies for the mixed path (same element offsets as the FP64 arrays):
 // the two solve-ordered band copies and the D^{-1} diagonal tiles of both box

@@ -79,14 +79,16 @@ __global__ __launch_bounds__(256) void k_spmm(const BoxMeta* __restrict__ meta, 
     }
   // Neighbours outside the box have zero stencil blocks (the assembly writes
   // all 27 blocks of every node), so their index is clamped into the box and
-  // the 27-point loop runs without branches.
+  // the 27-point loop runs without branches.  With the second output the x
+  // loop stays rolled: its registers then allow 4 wavefronts per SIMD.
+  constexpr int kUnrollX = TWO ? 1 : 3;
 #pragma unroll 1
   for (int dz = -1; dz <= 1; ++dz) {
     const int kk = min(max(lk + dz, 0), bm.mz - 1);
 #pragma unroll 1
     for (int dy = -1; dy <= 1; ++dy) {
       const int jj = min(max(lj + dy, 0), bm.my - 1);
-#pragma unroll
+#pragma unroll kUnrollX
       for (int dx = -1; dx <= 1; ++dx) {
         const int ii = min(max(li + dx, 0), bm.mx - 1);
         const int nn = ii + bm.mx * (jj + bm.my * kk);
