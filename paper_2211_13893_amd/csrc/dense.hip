@@ -340,6 +340,22 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
     }
   };
   int* zero_pq = order;   // scratch flags per pair (reused: order is set in step 6)
+  // A thread's share of a round is the same in every round: the 2x2 blocks
+  // (a, b), a <= b, numbered e = tid and tid + RR_THREADS along the rows of the
+  // triangle (row a holds h - a blocks; h (h + 1) / 2 <= 2 RR_THREADS for
+  // m <= 126), and the rows g, g + G, ... of V for rotation i.
+  int blk_a[2], blk_b[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    int e = tid + u * RR_THREADS, a = 0;
+    while (a < h && e >= h - a) {
+      e -= h - a;
+      ++a;
+    }
+    blk_a[u] = a < h ? a : -1;
+    blk_b[u] = a < h ? a + e : -1;
+  }
+  const int vG = RR_THREADS / h, vi = tid % h, vg = tid / h;
   for (int sweep = 0; sweep < 30; ++sweep) {
     // convergence test: off-diagonal mass vs. total (one barrier)
     double off = 0.0, tot = 0.0;
@@ -382,10 +398,12 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
         const double app = C[p * ld + p], aqq = C[q * ld + q];
         double c = 1.0, sn = 0.0;
         int z = 0;
-        if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
+        // (|apq| > 1e-18 sqrt|app aqq| compared squared: one square root less
+        // on the round's serial path)
+        if (fabs(apq) > 1e-300 && apq * apq > 1e-36 * fabs(app * aqq)) {
           const double th = (aqq - app) / (2.0 * apq);
           const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-          c = 1.0 / sqrt(1.0 + t * t);
+          c = rsqrt(1.0 + t * t);
           sn = t * c;
           z = 1;
         } else if (fabs(apq) > 0.0) {
@@ -397,9 +415,10 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
       }
       __syncthreads();
       // C <- R C R^T over the 2x2 blocks (a <= b) of the upper triangle
-      for (int t = tid; t < h * h; t += RR_THREADS) {
-        const int ia = t / h, ib = t - (t / h) * h;
-        if (ia > ib) continue;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int ia = blk_a[u], ib = blk_b[u];
+        if (ia < 0) continue;
         const int pa = pp[ia], qa = qq[ia], pb = pp[ib], qb = qq[ib];
         const double ca = rc[ia], sa = rs[ia], cb = rc[ib], sb = rs[ib];
         if (ia == ib) {
@@ -428,8 +447,7 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
       }
       // V <- V R^T: thread (pair i, row group g) takes rows g, g + G, ...
       {
-        const int G = RR_THREADS / h;
-        const int i = tid % h, g = tid / h;
+        const int G = vG, i = vi, g = vg;
         if (g < G) {
           const int p = pp[i], q = qq[i];
           const double c = rc[i], sn = rs[i];
