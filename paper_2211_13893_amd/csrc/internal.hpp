@@ -10,9 +10,10 @@
 //   * banded SPD factors are 32x32 tiles: tile (I, I-s) at
 //     ((I*BT + s) * 1024), row-major inside the tile, s = 0 the diagonal tile;
 //     the inverses of the diagonal tiles follow in a separate NT*1024 array;
-//   * after factorisation the off-diagonal band of every box matrix is copied
-//     twice more, once per sweep direction of the block solve, in the order
-//     the solve reads it, so that a wavefront's load instruction reads 1 KB of
+//   * after factorisation the unit-lower band (Lu, D^{-1}) of every box matrix
+//     is written twice more, once per sweep direction of the block solve, in
+//     the order the solve reads it (for bands of at most 33 tiles straight
+//     from L, the band then keeping L off the diagonal and D^{-1} on it), so that a wavefront's load instruction reads 1 KB of
 //     consecutive memory.  Bands of at most 33 tiles (matrix-core solve):
 //     1 + 8 nslot slots of 8 KB per tile row (slot 0 = D^{-1} in the forward
 //     copy, slot s = tile s), double2 pp of lane l at ((I*S + slot)*8 + pp)*64
