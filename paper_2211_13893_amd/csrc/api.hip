@@ -882,7 +882,7 @@ static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double*
     k_gram_reduce<<<g2, 256, 0, c.s>>>(m, c.p->n_gchunk, c.w.part, c.w.G, act);
     LAUNCHCHK(c.p);
   }
-  size_t lds_rr = ((size_t)2 * m * (m + 1) + 3 * m + 256 + 2 * m + 1) * 8;
+  size_t lds_rr = ((size_t)2 * m * (m + 1) + 4 * m + 256) * 8 + ((size_t)5 * m + 1) * 4;
   ProfScope ps2(c.p, PK_RR, c.s, 0.0, 0.0);
   k_rayleigh_ritz<<<c.nb, 1024, lds_rr, c.s>>>(m, k, 1, c.p->opts.shift, c.w.G, c.w.L, c.w.Y, c.w.Yp,
                                                c.w.nu, act);

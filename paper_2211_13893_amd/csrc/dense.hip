@@ -194,14 +194,14 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
   double* V = C + m * ld;
   double* dsc = V + m * ld;          // m scale factors
   double* ev = dsc + m;              // m eigenvalues
-  double* rc = ev + m;               // m/2 rotation cos
-  double* rs = rc + m / 2;           // m/2 rotation sin
-  double* red = rs + m / 2;          // 256 reduction slots
+  double* rcb = ev + m;              // 2 x m/2 rotation cos (two rounds: even, odd)
+  double* rsb = rcb + m;             // 2 x m/2 rotation sin
+  double* red = rsb + m;             // 256 reduction slots
   int* drop = (int*)(red + 256);     // m
   int* order = drop + m;             // m
-  int* pp = order + m;               // m/2: rotation pairs of the current round
-  int* qq = pp + m / 2;              // m/2
-  int* perm = qq + m / 2;            // m: active directions first (Jacobi on those only)
+  int* ppb = order + m;              // 2 x m/2: rotation pairs of the two rounds
+  int* qqb = ppb + m;                // 2 x m/2
+  int* perm = qqb + m;               // m: active directions first (Jacobi on those only)
   int* nj = perm + m;                // 1: size of the Jacobi block
   const int tid = threadIdx.x;
   const double* GA = G + (int64_t)box * 2 * m * m;
@@ -319,7 +319,8 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
   //    i = 1..m/2-1; all m/2 rotations of a round commute.  A round computes
   //    the rotations, then applies them to C from both sides in one pass over
   //    the 2x2 blocks C[{p_a,q_a},{p_b,q_b}] <- R_a B R_b^T, R = [[c,-s],[s,c]],
-  //    and to the columns of V (V <- V R^T).  Only the upper triangle of C is
+  //    and to the columns of V (V <- V R^T); the next round's rotations are
+//    computed while V is updated.  Only the upper triangle of C is
   //    kept (entry (x, y) at C[min][max]), so a round updates the blocks with
   //    a <= b; a thread applies one rotation to several rows of V.  Both halve
   //    the LDS traffic of a round, which bounds it.
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
       q = 1 + a2;
     }
   };
-  int* zero_pq = order;   // scratch flags per pair (reused: order is set in step 6)
+  int* zero_pq = order;   // 2 x m/2 flags per pair (reused: order is set in step 6)
   // A thread's share of a round is the same in every round: the 2x2 blocks
   // (a, b), a <= b, numbered e = tid and tid + RR_THREADS along the rows of the
   // triangle (row a holds h - a blocks; h (h + 1) / 2 <= 2 RR_THREADS for
@@ -355,7 +356,34 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
     blk_a[u] = a < h ? a : -1;
     blk_b[u] = a < h ? a + e : -1;
   }
-  const int vG = RR_THREADS / h, vi = tid % h, vg = tid / h;
+  // V is updated by the threads below RR_THREADS - 64 while the last wavefront
+  // computes the next round's rotations (they depend on C only)
+  const int vG = (RR_THREADS - 64) / h, vi = tid % h, vg = tid / h;
+  // rotation i of round r into buffer b (of two, by round parity)
+  auto rotation = [&](int r, int b, int i) {
+    int p, q;
+    pair_of(r, i, p, q);
+    ppb[b * (m / 2) + i] = p;
+    qqb[b * (m / 2) + i] = q;
+    const double apq = C[cix(p, q)];
+    const double app = C[p * ld + p], aqq = C[q * ld + q];
+    double c = 1.0, sn = 0.0;
+    int z = 0;
+    // (|apq| > 1e-18 sqrt|app aqq| compared squared: one square root less on
+    // the round's serial path)
+    if (fabs(apq) > 1e-300 && apq * apq > 1e-36 * fabs(app * aqq)) {
+      const double th = (aqq - app) / (2.0 * apq);
+      const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+      c = rsqrt(1.0 + t * t);
+      sn = t * c;
+      z = 1;
+    } else if (fabs(apq) > 0.0) {
+      z = 1;
+    }
+    rcb[b * (m / 2) + i] = c;
+    rsb[b * (m / 2) + i] = sn;
+    zero_pq[b * (m / 2) + i] = z;
+  };
   for (int sweep = 0; sweep < 30; ++sweep) {
     // convergence test: off-diagonal mass vs. total (one barrier)
     double off = 0.0, tot = 0.0;
@@ -388,32 +416,15 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
     __syncthreads();
     // relative off-diagonal norm 1e-13: Ritz values then carry errors ~1e-26
     if (offs <= 1e-26 * tots || tots == 0.0) break;
+    for (int i = tid; i < h; i += RR_THREADS) rotation(0, 0, i);
+    __syncthreads();
     for (int r = 0; r < m1; ++r) {
-      for (int i = tid; i < h; i += RR_THREADS) {
-        int p, q;
-        pair_of(r, i, p, q);
-        pp[i] = p;
-        qq[i] = q;
-        const double apq = C[cix(p, q)];
-        const double app = C[p * ld + p], aqq = C[q * ld + q];
-        double c = 1.0, sn = 0.0;
-        int z = 0;
-        // (|apq| > 1e-18 sqrt|app aqq| compared squared: one square root less
-        // on the round's serial path)
-        if (fabs(apq) > 1e-300 && apq * apq > 1e-36 * fabs(app * aqq)) {
-          const double th = (aqq - app) / (2.0 * apq);
-          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-          c = rsqrt(1.0 + t * t);
-          sn = t * c;
-          z = 1;
-        } else if (fabs(apq) > 0.0) {
-          z = 1;
-        }
-        rc[i] = c;
-        rs[i] = sn;
-        zero_pq[i] = z;
-      }
-      __syncthreads();
+      const int bo = (r & 1) * (m / 2);
+      const int* pp = ppb + bo;
+      const int* qq = qqb + bo;
+      const double* rc = rcb + bo;
+      const double* rs = rsb + bo;
+      const int* zq = zero_pq + bo;
       // C <- R C R^T over the 2x2 blocks (a <= b) of the upper triangle
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
@@ -428,9 +439,9 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
           const double r10 = sa * b00 + ca * b01, r11 = sa * b01 + ca * b11;
           const double n00 = ca * r00 - sa * r01, n11 = sa * r10 + ca * r11;
           // (pa, qa) is the entry the rotation annihilates
-          const double n01 = zero_pq[ia] ? 0.0 : sa * r00 + ca * r01;
+          const double n01 = zq[ia] ? 0.0 : sa * r00 + ca * r01;
           C[pa * ld + pa] = n00;
-          C[e01] = (pa < qa) ? n01 : (zero_pq[ia] ? 0.0 : ca * r10 - sa * r11);
+          C[e01] = (pa < qa) ? n01 : (zq[ia] ? 0.0 : ca * r10 - sa * r11);
           C[qa * ld + qa] = n11;
         } else {
           const int e00 = cix(pa, pb), e01 = cix(pa, qb), e10 = cix(qa, pb), e11 = cix(qa, qb);
@@ -445,8 +456,13 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
           C[e11] = sb * r10 + cb * r11;
         }
       }
-      // V <- V R^T: thread (pair i, row group g) takes rows g, g + G, ...
-      {
+      __syncthreads();
+      if (tid >= RR_THREADS - 64) {
+        // the next round's rotations, from the updated C
+        const int i = tid - (RR_THREADS - 64);
+        if (r + 1 < m1 && i < h) rotation(r + 1, (r + 1) & 1, i);
+      } else {
+        // V <- V R^T: thread (pair i, row group g) takes rows g, g + G, ...
         const int G = vG, i = vi, g = vg;
         if (g < G) {
           const int p = pp[i], q = qq[i];
