@@ -979,7 +979,7 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
       LAUNCHCHK(p);
       k_fill_i32<<<1, 32, 0, c.s>>>(c.w.nact, 1, 0);
       // FP32 phase: residuals are estimates, no box is retired
-      k_converge<<<(nb + 63) / 64, 64, 0, c.s>>>(c.v.meta, nb, k, n_chunk, c.w.rpart, c.w.nu,
+      k_converge<<<nb, 64, 0, c.s>>>(c.v.meta, nb, k, n_chunk, c.w.rpart, c.w.nu,
                                                   c.use32 ? 0.0 : p->opts.tol, c.w.rho, act, c.w.iters,
                                                   c.w.nact, it < p->opts.maxit ? 1 : 0);
       LAUNCHCHK(p);

@@ -710,12 +710,12 @@ __global__ void k_converge(const BoxMeta* __restrict__ meta, int n_box, int k, i
                            double tol, double* __restrict__ rho, int32_t* __restrict__ active,
                            int32_t* __restrict__ iters, int32_t* __restrict__ n_active,
                            int count_iter) {
-  int box = blockIdx.x * blockDim.x + threadIdx.x;
-  if (box >= n_box) return;
-  if (!active[box]) return;
-  int nev = meta[box].n_ev;
+  // one wavefront per box, lane c < k takes column c (chunks summed in order)
+  const int box = blockIdx.x, c = threadIdx.x;
+  if (box >= n_box || !active[box]) return;
+  const int nev = meta[box].n_ev;
   bool ok = true;
-  for (int c = 0; c < k; ++c) {
+  if (c < k) {
     double a = 0.0, b = 0.0, d = 0.0;
     for (int ch = 0; ch < n_chunk; ++ch) {
       const double* p = part + (((int64_t)box * n_chunk + ch) * 3) * 32;
@@ -723,17 +723,20 @@ __global__ void k_converge(const BoxMeta* __restrict__ meta, int n_box, int k, i
       b += p[32 + c];
       d += p[64 + c];
     }
-    double v = nu[(int64_t)box * k + c];
-    double den = sqrt(b) + v * sqrt(d);
-    double r = den > 0.0 ? sqrt(a) / den : 0.0;
+    const double v = nu[(int64_t)box * k + c];
+    const double den = sqrt(b) + v * sqrt(d);
+    const double r = den > 0.0 ? sqrt(a) / den : 0.0;
     rho[(int64_t)box * k + c] = r;
-    if (c < nev && !(r <= tol)) ok = false;
+    ok = !(c < nev && !(r <= tol));
   }
-  if (ok) {
-    active[box] = 0;
-  } else {
-    iters[box] += count_iter;
-    atomicAdd(n_active, 1);
+  const bool all_ok = __all(ok);
+  if (c == 0) {
+    if (all_ok) {
+      active[box] = 0;
+    } else {
+      iters[box] += count_iter;
+      atomicAdd(n_active, 1);
+    }
   }
 }
 
