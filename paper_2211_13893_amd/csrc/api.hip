@@ -1065,7 +1065,7 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
   }
   // boxes still active did not converge
   {
-    k_output<<<nb, 256, 0, c.s>>>(c.v.meta, k, p->opts.shift, B[0][0], c.w.nu, c.w.rho, evals, evecs,
+    k_output<<<nb, 1024, 0, c.s>>>(c.v.meta, k, p->opts.shift, B[0][0], c.w.nu, c.w.rho, evals, evecs,
                                   resid);
     LAUNCHCHK(p);
     HIPCHK(p, hipMemcpyAsync(iters, c.w.iters, nb * 4, hipMemcpyDeviceToDevice, c.s));

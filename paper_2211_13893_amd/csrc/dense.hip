@@ -799,16 +799,18 @@ __global__ void k_copy_start(const BoxMeta* __restrict__ meta, const uint8_t* __
 
 // Output: lambda ascending, unit 2-norm eigenvectors on all box DoFs (0 on B3)
 // with the entry of largest magnitude positive, rho per pair.  One workgroup per box.
-__global__ __launch_bounds__(256) void k_output(const BoxMeta* __restrict__ meta, int k,
+#define OUT_THREADS 1024   // k_output: 32 columns x 32 row slots
+
+__global__ __launch_bounds__(OUT_THREADS) void k_output(const BoxMeta* __restrict__ meta, int k,
                                                 double shift, const double* __restrict__ X,
                                                 const double* __restrict__ nu,
                                                 const double* __restrict__ rho,
                                                 double* __restrict__ evals,
                                                 double* __restrict__ evecs,
                                                 double* __restrict__ resid) {
-  __shared__ double sn[256];
-  __shared__ double sa[256];
-  __shared__ int si[256];
+  __shared__ double sn[OUT_THREADS];
+  __shared__ double sa[OUT_THREADS];
+  __shared__ int si[OUT_THREADS];
   __shared__ double scale[32];
   int box = blockIdx.x;
   const BoxMeta& bm = meta[box];
@@ -817,7 +819,7 @@ __global__ __launch_bounds__(256) void k_output(const BoxMeta* __restrict__ meta
   double s2 = 0.0, amax = -1.0;
   int imax = 0x7fffffff;
   if (col < nev) {
-    for (int row = slot; row < bm.n_dof; row += 8) {
+    for (int row = slot; row < bm.n_dof; row += OUT_THREADS / 32) {
       double v = X[(bm.dof_off * k) + (int64_t)row * k + col];
       s2 += v * v;
       double a = fabs(v);
@@ -831,7 +833,7 @@ __global__ __launch_bounds__(256) void k_output(const BoxMeta* __restrict__ meta
   if (tid < 32 && col < nev) {
     double n2 = 0.0, am = -1.0;
     int im = 0x7fffffff;
-    for (int s = 0; s < 8; ++s) {
+    for (int s = 0; s < OUT_THREADS / 32; ++s) {
       n2 += sn[s * 32 + tid];
       double a = sa[s * 32 + tid];
       int ii = si[s * 32 + tid];
@@ -846,7 +848,7 @@ __global__ __launch_bounds__(256) void k_output(const BoxMeta* __restrict__ meta
     resid[bm.eval_off + tid] = rho[(int64_t)box * k + tid];
   }
   __syncthreads();
-  for (int64_t t = tid; t < (int64_t)bm.n_dof * nev; t += 256) {
+  for (int64_t t = tid; t < (int64_t)bm.n_dof * nev; t += OUT_THREADS) {
     int row = (int)(t / nev), c = (int)(t % nev);
     evecs[bm.evec_off + t] = X[(bm.dof_off * k) + (int64_t)row * k + c] * scale[c];
   }
