@@ -973,7 +973,7 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
     // residual of the current Ritz block, convergence, active set
     {
       dim3 grid(n_chunk, nb);
-      k_residual<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, vcls, k, p->opts.shift, B[1][0],
+      k_residual<<<grid, 1024, 0, c.s>>>(c.v.meta, c.v.cls, vcls, k, p->opts.shift, B[1][0],
                                         geneo ? B[2][0] : B[3][0], c.w.nu,
                                         B[0][1], GRAM_ROWS, n_chunk, c.w.rpart, act);
       LAUNCHCHK(p);

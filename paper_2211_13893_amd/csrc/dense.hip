@@ -651,8 +651,9 @@ __global__ __launch_bounds__(UPD_THREADS, 3) void k_update(const BoxMeta* __rest
 // R = MX - nu (SX + s MX) on the rows whose class bit is set in rcls (B2 for
 // the A-harmonic GEVP, where SX = (A X~) on B2; B1 u B2 for GenEO), written
 // into R (zero elsewhere); partial column sums of |R|^2, |MX|^2, |TX|^2.
-// grid (n_chunk, n_box); thread = (row slot tid/32, column tid%32); k <= 32
-__global__ __launch_bounds__(256) void k_residual(const BoxMeta* __restrict__ meta,
+// grid (n_chunk, n_box), RES_THREADS threads; thread = (row slot tid/32, column tid%32); k <= 32
+#define RES_THREADS 1024   // k_residual: 32 columns x 32 row slots
+__global__ __launch_bounds__(RES_THREADS) void k_residual(const BoxMeta* __restrict__ meta,
                                                   const uint8_t* __restrict__ cls, int rcls, int k,
                                                   double shift, const double* __restrict__ AX,
                                                   const double* __restrict__ MX,
@@ -660,7 +661,7 @@ __global__ __launch_bounds__(256) void k_residual(const BoxMeta* __restrict__ me
                                                   double* __restrict__ R, int rows_per_chunk,
                                                   int n_chunk, double* __restrict__ part,
                                                   const int32_t* __restrict__ active) {
-  __shared__ double red[3][256];
+  __shared__ double red[3][RES_THREADS];
   int box = blockIdx.y, chunk = blockIdx.x;
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
@@ -670,7 +671,7 @@ __global__ __launch_bounds__(256) void k_residual(const BoxMeta* __restrict__ me
     double v = nu[(int64_t)box * k + col];
     int r_begin = chunk * rows_per_chunk;
     int r_end = min(bm.n_dof, r_begin + rows_per_chunk);
-    for (int row = r_begin + slot; row < r_end; row += 8) {
+    for (int row = r_begin + slot; row < r_end; row += RES_THREADS / 32) {
       int64_t o = (bm.dof_off * k) + (int64_t)row * k + col;
       double r = 0.0;
       if ((rcls >> cls[bm.dof_off + row]) & 1) {
@@ -690,7 +691,7 @@ __global__ __launch_bounds__(256) void k_residual(const BoxMeta* __restrict__ me
   __syncthreads();
   if (tid < 32) {
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int s = 0; s < 8; ++s) {
+    for (int s = 0; s < RES_THREADS / 32; ++s) {
       a += red[0][s * 32 + tid];
       b += red[1][s * 32 + tid];
       c += red[2][s * 32 + tid];
