@@ -34,7 +34,8 @@
  *
  * Status bits (device int32 per batch box): 1 = not converged within maxit
  * (best iterate returned), 4 = a pivot of a local factorisation was not
- * positive, 8 = non-finite value met.
+ * positive, 8 = non-finite value met, 16 = every computed eigenpair passed
+ * the threshold of msgfem_select_modes.
  */
 #ifndef MSGFEM_H
 #define MSGFEM_H
@@ -190,6 +191,25 @@ typedef struct {
   const int32_t *face;
   const double *g;
 } msgfem_load;
+
+/* Adaptive local spaces (Sec. 1 and Sec. 5, the threshold t on the reciprocals
+ * of the local eigenvalues that selects the eigenvectors of each local space):
+ * box j keeps its m_j leading eigenpairs, m_j = the number of its computed
+ * eigenvalues with lambda < 1/t (lambda ascending, so 1/lambda_{m_j+1} <= t;
+ * the zero eigenvalues of a floating box count while their rounding stays
+ * below 1/t).  The comparison is made in double with 1/t rounded once.
+ *   evals, evecs: device, as written by msgfem_local_eigs (not modified)
+ *   t:            the threshold, > 0 (MSGFEM_EARG otherwise)
+ *   evecs_out:    device, msgfem_local_eigs layout: the eigenvectors with the
+ *                 columns m_j .. n_ev_j - 1 of every box set to zero, which
+ *                 msgfem_coarse_assemble then drops from the coarse basis; it
+ *                 may be evecs itself
+ *   m:            device int32[nb], m_j per batch box
+ *   status:       device int32[nb], bit 16 ORed in where all n_ev_j eigenpairs
+ *                 pass (the threshold may need more than were computed). */
+int msgfem_select_modes(msgfem_plan *plan, const void *ops, const double *evals, double t,
+                        const double *evecs, double *evecs_out, int32_t *m, int32_t *status,
+                        void *stream);
 
 /* Size of the caller's coarse buffer and the number N_H of coarse functions
  * (the sum of n_ev over the batch).  The coarse problem needs a batch that

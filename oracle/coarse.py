@@ -135,3 +135,16 @@ def energy_error(prob, A, uh: np.ndarray, uG: np.ndarray) -> float:
     AF = A[F][:, F]
     e = (uh - uG)[F]
     return float(np.sqrt(e @ (AF @ e)) / np.sqrt(uh[F] @ (AF @ uh[F])))
+
+
+def select_modes(lam, t: float) -> int:
+    """m_j for the threshold t on reciprocal local eigenvalues (Sec. 1, Sec. 5).
+
+    The local space keeps the eigenvectors whose eigenvalue is below 1/t, so
+    that the smallest excluded eigenvalue lambda^{j,m_j+1} of the error bound
+    of Sec. 3.3 is at least 1/t.  The zero eigenvalues of a floating box (an
+    infinite reciprocal) count as long as their rounding stays below 1/t.
+    """
+    if not t > 0:
+        raise ValueError("threshold t must be positive")
+    return int(np.count_nonzero(np.asarray(lam, dtype=np.float64) < 1.0 / t))

@@ -75,6 +75,7 @@ __global__ void k_box_load(const BoxMeta*, MeshDev, const FaceLoad*, int, double
 __global__ void k_coarse_basis(const BoxMeta*, int, const double*, const double*, const double*, double*,
                                double*);
 __global__ void k_cholqr_coef(int, const double*, double*);
+__global__ void k_select_modes(const BoxMeta*, const double*, double, const double*, double*, int32_t*, int32_t*);
 __global__ void k_coarse_pairs(const BoxMeta*, const CoarsePair*, int, const double*, const double*,
                                const double*, int, double*, double*);
 __global__ void k_coarse_rhs(const BoxMeta*, int, const double*, const double*, const int32_t*,
@@ -1222,6 +1223,19 @@ static int coarse_plan(msgfem_plan* p) {
   p->c_y = off; off = align256(off + 2 * (int64_t)p->NTc * 32 * 8);
   p->coarse_bytes = off;
   p->coarse_ready = true;
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_select_modes(msgfem_plan* p, const void* ops, const double* evals, double t,
+                                   const double* evecs, double* evecs_out, int32_t* m, int32_t* status,
+                                   void* stream) {
+  if (!p || !ops || !evals || !evecs || !evecs_out || !m || !status) return fail(p, MSGFEM_EARG, "null argument");
+  if (!(t > 0.0)) return fail(p, MSGFEM_EARG, "the threshold must be positive (got %g)", t);
+  if (set_device(p)) return MSGFEM_EHIP;
+  const OpsView v = ops_view(p, ops);
+  const int nb = (int)p->meta.size();
+  k_select_modes<<<nb, 256, 0, (hipStream_t)stream>>>(v.meta, evals, 1.0 / t, evecs, evecs_out, m, status);
+  LAUNCHCHK(p);
   return MSGFEM_OK;
 }
 

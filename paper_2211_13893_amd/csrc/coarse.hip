@@ -33,6 +33,39 @@ struct CoarsePair {
   int32_t row_off, col_off;   // offsets in the coarse numbering
 };
 
+// Adaptive local spaces (Sec. 1 and Sec. 5: a threshold t on the reciprocals
+// of the local eigenvalues decides which eigenvectors enter a local space).
+// Box j keeps its m_j leading eigenpairs, m_j = #{k < n_ev_j : lambda_k <
+// 1/t} (lambda ascending, so 1/lambda_{m_j+1} <= t; the zero eigenvalues of
+// floating boxes, at rounding level either side of 0, count while that
+// rounding stays below 1/t), and the
+// other columns of its eigenvectors are written as zero, which the coarse
+// basis then drops.  Status bit 16 when all n_ev_j pass (the threshold may
+// need more eigenpairs than were computed).  One workgroup per box.
+__global__ __launch_bounds__(256) void k_select_modes(const BoxMeta* __restrict__ meta,
+                                                      const double* __restrict__ evals, double inv_t,
+                                                      const double* evecs, double* out,
+                                                      int32_t* __restrict__ m,
+                                                      int32_t* __restrict__ status) {
+  __shared__ int keep;
+  const BoxMeta& bm = meta[blockIdx.x];
+  const int nev = bm.n_ev;
+  if (threadIdx.x == 0) {
+    int c = 0;
+    while (c < nev && evals[bm.eval_off + c] < inv_t) ++c;
+    keep = c;
+    m[blockIdx.x] = c;
+    if (c == nev) status[blockIdx.x] |= 16;
+  }
+  __syncthreads();
+  const int kp = keep;
+  const int64_t n = (int64_t)bm.n_dof * nev;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int c = (int)(e % nev);
+    out[bm.evec_off + e] = c < kp ? evecs[bm.evec_off + e] : 0.0;
+  }
+}
+
 __global__ void k_box_load(const BoxMeta* __restrict__ meta, MeshDev mesh,
                            const FaceLoad* __restrict__ faces, int n_faces,
                            double* __restrict__ b) {

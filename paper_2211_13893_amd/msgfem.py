@@ -76,6 +76,7 @@ SIGNATURES = {
     "msgfem_assemble_local": (ctypes.c_int, [_P, _P, _P, _P]),
     "msgfem_local_eigs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "msgfem_local_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    "msgfem_select_modes": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
     "msgfem_coarse_sizes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_int32)]),
     "msgfem_coarse_assemble": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(msgfem_load), _P, _P, _P, _P,
@@ -265,6 +266,22 @@ class LocalStage:
         _check(self.lib.msgfem_coarse_sizes(self.plan, ctypes.byref(nb), ctypes.byref(nh)), self.plan,
                "msgfem_coarse_sizes")
         return nb.value, nh.value
+
+    def msgfem_select_modes(self, eig_out, t: float):
+        """Adaptive local spaces (msgfem_select_modes): per box the eigenpairs
+        with lambda < 1/t.  Returns (m, a copy of eig_out whose eigenvectors
+        have the other columns zeroed, ready for msgfem_coarse_assemble)."""
+        torch = self.torch
+        nb = len(self.batch)
+        m = torch.empty(nb, dtype=torch.int32, device=self.device)
+        sel = dict(eig_out)
+        sel["evecs"] = torch.empty_like(eig_out["evecs"])
+        rc = self.lib.msgfem_select_modes(self.plan, _ptr(self.ops), _ptr(eig_out["evals"]), float(t),
+                                          _ptr(eig_out["evecs"]), _ptr(sel["evecs"]), _ptr(m),
+                                          _ptr(self.status), _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_select_modes")
+        sel["status"] = self.status
+        return m, sel
 
     def msgfem_coarse_assemble(self, eig_out):
         torch = self.torch

@@ -86,3 +86,50 @@ def test_geneo_pcg_matches_direct_solve():
     # floating GenEO subdomains have six zero eigenvalues as well
     lam, *_ = geneo.geneo_local(p, 2, 8)
     assert np.sum(np.abs(lam) < 1e-8) == 6
+
+
+def test_select_modes_rule():
+    """The threshold rule of Sec. 1 and Sec. 5 on a hand-made spectrum: the kept
+    eigenvalues have reciprocals above t, the first dropped one at most t, and
+    rounding-level zeros (rigid modes of a floating box) are kept."""
+    lam = np.array([-3e-16, -1e-17, 0.0, 2e-16, 4e-16, 1e-15, 0.5, 2.0, 9.0, 40.0, 250.0])
+    assert coarse.select_modes(lam, 1.0) == 7          # 1/t = 1: 0.5 kept, 2.0 dropped
+    assert coarse.select_modes(lam, 0.1) == 9          # 1/t = 10
+    assert coarse.select_modes(lam, 1e-6) == 11        # every computed pair passes
+    assert coarse.select_modes(lam, 10.0) == 6         # rigid modes only
+    for t in (3.0, 0.3, 0.03, 3e-3):
+        m = coarse.select_modes(lam, t)
+        assert np.all(1.0 / lam[6:m] > t)
+        assert m == len(lam) or 1.0 / lam[m] <= t
+    with pytest.raises(ValueError):
+        coarse.select_modes(lam, 0.0)
+
+
+def test_threshold_nested_spaces_and_error_bound():
+    """Adaptive local spaces on a small beam: a smaller t keeps more
+    eigenvectors on every subdomain (nested spaces, so the Galerkin energy error
+    cannot grow), and e_a respects the bound of Sec. 3.3 with the constant
+    taken as the largest number of oversampled subdomains over any DoF."""
+    p = synth.laminated_beam(shape=(24, 3, 3), n_sub=4, overlap=1, ovs=1)
+    A = fem.assemble_global_sparse(p)
+    b = fem.traction_load(p)
+    uh = coarse.fine_solve(p, A, b)
+    kec = fem.KeCache(p)
+    locs = [coarse.local_basis(p, j, 40, kec, b) for j in range(p.nsd)]
+    cover = np.zeros(p.n_dofs, dtype=int)
+    for j in range(p.nsd):
+        cover[decomp.star_global_dofs(p, j)] += 1
+    C = cover.max()
+    prev_m, prev_e = None, np.inf
+    for t in (1e-1, 3e-2, 3e-3):
+        ms = [coarse.select_modes(l[4], t) for l in locs]
+        assert all(m < 40 for m in ms)
+        trunc = [(l[0][:, :m], l[1], l[2], l[3], l[4][:m]) for l, m in zip(locs, ms)]
+        e = coarse.energy_error(p, A, uh, coarse.msgfem(p, ms, A, b, locals_=trunc).uG)
+        lam_out = min(l[4][m] for l, m in zip(locs, ms))
+        assert lam_out >= 1.0 / t
+        assert e <= C * np.sqrt(1.0 / lam_out)
+        if prev_m is not None:
+            assert all(m >= q for m, q in zip(ms, prev_m)) and ms != prev_m
+            assert e <= prev_e * (1 + 1e-12)
+        prev_m, prev_e = ms, e
