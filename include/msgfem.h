@@ -211,6 +211,21 @@ int msgfem_select_modes(msgfem_plan *plan, const void *ops, const double *evals,
                         const double *evecs, double *evecs_out, int32_t *m, int32_t *status,
                         void *stream);
 
+/* Error metrics of Sec. 5.3: the relative L2 errors of displacement and
+ * strain, e_d = ||u_h - u||_2 / ||u_h||_2 and e_eps = ||eps(u_h) - eps(u)||_2 /
+ * ||eps(u_h)||_2, as integrals over the whole mesh (2x2x2 Gauss per element;
+ * eps = symmetric gradient, Frobenius norm).
+ *   u_ref: device double[n], the reference field u_h (global DoF 3*node+c,
+ *          node = i + (nx+1)(j + (ny+1) k), as msgfem_coarse_solve writes u^G)
+ *   u:     device double[n], the approximation (e.g. u^G)
+ *   n:     3 * the mesh's node count (MSGFEM_EARG otherwise)
+ *   out:   device double[6] = [int |u_h-u|^2, int |u_h|^2, int |eps(u_h-u)|^2,
+ *          int |eps(u_h)|^2, e_d, e_eps]; a zero reference gives 0 for a zero
+ *          difference and +inf otherwise.
+ * One workgroup in a fixed order: repeated calls give identical bits. */
+int msgfem_error_norms(msgfem_plan *plan, const double *u_ref, const double *u, int64_t n,
+                       double *out, void *stream);
+
 /* Size of the caller's coarse buffer and the number N_H of coarse functions
  * (the sum of n_ev over the batch).  The coarse problem needs a batch that
  * lists every subdomain of the decomposition exactly once (MSGFEM_EARG

@@ -148,3 +148,34 @@ def select_modes(lam, t: float) -> int:
     if not t > 0:
         raise ValueError("threshold t must be positive")
     return int(np.count_nonzero(np.asarray(lam, dtype=np.float64) < 1.0 / t))
+
+
+def error_norms(prob, uh: np.ndarray, u: np.ndarray) -> dict:
+    """e_d and e_eps of Sec. 5.3: relative L2 errors of displacement and strain.
+
+    Both are integrals over the mesh of the trilinear fields, by the 2x2x2
+    Gauss rule of the element stiffness; the strain is the symmetric gradient
+    with its Frobenius norm.  Returns the four integrals and the two ratios.
+    """
+    pts, wts = fem.gauss_rule(2)
+    sums = np.zeros(4)
+    for i, j, k in fem.box_elements((0, 0, 0), (prob.nx, prob.ny, prob.nz)):
+        ids = fem.element_nodes(prob, i, j, k)
+        X = prob.xyz[ids]
+        R = uh.reshape(-1, 3)[ids]
+        D = R - u.reshape(-1, 3)[ids]
+        for xi, w in zip(pts, wts):
+            N = np.prod(1.0 + fem.REF * xi, axis=1) / 8.0
+            dN = fem.shape_grad_ref(xi)
+            J = dN.T @ X
+            dNdx = np.linalg.solve(J, dN.T).T
+            wd = w * abs(np.linalg.det(J))
+            for q, F in ((0, D), (1, R)):
+                v = N @ F
+                G = F.T @ dNdx                      # G[c, e] = d u_c / d x_e
+                E = 0.5 * (G + G.T)
+                sums[q] += wd * (v @ v)
+                sums[2 + q] += wd * np.sum(E * E)
+    e_d = np.sqrt(sums[0] / sums[1])
+    e_eps = np.sqrt(sums[2] / sums[3])
+    return {"sums": sums, "e_d": float(e_d), "e_eps": float(e_eps)}

@@ -76,6 +76,7 @@ __global__ void k_coarse_basis(const BoxMeta*, int, const double*, const double*
                                double*);
 __global__ void k_cholqr_coef(int, const double*, double*);
 __global__ void k_select_modes(const BoxMeta*, const double*, double, const double*, double*, int32_t*, int32_t*);
+__global__ void k_error_norms(MeshDev, const double*, const double*, double*);
 __global__ void k_coarse_pairs(const BoxMeta*, const CoarsePair*, int, const double*, const double*,
                                const double*, int, double*, double*);
 __global__ void k_coarse_rhs(const BoxMeta*, int, const double*, const double*, const int32_t*,
@@ -1235,6 +1236,18 @@ extern "C" int msgfem_select_modes(msgfem_plan* p, const void* ops, const double
   const OpsView v = ops_view(p, ops);
   const int nb = (int)p->meta.size();
   k_select_modes<<<nb, 256, 0, (hipStream_t)stream>>>(v.meta, evals, 1.0 / t, evecs, evecs_out, m, status);
+  LAUNCHCHK(p);
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_error_norms(msgfem_plan* p, const double* u_ref, const double* u, int64_t n,
+                                  double* out, void* stream) {
+  if (!p || !u_ref || !u || !out) return fail(p, MSGFEM_EARG, "null argument");
+  const int64_t nn = (int64_t)(p->mesh.nx + 1) * (p->mesh.ny + 1) * (p->mesh.nz + 1);
+  if (n != 3 * nn) return fail(p, MSGFEM_EARG, "vector length %lld, the mesh has %lld DoFs",
+                               (long long)n, (long long)(3 * nn));
+  if (set_device(p)) return MSGFEM_EHIP;
+  k_error_norms<<<1, 1024, 0, (hipStream_t)stream>>>(mesh_dev(p), u_ref, u, out);
   LAUNCHCHK(p);
   return MSGFEM_OK;
 }

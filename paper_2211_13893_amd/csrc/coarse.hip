@@ -16,6 +16,7 @@
 //  k_dense_tiles / k_dense_tile_solve : the coarse matrix in dense tile form for
 //                    the tile Cholesky, and the single-RHS block solve.
 //  k_prolong       : u^G = sum_j R_j^T (mu_j psi_j + V_j c_j).
+//  k_error_norms   : the relative L2 errors e_d and e_eps of Sec. 5.3.
 #include "internal.hpp"
 
 namespace msg {
@@ -358,6 +359,108 @@ __global__ void k_prolong(const BoxMeta* __restrict__ meta, MeshDev mesh, int k,
   for (int a = 0; a < bm.n_ev; ++a) s += Vr[a] * cb[a];
   if (s != 0.0) atomicAdd(&uG[gd], s);
   if (up && p != 0.0) atomicAdd(&up[gd], p);
+}
+
+// Error metrics of Sec. 5.3: relative L2 errors of the displacement and of the
+// strain between a reference field u_h and an approximation u, as integrals
+// over the whole mesh by the 2x2x2 Gauss rule of the element stiffness (exact
+// for trilinear fields on parallelepiped elements).  The strain is the
+// symmetric gradient, measured by its Frobenius norm (each shear component
+// counted twice).  out = [int |u_h - u|^2, int |u_h|^2, int |eps(u_h - u)|^2,
+// int |eps(u_h)|^2, e_d, e_eps].  One workgroup with a fixed summation order,
+// so repeated calls give identical bits; the nodal values are re-read per
+// Gauss point from the caches rather than held in registers.
+#define ERR_THREADS 1024
+__global__ __launch_bounds__(ERR_THREADS) void k_error_norms(MeshDev mesh, const double* __restrict__ uref,
+                                                             const double* __restrict__ u,
+                                                             double* __restrict__ out) {
+  __shared__ double red[4][ERR_THREADS];
+  const int tid = threadIdx.x;
+  const int nx1 = mesh.nx + 1, ny1 = mesh.ny + 1;
+  const int64_t ne = (int64_t)mesh.nx * mesh.ny * mesh.nz;
+  const double gq = 0.57735026918962576451;   // 1/sqrt(3): 2-point Gauss abscissa, weight 1
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t e = tid; e < ne; e += ERR_THREADS) {
+    const int ei = (int)(e % mesh.nx);
+    const int ej = (int)((e / mesh.nx) % mesh.ny);
+    const int ek = (int)(e / ((int64_t)mesh.nx * mesh.ny));
+    int64_t nd[8];
+    for (int a = 0; a < 8; ++a)
+      nd[a] = (ei + (a & 1)) + (int64_t)nx1 * ((ej + ((a >> 1) & 1)) + (int64_t)ny1 * (ek + ((a >> 2) & 1)));
+    for (int g = 0; g < 8; ++g) {
+      const double xi[3] = {(g & 1) ? gq : -gq, (g & 2) ? gq : -gq, (g & 4) ? gq : -gq};
+      // J[d][c] = d x_c / d xi_d
+      double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      for (int a = 0; a < 8; ++a) {
+        const double r0 = (a & 1) ? 1.0 : -1.0, r1 = (a & 2) ? 1.0 : -1.0, r2 = (a & 4) ? 1.0 : -1.0;
+        const double f0 = 1.0 + r0 * xi[0], f1 = 1.0 + r1 * xi[1], f2 = 1.0 + r2 * xi[2];
+        const double dn[3] = {0.125 * r0 * f1 * f2, 0.125 * f0 * r1 * f2, 0.125 * f0 * f1 * r2};
+        for (int c = 0; c < 3; ++c) {
+          const double x = mesh.xyz[3 * nd[a] + c];
+          for (int d = 0; d < 3; ++d) J[d][c] += dn[d] * x;
+        }
+      }
+      const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+      const double id = 1.0 / det;
+      // Ji = J^{-1}: grad_x N = Ji grad_xi N
+      const double Ji[3][3] = {
+          {c00 * id, (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id, (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id},
+          {c01 * id, (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id, (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id},
+          {c02 * id, (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id, (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id}};
+      double vr[3] = {0, 0, 0}, vd[3] = {0, 0, 0};
+      double Gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Gd[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      for (int a = 0; a < 8; ++a) {
+        const double r0 = (a & 1) ? 1.0 : -1.0, r1 = (a & 2) ? 1.0 : -1.0, r2 = (a & 4) ? 1.0 : -1.0;
+        const double f0 = 1.0 + r0 * xi[0], f1 = 1.0 + r1 * xi[1], f2 = 1.0 + r2 * xi[2];
+        const double n = 0.125 * f0 * f1 * f2;
+        const double dn[3] = {0.125 * r0 * f1 * f2, 0.125 * f0 * r1 * f2, 0.125 * f0 * f1 * r2};
+        double dx[3];
+        for (int c = 0; c < 3; ++c) dx[c] = Ji[c][0] * dn[0] + Ji[c][1] * dn[1] + Ji[c][2] * dn[2];
+        for (int c = 0; c < 3; ++c) {
+          const double ra = uref[3 * nd[a] + c];
+          const double da = ra - u[3 * nd[a] + c];
+          vr[c] += n * ra;
+          vd[c] += n * da;
+          for (int q = 0; q < 3; ++q) {
+            Gr[c][q] += ra * dx[q];
+            Gd[c][q] += da * dx[q];
+          }
+        }
+      }
+      double sr = 0.0, sd = 0.0, er = 0.0, ed = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        sr += vr[c] * vr[c];
+        sd += vd[c] * vd[c];
+        for (int q = 0; q < 3; ++q) {
+          const double tr = 0.5 * (Gr[c][q] + Gr[q][c]), td = 0.5 * (Gd[c][q] + Gd[q][c]);
+          er += tr * tr;
+          ed += td * td;
+        }
+      }
+      const double w = fabs(det);
+      acc[0] += w * sd;
+      acc[1] += w * sr;
+      acc[2] += w * ed;
+      acc[3] += w * er;
+    }
+  }
+  for (int q = 0; q < 4; ++q) red[q][tid] = acc[q];
+  __syncthreads();
+  for (int h = ERR_THREADS / 2; h > 0; h >>= 1) {
+    if (tid < h)
+      for (int q = 0; q < 4; ++q) red[q][tid] += red[q][tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int q = 0; q < 4; ++q) out[q] = red[q][0];
+    for (int q = 0; q < 2; ++q) {
+      const double num = red[2 * q][0], den = red[2 * q + 1][0];
+      out[4 + q] = den > 0.0 ? sqrt(num / den) : (num == 0.0 ? 0.0 : INFINITY);
+    }
+  }
 }
 
 }  // namespace msg

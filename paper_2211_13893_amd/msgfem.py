@@ -77,6 +77,7 @@ SIGNATURES = {
     "msgfem_local_eigs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "msgfem_local_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
     "msgfem_select_modes": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
+    "msgfem_error_norms": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P]),
     "msgfem_coarse_sizes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_int32)]),
     "msgfem_coarse_assemble": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(msgfem_load), _P, _P, _P, _P,
@@ -282,6 +283,22 @@ class LocalStage:
         _check(rc, self.plan, "msgfem_select_modes")
         sel["status"] = self.status
         return m, sel
+
+    def msgfem_error_norms(self, u_ref, u):
+        """Error metrics of Sec. 5.3 (msgfem_error_norms): a device double[6] with
+        the four integrals and e_d, e_eps."""
+        torch = self.torch
+        for name, x in (("u_ref", u_ref), ("u", u)):
+            on_dev = x.device.type == "cuda" and (self.device.index is None or x.device.index == self.device.index)
+            if x.dtype != torch.float64 or not x.is_contiguous() or not on_dev:
+                raise MsgfemError(f"{name} must be a contiguous float64 tensor on {self.device}")
+        if u_ref.numel() != u.numel():
+            raise MsgfemError("u_ref and u differ in length")
+        out = torch.empty(6, dtype=torch.float64, device=self.device)
+        rc = self.lib.msgfem_error_norms(self.plan, _ptr(u_ref), _ptr(u), int(u.numel()), _ptr(out),
+                                         _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_error_norms")
+        return out
 
     def msgfem_coarse_assemble(self, eig_out):
         torch = self.torch

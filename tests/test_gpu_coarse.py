@@ -160,3 +160,37 @@ def test_select_modes_parity_beam(torch):
     assert m2.cpu().numpy().tolist() == [n_ev] * len(m)
     assert np.all(sel2["status"].cpu().numpy() & 16)
     assert torch.equal(sel2["evecs"], out["evecs"])
+
+
+@pytest.mark.parametrize("case", ["beam", "wrinkled_cube"])
+def test_error_norms_parity(torch, case):
+    """e_d and e_eps of Sec. 5.3 on the GPU against the oracle's integrals, on the
+    same fields: the fine solution u_h and the GPU's u^G (beam), and a random
+    field pair on the wrinkled cube (distorted elements)."""
+    say(f"[coarse] error norms, {case}")
+    if case == "beam":
+        prob = synth.laminated_beam(n_ev=10)
+        st, out, AH, bH, sol = _run(torch, prob)
+        A = fem.assemble_global_sparse(prob)
+        uh = coarse.fine_solve(prob, A, fem.traction_load(prob))
+        u = sol["uG"]
+    else:
+        prob = synth.small_box(n=8, core=4, overlap=1, ovs=1, wrinkle=0.4, clamp=True, n_ev=12)
+        from paper_2211_13893_amd import msgfem
+        st = msgfem.LocalStage(prob, tol=1e-6)
+        rng = np.random.default_rng(3)
+        uh = rng.normal(size=prob.n_dofs)
+        u = uh + 0.1 * rng.normal(size=prob.n_dofs)
+    ref = coarse.error_norms(prob, uh, u)
+    dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+    g1 = st.msgfem_error_norms(dev(uh), dev(u))
+    g2 = st.msgfem_error_norms(dev(uh), dev(u))
+    torch.cuda.synchronize()
+    g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
+    say(f"  gpu {g1.tolist()}\n  oracle {ref['sums'].tolist()} e_d {ref['e_d']:.6e} e_eps {ref['e_eps']:.6e}")
+    assert np.array_equal(g1, g2)
+    assert np.allclose(g1[:4], ref["sums"], rtol=1e-12, atol=0)
+    assert abs(g1[4] - ref["e_d"]) <= 1e-12 * ref["e_d"]
+    assert abs(g1[5] - ref["e_eps"]) <= 1e-12 * ref["e_eps"]
+    with pytest.raises(Exception, match="vector length"):
+        st.msgfem_error_norms(dev(uh[:-3]), dev(u[:-3]))

@@ -133,3 +133,51 @@ def test_threshold_nested_spaces_and_error_bound():
             assert all(m >= q for m, q in zip(ms, prev_m)) and ms != prev_m
             assert e <= prev_e * (1 + 1e-12)
         prev_m, prev_e = ms, e
+
+
+def _box_moments(L):
+    """Exact moments of the box [0,Lx]x[0,Ly]x[0,Lz]: volume, int x_i, int x_i x_j."""
+    V = float(np.prod(L))
+    M1 = V * np.asarray(L) / 2.0
+    M2 = V * np.outer(L, L) / 4.0
+    M2[np.diag_indices(3)] = V * np.asarray(L) ** 2 / 3.0
+    return V, M1, M2
+
+
+def test_error_norms_affine_fields_closed_form():
+    """Sec. 5.3 metrics on affine fields, which the trilinear elements reproduce
+    exactly: int |a + G x|^2 and int |sym G|_F^2 have closed forms on the box
+    (moments of the box; non-symmetric G so the symmetric part matters)."""
+    import dataclasses
+    p = synth.laminated_beam(shape=(6, 3, 3), n_sub=2, overlap=1, ovs=1)
+    L = p.xyz.max(axis=0) - p.xyz.min(axis=0)
+    assert np.allclose(p.xyz.min(axis=0), 0.0)
+    rng = np.random.default_rng(7)
+    a, G, H = rng.normal(size=3), rng.normal(size=(3, 3)), rng.normal(size=(3, 3))
+    uh = (a + p.xyz @ G.T).ravel()
+    u = (p.xyz @ H.T).ravel()
+    V, M1, M2 = _box_moments(L)
+
+    def l2sq(c, B):
+        return c @ c * V + 2 * c @ B @ M1 + np.trace(B.T @ B @ M2)
+
+    def epssq(B):
+        S = 0.5 * (B + B.T)
+        return np.sum(S * S) * V
+
+    r = coarse.error_norms(p, uh, u)
+    want = np.array([l2sq(a, G - H), l2sq(a, G), epssq(G - H), epssq(G)])
+    assert np.allclose(r["sums"], want, rtol=1e-12, atol=0)
+    assert np.isclose(r["e_d"], np.sqrt(want[0] / want[1]), rtol=1e-12)
+    assert np.isclose(r["e_eps"], np.sqrt(want[2] / want[3]), rtol=1e-12)
+    # a rigid motion has no strain; equal fields have no error
+    W = np.array([[0.0, -0.3, 0.2], [0.3, 0.0, -0.1], [-0.2, 0.1, 0.0]])
+    rr = coarse.error_norms(p, uh, uh + (a + p.xyz @ W.T).ravel())
+    assert rr["e_eps"] < 1e-13 and rr["e_d"] > 0.1
+    assert coarse.error_norms(p, uh, uh)["e_d"] == 0.0
+    # on a wrinkled mesh (nodes shifted in z uniformly through the thickness,
+    # which keeps every element's volume) the strain integral is unchanged
+    q = dataclasses.replace(p, xyz=p.xyz.copy())
+    q.xyz[:, 2] += 0.8 * np.exp(-((q.xyz[:, 0] - 3.0) ** 2 + (q.xyz[:, 1] - 1.5) ** 2) / 2.0)
+    rq = coarse.error_norms(q, (q.xyz @ G.T).ravel(), (q.xyz @ H.T).ravel())
+    assert np.allclose(rq["sums"][2:], [epssq(G - H), epssq(G)], rtol=1e-12, atol=0)
