@@ -226,6 +226,29 @@ int msgfem_select_modes(msgfem_plan *plan, const void *ops, const double *evals,
 int msgfem_error_norms(msgfem_plan *plan, const double *u_ref, const double *u, int64_t n,
                        double *out, void *stream);
 
+/* Offline/online reuse of local spaces (Sec. 1 and Sec. 6: when only some
+ * subdomains' data change, their local spaces are recomputed and the others
+ * kept).  msgfem_box_digest writes, per batch box, a 64-bit digest of what its
+ * local eigenproblem reads once assembled: the stencil of a_{Omega*}, the DoF
+ * classes, the partition of unity mu_j, the box geometry and n_ev, salted with
+ * the eigensolver options (shift, tol, maxit, block width, geneo, precision,
+ * overlap; not the seed).  Equal digests mean the same eigenproblem, bit for
+ * bit, so a stored local space can be kept; the digest is the same on every run.
+ *   ops:    the plan's assembled operators (after msgfem_assemble_local)
+ *   digest: device uint64[nb] */
+int msgfem_box_digest(msgfem_plan *plan, const void *ops, uint64_t *digest, void *stream);
+
+/* Copies the eigen output of every box of plan `src` (e.g. a plan over only the
+ * changed subdomains) into the slots of the same subdomains in the eigen output
+ * of plan `dst` (e.g. a stored full result), leaving the other boxes as they
+ * are.  Both outputs are in the msgfem_local_eigs layout of their plans.
+ * MSGFEM_EARG if a source subdomain is not in dst's batch, or its box, n_ev or
+ * geneo flag differs, or the plans are on different devices.  All pointers are
+ * device; the copies are asynchronous on `stream`. */
+int msgfem_merge_eigs(msgfem_plan *dst, msgfem_plan *src, const double *src_evals, const double *src_evecs,
+                      const double *src_resid, const int32_t *src_iters, double *evals, double *evecs,
+                      double *resid, int32_t *iters, void *stream);
+
 /* Size of the caller's coarse buffer and the number N_H of coarse functions
  * (the sum of n_ev over the batch).  The coarse problem needs a batch that
  * lists every subdomain of the decomposition exactly once (MSGFEM_EARG

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmsgfem.so")
-SOURCES = ["api.hip", "assemble.hip", "band.hip", "solve.hip", "spmm.hip", "dense.hip", "coarse.hip", "pcg.hip", "warm.hip"]
+SOURCES = ["api.hip", "assemble.hip", "band.hip", "solve.hip", "spmm.hip", "dense.hip", "coarse.hip", "pcg.hip", "warm.hip", "reuse.hip"]
 ARCH = os.environ.get("MSGFEM_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -77,6 +77,9 @@ __global__ void k_coarse_basis(const BoxMeta*, int, const double*, const double*
 __global__ void k_cholqr_coef(int, const double*, double*);
 __global__ void k_select_modes(const BoxMeta*, const double*, double, const double*, double*, int32_t*, int32_t*);
 __global__ void k_error_norms(MeshDev, const double*, const double*, double*);
+__global__ void k_box_digest(const BoxMeta*, const double*, const double*, const uint8_t*, uint64_t, uint64_t*);
+__global__ void k_copy_eigs(int, int64_t, const double*, const double*, const double*, const int32_t*, double*,
+                            double*, double*, int32_t*);
 __global__ void k_coarse_pairs(const BoxMeta*, const CoarsePair*, int, const double*, const double*,
                                const double*, int, double*, double*);
 __global__ void k_coarse_rhs(const BoxMeta*, int, const double*, const double*, const int32_t*,
@@ -1249,6 +1252,68 @@ extern "C" int msgfem_error_norms(msgfem_plan* p, const double* u_ref, const dou
   if (set_device(p)) return MSGFEM_EHIP;
   k_error_norms<<<1, 1024, 0, (hipStream_t)stream>>>(mesh_dev(p), u_ref, u, out);
   LAUNCHCHK(p);
+  return MSGFEM_OK;
+}
+
+static uint64_t host_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+extern "C" int msgfem_box_digest(msgfem_plan* p, const void* ops, uint64_t* digest, void* stream) {
+  if (!p || !ops || !digest) return fail(p, MSGFEM_EARG, "null argument");
+  if (set_device(p)) return MSGFEM_EHIP;
+  const OpsView v = ops_view(p, ops);
+  // the eigensolver options that change the computed local space (not the seed)
+  uint64_t salt = 0x5eed;
+  uint64_t words[7];
+  memcpy(&words[0], &p->opts.shift, 8);
+  memcpy(&words[1], &p->opts.tol, 8);
+  words[2] = (uint64_t)(uint32_t)p->opts.maxit;
+  words[3] = (uint64_t)(uint32_t)p->k;
+  words[4] = (uint64_t)(uint32_t)p->opts.geneo;
+  words[5] = (uint64_t)(uint32_t)p->opts.precision;
+  words[6] = (uint64_t)(uint32_t)p->overlap;
+  for (int q = 0; q < 7; ++q) salt = host_mix64(salt ^ words[q]);
+  const int nb = (int)p->meta.size();
+  k_box_digest<<<nb, 256, 0, (hipStream_t)stream>>>(v.meta, v.stencil, v.mu1, v.cls, salt, digest);
+  LAUNCHCHK(p);
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_merge_eigs(msgfem_plan* dst, msgfem_plan* src, const double* src_evals,
+                                 const double* src_evecs, const double* src_resid, const int32_t* src_iters,
+                                 double* evals, double* evecs, double* resid, int32_t* iters, void* stream) {
+  if (!dst || !src || !src_evals || !src_evecs || !src_resid || !src_iters || !evals || !evecs || !resid ||
+      !iters)
+    return fail(dst, MSGFEM_EARG, "null argument");
+  if (src->device != dst->device) return fail(dst, MSGFEM_EARG, "the two plans are on different devices");
+  if (src->opts.geneo != dst->opts.geneo)
+    return fail(dst, MSGFEM_EARG, "the two plans solve different eigenproblems (geneo flag)");
+  std::vector<int> where(dst->nsd, -1);
+  for (size_t d = 0; d < dst->meta.size(); ++d) where[dst->meta[d].sd] = (int)d;
+  for (size_t b = 0; b < src->meta.size(); ++b) {
+    const BoxMeta& s = src->meta[b];
+    if (s.sd < 0 || s.sd >= dst->nsd || where[s.sd] < 0)
+      return fail(dst, MSGFEM_EARG, "subdomain %d of the source batch is not in this plan's batch", s.sd);
+    const BoxMeta& t = dst->meta[where[s.sd]];
+    if (s.mx != t.mx || s.my != t.my || s.mz != t.mz || s.g0[0] != t.g0[0] || s.g0[1] != t.g0[1] ||
+        s.g0[2] != t.g0[2] || s.n_dof != t.n_dof || s.n_ev != t.n_ev)
+      return fail(dst, MSGFEM_EARG, "subdomain %d has another box or n_ev in the two plans", s.sd);
+  }
+  if (set_device(dst)) return MSGFEM_EHIP;
+  for (size_t b = 0; b < src->meta.size(); ++b) {
+    const BoxMeta& s = src->meta[b];
+    const int d = where[s.sd];
+    const BoxMeta& t = dst->meta[d];
+    const int64_t nv = (int64_t)s.n_dof * s.n_ev;
+    const int64_t grid = (std::max<int64_t>(nv, s.n_ev) + 255) / 256;
+    k_copy_eigs<<<(unsigned)grid, 256, 0, (hipStream_t)stream>>>(
+        s.n_ev, nv, src_evals + s.eval_off, src_evecs + s.evec_off, src_resid + s.eval_off, src_iters + b,
+        evals + t.eval_off, evecs + t.evec_off, resid + t.eval_off, iters + d);
+    LAUNCHCHK(dst);
+  }
   return MSGFEM_OK;
 }
 

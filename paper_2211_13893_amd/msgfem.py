@@ -78,6 +78,8 @@ SIGNATURES = {
     "msgfem_local_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
     "msgfem_select_modes": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
     "msgfem_error_norms": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P]),
+    "msgfem_box_digest": (ctypes.c_int, [_P, _P, _P, _P]),
+    "msgfem_merge_eigs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "msgfem_coarse_sizes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_int32)]),
     "msgfem_coarse_assemble": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(msgfem_load), _P, _P, _P, _P,
@@ -298,6 +300,29 @@ class LocalStage:
         rc = self.lib.msgfem_error_norms(self.plan, _ptr(u_ref), _ptr(u), int(u.numel()), _ptr(out),
                                          _stream_handle(torch, self.device))
         _check(rc, self.plan, "msgfem_error_norms")
+        return out
+
+    def msgfem_box_digest(self):
+        """Per-box 64-bit digests of the assembled local eigenproblems
+        (msgfem_box_digest), as a device int64 tensor (same bits as uint64)."""
+        torch = self.torch
+        if self.ops is None:
+            raise MsgfemError("assemble first")
+        d = torch.empty(len(self.batch), dtype=torch.int64, device=self.device)
+        rc = self.lib.msgfem_box_digest(self.plan, _ptr(self.ops), _ptr(d), _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_box_digest")
+        return d
+
+    def msgfem_merge_eigs(self, stored, src_stage, src_out):
+        """Returns a copy of `stored` (an eigen output of this stage's layout) with
+        the boxes of `src_stage` replaced by `src_out` (msgfem_merge_eigs)."""
+        torch = self.torch
+        out = {k: v.clone() for k, v in stored.items()}
+        rc = self.lib.msgfem_merge_eigs(self.plan, src_stage.plan, _ptr(src_out["evals"]), _ptr(src_out["evecs"]),
+                                        _ptr(src_out["resid"]), _ptr(src_out["iters"]), _ptr(out["evals"]),
+                                        _ptr(out["evecs"]), _ptr(out["resid"]), _ptr(out["iters"]),
+                                        _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_merge_eigs")
         return out
 
     def msgfem_coarse_assemble(self, eig_out):

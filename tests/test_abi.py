@@ -96,3 +96,31 @@ def test_plan_rejects_bad_arguments():
     lib, plan, rc, _ = _plan(prob, block=13)
     assert rc == msgfem.MSGFEM_EARG
     lib.msgfem_plan_destroy(plan)
+
+
+def test_merge_eigs_rejects_mismatched_plans():
+    """Host checks of msgfem_merge_eigs (no device work is reached): a source
+    subdomain missing from the destination batch, another n_ev, another box."""
+    prob = synth.laminated_beam()
+    one = ctypes.c_void_p(256)
+    ptrs = [one] * 8
+
+    def merge(dst, src):
+        return dst[0].msgfem_merge_eigs(dst[1], src[1], *ptrs, None)
+
+    full = _plan(prob)
+    assert full[2] == 0
+    part = _plan(prob, batch=[0, 2])
+    sub = _plan(prob, batch=[1])
+    sub_nev = _plan(prob, batch=[1], n_ev=[12])
+    other = _plan(synth.laminated_beam(overlap=1), batch=[1])
+    for p in (part, sub, sub_nev, other):
+        assert p[2] == 0
+    assert merge(part, sub) == msgfem.MSGFEM_EARG
+    assert b"not in this plan's batch" in full[0].msgfem_plan_error(part[1])
+    assert merge(full, sub_nev) == msgfem.MSGFEM_EARG
+    assert merge(full, other) == msgfem.MSGFEM_EARG
+    assert b"another box or n_ev" in full[0].msgfem_plan_error(full[1])
+    assert merge(full, (None, None)) == msgfem.MSGFEM_EARG
+    for p in (full, part, sub, sub_nev, other):
+        p[0].msgfem_plan_destroy(p[1])
