@@ -77,7 +77,8 @@ __global__ void k_coarse_basis(const BoxMeta*, int, const double*, const double*
 __global__ void k_cholqr_coef(int, const double*, double*);
 __global__ void k_select_modes(const BoxMeta*, const double*, double, const double*, double*, int32_t*, int32_t*);
 __global__ void k_error_norms(MeshDev, const double*, const double*, double*);
-__global__ void k_box_digest(const BoxMeta*, const double*, const double*, const uint8_t*, uint64_t, uint64_t*);
+__global__ void k_box_digest(const BoxMeta*, const double*, const double*, const uint8_t*, unsigned long long*);
+__global__ void k_box_digest_finish(const BoxMeta*, int, uint64_t, unsigned long long*);
 __global__ void k_copy_eigs(int, int64_t, const double*, const double*, const double*, const int32_t*, double*,
                             double*, double*, int32_t*);
 __global__ void k_coarse_pairs(const BoxMeta*, const CoarsePair*, int, const double*, const double*,
@@ -1277,7 +1278,11 @@ extern "C" int msgfem_box_digest(msgfem_plan* p, const void* ops, uint64_t* dige
   words[6] = (uint64_t)(uint32_t)p->overlap;
   for (int q = 0; q < 7; ++q) salt = host_mix64(salt ^ words[q]);
   const int nb = (int)p->meta.size();
-  k_box_digest<<<nb, 256, 0, (hipStream_t)stream>>>(v.meta, v.stencil, v.mu1, v.cls, salt, digest);
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* acc = (unsigned long long*)digest;
+  k_fill_i32<<<(2 * nb + 255) / 256, 256, 0, s>>>((int32_t*)digest, 2 * nb, 0);
+  k_box_digest<<<dim3(32, nb), 256, 0, s>>>(v.meta, v.stencil, v.mu1, v.cls, acc);
+  k_box_digest_finish<<<(nb + 63) / 64, 64, 0, s>>>(v.meta, nb, salt, acc);
   LAUNCHCHK(p);
   return MSGFEM_OK;
 }

@@ -23,6 +23,7 @@ import hashlib
 import os
 import re
 import sys
+import time
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -156,12 +157,77 @@ def run_workload(boxes: int, steps: int):
         print(f"step {i} done, iterations {out['iters'].cpu().numpy().mean():.2f}", flush=True)
 
 
+def run_reuse(boxes: int, changed: int):
+    """Offline/online reuse on the uniform batch: solve all boxes, change the
+    ply material in the middle 2^3 elements of every (boxes // changed)-th
+    core (elements that no other oversampled box holds), then time a full
+    recompute against the online path (assemble, digest, solve only the boxes
+    whose digest changed, merge)."""
+    import dataclasses
+    import json
+    import numpy as np
+    import torch
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_2211_13893_amd import msgfem, synth
+    p0 = synth.uniform_batch(n_boxes=boxes)
+    picked = [int(p0.batch[i]) for i in range(0, boxes, max(1, boxes // changed))][:changed]
+    em = p0.elem_mat.copy().reshape(p0.nz, p0.ny, p0.nx)
+    for sd in picked:
+        x, y, z = (int(c) + 3 for c in p0.cores[sd, :3])
+        em[z:z + 2, y:y + 2, x:x + 2] = (em[z:z + 2, y:y + 2, x:x + 2] + 1) % p0.materials.shape[0]
+    p1 = dataclasses.replace(p0, elem_mat=em.ravel())
+    st0 = msgfem.LocalStage(p0, tol=1e-6)
+    st0.msgfem_assemble_local()
+    d0 = st0.msgfem_box_digest()
+    out0 = st0.msgfem_local_eigs()
+    st1 = msgfem.LocalStage(p1, tol=1e-6)
+    torch.cuda.synchronize()
+    print("offline solve done", flush=True)
+    ms = {}
+
+    def timed(name, fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        ms[name] = (time.perf_counter() - t) * 1e3
+        return r
+
+    timed("assemble_all", st1.msgfem_assemble_local)
+    timed("eigs_all", st1.msgfem_local_eigs)
+    print("full recompute done", flush=True)
+    timed("assemble_all", st1.msgfem_assemble_local)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    d1 = timed("digest", st1.msgfem_box_digest)
+    e1.record()
+    found = [int(st1.batch[b]) for b in np.flatnonzero((d0 != d1).cpu().numpy())]
+    stc = timed("plan_changed", lambda: msgfem.LocalStage(p1, batch=found, tol=1e-6))
+    timed("assemble_changed", stc.msgfem_assemble_local)
+    outc = timed("eigs_changed", stc.msgfem_local_eigs)
+    timed("merge", lambda: st1.msgfem_merge_eigs(out0, stc, outc))
+    torch.cuda.synchronize()
+    digest_ms = e0.elapsed_time(e1)
+    nbytes = sum(243 * 8 * b.n_nodes + 9 * b.n_dof for b in st1.boxes)
+    full = ms["assemble_all"] + ms["eigs_all"]
+    online = sum(ms[k] for k in ("assemble_all", "digest", "plan_changed", "assemble_changed", "eigs_changed",
+                                 "merge"))
+    print(json.dumps({"reuse": {"boxes": boxes, "changed": picked, "found": found, "ms": ms,
+                                "full_ms": full, "online_ms": online, "digest_event_ms": digest_ms,
+                                "digest_bytes": nbytes, "digest_GBps": nbytes / digest_ms / 1e6}}), flush=True)
+    if found != picked:
+        raise SystemExit("digest found other boxes than the changed ones")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     r = sub.add_parser("run")
     r.add_argument("--boxes", type=int, default=64)
     r.add_argument("--steps", type=int, default=1)
+    u = sub.add_parser("reuse")
+    u.add_argument("--boxes", type=int, default=64)
+    u.add_argument("--changed", type=int, default=8)
     s = sub.add_parser("summarize")
     s.add_argument("--trace", required=True)
     s.add_argument("--fetch")
@@ -172,6 +238,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "run":
         run_workload(a.boxes, a.steps)
+    elif a.cmd == "reuse":
+        run_reuse(a.boxes, a.changed)
     else:
         summarize(a.trace, a.fetch, a.write, a.out, a.title, a.commands)
 
