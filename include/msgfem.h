@@ -238,14 +238,17 @@ int msgfem_error_norms(msgfem_plan *plan, const double *u_ref, const double *u, 
  *   digest: device uint64[nb] */
 int msgfem_box_digest(msgfem_plan *plan, const void *ops, uint64_t *digest, void *stream);
 
-/* Copies the eigen output of every box of plan `src` (e.g. a plan over only the
+/* Copies the eigen output of boxes of plan `src` (e.g. a plan over only the
  * changed subdomains) into the slots of the same subdomains in the eigen output
  * of plan `dst` (e.g. a stored full result), leaving the other boxes as they
  * are.  Both outputs are in the msgfem_local_eigs layout of their plans.
+ * boxes: host int32[n_boxes], positions in src's batch of the boxes to copy;
+ * NULL copies every box of src (MSGFEM_EARG for a position outside it).
  * MSGFEM_EARG if a source subdomain is not in dst's batch, or its box, n_ev or
  * geneo flag differs, or the plans are on different devices.  All pointers are
  * device; the copies are asynchronous on `stream`. */
-int msgfem_merge_eigs(msgfem_plan *dst, msgfem_plan *src, const double *src_evals, const double *src_evecs,
+int msgfem_merge_eigs(msgfem_plan *dst, msgfem_plan *src, const int32_t *boxes, int32_t n_boxes,
+                      const double *src_evals, const double *src_evecs,
                       const double *src_resid, const int32_t *src_iters, double *evals, double *evecs,
                       double *resid, int32_t *iters, void *stream);
 

@@ -1287,7 +1287,8 @@ extern "C" int msgfem_box_digest(msgfem_plan* p, const void* ops, uint64_t* dige
   return MSGFEM_OK;
 }
 
-extern "C" int msgfem_merge_eigs(msgfem_plan* dst, msgfem_plan* src, const double* src_evals,
+extern "C" int msgfem_merge_eigs(msgfem_plan* dst, msgfem_plan* src, const int32_t* boxes, int32_t n_boxes,
+                                 const double* src_evals,
                                  const double* src_evecs, const double* src_resid, const int32_t* src_iters,
                                  double* evals, double* evecs, double* resid, int32_t* iters, void* stream) {
   if (!dst || !src || !src_evals || !src_evecs || !src_resid || !src_iters || !evals || !evecs || !resid ||
@@ -1296,9 +1297,21 @@ extern "C" int msgfem_merge_eigs(msgfem_plan* dst, msgfem_plan* src, const doubl
   if (src->device != dst->device) return fail(dst, MSGFEM_EARG, "the two plans are on different devices");
   if (src->opts.geneo != dst->opts.geneo)
     return fail(dst, MSGFEM_EARG, "the two plans solve different eigenproblems (geneo flag)");
+  const int nsrc = (int)src->meta.size();
+  std::vector<int> pick;
+  if (boxes) {
+    if (n_boxes < 0) return fail(dst, MSGFEM_EARG, "negative box count");
+    for (int i = 0; i < n_boxes; ++i) {
+      if (boxes[i] < 0 || boxes[i] >= nsrc)
+        return fail(dst, MSGFEM_EARG, "source box %d outside the source batch of %d", boxes[i], nsrc);
+      pick.push_back(boxes[i]);
+    }
+  } else {
+    for (int i = 0; i < nsrc; ++i) pick.push_back(i);
+  }
   std::vector<int> where(dst->nsd, -1);
   for (size_t d = 0; d < dst->meta.size(); ++d) where[dst->meta[d].sd] = (int)d;
-  for (size_t b = 0; b < src->meta.size(); ++b) {
+  for (int b : pick) {
     const BoxMeta& s = src->meta[b];
     if (s.sd < 0 || s.sd >= dst->nsd || where[s.sd] < 0)
       return fail(dst, MSGFEM_EARG, "subdomain %d of the source batch is not in this plan's batch", s.sd);
@@ -1308,7 +1321,7 @@ extern "C" int msgfem_merge_eigs(msgfem_plan* dst, msgfem_plan* src, const doubl
       return fail(dst, MSGFEM_EARG, "subdomain %d has another box or n_ev in the two plans", s.sd);
   }
   if (set_device(dst)) return MSGFEM_EHIP;
-  for (size_t b = 0; b < src->meta.size(); ++b) {
+  for (int b : pick) {
     const BoxMeta& s = src->meta[b];
     const int d = where[s.sd];
     const BoxMeta& t = dst->meta[d];

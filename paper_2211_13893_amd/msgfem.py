@@ -79,7 +79,7 @@ SIGNATURES = {
     "msgfem_select_modes": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
     "msgfem_error_norms": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P]),
     "msgfem_box_digest": (ctypes.c_int, [_P, _P, _P, _P]),
-    "msgfem_merge_eigs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "msgfem_merge_eigs": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "msgfem_coarse_sizes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_int32)]),
     "msgfem_coarse_assemble": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(msgfem_load), _P, _P, _P, _P,
@@ -313,12 +313,26 @@ class LocalStage:
         _check(rc, self.plan, "msgfem_box_digest")
         return d
 
-    def msgfem_merge_eigs(self, stored, src_stage, src_out):
-        """Returns a copy of `stored` (an eigen output of this stage's layout) with
-        the boxes of `src_stage` replaced by `src_out` (msgfem_merge_eigs)."""
+    def new_eig_output(self):
+        """A zeroed eigen output in this stage's msgfem_local_eigs layout."""
         torch = self.torch
-        out = {k: v.clone() for k, v in stored.items()}
-        rc = self.lib.msgfem_merge_eigs(self.plan, src_stage.plan, _ptr(src_out["evals"]), _ptr(src_out["evecs"]),
+        s = self.sizes
+        return dict(evals=torch.zeros(s.n_eval, dtype=torch.float64, device=self.device),
+                    evecs=torch.zeros(s.n_evec, dtype=torch.float64, device=self.device),
+                    resid=torch.zeros(s.n_eval, dtype=torch.float64, device=self.device),
+                    iters=torch.zeros(s.n_box, dtype=torch.int32, device=self.device),
+                    status=self.status)
+
+    def msgfem_merge_eigs(self, stored, src_stage, src_out, boxes=None):
+        """Returns a copy of `stored` (an eigen output of this stage's layout) with
+        the boxes of `src_stage` (all, or the batch positions `boxes`) replaced by
+        `src_out` (msgfem_merge_eigs)."""
+        torch = self.torch
+        out = {k: (v if k == "status" else v.clone()) for k, v in stored.items()}
+        sel = None if boxes is None else np.ascontiguousarray(boxes, dtype=np.int32)
+        rc = self.lib.msgfem_merge_eigs(self.plan, src_stage.plan, None if sel is None else sel.ctypes.data,
+                                        0 if sel is None else int(sel.size),
+                                        _ptr(src_out["evals"]), _ptr(src_out["evecs"]),
                                         _ptr(src_out["resid"]), _ptr(src_out["iters"]), _ptr(out["evals"]),
                                         _ptr(out["evecs"]), _ptr(out["resid"]), _ptr(out["iters"]),
                                         _stream_handle(torch, self.device))

@@ -106,7 +106,7 @@ def test_merge_eigs_rejects_mismatched_plans():
     ptrs = [one] * 8
 
     def merge(dst, src):
-        return dst[0].msgfem_merge_eigs(dst[1], src[1], *ptrs, None)
+        return dst[0].msgfem_merge_eigs(dst[1], src[1], None, 0, *ptrs, None)
 
     full = _plan(prob)
     assert full[2] == 0
@@ -122,5 +122,8 @@ def test_merge_eigs_rejects_mismatched_plans():
     assert merge(full, other) == msgfem.MSGFEM_EARG
     assert b"another box or n_ev" in full[0].msgfem_plan_error(full[1])
     assert merge(full, (None, None)) == msgfem.MSGFEM_EARG
+    bad = (ctypes.c_int32 * 1)(5)
+    assert full[0].msgfem_merge_eigs(full[1], sub[1], bad, 1, *ptrs, None) == msgfem.MSGFEM_EARG
+    assert b"outside the source batch" in full[0].msgfem_plan_error(full[1])
     for p in (full, part, sub, sub_nev, other):
         p[0].msgfem_plan_destroy(p[1])
