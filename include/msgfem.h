@@ -171,6 +171,17 @@ int msgfem_local_eigs(msgfem_plan *plan, const void *ops, void *work, const doub
                       double *evals, double *evecs, double *resid, int32_t *iters,
                       int32_t *status, void *stream);
 
+/* msgfem_local_eigs for the boxes a caller selects: mask is a device int32[nb],
+ * nonzero = solve that box.  The other boxes are not iterated and their slots
+ * of evals, evecs, resid and iters (and their status) are left as they are, so
+ * a stored eigen output can be refreshed in place for the boxes whose data
+ * changed (offline/online reuse, Sec. 1 and Sec. 6; see msgfem_box_digest).
+ * Arguments and errors otherwise as msgfem_local_eigs (MSGFEM_EARG for a null
+ * mask). */
+int msgfem_local_eigs_subset(msgfem_plan *plan, const void *ops, void *work, const double *x0,
+                             const int32_t *mask, double *evals, double *evecs, double *resid,
+                             int32_t *iters, int32_t *status, void *stream);
+
 /* Apply one local operator to a block of k columns (box layout [n_dof][k] at
  * vec_off; k must equal the plan's block width, else MSGFEM_EARG):
  *   op 0: y = A x on B1 u B2 (B3 rows/columns removed, 0 on B3)

@@ -61,7 +61,7 @@ __global__ void k_lock(const BoxMeta*, int, const double*, double, double*, doub
                        const int32_t*);
 __global__ void k_copy_start(const BoxMeta*, const uint8_t*, int, int, const double*, double*);
 __global__ void k_output(const BoxMeta*, int, double, const double*, const double*, const double*,
-                         double*, double*, double*);
+                         double*, double*, double*, const int32_t*);
 struct FaceLoad {
   int32_t axis, side;
   double g[3];
@@ -896,9 +896,9 @@ static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double*
   return 0;
 }
 
-extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, const double* x0,
-                                 double* evals, double* evecs, double* resid, int32_t* iters,
-                                 int32_t* status, void* stream) {
+static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const double* x0, const int32_t* mask,
+                           double* evals, double* evecs, double* resid, int32_t* iters, int32_t* status,
+                           void* stream) {
   if (!p || !ops || !work || !evals || !evecs || !resid || !iters || !status)
     return fail(p, MSGFEM_EARG, "null argument");
   if (set_device(p)) return MSGFEM_EHIP;
@@ -930,6 +930,18 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
   k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(act, nb, 1);
   k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(c.w.iters, nb, 0);
   LAUNCHCHK(p);
+  // a caller mask solves only the boxes it selects; the others are inactive
+  // from the start and their outputs are left as they are
+  std::vector<int32_t> mask_h;
+  if (mask) {
+    mask_h.resize(nb);
+    HIPCHK(p, hipMemcpyAsync(mask_h.data(), mask, nb * 4, hipMemcpyDeviceToHost, c.s));
+    HIPCHK(p, hipStreamSynchronize(c.s));
+    for (int b = 0; b < nb; ++b) mask_h[b] = mask_h[b] != 0;
+    HIPCHK(p, hipMemcpyAsync(act, mask_h.data(), nb * 4, hipMemcpyHostToDevice, c.s));
+    c.act_h = mask_h;
+  }
+  const int32_t* act0 = mask ? act : nullptr;
   // start block
   {
     dim3 grid((unsigned)(((int64_t)p->max_dof * k + 255) / 256), nb);
@@ -958,8 +970,8 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
     for (int kind = 0; kind < 4; ++kind) std::swap(B[kind][0], B[kind][3]);
     return 0;
   };
-  if (images(B[0][0], B[1][0], B[2][0], B[3][0], nullptr)) return MSGFEM_EHIP;
-  if (rr_x(nullptr)) return MSGFEM_EHIP;
+  if (images(B[0][0], B[1][0], B[2][0], B[3][0], act0)) return MSGFEM_EHIP;
+  if (rr_x(act0)) return MSGFEM_EHIP;
   int n_chunk = p->n_gchunk;
   // Mixed path: the first phase runs the SpMM and the block solves with FP32
   // operator copies (FP64 arithmetic and FP64 dense steps); once every active
@@ -1072,9 +1084,20 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
   // boxes still active did not converge
   {
     k_output<<<nb, 1024, 0, c.s>>>(c.v.meta, k, p->opts.shift, B[0][0], c.w.nu, c.w.rho, evals, evecs,
-                                  resid);
+                                  resid, mask);
     LAUNCHCHK(p);
-    HIPCHK(p, hipMemcpyAsync(iters, c.w.iters, nb * 4, hipMemcpyDeviceToDevice, c.s));
+    if (mask) {
+      std::vector<int32_t> it_new(nb), it_old(nb);
+      HIPCHK(p, hipMemcpyAsync(it_new.data(), c.w.iters, nb * 4, hipMemcpyDeviceToHost, c.s));
+      HIPCHK(p, hipMemcpyAsync(it_old.data(), iters, nb * 4, hipMemcpyDeviceToHost, c.s));
+      HIPCHK(p, hipStreamSynchronize(c.s));
+      for (int b = 0; b < nb; ++b)
+        if (mask_h[b]) it_old[b] = it_new[b];
+      HIPCHK(p, hipMemcpyAsync(iters, it_old.data(), nb * 4, hipMemcpyHostToDevice, c.s));
+      HIPCHK(p, hipStreamSynchronize(c.s));
+    } else {
+      HIPCHK(p, hipMemcpyAsync(iters, c.w.iters, nb * 4, hipMemcpyDeviceToDevice, c.s));
+    }
     std::vector<int32_t> a(nb);
     HIPCHK(p, hipMemcpyAsync(a.data(), act, nb * 4, hipMemcpyDeviceToHost, c.s));
     HIPCHK(p, hipStreamSynchronize(c.s));
@@ -1091,6 +1114,19 @@ extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, co
     }
   }
   return MSGFEM_OK;
+}
+
+extern "C" int msgfem_local_eigs(msgfem_plan* p, const void* ops, void* work, const double* x0,
+                                 double* evals, double* evecs, double* resid, int32_t* iters,
+                                 int32_t* status, void* stream) {
+  return local_eigs_impl(p, ops, work, x0, nullptr, evals, evecs, resid, iters, status, stream);
+}
+
+extern "C" int msgfem_local_eigs_subset(msgfem_plan* p, const void* ops, void* work, const double* x0,
+                                        const int32_t* mask, double* evals, double* evecs, double* resid,
+                                        int32_t* iters, int32_t* status, void* stream) {
+  if (!mask) return fail(p, MSGFEM_EARG, "null mask");
+  return local_eigs_impl(p, ops, work, x0, mask, evals, evecs, resid, iters, status, stream);
 }
 
 extern "C" int msgfem_local_apply(msgfem_plan* p, const void* ops, void* work, int32_t op, int32_t kk,

@@ -808,12 +808,14 @@ __global__ __launch_bounds__(OUT_THREADS) void k_output(const BoxMeta* __restric
                                                 const double* __restrict__ rho,
                                                 double* __restrict__ evals,
                                                 double* __restrict__ evecs,
-                                                double* __restrict__ resid) {
+                                                double* __restrict__ resid,
+                                                const int32_t* __restrict__ mask) {
   __shared__ double sn[OUT_THREADS];
   __shared__ double sa[OUT_THREADS];
   __shared__ int si[OUT_THREADS];
   __shared__ double scale[32];
   int box = blockIdx.x;
+  if (mask && !mask[box]) return;   // a box the caller did not select keeps its output
   const BoxMeta& bm = meta[box];
   const int tid = threadIdx.x, col = tid & 31, slot = tid >> 5;
   const int nev = bm.n_ev;

@@ -75,6 +75,7 @@ SIGNATURES = {
     "msgfem_plan_box": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(msgfem_box_info)]),
     "msgfem_assemble_local": (ctypes.c_int, [_P, _P, _P, _P]),
     "msgfem_local_eigs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "msgfem_local_eigs_subset": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "msgfem_local_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
     "msgfem_select_modes": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
     "msgfem_error_norms": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P]),
@@ -250,6 +251,26 @@ class LocalStage:
                                         _ptr(out["iters"]), _ptr(self.status),
                                         _stream_handle(torch, self.device))
         _check(rc, self.plan, "msgfem_local_eigs")
+        out["status"] = self.status
+        return out
+
+    def msgfem_local_eigs_subset(self, mask, out, x0=None):
+        """Solves only the boxes with mask[b] != 0, writing their slots of the
+        eigen output `out` (this stage's layout) in place; the other boxes keep
+        what `out` holds (msgfem_local_eigs_subset)."""
+        torch = self.torch
+        if self.ops is None:
+            raise MsgfemError("assemble first")
+        m = np.ascontiguousarray(mask, dtype=np.int32)
+        if m.shape != (len(self.batch),):
+            raise MsgfemError(f"mask needs one entry per batch box ({len(self.batch)})")
+        md = torch.tensor(m, dtype=torch.int32, device=self.device)
+        work = self._alloc_work()
+        rc = self.lib.msgfem_local_eigs_subset(self.plan, _ptr(self.ops), _ptr(work), _ptr(x0), _ptr(md),
+                                               _ptr(out["evals"]), _ptr(out["evecs"]), _ptr(out["resid"]),
+                                               _ptr(out["iters"]), _ptr(self.status),
+                                               _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_local_eigs_subset")
         out["status"] = self.status
         return out
 

@@ -107,3 +107,26 @@ def test_reuse_recomputes_only_changed_subdomains(torch):
         f"uG energy diff {e_uG:.2e}; e_a gpu {ea_gpu:.6e} oracle {ea_ref:.6e} stale {ea_stale:.6e}")
     assert e_uG <= 1e-6
     assert abs(ea_gpu - ea_ref) <= 0.01 * ea_ref
+
+    # the same refresh in place on the full plan: msgfem_local_eigs_subset
+    # solves only the masked boxes and leaves the others' slots untouched
+    mask = [1 if int(j) in changed else 0 for j in st1.batch]
+    inplace = {k: v.clone() for k, v in out0.items() if k != "status"}
+    t0 = time.perf_counter()
+    st1.msgfem_local_eigs_subset(mask, inplace)
+    torch.cuda.synchronize()
+    t_subset = time.perf_counter() - t0
+    assert int(st1.status.abs().sum()) == 0
+    for b, j in enumerate(st1.batch):
+        if int(j) in changed:
+            lam_i, lam_c = st1.eigvals(inplace, b), stc.eigvals(outc, changed.index(int(j)))
+            assert torch.allclose(lam_i, lam_c, rtol=1e-8, atol=1e-10)
+        else:
+            assert torch.equal(st1.eigvals(inplace, b), st0.eigvals(out0, b))
+            assert torch.equal(st1.eigvecs(inplace, b), st0.eigvecs(out0, b))
+            assert torch.equal(inplace["iters"][b], out0["iters"][b])
+    AHi, bHi = st1.msgfem_coarse_assemble(inplace)
+    ui = st1.msgfem_coarse_solve(AHi, bHi)["uG"].cpu().numpy()
+    ea_in = coarse.energy_error(prob1, A, uh, ui)
+    say(f"  in place: {t_subset * 1e3:.1f} ms; e_a {ea_in:.6e}")
+    assert abs(ea_in - ea_ref) <= 0.01 * ea_ref
