@@ -157,10 +157,11 @@ def run_workload(boxes: int, steps: int):
         print(f"step {i} done, iterations {out['iters'].cpu().numpy().mean():.2f}", flush=True)
 
 
-def run_reuse(boxes: int, changed: int):
+def run_reuse(boxes: int, changed: int, layout: str = "contiguous"):
     """Offline/online reuse on the uniform batch: solve all boxes, change the
-    ply material in the middle 2^3 elements of every (boxes // changed)-th
-    core (elements that no other oversampled box holds), then time a full
+    ply material in the middle 2^3 elements of `changed` cores (a run of
+    neighbouring cores, or every (boxes // changed)-th core; elements that no
+    other oversampled box holds), then time a full
     recompute against the online path (assemble, digest, solve only the boxes
     whose digest changed, merge)."""
     import dataclasses
@@ -170,7 +171,11 @@ def run_reuse(boxes: int, changed: int):
     sys.path.insert(0, os.path.dirname(HERE))
     from paper_2211_13893_amd import msgfem, synth
     p0 = synth.uniform_batch(n_boxes=boxes)
-    picked = [int(p0.batch[i]) for i in range(0, boxes, max(1, boxes // changed))][:changed]
+    if layout == "strided":     # every (boxes // changed)-th core
+        picked = [int(p0.batch[i]) for i in range(0, boxes, max(1, boxes // changed))][:changed]
+    else:                       # a run of neighbouring cores in the middle of the column
+        first = max(0, boxes // 2 - changed // 2)
+        picked = [int(p0.batch[i]) for i in range(first, min(boxes, first + changed))]
     em = p0.elem_mat.copy().reshape(p0.nz, p0.ny, p0.nx)
     for sd in picked:
         x, y, z = (int(c) + 3 for c in p0.cores[sd, :3])
@@ -217,7 +222,7 @@ def run_reuse(boxes: int, changed: int):
     online = sum(ms[k] for k in ("assemble_all", "digest", "plan_changed", "assemble_changed", "eigs_changed",
                                  "merge"))
     online_inplace = ms["assemble_all"] + ms["digest"] + ms["eigs_subset_inplace"]
-    print(json.dumps({"reuse": {"boxes": boxes, "changed": picked, "found": found, "ms": ms,
+    print(json.dumps({"reuse": {"boxes": boxes, "layout": layout, "changed": picked, "found": found, "ms": ms,
                                 "full_ms": full, "online_ms": online, "online_inplace_ms": online_inplace, "digest_event_ms": digest_ms,
                                 "digest_bytes": nbytes, "digest_GBps": nbytes / digest_ms / 1e6}}), flush=True)
     if found != picked:
@@ -233,6 +238,7 @@ def main(argv=None):
     u = sub.add_parser("reuse")
     u.add_argument("--boxes", type=int, default=64)
     u.add_argument("--changed", type=int, default=8)
+    u.add_argument("--layout", choices=["contiguous", "strided"], default="contiguous")
     s = sub.add_parser("summarize")
     s.add_argument("--trace", required=True)
     s.add_argument("--fetch")
@@ -244,7 +250,7 @@ def main(argv=None):
     if a.cmd == "run":
         run_workload(a.boxes, a.steps)
     elif a.cmd == "reuse":
-        run_reuse(a.boxes, a.changed)
+        run_reuse(a.boxes, a.changed, a.layout)
     else:
         summarize(a.trace, a.fetch, a.write, a.out, a.title, a.commands)
 
