@@ -127,3 +127,20 @@ def test_merge_eigs_rejects_mismatched_plans():
     assert b"outside the source batch" in full[0].msgfem_plan_error(full[1])
     for p in (full, part, sub, sub_nev, other):
         p[0].msgfem_plan_destroy(p[1])
+
+
+def test_subset_and_adaptive_reject_bad_arguments():
+    """Host checks with no device work: msgfem_local_eigs_subset needs a mask;
+    the adaptive driver needs t > 0 and 1 <= n_ev0 <= n_ev_max <= 32."""
+    from paper_2211_13893_amd import adaptive
+    prob = synth.laminated_beam()
+    lib, plan, rc, _ = _plan(prob)
+    assert rc == 0
+    one = ctypes.c_void_p(256)
+    assert lib.msgfem_local_eigs_subset(plan, one, one, None, None, one, one, one, one, one, None) \
+        == msgfem.MSGFEM_EARG
+    assert b"null mask" in lib.msgfem_plan_error(plan)
+    lib.msgfem_plan_destroy(plan)
+    for t, n0, nmax in ((0.0, 8, 32), (-1.0, 8, 32), (0.1, 0, 32), (0.1, 16, 8), (0.1, 8, 40)):
+        with pytest.raises(ValueError):
+            adaptive.adaptive_local_spaces(prob, t, n_ev0=n0, n_ev_max=nmax)
