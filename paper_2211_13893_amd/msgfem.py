@@ -261,6 +261,8 @@ class LocalStage:
         torch = self.torch
         if self.ops is None:
             raise MsgfemError("assemble first")
+        if hasattr(mask, "cpu"):          # a torch tensor, e.g. digests compared on the device
+            mask = mask.cpu().numpy()
         m = np.ascontiguousarray(mask, dtype=np.int32)
         if m.shape != (len(self.batch),):
             raise MsgfemError(f"mask needs one entry per batch box ({len(self.batch)})")

@@ -110,7 +110,8 @@ def test_reuse_recomputes_only_changed_subdomains(torch):
 
     # the same refresh in place on the full plan: msgfem_local_eigs_subset
     # solves only the masked boxes and leaves the others' slots untouched
-    mask = [1 if int(j) in changed else 0 for j in st1.batch]
+    mask = d1 != d0                     # device tensor, as the call sequence passes it
+    assert mask.cpu().numpy().astype(int).tolist() == [1 if int(j) in changed else 0 for j in st1.batch]
     inplace = {k: v.clone() for k, v in out0.items() if k != "status"}
     t0 = time.perf_counter()
     st1.msgfem_local_eigs_subset(mask, inplace)
