@@ -11,6 +11,15 @@ A_0 = Z^T A Z, Z the GenEO coarse basis.  Sec. 5.3 uses the resulting CG to
 produce the fine reference solution.  The solution of that CG is pinned by
 the sparse direct solve; its iteration count has no pin (the condition bound
 of Sec. 3.2 has an unknown constant).
+
+Pins of the local GenEO pencil (tests/test_oracle_geneo.py): the literal
+pencil (A, D A D) by QZ on a tiny box; exactly 3 |P| eigenvalues equal to 1,
+P the nodes whose 27-point neighbourhood has mu = 1 (there D phi = phi and
+A phi = D A D phi); Courant-Fischer against the separately pinned A-harmonic
+oracle with no oversampling (V_A is a subspace of V_h(Omega_j), so every
+A-harmonic lambda_k is at least the GenEO lambda_k); independence of the
+oversampling; six rigid-body zeros on a floating subdomain and none on a
+clamped one.
 """
 from __future__ import annotations
 

@@ -55,7 +55,9 @@ __global__ void k_update(const BoxMeta*, int, int, Blk4x3, Out4, Out4, const dou
 __global__ void k_residual(const BoxMeta*, const uint8_t*, int, int, double, const double*, const double*,
                            const double*, double*, int, int, double*, const int32_t*);
 __global__ void k_converge(const BoxMeta*, int, int, int, const double*, const double*, double, double*,
-                           int32_t*, int32_t*, int32_t*, int);
+                           int32_t*, int32_t*, int32_t*, int, int32_t*);
+__global__ void k_status_clear(int, const int32_t*, int32_t*);
+__global__ void k_copy_masked_i32(int, const int32_t*, const int32_t*, int32_t*);
 __global__ void k_random_start(const BoxMeta*, const uint8_t*, int, int, uint64_t, double*);
 __global__ void k_lock(const BoxMeta*, int, const double*, double, double*, double*, double*, double*, double*,
                        const int32_t*);
@@ -187,15 +189,16 @@ struct ProfScope {
   hipStream_t s;
   hipEvent_t b = nullptr;
   double bytes, flops;
-  ProfScope(msgfem_plan* p_, int kernel_, hipStream_t s_, double bytes_, double flops_)
-      : p(p_), kernel(kernel_), s(s_), bytes(bytes_), flops(flops_) {
-    if (p->prof_on) {
+  bool on;
+  ProfScope(msgfem_plan* p_, int kernel_, hipStream_t s_, double bytes_, double flops_, bool allow = true)
+      : p(p_), kernel(kernel_), s(s_), bytes(bytes_), flops(flops_), on(allow && p_->prof_on) {
+    if (on) {
       b = prof_event(p);
       if (b) (void)hipEventRecord(b, s);
     }
   }
   ~ProfScope() {
-    if (p->prof_on && b) {
+    if (on && b) {
       hipEvent_t e = prof_event(p);
       if (e) {
         (void)hipEventRecord(e, s);
@@ -733,6 +736,7 @@ struct Ctx {
   hipStream_t s;
   int nb, k;
   bool use32 = false;           // FP32 operator copies (mixed path, first phase)
+  bool no_alloc = false;        // the static-scratch entry point: no event objects for profiling
   std::vector<int32_t> act_h;   // host copy of the active flags (all 1 when unknown)
   bool counts(int b, const int32_t* act) const { return !act || act_h.empty() || act_h[b]; }
 };
@@ -777,7 +781,7 @@ static int spmm(Ctx& c, const double* X, double* Y, double* Y2, int kk, int ycla
     by += 243.0 * 8 * m.n_nodes + 8.0 * m.n_dof * kk * (1 + nout);
     fl += 2.0 * 243 * m.n_nodes * kk * (Y2 ? 2 : 1);
   }
-  ProfScope ps(c.p, PK_SPMM, c.s, by, fl);
+  ProfScope ps(c.p, PK_SPMM, c.s, by, fl, !c.no_alloc);
   auto launch = [&](auto st) {
     if (Y2)
       k_spmm<true, 4><<<grid, 256, 0, c.s>>>(c.v.meta, c.nb, bpb, st, c.v.cls, c.v.mu1, X, Y, Y2, kk, yclasses,
@@ -809,7 +813,7 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
     by += 2 * 8.0 * e + 2 * 8.0 * n * kk;
     fl += 4.0 * e * kk;
   }
-  ProfScope ps(c.p, PK_SOLVE, c.s, by, fl);
+  ProfScope ps(c.p, PK_SOLVE, c.s, by, fl, !c.no_alloc);
   // bands wider than SOLVE_TILES + 1 tiles take two tile sets per step
   const bool two = c.p->max_bt_kind[kind] - 1 > SOLVE_TILES;
   auto launch = [&](auto kern, auto ft) {
@@ -929,6 +933,8 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
   };
   k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(act, nb, 1);
   k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(c.w.iters, nb, 0);
+  // bits of an earlier solve of the same boxes are stale (bit 4 of the assembly stays)
+  k_status_clear<<<(nb + 255) / 256, 256, 0, c.s>>>(nb, mask, status);
   LAUNCHCHK(p);
   // a caller mask solves only the boxes it selects; the others are inactive
   // from the start and their outputs are left as they are
@@ -998,8 +1004,8 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
       k_fill_i32<<<1, 32, 0, c.s>>>(c.w.nact, 1, 0);
       // FP32 phase: residuals are estimates, no box is retired
       k_converge<<<nb, 64, 0, c.s>>>(c.v.meta, nb, k, n_chunk, c.w.rpart, c.w.nu,
-                                                  c.use32 ? 0.0 : p->opts.tol, c.w.rho, act, c.w.iters,
-                                                  c.w.nact, it < p->opts.maxit ? 1 : 0);
+                                     c.use32 ? 0.0 : p->opts.tol, c.w.rho, act, c.w.iters,
+                                     c.w.nact, it == p->opts.maxit ? 1 : 0, status);
       LAUNCHCHK(p);
       c.act_h.resize(nb);
       HIPCHK(p, hipMemcpyAsync(c.act_h.data(), act, nb * 4, hipMemcpyDeviceToHost, c.s));
@@ -1081,38 +1087,15 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
       std::swap(B[kind][2], B[kind][4]);
     }
   }
-  // boxes still active did not converge
-  {
-    k_output<<<nb, 1024, 0, c.s>>>(c.v.meta, k, p->opts.shift, B[0][0], c.w.nu, c.w.rho, evals, evecs,
-                                  resid, mask);
-    LAUNCHCHK(p);
-    if (mask) {
-      std::vector<int32_t> it_new(nb), it_old(nb);
-      HIPCHK(p, hipMemcpyAsync(it_new.data(), c.w.iters, nb * 4, hipMemcpyDeviceToHost, c.s));
-      HIPCHK(p, hipMemcpyAsync(it_old.data(), iters, nb * 4, hipMemcpyDeviceToHost, c.s));
-      HIPCHK(p, hipStreamSynchronize(c.s));
-      for (int b = 0; b < nb; ++b)
-        if (mask_h[b]) it_old[b] = it_new[b];
-      HIPCHK(p, hipMemcpyAsync(iters, it_old.data(), nb * 4, hipMemcpyHostToDevice, c.s));
-      HIPCHK(p, hipStreamSynchronize(c.s));
-    } else {
-      HIPCHK(p, hipMemcpyAsync(iters, c.w.iters, nb * 4, hipMemcpyDeviceToDevice, c.s));
-    }
-    std::vector<int32_t> a(nb);
-    HIPCHK(p, hipMemcpyAsync(a.data(), act, nb * 4, hipMemcpyDeviceToHost, c.s));
-    HIPCHK(p, hipStreamSynchronize(c.s));
-    bool any = false;
-    for (int b = 0; b < nb; ++b) any |= a[b] != 0;
-    if (any) {
-      // status |= 1 for boxes left active
-      std::vector<int32_t> st(nb);
-      HIPCHK(p, hipMemcpyAsync(st.data(), status, nb * 4, hipMemcpyDeviceToHost, c.s));
-      HIPCHK(p, hipStreamSynchronize(c.s));
-      for (int b = 0; b < nb; ++b) st[b] |= a[b] ? 1 : 0;
-      HIPCHK(p, hipMemcpyAsync(status, st.data(), nb * 4, hipMemcpyHostToDevice, c.s));
-      HIPCHK(p, hipStreamSynchronize(c.s));
-    }
-  }
+  // outputs (k_converge has set bit 1 on the boxes still active after maxit)
+  k_output<<<nb, 1024, 0, c.s>>>(c.v.meta, k, p->opts.shift, B[0][0], c.w.nu, c.w.rho, evals, evecs, resid,
+                                mask);
+  LAUNCHCHK(p);
+  if (mask)
+    k_copy_masked_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(nb, mask, c.w.iters, iters);
+  else
+    HIPCHK(p, hipMemcpyAsync(iters, c.w.iters, nb * 4, hipMemcpyDeviceToDevice, c.s));
+  LAUNCHCHK(p);
   return MSGFEM_OK;
 }
 
@@ -1129,22 +1112,12 @@ extern "C" int msgfem_local_eigs_subset(msgfem_plan* p, const void* ops, void* w
   return local_eigs_impl(p, ops, work, x0, mask, evals, evecs, resid, iters, status, stream);
 }
 
-extern "C" int msgfem_local_apply(msgfem_plan* p, const void* ops, void* work, int32_t op, int32_t kk,
-                                  const double* x, double* y, void* stream) {
-  if (!p || !ops || !x || !y || x == y) return fail(p, MSGFEM_EARG, "bad argument");
-  if (kk != p->k) return fail(p, MSGFEM_EARG, "k must equal the plan's block width %d", p->k);
-  if (set_device(p)) return MSGFEM_EHIP;
-  Ctx c;
-  c.p = p;
-  c.v = ops_view(p, ops);
-  c.s = (hipStream_t)stream;
-  c.nb = (int)p->meta.size();
-  c.k = p->k;
-  if (!work) return fail(p, MSGFEM_EARG, "null work buffer");
-  c.w = work_view(p, work);
+// The operator products and solves of msgfem_local_apply with caller-chosen
+// scratch: xm (dofs_total * k doubles, ops 0 and 1) and scr (the solves' w rows).
+static int apply_impl(Ctx& c, int32_t op, int32_t kk, const double* x, double* y, double* xm) {
+  msgfem_plan* p = c.p;
   if (op == 0 || op == 1) {
     // B3 columns are removed from A: clear the caller's block there first
-    double* xm = c.w.vec + (int64_t)20 * p->vec_total;
     const int64_t n = p->dofs_total * kk;
     k_mask_b3<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, c.s>>>(c.v.cls, x, kk, n, xm);
     LAUNCHCHK(p);
@@ -1152,8 +1125,24 @@ extern "C" int msgfem_local_apply(msgfem_plan* p, const void* ops, void* work, i
     return spmm(c, xm, nullptr, y, kk, 0, 1.0, nullptr) ? MSGFEM_EHIP : 0;
   }
   if (op == 2) return solve(c, 0, x, y, kk, 1 << 1, 1, nullptr) ? MSGFEM_EHIP : 0;
-  if (op == 3) return solve(c, 1, x, y, kk, (1 << 1) | (1 << 2), 1, nullptr) ? MSGFEM_EHIP : 0;
-  return fail(p, MSGFEM_EARG, "unknown op %d", op);
+  return solve(c, 1, x, y, kk, (1 << 1) | (1 << 2), 1, nullptr) ? MSGFEM_EHIP : 0;
+}
+
+extern "C" int msgfem_local_apply(msgfem_plan* p, const void* ops, void* work, int32_t op, int32_t kk,
+                                  const double* x, double* y, void* stream) {
+  if (!p || !ops || !x || !y || x == y) return fail(p, MSGFEM_EARG, "bad argument");
+  if (kk != p->k) return fail(p, MSGFEM_EARG, "k must equal the plan's block width %d", p->k);
+  if (op < 0 || op > 3) return fail(p, MSGFEM_EARG, "unknown op %d", op);
+  if (!work) return fail(p, MSGFEM_EARG, "null work buffer");
+  if (set_device(p)) return MSGFEM_EHIP;
+  Ctx c;
+  c.p = p;
+  c.v = ops_view(p, ops);
+  c.s = (hipStream_t)stream;
+  c.nb = (int)p->meta.size();
+  c.k = p->k;
+  c.w = work_view(p, work);
+  return apply_impl(c, op, kk, x, y, c.w.vec + (int64_t)20 * p->vec_total);
 }
 
 extern "C" int msgfem_profile(msgfem_plan* p, int32_t enable) {

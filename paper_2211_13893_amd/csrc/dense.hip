@@ -17,6 +17,8 @@
 //  k_residual / k_converge        : R = M X - nu T X on B2, the scale-free
 //                                   residual rho = |R| / (|MX| + nu |TX|),
 //                                   convergence and iteration bookkeeping.
+#include <cfloat>
+
 #include "internal.hpp"
 
 namespace msg {
@@ -704,18 +706,22 @@ __global__ __launch_bounds__(RES_THREADS) void k_residual(const BoxMeta* __restr
 }
 
 // Per box: rho from the partial sums; converged when every one of the first
-// n_ev columns has rho <= tol.  Updates active/iters and the count of boxes
-// still active.  One thread per box.
+// n_ev columns has rho <= tol.  A column whose rho is not a finite number
+// (a zero or non-finite denominator, or a non-finite residual) sets status
+// bit 8; a box with bit 4 (a non-positive pivot in its factors) or bit 8 is
+// retired at once as failed, so it does not hold the batch loop.  On the last
+// iteration (last != 0) a box still unconverged gets bit 1.  Updates
+// active/iters and the count of boxes still active.
 __global__ void k_converge(const BoxMeta* __restrict__ meta, int n_box, int k, int n_chunk,
                            const double* __restrict__ part, const double* __restrict__ nu,
                            double tol, double* __restrict__ rho, int32_t* __restrict__ active,
                            int32_t* __restrict__ iters, int32_t* __restrict__ n_active,
-                           int count_iter) {
+                           int last, int32_t* __restrict__ status) {
   // one wavefront per box, lane c < k takes column c (chunks summed in order)
   const int box = blockIdx.x, c = threadIdx.x;
   if (box >= n_box || !active[box]) return;
   const int nev = meta[box].n_ev;
-  bool ok = true;
+  bool ok = true, fin = true;
   if (c < k) {
     double a = 0.0, b = 0.0, d = 0.0;
     for (int ch = 0; ch < n_chunk; ++ch) {
@@ -726,19 +732,46 @@ __global__ void k_converge(const BoxMeta* __restrict__ meta, int n_box, int k, i
     }
     const double v = nu[(int64_t)box * k + c];
     const double den = sqrt(b) + v * sqrt(d);
-    const double r = den > 0.0 ? sqrt(a) / den : 0.0;
+    // rho is defined for a positive finite denominator only (a zero column, or
+    // one with M x = T x = 0, has no eigenvalue)
+    const double r = (den > 0.0 && den <= DBL_MAX) ? sqrt(a) / den : __builtin_nan("");
     rho[(int64_t)box * k + c] = r;
-    ok = !(c < nev && !(r <= tol));
-  }
-  const bool all_ok = __all(ok);
-  if (c == 0) {
-    if (all_ok) {
-      active[box] = 0;
-    } else {
-      iters[box] += count_iter;
-      atomicAdd(n_active, 1);
+    if (c < nev) {
+      fin = r <= DBL_MAX;          // false for NaN and inf
+      ok = r <= tol;
     }
   }
+  const bool all_ok = __all(ok);
+  const bool all_fin = __all(fin);
+  if (c == 0) {
+    int32_t st = status[box];
+    if (!all_fin) st |= 8;
+    if (st & (4 | 8)) {
+      active[box] = 0;             // failed: retired, not converged
+    } else if (all_ok) {
+      active[box] = 0;
+    } else {
+      if (last) st |= 1;
+      iters[box] += last ? 0 : 1;
+      atomicAdd(n_active, 1);
+    }
+    status[box] = st;
+  }
+}
+
+// Clears the status bits a local eigensolve sets (1 not converged, 8
+// non-finite, 16 threshold) on the boxes it is about to solve (all boxes, or
+// those with mask[b] != 0), keeping bit 4 of the assembly.
+__global__ void k_status_clear(int n_box, const int32_t* __restrict__ mask, int32_t* __restrict__ status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n_box && (!mask || mask[b])) status[b] &= ~(1 | 8 | 16);
+}
+
+// dst[b] = src[b] where mask[b] != 0 (the iteration counts of a masked solve)
+__global__ void k_copy_masked_i32(int n, const int32_t* __restrict__ mask, const int32_t* __restrict__ src,
+                                  int32_t* __restrict__ dst) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n && mask[b]) dst[b] = src[b];
 }
 
 // Soft locking: a column whose residual is below lock_tol gets no new search

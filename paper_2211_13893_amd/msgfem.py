@@ -254,6 +254,24 @@ class LocalStage:
         out["status"] = self.status
         return out
 
+    def _check_eig_output(self, out, what: str):
+        """An eigen output in this stage's layout: float64 evals/evecs/resid and int32
+        iters, contiguous, on this stage's device, of this plan's lengths (the
+        kernels write through these pointers, so a stored output of another plan
+        must not reach them)."""
+        torch = self.torch
+        s = self.sizes
+        want = {"evals": (torch.float64, s.n_eval), "evecs": (torch.float64, s.n_evec),
+                "resid": (torch.float64, s.n_eval), "iters": (torch.int32, s.n_box)}
+        for key, (dt, n) in want.items():
+            t = out.get(key) if isinstance(out, dict) else None
+            if t is None:
+                raise MsgfemError(f"{what}: output '{key}' missing")
+            on_dev = t.device.type == "cuda" and (self.device.index is None or t.device.index == self.device.index)
+            if t.dtype != dt or not t.is_contiguous() or not on_dev or t.numel() != n:
+                raise MsgfemError(f"{what}: '{key}' must be a contiguous {dt} tensor of {n} elements on "
+                                  f"{self.device} (got {t.dtype}, {t.numel()} elements on {t.device})")
+
     def msgfem_local_eigs_subset(self, mask, out, x0=None):
         """Solves only the boxes with mask[b] != 0, writing their slots of the
         eigen output `out` (this stage's layout) in place; the other boxes keep
@@ -266,6 +284,7 @@ class LocalStage:
         m = np.ascontiguousarray(mask, dtype=np.int32)
         if m.shape != (len(self.batch),):
             raise MsgfemError(f"mask needs one entry per batch box ({len(self.batch)})")
+        self._check_eig_output(out, "msgfem_local_eigs_subset")
         md = torch.tensor(m, dtype=torch.int32, device=self.device)
         work = self._alloc_work()
         rc = self.lib.msgfem_local_eigs_subset(self.plan, _ptr(self.ops), _ptr(work), _ptr(x0), _ptr(md),
@@ -351,6 +370,8 @@ class LocalStage:
         the boxes of `src_stage` (all, or the batch positions `boxes`) replaced by
         `src_out` (msgfem_merge_eigs)."""
         torch = self.torch
+        self._check_eig_output(stored, "msgfem_merge_eigs (stored)")
+        src_stage._check_eig_output(src_out, "msgfem_merge_eigs (source)")
         out = {k: (v if k == "status" else v.clone()) for k, v in stored.items()}
         sel = None if boxes is None else np.ascontiguousarray(boxes, dtype=np.int32)
         rc = self.lib.msgfem_merge_eigs(self.plan, src_stage.plan, None if sel is None else sel.ctypes.data,
