@@ -84,15 +84,22 @@ typedef struct {
   double tol;       /* residual tolerance on rho (default 1e-6) */
   int32_t maxit;    /* LOBPCG iteration cap (default 200) */
   int32_t block;    /* block width k >= max n_ev (0: max(2 n_ev, n_ev + 8) rounded up to 8); at most 32 */
-  int32_t precision;/* 0 = FP64 throughout.  1 = mixed (A-harmonic GEVP only): the
-                       assembly also keeps FP32 copies of the stencil and of the
-                       factors' solve data (ops_bytes grows accordingly); LOBPCG
-                       first runs its SpMM and block solves on those copies (FP64
-                       arithmetic, FP64 Gram / Rayleigh-Ritz / update / residual)
-                       until every active box has rho <= max(1e-4, 100 tol) (or
-                       the largest rho stops halving over two iterations), then
-                       re-forms the block with the FP64 operators and finishes in
-                       FP64, so the returned residuals are FP64 residuals */
+  int32_t precision;/* 0 = FP64 throughout.
+                       1 = mixed: the preconditioner solve (A + s D A D)^{-1}
+                       reads an FP32 copy of its factor (FP64 arithmetic); the
+                       operator itself (SpMM, the extension and adjoint solves
+                       with A11), the Gram matrices, Rayleigh-Ritz, update and
+                       residuals stay FP64, so the eigenpairs and residuals are
+                       those of the FP64 pencil and only the search directions
+                       change (no restart).  ops_bytes grows by the FP32 copy.
+                       2 = FP32 operators first (A-harmonic GEVP only): SpMM and
+                       all block solves read FP32 copies of the stencil and
+                       factors (FP64 arithmetic and dense steps) until every
+                       active box has rho <= max(1e-4, 100 tol) (or the largest
+                       rho stops halving over two iterations, or after 30
+                       iterations), then the block is re-imaged with the FP64
+                       operators and the iteration finishes in FP64, so the
+                       returned residuals are FP64 residuals */
   int32_t geneo;    /* 0: A-harmonic GEVP on Omega_j^* (Sec. 3.3); 1: classic GenEO GEVP
                        a_{Omega_j}(phi, v) = lambda a_{Omega_j}(Xi phi, Xi v) on Omega_j
                        itself (Sec. 3.2; oversampling ignored), unknowns on every

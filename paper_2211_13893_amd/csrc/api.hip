@@ -38,7 +38,7 @@ __global__ void k_band_solve4(const BoxMeta*, int, int, int, const T*, const uin
 template <bool TWO, int CW, typename ST>
 __global__ void k_spmm(const BoxMeta*, int, int, const ST*, const uint8_t*, const double*, const double*,
                        double*, double*, int, int, double, const int32_t*);
-__global__ void k_mixed_copies(const BoxMeta*, const double*, float*, const double*, float*);
+__global__ void k_mixed_copies(const BoxMeta*, int, const double*, float*, const double*, float*);
 __global__ void k_mask_b3(const uint8_t*, const double*, int, int64_t, double*);
 __global__ void k_keep_classes(const uint8_t*, int, int, int64_t, double*);
 struct Blk3 { const double* p[3]; };
@@ -267,8 +267,9 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     if (!(o.tol > 0)) o.tol = 1e-6;
     if (o.maxit <= 0) o.maxit = 200;
   }
-  if (o.precision != 0 && o.precision != 1) return fail(p, MSGFEM_EARG, "precision %d not supported", o.precision);
-  if (o.precision == 1 && o.geneo) return fail(p, MSGFEM_EARG, "the mixed path is for the A-harmonic GEVP only");
+  if (o.precision < 0 || o.precision > 2) return fail(p, MSGFEM_EARG, "precision %d not supported", o.precision);
+  if (o.precision == 2 && o.geneo)
+    return fail(p, MSGFEM_EARG, "the FP32-operator phase is for the A-harmonic GEVP only");
   p->opts = o;
   const int N[3] = {mesh->nx, mesh->ny, mesh->nz};
   p->n_nodes_global = (int64_t)(N[0] + 1) * (N[1] + 1) * (N[2] + 1);
@@ -404,10 +405,11 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   p->o_mu = off; off = align256(off + p->dofs_total * 8);
   p->o_cls = off; off = align256(off + p->dofs_total);
   p->o_fac = off; off = align256(off + p->fac_total * 8);
-  if (o.precision == 1) {
-    // FP32 copies of the stencil and of the factors' solve data (mixed path)
+  if (o.precision >= 1) {
+    // FP32 copies of the factors' solve data (precision 1: the preconditioner's
+    // Ahat only; 2: both matrices) and of the stencil (precision 2)
     p->o_fac32 = off; off = align256(off + p->fac_total * 4);
-    p->o_st32 = off; off = align256(off + p->nodes_total * 243 * 4);
+    if (o.precision == 2) { p->o_st32 = off; off = align256(off + p->nodes_total * 243 * 4); }
   }
   p->ops_bytes = off;
   // work layout
@@ -681,9 +683,12 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
       k_band_relayout<<<dim3(SOLVE_TILES * max_sets, max_nt, nb), 256, 0, s>>>(v.meta, kind, v.fac);
     LAUNCHCHK(p);
   }
-  if (p->opts.precision == 1) {
+  if (p->opts.precision >= 1) {
     ProfScope ps(p, PK_BUILD, s, 0.0, 0.0);
-    k_mixed_copies<<<dim3(1024, nb, 3), 256, 0, s>>>(v.meta, v.fac, v.fac32, v.stencil, v.stencil32);
+    if (p->opts.precision == 1)
+      k_mixed_copies<<<dim3(1024, nb, 1), 256, 0, s>>>(v.meta, 1, v.fac, v.fac32, v.stencil, v.stencil32);
+    else
+      k_mixed_copies<<<dim3(1024, nb, 3), 256, 0, s>>>(v.meta, 0, v.fac, v.fac32, v.stencil, v.stencil32);
     LAUNCHCHK(p);
   }
   return MSGFEM_OK;
@@ -735,7 +740,8 @@ struct Ctx {
   Work w;
   hipStream_t s;
   int nb, k;
-  bool use32 = false;           // FP32 operator copies (mixed path, first phase)
+  bool use32 = false;           // FP32 operator copies (precision 2, first phase)
+  bool pre32 = false;           // FP32 copy of Ahat for the preconditioner solve (precision 1)
   bool no_alloc = false;        // the static-scratch entry point: no event objects for profiling
   std::vector<int32_t> act_h;   // host copy of the active flags (all 1 when unknown)
   bool counts(int b, const int32_t* act) const { return !act || act_h.empty() || act_h[b]; }
@@ -801,6 +807,8 @@ static int spmm(Ctx& c, const double* X, double* Y, double* Y2, int kk, int ycla
 
 static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int out_classes, int zero_rest,
                  const int32_t* active) {
+  // the preconditioner's matrix (kind 1) from its FP32 copy under precision 1
+  const bool f32 = c.use32 || (kind == 1 && c.pre32);
   int nchunk = (kk + KC - 1) / KC;
   dim3 grid(8 * nchunk * ((c.nb + 7) / 8));
   size_t lds = (size_t)c.p->max_bt_kind[kind] * 32 * KC * 8;
@@ -823,7 +831,7 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
   if (solve4_kind(c.p, kind)) {
     // bands of at most 33 tiles: the matrix-core solve, 1..4 tile slots per wavefront
     const int ns = solve4_nslot(c.p->max_bt_kind[kind]);
-    if (c.use32) {
+    if (f32) {
       const float* f = (const float*)c.v.fac32;
       if (ns <= 1) launch(k_band_solve4<1, float>, f);
       else if (ns == 2) launch(k_band_solve4<2, float>, f);
@@ -836,7 +844,7 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
       else if (ns == 3) launch(k_band_solve4<3, double>, f);
       else launch(k_band_solve4<4, double>, f);
     }
-  } else if (c.use32) {
+  } else if (f32) {
     if (two) launch(k_band_solve<KC, 2, float>, (const float*)c.v.fac32);
     else launch(k_band_solve<KC, 1, float>, (const float*)c.v.fac32);
   } else {
@@ -986,8 +994,9 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
   // re-imaged with the FP64 operators, re-orthonormalised, and the iteration
   // continues in FP64 (without the P block once) to the requested tolerance,
   // so the final residual check is FP64.
-  const bool mixed = p->opts.precision == 1;
+  const bool mixed = p->opts.precision == 2;
   c.use32 = mixed;
+  c.pre32 = p->opts.precision == 1;
   const double switch_tol = std::max(1e-4, 100.0 * p->opts.tol);
   const int fp32_cap = 30;
   int fp32_iters = 0;

@@ -834,17 +834,18 @@ __global__ __launch_bounds__(256) void k_band_unit_relayout4(const BoxMeta* __re
 // the two solve-ordered band copies and the D^{-1} diagonal tiles of both box
 // matrices (grid.y = box, grid.z = matrix kind), and the stencil
 // (grid.z = 2).
-__global__ void k_mixed_copies(const BoxMeta* __restrict__ meta, const double* __restrict__ fac,
+__global__ void k_mixed_copies(const BoxMeta* __restrict__ meta, int zbase, const double* __restrict__ fac,
                                float* __restrict__ fac32, const double* __restrict__ stencil,
                                float* __restrict__ stencil32) {
   const BoxMeta& bm = meta[blockIdx.y];
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, st = (int64_t)gridDim.x * blockDim.x;
-  if (blockIdx.z == 2) {
+  const int z = zbase + blockIdx.z;   // 0: A11 factor data, 1: Ahat factor data, 2: stencil
+  if (z == 2) {
     const int64_t o = bm.node_off * 243, n = (int64_t)bm.n_nodes * 243;
     for (int64_t e = t0; e < n; e += st) stencil32[o + e] = (float)stencil[o + e];
     return;
   }
-  BandView v = band_view(bm, blockIdx.z);
+  BandView v = band_view(bm, z);
   const int64_t nb = solve_copy_doubles(v.NT, v.BT);
   for (int64_t e = t0; e < nb; e += st) {
     fac32[v.fw + e] = (float)fac[v.fw + e];
