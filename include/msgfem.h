@@ -201,6 +201,25 @@ int msgfem_local_eigs_subset(msgfem_plan *plan, const void *ops, void *work, con
 int msgfem_local_apply(msgfem_plan *plan, const void *ops, void *work, int32_t op, int32_t k,
                        const double *x, double *y, void *stream);
 
+/* msgfem_local_apply without a work buffer, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same operators, kernels, layouts and results as
+ * msgfem_local_apply; the scratch it needs (the B3-masked copy of x for ops 0
+ * and 1, dofs_total * k doubles; the forward-sweep rows of the block solves for
+ * ops 2 and 3, about n_box * ceil(k / 8) * (tile rows + 1) * 256 doubles) lives
+ * in a static device buffer of msgfem_static_scratch_max() bytes (16 MiB), one
+ * per GPU, held until the process ends.  It allocates nothing (no hipMalloc,
+ * hipFree or event objects; kernel timing of msgfem_profile is not recorded).
+ * Nothing in the buffer needs to start at zero: every call writes the scratch
+ * it reads.  All calls on one GPU share that GPU's buffer, so calls that
+ * overlap in time on one GPU (two streams, two host threads) race; serialise
+ * them.  MSGFEM_ESIZE, before any device work, when a plan needs more scratch
+ * than the buffer holds (e.g. the 64-box uniform batch: use msgfem_local_apply
+ * with a work buffer there); other errors as msgfem_local_apply. */
+int msgfem_local_apply_static(msgfem_plan *plan, const void *ops, int32_t op, int32_t k, const double *x,
+                              double *y, void *stream);
+int64_t msgfem_static_scratch_max(void);
+
 /* Uniform tractions on the mesh faces (Sec. 2: b(v) = integral of g.v over
  * Gamma_N; the body force is zero).  Host arrays: face[n] with 0..5 =
  * x-, x+, y-, y+, z-, z+ and g[n][3] in MPa. */

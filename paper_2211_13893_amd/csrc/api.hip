@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1152,6 +1153,71 @@ extern "C" int msgfem_local_apply(msgfem_plan* p, const void* ops, void* work, i
   c.k = p->k;
   c.w = work_view(p, work);
   return apply_impl(c, op, kk, x, y, c.w.vec + (int64_t)20 * p->vec_total);
+}
+
+// ---------------------------------------------------------------------------
+// msgfem_local_apply_static: the same products and solves with the scratch in
+// a file-scope device array instead of the caller's work buffer.  Host code
+// never passes the array's name to a kernel (on the host it only names the
+// symbol): its device address is looked up once per device with
+// hipGetSymbolAddress, with that device current, and kept in g_scratch_ptr.
+
+#define MSGFEM_STATIC_SCRATCH_MAX ((int64_t)16 << 20)
+static __device__ __align__(256) unsigned char scratch[MSGFEM_STATIC_SCRATCH_MAX];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;   // per device ordinal, nullptr until looked up
+
+static int static_scratch(msgfem_plan* p, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  const int dev = p->device;
+  if (dev < 0) return fail(p, MSGFEM_EARG, "bad device %d", dev);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(p, MSGFEM_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MSGFEM_OK;
+}
+
+// bytes of static scratch an op of this plan needs (256-aligned pieces)
+static int64_t static_scratch_bytes(const msgfem_plan* p, int op) {
+  if (op == 0 || op == 1) return align256(p->dofs_total * p->k * 8);
+  const int nchunk = (p->k + KC - 1) / KC;
+  return align256((int64_t)p->meta.size() * nchunk * p->scr_stride * 8);
+}
+
+extern "C" int64_t msgfem_static_scratch_max(void) { return MSGFEM_STATIC_SCRATCH_MAX; }
+
+extern "C" int msgfem_local_apply_static(msgfem_plan* p, const void* ops, int32_t op, int32_t kk, const double* x,
+                                         double* y, void* stream) {
+  if (!p || !ops || !x || !y || x == y) return fail(p, MSGFEM_EARG, "bad argument");
+  if (kk != p->k) return fail(p, MSGFEM_EARG, "k must equal the plan's block width %d", p->k);
+  if (op < 0 || op > 3) return fail(p, MSGFEM_EARG, "unknown op %d", op);
+  const int64_t need = static_scratch_bytes(p, op);
+  if (need > MSGFEM_STATIC_SCRATCH_MAX)
+    return fail(p, MSGFEM_ESIZE,
+                "op %d of this plan needs %lld bytes of scratch, more than the %lld of the static buffer "
+                "(use msgfem_local_apply with a work buffer)",
+                op, (long long)need, (long long)MSGFEM_STATIC_SCRATCH_MAX);
+  if (set_device(p)) return MSGFEM_EHIP;
+  void* base = nullptr;
+  if (int rc = static_scratch(p, &base)) return rc;
+  Ctx c;
+  c.p = p;
+  c.v = ops_view(p, ops);
+  c.s = (hipStream_t)stream;
+  c.nb = (int)p->meta.size();
+  c.k = p->k;
+  c.no_alloc = true;
+  std::memset(&c.w, 0, sizeof c.w);
+  c.w.scr = (double*)base;   // the solves' w rows (written before they are read)
+  return apply_impl(c, op, kk, x, y, (double*)base);
 }
 
 extern "C" int msgfem_profile(msgfem_plan* p, int32_t enable) {

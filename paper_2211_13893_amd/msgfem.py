@@ -77,6 +77,8 @@ SIGNATURES = {
     "msgfem_local_eigs": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "msgfem_local_eigs_subset": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "msgfem_local_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    "msgfem_local_apply_static": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    "msgfem_static_scratch_max": (ctypes.c_int64, []),
     "msgfem_select_modes": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
     "msgfem_error_norms": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P]),
     "msgfem_box_digest": (ctypes.c_int, [_P, _P, _P, _P]),
@@ -303,6 +305,16 @@ class LocalStage:
         rc = self.lib.msgfem_local_apply(self.plan, _ptr(self.ops), _ptr(work), op, k, _ptr(x), _ptr(y),
                                          _stream_handle(torch, self.device))
         _check(rc, self.plan, "msgfem_local_apply")
+        return y
+
+    def msgfem_local_apply_static(self, op: int, x, y=None, k: Optional[int] = None):
+        """msgfem_local_apply with the library's static scratch (no work buffer)."""
+        torch = self.torch
+        k = self.k if k is None else k
+        y = torch.zeros_like(x) if y is None else y
+        rc = self.lib.msgfem_local_apply_static(self.plan, _ptr(self.ops), op, k, _ptr(x), _ptr(y),
+                                                _stream_handle(torch, self.device))
+        _check(rc, self.plan, "msgfem_local_apply_static")
         return y
 
     def msgfem_coarse_sizes(self):

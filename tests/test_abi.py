@@ -144,3 +144,21 @@ def test_subset_and_adaptive_reject_bad_arguments():
     for t, n0, nmax in ((0.0, 8, 32), (-1.0, 8, 32), (0.1, 0, 32), (0.1, 16, 8), (0.1, 8, 40)):
         with pytest.raises(ValueError):
             adaptive.adaptive_local_spaces(prob, t, n_ev0=n0, n_ev_max=nmax)
+
+
+def test_static_apply_rejects_plans_beyond_its_scratch():
+    # host-side check before any device work: the 64-box uniform batch needs far
+    # more than the static buffer; a small plan fits
+    lib = _lib()
+    assert lib.msgfem_static_scratch_max() == 16 << 20
+    prob = synth.uniform_batch(n_boxes=64)
+    lib, plan, rc, _ = _plan(prob)
+    assert rc == 0
+    x = ctypes.c_void_p(1)
+    y = ctypes.c_void_p(2)
+    for op in (0, 3):
+        r = lib.msgfem_local_apply_static(plan, ctypes.c_void_p(3), op, 32, x, y, None)
+        assert r == msgfem.MSGFEM_ESIZE
+        assert b"static buffer" in lib.msgfem_plan_error(plan)
+    assert lib.msgfem_local_apply_static(plan, ctypes.c_void_p(3), 7, 32, x, y, None) == msgfem.MSGFEM_EARG
+    lib.msgfem_plan_destroy(plan)
