@@ -339,6 +339,86 @@ int msgfem_geneo_pcg(msgfem_plan *plan, const void *ops, void *work, void *coars
                      const msgfem_load *load, double rtol, int32_t maxit, void *pcg, double *u,
                      int32_t *iters, double *relres, int32_t *status, void *stream);
 
+/* ------------------------------------------------------------------------
+ * The coarse problem gathered across plans.  A batch of large oversampled
+ * boxes can need more device memory than one plan may take (a 24^3-element
+ * box holds about 4 GB of operators and factors), so the local stage streams
+ * through plans that each hold part of the subdomains.  A coarse object
+ * describes every subdomain of one decomposition (the box of Omega_j^*, or of
+ * Omega_j for GenEO) and the layout of a caller-owned device "store"; after
+ * each plan's local eigensolve, msgfem_coarse_add puts that plan's share of
+ * the coarse problem into the store, and once every subdomain is in, the
+ * Galerkin system, the coarse solve and (GenEO) the two-level PCG run from
+ * the store alone.  Same mathematics as msgfem_coarse_assemble /
+ * msgfem_coarse_solve / msgfem_geneo_pcg (Sec. 3.2, 3.3, 4.3, 4.4).
+ * ------------------------------------------------------------------------ */
+typedef struct msgfem_coarse msgfem_coarse;
+
+/* Host-side: the boxes of every subdomain (geneo = 1: Omega_j, else
+ * Omega_j^*), n_ev[nsd] coarse functions per subdomain (1..32), the overlap
+ * pairs and the store layout.  The mesh's device pointers are kept (they must
+ * stay valid).  MSGFEM_EARG for inconsistent geometry. */
+int msgfem_coarse_create(msgfem_coarse **coarse, int device, const msgfem_mesh *mesh, const msgfem_decomp *dec,
+                         const int32_t *n_ev, int32_t geneo);
+void msgfem_coarse_destroy(msgfem_coarse *coarse);
+const char *msgfem_coarse_error(const msgfem_coarse *coarse);
+
+/* Device bytes of the store, N_H = sum of n_ev, and the number of columns kc
+ * the store keeps per subdomain (max n_ev, even). */
+int msgfem_coarse_store_sizes(const msgfem_coarse *coarse, int64_t *store_bytes, int32_t *n_coarse, int32_t *n_columns);
+
+/* Where subdomain sd sits: its first DoF in the store's box vectors, its box
+ * DoF count and its first row in A^H (any pointer may be NULL). */
+int msgfem_coarse_box(const msgfem_coarse *coarse, int32_t sd, int64_t *dof_off, int32_t *n_dof, int32_t *row_off);
+
+/* The coarse data of every box of `plan` (assembled, eigensolved; evecs in
+ * its msgfem_local_eigs layout) into the store: the box load b, the
+ * particular function psi (A11 psi = b on B1), V_j = mu_j phi orthonormalised
+ * by two Cholesky-QR passes with the 1e-12 drop, A V_j, mu_j psi_j and
+ * A mu_j psi_j; for a GenEO object also the solve data of the box's interior
+ * (Dirichlet) factor, rounded to FP32, for the PCG's local solves.  The plan
+ * must describe the same mesh, decomposition and eigenproblem, with the same
+ * box and n_ev for each of its subdomains, and (GenEO) the same solve layout
+ * as the object, which follows the widest band (MSGFEM_EARG otherwise).
+ * Uses the plan's work buffer.  Asynchronous on `stream`; a subdomain added
+ * again overwrites its slot. */
+int msgfem_coarse_add(msgfem_coarse *coarse, msgfem_plan *plan, const void *ops, void *work, const msgfem_load *load,
+                      const double *evecs, void *store, void *stream);
+
+/* AH (device, N_H x N_H row-major) = V^T A V and bH = V^T (b - A u^p) over all
+ * subdomains (a dropped coarse function gets a unit diagonal entry and a zero
+ * right-hand side).  MSGFEM_EARG until every subdomain has been added. */
+int msgfem_coarse_galerkin(msgfem_coarse *coarse, void *store, double *AH, double *bH, void *stream);
+
+/* FP64 tile Cholesky of AH (into the store), c = AH^{-1} bH by a
+ * multi-workgroup block solve, and uG = u^p + V c on the global mesh (up, if
+ * not NULL, receives u^p); vectors of 3 * mesh nodes.  status[0] gets bit 4
+ * if AH is not numerically positive definite. */
+int msgfem_coarse_solve_store(msgfem_coarse *coarse, void *store, const double *AH, const double *bH, double *c,
+                              double *uG, double *up, int32_t *status, void *stream);
+
+/* Device bytes of the workspace of msgfem_coarse_pcg (whole-mesh stencil,
+ * global and box vectors, the local solves' scratch). */
+int msgfem_coarse_pcg_sizes(const msgfem_coarse *coarse, int64_t *bytes);
+
+/* GenEO two-level additive Schwarz CG on the whole mesh from a GenEO store
+ * (every subdomain added): M^{-1} = R_0^T A_0^{-1} R_0 + sum_j R_j^T A_j^{-1} R_j
+ * with A_0 = A0 (msgfem_coarse_galerkin of this object) and the local
+ * Dirichlet solves A_j^{-1} from the store's FP32 factor copies (FP64
+ * arithmetic; the preconditioner only shapes the iteration).  u: initial
+ * guess in, solution out; stops at |r| <= rtol |b|.  iters, relres: host
+ * outputs (the call synchronises).  status[0]: bit 1 if maxit was reached,
+ * bit 4 if A_0 is not numerically positive definite. */
+int msgfem_coarse_pcg(msgfem_coarse *coarse, void *store, const double *A0, const msgfem_load *load, double rtol,
+                      int32_t maxit, void *pcg, double *u, int32_t *iters, double *relres, int32_t *status,
+                      void *stream);
+
+/* Energy norms with the whole-mesh stencil a completed msgfem_coarse_pcg left
+ * in `pcg`: out (device double[2]) = [(u_ref - u)^T A (u_ref - u), u_ref^T A u_ref]
+ * over the free DoFs, so e_a = sqrt(out[0] / out[1]). */
+int msgfem_coarse_energy(msgfem_coarse *coarse, void *pcg, const double *u_ref, const double *u, double *out,
+                         void *stream);
+
 /* Kernel timing.  msgfem_profile(plan, 1) clears the counters and starts
  * recording a pair of HIP events around every launch of the library's hot
  * kernels on the stream the kernel is launched on; msgfem_profile(plan, 0)

@@ -58,6 +58,7 @@ __global__ void k_residual(const BoxMeta*, const uint8_t*, int, int, double, con
 __global__ void k_converge(const BoxMeta*, int, int, int, const double*, const double*, double, double*,
                            int32_t*, int32_t*, int32_t*, int, int32_t*);
 __global__ void k_status_clear(int, const int32_t*, int32_t*);
+__global__ void k_status_or(int32_t*, int, int32_t);
 __global__ void k_copy_masked_i32(int, const int32_t*, const int32_t*, int32_t*);
 __global__ void k_random_start(const BoxMeta*, const uint8_t*, int, int, uint64_t, double*);
 __global__ void k_lock(const BoxMeta*, int, const double*, double, double*, double*, double*, double*, double*,
@@ -89,7 +90,14 @@ __global__ void k_coarse_pairs(const BoxMeta*, const CoarsePair*, int, const dou
 __global__ void k_coarse_rhs(const BoxMeta*, int, const double*, const double*, const int32_t*,
                              const int32_t*, int, const double*, double*, double*);
 __global__ void k_dense_tiles(const double*, int, int, double*);
-__global__ void k_dense_tile_solve(const double*, int, int, const double*, double*, double*);
+__global__ void k_trsv_init(const double*, int, int, double*);
+__global__ void k_trsv_fwd(const double*, int, int, double*);
+__global__ void k_trsv_diag(const double*, int, const double*, double*);
+__global__ void k_trsv_bwd(const double*, int, int, double*);
+__global__ void k_store_box(const BoxMeta*, const BoxMeta*, int, int, const double*, const double*, const double*,
+                            const double*, const double*, const uint8_t*, double*, double*, double*, double*,
+                            double*, uint8_t*);
+__global__ void k_store_local32(const BoxMeta*, const BoxMeta*, const double*, float*);
 __global__ void k_prolong(const BoxMeta*, MeshDev, int, const double*, const double*, const double*,
                           const int32_t*, double*, double*);
 __global__ void k_gather_boxes(const BoxMeta*, MeshDev, const uint8_t*, const double*, double*);
@@ -242,6 +250,48 @@ static void band_geom(int sx, int sy, int sz, int* n, int* nt, int* bt) {
   if (*bt > *nt) *bt = *nt;
 }
 
+// Geometry of the box of subdomain sd (Omega_j^*, or Omega_j for GenEO): node
+// box, Omega_j, interior-face flags, the node sub-box of B1 and the band
+// geometry of its two matrices.  Offsets are left zero.  omega: [nsd][6] node
+// boxes of Omega_j.  Returns an error message or nullptr.
+static const char* box_geometry(const int N[3], const msgfem_decomp* dec, const int32_t* omega, bool geneo, int sd,
+                                int n_ev, BoxMeta& m) {
+  std::memset(&m, 0, sizeof m);
+  m.sd = sd;
+  const int32_t* c = dec->cores + 6 * sd;
+  int g = dec->overlap + (geneo ? 0 : dec->ovs[sd]);   // GenEO works on Omega_j itself
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = std::max(c[d] - g, 0);
+    hi[d] = std::min(c[3 + d] + g, N[d]);
+    m.g0[d] = lo[d];
+    m.olo[d] = omega[6 * sd + d];
+    m.ohi[d] = omega[6 * sd + 3 + d];
+    m.olo_int[d] = m.olo[d] > 0;
+    m.ohi_int[d] = m.ohi[d] < N[d];
+    m.iface_lo[d] = lo[d] > 0;
+    m.iface_hi[d] = hi[d] < N[d];
+  }
+  m.mx = hi[0] - lo[0] + 1;
+  m.my = hi[1] - lo[1] + 1;
+  m.mz = hi[2] - lo[2] + 1;
+  int mm[3] = {m.mx, m.my, m.mz};
+  for (int d = 0; d < 3; ++d) {
+    m.sub_lo[d] = m.iface_lo[d] ? 1 : 0;
+    m.sub_hi[d] = mm[d] - 1 - (m.iface_hi[d] ? 1 : 0);
+    if (m.sub_hi[d] < m.sub_lo[d] || mm[d] < 3) return "box too thin for an interior block";
+  }
+  if (!(m.iface_lo[0] || m.iface_hi[0] || m.iface_lo[1] || m.iface_hi[1] || m.iface_lo[2] || m.iface_hi[2]))
+    return "oversampling box covers the whole mesh (B2 empty)";
+  m.n_nodes = m.mx * m.my * m.mz;
+  m.n_dof = 3 * m.n_nodes;
+  m.n_ev = n_ev;
+  band_geom(m.sub_hi[0] - m.sub_lo[0] + 1, m.sub_hi[1] - m.sub_lo[1] + 1, m.sub_hi[2] - m.sub_lo[2] + 1, &m.n11,
+            &m.nt11, &m.bt11);
+  band_geom(m.mx, m.my, m.mz, &m.nh, &m.nth, &m.bth);
+  return nullptr;
+}
+
 extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_mesh* mesh,
                                   const msgfem_decomp* dec, const int32_t* batch,
                                   const int32_t* n_ev, int32_t nb,
@@ -307,40 +357,8 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     if (n_ev[b] < 1) return fail(p, MSGFEM_EARG, "n_ev[%d] < 1", b);
     if (dec->ovs[sd] < 0) return fail(p, MSGFEM_EARG, "ovs[%d] < 0", sd);
     BoxMeta m;
-    std::memset(&m, 0, sizeof m);
-    m.sd = sd;
-    const int32_t* c = dec->cores + 6 * sd;
-    int g = dec->overlap + (o.geneo ? 0 : dec->ovs[sd]);   // GenEO works on Omega_j itself
-    int lo[3], hi[3];
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = std::max(c[d] - g, 0);
-      hi[d] = std::min(c[3 + d] + g, N[d]);
-      m.g0[d] = lo[d];
-      m.olo[d] = p->omega[6 * sd + d];
-      m.ohi[d] = p->omega[6 * sd + 3 + d];
-      m.olo_int[d] = m.olo[d] > 0;
-      m.ohi_int[d] = m.ohi[d] < N[d];
-      m.iface_lo[d] = lo[d] > 0;
-      m.iface_hi[d] = hi[d] < N[d];
-    }
-    m.mx = hi[0] - lo[0] + 1;
-    m.my = hi[1] - lo[1] + 1;
-    m.mz = hi[2] - lo[2] + 1;
-    int mm[3] = {m.mx, m.my, m.mz};
-    for (int d = 0; d < 3; ++d) {
-      m.sub_lo[d] = m.iface_lo[d] ? 1 : 0;
-      m.sub_hi[d] = mm[d] - 1 - (m.iface_hi[d] ? 1 : 0);
-      if (m.sub_hi[d] < m.sub_lo[d] || mm[d] < 3)
-        return fail(p, MSGFEM_EARG, "subdomain %d: box too thin for an interior block", sd);
-    }
-    if (!(m.iface_lo[0] || m.iface_hi[0] || m.iface_lo[1] || m.iface_hi[1] || m.iface_lo[2] || m.iface_hi[2]))
-      return fail(p, MSGFEM_EARG, "subdomain %d: oversampling box covers the whole mesh (B2 empty)", sd);
-    m.n_nodes = m.mx * m.my * m.mz;
-    m.n_dof = 3 * m.n_nodes;
-    m.n_ev = n_ev[b];
-    band_geom(m.sub_hi[0] - m.sub_lo[0] + 1, m.sub_hi[1] - m.sub_lo[1] + 1,
-              m.sub_hi[2] - m.sub_lo[2] + 1, &m.n11, &m.nt11, &m.bt11);
-    band_geom(m.mx, m.my, m.mz, &m.nh, &m.nth, &m.bth);
+    if (const char* e = box_geometry(N, dec, p->omega.data(), o.geneo != 0, sd, n_ev[b], m))
+      return fail(p, MSGFEM_EARG, "subdomain %d: %s", sd, e);
     m.node_off = node_off;
     m.dof_off = dof_off;
     m.vec_off = vec_off;
@@ -574,6 +592,17 @@ static int tile_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_
   k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
   LAUNCHCHK(p);
   return 0;
+}
+
+// Single-RHS solve with the dense unit-lower tile factor (BT = NT): x = A^{-1} b
+// (b of length NH, y and x of NT*32 doubles) by column launches over many
+// workgroups (k_trsv_*).
+static int tile_trsv(const double* T, int NT, int NH, const double* b, double* y, double* x, hipStream_t s) {
+  k_trsv_init<<<(NT * 32 + 255) / 256, 256, 0, s>>>(b, NH, NT * 32, y);
+  for (int J = 0; J < NT - 1; ++J) k_trsv_fwd<<<NT - 1 - J, 256, 0, s>>>(T, NT, J, y);
+  k_trsv_diag<<<NT, 256, 0, s>>>(T, NT, y, x);
+  for (int J = NT - 1; J >= 1; --J) k_trsv_bwd<<<J, 256, 0, s>>>(T, NT, J, x);
+  return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
 // Left-looking tile Cholesky of banded SPD matrices, one launch per tile
@@ -1566,8 +1595,7 @@ extern "C" int msgfem_coarse_solve(msgfem_plan* p, const void* ops, void* work, 
   if (tile_cholesky(p, (const MatDesc*)(cb + p->c_mat), 1, NT, NT, tiles, status, s)) return MSGFEM_EHIP;
   double* ysc = (double*)(cb + p->c_y);
   double* xsc = ysc + (int64_t)NT * 32;
-  k_dense_tile_solve<<<1, 256, 0, s>>>(tiles, NT, NH, bH, ysc, xsc);
-  LAUNCHCHK(p);
+  if (tile_trsv(tiles, NT, NH, bH, ysc, xsc, s)) return fail(p, MSGFEM_EHIP, "coarse triangular solve launch failed");
   HIPCHK(p, hipMemcpyAsync(cvec, xsc, (size_t)NH * 8, hipMemcpyDeviceToDevice, s));
   // u^G = u^p + V c on the global mesh
   const int64_t ng = 3 * p->n_nodes_global;
@@ -1708,7 +1736,7 @@ extern "C" int msgfem_geneo_pcg(msgfem_plan* p, const void* ops, void* work, voi
     k_scatter_boxes<<<dim3((p->max_dof + 255) / 256, nb), 256, 0, s>>>(v.meta, md, v.cls, zb, zout);
     k_coarse_restrict<<<nb, 256, 0, s>>>(v.meta, k, (const double*)(cb + p->c_V), rb,
                                          (const int32_t*)(cb + p->c_roff), rc);
-    k_dense_tile_solve<<<1, 256, 0, s>>>(tiles, NT, NH, rc, ysc, xsc);
+    if (tile_trsv(tiles, NT, NH, rc, ysc, xsc, s)) return MSGFEM_EHIP;
     k_prolong<<<dim3((p->max_dof + 255) / 256, nb), 256, 0, s>>>(v.meta, md, k, (const double*)(cb + p->c_V), zero,
                                                                  xsc, (const int32_t*)(cb + p->c_roff), zout,
                                                                  nullptr);
@@ -1751,9 +1779,610 @@ extern "C" int msgfem_geneo_pcg(msgfem_plan* p, const void* ops, void* work, voi
   *iters = it;
   *relres = rel;
   if (rel > rtol) {
-    int32_t one = 1;
-    HIPCHK(p, hipMemcpy(status, &one, 4, hipMemcpyHostToDevice));
+    k_status_or<<<1, 32, 0, s>>>(status, 1, 1);
+    LAUNCHCHK(p);
+    HIPCHK(p, hipStreamSynchronize(s));
   }
+  return MSGFEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Coarse problem gathered from several plans (the local stage streamed
+// through plans that hold only part of the subdomains at a time)
+
+struct msgfem_coarse {
+  int device = 0;
+  msgfem_mesh mesh{};
+  int nsd = 0, overlap = 0, geneo = 0, kc = 0, NH = 0, NTc = 0;
+  int64_t n_nodes_global = 0, dofs_total = 0, loc_total = 0;
+  int max_dof = 0, max_nt11 = 0, max_bt11 = 0;
+  bool loc_solve4 = false;          // layout of the exported local solves (GenEO)
+  std::vector<int32_t> omega;       // [nsd][6] node boxes of Omega_j
+  std::vector<int32_t> cores, ovs;
+  std::vector<BoxMeta> meta;        // every subdomain, in subdomain order
+  std::vector<CoarsePair> pairs;
+  std::vector<int32_t> pair_start, row_off;
+  std::vector<uint8_t> added;
+  int64_t s_meta = 0, s_pairs = 0, s_pstart = 0, s_roff = 0, s_mat = 0, s_faces = 0, s_cls = 0, s_V = 0, s_AV = 0,
+          s_pv = 0, s_Ap = 0, s_bload = 0, s_rpart = 0, s_rc = 0, s_tiles = 0, s_y = 0, s_loc = 0, store_bytes = 0;
+  std::string err;
+};
+
+static int cfail(msgfem_coarse* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define CHIPCHK(c, call)                                                                   \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return cfail(c, MSGFEM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CLAUNCHCHK(c)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = hipGetLastError();                                                     \
+    if (e_ != hipSuccess)                                                                  \
+      return cfail(c, MSGFEM_EHIP, "launch failed (line %d): %s", __LINE__, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" int msgfem_coarse_create(msgfem_coarse** out, int device, const msgfem_mesh* mesh,
+                                    const msgfem_decomp* dec, const int32_t* n_ev, int32_t geneo) {
+  if (!out || !mesh || !dec || !n_ev) return MSGFEM_EARG;
+  msgfem_coarse* c = new msgfem_coarse();
+  *out = c;
+  c->device = device;
+  c->mesh = *mesh;
+  c->nsd = dec->nsd;
+  c->overlap = dec->overlap;
+  c->geneo = geneo != 0;
+  if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1 || mesh->n_mat < 1) return cfail(c, MSGFEM_EARG, "bad mesh dimensions");
+  if (dec->nsd < 1 || !dec->cores || !dec->ovs || dec->overlap < 1)
+    return cfail(c, MSGFEM_EARG, "bad decomposition (nsd >= 1, overlap >= 1 required)");
+  const int N[3] = {mesh->nx, mesh->ny, mesh->nz};
+  c->n_nodes_global = (int64_t)(N[0] + 1) * (N[1] + 1) * (N[2] + 1);
+  c->cores.assign(dec->cores, dec->cores + 6 * (size_t)dec->nsd);
+  c->ovs.assign(dec->ovs, dec->ovs + dec->nsd);
+  c->omega.resize(6 * (size_t)dec->nsd);
+  for (int j = 0; j < dec->nsd; ++j) {
+    const int32_t* cr = dec->cores + 6 * j;
+    for (int d = 0; d < 3; ++d) {
+      if (cr[d] < 0 || cr[3 + d] > N[d] || cr[d] >= cr[3 + d]) return cfail(c, MSGFEM_EARG, "core %d out of the mesh", j);
+      c->omega[6 * j + d] = std::max(cr[d] - dec->overlap, 0);
+      c->omega[6 * j + 3 + d] = std::min(cr[3 + d] + dec->overlap, N[d]);
+    }
+    if (dec->ovs[j] < 0) return cfail(c, MSGFEM_EARG, "ovs[%d] < 0", j);
+    if (n_ev[j] < 1 || n_ev[j] > 32) return cfail(c, MSGFEM_EARG, "n_ev[%d] = %d outside [1, 32]", j, n_ev[j]);
+  }
+  c->meta.resize(dec->nsd);
+  int64_t dof_off = 0, node_off = 0, loc_off = 0;
+  int kc = 0;
+  for (int j = 0; j < dec->nsd; ++j) {
+    BoxMeta& m = c->meta[j];
+    if (const char* e = box_geometry(N, dec, c->omega.data(), c->geneo, j, n_ev[j], m))
+      return cfail(c, MSGFEM_EARG, "subdomain %d: %s", j, e);
+    m.node_off = node_off;
+    m.dof_off = dof_off;
+    m.eval_off = c->NH;
+    if (c->geneo) {
+      m.f11_fw = loc_off;
+      loc_off += solve_copy_doubles(m.nt11, m.bt11);
+      m.f11_bw = loc_off;
+      loc_off += solve_copy_doubles(m.nt11, m.bt11);
+      m.f11i_off = loc_off;            // D^{-1} tiles, compact
+      loc_off += (int64_t)m.nt11 * MSG_TILE2;
+      m.flags |= BOX_COMPACT_DINV;
+    }
+    node_off += m.n_nodes;
+    dof_off += m.n_dof;
+    c->NH += m.n_ev;
+    kc = std::max(kc, m.n_ev);
+    c->max_dof = std::max(c->max_dof, m.n_dof);
+    c->max_nt11 = std::max(c->max_nt11, m.nt11);
+    c->max_bt11 = std::max(c->max_bt11, m.bt11);
+  }
+  c->kc = kc + (kc & 1);
+  c->dofs_total = dof_off;
+  c->loc_total = loc_off;
+  c->NTc = (c->NH + 31) / 32;
+  c->loc_solve4 = c->max_bt11 - 1 <= 8 * SOLVE4_MAX_SLOTS;
+  if (c->geneo && c->max_bt11 > SOLVE_MAX_BT)
+    return cfail(c, MSGFEM_ESIZE, "band of %d tiles too wide for the block solve", c->max_bt11);
+  // pairs (i, j): Omega_i meets the box of j (the support of A V_j)
+  c->row_off.assign(c->nsd, 0);
+  c->pair_start.assign(c->nsd + 1, 0);
+  for (int i = 0; i < c->nsd; ++i) c->row_off[i] = (int)c->meta[i].eval_off;
+  for (int i = 0; i < c->nsd; ++i) {
+    c->pair_start[i] = (int)c->pairs.size();
+    const BoxMeta& bi = c->meta[i];
+    for (int j = 0; j < c->nsd; ++j) {
+      const BoxMeta& bj = c->meta[j];
+      CoarsePair pr;
+      bool ok = true;
+      for (int d = 0; d < 3; ++d) {
+        int jlo = bj.g0[d], jhi = bj.g0[d] + (d == 0 ? bj.mx : d == 1 ? bj.my : bj.mz) - 1;
+        pr.lo[d] = std::max(bi.olo[d], jlo);
+        pr.hi[d] = std::min(bi.ohi[d], jhi);
+        if (pr.lo[d] > pr.hi[d]) ok = false;
+      }
+      if (!ok) continue;
+      pr.i = i;
+      pr.j = j;
+      pr.row_off = c->row_off[i];
+      pr.col_off = c->row_off[j];
+      c->pairs.push_back(pr);
+    }
+  }
+  c->pair_start[c->nsd] = (int)c->pairs.size();
+  c->added.assign(c->nsd, 0);
+  const int64_t nd = c->dofs_total, np = (int64_t)c->pairs.size(), K = c->kc;
+  int64_t off = 0;
+  c->s_meta = off; off = align256(off + (int64_t)c->nsd * sizeof(BoxMeta));
+  c->s_pairs = off; off = align256(off + np * sizeof(CoarsePair));
+  c->s_pstart = off; off = align256(off + (c->nsd + 1) * 4);
+  c->s_roff = off; off = align256(off + c->nsd * 4);
+  c->s_mat = off; off = align256(off + sizeof(MatDesc));
+  c->s_faces = off; off = align256(off + 6 * sizeof(FaceLoad));
+  c->s_cls = off; off = align256(off + nd);
+  c->s_V = off; off = align256(off + nd * K * 8);
+  c->s_AV = off; off = align256(off + nd * K * 8);
+  c->s_pv = off; off = align256(off + nd * 8);
+  c->s_Ap = off; off = align256(off + nd * 8);
+  c->s_bload = off; off = align256(off + nd * 8);
+  c->s_rpart = off; off = align256(off + np * 32 * 8);
+  c->s_rc = off; off = align256(off + (int64_t)c->NTc * 32 * 8);
+  c->s_tiles = off; off = align256(off + ((int64_t)c->NTc * c->NTc + c->NTc) * 1024 * 8);
+  c->s_y = off; off = align256(off + 2 * (int64_t)c->NTc * 32 * 8);
+  c->s_loc = off; off = align256(off + c->loc_total * 4);
+  c->store_bytes = off;
+  return MSGFEM_OK;
+}
+
+extern "C" void msgfem_coarse_destroy(msgfem_coarse* c) { delete c; }
+
+extern "C" const char* msgfem_coarse_error(const msgfem_coarse* c) { return c ? c->err.c_str() : "null coarse object"; }
+
+extern "C" int msgfem_coarse_store_sizes(const msgfem_coarse* c, int64_t* store_bytes, int32_t* n_coarse,
+                                         int32_t* n_columns) {
+  if (!c || !store_bytes || !n_coarse) return MSGFEM_EARG;
+  *store_bytes = c->store_bytes;
+  *n_coarse = c->NH;
+  if (n_columns) *n_columns = c->kc;
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_coarse_box(const msgfem_coarse* c, int32_t sd, int64_t* dof_off, int32_t* n_dof,
+                                 int32_t* row_off) {
+  if (!c || sd < 0 || sd >= c->nsd) return MSGFEM_EARG;
+  if (dof_off) *dof_off = c->meta[sd].dof_off;
+  if (n_dof) *n_dof = c->meta[sd].n_dof;
+  if (row_off) *row_off = c->row_off[sd];
+  return MSGFEM_OK;
+}
+
+static int coarse_upload_tables(msgfem_coarse* c, char* st, hipStream_t s) {
+  CHIPCHK(c, hipMemcpyAsync(st + c->s_meta, c->meta.data(), c->meta.size() * sizeof(BoxMeta), hipMemcpyHostToDevice, s));
+  if (!c->pairs.empty())
+    CHIPCHK(c, hipMemcpyAsync(st + c->s_pairs, c->pairs.data(), c->pairs.size() * sizeof(CoarsePair),
+                              hipMemcpyHostToDevice, s));
+  CHIPCHK(c, hipMemcpyAsync(st + c->s_pstart, c->pair_start.data(), c->pair_start.size() * 4, hipMemcpyHostToDevice, s));
+  CHIPCHK(c, hipMemcpyAsync(st + c->s_roff, c->row_off.data(), c->row_off.size() * 4, hipMemcpyHostToDevice, s));
+  return MSGFEM_OK;
+}
+
+static int load_faces(const msgfem_load* load, std::vector<FaceLoad>& faces) {
+  faces.clear();
+  if (!load) return 0;
+  if (load->n < 0 || load->n > 6 || (load->n > 0 && (!load->face || !load->g))) return 1;
+  for (int f = 0; f < load->n; ++f) {
+    const int fc = load->face[f];
+    if (fc < 0 || fc > 5) return 1;
+    FaceLoad fl;
+    fl.axis = fc / 2;
+    fl.side = fc % 2;
+    for (int q = 0; q < 3; ++q) fl.g[q] = load->g[3 * f + q];
+    faces.push_back(fl);
+  }
+  return 0;
+}
+
+extern "C" int msgfem_coarse_add(msgfem_coarse* c, msgfem_plan* p, const void* ops, void* work,
+                                 const msgfem_load* load, const double* evecs, void* store, void* stream) {
+  if (!c || !p || !ops || !work || !evecs || !store) return cfail(c, MSGFEM_EARG, "null argument");
+  if (p->device != c->device) return cfail(c, MSGFEM_EARG, "the plan is on device %d, the coarse object on %d",
+                                           p->device, c->device);
+  if (p->mesh.nx != c->mesh.nx || p->mesh.ny != c->mesh.ny || p->mesh.nz != c->mesh.nz || p->nsd != c->nsd ||
+      p->overlap != c->overlap || (p->opts.geneo != 0) != (c->geneo != 0))
+    return cfail(c, MSGFEM_EARG, "the plan's mesh, decomposition or eigenproblem differs from the coarse object's");
+  for (const BoxMeta& m : p->meta) {
+    const BoxMeta& t = c->meta[m.sd];
+    if (m.mx != t.mx || m.my != t.my || m.mz != t.mz || m.g0[0] != t.g0[0] || m.g0[1] != t.g0[1] ||
+        m.g0[2] != t.g0[2] || m.n_ev != t.n_ev)
+      return cfail(c, MSGFEM_EARG, "subdomain %d has another box or n_ev in the plan", m.sd);
+  }
+  if (c->geneo && solve4_kind(p, 0) != c->loc_solve4)
+    return cfail(c, MSGFEM_EARG,
+                 "the plan's interior factors use the %s solve layout, the coarse object the %s one (give the plan "
+                 "a box with the widest band)",
+                 solve4_kind(p, 0) ? "matrix-core" : "vector", c->loc_solve4 ? "matrix-core" : "vector");
+  std::vector<FaceLoad> faces;
+  if (load_faces(load, faces)) return cfail(c, MSGFEM_EARG, "bad load description");
+  if (set_device(p)) return cfail(c, MSGFEM_EHIP, "%s", p->err.c_str());
+  hipStream_t s = (hipStream_t)stream;
+  char* st = (char*)store;
+  if (int rc = coarse_upload_tables(c, st, s)) return rc;
+  if (!faces.empty())
+    CHIPCHK(c, hipMemcpyAsync(st + c->s_faces, faces.data(), faces.size() * sizeof(FaceLoad), hipMemcpyHostToDevice, s));
+  // the host copies above must stay valid until the copies are done (faces is local)
+  CHIPCHK(c, hipStreamSynchronize(s));
+  Ctx x;
+  x.p = p;
+  x.v = ops_view(p, ops);
+  x.w = work_view(p, work);
+  x.s = s;
+  x.nb = (int)p->meta.size();
+  x.k = p->k;
+  const int k = p->k, nb = x.nb;
+  const int64_t VT = p->vec_total, nd = p->dofs_total;
+  double* V = x.w.vec;
+  double* Vn = x.w.vec + VT;
+  double* AV = x.w.vec + 2 * VT;
+  double* psi = x.w.vec + 3 * VT;
+  double* pv = psi + nd;
+  double* Ap = psi + 2 * nd;
+  double* bload = psi + 3 * nd;
+  MeshDev mdv = mesh_dev(p);
+  k_box_load<<<dim3((p->max_nodes + 255) / 256, nb), 256, 0, s>>>(x.v.meta, mdv, (const FaceLoad*)(st + c->s_faces),
+                                                                 (int)faces.size(), bload);
+  CLAUNCHCHK(c);
+  if (solve(x, 0, bload, psi, 1, 1 << 1, 1, nullptr)) return cfail(c, MSGFEM_EHIP, "%s", p->err.c_str());
+  k_coarse_basis<<<dim3((unsigned)(((int64_t)p->max_dof * k + 255) / 256), nb), 256, 0, s>>>(x.v.meta, k, x.v.mu1, evecs,
+                                                                                          psi, V, pv);
+  CLAUNCHCHK(c);
+  for (int pass = 0; pass < 2; ++pass) {
+    Blk3 Z, A, B;
+    Z.p[0] = A.p[0] = B.p[0] = V;
+    Z.p[1] = Z.p[2] = A.p[1] = A.p[2] = B.p[1] = B.p[2] = nullptr;
+    auto kern = k <= 32 ? k_gram_partial<2> : (k <= 64 ? k_gram_partial<4> : k_gram_partial<6>);
+    kern<<<dim3(p->n_gchunk, nb, 2), 256, (size_t)k * k * 8, s>>>(x.v.meta, 1, Z, A, B, k, GRAM_ROWS, p->n_gchunk,
+                                                                  x.w.part, nullptr);
+    k_gram_reduce<<<dim3((2 * k * k + 255) / 256, nb), 256, 0, s>>>(k, p->n_gchunk, x.w.part, x.w.G, nullptr);
+    k_cholqr_coef<<<nb, 256, (size_t)(k * (k + 1) + k) * 8, s>>>(k, x.w.G, x.w.Y);
+    Blk4x3 Zu;
+    Out4 OX, OP;
+    for (int kind = 0; kind < 4; ++kind) {
+      Zu.p[kind][0] = Zu.p[kind][1] = Zu.p[kind][2] = nullptr;
+      OX.p[kind] = OP.p[kind] = nullptr;
+    }
+    Zu.p[0][0] = V;
+    OX.p[0] = Vn;
+    k_update<<<dim3((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, 1), UPD_THREADS, (size_t)2 * k * k * 8, s>>>(
+        x.v.meta, 1, k, Zu, OX, OP, x.w.Y, x.w.Yp, nullptr);
+    CLAUNCHCHK(c);
+    std::swap(V, Vn);
+  }
+  if (spmm(x, V, AV, nullptr, k, (1 << 1) | (1 << 2), 1.0, nullptr)) return cfail(c, MSGFEM_EHIP, "%s", p->err.c_str());
+  if (spmm(x, pv, Ap, nullptr, 1, (1 << 1) | (1 << 2), 1.0, nullptr)) return cfail(c, MSGFEM_EHIP, "%s", p->err.c_str());
+  const int K = c->kc;
+  k_store_box<<<dim3((unsigned)(((int64_t)p->max_dof * K + 255) / 256), nb), 256, 0, s>>>(
+      x.v.meta, (const BoxMeta*)(st + c->s_meta), k, K, V, AV, pv, Ap, bload, x.v.cls, (double*)(st + c->s_V),
+      (double*)(st + c->s_AV), (double*)(st + c->s_pv), (double*)(st + c->s_Ap), (double*)(st + c->s_bload),
+      (uint8_t*)(st + c->s_cls));
+  CLAUNCHCHK(c);
+  if (c->geneo) {
+    k_store_local32<<<dim3(2048, nb), 256, 0, s>>>(x.v.meta, (const BoxMeta*)(st + c->s_meta), x.v.fac,
+                                                   (float*)(st + c->s_loc));
+    CLAUNCHCHK(c);
+  }
+  for (const BoxMeta& m : p->meta) c->added[m.sd] = 1;
+  return MSGFEM_OK;
+}
+
+static int coarse_all_added(msgfem_coarse* c) {
+  for (int j = 0; j < c->nsd; ++j)
+    if (!c->added[j]) return cfail(c, MSGFEM_EARG, "subdomain %d has not been added to the coarse store", j);
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_coarse_galerkin(msgfem_coarse* c, void* store, double* AH, double* bH, void* stream) {
+  if (!c || !store || !AH || !bH) return cfail(c, MSGFEM_EARG, "null argument");
+  if (int rc = coarse_all_added(c)) return rc;
+  CHIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  char* st = (char*)store;
+  if (int rc = coarse_upload_tables(c, st, s)) return rc;
+  const int NH = c->NH;
+  k_fill_f64<<<4096, 256, 0, s>>>(AH, (int64_t)NH * NH, 0.0);
+  if (!c->pairs.empty())
+    k_coarse_pairs<<<(unsigned)c->pairs.size(), 256, 0, s>>>((const BoxMeta*)(st + c->s_meta),
+                                                             (const CoarsePair*)(st + c->s_pairs), c->kc,
+                                                             (const double*)(st + c->s_V), (const double*)(st + c->s_AV),
+                                                             (const double*)(st + c->s_Ap), NH, AH,
+                                                             (double*)(st + c->s_rpart));
+  k_coarse_rhs<<<c->nsd, 256, 0, s>>>((const BoxMeta*)(st + c->s_meta), c->kc, (const double*)(st + c->s_V),
+                                      (const double*)(st + c->s_bload), (const int32_t*)(st + c->s_pstart),
+                                      (const int32_t*)(st + c->s_roff), NH, (const double*)(st + c->s_rpart), AH, bH);
+  CLAUNCHCHK(c);
+  return MSGFEM_OK;
+}
+
+// tile Cholesky of the dense coarse matrix into the store's tiles
+static int coarse_factor(msgfem_coarse* c, char* st, const double* AH, int32_t* status, hipStream_t s) {
+  const int NT = c->NTc;
+  MatDesc md{NT, NT, 0, 0, 0, (int64_t)NT * NT * 1024};
+  CHIPCHK(c, hipMemcpyAsync(st + c->s_mat, &md, sizeof md, hipMemcpyHostToDevice, s));
+  CHIPCHK(c, hipStreamSynchronize(s));
+  double* tiles = (double*)(st + c->s_tiles);
+  k_fill_i32<<<1, 32, 0, s>>>(status, 1, 0);
+  k_dense_tiles<<<4096, 256, 0, s>>>(AH, c->NH, NT, tiles);
+  CLAUNCHCHK(c);
+  if (tile_cholesky(nullptr, (const MatDesc*)(st + c->s_mat), 1, NT, NT, tiles, status, s))
+    return cfail(c, MSGFEM_EHIP, "coarse Cholesky launch failed");
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_coarse_solve_store(msgfem_coarse* c, void* store, const double* AH, const double* bH, double* cvec,
+                                         double* uG, double* up, int32_t* status, void* stream) {
+  if (!c || !store || !AH || !bH || !cvec || !uG || !status) return cfail(c, MSGFEM_EARG, "null argument");
+  if (int rc = coarse_all_added(c)) return rc;
+  CHIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  char* st = (char*)store;
+  if (int rc = coarse_upload_tables(c, st, s)) return rc;
+  if (int rc = coarse_factor(c, st, AH, status, s)) return rc;
+  const int NT = c->NTc;
+  double* ysc = (double*)(st + c->s_y);
+  double* xsc = ysc + (int64_t)NT * 32;
+  if (tile_trsv((const double*)(st + c->s_tiles), NT, c->NH, bH, ysc, xsc, s))
+    return cfail(c, MSGFEM_EHIP, "coarse triangular solve launch failed");
+  CHIPCHK(c, hipMemcpyAsync(cvec, xsc, (size_t)c->NH * 8, hipMemcpyDeviceToDevice, s));
+  const int64_t ng = 3 * c->n_nodes_global;
+  k_fill_f64<<<1024, 256, 0, s>>>(uG, ng, 0.0);
+  if (up) k_fill_f64<<<1024, 256, 0, s>>>(up, ng, 0.0);
+  MeshDev md;
+  md.nx = c->mesh.nx; md.ny = c->mesh.ny; md.nz = c->mesh.nz; md.n_mat = c->mesh.n_mat;
+  md.xyz = c->mesh.node_xyz; md.elem_mat = c->mesh.elem_mat; md.materials = c->mesh.materials;
+  md.dirichlet = c->mesh.dirichlet;
+  k_prolong<<<dim3((c->max_dof + 255) / 256, c->nsd), 256, 0, s>>>((const BoxMeta*)(st + c->s_meta), md, c->kc,
+                                                                   (const double*)(st + c->s_V),
+                                                                   (const double*)(st + c->s_pv), cvec,
+                                                                   (const int32_t*)(st + c->s_roff), uG, up);
+  CLAUNCHCHK(c);
+  return MSGFEM_OK;
+}
+
+// Block solve of kind `kind` on FP32 factor copies for a box list given only
+// on the device (no plan): the store-based PCG's local Dirichlet solves.
+static int solve_f32(hipStream_t s, const BoxMeta* meta, int nb, int max_bt, bool use4, int kind, const float* ft,
+                     const uint8_t* cls, const double* in, double* out, int kk, int out_classes, int zero_rest,
+                     double* scr, int64_t scr_stride) {
+  const int nchunk = (kk + KC - 1) / KC;
+  dim3 grid(8 * nchunk * ((nb + 7) / 8));
+  const size_t lds = (size_t)max_bt * 32 * KC * 8;
+  auto launch = [&](auto kern) {
+    kern<<<grid, 512, lds, s>>>(meta, nb, nchunk, kind, ft, cls, in, out, kk, out_classes, zero_rest, scr, scr_stride,
+                                nullptr);
+  };
+  if (use4) {
+    const int ns = solve4_nslot(max_bt);
+    if (ns <= 1) launch(k_band_solve4<1, float>);
+    else if (ns == 2) launch(k_band_solve4<2, float>);
+    else if (ns == 3) launch(k_band_solve4<3, float>);
+    else launch(k_band_solve4<4, float>);
+  } else if (max_bt - 1 > SOLVE_TILES) {
+    launch(k_band_solve<KC, 2, float>);
+  } else {
+    launch(k_band_solve<KC, 1, float>);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+namespace {
+struct CPcgLayout {
+  int64_t meta, ctab, omega, wtot, stencil, cls, mu, b, x, r, z, p, q, rb, zb, zero, part, sc, scr, total;
+  int64_t scr_stride;
+};
+}  // namespace
+
+static CPcgLayout cpcg_layout(const msgfem_coarse* c) {
+  CPcgLayout L;
+  const int64_t ng = c->n_nodes_global, nd = 3 * ng, nbd = c->dofs_total;
+  L.scr_stride = (int64_t)(c->max_nt11 + 1) * 32 * KC;
+  int64_t off = 0;
+  L.meta = off; off = align256(off + sizeof(BoxMeta));
+  L.ctab = off; off = align256(off + (int64_t)c->mesh.n_mat * 36 * 8);
+  L.omega = off; off = align256(off + (int64_t)c->nsd * 6 * 4);
+  L.wtot = off; off = align256(off + ng * 4);
+  L.stencil = off; off = align256(off + ng * 243 * 8);
+  L.cls = off; off = align256(off + nd);
+  L.mu = off; off = align256(off + nd * 8);
+  L.b = off; off = align256(off + nd * 8);
+  L.x = off; off = align256(off + nd * 8);
+  L.r = off; off = align256(off + nd * 8);
+  L.z = off; off = align256(off + nd * 8);
+  L.p = off; off = align256(off + nd * 8);
+  L.q = off; off = align256(off + nd * 8);
+  L.rb = off; off = align256(off + nbd * 8);
+  L.zb = off; off = align256(off + nbd * 8);
+  L.zero = off; off = align256(off + nbd * 8);
+  L.part = off; off = align256(off + 1024 * 8);
+  L.sc = off; off = align256(off + 16 * 8);
+  L.scr = off; off = align256(off + (int64_t)c->nsd * L.scr_stride * 8);
+  L.total = off;
+  return L;
+}
+
+extern "C" int msgfem_coarse_pcg_sizes(const msgfem_coarse* c, int64_t* bytes) {
+  if (!c || !bytes) return MSGFEM_EARG;
+  *bytes = cpcg_layout(c).total;
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_coarse_pcg(msgfem_coarse* c, void* store, const double* A0, const msgfem_load* load, double rtol,
+                                 int32_t maxit, void* pcg, double* u, int32_t* iters, double* relres, int32_t* status,
+                                 void* stream) {
+  if (!c || !store || !A0 || !pcg || !u || !iters || !relres || !status) return cfail(c, MSGFEM_EARG, "null argument");
+  if (!c->geneo) return cfail(c, MSGFEM_EARG, "msgfem_coarse_pcg needs a GenEO coarse object (geneo = 1)");
+  if (!(rtol > 0) || maxit < 1) return cfail(c, MSGFEM_EARG, "bad rtol / maxit");
+  if (int rc = coarse_all_added(c)) return rc;
+  std::vector<FaceLoad> faces;
+  if (load_faces(load, faces)) return cfail(c, MSGFEM_EARG, "bad load description");
+  CHIPCHK(c, hipSetDevice(c->device));
+  lds_attributes();
+  hipStream_t s = (hipStream_t)stream;
+  char* st = (char*)store;
+  char* pb = (char*)pcg;
+  const CPcgLayout L = cpcg_layout(c);
+  const int nsd = c->nsd, K = c->kc, NT = c->NTc, NH = c->NH;
+  const int64_t ng = c->n_nodes_global, nd = 3 * ng;
+  MeshDev md;
+  md.nx = c->mesh.nx; md.ny = c->mesh.ny; md.nz = c->mesh.nz; md.n_mat = c->mesh.n_mat;
+  md.xyz = c->mesh.node_xyz; md.elem_mat = c->mesh.elem_mat; md.materials = c->mesh.materials;
+  md.dirichlet = c->mesh.dirichlet;
+  // whole-mesh box: stencil, classes (B1 free, B3 clamped), zero PoU
+  BoxMeta gm;
+  std::memset(&gm, 0, sizeof gm);
+  gm.sd = -1;
+  gm.mx = c->mesh.nx + 1; gm.my = c->mesh.ny + 1; gm.mz = c->mesh.nz + 1;
+  for (int d = 0; d < 3; ++d) { gm.olo[d] = 1; gm.ohi[d] = 0; }
+  gm.n_nodes = (int32_t)ng;
+  gm.n_dof = (int32_t)nd;
+  if (int rc = coarse_upload_tables(c, st, s)) return rc;
+  CHIPCHK(c, hipMemcpyAsync(pb + L.meta, &gm, sizeof gm, hipMemcpyHostToDevice, s));
+  CHIPCHK(c, hipMemcpyAsync(pb + L.omega, c->omega.data(), c->omega.size() * 4, hipMemcpyHostToDevice, s));
+  if (!faces.empty())
+    CHIPCHK(c, hipMemcpyAsync(st + c->s_faces, faces.data(), faces.size() * sizeof(FaceLoad), hipMemcpyHostToDevice, s));
+  CHIPCHK(c, hipStreamSynchronize(s));
+  const BoxMeta* gmeta = (const BoxMeta*)(pb + L.meta);
+  double* ctab = (double*)(pb + L.ctab);
+  int32_t* wtot = (int32_t*)(pb + L.wtot);
+  double* gst = (double*)(pb + L.stencil);
+  uint8_t* gcls = (uint8_t*)(pb + L.cls);
+  double* gmu = (double*)(pb + L.mu);
+  double *b = (double*)(pb + L.b), *x = (double*)(pb + L.x), *r = (double*)(pb + L.r), *z = (double*)(pb + L.z),
+         *pp = (double*)(pb + L.p), *q = (double*)(pb + L.q);
+  double *rb = (double*)(pb + L.rb), *zb = (double*)(pb + L.zb), *zero = (double*)(pb + L.zero);
+  double *part = (double*)(pb + L.part), *sc = (double*)(pb + L.sc), *scr = (double*)(pb + L.scr);
+  const BoxMeta* smeta = (const BoxMeta*)(st + c->s_meta);
+  const uint8_t* scls = (const uint8_t*)(st + c->s_cls);
+  const double* sV = (const double*)(st + c->s_V);
+  const int32_t* sroff = (const int32_t*)(st + c->s_roff);
+  double* rc = (double*)(st + c->s_rc);
+  k_materials<<<(c->mesh.n_mat + 63) / 64, 64, 0, s>>>(c->mesh.materials, c->mesh.n_mat, ctab);
+  k_fill_i32<<<1024, 256, 0, s>>>(wtot, ng, 0);
+  {
+    int maxo = 1;
+    for (int j = 0; j < nsd; ++j) {
+      const int32_t* o = &c->omega[6 * j];
+      maxo = std::max(maxo, (o[3] - o[0] + 1) * (o[4] - o[1] + 1) * (o[5] - o[2] + 1));
+    }
+    k_pou_total<<<dim3((maxo + 255) / 256, nsd), 256, 0, s>>>((const int32_t*)(pb + L.omega), nsd, c->mesh.nx,
+                                                              c->mesh.ny, c->mesh.nz, 2 * c->overlap, wtot);
+  }
+  k_assemble<<<dim3((unsigned)((ng + 3) / 4), 1), 256, 0, s>>>(gmeta, md, ctab, gst);
+  k_classes_mu<<<dim3((unsigned)((ng + 255) / 256), 1), 256, 0, s>>>(gmeta, md, 2 * c->overlap, wtot, gcls, gmu);
+  k_box_load<<<dim3((unsigned)((ng + 255) / 256), 1), 256, 0, s>>>(gmeta, md, (const FaceLoad*)(st + c->s_faces),
+                                                                  (int)faces.size(), b);
+  k_fill_f64<<<1024, 256, 0, s>>>(zero, c->dofs_total, 0.0);
+  CLAUNCHCHK(c);
+  // coarse factor A_0
+  if (int rc_ = coarse_factor(c, st, A0, status, s)) return rc_;
+  const double* tiles = (const double*)(st + c->s_tiles);
+  double* ysc = (double*)(st + c->s_y);
+  double* xsc = ysc + (int64_t)NT * 32;
+  const unsigned gblk = (unsigned)std::min<int64_t>((nd + 255) / 256, 4096);
+  auto gspmv = [&](const double* in, double* out) {
+    const int gb = (int)((ng + 255) / 256);
+    k_spmm<false, 1><<<dim3((unsigned)gb), 256, 0, s>>>(gmeta, 1, gb, (const double*)gst, gcls, gmu, in, out, nullptr,
+                                                        1, 1 << 1, 1.0, nullptr);
+  };
+  auto dot = [&](const double* a_, const double* b_, double* out) {
+    k_dot_partial<<<1024, 256, 0, s>>>(a_, b_, gcls, nd, part);
+    k_dot_final<<<1, 256, 0, s>>>(part, 1024, out);
+  };
+  auto precond = [&](const double* rin, double* zout) -> int {
+    k_fill_f64<<<4096, 256, 0, s>>>(zout, nd, 0.0);
+    k_gather_boxes<<<dim3((c->max_dof + 255) / 256, nsd), 256, 0, s>>>(smeta, md, scls, rin, rb);
+    if (solve_f32(s, smeta, nsd, c->max_bt11, c->loc_solve4, 0, (const float*)(st + c->s_loc), scls, rb, zb, 1,
+                  1 << 1, 1, scr, L.scr_stride))
+      return 1;
+    k_scatter_boxes<<<dim3((c->max_dof + 255) / 256, nsd), 256, 0, s>>>(smeta, md, scls, zb, zout);
+    k_coarse_restrict<<<nsd, 256, 0, s>>>(smeta, K, sV, rb, sroff, rc);
+    if (tile_trsv(tiles, NT, NH, rc, ysc, xsc, s)) return 1;
+    k_prolong<<<dim3((c->max_dof + 255) / 256, nsd), 256, 0, s>>>(smeta, md, K, sV, zero, xsc, sroff, zout, nullptr);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+  };
+  CHIPCHK(c, hipMemcpyAsync(x, u, nd * 8, hipMemcpyDeviceToDevice, s));
+  gspmv(x, q);
+  k_sub<<<gblk, 256, 0, s>>>(gcls, nd, b, q, r);
+  if (precond(r, z)) return cfail(c, MSGFEM_EHIP, "preconditioner launch failed");
+  k_pcg_p<<<gblk, 256, 0, s>>>(gcls, nd, nullptr, z, pp);
+  dot(r, z, sc + 0);
+  dot(b, b, sc + 6);
+  dot(r, r, sc + 3);
+  CLAUNCHCHK(c);
+  double h[8];
+  CHIPCHK(c, hipMemcpyAsync(h, sc, 8 * 8, hipMemcpyDeviceToHost, s));
+  CHIPCHK(c, hipStreamSynchronize(s));
+  const double nb2 = h[6] > 0 ? std::sqrt(h[6]) : 1.0;
+  double rel = std::sqrt(h[3]) / nb2;
+  int it = 0;
+  while (rel > rtol && it < maxit) {
+    gspmv(pp, q);
+    dot(pp, q, sc + 1);
+    k_pcg_alpha<<<1, 1, 0, s>>>(sc);
+    k_pcg_xr<<<gblk, 256, 0, s>>>(gcls, nd, sc, pp, q, x, r);
+    dot(r, r, sc + 3);
+    if (precond(r, z)) return cfail(c, MSGFEM_EHIP, "preconditioner launch failed");
+    dot(r, z, sc + 2);
+    k_pcg_beta<<<1, 1, 0, s>>>(sc);
+    k_pcg_p<<<gblk, 256, 0, s>>>(gcls, nd, sc, z, pp);
+    CLAUNCHCHK(c);
+    // one 8-byte read per iteration (an iteration moves tens of GB at this size)
+    CHIPCHK(c, hipMemcpyAsync(h + 3, sc + 3, 8, hipMemcpyDeviceToHost, s));
+    CHIPCHK(c, hipStreamSynchronize(s));
+    rel = std::sqrt(h[3]) / nb2;
+    ++it;
+  }
+  CHIPCHK(c, hipMemcpyAsync(u, x, nd * 8, hipMemcpyDeviceToDevice, s));
+  if (rel > rtol) k_status_or<<<1, 32, 0, s>>>(status, 1, 1);
+  CLAUNCHCHK(c);
+  CHIPCHK(c, hipStreamSynchronize(s));
+  *iters = it;
+  *relres = rel;
+  return MSGFEM_OK;
+}
+
+extern "C" int msgfem_coarse_energy(msgfem_coarse* c, void* pcg, const double* u_ref, const double* u, double* out,
+                                    void* stream) {
+  if (!c || !pcg || !u_ref || !u || !out) return cfail(c, MSGFEM_EARG, "null argument");
+  if (!c->geneo) return cfail(c, MSGFEM_EARG, "msgfem_coarse_energy reads the workspace of msgfem_coarse_pcg");
+  CHIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  char* pb = (char*)pcg;
+  const CPcgLayout L = cpcg_layout(c);
+  const int64_t ng = c->n_nodes_global, nd = 3 * ng;
+  const BoxMeta* gmeta = (const BoxMeta*)(pb + L.meta);
+  const uint8_t* gcls = (const uint8_t*)(pb + L.cls);
+  double *e = (double*)(pb + L.z), *Ae = (double*)(pb + L.q), *part = (double*)(pb + L.part);
+  const unsigned gblk = (unsigned)std::min<int64_t>((nd + 255) / 256, 4096);
+  const int gb = (int)((ng + 255) / 256);
+  k_sub<<<gblk, 256, 0, s>>>(gcls, nd, u_ref, u, e);
+  k_spmm<false, 1><<<dim3((unsigned)gb), 256, 0, s>>>(gmeta, 1, gb, (const double*)(pb + L.stencil), gcls,
+                                                      (const double*)(pb + L.mu), e, Ae, nullptr, 1, 1 << 1, 1.0, nullptr);
+  k_dot_partial<<<1024, 256, 0, s>>>(e, Ae, gcls, nd, part);
+  k_dot_final<<<1, 256, 0, s>>>(part, 1024, out);
+  k_spmm<false, 1><<<dim3((unsigned)gb), 256, 0, s>>>(gmeta, 1, gb, (const double*)(pb + L.stencil), gcls,
+                                                      (const double*)(pb + L.mu), u_ref, Ae, nullptr, 1, 1 << 1, 1.0,
+                                                      nullptr);
+  k_dot_partial<<<1024, 256, 0, s>>>(u_ref, Ae, gcls, nd, part);
+  k_dot_final<<<1, 256, 0, s>>>(part, 1024, out + 1);
+  CLAUNCHCHK(c);
   return MSGFEM_OK;
 }
 

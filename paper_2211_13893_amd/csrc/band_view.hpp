@@ -8,6 +8,7 @@ namespace msg {
 struct BandView {
   int NT, BT, n;
   int64_t off, ioff;
+  int64_t doff, dstride;   // D^{-1} tile I of the unit-lower factor at doff + I*dstride
   int64_t fw, bw;   // solve-ordered band copies (forward / backward sweep)
   int sx, sy, sz;   // (sub-)box node dims of the ordering
   int ox, oy, oz;   // offset of the ordering's node (0,0,0) inside the box
@@ -22,11 +23,16 @@ __device__ inline BandView band_view(const BoxMeta& bm, int kind) {
     v.sy = bm.sub_hi[1] - bm.sub_lo[1] + 1;
     v.sz = bm.sub_hi[2] - bm.sub_lo[2] + 1;
     v.ox = bm.sub_lo[0]; v.oy = bm.sub_lo[1]; v.oz = bm.sub_lo[2];
+    const bool compact = bm.flags & BOX_COMPACT_DINV;
+    v.doff = compact ? bm.f11i_off : bm.f11_off;
+    v.dstride = compact ? (int64_t)MSG_TILE2 : (int64_t)bm.bt11 * MSG_TILE2;
   } else {
     v.NT = bm.nth; v.BT = bm.bth; v.n = bm.nh; v.off = bm.fh_off; v.ioff = bm.fhi_off;
     v.fw = bm.fh_fw; v.bw = bm.fh_bw;
     v.sx = bm.mx; v.sy = bm.my; v.sz = bm.mz;
     v.ox = v.oy = v.oz = 0;
+    v.doff = bm.fh_off;
+    v.dstride = (int64_t)bm.bth * MSG_TILE2;
   }
   return v;
 }

@@ -13,8 +13,11 @@
 //                    intersection of Omega_i with the box of Omega_j^*, and
 //                    V_i^T A (mu_j psi_j) for the right-hand side.
 //  k_coarse_rhs    : b^H_i = V_i^T b - sum_j V_i^T A (mu_j psi_j).
-//  k_dense_tiles / k_dense_tile_solve : the coarse matrix in dense tile form for
-//                    the tile Cholesky, and the single-RHS block solve.
+//  k_dense_tiles / k_trsv_* : the coarse matrix in dense tile form for the
+//                    tile Cholesky, and the single-RHS solve by column launches.
+//  k_store_box / k_store_local32 : a plan's coarse data (and, for GenEO, its
+//                    local Dirichlet solve data in FP32) into a coarse store
+//                    that gathers every subdomain across plans.
 //  k_prolong       : u^G = sum_j R_j^T (mu_j psi_j + V_j c_j).
 //  k_error_norms   : the relative L2 errors e_d and e_eps of Sec. 5.3.
 #include "internal.hpp"
@@ -285,58 +288,109 @@ __global__ void k_dense_tiles(const double* __restrict__ AH, int NH, int NT, dou
   }
 }
 
-// Single-RHS solve with the unit-lower tile factor A = Lu D Lu^T of a dense
-// matrix (BT = NT).  One workgroup of 256 threads; y, w in global scratch.
-__global__ __launch_bounds__(256) void k_dense_tile_solve(const double* __restrict__ T, int NT,
-                                                          int NH, const double* __restrict__ b,
-                                                          double* __restrict__ y,
-                                                          double* __restrict__ x) {
-  __shared__ double part[8][33];
-  const int tid = threadIdx.x, r = tid & 31, g = tid >> 5;
-  const int BT = NT;
-  // forward Lu y = b
-  for (int I = 0; I < NT; ++I) {
-    double acc = 0.0;
-    for (int s = 1 + g; s <= I; s += 8) {
-      const double* Lr = T + ((int64_t)I * BT + s) * MSG_TILE2 + r * 32;
-      const double* yp = y + (int64_t)(I - s) * 32;
-      for (int q = 0; q < 32; ++q) acc += Lr[q] * yp[q];
-    }
-    part[g][r] = acc;
-    __syncthreads();
-    if (tid < 32) {
-      double sum = 0.0;
-      for (int q = 0; q < 8; ++q) sum += part[q][tid];
-      int row = I * 32 + tid;
-      y[row] = (row < NH ? b[row] : 0.0) - sum;
-    }
-    __syncthreads();
-  }
-  // w = D^{-1} y (diagonal tile slot holds D^{-1}), stored in x
-  for (int I = g; I < NT; I += 8) {
-    const double* Dr = T + ((int64_t)I * BT) * MSG_TILE2 + r * 32;
-    double s = 0.0;
-    for (int q = 0; q < 32; ++q) s += Dr[q] * y[I * 32 + q];
-    x[I * 32 + r] = s;
-  }
+// Multi-workgroup single-RHS solve with the unit-lower tile factor A = Lu D Lu^T
+// of a dense matrix (BT = NT, D^{-1} in the diagonal tile slot), in three
+// phases of launches: forward columns J = 0..NT-2 (y_I -= Lu(I,J) y_J for
+// every I > J, one workgroup per I; y_J is final once launch J-1 is done),
+// w = D^{-1} y, then backward columns J = NT-1..1 (x_I -= Lu(J,I)^T x_J for
+// every I < J).  y starts as b (zero past NH).
+__global__ void k_trsv_init(const double* __restrict__ b, int NH, int n, double* __restrict__ y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) y[i] = i < NH ? b[i] : 0.0;
+}
+
+// 256 threads per target tile: thread t takes row t >> 3 and inner indices
+// 4 (t & 7) .. +3 (32 contiguous bytes per thread, a tile row per 8 lanes)
+__global__ __launch_bounds__(256) void k_trsv_fwd(const double* __restrict__ T, int NT, int J, double* __restrict__ y) {
+  const int I = J + 1 + blockIdx.x;
+  if (I >= NT) return;
+  const int t = threadIdx.x, r = t >> 3, q0 = 4 * (t & 7);
+  const double* L = T + ((int64_t)I * NT + (I - J)) * MSG_TILE2 + r * 32 + q0;
+  const double* yj = y + (int64_t)J * 32 + q0;
+  double acc = L[0] * yj[0] + L[1] * yj[1] + L[2] * yj[2] + L[3] * yj[3];
+  acc += __shfl_xor(acc, 1);
+  acc += __shfl_xor(acc, 2);
+  acc += __shfl_xor(acc, 4);
+  if ((t & 7) == 0) y[(int64_t)I * 32 + r] -= acc;
+}
+
+// w_I = D^{-1}_I y_I into x, one workgroup per tile row
+__global__ __launch_bounds__(256) void k_trsv_diag(const double* __restrict__ T, int NT, const double* __restrict__ y,
+                                                   double* __restrict__ x) {
+  const int I = blockIdx.x, t = threadIdx.x, r = t >> 3, q0 = 4 * (t & 7);
+  const double* D = T + ((int64_t)I * NT) * MSG_TILE2 + r * 32 + q0;
+  const double* yi = y + (int64_t)I * 32 + q0;
+  double acc = D[0] * yi[0] + D[1] * yi[1] + D[2] * yi[2] + D[3] * yi[3];
+  acc += __shfl_xor(acc, 1);
+  acc += __shfl_xor(acc, 2);
+  acc += __shfl_xor(acc, 4);
+  if ((t & 7) == 0) x[(int64_t)I * 32 + r] = acc;
+}
+
+// 256 threads per target: thread t takes output row r = t & 31 and inner
+// indices 4 (t >> 5) .. +3 (a column of Lu(J,I) read across the lanes), the
+// eight partial sums added in LDS in a fixed order
+__global__ __launch_bounds__(256) void k_trsv_bwd(const double* __restrict__ T, int NT, int J, double* __restrict__ x) {
+  __shared__ double part[8][32];
+  const int I = blockIdx.x;
+  if (I >= J) return;
+  const int t = threadIdx.x, r = t & 31, g = t >> 5;
+  const double* L = T + ((int64_t)J * NT + (J - I)) * MSG_TILE2;
+  const double* xj = x + (int64_t)J * 32;
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc += L[(4 * g + u) * 32 + r] * xj[4 * g + u];
+  part[g][r] = acc;
   __syncthreads();
-  // backward Lu^T x = w (in place: x_I final once all later blocks are final)
-  for (int I = NT - 1; I >= 0; --I) {
-    double acc = 0.0;
-    for (int s = 1 + g; s <= NT - 1 - I; s += 8) {
-      const double* Lc = T + ((int64_t)(I + s) * BT + s) * MSG_TILE2 + r;
-      const double* xp = x + (int64_t)(I + s) * 32;
-      for (int q = 0; q < 32; ++q) acc += Lc[q * 32] * xp[q];
-    }
-    part[g][r] = acc;
-    __syncthreads();
-    if (tid < 32) {
-      double sum = 0.0;
-      for (int q = 0; q < 8; ++q) sum += part[q][tid];
-      x[I * 32 + tid] -= sum;
-    }
-    __syncthreads();
+  if (t < 32) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += part[q][t];
+    x[(int64_t)I * 32 + t] -= s;
   }
+}
+
+// Export of one plan's coarse data into a coarse store: box b of the plan is
+// subdomain pm.sd, whose slot in the store is described by smeta[pm.sd].
+// V, AV: plan block layout [n_dof][kp]; the store keeps kc columns.
+__global__ void k_store_box(const BoxMeta* __restrict__ pmeta, const BoxMeta* __restrict__ smeta, int kp, int kc,
+                            const double* __restrict__ V, const double* __restrict__ AV, const double* __restrict__ pv,
+                            const double* __restrict__ Ap, const double* __restrict__ bload,
+                            const uint8_t* __restrict__ cls, double* __restrict__ sV, double* __restrict__ sAV,
+                            double* __restrict__ spv, double* __restrict__ sAp, double* __restrict__ sbload,
+                            uint8_t* __restrict__ scls) {
+  const BoxMeta& pm = pmeta[blockIdx.y];
+  const BoxMeta& sm = smeta[pm.sd];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)pm.n_dof * kc) return;
+  const int dof = (int)(t / kc), c = (int)(t % kc);
+  const int64_t pr = pm.dof_off + dof, sr = sm.dof_off + dof;
+  sV[sr * kc + c] = c < kp ? V[pr * kp + c] : 0.0;
+  sAV[sr * kc + c] = c < kp ? AV[pr * kp + c] : 0.0;
+  if (c == 0) {
+    spv[sr] = pv[pr];
+    sAp[sr] = Ap[pr];
+    sbload[sr] = bload[pr];
+    scls[sr] = cls[pr];
+  }
+}
+
+// FP32 copies of the two solve-ordered copies of a plan box's A11 factor and
+// of its D^{-1} tiles into the store's local-solve area (element offsets
+// smeta[sd].f11_fw / f11_bw / f11i_off, the last compact: BOX_COMPACT_DINV)
+__global__ void k_store_local32(const BoxMeta* __restrict__ pmeta, const BoxMeta* __restrict__ smeta,
+                                const double* __restrict__ fac, float* __restrict__ loc) {
+  const BoxMeta& pm = pmeta[blockIdx.y];
+  const BoxMeta& sm = smeta[pm.sd];
+  const int64_t n = solve_copy_doubles(pm.nt11, pm.bt11);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    loc[sm.f11_fw + e] = (float)fac[pm.f11_fw + e];
+    loc[sm.f11_bw + e] = (float)fac[pm.f11_bw + e];
+  }
+  // the D^{-1} tiles the vector-FMA solve reads from the band's diagonal slot
+  // (the matrix-core layout keeps them in its forward copy), compactly
+  const int64_t nd = (int64_t)pm.nt11 * MSG_TILE2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nd; e += (int64_t)gridDim.x * blockDim.x)
+    loc[sm.f11i_off + e] = (float)fac[pm.f11_off + (e >> 10) * pm.bt11 * MSG_TILE2 + (e & 1023)];
 }
 
 // u^G[global dof] += mu_j psi_j + V_j c_j (atomic over the boxes sharing a node)

@@ -767,6 +767,12 @@ __global__ void k_status_clear(int n_box, const int32_t* __restrict__ mask, int3
   if (b < n_box && (!mask || mask[b])) status[b] &= ~(1 | 8 | 16);
 }
 
+// status[i] |= bits for i < n
+__global__ void k_status_or(int32_t* __restrict__ status, int n, int32_t bits) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) status[i] |= bits;
+}
+
 // dst[b] = src[b] where mask[b] != 0 (the iteration counts of a masked solve)
 __global__ void k_copy_masked_i32(int n, const int32_t* __restrict__ mask, const int32_t* __restrict__ src,
                                   int32_t* __restrict__ dst) {

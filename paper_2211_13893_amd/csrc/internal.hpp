@@ -48,7 +48,7 @@ struct BoxMeta {
   // factor geometry (tiles of 32): A11 on the sub-box, Ahat on the full box
   int32_t nt11, bt11, n11;    // tile rows, band tiles, matrix order (unpadded)
   int32_t nth, bth, nh;
-  int32_t pad_;
+  int32_t flags;              // BOX_COMPACT_DINV: D^{-1} of the A11 factor compact at f11i_off (coarse store)
   int64_t node_off;           // offset into per-node arrays of the batch
   int64_t dof_off;            // offset into per-dof arrays
   int64_t vec_off;            // offset (doubles) of this box inside one block-vector array
@@ -59,6 +59,11 @@ struct BoxMeta {
   int64_t f11_fw, f11_bw;     // solve-ordered copies of the A11 band (forward / backward sweep)
   int64_t fh_fw, fh_bw;       // same for Ahat
 };
+
+// BoxMeta.flags: the D^{-1} tiles of the A11 factor are stored compactly,
+// tile I at f11i_off + I*1024, instead of on the band's diagonal (a coarse
+// store keeps only what the block solves read)
+#define BOX_COMPACT_DINV 1
 
 // solve threads that hold a band fragment: 16 per off-diagonal tile of a set
 __host__ __device__ inline int solve_nthr(int BT) {

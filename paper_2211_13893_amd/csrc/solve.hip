@@ -257,7 +257,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     const int dofc = dof >= 0 ? dof : 0;
     const double fraw = vin[(int64_t)dofc * ldk + colc];
     const uint8_t cb = cl[dofc];
-    const V2* dp = (const V2*)(ft + v.off + (int64_t)I * BT * MSG_TILE2) + 2 * t8;
+    const V2* dp = (const V2*)(ft + v.doff + (int64_t)I * v.dstride) + 2 * t8;
     const V2 da = dp[0], db = dp[1];
     // w_{I-1} (Dl and its ring slot were completed last step)
     if (wthr && I >= 1) form_w(I - 1);

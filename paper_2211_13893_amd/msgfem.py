@@ -92,6 +92,22 @@ SIGNATURES = {
     "msgfem_geneo_pcg": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(msgfem_load), ctypes.c_double,
                                         ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_double), _P, _P]),
+    "msgfem_coarse_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(msgfem_mesh),
+                                            ctypes.POINTER(msgfem_decomp), _P, ctypes.c_int32]),
+    "msgfem_coarse_destroy": (None, [_P]),
+    "msgfem_coarse_error": (ctypes.c_char_p, [_P]),
+    "msgfem_coarse_store_sizes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_int32)]),
+    "msgfem_coarse_box": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "msgfem_coarse_add": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(msgfem_load), _P, _P, _P]),
+    "msgfem_coarse_galerkin": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "msgfem_coarse_solve_store": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "msgfem_coarse_pcg_sizes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "msgfem_coarse_pcg": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(msgfem_load), ctypes.c_double, ctypes.c_int32,
+                                         _P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                         _P, _P]),
+    "msgfem_coarse_energy": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "msgfem_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "msgfem_profile_stats": (ctypes.c_int, [_P, ctypes.POINTER(msgfem_kernel_stat), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
@@ -538,6 +554,128 @@ class LocalStage:
     def resid(self, out, b: int):
         bi = self.boxes[b]
         return out["resid"][bi.eval_off:bi.eval_off + bi.n_ev]
+
+
+class CoarseStore:
+    """The coarse problem of one decomposition gathered across plans
+    (msgfem_coarse_*): ``add`` every plan's eigen output, then ``galerkin``,
+    ``solve`` (MS-GFEM) or, for a GenEO store, ``pcg`` and ``energy``.
+
+    Keeps device copies of the mesh arrays and the store buffer."""
+
+    def __init__(self, problem, geneo: bool = False, n_ev: Optional[Sequence[int]] = None, device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        lib = load()
+        self.lib = lib
+        self.device = torch.device(device)
+        p = problem
+        self.problem = p
+        self.geneo = geneo
+        dev = self.device
+        self._xyz = torch.as_tensor(np.ascontiguousarray(p.xyz, dtype=np.float64), device=dev)
+        self._emat = torch.as_tensor(np.ascontiguousarray(p.elem_mat, dtype=np.int32), device=dev)
+        self._mats = torch.as_tensor(np.ascontiguousarray(p.materials, dtype=np.float64), device=dev)
+        self._dir = torch.as_tensor(np.ascontiguousarray(p.dirichlet, dtype=np.uint8), device=dev)
+        self.mesh = msgfem_mesh(p.nx, p.ny, p.nz, p.materials.shape[0], _ptr(self._xyz), _ptr(self._emat),
+                                _ptr(self._mats), _ptr(self._dir))
+        self._cores = np.ascontiguousarray(p.cores, dtype=np.int32)
+        self._ovs = np.ascontiguousarray(p.ovs, dtype=np.int32)
+        dec = msgfem_decomp(p.nsd, self._cores.ctypes.data, p.overlap, self._ovs.ctypes.data)
+        self.n_ev = np.ascontiguousarray(p.n_ev if n_ev is None else n_ev, dtype=np.int32)
+        h = _P()
+        idx = dev.index if dev.index is not None else torch.cuda.current_device()
+        rc = lib.msgfem_coarse_create(ctypes.byref(h), idx, ctypes.byref(self.mesh), ctypes.byref(dec),
+                                      self.n_ev.ctypes.data, 1 if geneo else 0)
+        self.h = h
+        self._check(rc, "msgfem_coarse_create")
+        nb, nh, kc = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib.msgfem_coarse_store_sizes(h, ctypes.byref(nb), ctypes.byref(nh), ctypes.byref(kc)),
+                    "msgfem_coarse_store_sizes")
+        self.store_bytes, self.NH, self.kc = nb.value, nh.value, kc.value
+        self.store = torch.empty(self.store_bytes, dtype=torch.uint8, device=dev)
+        self.pcg_ws = None
+
+    def _check(self, rc, what):
+        if rc != MSGFEM_OK:
+            m = self.lib.msgfem_coarse_error(self.h) if getattr(self, "h", None) else b""
+            raise MsgfemError(f"{what} failed with code {rc}: {m.decode() if m else ''}")
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.msgfem_coarse_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def _stream(self):
+        return _stream_handle(self.torch, self.device)
+
+    def add(self, stage: "LocalStage", eig_out):
+        ld = stage._load()
+        rc = self.lib.msgfem_coarse_add(self.h, stage.plan, _ptr(stage.ops), _ptr(stage._alloc_work()), ctypes.byref(ld),
+                                        _ptr(eig_out["evecs"]), _ptr(self.store), self._stream())
+        self._check(rc, "msgfem_coarse_add")
+
+    def galerkin(self):
+        torch = self.torch
+        AH = torch.empty((self.NH, self.NH), dtype=torch.float64, device=self.device)
+        bH = torch.empty(self.NH, dtype=torch.float64, device=self.device)
+        self._check(self.lib.msgfem_coarse_galerkin(self.h, _ptr(self.store), _ptr(AH), _ptr(bH), self._stream()),
+                    "msgfem_coarse_galerkin")
+        return AH, bH
+
+    def solve(self, AH, bH):
+        torch = self.torch
+        n = self.problem.n_dofs
+        c = torch.empty(self.NH, dtype=torch.float64, device=self.device)
+        uG = torch.empty(n, dtype=torch.float64, device=self.device)
+        up = torch.empty(n, dtype=torch.float64, device=self.device)
+        st = torch.zeros(1, dtype=torch.int32, device=self.device)
+        rc = self.lib.msgfem_coarse_solve_store(self.h, _ptr(self.store), _ptr(AH), _ptr(bH), _ptr(c), _ptr(uG),
+                                                _ptr(up), _ptr(st), self._stream())
+        self._check(rc, "msgfem_coarse_solve_store")
+        return dict(c=c, uG=uG, up=up, status=st)
+
+    def _load(self):
+        faces = {"x-": 0, "x+": 1, "y-": 2, "y+": 3, "z-": 4, "z+": 5}
+        tr = self.problem.tractions
+        self._face = np.asarray([faces[f] for f, _ in tr], dtype=np.int32)
+        self._g = np.ascontiguousarray(np.asarray([g for _, g in tr], dtype=np.float64).reshape(-1, 3))
+        return msgfem_load(len(tr), self._face.ctypes.data if len(tr) else 0, self._g.ctypes.data if len(tr) else 0)
+
+    def pcg(self, A0, rtol: float = 1e-8, maxit: int = 1000, u0=None):
+        torch = self.torch
+        nb = ctypes.c_int64()
+        self._check(self.lib.msgfem_coarse_pcg_sizes(self.h, ctypes.byref(nb)), "msgfem_coarse_pcg_sizes")
+        if self.pcg_ws is None or self.pcg_ws.numel() < nb.value:
+            self.pcg_ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        u = torch.zeros(self.problem.n_dofs, dtype=torch.float64, device=self.device) if u0 is None else u0.clone()
+        it, rel = ctypes.c_int32(), ctypes.c_double()
+        st = torch.zeros(1, dtype=torch.int32, device=self.device)
+        ld = self._load()
+        rc = self.lib.msgfem_coarse_pcg(self.h, _ptr(self.store), _ptr(A0), ctypes.byref(ld), rtol, maxit,
+                                        _ptr(self.pcg_ws), _ptr(u), ctypes.byref(it), ctypes.byref(rel), _ptr(st),
+                                        self._stream())
+        self._check(rc, "msgfem_coarse_pcg")
+        return dict(u=u, iters=it.value, relres=rel.value, status=st)
+
+    def energy(self, u_ref, u):
+        """[(u_ref-u)^T A (u_ref-u), u_ref^T A u_ref] (device float64[2]) after ``pcg``."""
+        torch = self.torch
+        if self.pcg_ws is None:
+            raise MsgfemError("energy needs the workspace of a completed pcg")
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        self._check(self.lib.msgfem_coarse_energy(self.h, _ptr(self.pcg_ws), _ptr(u_ref), _ptr(u), _ptr(out),
+                                                  self._stream()), "msgfem_coarse_energy")
+        return out
+
+    def box(self, sd: int):
+        off, n, row = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.msgfem_coarse_box(self.h, sd, ctypes.byref(off), ctypes.byref(n), ctypes.byref(row)),
+                    "msgfem_coarse_box")
+        return off.value, n.value, row.value
 
 
 # -- the warm-start network (plan-independent) ---------------------------------

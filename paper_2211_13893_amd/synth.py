@@ -369,12 +369,14 @@ def small_box(n: int = 4, core: int = 2, overlap: int = 1, ovs: int = 1, n_ev: i
 
 
 def slab(nxy: int = 40, nz: int = 4, core: int = 20, overlap: int = 1, ovs: int = 1, n_ev: int = 8,
-         seed: int = 0) -> Problem:
+         seed: int = 0, clamp: bool = False) -> Problem:
     """Thin laminate slab of unit elements (``nxy x nxy x nz``, one random ply
     angle per element layer) tiled by ``core x core x nz`` cores.  Its
     oversampled boxes have wide node planes (about ``(core+3)^2`` nodes), so
     their banded matrices span more than 33 tiles of 32 rows: the wide-band
-    test problem.  Every core is in the batch."""
+    test problem.  Every core is in the batch.  ``clamp`` fixes the x = 0
+    face and compresses the x = nxy face by 10 MPa (a well-posed global
+    problem for the fine solve)."""
     rng = _rng(8, seed)
     nx = ny = nxy
     xyz = _grid_xyz(np.arange(nx + 1, dtype=float), np.arange(ny + 1, dtype=float),
@@ -385,8 +387,9 @@ def slab(nxy: int = 40, nz: int = 4, core: int = 20, overlap: int = 1, ovs: int 
     elem_mat = _elem_mat_by_layer(nx, ny, nz)
     cores = _tiles(nx, ny, nz, (core, core, nz))
     nsd = cores.shape[0]
-    return Problem("slab", nx, ny, nz, xyz, elem_mat, mats,
-                   np.zeros(3 * (nx + 1) * (ny + 1) * (nz + 1), np.uint8), [], cores, overlap,
+    d = _clamp_x0(nx, ny, nz) if clamp else np.zeros(3 * (nx + 1) * (ny + 1) * (nz + 1), np.uint8)
+    tr = [("x+", (-10.0, 0.0, 0.0))] if clamp else []
+    return Problem("slab", nx, ny, nz, xyz, elem_mat, mats, d, tr, cores, overlap,
                    np.full(nsd, ovs, np.int32), np.full(nsd, n_ev, np.int32), np.arange(nsd, dtype=np.int32))
 
 
