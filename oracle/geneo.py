@@ -19,7 +19,10 @@ A phi = D A D phi); Courant-Fischer against the separately pinned A-harmonic
 oracle with no oversampling (V_A is a subspace of V_h(Omega_j), so every
 A-harmonic lambda_k is at least the GenEO lambda_k); independence of the
 oversampling; six rigid-body zeros on a floating subdomain and none on a
-clamped one.
+clamped one.  The GenEO coarse approximation (geneo_msgfem) is pinned by
+recovering the fine solution when every GenEO eigenvector is kept (the
+partition-of-unity-weighted local spaces then span all of V_h), by Galerkin
+orthogonality and by nested spaces (e_a non-increasing in n_ev).
 """
 from __future__ import annotations
 
@@ -57,6 +60,42 @@ def geneo_local(prob, j: int, n_ev: int, s: float = 1.0, kecache=None):
     phi = np.zeros((gd.size, n_ev))
     phi[keep] = X
     return 1.0 / nu - s, phi, gd, mu
+
+
+def geneo_locals(prob, n_ev, kecache=None, load=None, s: float = 1.0):
+    """Per subdomain (phi, psi, mu, dofs, lambda) of the GenEO local space used as
+    a stand-alone coarse approximation (Sec. 5.4 compares it with the
+    A-harmonic space): phi the n_ev lowest GenEO eigenvectors on Omega_j, psi
+    the particular function on Omega_j itself (A psi = b on the DoFs that are
+    neither on the interior boundary of Omega_j nor clamped, psi = 0 there),
+    the same construction as the A-harmonic case with Omega_j^* = Omega_j.
+    The tuple matches the ``locals_`` argument of ``coarse.msgfem``."""
+    if load is None:
+        load = fem.traction_load(prob)
+    out = []
+    for j in range(prob.nsd):
+        k = int(prob.n_ev[j]) if n_ev is None else (n_ev[j] if hasattr(n_ev, "__len__") else int(n_ev))
+        lam, phi, gd, mu = geneo_local(prob, j, k, s=s, kecache=kecache)
+        _, inner, _ = omega_dofs(prob, j)
+        i1 = np.flatnonzero(inner & (prob.dirichlet[gd] == 0))
+        psi = np.zeros(gd.size)
+        bj = load[gd]
+        if np.any(bj[i1] != 0.0):
+            elo, ehi = prob.omega_box(j)
+            A = fem.assemble_box_dense(prob, elo, ehi, kecache)
+            psi[i1] = sla.cho_solve(sla.cho_factor(A[np.ix_(i1, i1)], lower=True), bj[i1])
+        out.append((phi, psi, mu, gd, lam))
+    return out
+
+
+def geneo_msgfem(prob, n_ev=None, A=None, b=None, s: float = 1.0):
+    """The coarse approximation u^G in the GenEO space (Galerkin with the
+    particular functions of ``geneo_locals``), for comparison with the
+    A-harmonic MS-GFEM space of ``coarse.msgfem``."""
+    kec = fem.KeCache(prob)
+    A = fem.assemble_global_sparse(prob, kec) if A is None else A
+    b = fem.traction_load(prob) if b is None else b
+    return coarse.msgfem(prob, n_ev, A, b, s, locals_=geneo_locals(prob, n_ev, kec, b, s))
 
 
 def geneo_coarse_basis(prob, n_ev, kecache=None) -> np.ndarray:

@@ -169,3 +169,28 @@ def error_norms(problem, u_ref, u, device: str = "cuda:0"):
     """e_d, e_eps of Sec. 5.3 (msgfem_error_norms through a one-box plan of the same mesh)."""
     st = msgfem.LocalStage(problem, batch=[0], device=device)
     return st.msgfem_error_norms(u_ref, u).cpu().numpy()
+
+
+def coarse_approximation(problem, geneo: bool, n_ev: int, tol: float = 1e-6, budget_fraction: float = 0.6,
+                         device: str = "cuda:0", log=None):
+    """u^G of one coarse space with n_ev functions per subdomain: the A-harmonic
+    MS-GFEM space (geneo False) or the classic GenEO space (geneo True, local
+    spaces and particular functions on Omega_j), streamed through plans.
+    Returns (uG, local result, seconds)."""
+    import torch
+    p = dataclasses.replace(problem, n_ev=np.full(problem.nsd, int(n_ev), np.int32))
+    store = msgfem.CoarseStore(p, geneo=geneo, device=device)
+    free, _ = torch.cuda.mem_get_info()
+    chunks = make_chunks(p, int(free * budget_fraction), geneo=geneo)
+    t0 = time.perf_counter()
+    loc = local_stage_streamed(p, store, chunks, geneo=geneo, tol=tol, device=device)
+    AH, bH = store.galerkin()
+    sol = store.solve(AH, bH)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    uG = sol["uG"].clone()
+    del store, AH, bH, sol
+    torch.cuda.empty_cache()
+    if log:
+        log(f"  {'GenEO' if geneo else 'MS-GFEM'} n_ev {n_ev}: {len(chunks)} plans, {dt:.2f} s")
+    return uG, loc, dt

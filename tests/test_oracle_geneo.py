@@ -113,3 +113,36 @@ def test_geneo_rigid_modes_floating_and_clamped():
     cl = synth.small_box(n=8, core=4, overlap=1, ovs=1, n_ev=8, seed=5, clamp=True)
     lam, *_ = geneo.geneo_local(cl, 0, 10)      # core 0 touches the clamped face x = 0
     assert lam[0] > 1e-3
+
+
+def test_geneo_coarse_approximation_all_modes_recovers_fine_solution():
+    # every GenEO eigenvector kept: sum_j R_j^T Xi_j V_h(Omega_j) = V_h, so u^G = u_h
+    from oracle import coarse
+    p = synth.small_box(n=4, core=2, overlap=1, ovs=1, n_ev=8, seed=3, clamp=True)
+    A = fem.assemble_global_sparse(p)
+    b = fem.traction_load(p)
+    uh = coarse.fine_solve(p, A, b)
+    n_all = []
+    for j in range(p.nsd):
+        gd, _, _ = geneo.omega_dofs(p, j)
+        n_all.append(int(np.sum(p.dirichlet[gd] == 0)))
+    res = geneo.geneo_msgfem(p, n_all, A, b)
+    assert coarse.energy_error(p, A, uh, res.uG) <= 1e-8
+
+
+def test_geneo_coarse_approximation_galerkin_and_nested():
+    from oracle import coarse
+    p = synth.laminated_beam()
+    A = fem.assemble_global_sparse(p)
+    b = fem.traction_load(p)
+    uh = coarse.fine_solve(p, A, b)
+    F = coarse.free_dofs(p)
+    AF = A[F][:, F]
+    prev = np.inf
+    for n in (4, 8, 12):
+        res = geneo.geneo_msgfem(p, n, A, b)
+        g = res.V[F].T @ (AF @ (uh - res.uG)[F])
+        assert np.abs(g).max() <= 1e-9 * np.abs(res.V[F].T @ (AF @ uh[F])).max()
+        ea = coarse.energy_error(p, A, uh, res.uG)
+        assert ea <= prev * (1 + 1e-12)
+        prev = ea
