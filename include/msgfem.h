@@ -83,7 +83,9 @@ typedef struct {
   double shift;     /* s > 0 of the shifted pencil M x = nu (S + s M) x (default 1) */
   double tol;       /* residual tolerance on rho (default 1e-6) */
   int32_t maxit;    /* LOBPCG iteration cap (default 200) */
-  int32_t block;    /* block width k >= max n_ev (0: max(2 n_ev, n_ev + 8) rounded up to 8); at most 32 */
+  int32_t block;    /* block width k >= max n_ev (0: max(2 n_ev, n_ev + 8) rounded up to 8); at most 32.
+                       With some n_ev > 32 the block is 32 (0 or 32 accepted) and the
+                       pairs come in deflated rounds of 24 (see msgfem_local_eigs) */
   int32_t precision;/* 0 = FP64 throughout.
                        1 = mixed: the preconditioner solve (A + s D A D)^{-1}
                        reads an FP32 copy of its factor (FP64 arithmetic); the
@@ -138,7 +140,7 @@ typedef struct {
 
 /* Create a plan for one mesh, one decomposition and a batch of subdomains.
  * batch[nb] are subdomain ids, n_ev[nb] the number of eigenpairs of each
- * (1 <= n_ev <= 32).  `opts` may be NULL (defaults).  Host-side only: reads
+ * (1 <= n_ev <= 48).  `opts` may be NULL (defaults).  Host-side only: reads
  * the host arrays, keeps copies of the mesh descriptor's device pointers
  * (which must stay valid while the plan is used).  Returns MSGFEM_EARG for
  * inconsistent geometry (empty interior block, box thinner than 3 nodes). */
@@ -172,8 +174,19 @@ int msgfem_assemble_local(msgfem_plan *plan, void *ops, int32_t *status, void *s
  *           A-harmonic eigenvectors phi = (E x, x, 0) on every DoF of the box,
  *           unit 2-norm, entry of largest magnitude positive
  *   resid : device double[n_eval], rho = |Mx - nu T x| / (|Mx| + nu |T x|)
- *   iters : device int32[nb] LOBPCG iterations
- *   status: device int32[nb], bits ORed in (1 = not converged) */
+ *   iters : device int32[nb] LOBPCG iterations (summed over the rounds)
+ *   status: device int32[nb], bits ORed in (1 = not converged)
+ * With n_ev > 32 on some box (at most 48) the pairs come in deflated rounds:
+ * round r finds pairs 24 r .. 24 r + 23 of every box that has them, with a
+ * block of 32 kept T-orthogonal (T = S + s M) to the converged pairs of the
+ * earlier rounds (classical Gram-Schmidt through the T-Gram cross block,
+ * applied to the start block and every preconditioned residual), so the
+ * Rayleigh-Ritz step stays 96 x 96.  A round that a later round deflates
+ * against converges to rho <= max(1e-4 tol, 1e-10) (the later pairs' residual
+ * floor is the earlier pairs' error times the ratio of their nu), or stops
+ * six iterations after reaching tol when it stalls short of that.  The work
+ * buffer then also holds the four image kinds of every round's converged
+ * block. */
 int msgfem_local_eigs(msgfem_plan *plan, const void *ops, void *work, const double *x0,
                       double *evals, double *evecs, double *resid, int32_t *iters,
                       int32_t *status, void *stream);

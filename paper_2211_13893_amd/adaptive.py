@@ -4,7 +4,8 @@ The local space of subdomain j keeps the eigenpairs with lambda < 1/t, so the
 number m_j is known only once an eigenvalue at or above 1/t has been computed.
 Every subdomain starts with n_ev0 pairs; the boxes where all computed pairs
 pass (status bit 16 of msgfem_select_modes) are solved again with twice as
-many, up to n_ev_max, until an eigenvalue crosses 1/t or the cap is reached.
+many, up to n_ev_max (at most 48; the library computes more than 32 pairs
+in deflated rounds), until an eigenvalue crosses 1/t or the cap is reached.
 The final eigen output, in the layout of a plan with each box's last n_ev, is
 merged from those solves by msgfem_merge_eigs and selected with t.  This
 module only orchestrates: every array operation is a library call.
@@ -18,6 +19,9 @@ import numpy as np
 
 from . import msgfem
 
+# the library's cap on eigenpairs per box (beyond 32 they come in deflated rounds)
+MAX_NEV = 48
+
 
 @dataclasses.dataclass
 class AdaptiveResult:
@@ -30,11 +34,11 @@ class AdaptiveResult:
     rounds: List[List[int]]       # subdomains solved in each round
 
 
-def adaptive_local_spaces(problem, t: float, n_ev0: int = 8, n_ev_max: int = 32, **stage_kw) -> AdaptiveResult:
+def adaptive_local_spaces(problem, t: float, n_ev0: int = 8, n_ev_max: int = 48, **stage_kw) -> AdaptiveResult:
     if not t > 0:
         raise ValueError("threshold t must be positive")
-    if not 1 <= n_ev0 <= n_ev_max <= 32:
-        raise ValueError("need 1 <= n_ev0 <= n_ev_max <= 32")
+    if not 1 <= n_ev0 <= n_ev_max <= MAX_NEV:
+        raise ValueError(f"need 1 <= n_ev0 <= n_ev_max <= {MAX_NEV}")
     batch = [int(j) for j in problem.batch]
     nev = {j: n_ev0 for j in batch}
     solves, rounds = [], []

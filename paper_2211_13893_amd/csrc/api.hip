@@ -51,12 +51,15 @@ __global__ void k_gram_partial(const BoxMeta*, int, Blk3, Blk3, Blk3, int, int, 
 __global__ void k_gram_reduce(int, int, const double*, double*, const int32_t*);
 __global__ void k_rayleigh_ritz(int, int, int, double, const double*, double*, double*, double*,
                                 double*, const int32_t*);
+template <int CB>
 __global__ void k_update(const BoxMeta*, int, int, Blk4x3, Out4, Out4, const double*, const double*,
                          const int32_t*);
+__global__ void k_proj_coef(int, double, const double*, double*, const int32_t*);
+__global__ void k_keep_cols(const BoxMeta*, int, int, int, const double*, double*);
 __global__ void k_residual(const BoxMeta*, const uint8_t*, int, int, double, const double*, const double*,
                            const double*, double*, int, int, double*, const int32_t*);
-__global__ void k_converge(const BoxMeta*, int, int, int, const double*, const double*, double, double*,
-                           int32_t*, int32_t*, int32_t*, int, int32_t*);
+__global__ void k_converge(const BoxMeta*, int, int, int, const double*, const double*, double, double, double*,
+                           int32_t*, int32_t*, int32_t*, int, int32_t*, int, int, int, int32_t*);
 __global__ void k_status_clear(int, const int32_t*, int32_t*);
 __global__ void k_status_or(int32_t*, int, int32_t);
 __global__ void k_copy_masked_i32(int, const int32_t*, const int32_t*, int32_t*);
@@ -65,7 +68,7 @@ __global__ void k_lock(const BoxMeta*, int, const double*, double, double*, doub
                        const int32_t*);
 __global__ void k_copy_start(const BoxMeta*, const uint8_t*, int, int, const double*, double*);
 __global__ void k_output(const BoxMeta*, int, double, const double*, const double*, const double*,
-                         double*, double*, double*, const int32_t*);
+                         double*, double*, double*, const int32_t*, int, int);
 struct FaceLoad {
   int32_t axis, side;
   double g[3];
@@ -86,9 +89,9 @@ __global__ void k_box_digest_finish(const BoxMeta*, int, uint64_t, unsigned long
 __global__ void k_copy_eigs(int, int64_t, const double*, const double*, const double*, const int32_t*, double*,
                             double*, double*, int32_t*);
 __global__ void k_coarse_pairs(const BoxMeta*, const CoarsePair*, int, const double*, const double*,
-                               const double*, int, double*, double*);
+                               const double*, int, int, double*, double*);
 __global__ void k_coarse_rhs(const BoxMeta*, int, const double*, const double*, const int32_t*,
-                             const int32_t*, int, const double*, double*, double*);
+                             const int32_t*, int, int, const double*, double*, double*);
 __global__ void k_dense_tiles(const double*, int, int, double*);
 __global__ void k_trsv_init(const double*, int, int, double*);
 __global__ void k_trsv_fwd(const double*, int, int, double*);
@@ -121,6 +124,12 @@ __global__ void k_warm_start(const BoxMeta*, const uint8_t*, const float*, const
 using namespace msg;
 
 static const int KC = 8;           // columns per solve workgroup
+// eigenpairs per box: beyond 32 they come in deflated rounds; two rounds at
+// most, because a third round's pairs can sit 1e4 below the first round's in
+// nu (the end subdomains of a clamped beam), where the first round's error is
+// amplified past what the FP64 images resolve
+static const int MAX_NEV = 48;
+static const int ROUND_PAIRS = 24; // pairs per deflated round (block 32, 8 guard columns)
 static const int GRAM_ROWS = 1024; // rows per Gram / residual chunk
 
 static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
@@ -134,6 +143,9 @@ struct msgfem_plan {
   std::vector<MatDesc> mats;      // the two banded matrices of every box (A11, Ahat)
   msgfem_eig_opts opts{};
   int k = 0;
+  int nround = 0;    // eigenpairs per deflated round (n_ev > 32 takes several rounds)
+  int rounds = 1;
+  int kv = 0;        // columns of a coarse basis block (max(k, max n_ev) rounded up to 8)
   int64_t n_nodes_global = 0;
   // ops layout (bytes)
   int64_t o_meta = 0, o_mats = 0, o_omega = 0, o_ctab = 0, o_wtot = 0, o_stencil = 0, o_mu = 0,
@@ -146,7 +158,7 @@ struct msgfem_plan {
   int n_gchunk = 0;
   // work layout (bytes)
   int64_t w_vec = 0, w_part = 0, w_G = 0, w_L = 0, w_Y = 0, w_Yp = 0, w_nu = 0, w_rho = 0,
-          w_rpart = 0, w_active = 0, w_iters = 0, w_nact = 0, w_scr = 0, work_bytes = 0;
+          w_rpart = 0, w_active = 0, w_iters = 0, w_nact = 0, w_reached = 0, w_scr = 0, work_bytes = 0;
   int64_t scr_stride = 0;
   // coarse problem (built on the first coarse call)
   bool coarse_ready = false;
@@ -336,19 +348,30 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   }
   int maxnev = 0;
   for (int b = 0; b < nb; ++b) maxnev = std::max(maxnev, n_ev[b]);
-  if (maxnev < 1 || maxnev > 32) return fail(p, MSGFEM_EARG, "n_ev must be in [1, 32]");
+  if (maxnev < 1 || maxnev > MAX_NEV) return fail(p, MSGFEM_EARG, "n_ev must be in [1, %d]", MAX_NEV);
   int k = o.block;
-  if (k <= 0) {
-    // twice n_ev, at least n_ev + 8: the block solves of 8-column chunks run
-    // side by side, so wider blocks cost little per iteration and cut the
-    // iteration count (uniform batch: 6.9 iterations at k = 32, 8.6 at 24)
-    k = std::max(2 * maxnev, maxnev + 8);
-    k = (k + 7) / 8 * 8;
+  if (maxnev <= 32) {
+    if (k <= 0) {
+      // twice n_ev, at least n_ev + 8: the block solves of 8-column chunks run
+      // side by side, so wider blocks cost little per iteration and cut the
+      // iteration count (uniform batch: 6.9 iterations at k = 32, 8.6 at 24)
+      k = std::max(2 * maxnev, maxnev + 8);
+      k = (k + 7) / 8 * 8;
+    }
+    k = std::min(k, 32);
+    if (k < maxnev) return fail(p, MSGFEM_EARG, "block %d < n_ev %d", k, maxnev);
+    p->nround = maxnev;
+    p->rounds = 1;
+  } else {
+    // deflated rounds of ROUND_PAIRS pairs with a block of 32 (8 guard columns)
+    if (k > 0 && k != 32) return fail(p, MSGFEM_EARG, "n_ev > 32 runs deflated rounds with block 32 (got %d)", k);
+    k = 32;
+    p->nround = ROUND_PAIRS;
+    p->rounds = (maxnev + ROUND_PAIRS - 1) / ROUND_PAIRS;
   }
-  k = std::min(k, 32);
-  if (k < maxnev) return fail(p, MSGFEM_EARG, "block %d < n_ev %d", k, maxnev);
   if (k % 2) return fail(p, MSGFEM_EARG, "block width must be even");
   p->k = k;
+  p->kv = std::max(k, (maxnev + 7) / 8 * 8);
   p->meta.resize(nb);
   int64_t node_off = 0, dof_off = 0, vec_off = 0, fac_off = 0, evec_off = 0, eval_off = 0;
   for (int b = 0; b < nb; ++b) {
@@ -438,11 +461,15 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   // w rows of the solve plus one row that absorbs stores without a target
   p->scr_stride = (int64_t)(p->max_nt + 1) * 32 * KC;
   off = 0;
-  p->w_vec = off; off = align256(off + 22 * p->vec_total * 8);
+  // 20 LOBPCG blocks, two scratch blocks, and the four image kinds of the
+  // converged block of every round but the last
+  p->w_vec = off; off = align256(off + (22 + 4 * (int64_t)(p->rounds - 1)) * p->vec_total * 8);
   p->w_part = off; off = align256(off + (int64_t)nb * p->n_gchunk * 2 * m3 * m3 * 8);
   p->w_G = off; off = align256(off + (int64_t)nb * 2 * m3 * m3 * 8);
   p->w_L = off; off = align256(off + (int64_t)nb * m3 * m3 * 8);
-  p->w_Y = off; off = align256(off + (int64_t)nb * m3 * k * 8);
+  // Rayleigh-Ritz coefficients (3k x k), or a coarse basis's CholQR
+  // coefficients (kv x kv)
+  p->w_Y = off; off = align256(off + (int64_t)nb * std::max(m3 * k, p->kv * p->kv) * 8);
   p->w_Yp = off; off = align256(off + (int64_t)nb * m3 * k * 8);
   p->w_nu = off; off = align256(off + (int64_t)nb * k * 8);
   p->w_rho = off; off = align256(off + (int64_t)nb * k * 8);
@@ -450,6 +477,7 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   p->w_active = off; off = align256(off + (int64_t)nb * 4);
   p->w_iters = off; off = align256(off + (int64_t)nb * 4);
   p->w_nact = off; off = align256(off + 4);
+  p->w_reached = off; off = align256(off + (int64_t)nb * 4);
   p->w_scr = off; off = align256(off + (int64_t)nb * nchunk_solve * p->scr_stride * 8);
   p->work_bytes = off;
   return MSGFEM_OK;
@@ -741,6 +769,7 @@ struct Work {
   int32_t* active;
   int32_t* iters;
   int32_t* nact;
+  int32_t* reached;
   double* scr;
 };
 }  // namespace
@@ -760,6 +789,7 @@ static Work work_view(const msgfem_plan* p, void* work) {
   w.active = (int32_t*)(b + p->w_active);
   w.iters = (int32_t*)(b + p->w_iters);
   w.nact = (int32_t*)(b + p->w_nact);
+  w.reached = (int32_t*)(b + p->w_reached);
   w.scr = (double*)(b + p->w_scr);
   return w;
 }
@@ -792,7 +822,9 @@ static void lds_attributes() {
                             (const void*)k_band_solve4<1, float>,  (const void*)k_band_solve4<2, float>,
                             (const void*)k_band_solve4<3, float>,  (const void*)k_band_solve4<4, float>};
   for (const void* f : solves4) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  (void)hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)k_update<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_update<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_gram_partial<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
@@ -900,8 +932,10 @@ static int harmonic_images(Ctx& c, double* Z, double* AZ, double* BZ, double* MZ
   return 0;
 }
 
-static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double* const* BZb,
-                const int32_t* act) {
+// Gram matrices G_S = Z~^T A Z~ and G_M = Z~^T (D A D) Z~ of the blocks
+// [Z_0 .. Z_{nblk-1}] into c.w.G ([box][2][m][m], m = nblk k)
+static int gram_only(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double* const* BZb,
+                     const int32_t* act) {
   const int k = c.k, m = nblk * k;
   Blk3 Z, A, B;
   for (int i = 0; i < 3; ++i) {
@@ -918,24 +952,35 @@ static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double*
     by += 3 * 8.0 * mt.n_dof * m;
     fl += 2 * 2.0 * mt.n_dof * m * m;
   }
-  {
-    ProfScope ps(c.p, PK_GRAM, c.s, by, fl);
-    // 16x16 blocks of the m x m result per side: 2, 4 or 6
-    const int nb16 = (m + 15) / 16;
-    auto kern = nb16 <= 2 ? k_gram_partial<2> : (nb16 <= 4 ? k_gram_partial<4> : k_gram_partial<6>);
-    kern<<<grid, 256, lds, c.s>>>(c.v.meta, nblk, Z, A, B, k, GRAM_ROWS, c.p->n_gchunk, c.w.part,
-                                            act);
-    LAUNCHCHK(c.p);
-    dim3 g2((2 * m * m + 255) / 256, c.nb);
-    k_gram_reduce<<<g2, 256, 0, c.s>>>(m, c.p->n_gchunk, c.w.part, c.w.G, act);
-    LAUNCHCHK(c.p);
-  }
+  ProfScope ps(c.p, PK_GRAM, c.s, by, fl);
+  // 16x16 blocks of the m x m result per side: 2, 4 or 6
+  const int nb16 = (m + 15) / 16;
+  auto kern = nb16 <= 2 ? k_gram_partial<2> : (nb16 <= 4 ? k_gram_partial<4> : k_gram_partial<6>);
+  kern<<<grid, 256, lds, c.s>>>(c.v.meta, nblk, Z, A, B, k, GRAM_ROWS, c.p->n_gchunk, c.w.part, act);
+  LAUNCHCHK(c.p);
+  dim3 g2((2 * m * m + 255) / 256, c.nb);
+  k_gram_reduce<<<g2, 256, 0, c.s>>>(m, c.p->n_gchunk, c.w.part, c.w.G, act);
+  LAUNCHCHK(c.p);
+  return 0;
+}
+
+static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double* const* BZb,
+                const int32_t* act) {
+  const int k = c.k, m = nblk * k;
+  if (gram_only(c, nblk, Zb, AZb, BZb, act)) return MSGFEM_EHIP;
   size_t lds_rr = ((size_t)2 * m * (m + 1) + 4 * m + 256) * 8 + ((size_t)5 * m + 1) * 4;
   ProfScope ps2(c.p, PK_RR, c.s, 0.0, 0.0);
   k_rayleigh_ritz<<<c.nb, 1024, lds_rr, c.s>>>(m, k, 1, c.p->opts.shift, c.w.G, c.w.L, c.w.Y, c.w.Yp,
                                                c.w.nu, act);
   LAUNCHCHK(c.p);
   return 0;
+}
+
+static uint64_t round_seed(uint64_t seed, int r) {
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(r + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
 }
 
 static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const double* x0, const int32_t* mask,
@@ -958,40 +1003,30 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
   for (int kind = 0; kind < 4; ++kind)
     for (int sl = 0; sl < 5; ++sl) B[kind][sl] = c.w.vec + (int64_t)(kind * 5 + sl) * VT;
   double* tmp = c.w.vec + (int64_t)20 * VT;
+  // converged blocks of the earlier rounds, four image kinds each
+  auto Yblk = [&](int r, int kind) { return c.w.vec + (int64_t)(22 + 4 * r + kind) * VT; };
   int32_t* act = c.w.active;
-  const size_t lds_upd3 = (size_t)2 * 3 * k * k * 8;
   // A-harmonic GEVP: unknowns on B2, images through the extension; GenEO: all
   // of B1 u B2, M = D A D itself (kind 2 doubles as M Z)
   const bool geneo = p->opts.geneo != 0;
   const int vcls = geneo ? ((1 << 1) | (1 << 2)) : (1 << 2);
   const int nkinds = geneo ? 3 : 4;
+  const dim3 ugrid((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, nkinds);
   auto images = [&](double* Z, double* AZ, double* BZ, double* MZ, const int32_t* a_) -> int {
     if (geneo) return spmm(c, Z, AZ, BZ, k, (1 << 1) | (1 << 2), 1.0, a_);
     return harmonic_images(c, Z, AZ, BZ, MZ, tmp, a_);
   };
-  k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(act, nb, 1);
   k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(c.w.iters, nb, 0);
   // bits of an earlier solve of the same boxes are stale (bit 4 of the assembly stays)
   k_status_clear<<<(nb + 255) / 256, 256, 0, c.s>>>(nb, mask, status);
   LAUNCHCHK(p);
   // a caller mask solves only the boxes it selects; the others are inactive
   // from the start and their outputs are left as they are
-  std::vector<int32_t> mask_h;
+  std::vector<int32_t> mask_h(nb, 1);
   if (mask) {
-    mask_h.resize(nb);
     HIPCHK(p, hipMemcpyAsync(mask_h.data(), mask, nb * 4, hipMemcpyDeviceToHost, c.s));
     HIPCHK(p, hipStreamSynchronize(c.s));
     for (int b = 0; b < nb; ++b) mask_h[b] = mask_h[b] != 0;
-    HIPCHK(p, hipMemcpyAsync(act, mask_h.data(), nb * 4, hipMemcpyHostToDevice, c.s));
-    c.act_h = mask_h;
-  }
-  const int32_t* act0 = mask ? act : nullptr;
-  // start block
-  {
-    dim3 grid((unsigned)(((int64_t)p->max_dof * k + 255) / 256), nb);
-    if (x0) k_copy_start<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, vcls, x0, B[0][0]);
-    else k_random_start<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, vcls, p->opts.seed, B[0][0]);
-    LAUNCHCHK(p);
   }
   // Rayleigh-Ritz on X alone (T-orthonormalises the block; also used when the
   // mixed path moves to the FP64 operators)
@@ -1008,128 +1043,203 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
       OX.p[kind] = B[kind][3];
       OP.p[kind] = nullptr;
     }
-    dim3 grid((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, nkinds);
-    k_update<<<grid, UPD_THREADS, (size_t)2 * k * k * 8, c.s>>>(c.v.meta, 1, k, Z, OX, OP, c.w.Y, c.w.Yp, a_);
+    k_update<2><<<ugrid, UPD_THREADS, (size_t)2 * k * k * 8, c.s>>>(c.v.meta, 1, k, Z, OX, OP, c.w.Y, c.w.Yp, a_);
     LAUNCHCHK(p);
     for (int kind = 0; kind < 4; ++kind) std::swap(B[kind][0], B[kind][3]);
     return 0;
   };
-  if (images(B[0][0], B[1][0], B[2][0], B[3][0], act0)) return MSGFEM_EHIP;
-  if (rr_x(act0)) return MSGFEM_EHIP;
-  int n_chunk = p->n_gchunk;
-  // Mixed path: the first phase runs the SpMM and the block solves with FP32
+  // Deflation: block slot sl (all image kinds) made T-orthogonal to the
+  // converged blocks of rounds 0 .. r-1 (classical Gram-Schmidt against each,
+  // through the T-Gram cross block), the result swapped into slot sl
+  auto deflate = [&](int r, int sl, const int32_t* a_) -> int {
+    for (int q = 0; q < r; ++q) {
+      double* Zb[2] = {B[0][sl], Yblk(q, 0)};
+      double* Ab[2] = {B[1][sl], Yblk(q, 1)};
+      double* Bb[2] = {B[2][sl], Yblk(q, 2)};
+      if (gram_only(c, 2, Zb, Ab, Bb, a_)) return MSGFEM_EHIP;
+      k_proj_coef<<<nb, 256, 0, c.s>>>(k, p->opts.shift, c.w.G, c.w.Y, a_);
+      Blk4x3 Z;
+      Out4 OX, OP;
+      for (int kind = 0; kind < 4; ++kind) {
+        Z.p[kind][0] = B[kind][sl];
+        Z.p[kind][1] = Yblk(q, kind);
+        Z.p[kind][2] = nullptr;
+        OX.p[kind] = B[kind][3];
+        OP.p[kind] = nullptr;
+      }
+      k_update<2><<<ugrid, UPD_THREADS, (size_t)2 * 2 * k * k * 8, c.s>>>(c.v.meta, 2, k, Z, OX, OP, c.w.Y, c.w.Yp,
+                                                                         a_);
+      LAUNCHCHK(p);
+      for (int kind = 0; kind < 4; ++kind) std::swap(B[kind][sl], B[kind][3]);
+    }
+    return 0;
+  };
+  const int n_chunk = p->n_gchunk;
+  const int nround = p->nround;
+  // target of the rounds that later rounds deflate against (see k_converge)
+  // (not below 1e-10: the FP64 images' rounding floor, below which an
+  // unlocked column's preconditioned residual is noise)
+  const double tol_defl = std::max(1e-4 * p->opts.tol, 1e-10);
+  // Precision 2: the first phase runs the SpMM and the block solves with FP32
   // operator copies (FP64 arithmetic and FP64 dense steps); once every active
   // box has rho <= switch_tol (or the FP32 phase stagnates, or after fp32_cap
-  // iterations) the block X is
-  // re-imaged with the FP64 operators, re-orthonormalised, and the iteration
-  // continues in FP64 (without the P block once) to the requested tolerance,
-  // so the final residual check is FP64.
+  // iterations) the block X is re-imaged with the FP64 operators,
+  // re-orthonormalised, and the iteration continues in FP64 (without the P
+  // block once) to the requested tolerance, so the final residual check is
+  // FP64.  Precision 1: the preconditioner solve reads its FP32 copy.
   const bool mixed = p->opts.precision == 2;
-  c.use32 = mixed;
   c.pre32 = p->opts.precision == 1;
   const double switch_tol = std::max(1e-4, 100.0 * p->opts.tol);
   const int fp32_cap = 30;
-  int fp32_iters = 0;
-  bool restart = false;
   std::vector<double> rho_h, rhist;
-  for (int it = 0; it <= p->opts.maxit; ++it) {
-    // residual of the current Ritz block, convergence, active set
-    {
-      dim3 grid(n_chunk, nb);
-      k_residual<<<grid, 1024, 0, c.s>>>(c.v.meta, c.v.cls, vcls, k, p->opts.shift, B[1][0],
-                                        geneo ? B[2][0] : B[3][0], c.w.nu,
-                                        B[0][1], GRAM_ROWS, n_chunk, c.w.rpart, act);
-      LAUNCHCHK(p);
-      k_fill_i32<<<1, 32, 0, c.s>>>(c.w.nact, 1, 0);
-      // FP32 phase: residuals are estimates, no box is retired
-      k_converge<<<nb, 64, 0, c.s>>>(c.v.meta, nb, k, n_chunk, c.w.rpart, c.w.nu,
-                                     c.use32 ? 0.0 : p->opts.tol, c.w.rho, act, c.w.iters,
-                                     c.w.nact, it == p->opts.maxit ? 1 : 0, status);
-      LAUNCHCHK(p);
-      c.act_h.resize(nb);
-      HIPCHK(p, hipMemcpyAsync(c.act_h.data(), act, nb * 4, hipMemcpyDeviceToHost, c.s));
-      if (c.use32) {
-        rho_h.resize((size_t)nb * k);
-        HIPCHK(p, hipMemcpyAsync(rho_h.data(), c.w.rho, (size_t)nb * k * 8, hipMemcpyDeviceToHost, c.s));
-      }
-      HIPCHK(p, hipStreamSynchronize(c.s));
-      int nact = 0;
-      for (int b = 0; b < nb; ++b) nact += c.act_h[b] != 0;
-      if (nact == 0 || it == p->opts.maxit) break;
-      if (c.use32) {
-        double rmax = 0.0;
-        for (int b = 0; b < nb; ++b) {
-          if (!c.act_h[b]) continue;
-          for (int cc = 0; cc < p->meta[b].n_ev; ++cc) rmax = std::max(rmax, rho_h[(size_t)b * k + cc]);
-        }
-        // leave the FP32 phase when it has done its part (rho <= switch_tol),
-        // when it stagnates at the FP32 operators' accuracy (rho not halved
-        // over two iterations) or at the iteration cap
-        rhist.push_back(rmax);
-        const size_t nh = rhist.size();
-        const bool stalled = nh >= 3 && !(rhist[nh - 1] <= 0.5 * rhist[nh - 3]);
-        if (!(rmax <= switch_tol) && !stalled && ++fp32_iters < fp32_cap) {
-          // stay in the FP32 phase
-        } else {
-          c.use32 = false;
-          const int64_t n = p->dofs_total * k;
-          k_keep_classes<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, c.s>>>(c.v.cls, vcls, k, n,
-                                                                                               B[0][0]);
-          LAUNCHCHK(p);
-          if (images(B[0][0], B[1][0], B[2][0], B[3][0], act)) return MSGFEM_EHIP;
-          if (rr_x(act)) return MSGFEM_EHIP;
-          restart = true;
-          continue;
-        }
-      }
+  // Round r finds the pairs r*nround .. r*nround + nround - 1 of every box that
+  // has that many (one round when n_ev <= 32), its block kept T-orthogonal to
+  // the converged blocks of the earlier rounds
+  for (int r = 0; r < p->rounds; ++r) {
+    const int col0 = r * nround;
+    std::vector<int32_t> act_r(nb);
+    int n_r = 0;
+    for (int b = 0; b < nb; ++b) {
+      act_r[b] = mask_h[b] && p->meta[b].n_ev > col0;
+      n_r += act_r[b];
     }
-    // soft locking of converged columns (their W and P directions vanish)
+    if (n_r == 0) break;
+    HIPCHK(p, hipMemcpyAsync(act, act_r.data(), nb * 4, hipMemcpyHostToDevice, c.s));
+    HIPCHK(p, hipStreamSynchronize(c.s));
+    c.act_h = act_r;
+    // start block (a caller block starts round 0 only)
     {
       dim3 grid((unsigned)(((int64_t)p->max_dof * k + 255) / 256), nb);
-      const bool hasP = it > 0 && !restart;
-      k_lock<<<grid, 256, 0, c.s>>>(c.v.meta, k, c.w.rho, 0.1 * p->opts.tol, B[0][1],
-                                    hasP ? B[0][2] : nullptr, hasP ? B[1][2] : nullptr,
-                                    hasP ? B[2][2] : nullptr, (hasP && !geneo) ? B[3][2] : nullptr, act);
+      if (x0 && r == 0) k_copy_start<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, vcls, x0, B[0][0]);
+      else k_random_start<<<grid, 256, 0, c.s>>>(c.v.meta, c.v.cls, k, vcls,
+                                                 r == 0 ? p->opts.seed : round_seed(p->opts.seed, r), B[0][0]);
       LAUNCHCHK(p);
     }
-    // W = preconditioned residual: B2 trace of (A + s DAD)^{-1} [0; R]
-    if (solve(c, 1, B[0][1], B[0][1], k, vcls, 1, act)) return MSGFEM_EHIP;
-    if (images(B[0][1], B[1][1], B[2][1], B[3][1], act)) return MSGFEM_EHIP;
-    int nblk = (it == 0 || restart) ? 2 : 3;
-    restart = false;
-    double* Zb[3] = {B[0][0], B[0][1], B[0][2]};
-    double* Ab[3] = {B[1][0], B[1][1], B[1][2]};
-    double* Bb[3] = {B[2][0], B[2][1], B[2][2]};
-    if (gram(c, nblk, Zb, Ab, Bb, act)) return MSGFEM_EHIP;
-    Blk4x3 Z;
-    Out4 OX, OP;
-    for (int kind = 0; kind < 4; ++kind) {
-      for (int b = 0; b < 3; ++b) Z.p[kind][b] = b < nblk ? B[kind][b] : nullptr;
-      OX.p[kind] = B[kind][3];
-      OP.p[kind] = B[kind][4];
+    c.use32 = mixed;
+    int fp32_iters = 0;
+    bool restart = false;
+    rhist.clear();
+    k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(c.w.reached, nb, -1);
+    // a round that later rounds deflate against converges to tol_defl
+    bool deflated_later = false;
+    for (int b = 0; b < nb; ++b) deflated_later |= act_r[b] && p->meta[b].n_ev - col0 > nround;
+    // columns are locked once at their round's target: below it their
+    // preconditioned residuals are rounding noise that corrupts the Gram
+    // matrices (the single-round target keeps a 10x margin)
+    const double lock_tol = deflated_later ? tol_defl : 0.1 * p->opts.tol;
+    if (images(B[0][0], B[1][0], B[2][0], B[3][0], act)) return MSGFEM_EHIP;
+    if (deflate(r, 0, act)) return MSGFEM_EHIP;
+    if (rr_x(act)) return MSGFEM_EHIP;
+    for (int it = 0; it <= p->opts.maxit; ++it) {
+      // residual of the current Ritz block, convergence, active set
+      {
+        dim3 grid(n_chunk, nb);
+        k_residual<<<grid, 1024, 0, c.s>>>(c.v.meta, c.v.cls, vcls, k, p->opts.shift, B[1][0],
+                                          geneo ? B[2][0] : B[3][0], c.w.nu,
+                                          B[0][1], GRAM_ROWS, n_chunk, c.w.rpart, act);
+        LAUNCHCHK(p);
+        k_fill_i32<<<1, 32, 0, c.s>>>(c.w.nact, 1, 0);
+        // FP32 phase: residuals are estimates, no box is retired
+        k_converge<<<nb, 64, 0, c.s>>>(c.v.meta, nb, k, n_chunk, c.w.rpart, c.w.nu,
+                                       c.use32 ? 0.0 : p->opts.tol, c.use32 ? 0.0 : tol_defl, c.w.rho, act,
+                                       c.w.iters, c.w.nact, it == p->opts.maxit ? 1 : 0, status, col0, nround, it,
+                                       c.w.reached);
+        LAUNCHCHK(p);
+        c.act_h.resize(nb);
+        HIPCHK(p, hipMemcpyAsync(c.act_h.data(), act, nb * 4, hipMemcpyDeviceToHost, c.s));
+        if (c.use32) {
+          rho_h.resize((size_t)nb * k);
+          HIPCHK(p, hipMemcpyAsync(rho_h.data(), c.w.rho, (size_t)nb * k * 8, hipMemcpyDeviceToHost, c.s));
+        }
+        HIPCHK(p, hipStreamSynchronize(c.s));
+        int nact = 0;
+        for (int b = 0; b < nb; ++b) nact += c.act_h[b] != 0;
+        if (nact == 0 || it == p->opts.maxit) break;
+        if (c.use32) {
+          double rmax = 0.0;
+          for (int b = 0; b < nb; ++b) {
+            if (!c.act_h[b]) continue;
+            const int nev = std::min(nround, p->meta[b].n_ev - col0);
+            for (int cc = 0; cc < nev; ++cc) rmax = std::max(rmax, rho_h[(size_t)b * k + cc]);
+          }
+          // leave the FP32 phase when it has done its part (rho <= switch_tol),
+          // when it stagnates at the FP32 operators' accuracy (rho not halved
+          // over two iterations) or at the iteration cap
+          rhist.push_back(rmax);
+          const size_t nh = rhist.size();
+          const bool stalled = nh >= 3 && !(rhist[nh - 1] <= 0.5 * rhist[nh - 3]);
+          if (!(rmax <= switch_tol) && !stalled && ++fp32_iters < fp32_cap) {
+            // stay in the FP32 phase
+          } else {
+            c.use32 = false;
+            const int64_t n = p->dofs_total * k;
+            k_keep_classes<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, c.s>>>(c.v.cls, vcls, k, n,
+                                                                                                 B[0][0]);
+            LAUNCHCHK(p);
+            if (images(B[0][0], B[1][0], B[2][0], B[3][0], act)) return MSGFEM_EHIP;
+            if (deflate(r, 0, act)) return MSGFEM_EHIP;
+            if (rr_x(act)) return MSGFEM_EHIP;
+            restart = true;
+            continue;
+          }
+        }
+      }
+      // soft locking of converged columns (their W and P directions vanish)
+      {
+        dim3 grid((unsigned)(((int64_t)p->max_dof * k + 255) / 256), nb);
+        const bool hasP = it > 0 && !restart;
+        k_lock<<<grid, 256, 0, c.s>>>(c.v.meta, k, c.w.rho, lock_tol, B[0][1],
+                                      hasP ? B[0][2] : nullptr, hasP ? B[1][2] : nullptr,
+                                      hasP ? B[2][2] : nullptr, (hasP && !geneo) ? B[3][2] : nullptr, act);
+        LAUNCHCHK(p);
+      }
+      // W = preconditioned residual: B2 trace of (A + s DAD)^{-1} [0; R]
+      if (solve(c, 1, B[0][1], B[0][1], k, vcls, 1, act)) return MSGFEM_EHIP;
+      if (images(B[0][1], B[1][1], B[2][1], B[3][1], act)) return MSGFEM_EHIP;
+      if (deflate(r, 1, act)) return MSGFEM_EHIP;
+      int nblk = (it == 0 || restart) ? 2 : 3;
+      restart = false;
+      double* Zb[3] = {B[0][0], B[0][1], B[0][2]};
+      double* Ab[3] = {B[1][0], B[1][1], B[1][2]};
+      double* Bb[3] = {B[2][0], B[2][1], B[2][2]};
+      if (gram(c, nblk, Zb, Ab, Bb, act)) return MSGFEM_EHIP;
+      Blk4x3 Z;
+      Out4 OX, OP;
+      for (int kind = 0; kind < 4; ++kind) {
+        for (int b = 0; b < 3; ++b) Z.p[kind][b] = b < nblk ? B[kind][b] : nullptr;
+        OX.p[kind] = B[kind][3];
+        OP.p[kind] = B[kind][4];
+      }
+      double by = 0, fl = 0;
+      for (int b = 0; b < nb; ++b) {
+        if (!c.counts(b, act)) continue;
+        const BoxMeta& mt = p->meta[b];
+        by += 4 * 8.0 * mt.n_dof * k * (nblk + 2);
+        fl += 4 * 2 * 2.0 * mt.n_dof * (nblk * k) * k;
+      }
+      ProfScope ps(p, PK_UPDATE, c.s, by, fl);
+      k_update<2><<<ugrid, UPD_THREADS, (size_t)2 * nblk * k * k * 8, c.s>>>(c.v.meta, nblk, k, Z, OX, OP, c.w.Y,
+                                                                            c.w.Yp, act);
+      LAUNCHCHK(p);
+      for (int kind = 0; kind < 4; ++kind) {
+        std::swap(B[kind][0], B[kind][3]);
+        std::swap(B[kind][2], B[kind][4]);
+      }
     }
-    dim3 grid((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, nkinds);
-    double by = 0, fl = 0;
-    for (int b = 0; b < nb; ++b) {
-      if (!c.counts(b, act)) continue;
-      const BoxMeta& mt = p->meta[b];
-      by += 4 * 8.0 * mt.n_dof * k * (nblk + 2);
-      fl += 4 * 2 * 2.0 * mt.n_dof * (nblk * k) * k;
-    }
-    ProfScope ps(p, PK_UPDATE, c.s, by, fl);
-    k_update<<<grid, UPD_THREADS, (size_t)2 * nblk * k * k * 8, c.s>>>(c.v.meta, nblk, k, Z, OX, OP, c.w.Y,
-                                                                c.w.Yp, act);
+    // this round's pairs (k_converge has set bit 1 on the boxes still active
+    // after maxit); its converged block is kept for the later rounds
+    HIPCHK(p, hipMemcpyAsync(act, act_r.data(), nb * 4, hipMemcpyHostToDevice, c.s));
+    k_output<<<nb, 1024, 0, c.s>>>(c.v.meta, k, p->opts.shift, B[0][0], c.w.nu, c.w.rho, evals, evecs, resid,
+                                  act, col0, nround);
     LAUNCHCHK(p);
-    (void)lds_upd3;
-    for (int kind = 0; kind < 4; ++kind) {
-      std::swap(B[kind][0], B[kind][3]);
-      std::swap(B[kind][2], B[kind][4]);
+    if (r + 1 < p->rounds) {
+      dim3 grid((unsigned)std::min<int64_t>(((int64_t)p->max_dof * k + 255) / 256, 4096), nb);
+      for (int kind = 0; kind < nkinds; ++kind)
+        k_keep_cols<<<grid, 256, 0, c.s>>>(c.v.meta, k, col0, nround, B[kind][0], Yblk(r, kind));
+      LAUNCHCHK(p);
     }
+    HIPCHK(p, hipStreamSynchronize(c.s));   // act_r is read by the copy above
   }
-  // outputs (k_converge has set bit 1 on the boxes still active after maxit)
-  k_output<<<nb, 1024, 0, c.s>>>(c.v.meta, k, p->opts.shift, B[0][0], c.w.nu, c.w.rho, evals, evecs, resid,
-                                mask);
-  LAUNCHCHK(p);
   if (mask)
     k_copy_masked_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(nb, mask, c.w.iters, iters);
   else
@@ -1338,7 +1448,7 @@ static int coarse_plan(msgfem_plan* p) {
     }
   }
   p->pair_start[nb] = (int)p->pairs.size();
-  const int64_t k = p->k, nd = p->dofs_total, np = (int64_t)p->pairs.size();
+  const int64_t kv = p->kv, nd = p->dofs_total, np = (int64_t)p->pairs.size();
   int64_t off = 0;
   p->c_faces = off; off = align256(off + 6 * sizeof(FaceLoad));
   p->c_pairs = off; off = align256(off + np * sizeof(CoarsePair));
@@ -1348,11 +1458,11 @@ static int coarse_plan(msgfem_plan* p) {
   p->c_bload = off; off = align256(off + nd * 8);
   p->c_psi = off; off = align256(off + nd * 8);
   p->c_pv = off; off = align256(off + nd * 8);
-  p->c_V = off; off = align256(off + nd * k * 8);
-  p->c_Vn = off; off = align256(off + nd * k * 8);
-  p->c_AV = off; off = align256(off + nd * k * 8);
+  p->c_V = off; off = align256(off + nd * kv * 8);
+  p->c_Vn = off; off = align256(off + nd * kv * 8);
+  p->c_AV = off; off = align256(off + nd * kv * 8);
   p->c_Ap = off; off = align256(off + nd * 8);
-  p->c_rpart = off; off = align256(off + np * 32 * 8);
+  p->c_rpart = off; off = align256(off + np * kv * 8);
   p->c_tiles = off; off = align256(off + ((int64_t)p->NTc * p->NTc + p->NTc) * 1024 * 8);
   p->c_y = off; off = align256(off + 2 * (int64_t)p->NTc * 32 * 8);
   p->coarse_bytes = off;
@@ -1484,7 +1594,7 @@ extern "C" int msgfem_coarse_assemble(msgfem_plan* p, const void* ops, void* wor
   hipStream_t s = (hipStream_t)stream;
   OpsView v = ops_view(p, ops);
   char* cb = (char*)coarse;
-  const int nb = (int)p->meta.size(), k = p->k, NH = p->NH;
+  const int nb = (int)p->meta.size(), k = p->kv, NH = p->NH;
   // load description and pair tables
   std::vector<FaceLoad> faces;
   if (load) {
@@ -1556,7 +1666,8 @@ extern "C" int msgfem_coarse_assemble(msgfem_plan* p, const void* ops, void* wor
     }
     Zu.p[0][0] = V;
     OX.p[0] = Vn;
-    k_update<<<dim3((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, 1), UPD_THREADS, (size_t)2 * k * k * 8, s>>>(
+    auto upd = k <= 32 ? k_update<2> : k_update<6>;
+    upd<<<dim3((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, 1), UPD_THREADS, (size_t)2 * k * k * 8, s>>>(
         v.meta, 1, k, Zu, OX, OP, c.w.Y, c.w.Yp, nullptr);
     LAUNCHCHK(p);
     std::swap(V, Vn);
@@ -1568,9 +1679,9 @@ extern "C" int msgfem_coarse_assemble(msgfem_plan* p, const void* ops, void* wor
   k_fill_f64<<<1024, 256, 0, s>>>(AH, (int64_t)NH * NH, 0.0);
   if (!p->pairs.empty())
     k_coarse_pairs<<<(unsigned)p->pairs.size(), 256, 0, s>>>(v.meta, (const CoarsePair*)(cb + p->c_pairs), k, V, AV,
-                                                            Ap, NH, AH, rpart);
+                                                            Ap, NH, k, AH, rpart);
   k_coarse_rhs<<<nb, 256, 0, s>>>(v.meta, k, V, bload, (const int32_t*)(cb + p->c_pstart),
-                                  (const int32_t*)(cb + p->c_roff), NH, rpart, AH, bH);
+                                  (const int32_t*)(cb + p->c_roff), NH, k, rpart, AH, bH);
   LAUNCHCHK(p);
   (void)status;
   return MSGFEM_OK;
@@ -1587,7 +1698,7 @@ extern "C" int msgfem_coarse_solve(msgfem_plan* p, const void* ops, void* work, 
   hipStream_t s = (hipStream_t)stream;
   OpsView v = ops_view(p, ops);
   char* cb = (char*)coarse;
-  const int NT = p->NTc, NH = p->NH, k = p->k;
+  const int NT = p->NTc, NH = p->NH, k = p->kv;
   double* tiles = (double*)(cb + p->c_tiles);
   k_fill_i32<<<1, 32, 0, s>>>(status, 1, 0);
   k_dense_tiles<<<2048, 256, 0, s>>>(AH, NH, NT, tiles);
@@ -1660,7 +1771,7 @@ extern "C" int msgfem_geneo_pcg(msgfem_plan* p, const void* ops, void* work, voi
   char* cb = (char*)coarse;
   char* pb = (char*)pcg;
   const PcgLayout L = pcg_layout(p);
-  const int nb = (int)p->meta.size(), k = p->k, NT = p->NTc, NH = p->NH;
+  const int nb = (int)p->meta.size(), k = p->kv, NT = p->NTc, NH = p->NH;
   const int64_t ng = p->n_nodes_global, nd = 3 * ng;
   MeshDev md = mesh_dev(p);
   // whole-mesh box: stencil, classes (B1 free, B3 clamped), zero PoU
@@ -1857,7 +1968,8 @@ extern "C" int msgfem_coarse_create(msgfem_coarse** out, int device, const msgfe
       c->omega[6 * j + 3 + d] = std::min(cr[3 + d] + dec->overlap, N[d]);
     }
     if (dec->ovs[j] < 0) return cfail(c, MSGFEM_EARG, "ovs[%d] < 0", j);
-    if (n_ev[j] < 1 || n_ev[j] > 32) return cfail(c, MSGFEM_EARG, "n_ev[%d] = %d outside [1, 32]", j, n_ev[j]);
+    if (n_ev[j] < 1 || n_ev[j] > MAX_NEV)
+      return cfail(c, MSGFEM_EARG, "n_ev[%d] = %d outside [1, %d]", j, n_ev[j], MAX_NEV);
   }
   c->meta.resize(dec->nsd);
   int64_t dof_off = 0, node_off = 0, loc_off = 0;
@@ -1934,7 +2046,7 @@ extern "C" int msgfem_coarse_create(msgfem_coarse** out, int device, const msgfe
   c->s_pv = off; off = align256(off + nd * 8);
   c->s_Ap = off; off = align256(off + nd * 8);
   c->s_bload = off; off = align256(off + nd * 8);
-  c->s_rpart = off; off = align256(off + np * 32 * 8);
+  c->s_rpart = off; off = align256(off + np * K * 8);
   c->s_rc = off; off = align256(off + (int64_t)c->NTc * 32 * 8);
   c->s_tiles = off; off = align256(off + ((int64_t)c->NTc * c->NTc + c->NTc) * 1024 * 8);
   c->s_y = off; off = align256(off + 2 * (int64_t)c->NTc * 32 * 8);
@@ -2027,12 +2139,12 @@ extern "C" int msgfem_coarse_add(msgfem_coarse* c, msgfem_plan* p, const void* o
   x.s = s;
   x.nb = (int)p->meta.size();
   x.k = p->k;
-  const int k = p->k, nb = x.nb;
-  const int64_t VT = p->vec_total, nd = p->dofs_total;
+  const int k = p->kv, nb = x.nb;
+  const int64_t nd = p->dofs_total, VK = nd * k;
   double* V = x.w.vec;
-  double* Vn = x.w.vec + VT;
-  double* AV = x.w.vec + 2 * VT;
-  double* psi = x.w.vec + 3 * VT;
+  double* Vn = x.w.vec + VK;
+  double* AV = x.w.vec + 2 * VK;
+  double* psi = x.w.vec + 3 * VK;
   double* pv = psi + nd;
   double* Ap = psi + 2 * nd;
   double* bload = psi + 3 * nd;
@@ -2061,7 +2173,8 @@ extern "C" int msgfem_coarse_add(msgfem_coarse* c, msgfem_plan* p, const void* o
     }
     Zu.p[0][0] = V;
     OX.p[0] = Vn;
-    k_update<<<dim3((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, 1), UPD_THREADS, (size_t)2 * k * k * 8, s>>>(
+    auto upd = k <= 32 ? k_update<2> : k_update<6>;
+    upd<<<dim3((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, 1), UPD_THREADS, (size_t)2 * k * k * 8, s>>>(
         x.v.meta, 1, k, Zu, OX, OP, x.w.Y, x.w.Yp, nullptr);
     CLAUNCHCHK(c);
     std::swap(V, Vn);
@@ -2102,11 +2215,12 @@ extern "C" int msgfem_coarse_galerkin(msgfem_coarse* c, void* store, double* AH,
     k_coarse_pairs<<<(unsigned)c->pairs.size(), 256, 0, s>>>((const BoxMeta*)(st + c->s_meta),
                                                              (const CoarsePair*)(st + c->s_pairs), c->kc,
                                                              (const double*)(st + c->s_V), (const double*)(st + c->s_AV),
-                                                             (const double*)(st + c->s_Ap), NH, AH,
+                                                             (const double*)(st + c->s_Ap), NH, c->kc, AH,
                                                              (double*)(st + c->s_rpart));
   k_coarse_rhs<<<c->nsd, 256, 0, s>>>((const BoxMeta*)(st + c->s_meta), c->kc, (const double*)(st + c->s_V),
                                       (const double*)(st + c->s_bload), (const int32_t*)(st + c->s_pstart),
-                                      (const int32_t*)(st + c->s_roff), NH, (const double*)(st + c->s_rpart), AH, bH);
+                                      (const int32_t*)(st + c->s_roff), NH, c->kc, (const double*)(st + c->s_rpart),
+                                      AH, bH);
   CLAUNCHCHK(c);
   return MSGFEM_OK;
 }

@@ -200,12 +200,13 @@ __global__ __launch_bounds__(256) void k_cholqr_coef(int k, const double* __rest
 }
 
 // One workgroup per pair.  outputs (a, b), a < n_ev(i), b <= n_ev(j) (b = n_ev(j)
-// is the particular column); AH row-major NH x NH; rpart[pair][32].
+// is the particular column); AH row-major NH x NH; rpart[pair][rstride]
+// (rstride >= every n_ev).
 __global__ __launch_bounds__(256) void k_coarse_pairs(const BoxMeta* __restrict__ meta,
                                                       const CoarsePair* __restrict__ pairs, int k,
                                                       const double* __restrict__ V,
                                                       const double* __restrict__ AV,
-                                                      const double* __restrict__ Ap, int NH,
+                                                      const double* __restrict__ Ap, int NH, int rstride,
                                                       double* __restrict__ AH,
                                                       double* __restrict__ rpart) {
   const CoarsePair pr = pairs[blockIdx.x];
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(256) void k_coarse_pairs(const BoxMeta* __restrict_
       }
     }
     if (b < bj.n_ev) AH[(int64_t)(pr.row_off + a) * NH + pr.col_off + b] = acc;
-    else rpart[(int64_t)blockIdx.x * 32 + a] = acc;
+    else rpart[(int64_t)blockIdx.x * rstride + a] = acc;
   }
 }
 
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(256) void k_coarse_rhs(const BoxMeta* __restrict__ 
                                                     const double* __restrict__ V,
                                                     const double* __restrict__ bload,
                                                     const int32_t* __restrict__ pair_start,
-                                                    const int32_t* __restrict__ row_off, int NH,
+                                                    const int32_t* __restrict__ row_off, int NH, int rstride,
                                                     const double* __restrict__ rpart,
                                                     double* __restrict__ AH,
                                                     double* __restrict__ bH) {
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(256) void k_coarse_rhs(const BoxMeta* __restrict__ 
     }
     if (threadIdx.x == 0) {
       double r = red[0];
-      for (int p = pair_start[box]; p < pair_start[box + 1]; ++p) r -= rpart[(int64_t)p * 32 + a];
+      for (int p = pair_start[box]; p < pair_start[box + 1]; ++p) r -= rpart[(int64_t)p * rstride + a];
       const int64_t l = row_off[box] + a;
       bH[l] = r;
       if (AH[l * NH + l] == 0.0) AH[l * NH + l] = 1.0;

@@ -547,10 +547,12 @@ struct Out4 {
 // Z = [Z_0 .. Z_{nblk-1}] of m = nblk*k columns, Y and Yp m x k per box.
 // FP64 matrix cores (16x16x4): a wavefront takes 16 rows at a time (4 blocks
 // of 16 rows per wavefront, UPD_ROWS rows per workgroup); the inner index
-// runs over the m columns of Z in steps of 4, the output columns in blocks
-// of 16 (k <= 32); Y and Yp are staged in LDS once per workgroup.
+// runs over the m columns of Z in steps of 4, the output columns in CB blocks
+// of 16 (k <= 16 CB: 2 for the LOBPCG block, 6 for a coarse basis of up to
+// 96 columns); Y and Yp are staged in LDS once per workgroup.
 // grid (ceil(max n_dof / UPD_ROWS), n_box, kinds); dynamic LDS = 2*m*k doubles
-__global__ __launch_bounds__(UPD_THREADS, 3) void k_update(const BoxMeta* __restrict__ meta, int nblk, int k,
+template <int CB>
+__global__ __launch_bounds__(UPD_THREADS, CB == 2 ? 3 : 1) void k_update(const BoxMeta* __restrict__ meta, int nblk, int k,
                                                 Blk4x3 Z, Out4 OX, Out4 OP,
                                                 const double* __restrict__ Y,
                                                 const double* __restrict__ Yp,
@@ -589,9 +591,9 @@ __global__ __launch_bounds__(UPD_THREADS, 3) void k_update(const BoxMeta* __rest
     if (r0 >= bm.n_dof) break;
     const int row = r0 + li;
     const bool rok = row < bm.n_dof;
-    dbl4 ax[2], ap[2];
+    dbl4 ax[CB], ap[CB];
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
+    for (int cb = 0; cb < CB; ++cb) {
       ax[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
       ap[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
     }
@@ -611,7 +613,7 @@ __global__ __launch_bounds__(UPD_THREADS, 3) void k_update(const BoxMeta* __rest
       if (st < nsteps) {
         const int i = 4 * st + lk;
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < CB; ++cb) {
           const int col = 16 * cb + li;
           const bool ok = i < m && col < k;
           ax[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ok ? ys[i * k + col] : 0.0, ax[cb], 0, 0, 0);
@@ -636,7 +638,7 @@ __global__ __launch_bounds__(UPD_THREADS, 3) void k_update(const BoxMeta* __rest
     double* ox = OX.p[kind] + base;
     double* op = wantP ? OP.p[kind] + base : nullptr;
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
+    for (int cb = 0; cb < CB; ++cb) {
       const int col = 16 * cb + li;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -647,6 +649,50 @@ __global__ __launch_bounds__(UPD_THREADS, 3) void k_update(const BoxMeta* __rest
         }
       }
     }
+  }
+}
+
+template __global__ void k_update<2>(const BoxMeta*, int, int, Blk4x3, Out4, Out4, const double*, const double*,
+                                     const int32_t*);
+template __global__ void k_update<6>(const BoxMeta*, int, int, Blk4x3, Out4, Out4, const double*, const double*,
+                                     const int32_t*);
+
+// Deflation against the converged block Yq of an earlier round (Z = [W, Yq]):
+// Yc = [I; -C] with C = (T Yq)^T W, the cross block of the T-Gram matrix
+// G_S + s G_M of [W, Yq] (m = 2k; Yq is T-orthonormal with zero guard
+// columns), so that k_update forms W - Yq C for every image kind.
+__global__ void k_proj_coef(int k, double shift, const double* __restrict__ G, double* __restrict__ Yc,
+                            const int32_t* __restrict__ active) {
+  const int box = blockIdx.x;
+  if (active && !active[box]) return;
+  const int m = 2 * k, mm = m * m;
+  const double* GS = G + (int64_t)box * 2 * mm;
+  const double* GM = GS + mm;
+  double* Y = Yc + (int64_t)box * m * k;
+  for (int t = threadIdx.x; t < m * k; t += blockDim.x) {
+    const int i = t / k, c = t % k;
+    double v;
+    if (i < k) {
+      v = (i == c) ? 1.0 : 0.0;
+    } else {
+      const int e = i * m + c;   // row k + q (Yq column q), column c (W column c)
+      v = -(GS[e] + shift * GM[e]);
+    }
+    Y[t] = v;
+  }
+}
+
+// dst = src on the first cnt columns of every box, 0 on the others, cnt =
+// min(nround, n_ev - col0): a round's converged block with its guard columns
+// cleared (flat over the boxes' [n_dof][k] blocks; grid (rows, n_box))
+__global__ void k_keep_cols(const BoxMeta* __restrict__ meta, int k, int col0, int nround,
+                            const double* __restrict__ src, double* __restrict__ dst) {
+  const BoxMeta& bm = meta[blockIdx.y];
+  const int cnt = min(nround, bm.n_ev - col0);
+  const int64_t n = (int64_t)bm.n_dof * k;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(t % k);
+    dst[bm.dof_off * k + t] = c < cnt ? src[bm.dof_off * k + t] : 0.0;
   }
 }
 
@@ -705,23 +751,34 @@ __global__ __launch_bounds__(RES_THREADS) void k_residual(const BoxMeta* __restr
   }
 }
 
-// Per box: rho from the partial sums; converged when every one of the first
-// n_ev columns has rho <= tol.  A column whose rho is not a finite number
-// (a zero or non-finite denominator, or a non-finite residual) sets status
-// bit 8; a box with bit 4 (a non-positive pivot in its factors) or bit 8 is
-// retired at once as failed, so it does not hold the batch loop.  On the last
-// iteration (last != 0) a box still unconverged gets bit 1.  Updates
-// active/iters and the count of boxes still active.
+// Per box: rho from the partial sums of this round's pairs (nev = min(nround,
+// n_ev - col0) of them, the box's pairs col0 ..).  On the box's last round
+// the pairs are converged at rho <= tol.  On a round that later rounds deflate
+// against, the target is tol_defl (< tol): an error e in those vectors limits
+// the later pairs' residuals to about (nu_earlier / nu_later) |e|; a box that
+// meets tol but stalls short of tol_defl (near the rounding floor of its
+// images) is retired STALL_ITERS iterations after it met tol (reached[box] =
+// that iteration, -1 before).
+// A column whose rho is not a finite number (a zero or non-finite
+// denominator, or a non-finite residual) sets status bit 8; a box with bit 4
+// (a non-positive pivot in its factors) or bit 8 is retired at once as failed,
+// so it does not hold the batch loop.  On the last iteration (last != 0) a box
+// still active whose pairs miss tol gets bit 1.  Updates active/iters and the
+// count of boxes still active.
+#define STALL_ITERS 6
 __global__ void k_converge(const BoxMeta* __restrict__ meta, int n_box, int k, int n_chunk,
                            const double* __restrict__ part, const double* __restrict__ nu,
-                           double tol, double* __restrict__ rho, int32_t* __restrict__ active,
+                           double tol, double tol_defl, double* __restrict__ rho, int32_t* __restrict__ active,
                            int32_t* __restrict__ iters, int32_t* __restrict__ n_active,
-                           int last, int32_t* __restrict__ status) {
+                           int last, int32_t* __restrict__ status, int col0, int nround, int it,
+                           int32_t* __restrict__ reached) {
   // one wavefront per box, lane c < k takes column c (chunks summed in order)
   const int box = blockIdx.x, c = threadIdx.x;
   if (box >= n_box || !active[box]) return;
-  const int nev = meta[box].n_ev;
-  bool ok = true, fin = true;
+  const int nev = min(nround, meta[box].n_ev - col0);
+  const bool last_round = meta[box].n_ev - col0 <= nround;
+  const double tol_eff = last_round ? tol : tol_defl;
+  bool ok = true, ok_user = true, fin = true;
   if (c < k) {
     double a = 0.0, b = 0.0, d = 0.0;
     for (int ch = 0; ch < n_chunk; ++ch) {
@@ -731,27 +788,37 @@ __global__ void k_converge(const BoxMeta* __restrict__ meta, int n_box, int k, i
       d += p[64 + c];
     }
     const double v = nu[(int64_t)box * k + c];
-    const double den = sqrt(b) + v * sqrt(d);
+    // |nu|: a Ritz value at rounding level may come out slightly negative
+    const double den = sqrt(b) + fabs(v) * sqrt(d);
     // rho is defined for a positive finite denominator only (a zero column, or
     // one with M x = T x = 0, has no eigenvalue)
     const double r = (den > 0.0 && den <= DBL_MAX) ? sqrt(a) / den : __builtin_nan("");
     rho[(int64_t)box * k + c] = r;
     if (c < nev) {
       fin = r <= DBL_MAX;          // false for NaN and inf
-      ok = r <= tol;
+      ok = r <= tol_eff;
+      ok_user = r <= tol;
     }
   }
   const bool all_ok = __all(ok);
+  const bool all_user = __all(ok_user);
   const bool all_fin = __all(fin);
   if (c == 0) {
     int32_t st = status[box];
     if (!all_fin) st |= 8;
+    bool retire = false;
     if (st & (4 | 8)) {
-      active[box] = 0;             // failed: retired, not converged
+      retire = true;             // failed: retired, not converged
     } else if (all_ok) {
+      retire = true;
+    } else if (all_user && !last_round) {
+      if (reached[box] < 0) reached[box] = it;
+      retire = it - reached[box] >= STALL_ITERS;
+    }
+    if (retire) {
       active[box] = 0;
     } else {
-      if (last) st |= 1;
+      if (last && !all_user) st |= 1;
       iters[box] += last ? 0 : 1;
       atomicAdd(n_active, 1);
     }
@@ -848,7 +915,7 @@ __global__ __launch_bounds__(OUT_THREADS) void k_output(const BoxMeta* __restric
                                                 double* __restrict__ evals,
                                                 double* __restrict__ evecs,
                                                 double* __restrict__ resid,
-                                                const int32_t* __restrict__ mask) {
+                                                const int32_t* __restrict__ mask, int col0, int nround) {
   __shared__ double sn[OUT_THREADS];
   __shared__ double sa[OUT_THREADS];
   __shared__ int si[OUT_THREADS];
@@ -857,7 +924,11 @@ __global__ __launch_bounds__(OUT_THREADS) void k_output(const BoxMeta* __restric
   if (mask && !mask[box]) return;   // a box the caller did not select keeps its output
   const BoxMeta& bm = meta[box];
   const int tid = threadIdx.x, col = tid & 31, slot = tid >> 5;
-  const int nev = bm.n_ev;
+  // this round writes pairs col0 .. col0 + nev - 1 of the box (columns of X
+  // 0 .. nev - 1); the rows of evecs hold all n_ev pairs
+  const int nev = min(nround, bm.n_ev - col0);
+  if (nev <= 0) return;
+  const int ld = bm.n_ev;
   double s2 = 0.0, amax = -1.0;
   int imax = 0x7fffffff;
   if (col < nev) {
@@ -886,13 +957,13 @@ __global__ __launch_bounds__(OUT_THREADS) void k_output(const BoxMeta* __restric
     double sg = (v < 0.0) ? -1.0 : 1.0;
     scale[tid] = sg / sqrt(n2);
     double nv = nu[(int64_t)box * k + tid];
-    evals[bm.eval_off + tid] = 1.0 / nv - shift;
-    resid[bm.eval_off + tid] = rho[(int64_t)box * k + tid];
+    evals[bm.eval_off + col0 + tid] = 1.0 / nv - shift;
+    resid[bm.eval_off + col0 + tid] = rho[(int64_t)box * k + tid];
   }
   __syncthreads();
   for (int64_t t = tid; t < (int64_t)bm.n_dof * nev; t += OUT_THREADS) {
     int row = (int)(t / nev), c = (int)(t % nev);
-    evecs[bm.evec_off + t] = X[(bm.dof_off * k) + (int64_t)row * k + c] * scale[c];
+    evecs[bm.evec_off + (int64_t)row * ld + col0 + c] = X[(bm.dof_off * k) + (int64_t)row * k + c] * scale[c];
   }
 }
 

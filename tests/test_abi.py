@@ -83,7 +83,16 @@ def test_plan_rejects_bad_arguments():
     lib, plan, rc, _ = _plan(prob, batch=[7], n_ev=[10])
     assert rc == msgfem.MSGFEM_EARG
     lib.msgfem_plan_destroy(plan)
+    lib, plan, rc, _ = _plan(prob, n_ev=[49, 10, 10, 10])
+    assert rc == msgfem.MSGFEM_EARG
+    lib.msgfem_plan_destroy(plan)
+    # more than 32 pairs: deflated rounds with block 32 (another block is refused)
     lib, plan, rc, _ = _plan(prob, n_ev=[40, 10, 10, 10])
+    assert rc == 0
+    s = msgfem.msgfem_sizes()
+    assert lib.msgfem_plan_sizes(plan, ctypes.byref(s)) == 0 and s.block == 32
+    lib.msgfem_plan_destroy(plan)
+    lib, plan, rc, _ = _plan(prob, n_ev=[40, 10, 10, 10], block=24)
     assert rc == msgfem.MSGFEM_EARG
     lib.msgfem_plan_destroy(plan)
     lib, plan, rc, _ = _plan(prob, precision=5)
@@ -141,7 +150,7 @@ def test_subset_and_adaptive_reject_bad_arguments():
         == msgfem.MSGFEM_EARG
     assert b"null mask" in lib.msgfem_plan_error(plan)
     lib.msgfem_plan_destroy(plan)
-    for t, n0, nmax in ((0.0, 8, 32), (-1.0, 8, 32), (0.1, 0, 32), (0.1, 16, 8), (0.1, 8, 40)):
+    for t, n0, nmax in ((0.0, 8, 32), (-1.0, 8, 32), (0.1, 0, 32), (0.1, 16, 8), (0.1, 8, 49)):
         with pytest.raises(ValueError):
             adaptive.adaptive_local_spaces(prob, t, n_ev0=n0, n_ev_max=nmax)
 
