@@ -152,6 +152,31 @@ const char *msgfem_plan_error(const msgfem_plan *plan);
 int msgfem_plan_sizes(const msgfem_plan *plan, msgfem_sizes *out);
 int msgfem_plan_box(const msgfem_plan *plan, int32_t b, msgfem_box_info *out);
 
+/* Plan options, set on the host between calls (they apply from the next call).
+ *   MSGFEM_OPT_GRAPH: 0 (default) = every LOBPCG iteration of msgfem_local_eigs
+ *     is launched kernel by kernel, with one 4-byte read of the active flags
+ *     (a stream synchronisation) per iteration.  1 = the iterations after the
+ *     first of each deflated round (FP64 operators, search block [X, W, P]) run
+ *     as HIP graphs of 4 (first round) or 6 (later rounds) iterations, captured
+ *     on the plan's own non-blocking stream on first use and launched on the
+ *     caller's stream, with one read of the active count per launch.  A box
+ *     that converges inside a launch is retired there and skipped by every
+ *     later kernel, so evals, evecs, resid, iters and status are bitwise those
+ *     of mode 0.  Iterations near maxit, the FP32 phase of precision 2 and
+ *     profiled calls (msgfem_profile) stay eager.  The plan keeps up to 8
+ *     instantiated graphs, keyed by the ops, work and status pointers (a call
+ *     with other buffers captures again); setting 0 releases them.
+ * msgfem_plan_set_option returns MSGFEM_EARG for an unknown key or value.
+ * msgfem_plan_get_option reads an option or one of the counters of the last
+ * msgfem_local_eigs call: MSGFEM_INFO_GRAPH_LAUNCHES (graph launches),
+ * MSGFEM_INFO_GRAPH_ITERS (iterations they ran), MSGFEM_INFO_GRAPHS_CACHED. */
+#define MSGFEM_OPT_GRAPH 1
+#define MSGFEM_INFO_GRAPH_LAUNCHES 100
+#define MSGFEM_INFO_GRAPH_ITERS 101
+#define MSGFEM_INFO_GRAPHS_CACHED 102
+int msgfem_plan_set_option(msgfem_plan *plan, int32_t key, int64_t value);
+int msgfem_plan_get_option(const msgfem_plan *plan, int32_t key, int64_t *value);
+
 /* Assemble the local operators of every batch box into `ops` (device,
  * ops_bytes): material tensors, partition-of-unity weight sums over all
  * subdomains (Sec. 4.2), block-27 stencils of a_{Omega*} (Sec. 2), DoF

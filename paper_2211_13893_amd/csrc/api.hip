@@ -55,11 +55,13 @@ template <int CB>
 __global__ void k_update(const BoxMeta*, int, int, Blk4x3, Out4, Out4, const double*, const double*,
                          const int32_t*);
 __global__ void k_proj_coef(int, double, const double*, double*, const int32_t*);
-__global__ void k_keep_cols(const BoxMeta*, int, int, int, const double*, double*);
+__global__ void k_keep_cols(const BoxMeta*, int, int, int, XLoc, int, double*);
 __global__ void k_residual(const BoxMeta*, const uint8_t*, int, int, double, const double*, const double*,
                            const double*, double*, int, int, double*, const int32_t*);
 __global__ void k_converge(const BoxMeta*, int, int, int, const double*, const double*, double, double, double*,
-                           int32_t*, int32_t*, int32_t*, int, int32_t*, int, int, int, int32_t*);
+                           int32_t*, int32_t*, int32_t*, int, int32_t*, int, int, const int32_t*, int32_t*, int,
+                           int32_t*);
+__global__ void k_add_i32(int32_t*, int32_t);
 __global__ void k_status_clear(int, const int32_t*, int32_t*);
 __global__ void k_status_or(int32_t*, int, int32_t);
 __global__ void k_copy_masked_i32(int, const int32_t*, const int32_t*, int32_t*);
@@ -67,7 +69,7 @@ __global__ void k_random_start(const BoxMeta*, const uint8_t*, int, int, uint64_
 __global__ void k_lock(const BoxMeta*, int, const double*, double, double*, double*, double*, double*, double*,
                        const int32_t*);
 __global__ void k_copy_start(const BoxMeta*, const uint8_t*, int, int, const double*, double*);
-__global__ void k_output(const BoxMeta*, int, double, const double*, const double*, const double*,
+__global__ void k_output(const BoxMeta*, int, double, XLoc, const double*, const double*,
                          double*, double*, double*, const int32_t*, int, int);
 struct FaceLoad {
   int32_t axis, side;
@@ -158,7 +160,8 @@ struct msgfem_plan {
   int n_gchunk = 0;
   // work layout (bytes)
   int64_t w_vec = 0, w_part = 0, w_G = 0, w_L = 0, w_Y = 0, w_Yp = 0, w_nu = 0, w_rho = 0,
-          w_rpart = 0, w_active = 0, w_iters = 0, w_nact = 0, w_reached = 0, w_scr = 0, work_bytes = 0;
+          w_rpart = 0, w_active = 0, w_iters = 0, w_nact = 0, w_reached = 0, w_xbuf = 0, w_scr = 0,
+          work_bytes = 0;
   int64_t scr_stride = 0;
   // coarse problem (built on the first coarse call)
   bool coarse_ready = false;
@@ -180,6 +183,22 @@ struct msgfem_plan {
   std::vector<hipEvent_t> ev_pool;
   double prof_ms[16] = {}, prof_bytes[16] = {}, prof_flops[16] = {};
   int64_t prof_launches[16] = {};
+  // LOBPCG iterations captured in HIP graphs (msgfem_plan_set_option)
+  int graph_mode = 0;
+  hipStream_t cap_stream = nullptr;   // capture only: the graphs are launched on the caller's stream
+  struct GraphEntry {
+    const void* ops;
+    const void* work;
+    const int32_t* status;
+    int r, pre32;
+    double lock_tol;
+    double* B[4][5];
+    int L;                            // iterations per launch
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  int64_t graph_launches = 0;         // graph launches of the last msgfem_local_eigs call
+  int64_t graph_iters = 0;            // LOBPCG iterations they ran
   ~msgfem_plan();
 };
 
@@ -190,6 +209,8 @@ enum { PK_ASSEMBLE, PK_BUILD, PK_POTRF, PK_SOLVE, PK_SPMM, PK_GRAM, PK_RR, PK_UP
 msgfem_plan::~msgfem_plan() {
   for (auto& r : prof_pending) { ev_pool.push_back(r.b); ev_pool.push_back(r.e); }
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
 static hipEvent_t prof_event(msgfem_plan* p) {
@@ -476,8 +497,9 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   p->w_rpart = off; off = align256(off + (int64_t)nb * p->n_gchunk * 3 * 32 * 8);
   p->w_active = off; off = align256(off + (int64_t)nb * 4);
   p->w_iters = off; off = align256(off + (int64_t)nb * 4);
-  p->w_nact = off; off = align256(off + 4);
+  p->w_nact = off; off = align256(off + 8);   // active-box count, iteration index
   p->w_reached = off; off = align256(off + (int64_t)nb * 4);
+  p->w_xbuf = off; off = align256(off + (int64_t)nb * 4);
   p->w_scr = off; off = align256(off + (int64_t)nb * nchunk_solve * p->scr_stride * 8);
   p->work_bytes = off;
   return MSGFEM_OK;
@@ -770,6 +792,7 @@ struct Work {
   int32_t* iters;
   int32_t* nact;
   int32_t* reached;
+  int32_t* xbuf;
   double* scr;
 };
 }  // namespace
@@ -790,6 +813,7 @@ static Work work_view(const msgfem_plan* p, void* work) {
   w.iters = (int32_t*)(b + p->w_iters);
   w.nact = (int32_t*)(b + p->w_nact);
   w.reached = (int32_t*)(b + p->w_reached);
+  w.xbuf = (int32_t*)(b + p->w_xbuf);
   w.scr = (double*)(b + p->w_scr);
   return w;
 }
@@ -1095,6 +1119,11 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
   // Round r finds the pairs r*nround .. r*nround + nround - 1 of every box that
   // has that many (one round when n_ev <= 32), its block kept T-orthogonal to
   // the converged blocks of the earlier rounds
+  int32_t* it_dev = c.w.nact + 1;   // the iteration index k_converge sees
+  // physical buffer id (0..4) of a slot (the same for every image kind)
+  auto buf_id = [&](int sl) { return (int)((B[0][sl] - c.w.vec) / VT); };
+  const bool use_graph = p->graph_mode != 0 && !p->prof_on;
+  p->graph_launches = p->graph_iters = 0;
   for (int r = 0; r < p->rounds; ++r) {
     const int col0 = r * nround;
     std::vector<int32_t> act_r(nb);
@@ -1120,6 +1149,9 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
     bool restart = false;
     rhist.clear();
     k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(c.w.reached, nb, -1);
+    k_fill_i32<<<(nb + 255) / 256, 256, 0, c.s>>>(c.w.xbuf, nb, -1);
+    k_fill_i32<<<1, 32, 0, c.s>>>(it_dev, 1, 0);
+    LAUNCHCHK(p);
     // a round that later rounds deflate against converges to tol_defl
     bool deflated_later = false;
     for (int b = 0; b < nb; ++b) deflated_later |= act_r[b] && p->meta[b].n_ev - col0 > nround;
@@ -1130,75 +1162,39 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
     if (images(B[0][0], B[1][0], B[2][0], B[3][0], act)) return MSGFEM_EHIP;
     if (deflate(r, 0, act)) return MSGFEM_EHIP;
     if (rr_x(act)) return MSGFEM_EHIP;
-    for (int it = 0; it <= p->opts.maxit; ++it) {
-      // residual of the current Ritz block, convergence, active set
+    // first half of an iteration: residual of the current Ritz block,
+    // convergence, active set (boxes retired here keep X where it is)
+    auto head = [&](int last) -> int {
+      dim3 grid(n_chunk, nb);
+      k_residual<<<grid, 1024, 0, c.s>>>(c.v.meta, c.v.cls, vcls, k, p->opts.shift, B[1][0],
+                                        geneo ? B[2][0] : B[3][0], c.w.nu, B[0][1], GRAM_ROWS, n_chunk, c.w.rpart,
+                                        act);
+      LAUNCHCHK(p);
+      k_fill_i32<<<1, 32, 0, c.s>>>(c.w.nact, 1, 0);
+      // FP32 phase: residuals are estimates, no box is retired
+      k_converge<<<nb, 64, 0, c.s>>>(c.v.meta, nb, k, n_chunk, c.w.rpart, c.w.nu, c.use32 ? 0.0 : p->opts.tol,
+                                     c.use32 ? 0.0 : tol_defl, c.w.rho, act, c.w.iters, c.w.nact, last, status,
+                                     col0, nround, it_dev, c.w.reached, buf_id(0), c.w.xbuf);
+      k_add_i32<<<1, 32, 0, c.s>>>(it_dev, 1);
+      LAUNCHCHK(p);
+      return 0;
+    };
+    // second half: soft locking, preconditioned residual, images, deflation,
+    // Rayleigh-Ritz over [X, W] or [X, W, P], update; the slot -> buffer map
+    // rotates (X <-> Xn, P <-> Pn)
+    auto tail = [&](bool hasP, int nblk) -> int {
       {
-        dim3 grid(n_chunk, nb);
-        k_residual<<<grid, 1024, 0, c.s>>>(c.v.meta, c.v.cls, vcls, k, p->opts.shift, B[1][0],
-                                          geneo ? B[2][0] : B[3][0], c.w.nu,
-                                          B[0][1], GRAM_ROWS, n_chunk, c.w.rpart, act);
-        LAUNCHCHK(p);
-        k_fill_i32<<<1, 32, 0, c.s>>>(c.w.nact, 1, 0);
-        // FP32 phase: residuals are estimates, no box is retired
-        k_converge<<<nb, 64, 0, c.s>>>(c.v.meta, nb, k, n_chunk, c.w.rpart, c.w.nu,
-                                       c.use32 ? 0.0 : p->opts.tol, c.use32 ? 0.0 : tol_defl, c.w.rho, act,
-                                       c.w.iters, c.w.nact, it == p->opts.maxit ? 1 : 0, status, col0, nround, it,
-                                       c.w.reached);
-        LAUNCHCHK(p);
-        c.act_h.resize(nb);
-        HIPCHK(p, hipMemcpyAsync(c.act_h.data(), act, nb * 4, hipMemcpyDeviceToHost, c.s));
-        if (c.use32) {
-          rho_h.resize((size_t)nb * k);
-          HIPCHK(p, hipMemcpyAsync(rho_h.data(), c.w.rho, (size_t)nb * k * 8, hipMemcpyDeviceToHost, c.s));
-        }
-        HIPCHK(p, hipStreamSynchronize(c.s));
-        int nact = 0;
-        for (int b = 0; b < nb; ++b) nact += c.act_h[b] != 0;
-        if (nact == 0 || it == p->opts.maxit) break;
-        if (c.use32) {
-          double rmax = 0.0;
-          for (int b = 0; b < nb; ++b) {
-            if (!c.act_h[b]) continue;
-            const int nev = std::min(nround, p->meta[b].n_ev - col0);
-            for (int cc = 0; cc < nev; ++cc) rmax = std::max(rmax, rho_h[(size_t)b * k + cc]);
-          }
-          // leave the FP32 phase when it has done its part (rho <= switch_tol),
-          // when it stagnates at the FP32 operators' accuracy (rho not halved
-          // over two iterations) or at the iteration cap
-          rhist.push_back(rmax);
-          const size_t nh = rhist.size();
-          const bool stalled = nh >= 3 && !(rhist[nh - 1] <= 0.5 * rhist[nh - 3]);
-          if (!(rmax <= switch_tol) && !stalled && ++fp32_iters < fp32_cap) {
-            // stay in the FP32 phase
-          } else {
-            c.use32 = false;
-            const int64_t n = p->dofs_total * k;
-            k_keep_classes<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, c.s>>>(c.v.cls, vcls, k, n,
-                                                                                                 B[0][0]);
-            LAUNCHCHK(p);
-            if (images(B[0][0], B[1][0], B[2][0], B[3][0], act)) return MSGFEM_EHIP;
-            if (deflate(r, 0, act)) return MSGFEM_EHIP;
-            if (rr_x(act)) return MSGFEM_EHIP;
-            restart = true;
-            continue;
-          }
-        }
-      }
-      // soft locking of converged columns (their W and P directions vanish)
-      {
+        // soft locking of converged columns (their W and P directions vanish)
         dim3 grid((unsigned)(((int64_t)p->max_dof * k + 255) / 256), nb);
-        const bool hasP = it > 0 && !restart;
-        k_lock<<<grid, 256, 0, c.s>>>(c.v.meta, k, c.w.rho, lock_tol, B[0][1],
-                                      hasP ? B[0][2] : nullptr, hasP ? B[1][2] : nullptr,
-                                      hasP ? B[2][2] : nullptr, (hasP && !geneo) ? B[3][2] : nullptr, act);
+        k_lock<<<grid, 256, 0, c.s>>>(c.v.meta, k, c.w.rho, lock_tol, B[0][1], hasP ? B[0][2] : nullptr,
+                                      hasP ? B[1][2] : nullptr, hasP ? B[2][2] : nullptr,
+                                      (hasP && !geneo) ? B[3][2] : nullptr, act);
         LAUNCHCHK(p);
       }
       // W = preconditioned residual: B2 trace of (A + s DAD)^{-1} [0; R]
       if (solve(c, 1, B[0][1], B[0][1], k, vcls, 1, act)) return MSGFEM_EHIP;
       if (images(B[0][1], B[1][1], B[2][1], B[3][1], act)) return MSGFEM_EHIP;
       if (deflate(r, 1, act)) return MSGFEM_EHIP;
-      int nblk = (it == 0 || restart) ? 2 : 3;
-      restart = false;
       double* Zb[3] = {B[0][0], B[0][1], B[0][2]};
       double* Ab[3] = {B[1][0], B[1][1], B[1][2]};
       double* Bb[3] = {B[2][0], B[2][1], B[2][2]};
@@ -1225,17 +1221,144 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
         std::swap(B[kind][0], B[kind][3]);
         std::swap(B[kind][2], B[kind][4]);
       }
+      return 0;
+    };
+    // Steady-state iterations (after the first, with P, FP64 operators) run as
+    // HIP graphs of L iterations each, L the order of the slot rotation (the
+    // deflation of round r swaps W with the spare slot r times), so a launch
+    // leaves the slots where it found them.  The active count is read once per
+    // launch; a box converged inside a launch is retired by k_converge and
+    // every later kernel skips it, so the results are those of the eager loop.
+    int L = 0;
+    {
+      int perm[5] = {0, 1, 2, 3, 4};
+      for (int n = 1; n <= 12 && !L; ++n) {
+        for (int q = 0; q < r; ++q) std::swap(perm[1], perm[3]);
+        std::swap(perm[0], perm[3]);
+        std::swap(perm[2], perm[4]);
+        bool id = true;
+        for (int i = 0; i < 5; ++i) id = id && perm[i] == i;
+        if (id) L = n;
+      }
+      if (L && L < 4) L *= (4 + L - 1) / L;   // at least 4 iterations per launch
+    }
+    auto graph_get = [&](msgfem_plan::GraphEntry** out) -> int {
+      for (auto& g : p->graphs) {
+        if (g.ops == ops && g.work == work && g.status == status && g.r == r && g.pre32 == (int)c.pre32 &&
+            g.L == L && g.lock_tol == lock_tol && !memcmp(g.B, B, sizeof B)) {
+          *out = &g;
+          return 0;
+        }
+      }
+      if (!p->cap_stream) HIPCHK(p, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+      msgfem_plan::GraphEntry e{};
+      e.ops = ops;
+      e.work = work;
+      e.status = status;
+      e.r = r;
+      e.pre32 = (int)c.pre32;
+      e.L = L;
+      e.lock_tol = lock_tol;
+      memcpy(e.B, B, sizeof B);
+      const hipStream_t user = c.s;
+      c.s = p->cap_stream;
+      HIPCHK(p, hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
+      int rc = 0;
+      for (int j = 0; j < L && !rc; ++j) {
+        rc = head(0);
+        if (!rc) rc = tail(true, 3);
+      }
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(c.s, &graph);
+      c.s = user;
+      if (rc || ec != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc ? rc : fail(p, MSGFEM_EHIP, "LOBPCG graph capture: %s", hipGetErrorString(ec));
+      }
+      if (memcmp(e.B, B, sizeof B)) {
+        (void)hipGraphDestroy(graph);
+        return fail(p, MSGFEM_EHIP, "LOBPCG graph capture: slot rotation of order %d did not close", L);
+      }
+      const hipError_t ei = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return fail(p, MSGFEM_EHIP, "LOBPCG graph instantiate: %s", hipGetErrorString(ei));
+      if (p->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(p->graphs.front().exec);
+        p->graphs.erase(p->graphs.begin());
+      }
+      p->graphs.push_back(e);
+      *out = &p->graphs.back();
+      return 0;
+    };
+    for (int it = 0; it <= p->opts.maxit; ++it) {
+      if (use_graph && L && it >= 1 && !restart && !c.use32 && it + L <= p->opts.maxit) {
+        msgfem_plan::GraphEntry* g = nullptr;
+        if (graph_get(&g)) return MSGFEM_EHIP;
+        HIPCHK(p, hipGraphLaunch(g->exec, c.s));
+        int32_t nact_h = 0;
+        HIPCHK(p, hipMemcpyAsync(&nact_h, c.w.nact, 4, hipMemcpyDeviceToHost, c.s));
+        HIPCHK(p, hipStreamSynchronize(c.s));
+        p->graph_launches += 1;
+        p->graph_iters += L;
+        it += L - 1;
+        if (nact_h == 0) break;
+        continue;
+      }
+      if (head(it == p->opts.maxit ? 1 : 0)) return MSGFEM_EHIP;
+      c.act_h.resize(nb);
+      HIPCHK(p, hipMemcpyAsync(c.act_h.data(), act, nb * 4, hipMemcpyDeviceToHost, c.s));
+      if (c.use32) {
+        rho_h.resize((size_t)nb * k);
+        HIPCHK(p, hipMemcpyAsync(rho_h.data(), c.w.rho, (size_t)nb * k * 8, hipMemcpyDeviceToHost, c.s));
+      }
+      HIPCHK(p, hipStreamSynchronize(c.s));
+      int nact = 0;
+      for (int b = 0; b < nb; ++b) nact += c.act_h[b] != 0;
+      if (nact == 0 || it == p->opts.maxit) break;
+      if (c.use32) {
+        double rmax = 0.0;
+        for (int b = 0; b < nb; ++b) {
+          if (!c.act_h[b]) continue;
+          const int nev = std::min(nround, p->meta[b].n_ev - col0);
+          for (int cc = 0; cc < nev; ++cc) rmax = std::max(rmax, rho_h[(size_t)b * k + cc]);
+        }
+        // leave the FP32 phase when it has done its part (rho <= switch_tol),
+        // when it stagnates at the FP32 operators' accuracy (rho not halved
+        // over two iterations) or at the iteration cap
+        rhist.push_back(rmax);
+        const size_t nh = rhist.size();
+        const bool stalled = nh >= 3 && !(rhist[nh - 1] <= 0.5 * rhist[nh - 3]);
+        if (!(rmax <= switch_tol) && !stalled && ++fp32_iters < fp32_cap) {
+          // stay in the FP32 phase
+        } else {
+          c.use32 = false;
+          const int64_t n = p->dofs_total * k;
+          k_keep_classes<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, c.s>>>(c.v.cls, vcls, k, n,
+                                                                                               B[0][0]);
+          LAUNCHCHK(p);
+          if (images(B[0][0], B[1][0], B[2][0], B[3][0], act)) return MSGFEM_EHIP;
+          if (deflate(r, 0, act)) return MSGFEM_EHIP;
+          if (rr_x(act)) return MSGFEM_EHIP;
+          restart = true;
+          continue;
+        }
+      }
+      const bool hasP = it > 0 && !restart;
+      const int nblk = hasP ? 3 : 2;
+      restart = false;
+      if (tail(hasP, nblk)) return MSGFEM_EHIP;
     }
     // this round's pairs (k_converge has set bit 1 on the boxes still active
     // after maxit); its converged block is kept for the later rounds
     HIPCHK(p, hipMemcpyAsync(act, act_r.data(), nb * 4, hipMemcpyHostToDevice, c.s));
-    k_output<<<nb, 1024, 0, c.s>>>(c.v.meta, k, p->opts.shift, B[0][0], c.w.nu, c.w.rho, evals, evecs, resid,
-                                  act, col0, nround);
+    const XLoc xl{c.w.vec, VT, buf_id(0), c.w.xbuf};
+    k_output<<<nb, 1024, 0, c.s>>>(c.v.meta, k, p->opts.shift, xl, c.w.nu, c.w.rho, evals, evecs, resid, act, col0,
+                                  nround);
     LAUNCHCHK(p);
     if (r + 1 < p->rounds) {
       dim3 grid((unsigned)std::min<int64_t>(((int64_t)p->max_dof * k + 255) / 256, 4096), nb);
       for (int kind = 0; kind < nkinds; ++kind)
-        k_keep_cols<<<grid, 256, 0, c.s>>>(c.v.meta, k, col0, nround, B[kind][0], Yblk(r, kind));
+        k_keep_cols<<<grid, 256, 0, c.s>>>(c.v.meta, k, col0, nround, xl, kind, Yblk(r, kind));
       LAUNCHCHK(p);
     }
     HIPCHK(p, hipStreamSynchronize(c.s));   // act_r is read by the copy above
@@ -1371,6 +1494,34 @@ extern "C" int msgfem_profile(msgfem_plan* p, int32_t enable) {
   }
   p->prof_on = enable != 0;
   return MSGFEM_OK;
+}
+
+extern "C" int msgfem_plan_set_option(msgfem_plan* p, int32_t key, int64_t value) {
+  if (!p) return MSGFEM_EARG;
+  switch (key) {
+    case MSGFEM_OPT_GRAPH:
+      if (value != 0 && value != 1) return fail(p, MSGFEM_EARG, "MSGFEM_OPT_GRAPH takes 0 or 1, not %lld",
+                                               (long long)value);
+      p->graph_mode = (int)value;
+      if (!value) {
+        for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+        p->graphs.clear();
+      }
+      return MSGFEM_OK;
+    default:
+      return fail(p, MSGFEM_EARG, "unknown plan option %d", key);
+  }
+}
+
+extern "C" int msgfem_plan_get_option(const msgfem_plan* p, int32_t key, int64_t* value) {
+  if (!p || !value) return MSGFEM_EARG;
+  switch (key) {
+    case MSGFEM_OPT_GRAPH: *value = p->graph_mode; return MSGFEM_OK;
+    case MSGFEM_INFO_GRAPH_LAUNCHES: *value = p->graph_launches; return MSGFEM_OK;
+    case MSGFEM_INFO_GRAPH_ITERS: *value = p->graph_iters; return MSGFEM_OK;
+    case MSGFEM_INFO_GRAPHS_CACHED: *value = (int64_t)p->graphs.size(); return MSGFEM_OK;
+    default: return fail(const_cast<msgfem_plan*>(p), MSGFEM_EARG, "unknown plan option %d", key);
+  }
 }
 
 extern "C" int msgfem_profile_stats(msgfem_plan* p, msgfem_kernel_stat* out, int32_t max_out,

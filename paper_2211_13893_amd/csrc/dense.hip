@@ -560,17 +560,8 @@ __global__ __launch_bounds__(UPD_THREADS, CB == 2 ? 3 : 1) void k_update(const B
   extern __shared__ double sm[];
   int box = blockIdx.y, kind = blockIdx.z;
   const BoxMeta& bm = meta[box];
-  if (active && !active[box]) {
-    // converged box: carry X (and P) over to the output slots, which the host
-    // swaps with the current ones for every box
-    int64_t n = (int64_t)bm.n_dof * k;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x) {
-      OX.p[kind][(bm.dof_off * k) + t] = Z.p[kind][0][(bm.dof_off * k) + t];
-      if (OP.p[kind] && nblk == 3) OP.p[kind][(bm.dof_off * k) + t] = Z.p[kind][2][(bm.dof_off * k) + t];
-    }
-    return;
-  }
+  // a converged box's block stays in the buffer it was retired in (XLoc)
+  if (active && !active[box]) return;
   const int r_wg = blockIdx.x * UPD_ROWS;
   if (r_wg >= bm.n_dof) return;
   const int m = nblk * k;
@@ -682,12 +673,13 @@ __global__ void k_proj_coef(int k, double shift, const double* __restrict__ G, d
   }
 }
 
-// dst = src on the first cnt columns of every box, 0 on the others, cnt =
-// min(nround, n_ev - col0): a round's converged block with its guard columns
-// cleared (flat over the boxes' [n_dof][k] blocks; grid (rows, n_box))
-__global__ void k_keep_cols(const BoxMeta* __restrict__ meta, int k, int col0, int nround,
-                            const double* __restrict__ src, double* __restrict__ dst) {
+// dst = X (image kind `kind`, located by xl) on the first cnt columns of
+// every box, 0 on the others, cnt = min(nround, n_ev - col0): a round's
+// converged block with its guard columns cleared (grid (rows, n_box))
+__global__ void k_keep_cols(const BoxMeta* __restrict__ meta, int k, int col0, int nround, XLoc xl, int kind,
+                            double* __restrict__ dst) {
   const BoxMeta& bm = meta[blockIdx.y];
+  const double* __restrict__ src = xl.at(kind, blockIdx.y);
   const int cnt = min(nround, bm.n_ev - col0);
   const int64_t n = (int64_t)bm.n_dof * k;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
@@ -764,14 +756,17 @@ __global__ __launch_bounds__(RES_THREADS) void k_residual(const BoxMeta* __restr
 // (a non-positive pivot in its factors) or bit 8 is retired at once as failed,
 // so it does not hold the batch loop.  On the last iteration (last != 0) a box
 // still active whose pairs miss tol gets bit 1.  Updates active/iters and the
-// count of boxes still active.
+// count of boxes still active; a retired box's xbuf entry records x_id, the
+// buffer that holds the current block X (no kernel moves it afterwards).
 #define STALL_ITERS 6
 __global__ void k_converge(const BoxMeta* __restrict__ meta, int n_box, int k, int n_chunk,
                            const double* __restrict__ part, const double* __restrict__ nu,
                            double tol, double tol_defl, double* __restrict__ rho, int32_t* __restrict__ active,
                            int32_t* __restrict__ iters, int32_t* __restrict__ n_active,
-                           int last, int32_t* __restrict__ status, int col0, int nround, int it,
-                           int32_t* __restrict__ reached) {
+                           int last, int32_t* __restrict__ status, int col0, int nround,
+                           const int32_t* __restrict__ it_dev, int32_t* __restrict__ reached, int x_id,
+                           int32_t* __restrict__ xbuf) {
+  const int it = *it_dev;   // the iteration index (device-side, so a captured graph can advance it)
   // one wavefront per box, lane c < k takes column c (chunks summed in order)
   const int box = blockIdx.x, c = threadIdx.x;
   if (box >= n_box || !active[box]) return;
@@ -817,6 +812,7 @@ __global__ void k_converge(const BoxMeta* __restrict__ meta, int n_box, int k, i
     }
     if (retire) {
       active[box] = 0;
+      xbuf[box] = x_id;          // its block X stays in buffer x_id from now on
     } else {
       if (last && !all_user) st |= 1;
       iters[box] += last ? 0 : 1;
@@ -832,6 +828,11 @@ __global__ void k_converge(const BoxMeta* __restrict__ meta, int n_box, int k, i
 __global__ void k_status_clear(int n_box, const int32_t* __restrict__ mask, int32_t* __restrict__ status) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < n_box && (!mask || mask[b])) status[b] &= ~(1 | 8 | 16);
+}
+
+// *x += d (the iteration counter of a captured LOBPCG iteration)
+__global__ void k_add_i32(int32_t* __restrict__ x, int32_t d) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *x += d;
 }
 
 // status[i] |= bits for i < n
@@ -909,7 +910,7 @@ __global__ void k_copy_start(const BoxMeta* __restrict__ meta, const uint8_t* __
 #define OUT_THREADS 1024   // k_output: 32 columns x 32 row slots
 
 __global__ __launch_bounds__(OUT_THREADS) void k_output(const BoxMeta* __restrict__ meta, int k,
-                                                double shift, const double* __restrict__ X,
+                                                double shift, XLoc xl,
                                                 const double* __restrict__ nu,
                                                 const double* __restrict__ rho,
                                                 double* __restrict__ evals,
@@ -923,6 +924,7 @@ __global__ __launch_bounds__(OUT_THREADS) void k_output(const BoxMeta* __restric
   int box = blockIdx.x;
   if (mask && !mask[box]) return;   // a box the caller did not select keeps its output
   const BoxMeta& bm = meta[box];
+  const double* __restrict__ X = xl.at(0, box);
   const int tid = threadIdx.x, col = tid & 31, slot = tid >> 5;
   // this round writes pairs col0 .. col0 + nev - 1 of the box (columns of X
   // 0 .. nev - 1); the rows of evecs hold all n_ev pairs

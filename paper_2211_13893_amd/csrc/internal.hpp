@@ -104,6 +104,23 @@ struct MeshDev {
   const uint8_t* dirichlet;
 };
 
+// Where the LOBPCG block X of a box lives.  The iteration keeps its blocks
+// (four image kinds x five slots) in 20 buffers of the workspace, buffer
+// (kind * 5 + id) at vec + (kind * 5 + id) * VT; the host rotates the slot ->
+// buffer map every iteration without moving data, and a box retired as
+// converged is left in the buffer it was in (xbuf[box] = its id, -1 while it
+// is still iterated, when X is in buffer cur).
+struct XLoc {
+  const double* vec;
+  int64_t VT;
+  int32_t cur;
+  const int32_t* xbuf;
+  __device__ const double* at(int kind, int box) const {
+    const int id = xbuf[box] >= 0 ? xbuf[box] : cur;
+    return vec + (int64_t)(kind * 5 + id) * VT;
+  }
+};
+
 __host__ __device__ inline int nb_index(int dx, int dy, int dz) {
   return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
 }

@@ -64,6 +64,12 @@ class msgfem_kernel_stat(ctypes.Structure):
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
+# plan option keys (msgfem.h)
+OPT_GRAPH = 1
+INFO_GRAPH_LAUNCHES = 100
+INFO_GRAPH_ITERS = 101
+INFO_GRAPHS_CACHED = 102
+
 _P = ctypes.c_void_p
 SIGNATURES = {
     "msgfem_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
@@ -108,6 +114,8 @@ SIGNATURES = {
                                          _P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                          _P, _P]),
     "msgfem_coarse_energy": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "msgfem_plan_set_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64]),
+    "msgfem_plan_get_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "msgfem_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "msgfem_profile_stats": (ctypes.c_int, [_P, ctypes.POINTER(msgfem_kernel_stat), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
@@ -175,7 +183,7 @@ class LocalStage:
     def __init__(self, problem, batch: Optional[Sequence[int]] = None,
                  n_ev: Optional[Sequence[int]] = None, device: str = "cuda:0", shift: float = 1.0,
                  tol: float = 1e-6, maxit: int = 200, block: int = 0, seed: int = 1234,
-                 geneo: bool = False, precision: int = 0):
+                 geneo: bool = False, precision: int = 0, graph: bool = False):
         import torch
         self.torch = torch
         lib = load()
@@ -220,6 +228,19 @@ class LocalStage:
             self.boxes.append(bi)
         self.ops = None
         self.work = None
+        if graph:
+            self.set_option(OPT_GRAPH, 1)
+
+    def set_option(self, key: int, value: int):
+        """msgfem_plan_set_option"""
+        _check(self.lib.msgfem_plan_set_option(self.plan, int(key), int(value)), self.plan, "msgfem_plan_set_option")
+
+    def get_option(self, key: int) -> int:
+        """msgfem_plan_get_option"""
+        v = ctypes.c_int64()
+        _check(self.lib.msgfem_plan_get_option(self.plan, int(key), ctypes.byref(v)), self.plan,
+               "msgfem_plan_get_option")
+        return int(v.value)
 
     def __del__(self):
         try:
