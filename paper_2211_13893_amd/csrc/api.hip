@@ -275,9 +275,17 @@ static int fail(msgfem_plan* p, int code, const char* fmt, ...) {
                   hipGetErrorString(e_));                                                  \
   } while (0)
 
-static void band_geom(int sx, int sy, int sz, int* n, int* nt, int* bt) {
-  *n = 3 * sx * sy * sz;
-  int b = 3 * (sx * sy + sx + 1) + 2;
+// Band of the lexicographic node order of a (sub-)box with node dims d[3]:
+// the order runs over the box axes from the shortest (fastest index) to the
+// longest (slowest), which minimises the half-bandwidth 3 (s0 s1 + s0 + 1) + 2
+// (ties keep the axis order x, y, z).  ord encodes the axes (BoxMeta.ord).
+static void band_geom(const int d[3], int* n, int* nt, int* bt, int32_t* ord) {
+  int a[3] = {0, 1, 2};
+  std::stable_sort(a, a + 3, [&](int x, int y) { return d[x] < d[y]; });
+  const int s0 = d[a[0]], s1 = d[a[1]];
+  *ord = a[0] | (a[1] << 2) | (a[2] << 4);
+  *n = 3 * d[0] * d[1] * d[2];
+  int b = 3 * (s0 * s1 + s0 + 1) + 2;
   *nt = (*n + 31) / 32;
   *bt = (b + 31) / 32 + 1;
   if (*bt > *nt) *bt = *nt;
@@ -319,9 +327,9 @@ static const char* box_geometry(const int N[3], const msgfem_decomp* dec, const 
   m.n_nodes = m.mx * m.my * m.mz;
   m.n_dof = 3 * m.n_nodes;
   m.n_ev = n_ev;
-  band_geom(m.sub_hi[0] - m.sub_lo[0] + 1, m.sub_hi[1] - m.sub_lo[1] + 1, m.sub_hi[2] - m.sub_lo[2] + 1, &m.n11,
-            &m.nt11, &m.bt11);
-  band_geom(m.mx, m.my, m.mz, &m.nh, &m.nth, &m.bth);
+  const int d11[3] = {m.sub_hi[0] - m.sub_lo[0] + 1, m.sub_hi[1] - m.sub_lo[1] + 1, m.sub_hi[2] - m.sub_lo[2] + 1};
+  band_geom(d11, &m.n11, &m.nt11, &m.bt11, &m.ord[0]);
+  band_geom(mm, &m.nh, &m.nth, &m.bth, &m.ord[1]);
   return nullptr;
 }
 
@@ -562,16 +570,12 @@ static double band_entries(double n, double b) {
 }
 
 static void band_nb(const BoxMeta& m, int kind, double* n, double* b) {
-  int sx, sy;
-  if (kind == 0) {
-    sx = m.sub_hi[0] - m.sub_lo[0] + 1;
-    sy = m.sub_hi[1] - m.sub_lo[1] + 1;
-    *n = m.n11;
-  } else {
-    sx = m.mx;
-    sy = m.my;
-    *n = m.nh;
-  }
+  int d[3];
+  for (int a = 0; a < 3; ++a)
+    d[a] = kind == 0 ? m.sub_hi[a] - m.sub_lo[a] + 1 : (a == 0 ? m.mx : (a == 1 ? m.my : m.mz));
+  const int ord = m.ord[kind];
+  const int sx = d[ord & 3], sy = d[(ord >> 2) & 3];
+  *n = kind == 0 ? m.n11 : m.nh;
   *b = 3.0 * (sx * sy + sx + 1) + 2;
 }
 

@@ -43,7 +43,7 @@ __global__ void k_band_build(const BoxMeta* __restrict__ meta, int kind,
     const bool rin = row < v.n;
     const int rnode = rin ? row / 3 : 0, rc = rin ? row - 3 * (row / 3) : 0;
     const int ri = rnode % v.sx, rj = (rnode / v.sx) % v.sy, rk = rnode / sxy;
-    const int dr = 3 * ((ri + v.ox) + bm.mx * ((rj + v.oy) + bm.my * (rk + v.oz))) + rc;
+    const int dr = 3 * (v.base + ri * v.st0 + rj * v.st1 + rk * v.st2) + rc;
     const bool ar = rin && dof_active(kind, cl[dr]);
     const double mr = (kind == 1 && rin) ? m1[dr] : 0.0;
     // first column, then increments
@@ -58,15 +58,16 @@ __global__ void k_band_build(const BoxMeta* __restrict__ meta, int kind,
         if (!rin) {
           x = (row == col) ? 1.0 : 0.0;
         } else {
-          const int dc = 3 * ((ci + v.ox) + bm.mx * ((cj + v.oy) + bm.my * (ck + v.oz))) + cc;
+          const int dc = 3 * (v.base + ci * v.st0 + cj * v.st1 + ck * v.st2) + cc;
           const bool ac = dof_active(kind, cl[dc]);
           if (!ar || !ac) {
             x = (row == col) ? 1.0 : 0.0;
           } else {
-            const int dx = ci - ri, dy = cj - rj, dz = ck - rk;
-            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
+            const int di = ci - ri, dj = cj - rj, dk = ck - rk;
+            if (di >= -1 && di <= 1 && dj >= -1 && dj <= 1 && dk >= -1 && dk <= 1) {
               const int nr = dr / 3;
-              const double a = st[(int64_t)(nb_index(dx, dy, dz) * 9 + 3 * rc + cc) * bm.n_nodes + nr];
+              const int nbi = 13 + di * v.w0 + dj * v.w1 + dk * v.w2;   // 27-point index of the box offset
+              const double a = st[(int64_t)(nbi * 9 + 3 * rc + cc) * bm.n_nodes + nr];
               x = (kind == 1) ? a * (1.0 + shift * mr * m1[dc]) : a;
             }
           }

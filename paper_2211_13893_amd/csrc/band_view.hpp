@@ -10,27 +10,40 @@ struct BandView {
   int64_t off, ioff;
   int64_t doff, dstride;   // D^{-1} tile I of the unit-lower factor at doff + I*dstride
   int64_t fw, bw;   // solve-ordered band copies (forward / backward sweep)
-  int sx, sy, sz;   // (sub-)box node dims of the ordering
-  int ox, oy, oz;   // offset of the ordering's node (0,0,0) inside the box
+  int sx, sy, sz;   // node dims of the ordering, fastest to slowest index
+  int base;         // box node of the ordering's node (0,0,0)
+  int st0, st1, st2;   // box node strides of the three order indices
+  int w0, w1, w2;      // their weights in the 27-point neighbour index (1, 3 or 9)
 };
+
+// the ordering of a (sub-)box with node dims d[3] (box axes) starting at box
+// node (o[0], o[1], o[2]); ord encodes the box axis of each order index
+__device__ inline void band_order(BandView& v, const BoxMeta& bm, int ord, const int d[3], const int o[3]) {
+  const int a0 = ord & 3, a1 = (ord >> 2) & 3, a2 = (ord >> 4) & 3;
+  const int st[3] = {1, bm.mx, bm.mx * bm.my};
+  const int w[3] = {1, 3, 9};
+  v.sx = d[a0]; v.sy = d[a1]; v.sz = d[a2];
+  v.st0 = st[a0]; v.st1 = st[a1]; v.st2 = st[a2];
+  v.w0 = w[a0]; v.w1 = w[a1]; v.w2 = w[a2];
+  v.base = o[0] + bm.mx * (o[1] + bm.my * o[2]);
+}
 
 __device__ inline BandView band_view(const BoxMeta& bm, int kind) {
   BandView v;
   if (kind == 0) {
     v.NT = bm.nt11; v.BT = bm.bt11; v.n = bm.n11; v.off = bm.f11_off; v.ioff = bm.f11i_off;
     v.fw = bm.f11_fw; v.bw = bm.f11_bw;
-    v.sx = bm.sub_hi[0] - bm.sub_lo[0] + 1;
-    v.sy = bm.sub_hi[1] - bm.sub_lo[1] + 1;
-    v.sz = bm.sub_hi[2] - bm.sub_lo[2] + 1;
-    v.ox = bm.sub_lo[0]; v.oy = bm.sub_lo[1]; v.oz = bm.sub_lo[2];
+    const int d[3] = {bm.sub_hi[0] - bm.sub_lo[0] + 1, bm.sub_hi[1] - bm.sub_lo[1] + 1,
+                      bm.sub_hi[2] - bm.sub_lo[2] + 1};
+    band_order(v, bm, bm.ord[0], d, bm.sub_lo);
     const bool compact = bm.flags & BOX_COMPACT_DINV;
     v.doff = compact ? bm.f11i_off : bm.f11_off;
     v.dstride = compact ? (int64_t)MSG_TILE2 : (int64_t)bm.bt11 * MSG_TILE2;
   } else {
     v.NT = bm.nth; v.BT = bm.bth; v.n = bm.nh; v.off = bm.fh_off; v.ioff = bm.fhi_off;
     v.fw = bm.fh_fw; v.bw = bm.fh_bw;
-    v.sx = bm.mx; v.sy = bm.my; v.sz = bm.mz;
-    v.ox = v.oy = v.oz = 0;
+    const int d[3] = {bm.mx, bm.my, bm.mz}, o[3] = {0, 0, 0};
+    band_order(v, bm, bm.ord[1], d, o);
     v.doff = bm.fh_off;
     v.dstride = (int64_t)bm.bth * MSG_TILE2;
   }
@@ -42,8 +55,7 @@ __device__ inline int band_to_dof(const BandView& v, const BoxMeta& bm, int r) {
   if (r >= v.n) return -1;
   int node = r / 3, c = r - 3 * node;
   int i = node % v.sx, j = (node / v.sx) % v.sy, k = node / (v.sx * v.sy);
-  int bn = (i + v.ox) + bm.mx * ((j + v.oy) + bm.my * (k + v.oz));
-  return 3 * bn + c;
+  return 3 * (v.base + i * v.st0 + j * v.st1 + k * v.st2) + c;
 }
 
 __device__ inline bool dof_active(int kind, uint8_t c) {

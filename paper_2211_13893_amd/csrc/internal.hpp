@@ -49,6 +49,8 @@ struct BoxMeta {
   int32_t nt11, bt11, n11;    // tile rows, band tiles, matrix order (unpadded)
   int32_t nth, bth, nh;
   int32_t flags;              // BOX_COMPACT_DINV: D^{-1} of the A11 factor compact at f11i_off (coarse store)
+  int32_t ord[2];             // node order of the A11 / Ahat bands: box axis of the fastest, middle and
+                              // slowest order index in bits 0-1, 2-3, 4-5 (the longest axis slowest)
   int64_t node_off;           // offset into per-node arrays of the batch
   int64_t dof_off;            // offset into per-dof arrays
   int64_t vec_off;            // offset (doubles) of this box inside one block-vector array

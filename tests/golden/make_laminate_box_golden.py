@@ -1,14 +1,18 @@
-"""Writes oracle eigenvalues of boxes of the large ply/resin laminate.
+"""Writes oracle eigenvalues of large boxes as text fixtures.
 
-The full one-GPU pipeline runs 16^3-element cores with overlap 2 and
-oversampling 2 on a wrinkled ply/resin laminate; its boxes are too large for
-the dense FP64 oracle inside a GPU test, so this script computes, once, the
-oracle's eigenvalues (nu = 1/(lambda + 1), descending, and lambda) of chosen
-subdomains of the shortened laminate (96 x 64 x 48 elements, the same box
-shapes) and stores them as text.  It calls only oracle/ and the seeded
-input generator.
+Boxes too large for the dense FP64 oracle inside a GPU test get their
+oracle eigenvalues (nu = 1/(lambda + 1), descending, and lambda) computed
+once by this script, which calls only oracle/ and the seeded input
+generators:
+  laminate: subdomains of the shortened ply/resin laminate (96 x 64 x 48
+            elements, 16^3-element cores, overlap 2, oversampling 2: the box
+            shapes of the full one-GPU pipeline) -> laminate_box_<sd>.txt
+  uneven:   subdomains of the uneven batch (wrinkled 256 x 32 x 24-element
+            laminate with random cuts), e.g. its largest box, sd 41 (26 x 18
+            x 18 nodes, 25,272 DoF, a band of 48 tiles in x-fastest order)
+            -> uneven_box_<sd>.txt
 
-Usage: python tests/golden/make_laminate_box_golden.py [sd ...]
+Usage: python tests/golden/make_laminate_box_golden.py [laminate|uneven] [sd ...]
 """
 import os
 import sys
@@ -26,19 +30,23 @@ SHAPE = dict(nx=96, ny=64, nz=48)
 N_KEEP = 24
 
 
-def main(sds):
-    prob = synth.full_laminate(**SHAPE)
+def main(which, sds):
+    if which == "uneven":
+        prob = synth.uneven_laminate()
+        label = "uneven_laminate(): wrinkled 256 x 32 x 24-element laminate, random cuts,\n# overlap 1, oversampling 1-3"
+    else:
+        prob = synth.full_laminate(**SHAPE)
+        label = ("full_laminate(nx=96, ny=64, nz=48): 16^3 cores,\n# overlap 2, oversampling 2")
     kec = fem.KeCache(prob)
     for sd in sds:
         t0 = time.perf_counter()
         ops = gevp.local_ops(prob, sd, kec)
         ref = gevp.schur_gevp(ops, N_KEEP)
-        out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"laminate_box_{sd}.txt")
+        out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{which}_box_{sd}.txt")
         elo, ehi = prob.omega_star_box(sd)
         with open(out, "w") as f:
             f.write("# Oracle (dense FP64 Schur reduction + scipy eigh of M x = nu (S + M) x, Sec. 3.3 / 4.3)\n")
-            f.write(f"# eigenvalues of subdomain {sd} of full_laminate(nx=96, ny=64, nz=48): 16^3 cores,\n")
-            f.write(f"# overlap 2, oversampling 2; box elements {elo.tolist()} .. {ehi.tolist()}, "
+            f.write(f"# eigenvalues of subdomain {sd} of {label}; box elements {elo.tolist()} .. {ehi.tolist()}, "
                     f"{ops.A.shape[0]} DoF, n1 {ops.i1.size}, n2 {ops.i2.size}\n")
             f.write("# written by tests/golden/make_laminate_box_golden.py\n")
             f.write("# k nu lambda\n")
@@ -49,4 +57,8 @@ def main(sds):
 
 
 if __name__ == "__main__":
-    main([int(a) for a in sys.argv[1:]] or [0])
+    args = sys.argv[1:]
+    which = "laminate"
+    if args and args[0] in ("laminate", "uneven"):
+        which = args.pop(0)
+    main(which, [int(a) for a in args] or [0])

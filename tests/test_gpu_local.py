@@ -10,6 +10,7 @@ eigenvector subspaces at every cut with a relative gap > 1e-3 within the
 Davis-Kahan sin-theta bound formed from the oracle's matrices
 (tests/eigcheck.py).
 """
+import os
 import sys
 
 import numpy as np
@@ -21,6 +22,7 @@ from paper_2211_13893_amd import synth
 import eigcheck
 
 pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def say(*a):
@@ -264,6 +266,17 @@ def test_eigs_uneven_laminate_sampled(torch):
         eigcheck.check_subspaces(ref, ops.i2, phi, n_ev, say=say)
         assert np.allclose(np.linalg.norm(phi, axis=0), 1.0, atol=1e-12)
         assert np.all(phi[ops.cls == 3] == 0.0)
+    # the largest box (sd 41: 26 x 18 x 18 nodes, 25,272 DoF; a 48-tile band
+    # in x-fastest order) against the oracle's eigenvalues stored in
+    # tests/golden (too large for the dense oracle inside this test)
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "uneven_box_41.txt")) if l.strip() and not l.startswith("#")]
+    nu_ref = np.array([float(r[1]) for r in rows])
+    b = int(np.flatnonzero(prob.batch == 41)[0])
+    assert dofs[b] == 25272 and dofs[b] == dofs.max()
+    lam = st.eigvals(out, b).cpu().numpy()
+    err = np.max(np.abs(1.0 / (lam + 1.0) - nu_ref[:lam.size]) / nu_ref[:lam.size])
+    say(f"  box {b} (sd 41, {dofs[b]} DoF, n_ev {lam.size}): nu rel err vs stored oracle {err:.2e}")
+    assert err <= 1e-8
 
 
 def test_eigs_parity_beam(torch):
