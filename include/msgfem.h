@@ -166,14 +166,28 @@ int msgfem_plan_box(const msgfem_plan *plan, int32_t b, msgfem_box_info *out);
  *     profiled calls (msgfem_profile) stay eager.  The plan keeps up to 8
  *     instantiated graphs, keyed by the ops, work and status pointers (a call
  *     with other buffers captures again); setting 0 releases them.
+ *   MSGFEM_OPT_SPLIT: 1 (default) = a box matrix (A11 or A + s D A D) whose
+ *     slowest node-order axis has at least 8 layers is factored by one level
+ *     of nested dissection: the middle layer of nodes is a separator, the
+ *     layers on either side are two band chains factored and swept
+ *     independently (two work units per box in the block solves), and the
+ *     separator's Schur complement is a dense block.  0 = every box matrix
+ *     is one band.  Both give the same operators up to rounding.  The layout
+ *     of the factors changes, so set it right after msgfem_plan_create,
+ *     before msgfem_plan_sizes and msgfem_assemble_local (ops_bytes and
+ *     work_bytes change).  A coarse store (msgfem_coarse_create) takes the
+ *     plans of the default layout.
  * msgfem_plan_set_option returns MSGFEM_EARG for an unknown key or value.
  * msgfem_plan_get_option reads an option or one of the counters of the last
  * msgfem_local_eigs call: MSGFEM_INFO_GRAPH_LAUNCHES (graph launches),
- * MSGFEM_INFO_GRAPH_ITERS (iterations they ran), MSGFEM_INFO_GRAPHS_CACHED. */
+ * MSGFEM_INFO_GRAPH_ITERS (iterations they ran), MSGFEM_INFO_GRAPHS_CACHED;
+ * MSGFEM_INFO_SPLIT_BOXES: sum over the batch of 1 (A11 split) + 2 (Ahat split). */
 #define MSGFEM_OPT_GRAPH 1
+#define MSGFEM_OPT_SPLIT 2
 #define MSGFEM_INFO_GRAPH_LAUNCHES 100
 #define MSGFEM_INFO_GRAPH_ITERS 101
 #define MSGFEM_INFO_GRAPHS_CACHED 102
+#define MSGFEM_INFO_SPLIT_BOXES 103
 int msgfem_plan_set_option(msgfem_plan *plan, int32_t key, int64_t value);
 int msgfem_plan_get_option(const msgfem_plan *plan, int32_t key, int64_t *value);
 
@@ -244,7 +258,8 @@ int msgfem_local_apply(msgfem_plan *plan, const void *ops, void *work, int32_t o
  * that forbid hipMalloc).  Same operators, kernels, layouts and results as
  * msgfem_local_apply; the scratch it needs (the B3-masked copy of x for ops 0
  * and 1, dofs_total * k doubles; the forward-sweep rows of the block solves for
- * ops 2 and 3, about n_box * ceil(k / 8) * (tile rows + 1) * 256 doubles) lives
+ * ops 2 and 3, about 2 n_box * ceil(k / 8) * (tile rows + 1) * 256 doubles, and
+ * for split boxes 4 n_box * ceil(k / 8) * (separator tile rows + 1) * 256) lives
  * in a static device buffer of msgfem_static_scratch_max() bytes (16 MiB), one
  * per GPU, held until the process ends.  It allocates nothing (no hipMalloc,
  * hipFree or event objects; kernel timing of msgfem_profile is not recorded).

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -26,15 +27,16 @@ __global__ void k_chol_update(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_panel(const MatDesc*, int, double*);
 __global__ void k_chol_step(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_unit(const MatDesc*, double*);
-__global__ void k_band_unit_relayout4(const BoxMeta*, int, double*);
+__global__ void k_band_unit_relayout4(const BoxMeta*, int, double*, int);
 __global__ void k_band_relayout(const BoxMeta*, int, double*);
-__global__ void k_band_relayout4(const BoxMeta*, int, double*);
+__global__ void k_band_relayout4(const BoxMeta*, int, double*, int);
 template <int KC, int NS, typename T>
 __global__ void k_band_solve(const BoxMeta*, int, int, int, const T*, const uint8_t*, const double*, double*, int,
-                             int, int, double*, int64_t, const int32_t*);
-template <int NSLOT, typename T>
+                             int, int, double*, int64_t, const int32_t*, int, double*, int64_t);
+template <int NSLOT, bool WIDE, typename T>
 __global__ void k_band_solve4(const BoxMeta*, int, int, int, const T*, const uint8_t*, const double*, double*, int,
-                              int, int, double*, int64_t, const int32_t*);
+                              int, int, double*, int64_t, const int32_t*, int, double*, int64_t);
+__global__ void k_sep_syrk(const SepDesc*, double*);
 
 template <bool TWO, int CW, typename ST>
 __global__ void k_spmm(const BoxMeta*, int, int, const ST*, const uint8_t*, const double*, const double*,
@@ -125,7 +127,11 @@ __global__ void k_warm_start(const BoxMeta*, const uint8_t*, const float*, const
 
 using namespace msg;
 
-static const int KC = 8;           // columns per solve workgroup
+static const int KC = 8;           // columns per solve workgroup (16 in the wide matrix-core solve)
+// the wide matrix-core solve (16 columns per workgroup, v_mfma_f64_16x16x4f64)
+// keeps a ring of BT rows x 16 columns and 8 x 32 x 17 partial sums in LDS:
+// bands of at most 31 tiles
+static const int WIDE_MAX_BT = 31;
 // eigenpairs per box: beyond 32 they come in deflated rounds; two rounds at
 // most, because a third round's pairs can sit 1e4 below the first round's in
 // nu (the end subdomains of a clamped beam), where the first round's error is
@@ -157,6 +163,13 @@ struct msgfem_plan {
   int max_nodes = 0, max_dof = 0, max_nt = 0, max_bt = 0;
   int max_bt_kind[2] = {0, 0};   // per matrix kind (A11, Ahat)
   int64_t max_fac_tiles = 0;
+  // nested dissection of the box matrices (MSGFEM_OPT_SPLIT)
+  int split = 1;
+  bool any_split[2] = {false, false};
+  int max_nts = 0;               // separator tile rows
+  int n_chain_mats = 0;          // mats[0 .. n_chain_mats): whole bands and chains; then the separator blocks
+  std::vector<SepDesc> seps;
+  int64_t o_seps = 0, w_sep = 0, sep_q = 0;
   int n_gchunk = 0;
   // work layout (bytes)
   int64_t w_vec = 0, w_part = 0, w_G = 0, w_L = 0, w_Y = 0, w_Yp = 0, w_nu = 0, w_rho = 0,
@@ -333,6 +346,159 @@ static const char* box_geometry(const int N[3], const msgfem_decomp* dec, const 
   return nullptr;
 }
 
+// Nested dissection of a box matrix: split when its slowest order axis has
+// at least this many node layers (each chain then has at least 3.5 layers)
+static const int SPLIT_MIN_LAYERS = 8;
+
+// The band parts of both box matrices (geometry only; offsets in plan_layout):
+// one whole band, or with split two chains of (layers before / after the
+// middle layer zs) + separator rows and the separator block.
+static void band_parts(BoxMeta& m, bool split) {
+  for (int kind = 0; kind < 2; ++kind) {
+    int d[3];
+    for (int a = 0; a < 3; ++a)
+      d[a] = kind == 0 ? m.sub_hi[a] - m.sub_lo[a] + 1 : (a == 0 ? m.mx : (a == 1 ? m.my : m.mz));
+    const int ord = m.ord[kind];
+    const int s0 = d[ord & 3], s1 = d[(ord >> 2) & 3], s2 = d[(ord >> 4) & 3];
+    const int n = kind ? m.nh : m.n11, NT = kind ? m.nth : m.nt11, BT = kind ? m.bth : m.bt11;
+    BandPart* q = m.part[kind];
+    for (int pi = 0; pi < 3; ++pi) q[pi] = BandPart{};
+    m.nd[kind] = 0;
+    m.zs[kind] = 0;
+    if (split && s2 >= SPLIT_MIN_LAYERS) {
+      const int L = 3 * s0 * s1, zs = s2 / 2;
+      const int n0 = L * zs, n1 = L * (s2 - zs - 1);
+      const int NT0 = (n0 + 31) / 32, NT1 = (n1 + 31) / 32, NTs = (L + 31) / 32;
+      m.nd[kind] = 1;
+      m.zs[kind] = zs;
+      q[0] = BandPart{NT0 + NTs, BT, NT0, 32 * NT0 - n0, n0, L, 0, 0, 0, 0, 0, 0};
+      q[1] = BandPart{NT1 + NTs, BT, NT1, 32 * NT1 - n1, n1, L, 1, 0, 0, 0, 0, 0};
+      q[2] = BandPart{NTs, NTs, NTs, 0, 0, L, 0, 0, 0, 0, 0, 0};
+    } else {
+      q[0] = BandPart{NT, BT, NT, 0, n, 0, 0, 0, 0, 0, 0, 0};
+    }
+  }
+}
+
+// Factor storage of every box part, the factorisation descriptors, and the
+// ops and work layouts (rerun when MSGFEM_OPT_SPLIT changes).
+static int plan_layout(msgfem_plan* p, int nsd, int n_mat) {
+  const int nb = (int)p->meta.size(), k = p->k;
+  p->max_nt = p->max_bt = 0;
+  p->max_bt_kind[0] = p->max_bt_kind[1] = 0;
+  p->max_fac_tiles = 0;
+  p->max_nts = 0;
+  p->any_split[0] = p->any_split[1] = false;
+  int64_t fac_off = 0;
+  for (int b = 0; b < nb; ++b) {
+    BoxMeta& m = p->meta[b];
+    band_parts(m, p->split != 0);
+    for (int kind = 0; kind < 2; ++kind) {
+      for (int pi = 0; pi < (m.nd[kind] ? 3 : 1); ++pi) {
+        BandPart& q = m.part[kind][pi];
+        q.off = fac_off;
+        fac_off += (int64_t)q.NT * q.BT * 1024;
+        q.ioff = fac_off;
+        fac_off += (int64_t)q.NT * 1024;
+        q.fw = fac_off;
+        fac_off += solve_copy_doubles(q.NT, q.BT);
+        q.bw = fac_off;
+        fac_off += solve_copy_doubles(q.NT, q.BT);
+        p->max_nt = std::max(p->max_nt, q.NT);
+        p->max_bt = std::max(p->max_bt, q.BT);
+        p->max_bt_kind[kind] = std::max(p->max_bt_kind[kind], q.BT);
+        p->max_fac_tiles = std::max(p->max_fac_tiles, (int64_t)q.NT * q.BT);
+      }
+      if (m.nd[kind]) {
+        p->any_split[kind] = true;
+        p->max_nts = std::max(p->max_nts, m.part[kind][2].NT);
+      }
+    }
+  }
+  // block solve LDS: per-wavefront partial sums, D^{-1} tile, w row, ring of BT solution rows
+  if (p->max_bt > SOLVE_MAX_BT ||
+      (int64_t)(8 * 32 * (KC + 1) + 32 * 33 + 32 * KC + p->max_bt * 32 * KC) * 8 > 160 * 1024)
+    return fail(p, MSGFEM_ESIZE, "band of %d tiles too wide for the block solve (at most %d)", p->max_bt,
+                SOLVE_MAX_BT);
+  // factorisation descriptors: whole bands and chains, then separator blocks
+  p->mats.clear();
+  p->seps.clear();
+  for (int b = 0; b < nb; ++b)
+    for (int kind = 0; kind < 2; ++kind) {
+      const BoxMeta& m = p->meta[b];
+      for (int pi = 0; pi < (m.nd[kind] ? 2 : 1); ++pi) {
+        const BandPart& q = m.part[kind][pi];
+        p->mats.push_back(MatDesc{q.NT, q.BT, b, q.NTf, q.off, q.ioff});
+      }
+    }
+  p->n_chain_mats = (int)p->mats.size();
+  for (int b = 0; b < nb; ++b)
+    for (int kind = 0; kind < 2; ++kind) {
+      const BoxMeta& m = p->meta[b];
+      if (!m.nd[kind]) continue;
+      const BandPart *c0 = &m.part[kind][0], *c1 = &m.part[kind][1], *q = &m.part[kind][2];
+      p->mats.push_back(MatDesc{q->NT, q->BT, b, q->NTf, q->off, q->ioff});
+      p->seps.push_back(SepDesc{q->NT, c0->BT, c0->NTf, c1->NTf, c0->off, c1->off, q->off});
+    }
+  p->fac_total = fac_off;
+  const msgfem_eig_opts& o = p->opts;
+  // ops layout
+  int64_t off = 0;
+  p->o_meta = off; off = align256(off + (int64_t)nb * sizeof(BoxMeta));
+  p->o_mats = off; off = align256(off + (int64_t)p->mats.size() * sizeof(MatDesc));
+  p->o_seps = off; off = align256(off + (int64_t)std::max<size_t>(p->seps.size(), 1) * sizeof(SepDesc));
+  p->o_omega = off; off = align256(off + (int64_t)nsd * 6 * 4);
+  p->o_ctab = off; off = align256(off + (int64_t)n_mat * 36 * 8);
+  p->o_wtot = off; off = align256(off + p->n_nodes_global * 4);
+  p->o_stencil = off; off = align256(off + p->nodes_total * 243 * 8);
+  p->o_mu = off; off = align256(off + p->dofs_total * 8);
+  p->o_cls = off; off = align256(off + p->dofs_total);
+  p->o_fac = off; off = align256(off + p->fac_total * 8);
+  p->o_fac32 = p->o_st32 = 0;
+  if (o.precision >= 1) {
+    // FP32 copies of the factors' solve data (precision 1: the preconditioner's
+    // Ahat only; 2: both matrices) and of the stencil (precision 2)
+    p->o_fac32 = off; off = align256(off + p->fac_total * 4);
+    if (o.precision == 2) { p->o_st32 = off; off = align256(off + p->nodes_total * 243 * 4); }
+  }
+  p->ops_bytes = off;
+  // work layout
+  int m3 = 3 * k;
+  int nchunk_solve = (k + KC - 1) / KC;
+  // w rows of the solve plus one row that absorbs stores without a target
+  // (per 8 columns; a 16-column solve takes two strides per chunk)
+  p->scr_stride = (int64_t)(p->max_nt + 1) * 32 * KC;
+  // separator exchange of a split solve: t_0, t_1, w of S, x_s
+  p->sep_q = (int64_t)(p->max_nts + 1) * 32 * KC;
+  // chunks of 8 columns, rounded up to whole chunks of 16
+  nchunk_solve = 2 * ((k + 15) / 16);
+  off = 0;
+  // 20 LOBPCG blocks, two scratch blocks, and the four image kinds of the
+  // converged block of every round but the last
+  p->w_vec = off; off = align256(off + (22 + 4 * (int64_t)(p->rounds - 1)) * p->vec_total * 8);
+  p->w_part = off; off = align256(off + (int64_t)nb * p->n_gchunk * 2 * m3 * m3 * 8);
+  p->w_G = off; off = align256(off + (int64_t)nb * 2 * m3 * m3 * 8);
+  p->w_L = off; off = align256(off + (int64_t)nb * m3 * m3 * 8);
+  // Rayleigh-Ritz coefficients (3k x k), or a coarse basis's CholQR
+  // coefficients (kv x kv)
+  p->w_Y = off; off = align256(off + (int64_t)nb * std::max(m3 * k, p->kv * p->kv) * 8);
+  p->w_Yp = off; off = align256(off + (int64_t)nb * m3 * k * 8);
+  p->w_nu = off; off = align256(off + (int64_t)nb * k * 8);
+  p->w_rho = off; off = align256(off + (int64_t)nb * k * 8);
+  p->w_rpart = off; off = align256(off + (int64_t)nb * p->n_gchunk * 3 * 32 * 8);
+  p->w_active = off; off = align256(off + (int64_t)nb * 4);
+  p->w_iters = off; off = align256(off + (int64_t)nb * 4);
+  p->w_nact = off; off = align256(off + 8);   // active-box count, iteration index
+  p->w_reached = off; off = align256(off + (int64_t)nb * 4);
+  p->w_xbuf = off; off = align256(off + (int64_t)nb * 4);
+  // one w block per (box, chain, chunk)
+  p->w_scr = off; off = align256(off + (int64_t)2 * nb * nchunk_solve * p->scr_stride * 8);
+  p->w_sep = off;
+  if (p->any_split[0] || p->any_split[1]) off = align256(off + (int64_t)nb * nchunk_solve * 4 * p->sep_q * 8);
+  p->work_bytes = off;
+  return MSGFEM_OK;
+}
+
 extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_mesh* mesh,
                                   const msgfem_decomp* dec, const int32_t* batch,
                                   const int32_t* n_ev, int32_t nb,
@@ -402,7 +568,7 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
   p->k = k;
   p->kv = std::max(k, (maxnev + 7) / 8 * 8);
   p->meta.resize(nb);
-  int64_t node_off = 0, dof_off = 0, vec_off = 0, fac_off = 0, evec_off = 0, eval_off = 0;
+  int64_t node_off = 0, dof_off = 0, vec_off = 0, evec_off = 0, eval_off = 0;
   for (int b = 0; b < nb; ++b) {
     int sd = batch[b];
     if (sd < 0 || sd >= dec->nsd) return fail(p, MSGFEM_EARG, "batch[%d] = %d out of range", b, sd);
@@ -414,22 +580,6 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     m.node_off = node_off;
     m.dof_off = dof_off;
     m.vec_off = vec_off;
-    m.f11_off = fac_off;
-    fac_off += (int64_t)m.nt11 * m.bt11 * 1024;
-    m.f11i_off = fac_off;
-    fac_off += (int64_t)m.nt11 * 1024;
-    m.fh_off = fac_off;
-    fac_off += (int64_t)m.nth * m.bth * 1024;
-    m.fhi_off = fac_off;
-    fac_off += (int64_t)m.nth * 1024;
-    m.f11_fw = fac_off;
-    fac_off += solve_copy_doubles(m.nt11, m.bt11);
-    m.f11_bw = fac_off;
-    fac_off += solve_copy_doubles(m.nt11, m.bt11);
-    m.fh_fw = fac_off;
-    fac_off += solve_copy_doubles(m.nth, m.bth);
-    m.fh_bw = fac_off;
-    fac_off += solve_copy_doubles(m.nth, m.bth);
     m.evec_off = evec_off;
     m.eval_off = eval_off;
     node_off += m.n_nodes;
@@ -439,78 +589,15 @@ extern "C" int msgfem_plan_create(msgfem_plan** out, int device, const msgfem_me
     eval_off += m.n_ev;
     p->max_nodes = std::max(p->max_nodes, m.n_nodes);
     p->max_dof = std::max(p->max_dof, m.n_dof);
-    p->max_nt = std::max(p->max_nt, std::max(m.nt11, m.nth));
-    p->max_bt = std::max(p->max_bt, std::max(m.bt11, m.bth));
-    p->max_bt_kind[0] = std::max(p->max_bt_kind[0], m.bt11);
-    p->max_bt_kind[1] = std::max(p->max_bt_kind[1], m.bth);
-    p->max_fac_tiles = std::max(p->max_fac_tiles, (int64_t)std::max(m.nt11 * m.bt11, m.nth * m.bth));
     p->meta[b] = m;
-  }
-  // LDS of the block solve: partial sums, the D^{-1} tile and a ring of BT solution tiles
-  // block solve LDS: per-wavefront partial sums, D^{-1} tile, w row, ring of BT solution rows
-  if (p->max_bt > SOLVE_MAX_BT ||
-      (int64_t)(8 * 32 * (KC + 1) + 32 * 33 + 32 * KC + p->max_bt * 32 * KC) * 8 > 160 * 1024)
-    return fail(p, MSGFEM_ESIZE, "band of %d tiles too wide for the block solve (at most %d)", p->max_bt,
-                SOLVE_MAX_BT);
-  for (int b = 0; b < nb; ++b) {
-    const BoxMeta& m = p->meta[b];
-    MatDesc a11{m.nt11, m.bt11, b, 0, m.f11_off, m.f11i_off};
-    MatDesc ah{m.nth, m.bth, b, 0, m.fh_off, m.fhi_off};
-    p->mats.push_back(a11);
-    p->mats.push_back(ah);
   }
   p->nodes_total = node_off;
   p->dofs_total = dof_off;
-  p->fac_total = fac_off;
   p->vec_total = vec_off;
   p->evec_total = evec_off;
   p->eval_total = eval_off;
-  // ops layout
-  int64_t off = 0;
-  p->o_meta = off; off = align256(off + (int64_t)nb * sizeof(BoxMeta));
-  p->o_mats = off; off = align256(off + (int64_t)p->mats.size() * sizeof(MatDesc));
-  p->o_omega = off; off = align256(off + (int64_t)dec->nsd * 6 * 4);
-  p->o_ctab = off; off = align256(off + (int64_t)mesh->n_mat * 36 * 8);
-  p->o_wtot = off; off = align256(off + p->n_nodes_global * 4);
-  p->o_stencil = off; off = align256(off + p->nodes_total * 243 * 8);
-  p->o_mu = off; off = align256(off + p->dofs_total * 8);
-  p->o_cls = off; off = align256(off + p->dofs_total);
-  p->o_fac = off; off = align256(off + p->fac_total * 8);
-  if (o.precision >= 1) {
-    // FP32 copies of the factors' solve data (precision 1: the preconditioner's
-    // Ahat only; 2: both matrices) and of the stencil (precision 2)
-    p->o_fac32 = off; off = align256(off + p->fac_total * 4);
-    if (o.precision == 2) { p->o_st32 = off; off = align256(off + p->nodes_total * 243 * 4); }
-  }
-  p->ops_bytes = off;
-  // work layout
   p->n_gchunk = (p->max_dof + GRAM_ROWS - 1) / GRAM_ROWS;
-  int m3 = 3 * k;
-  int nchunk_solve = (k + KC - 1) / KC;
-  // w rows of the solve plus one row that absorbs stores without a target
-  p->scr_stride = (int64_t)(p->max_nt + 1) * 32 * KC;
-  off = 0;
-  // 20 LOBPCG blocks, two scratch blocks, and the four image kinds of the
-  // converged block of every round but the last
-  p->w_vec = off; off = align256(off + (22 + 4 * (int64_t)(p->rounds - 1)) * p->vec_total * 8);
-  p->w_part = off; off = align256(off + (int64_t)nb * p->n_gchunk * 2 * m3 * m3 * 8);
-  p->w_G = off; off = align256(off + (int64_t)nb * 2 * m3 * m3 * 8);
-  p->w_L = off; off = align256(off + (int64_t)nb * m3 * m3 * 8);
-  // Rayleigh-Ritz coefficients (3k x k), or a coarse basis's CholQR
-  // coefficients (kv x kv)
-  p->w_Y = off; off = align256(off + (int64_t)nb * std::max(m3 * k, p->kv * p->kv) * 8);
-  p->w_Yp = off; off = align256(off + (int64_t)nb * m3 * k * 8);
-  p->w_nu = off; off = align256(off + (int64_t)nb * k * 8);
-  p->w_rho = off; off = align256(off + (int64_t)nb * k * 8);
-  p->w_rpart = off; off = align256(off + (int64_t)nb * p->n_gchunk * 3 * 32 * 8);
-  p->w_active = off; off = align256(off + (int64_t)nb * 4);
-  p->w_iters = off; off = align256(off + (int64_t)nb * 4);
-  p->w_nact = off; off = align256(off + 8);   // active-box count, iteration index
-  p->w_reached = off; off = align256(off + (int64_t)nb * 4);
-  p->w_xbuf = off; off = align256(off + (int64_t)nb * 4);
-  p->w_scr = off; off = align256(off + (int64_t)nb * nchunk_solve * p->scr_stride * 8);
-  p->work_bytes = off;
-  return MSGFEM_OK;
+  return plan_layout(p, dec->nsd, mesh->n_mat);
 }
 
 extern "C" void msgfem_plan_destroy(msgfem_plan* p) { delete p; }
@@ -590,6 +677,7 @@ static MeshDev mesh_dev(const msgfem_plan* p) {
 struct OpsView {
   const BoxMeta* meta;
   MatDesc* mats;
+  SepDesc* seps;
   int32_t* omega;
   double* ctab;
   int32_t* wtot;
@@ -606,6 +694,7 @@ static OpsView ops_view(const msgfem_plan* p, const void* ops) {
   OpsView v;
   v.meta = (const BoxMeta*)(b + p->o_meta);
   v.mats = (MatDesc*)(b + p->o_mats);
+  v.seps = (SepDesc*)(b + p->o_seps);
   v.omega = (int32_t*)(b + p->o_omega);
   v.ctab = (double*)(b + p->o_ctab);
   v.wtot = (int32_t*)(b + p->o_wtot);
@@ -623,6 +712,11 @@ static void lds_attributes();
 // the matrix-core block solve serves a matrix kind whose bands all fit its slots
 static bool solve4_kind(const msgfem_plan* p, int kind) {
   return p->max_bt_kind[kind] - 1 <= 8 * SOLVE4_MAX_SLOTS;
+}
+
+// the wide (16-column) matrix-core solve for this matrix kind
+static bool wide_kind(const msgfem_plan* p, int kind) {
+  return solve4_kind(p, kind) && p->max_bt_kind[kind] <= WIDE_MAX_BT;
 }
 
 static int set_device(msgfem_plan* p) {
@@ -662,9 +756,11 @@ static int tile_trsv(const double* T, int NT, int NH, const double* b, double* y
 // Left-looking tile Cholesky of banded SPD matrices, one launch per tile
 // column (which also factors the next diagonal tile), then (unit) the block
 // unit-lower rewrite.
-static int band_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int max_nt, int max_bt, double* fac,
-                         int32_t* status, bool unit, hipStream_t s) {
-  for (int J = -1; J <= max_nt - 2; ++J)
+// steps J = -1 .. last_J of k_chol_step (last_J = NT - 2 for a whole band,
+// NTf - 1 for a chain, whose last step gives its separator rows' L tiles)
+static int band_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int last_J, int max_nt, int max_bt,
+                         double* fac, int32_t* status, bool unit, hipStream_t s) {
+  for (int J = -1; J <= last_J; ++J)
     k_chol_step<<<dim3(nmat, (max_bt + 1 + 3) / 4), 256, 0, s>>>(mats, J, fac, status);
   if (unit) k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
   LAUNCHCHK(p);
@@ -681,6 +777,8 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
   HIPCHK(p, hipMemcpyAsync(v.omega, p->omega.data(), p->omega.size() * 4, hipMemcpyHostToDevice, s));
   HIPCHK(p, hipMemcpyAsync(v.mats, p->mats.data(), p->mats.size() * sizeof(MatDesc),
                            hipMemcpyHostToDevice, s));
+  if (!p->seps.empty())
+    HIPCHK(p, hipMemcpyAsync(v.seps, p->seps.data(), p->seps.size() * sizeof(SepDesc), hipMemcpyHostToDevice, s));
   // the host copies must stay alive until the copies complete
   HIPCHK(p, hipStreamSynchronize(s));
   k_fill_i32<<<(nb + 255) / 256, 256, 0, s>>>(status, nb, 0);
@@ -720,7 +818,7 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
   for (int kind = 0; kind < 2; ++kind) {
     int64_t tot = p->max_fac_tiles * 128;
     int64_t blocks = std::min<int64_t>((tot + 255) / 256, 65535);
-    dim3 grid((unsigned)blocks, nb);
+    dim3 grid((unsigned)blocks, nb, p->any_split[kind] ? 3 : 1);
     double by = 0;
     for (auto& m : p->meta) {
       double n, b;
@@ -733,7 +831,6 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
   }
   {
     double by = 0, fl = 0;
-    int max_nt = 0, max_bt = 0;
     for (auto& m : p->meta) {
       for (int kind = 0; kind < 2; ++kind) {
         double n, b;
@@ -741,30 +838,57 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
         by += 2 * 8.0 * band_entries(n, b);
         fl += n * b * b - 2.0 / 3.0 * b * b * b;
       }
-      max_nt = std::max(max_nt, std::max(m.nt11, m.nth));
-      max_bt = std::max(max_bt, std::max(m.bt11, m.bth));
     }
     ProfScope ps(p, PK_POTRF, s, by, fl);
-    if (band_cholesky(p, v.mats, (int)p->mats.size(), max_nt, max_bt, v.fac, status, !fused_unit, s))
+    // whole bands and chains (a chain stops at its separator rows), the
+    // separators' Schur complements, then the separator blocks
+    int last_J = -1, max_nt = 0, max_bt = 0;
+    for (int i = 0; i < p->n_chain_mats; ++i) {
+      const MatDesc& d = p->mats[i];
+      last_J = std::max(last_J, d.NTf < d.NT ? d.NTf - 1 : d.NT - 2);
+      max_nt = std::max(max_nt, d.NT);
+      max_bt = std::max(max_bt, d.BT);
+    }
+    const int nsep = (int)p->seps.size();
+    // the separators' Schur complements read the chains' Cholesky tiles, so
+    // the unit-lower rewrite of the chains (when not fused into the copies)
+    // comes after them
+    if (band_cholesky(p, v.mats, p->n_chain_mats, last_J, max_nt, max_bt, v.fac, status, !fused_unit && !nsep, s))
       return MSGFEM_EHIP;
+    if (nsep) {
+      const int nts = p->max_nts;
+      k_sep_syrk<<<dim3((nts * (nts + 1) / 2 + 3) / 4, nsep), 256, 0, s>>>(v.seps, v.fac);
+      LAUNCHCHK(p);
+      if (!fused_unit) {
+        k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), p->n_chain_mats), 256, 0, s>>>(v.mats,
+                                                                                                         v.fac);
+        LAUNCHCHK(p);
+      }
+      if (band_cholesky(p, v.mats + p->n_chain_mats, nsep, nts - 2, nts, nts, v.fac, status, !fused_unit, s))
+        return MSGFEM_EHIP;
+    }
   }
   for (int kind = 0; kind < 2; ++kind) {
     int max_nt = 1, max_sets = 1;
     double by = 0;
-    for (auto& m : p->meta) {
-      int nt = kind == 0 ? m.nt11 : m.nth, bt = kind == 0 ? m.bt11 : m.bth;
-      max_nt = std::max(max_nt, nt);
-      max_sets = std::max(max_sets, solve_sets(bt));
-      by += 3 * 8.0 * solve_copy_doubles(nt, bt);
-    }
+    for (auto& m : p->meta)
+      for (int pi = 0; pi < (m.nd[kind] ? 3 : 1); ++pi) {
+        const BandPart& q = m.part[kind][pi];
+        max_nt = std::max(max_nt, q.NT);
+        max_sets = std::max(max_sets, solve_sets(q.BT));
+        by += 3 * 8.0 * solve_copy_doubles(q.NT, q.BT);
+      }
     ProfScope ps(p, PK_BUILD, s, by, 0.0);
+    const unsigned nz = (unsigned)(3 * nb);
+    const int wide = wide_kind(p, kind) ? 1 : 0;
     if (fused_unit)
-      k_band_unit_relayout4<<<dim3((solve4_slots(p->max_bt_kind[kind]) + 3) / 4, max_nt, nb), 256, 0, s>>>(
-          v.meta, kind, v.fac);
+      k_band_unit_relayout4<<<dim3((solve4_slots(p->max_bt_kind[kind]) + 3) / 4, max_nt, nz), 256, 0, s>>>(
+          v.meta, kind, v.fac, wide);
     else if (solve4_kind(p, kind))
-      k_band_relayout4<<<dim3(solve4_slots(p->max_bt_kind[kind]), max_nt, nb), 256, 0, s>>>(v.meta, kind, v.fac);
+      k_band_relayout4<<<dim3(solve4_slots(p->max_bt_kind[kind]), max_nt, nz), 256, 0, s>>>(v.meta, kind, v.fac,
+                                                                                             wide);
     else
-      k_band_relayout<<<dim3(SOLVE_TILES * max_sets, max_nt, nb), 256, 0, s>>>(v.meta, kind, v.fac);
+      k_band_relayout<<<dim3(SOLVE_TILES * max_sets, max_nt, nz), 256, 0, s>>>(v.meta, kind, v.fac);
     LAUNCHCHK(p);
   }
   if (p->opts.precision >= 1) {
@@ -798,6 +922,7 @@ struct Work {
   int32_t* reached;
   int32_t* xbuf;
   double* scr;
+  double* sep;
 };
 }  // namespace
 
@@ -819,6 +944,7 @@ static Work work_view(const msgfem_plan* p, void* work) {
   w.reached = (int32_t*)(b + p->w_reached);
   w.xbuf = (int32_t*)(b + p->w_xbuf);
   w.scr = (double*)(b + p->w_scr);
+  w.sep = (double*)(b + p->w_sep);
   return w;
 }
 
@@ -845,10 +971,15 @@ static void lds_attributes() {
   const void* solves[4] = {(const void*)k_band_solve<KC, 1, double>, (const void*)k_band_solve<KC, 2, double>,
                            (const void*)k_band_solve<KC, 1, float>, (const void*)k_band_solve<KC, 2, float>};
   for (const void* f : solves) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  const void* solves4[8] = {(const void*)k_band_solve4<1, double>, (const void*)k_band_solve4<2, double>,
-                            (const void*)k_band_solve4<3, double>, (const void*)k_band_solve4<4, double>,
-                            (const void*)k_band_solve4<1, float>,  (const void*)k_band_solve4<2, float>,
-                            (const void*)k_band_solve4<3, float>,  (const void*)k_band_solve4<4, float>};
+  const void* solves4[16] = {
+      (const void*)k_band_solve4<1, false, double>, (const void*)k_band_solve4<2, false, double>,
+      (const void*)k_band_solve4<3, false, double>, (const void*)k_band_solve4<4, false, double>,
+      (const void*)k_band_solve4<1, false, float>,  (const void*)k_band_solve4<2, false, float>,
+      (const void*)k_band_solve4<3, false, float>,  (const void*)k_band_solve4<4, false, float>,
+      (const void*)k_band_solve4<1, true, double>,  (const void*)k_band_solve4<2, true, double>,
+      (const void*)k_band_solve4<3, true, double>,  (const void*)k_band_solve4<4, true, double>,
+      (const void*)k_band_solve4<1, true, float>,   (const void*)k_band_solve4<2, true, float>,
+      (const void*)k_band_solve4<3, true, float>,   (const void*)k_band_solve4<4, true, float>};
   for (const void* f : solves4) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_update<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
@@ -899,9 +1030,12 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
                  const int32_t* active) {
   // the preconditioner's matrix (kind 1) from its FP32 copy under precision 1
   const bool f32 = c.use32 || (kind == 1 && c.pre32);
-  int nchunk = (kk + KC - 1) / KC;
-  dim3 grid(8 * nchunk * ((c.nb + 7) / 8));
-  size_t lds = (size_t)c.p->max_bt_kind[kind] * 32 * KC * 8;
+  const bool wide = wide_kind(c.p, kind);
+  const int kc = wide ? 16 : KC;
+  const int nchunk = (kk + kc - 1) / kc;
+  const size_t lds = (size_t)c.p->max_bt_kind[kind] * 32 * kc * 8;
+  // a 16-column chunk takes the scratch of two 8-column chunks
+  const int64_t scr_stride = c.p->scr_stride * (kc / KC), sep_q = c.p->sep_q * (kc / KC);
   double by = 0, fl = 0;
   for (int b = 0; b < c.nb; ++b) {
     if (!c.counts(b, active)) continue;
@@ -914,25 +1048,36 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
   ProfScope ps(c.p, PK_SOLVE, c.s, by, fl, !c.no_alloc);
   // bands wider than SOLVE_TILES + 1 tiles take two tile sets per step
   const bool two = c.p->max_bt_kind[kind] - 1 > SOLVE_TILES;
+  // one launch (phase 0) without split boxes, else chains forward (two units
+  // per box), separator blocks, chains backward
+  const bool split = c.p->any_split[kind];
   auto launch = [&](auto kern, auto ft) {
-    kern<<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, ft, c.v.cls, in, out, kk, out_classes, zero_rest,
-                                  c.w.scr, c.p->scr_stride, active);
+    for (int ph = split ? 1 : 0; ph <= (split ? 3 : 0); ++ph) {
+      const int nun = (ph == 1 || ph == 3) ? 2 * c.nb : c.nb;
+      dim3 grid(8 * nchunk * ((nun + 7) / 8));
+      kern<<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, ft, c.v.cls, in, out, kk, out_classes, zero_rest,
+                                    c.w.scr, scr_stride, active, ph, c.w.sep, sep_q);
+    }
   };
   if (solve4_kind(c.p, kind)) {
     // bands of at most 33 tiles: the matrix-core solve, 1..4 tile slots per wavefront
     const int ns = solve4_nslot(c.p->max_bt_kind[kind]);
+    auto pick = [&](auto wide_tag, auto ft) {
+      constexpr bool W = decltype(wide_tag)::value;
+      typedef typename std::remove_const<typename std::remove_pointer<decltype(ft)>::type>::type FT;
+      if (ns <= 1) launch(k_band_solve4<1, W, FT>, ft);
+      else if (ns == 2) launch(k_band_solve4<2, W, FT>, ft);
+      else if (ns == 3) launch(k_band_solve4<3, W, FT>, ft);
+      else launch(k_band_solve4<4, W, FT>, ft);
+    };
     if (f32) {
       const float* f = (const float*)c.v.fac32;
-      if (ns <= 1) launch(k_band_solve4<1, float>, f);
-      else if (ns == 2) launch(k_band_solve4<2, float>, f);
-      else if (ns == 3) launch(k_band_solve4<3, float>, f);
-      else launch(k_band_solve4<4, float>, f);
+      if (wide) pick(std::true_type(), f);
+      else pick(std::false_type(), f);
     } else {
       const double* f = (const double*)c.v.fac;
-      if (ns <= 1) launch(k_band_solve4<1, double>, f);
-      else if (ns == 2) launch(k_band_solve4<2, double>, f);
-      else if (ns == 3) launch(k_band_solve4<3, double>, f);
-      else launch(k_band_solve4<4, double>, f);
+      if (wide) pick(std::true_type(), f);
+      else pick(std::false_type(), f);
     }
   } else if (f32) {
     if (two) launch(k_band_solve<KC, 2, float>, (const float*)c.v.fac32);
@@ -1452,10 +1597,15 @@ static int static_scratch(msgfem_plan* p, void** out) {
 }
 
 // bytes of static scratch an op of this plan needs (256-aligned pieces)
+static int64_t static_scratch_w_bytes(const msgfem_plan* p) {
+  const int nchunk = 2 * ((p->k + 15) / 16);   // 8-column chunks, whole chunks of 16
+  return align256((int64_t)2 * p->meta.size() * nchunk * p->scr_stride * 8);
+}
 static int64_t static_scratch_bytes(const msgfem_plan* p, int op) {
   if (op == 0 || op == 1) return align256(p->dofs_total * p->k * 8);
-  const int nchunk = (p->k + KC - 1) / KC;
-  return align256((int64_t)p->meta.size() * nchunk * p->scr_stride * 8);
+  const int nchunk = 2 * ((p->k + 15) / 16);
+  const bool split = p->any_split[op == 2 ? 0 : 1];
+  return static_scratch_w_bytes(p) + (split ? align256((int64_t)p->meta.size() * nchunk * 4 * p->sep_q * 8) : 0);
 }
 
 extern "C" int64_t msgfem_static_scratch_max(void) { return MSGFEM_STATIC_SCRATCH_MAX; }
@@ -1482,7 +1632,9 @@ extern "C" int msgfem_local_apply_static(msgfem_plan* p, const void* ops, int32_
   c.k = p->k;
   c.no_alloc = true;
   std::memset(&c.w, 0, sizeof c.w);
-  c.w.scr = (double*)base;   // the solves' w rows (written before they are read)
+  // the solves' w rows and separator exchange (written before they are read)
+  c.w.scr = (double*)base;
+  c.w.sep = (double*)((char*)base + static_scratch_w_bytes(p));
   return apply_impl(c, op, kk, x, y, (double*)base);
 }
 
@@ -1512,6 +1664,15 @@ extern "C" int msgfem_plan_set_option(msgfem_plan* p, int32_t key, int64_t value
         p->graphs.clear();
       }
       return MSGFEM_OK;
+    case MSGFEM_OPT_SPLIT: {
+      if (value != 0 && value != 1) return fail(p, MSGFEM_EARG, "MSGFEM_OPT_SPLIT takes 0 or 1, not %lld",
+                                               (long long)value);
+      if (p->split == (int)value) return MSGFEM_OK;
+      p->split = (int)value;
+      for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+      p->graphs.clear();
+      return plan_layout(p, p->nsd, p->mesh.n_mat);
+    }
     default:
       return fail(p, MSGFEM_EARG, "unknown plan option %d", key);
   }
@@ -1521,6 +1682,13 @@ extern "C" int msgfem_plan_get_option(const msgfem_plan* p, int32_t key, int64_t
   if (!p || !value) return MSGFEM_EARG;
   switch (key) {
     case MSGFEM_OPT_GRAPH: *value = p->graph_mode; return MSGFEM_OK;
+    case MSGFEM_OPT_SPLIT: *value = p->split; return MSGFEM_OK;
+    case MSGFEM_INFO_SPLIT_BOXES: {
+      int64_t n = 0;
+      for (auto& m : p->meta) n += m.nd[0] + 2 * m.nd[1];
+      *value = n;
+      return MSGFEM_OK;
+    }
     case MSGFEM_INFO_GRAPH_LAUNCHES: *value = p->graph_launches; return MSGFEM_OK;
     case MSGFEM_INFO_GRAPH_ITERS: *value = p->graph_iters; return MSGFEM_OK;
     case MSGFEM_INFO_GRAPHS_CACHED: *value = (int64_t)p->graphs.size(); return MSGFEM_OK;
@@ -2062,7 +2230,10 @@ struct msgfem_coarse {
   int nsd = 0, overlap = 0, geneo = 0, kc = 0, NH = 0, NTc = 0;
   int64_t n_nodes_global = 0, dofs_total = 0, loc_total = 0;
   int max_dof = 0, max_nt11 = 0, max_bt11 = 0;
-  bool loc_solve4 = false;          // layout of the exported local solves (GenEO)
+  bool split11 = false;             // some A11 band is split (its local solve takes three phases)
+  int max_nts = 0;
+  bool loc_solve4 = false;          // layout of the exported local solves (GenEO): matrix-core
+  bool loc_wide = false;            // ... with 16 columns per workgroup
   std::vector<int32_t> omega;       // [nsd][6] node boxes of Omega_j
   std::vector<int32_t> cores, ovs;
   std::vector<BoxMeta> meta;        // every subdomain, in subdomain order
@@ -2136,13 +2307,24 @@ extern "C" int msgfem_coarse_create(msgfem_coarse** out, int device, const msgfe
     m.node_off = node_off;
     m.dof_off = dof_off;
     m.eval_off = c->NH;
+    // the band parts of a plan with the default layout (MSGFEM_OPT_SPLIT = 1)
+    band_parts(m, true);
     if (c->geneo) {
-      m.f11_fw = loc_off;
-      loc_off += solve_copy_doubles(m.nt11, m.bt11);
-      m.f11_bw = loc_off;
-      loc_off += solve_copy_doubles(m.nt11, m.bt11);
-      m.f11i_off = loc_off;            // D^{-1} tiles, compact
-      loc_off += (int64_t)m.nt11 * MSG_TILE2;
+      for (int pi = 0; pi < (m.nd[0] ? 3 : 1); ++pi) {
+        BandPart& q = m.part[0][pi];
+        q.fw = loc_off;
+        loc_off += solve_copy_doubles(q.NT, q.BT);
+        q.bw = loc_off;
+        loc_off += solve_copy_doubles(q.NT, q.BT);
+        q.ioff = loc_off;            // D^{-1} tiles, compact
+        loc_off += (int64_t)q.NT * MSG_TILE2;
+        c->max_nt11 = std::max(c->max_nt11, q.NT);
+        c->max_bt11 = std::max(c->max_bt11, q.BT);
+      }
+      if (m.nd[0]) {
+        c->split11 = true;
+        c->max_nts = std::max(c->max_nts, m.part[0][2].NT);
+      }
       m.flags |= BOX_COMPACT_DINV;
     }
     node_off += m.n_nodes;
@@ -2150,14 +2332,13 @@ extern "C" int msgfem_coarse_create(msgfem_coarse** out, int device, const msgfe
     c->NH += m.n_ev;
     kc = std::max(kc, m.n_ev);
     c->max_dof = std::max(c->max_dof, m.n_dof);
-    c->max_nt11 = std::max(c->max_nt11, m.nt11);
-    c->max_bt11 = std::max(c->max_bt11, m.bt11);
   }
   c->kc = kc + (kc & 1);
   c->dofs_total = dof_off;
   c->loc_total = loc_off;
   c->NTc = (c->NH + 31) / 32;
   c->loc_solve4 = c->max_bt11 - 1 <= 8 * SOLVE4_MAX_SLOTS;
+  c->loc_wide = c->loc_solve4 && c->max_bt11 <= WIDE_MAX_BT;
   if (c->geneo && c->max_bt11 > SOLVE_MAX_BT)
     return cfail(c, MSGFEM_ESIZE, "band of %d tiles too wide for the block solve", c->max_bt11);
   // pairs (i, j): Omega_i meets the box of j (the support of A V_j)
@@ -2271,8 +2452,11 @@ extern "C" int msgfem_coarse_add(msgfem_coarse* c, msgfem_plan* p, const void* o
     if (m.mx != t.mx || m.my != t.my || m.mz != t.mz || m.g0[0] != t.g0[0] || m.g0[1] != t.g0[1] ||
         m.g0[2] != t.g0[2] || m.n_ev != t.n_ev)
       return cfail(c, MSGFEM_EARG, "subdomain %d has another box or n_ev in the plan", m.sd);
+    if (c->geneo && (m.nd[0] != t.nd[0] || m.part[0][0].NT != t.part[0][0].NT))
+      return cfail(c, MSGFEM_EARG, "subdomain %d: the plan's interior band layout differs from the coarse object's "
+                   "(the store takes the default MSGFEM_OPT_SPLIT)", m.sd);
   }
-  if (c->geneo && solve4_kind(p, 0) != c->loc_solve4)
+  if (c->geneo && (solve4_kind(p, 0) != c->loc_solve4 || wide_kind(p, 0) != c->loc_wide))
     return cfail(c, MSGFEM_EARG,
                  "the plan's interior factors use the %s solve layout, the coarse object the %s one (give the plan "
                  "a box with the widest band)",
@@ -2427,22 +2611,32 @@ extern "C" int msgfem_coarse_solve_store(msgfem_coarse* c, void* store, const do
 
 // Block solve of kind `kind` on FP32 factor copies for a box list given only
 // on the device (no plan): the store-based PCG's local Dirichlet solves.
-static int solve_f32(hipStream_t s, const BoxMeta* meta, int nb, int max_bt, bool use4, int kind, const float* ft,
-                     const uint8_t* cls, const double* in, double* out, int kk, int out_classes, int zero_rest,
-                     double* scr, int64_t scr_stride) {
-  const int nchunk = (kk + KC - 1) / KC;
-  dim3 grid(8 * nchunk * ((nb + 7) / 8));
-  const size_t lds = (size_t)max_bt * 32 * KC * 8;
+static int solve_f32(hipStream_t s, const BoxMeta* meta, int nb, int max_bt, bool use4, bool wide, int kind,
+                     const float* ft, const uint8_t* cls, const double* in, double* out, int kk, int out_classes,
+                     int zero_rest, double* scr, int64_t scr_stride, bool split, double* sep, int64_t sep_q) {
+  const int kc = wide ? 16 : KC;
+  const int nchunk = (kk + kc - 1) / kc;
+  const size_t lds = (size_t)max_bt * 32 * kc * 8;
   auto launch = [&](auto kern) {
-    kern<<<grid, 512, lds, s>>>(meta, nb, nchunk, kind, ft, cls, in, out, kk, out_classes, zero_rest, scr, scr_stride,
-                                nullptr);
+    for (int ph = split ? 1 : 0; ph <= (split ? 3 : 0); ++ph) {
+      const int nun = (ph == 1 || ph == 3) ? 2 * nb : nb;
+      dim3 grid(8 * nchunk * ((nun + 7) / 8));
+      kern<<<grid, 512, lds, s>>>(meta, nb, nchunk, kind, ft, cls, in, out, kk, out_classes, zero_rest, scr,
+                                  scr_stride, nullptr, ph, sep, sep_q);
+    }
   };
-  if (use4) {
+  if (use4 && wide) {
     const int ns = solve4_nslot(max_bt);
-    if (ns <= 1) launch(k_band_solve4<1, float>);
-    else if (ns == 2) launch(k_band_solve4<2, float>);
-    else if (ns == 3) launch(k_band_solve4<3, float>);
-    else launch(k_band_solve4<4, float>);
+    if (ns <= 1) launch(k_band_solve4<1, true, float>);
+    else if (ns == 2) launch(k_band_solve4<2, true, float>);
+    else if (ns == 3) launch(k_band_solve4<3, true, float>);
+    else launch(k_band_solve4<4, true, float>);
+  } else if (use4) {
+    const int ns = solve4_nslot(max_bt);
+    if (ns <= 1) launch(k_band_solve4<1, false, float>);
+    else if (ns == 2) launch(k_band_solve4<2, false, float>);
+    else if (ns == 3) launch(k_band_solve4<3, false, float>);
+    else launch(k_band_solve4<4, false, float>);
   } else if (max_bt - 1 > SOLVE_TILES) {
     launch(k_band_solve<KC, 2, float>);
   } else {
@@ -2453,15 +2647,17 @@ static int solve_f32(hipStream_t s, const BoxMeta* meta, int nb, int max_bt, boo
 
 namespace {
 struct CPcgLayout {
-  int64_t meta, ctab, omega, wtot, stencil, cls, mu, b, x, r, z, p, q, rb, zb, zero, part, sc, scr, total;
-  int64_t scr_stride;
+  int64_t meta, ctab, omega, wtot, stencil, cls, mu, b, x, r, z, p, q, rb, zb, zero, part, sc, scr, sep, total;
+  int64_t scr_stride, sep_q;
 };
 }  // namespace
 
 static CPcgLayout cpcg_layout(const msgfem_coarse* c) {
   CPcgLayout L;
   const int64_t ng = c->n_nodes_global, nd = 3 * ng, nbd = c->dofs_total;
-  L.scr_stride = (int64_t)(c->max_nt11 + 1) * 32 * KC;
+  const int kc = c->loc_wide ? 16 : KC;
+  L.scr_stride = (int64_t)(c->max_nt11 + 1) * 32 * kc;
+  L.sep_q = (int64_t)(c->max_nts + 1) * 32 * kc;
   int64_t off = 0;
   L.meta = off; off = align256(off + sizeof(BoxMeta));
   L.ctab = off; off = align256(off + (int64_t)c->mesh.n_mat * 36 * 8);
@@ -2481,7 +2677,8 @@ static CPcgLayout cpcg_layout(const msgfem_coarse* c) {
   L.zero = off; off = align256(off + nbd * 8);
   L.part = off; off = align256(off + 1024 * 8);
   L.sc = off; off = align256(off + 16 * 8);
-  L.scr = off; off = align256(off + (int64_t)c->nsd * L.scr_stride * 8);
+  L.scr = off; off = align256(off + (int64_t)2 * c->nsd * L.scr_stride * 8);
+  L.sep = off; off = align256(off + (c->split11 ? (int64_t)c->nsd * 4 * L.sep_q * 8 : 0));
   L.total = off;
   return L;
 }
@@ -2577,8 +2774,8 @@ extern "C" int msgfem_coarse_pcg(msgfem_coarse* c, void* store, const double* A0
   auto precond = [&](const double* rin, double* zout) -> int {
     k_fill_f64<<<4096, 256, 0, s>>>(zout, nd, 0.0);
     k_gather_boxes<<<dim3((c->max_dof + 255) / 256, nsd), 256, 0, s>>>(smeta, md, scls, rin, rb);
-    if (solve_f32(s, smeta, nsd, c->max_bt11, c->loc_solve4, 0, (const float*)(st + c->s_loc), scls, rb, zb, 1,
-                  1 << 1, 1, scr, L.scr_stride))
+    if (solve_f32(s, smeta, nsd, c->max_bt11, c->loc_solve4, c->loc_wide, 0, (const float*)(st + c->s_loc), scls, rb, zb, 1,
+                  1 << 1, 1, scr, L.scr_stride, c->split11, (double*)(pb + L.sep), L.sep_q))
       return 1;
     k_scatter_boxes<<<dim3((c->max_dof + 255) / 256, nsd), 256, 0, s>>>(smeta, md, scls, zb, zout);
     k_coarse_restrict<<<nsd, 256, 0, s>>>(smeta, K, sV, rb, sroff, rc);

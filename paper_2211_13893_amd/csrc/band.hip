@@ -16,21 +16,26 @@
 
 namespace msg {
 
-// One thread per 8 consecutive entries of a tile row (the row is decoded
-// once, the columns by increments); grid.x strides over NT*BT*128 of the
-// largest box, grid.y = box.  Entries beyond the matrix are identity rows,
-// entries between inactive DoFs identity or zero, the rest the stencil value
-// (times 1 + s mu_r mu_c for Ahat).
+// One thread per 8 consecutive entries of a tile row; grid.x strides over
+// NT*BT*128 of the largest part, grid.y = box, grid.z = part.  Entries of
+// padding rows are identity rows, entries between inactive DoFs identity or
+// zero, the rest the stencil value (times 1 + s mu_r mu_c for Ahat).  In a
+// chain of a split matrix the separator x separator block is left zero (it
+// belongs to S alone).
 __global__ void k_band_build(const BoxMeta* __restrict__ meta, int kind,
                              const double* __restrict__ stencil, const uint8_t* __restrict__ cls,
                              const double* __restrict__ mu1, double shift, double* __restrict__ fac) {
   const BoxMeta& bm = meta[blockIdx.y];
-  BandView v = band_view(bm, kind);
+  const int part = blockIdx.z;
+  if (part > 0 && !bm.nd[kind]) return;
+  BandView v = band_view(bm, kind, part);
+  const bool chain = bm.nd[kind] && part < 2;
+  const int sep0 = chain ? v.NTf * MSG_TILE : 0x7fffffff;   // first separator row of a chain
   const int64_t total = (int64_t)v.NT * v.BT * (MSG_TILE2 / 8);
   const double* st = stencil + bm.node_off * 243;
   const uint8_t* cl = cls + bm.dof_off;
   const double* m1 = mu1 + bm.dof_off;
-  double* out = fac + (kind == 0 ? bm.f11_off : bm.fh_off);
+  double* out = fac + v.off;
   const int sxy = v.sx * v.sy;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -39,25 +44,25 @@ __global__ void k_band_build(const BoxMeta* __restrict__ meta, int kind,
     const int I = (int)(tile / v.BT), s = (int)(tile % v.BT);
     const int row = I * MSG_TILE + (g >> 2), col0 = (I - s) * MSG_TILE + 8 * (g & 3);
     double val[8];
-    // row: sub-box node coordinates, component, DoF, class
-    const bool rin = row < v.n;
-    const int rnode = rin ? row / 3 : 0, rc = rin ? row - 3 * (row / 3) : 0;
+    // row: order coordinates, component, DoF, class
+    const int rq = band_to_order(v, row);
+    const bool rin = rq >= 0;
+    const int rnode = rin ? rq / 3 : 0, rc = rin ? rq - 3 * (rq / 3) : 0;
     const int ri = rnode % v.sx, rj = (rnode / v.sx) % v.sy, rk = rnode / sxy;
     const int dr = 3 * (v.base + ri * v.st0 + rj * v.st1 + rk * v.st2) + rc;
     const bool ar = rin && dof_active(kind, cl[dr]);
     const double mr = (kind == 1 && rin) ? m1[dr] : 0.0;
-    // first column, then increments
-    const int c0 = max(col0, 0);
-    int cnode = c0 / 3, cc = c0 - 3 * cnode;
-    int ci = cnode % v.sx, cj = (cnode / v.sx) % v.sy, ck = cnode / sxy;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int col = col0 + q;
       double x = 0.0;
-      if (col >= 0 && col <= row) {
-        if (!rin) {
+      if (col >= 0 && col <= row && !(row >= sep0 && col >= sep0)) {
+        const int cq = band_to_order(v, col);
+        if (!rin || cq < 0) {
           x = (row == col) ? 1.0 : 0.0;
         } else {
+          const int cnode = cq / 3, cc = cq - 3 * cnode;
+          const int ci = cnode % v.sx, cj = (cnode / v.sx) % v.sy, ck = cnode / sxy;
           const int dc = 3 * (v.base + ci * v.st0 + cj * v.st1 + ck * v.st2) + cc;
           const bool ac = dof_active(kind, cl[dc]);
           if (!ar || !ac) {
@@ -74,19 +79,6 @@ __global__ void k_band_build(const BoxMeta* __restrict__ meta, int kind,
         }
       }
       val[q] = x;
-      if (col >= 0) {
-        // next column: component, then node in the sub-box
-        if (++cc == 3) {
-          cc = 0;
-          if (++ci == v.sx) {
-            ci = 0;
-            if (++cj == v.sy) {
-              cj = 0;
-              ++ck;
-            }
-          }
-        }
-      }
     }
     double2* o = (double2*)(out + (tile << 10) + (g >> 2) * 32 + 8 * (g & 3));
 #pragma unroll
@@ -497,6 +489,10 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
   const int lane = threadIdx.x & 63;
   const int job = (int)blockIdx.y * 4 + (threadIdx.x >> 6);
   const int BT = v.BT, NT = v.NT;
+  // a chain of a split matrix factors its first NF columns only: its
+  // separator rows get L(I, J) for J < NF, no tile of a column >= NF changes
+  const int NF = v.NTf > 0 ? v.NTf : NT;
+  if (J >= NF) return;
   double* L = fac + v.off;
   auto tile = [&](int I, int K) { return L + ((int64_t)I * BT + (I - K)) * MSG_TILE2; };
   const double* LinvJ = fac + v.ioff + (int64_t)(J < 0 ? 0 : J) * MSG_TILE2;
@@ -507,6 +503,7 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
   if (job == 0) {
     const int R = J + 1;
     if (R > NT - 1) return;
+    const bool diag = R < NF;                // the diagonal tile R is factored here
     const bool has_x = J >= 0 && BT >= 2;    // tile (R, J) exists
     const bool has_k = J >= 1 && BT >= 3;    // tiles (R, J-1), (J, J-1) exist
     // first K of the diagonal tile's remaining products
@@ -532,6 +529,7 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) xt[bi][bj] = quadT_get(tile(R, J), bi, bj, lane) - xt[bi][bj];
       trsm_from_xt(LinvJ, xt, tile(R, J), lt, lane);
+      if (!diag) return;
       // + L(R,J) L(R,J)^T: the accumulators of L^T serve as both operands
 #pragma unroll
       for (int bk = 0; bk < 2; ++bk)
@@ -543,6 +541,7 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
             for (int bj = 0; bj < 2; ++bj)
               acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(lt[bk][bi][w], lt[bk][bj][w], acc[bi][bj], 0, 0, 0);
     }
+    if (!diag) return;
     for (int K = kd; K <= J - 1; ++K) {
       TileOps a;
       tops_load(tile(R, K), lane, a);
@@ -561,7 +560,7 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
   }
   if (job <= 2) {
     const int R = J + 1 + job;
-    if (!pair || R > NT - 1) return;
+    if (!pair || R > NT - 1 || R >= NF) return;
     const int k0 = max(0, R - (BT - 1)), k1 = J - 1;
     if (k0 > k1) return;
 #pragma unroll
@@ -603,10 +602,10 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
       for (int bj = 0; bj < 2; ++bj) xt[bi][bj] = quadT_get(T, bi, bj, lane) - xt[bi][bj];
     trsm_from_xt(LinvJ, xt, T, lt, lane);
   }
-  if (kb > k1) return;
+  if (kb > k1 || J + 1 >= NF) return;
   // the next column(s): odd J all final products, even J the one with K = J-1
   const int k0 = pair ? kb : k1;
-  const bool two = pair && s >= 3;
+  const bool two = pair && s >= 3 && J + 2 < NF;
   dbl4 acc2[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -644,6 +643,52 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
     for (int bj = 0; bj < 2; ++bj) quad_put(T1, 32, bi, bj, lane, quad_get(T1, 32, bi, bj, lane) - acc[bi][bj]);
 }
 
+// The separator's Schur complement of a split matrix, once both chains are
+// factored on their own columns:
+//   S(I,J) -= sum_{c = 0,1} sum_K Lc(NFc + I, K) Lc(NFc + J, K)^T,  I >= J,
+// K over chain c's columns in band of row NFc + I (the chain's separator
+// rows hold L_sc = A_sc L_cc^{-T}).  S then holds A_ss - sum_c L_sc L_sc^T
+// and is factored as a dense band.  One target tile per wavefront;
+// grid (ceil(max NTs (NTs + 1) / 2 / 4), n_sep), 256 threads.
+__global__ __launch_bounds__(256) void k_sep_syrk(const SepDesc* __restrict__ seps, double* __restrict__ fac) {
+  const SepDesc d = seps[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int t = (int)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int NTs = d.NTs;
+  if (t >= NTs * (NTs + 1) / 2) return;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (I > 0 && I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  const int J = t - I * (I + 1) / 2;
+  const dbl4 zero = {0.0, 0.0, 0.0, 0.0};
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = zero;
+  for (int c = 0; c < 2; ++c) {
+    const int NF = c ? d.NTf1 : d.NTf0;
+    const double* L = fac + (c ? d.off1 : d.off0);
+    auto tile = [&](int R, int K) { return L + ((int64_t)R * d.BT + (R - K)) * MSG_TILE2; };
+    for (int K = max(0, NF + I - (d.BT - 1)); K < NF; ++K) {
+      TileOps a, b;
+      tops_load(tile(NF + I, K), lane, a);
+      if (I == J) {
+        tops_abt<true>(a, a, acc);
+      } else {
+        tops_load(tile(NF + J, K), lane, b);
+        tops_abt(a, b, acc);
+      }
+    }
+  }
+  double* T = fac + d.offS + ((int64_t)I * NTs + (I - J)) * MSG_TILE2;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+      if (I != J || bi >= bj) quad_put(T, 32, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - acc[bi][bj]);
+}
+
 // After the factorisation A = L L^T: rewrite the factor in block unit-lower
 // form A = Lu D Lu^T with Lu(I,J) = L(I,J) L_JJ^{-1} (off-diagonal tiles, in
 // place) and D^{-1}_II = L_II^{-T} L_II^{-1} stored in the diagonal tile slot,
@@ -657,6 +702,7 @@ __global__ __launch_bounds__(256) void k_chol_unit(const MatDesc* __restrict__ m
   if (t >= (int64_t)v.NT * v.BT) return;
   const int I = (int)(t / v.BT), s = (int)(t % v.BT);
   if (s > I) return;
+  if (v.NTf > 0 && I - s >= v.NTf) return;   // a chain's separator block stays zero
   double* T = fac + v.off + ((int64_t)I * v.BT + s) * MSG_TILE2;
   const double* Ti = fac + v.ioff + (int64_t)(I - s) * MSG_TILE2;
   dbl4 acc[2][2];
@@ -678,18 +724,21 @@ __global__ __launch_bounds__(256) void k_chol_unit(const MatDesc* __restrict__ m
 // the band are zero.  One workgroup per (tile slot s, tile row I, box): it
 // stages the forward source tile (I, s) and the backward source tile
 // (I+s, s) in LDS with coalesced loads and writes the 16 threads' pieces of
-// each, 256 contiguous bytes per j.  grid (32*max nsets, max NT, n_box).
+// each, 256 contiguous bytes per j.  A chain of a split matrix has no tiles
+// in its separator columns.  grid (32*max nsets, max NT, 3 n_box): z = 3 box + part.
 __global__ __launch_bounds__(256) void k_band_relayout(const BoxMeta* __restrict__ meta, int kind,
                                                        double* __restrict__ fac) {
   __shared__ double Tf[MSG_TILE2], Tb[MSG_TILE2];
-  const BoxMeta& bm = meta[blockIdx.z];
-  BandView v = band_view(bm, kind);
+  const BoxMeta& bm = meta[blockIdx.z / 3];
+  const int part = blockIdx.z % 3;
+  if (part > 0 && !bm.nd[kind]) return;
+  BandView v = band_view(bm, kind, part);
   const int nthr = solve_nthr(v.BT), nsets = solve_sets(v.BT);
   const int s = 1 + blockIdx.x, I = blockIdx.y;
   if (I >= v.NT || s > SOLVE_TILES * nsets || (nsets == 1 && s > v.BT - 1)) return;
   const int p = (s - 1) / SOLVE_TILES, tbase = 16 * ((s - 1) % SOLVE_TILES);
   const double* L = fac + v.off;
-  const bool fok = s < v.BT && s <= I, bok = s < v.BT && I + s < v.NT;
+  const bool fok = s < v.BT && s <= I && I - s < v.NTf, bok = s < v.BT && I + s < v.NT && I < v.NTf;
   const int u = threadIdx.x;
   {
     const double2* src = (const double2*)(L + ((int64_t)I * v.BT + (fok ? s : 0)) * MSG_TILE2);
@@ -723,28 +772,46 @@ __global__ __launch_bounds__(256) void k_band_relayout(const BoxMeta* __restrict
 
 
 
+// Entry (row, inner index c0 of e = 0; e = 1 is c0 + 4) of a 32x32 tile held
+// by lane l in double2 piece pp of the matrix-core solve copies.  wide = 0:
+// the A operand of v_mfma_f64_4x4x4f64 (k_band_solve4), lane l = 16 kk + 4 o
+// + i -> row 16 (pp >> 2) + 4 o + i, c0 = 8 (pp & 3) + kk; wide = 1: the A
+// operand of v_mfma_f64_16x16x4f64 (k_band_solve16), lane l = 16 k + i ->
+// row 16 (pp >> 2) + i, c0 = 8 (pp & 3) + k.
+__device__ inline void solve_piece_entry(int wide, int pp, int l, int* row, int* c0) {
+  if (wide) {
+    *row = 16 * (pp >> 2) + (l & 15);
+    *c0 = 8 * (pp & 3) + (l >> 4);
+  } else {
+    *row = 16 * (pp >> 2) + 4 * ((l >> 2) & 3) + (l & 3);
+    *c0 = 8 * (pp & 3) + (l >> 4);
+  }
+}
+
 // Copies of the unit-lower band in the operand order of the matrix-core block
-// solve (k_band_solve4; bands of at most 33 tiles).  Tile row I has 1 + 8
+// solves (k_band_solve4, k_band_solve16; bands of at most 33 tiles).  Tile row I has 1 + 8
 // nslot slots of 8 KB: slot 0 of the forward copy is D^{-1}_I, slot s >= 1 the
 // tile (I, I-s) (forward) or (I+s, I)^T (backward); tiles outside the matrix
 // or the band are zero.  Inside a slot, double2 pp (0..7) of lane l = 16 kk +
 // 4 o + i holds A[16 rh + 4 o + i][4 ss + kk] for rh = pp >> 2 and ss = 2 (pp
 // & 3) + e, e = 0, 1 (the A operand of v_mfma_f64_4x4x4f64 for 4x4 blocks o),
 // at ((I S + slot) 8 + pp) 64 + l, S = solve4_slots(BT).  One workgroup per
-// (slot, tile row, box) stages the source tiles in LDS and writes 1 KB per pp.
-// grid (1 + 8 max nslot, max NT, n_box).
+// (slot, tile row, box part) stages the source tiles in LDS and writes 1 KB
+// per pp.  grid (1 + 8 max nslot, max NT, 3 n_box): z = 3 box + part.
 __global__ __launch_bounds__(256) void k_band_relayout4(const BoxMeta* __restrict__ meta, int kind,
-                                                        double* __restrict__ fac) {
+                                                        double* __restrict__ fac, int wide) {
   __shared__ double Tf[MSG_TILE2], Tb[MSG_TILE2];
-  const BoxMeta& bm = meta[blockIdx.z];
-  BandView v = band_view(bm, kind);
+  const BoxMeta& bm = meta[blockIdx.z / 3];
+  const int part = blockIdx.z % 3;
+  if (part > 0 && !bm.nd[kind]) return;
+  BandView v = band_view(bm, kind, part);
   const int S = solve4_slots(v.BT);
   const int slot = blockIdx.x, I = blockIdx.y;
   if (I >= v.NT || slot >= S) return;
   const double* L = fac + v.off;
   // forward source: D^{-1}_I (the diagonal slot after the unit-lower rewrite) or tile (I, I-s)
-  const bool fok = slot == 0 || (slot < v.BT && slot <= I);
-  const bool bok = slot >= 1 && slot < v.BT && I + slot < v.NT;
+  const bool fok = slot == 0 ? I < v.NTf : (slot < v.BT && slot <= I && I - slot < v.NTf);
+  const bool bok = slot >= 1 && slot < v.BT && I + slot < v.NT && I < v.NTf;
   const int u = threadIdx.x;
   {
     const double2* src = (const double2*)(L + ((int64_t)I * v.BT + (fok ? slot : 0)) * MSG_TILE2);
@@ -766,8 +833,8 @@ __global__ __launch_bounds__(256) void k_band_relayout4(const BoxMeta* __restric
   for (int r = 0; r < 2; ++r) {
     const int q = u + 256 * r;                 // (pp, lane)
     const int pp = q >> 6, l = q & 63;
-    const int kk = l >> 4, o = (l >> 2) & 3, i = l & 3;
-    const int row = 16 * (pp >> 2) + 4 * o + i, c0 = 4 * (2 * (pp & 3)) + kk;   // inner index of e = 0; e = 1 adds 4
+    int row, c0;   // entry of e = 0 (e = 1 adds 4 to the inner index)
+    solve_piece_entry(wide, pp, l, &row, &c0);
     fw[q] = make_double2(Tf[row * 32 + c0], Tf[row * 32 + c0 + 4]);
     bw[q] = make_double2(Tb[c0 * 32 + row], Tb[(c0 + 4) * 32 + row]);
   }
@@ -783,13 +850,17 @@ __global__ __launch_bounds__(256) void k_band_relayout4(const BoxMeta* __restric
 // copies written once, instead of reading the band, rewriting it and reading
 // it again.  Slots outside the matrix or the band are zero: a forward slot
 // with s > I or s >= BT, a backward slot with s = 0, s >= BT or I + s >= NT.
-// One wavefront per slot s = 4 blockIdx.x + wave of tile row I = blockIdx.y;
-// grid (ceil(S / 4), max NT, n_box), 256 threads.
+// A chain of a split matrix has no D^{-1} on its separator rows and no
+// tiles in its separator columns.  One wavefront per slot s = 4 blockIdx.x +
+// wave of tile row I = blockIdx.y; grid (ceil(S / 4), max NT, 3 n_box): z = 3
+// box + part, 256 threads.
 __global__ __launch_bounds__(256) void k_band_unit_relayout4(const BoxMeta* __restrict__ meta, int kind,
-                                                             double* __restrict__ fac) {
+                                                             double* __restrict__ fac, int wide) {
   __shared__ double Tl[4][MSG_TILE2];
-  const BoxMeta& bm = meta[blockIdx.z];
-  BandView v = band_view(bm, kind);
+  const BoxMeta& bm = meta[blockIdx.z / 3];
+  const int part = blockIdx.z % 3;
+  if (part > 0 && !bm.nd[kind]) return;
+  BandView v = band_view(bm, kind, part);
   const int S = solve4_slots(v.BT);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int s = 4 * blockIdx.x + wave, I = blockIdx.y;
@@ -797,9 +868,8 @@ __global__ __launch_bounds__(256) void k_band_unit_relayout4(const BoxMeta* __re
   double* L = fac + v.off;
   const double* Linv = fac + v.ioff;
   double2* fw = (double2*)(fac + v.fw) + ((int64_t)I * S + s) * 8 * 64;
-  // operand order of the lane (see k_band_relayout4): row and inner index of e = 0
-  const int kk = lane >> 4, o = (lane >> 2) & 3, i = lane & 3;
-  if (s == 0 || (s < v.BT && s <= I)) {
+
+  if (s == 0 ? I < v.NTf : (s < v.BT && s <= I && I - s < v.NTf)) {
     double* T = Tl[wave];
     dbl4 acc[2][2];
 #pragma unroll
@@ -815,7 +885,9 @@ __global__ __launch_bounds__(256) void k_band_unit_relayout4(const BoxMeta* __re
     double2* bw = (double2*)(fac + v.bw) + ((int64_t)(I - s) * S + s) * 8 * 64;
 #pragma unroll
     for (int pp = 0; pp < 8; ++pp) {
-      const int row = 16 * (pp >> 2) + 4 * o + i, c0 = 8 * (pp & 3) + kk;
+      // operand order of the lane (see k_band_relayout4): row and inner index of e = 0
+      int row, c0;
+      solve_piece_entry(wide, pp, lane, &row, &c0);
       fw[pp * 64 + lane] = make_double2(T[row * 32 + c0], T[row * 32 + c0 + 4]);
       if (s >= 1) bw[pp * 64 + lane] = make_double2(T[c0 * 32 + row], T[(c0 + 4) * 32 + row]);
     }
@@ -823,7 +895,7 @@ __global__ __launch_bounds__(256) void k_band_unit_relayout4(const BoxMeta* __re
 #pragma unroll
     for (int pp = 0; pp < 8; ++pp) fw[pp * 64 + lane] = make_double2(0.0, 0.0);
   }
-  if (s == 0 || s >= v.BT || I + s >= v.NT) {
+  if (s == 0 || s >= v.BT || I + s >= v.NT || I >= v.NTf) {
     double2* bz = (double2*)(fac + v.bw) + ((int64_t)I * S + s) * 8 * 64;
 #pragma unroll
     for (int pp = 0; pp < 8; ++pp) bz[pp * 64 + lane] = make_double2(0.0, 0.0);
@@ -832,9 +904,9 @@ __global__ __launch_bounds__(256) void k_band_unit_relayout4(const BoxMeta* __re
 
 
 // FP32 copies for the mixed path (same element offsets as the FP64 arrays):
-// the two solve-ordered band copies and the D^{-1} diagonal tiles of both box
-// matrices (grid.y = box, grid.z = matrix kind), and the stencil
-// (grid.z = 2).
+// the two solve-ordered band copies and the D^{-1} diagonal tiles of every
+// part of both box matrices (grid.y = box, grid.z = matrix kind), and the
+// stencil (grid.z = 2).
 __global__ void k_mixed_copies(const BoxMeta* __restrict__ meta, int zbase, const double* __restrict__ fac,
                                float* __restrict__ fac32, const double* __restrict__ stencil,
                                float* __restrict__ stencil32) {
@@ -846,16 +918,18 @@ __global__ void k_mixed_copies(const BoxMeta* __restrict__ meta, int zbase, cons
     for (int64_t e = t0; e < n; e += st) stencil32[o + e] = (float)stencil[o + e];
     return;
   }
-  BandView v = band_view(bm, z);
-  const int64_t nb = solve_copy_doubles(v.NT, v.BT);
-  for (int64_t e = t0; e < nb; e += st) {
-    fac32[v.fw + e] = (float)fac[v.fw + e];
-    fac32[v.bw + e] = (float)fac[v.bw + e];
-  }
-  const int64_t nd = (int64_t)v.NT * MSG_TILE2;
-  for (int64_t e = t0; e < nd; e += st) {
-    const int64_t o = v.off + (e >> 10) * v.BT * MSG_TILE2 + (e & 1023);
-    fac32[o] = (float)fac[o];
+  for (int part = 0; part < (bm.nd[z] ? 3 : 1); ++part) {
+    BandView v = band_view(bm, z, part);
+    const int64_t nb = solve_copy_doubles(v.NT, v.BT);
+    for (int64_t e = t0; e < nb; e += st) {
+      fac32[v.fw + e] = (float)fac[v.fw + e];
+      fac32[v.bw + e] = (float)fac[v.bw + e];
+    }
+    const int64_t nd = (int64_t)v.NT * MSG_TILE2;
+    for (int64_t e = t0; e < nd; e += st) {
+      const int64_t o = v.off + (e >> 10) * v.BT * MSG_TILE2 + (e & 1023);
+      fac32[o] = (float)fac[o];
+    }
   }
 }
 

@@ -375,23 +375,28 @@ __global__ void k_store_box(const BoxMeta* __restrict__ pmeta, const BoxMeta* __
   }
 }
 
-// FP32 copies of the two solve-ordered copies of a plan box's A11 factor and
-// of its D^{-1} tiles into the store's local-solve area (element offsets
-// smeta[sd].f11_fw / f11_bw / f11i_off, the last compact: BOX_COMPACT_DINV)
+// FP32 copies of the two solve-ordered copies of every part of a plan box's
+// A11 factor and of its D^{-1} tiles into the store's local-solve area
+// (element offsets fw / bw / ioff of smeta[sd].part[0][*], the last compact:
+// BOX_COMPACT_DINV)
 __global__ void k_store_local32(const BoxMeta* __restrict__ pmeta, const BoxMeta* __restrict__ smeta,
                                 const double* __restrict__ fac, float* __restrict__ loc) {
   const BoxMeta& pm = pmeta[blockIdx.y];
   const BoxMeta& sm = smeta[pm.sd];
-  const int64_t n = solve_copy_doubles(pm.nt11, pm.bt11);
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    loc[sm.f11_fw + e] = (float)fac[pm.f11_fw + e];
-    loc[sm.f11_bw + e] = (float)fac[pm.f11_bw + e];
+  for (int pi = 0; pi < (pm.nd[0] ? 3 : 1); ++pi) {
+    const BandPart& q = pm.part[0][pi];
+    const BandPart& t = sm.part[0][pi];
+    const int64_t n = solve_copy_doubles(q.NT, q.BT);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+      loc[t.fw + e] = (float)fac[q.fw + e];
+      loc[t.bw + e] = (float)fac[q.bw + e];
+    }
+    // the D^{-1} tiles the vector-FMA solve reads from the band's diagonal slot
+    // (the matrix-core layout keeps them in its forward copy), compactly
+    const int64_t nd = (int64_t)q.NT * MSG_TILE2;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nd; e += (int64_t)gridDim.x * blockDim.x)
+      loc[t.ioff + e] = (float)fac[q.off + (e >> 10) * q.BT * MSG_TILE2 + (e & 1023)];
   }
-  // the D^{-1} tiles the vector-FMA solve reads from the band's diagonal slot
-  // (the matrix-core layout keeps them in its forward copy), compactly
-  const int64_t nd = (int64_t)pm.nt11 * MSG_TILE2;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nd; e += (int64_t)gridDim.x * blockDim.x)
-    loc[sm.f11i_off + e] = (float)fac[pm.f11_off + (e >> 10) * pm.bt11 * MSG_TILE2 + (e & 1023)];
 }
 
 // u^G[global dof] += mu_j psi_j + V_j c_j (atomic over the boxes sharing a node)

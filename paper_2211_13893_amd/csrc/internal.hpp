@@ -32,6 +32,26 @@
 
 namespace msg {
 
+// One banded SPD matrix of a box in 32x32 tile-band storage.  A box matrix
+// (A11 or Ahat) is either one band over the node order (one part), or split
+// by one layer of nodes across the slowest order axis (nested dissection,
+// three parts): chain 0 = the layers before the separator, chain 1 = the
+// layers after it taken from the far end, each followed by the separator
+// rows, and the separator block S itself (dense, BT == NT).  The chains are
+// factored on their own rows (NTf tile rows; their separator rows get the
+// off-diagonal factor tiles L_sc only) and S holds the Cholesky factor of the
+// Schur complement A_ss - sum_c L_sc L_sc^T.
+struct BandPart {
+  int32_t NT, BT;       // tile rows, band tiles
+  int32_t NTf;          // tile rows factored (chain rows; NT for a whole band and for S)
+  int32_t pad;          // leading identity rows (a chain's last row ends tile row NTf - 1)
+  int32_t nc, nsep;     // rows of the order after the padding, then separator rows
+  int32_t mirror;       // the rows run over the layers from the far end (chain 1)
+  int32_t pad_;
+  int64_t off, ioff;    // band tiles, inverse diagonal tiles (doubles)
+  int64_t fw, bw;       // solve-ordered copies (forward / backward sweep)
+};
+
 // Per-box metadata, uploaded once per plan.
 struct BoxMeta {
   int32_t sd;                 // subdomain id in the decomposition
@@ -45,26 +65,26 @@ struct BoxMeta {
   int32_t sub_lo[3], sub_hi[3];  // node sub-box (box-relative, inclusive) holding B1 (and B3)
   int32_t n_nodes, n_dof;
   int32_t n_ev;
-  // factor geometry (tiles of 32): A11 on the sub-box, Ahat on the full box
+  // whole-band geometry (tiles of 32) of A11 on the sub-box and Ahat on the full box
   int32_t nt11, bt11, n11;    // tile rows, band tiles, matrix order (unpadded)
   int32_t nth, bth, nh;
-  int32_t flags;              // BOX_COMPACT_DINV: D^{-1} of the A11 factor compact at f11i_off (coarse store)
+  int32_t flags;              // BOX_COMPACT_DINV: D^{-1} tiles compact at each part's ioff (coarse store)
   int32_t ord[2];             // node order of the A11 / Ahat bands: box axis of the fastest, middle and
                               // slowest order index in bits 0-1, 2-3, 4-5 (the longest axis slowest)
+  int32_t nd[2];              // 1: the matrix is split into two chains and a separator (three parts)
+  int32_t zs[2];              // separator layer (slowest order index) of a split matrix
+  int32_t pad0_;
   int64_t node_off;           // offset into per-node arrays of the batch
   int64_t dof_off;            // offset into per-dof arrays
   int64_t vec_off;            // offset (doubles) of this box inside one block-vector array
-  int64_t f11_off, f11i_off;  // band tiles / inverse diag tiles of A11 (doubles)
-  int64_t fh_off, fhi_off;    // same for Ahat
   int64_t evec_off;           // offset (doubles) into the eigenvector output
   int64_t eval_off;           // offset into eigenvalue output
-  int64_t f11_fw, f11_bw;     // solve-ordered copies of the A11 band (forward / backward sweep)
-  int64_t fh_fw, fh_bw;       // same for Ahat
+  BandPart part[2][3];        // [kind][part]: part 0 alone for a whole band
 };
 
-// BoxMeta.flags: the D^{-1} tiles of the A11 factor are stored compactly,
-// tile I at f11i_off + I*1024, instead of on the band's diagonal (a coarse
-// store keeps only what the block solves read)
+// BoxMeta.flags: the D^{-1} tiles of the factors are stored compactly, tile
+// I of a part at its ioff + I*1024, instead of on the band's diagonal (a
+// coarse store keeps only what the block solves read)
 #define BOX_COMPACT_DINV 1
 
 // solve threads that hold a band fragment: 16 per off-diagonal tile of a set
@@ -93,8 +113,16 @@ __host__ __device__ inline int64_t solve_copy_doubles(int NT, int BT) {
 struct MatDesc {
   int32_t NT, BT;
   int32_t status_idx;   // index into the status array for pivot failures
-  int32_t pad_;
+  int32_t NTf;          // columns factored (a chain stops before its separator rows; 0 = NT)
   int64_t off, ioff;
+};
+
+// The separator Schur complement of a split matrix: the two chains' bands
+// (off0, off1, factored on NTf0, NTf1 tile rows, band BT) and S (offS, NTs x
+// NTs tiles, dense lower in band storage with BT = NTs).
+struct SepDesc {
+  int32_t NTs, BT, NTf0, NTf1;
+  int64_t off0, off1, offS;
 };
 
 struct MeshDev {

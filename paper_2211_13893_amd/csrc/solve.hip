@@ -4,6 +4,8 @@
 
 namespace msg {
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 // Block solve A x = f with A = Lu D Lu^T for KC columns [chunk*KC, +KC) of a
 // box block vector.  Reads `in` (box layout [n_dof][ldk]) on the matrix's
 // DoFs, writes `out` on the DoFs whose class bit is set in out_classes (bit c
@@ -34,9 +36,27 @@ namespace msg {
 // same order: out-of-range work items read a valid address and discard the
 // value, and stores without a target write the spare scratch row.
 //
+// A matrix split by a separator layer (BoxMeta.nd) is solved in three
+// launches over the block A = [A_00 . A_0s; . A_11 A_1s; A_s0 A_s1 A_ss]:
+//   phase 1, per chain c: y_c = Lu_cc^{-1} f_c and, continuing over the
+//            chain's separator rows, t_c = -Lu_sc y_c (the chain's band with
+//            zero tiles in its separator columns), w_c = D_c^{-1} y_c;
+//   phase 2, per box: the separator block S = Lu_ss D_s Lu_ss^T on
+//            f_s + t_0 + t_1 (forward, D^{-1}, backward) gives x_s;
+//   phase 3, per chain: x_c = Lu_cc^{-T} (w_c - Lu_sc^T x_s), the backward
+//            sweep from the chain's last row with x_s in the ring.
+// The two chains of a box are independent work units, so each box streams
+// its factor on two CUs at once, each over half of the rows.  A whole band
+// takes phases 1 and 3 as one chain (or phase 0, both sweeps in one launch,
+// when no box of the plan is split).
+//
 // The column chunks of one box share an XCD (block id mod 8) so the factor
 // they stream is read from HBM once and then hit in that XCD's L2.
-// grid.x = 8 * n_chunk * ceil(n_box/8), 512 threads; dynamic LDS = BT*32*KC doubles.
+// grid.x = 8 * n_chunk * ceil(n_unit/8) (n_unit = 2 n_box in phases 1 and 3,
+// n_box otherwise), 512 threads; dynamic LDS = BT*32*KC doubles.  Scratch:
+// w of unit (box, chain) at (2 box + chain) * n_chunk + chunk; the separator
+// exchange of (box, chunk) at sep + (box * n_chunk + chunk) * 4 sep_q: t_0,
+// t_1, w of S and x_s, sep_q doubles each ((NTs + 1) * 32 * KC).
 #define SOLVE_THREADS 512
 #define SOLVE_WAVES (SOLVE_THREADS / 64)
 // Barrier for LDS traffic only (__syncthreads would also wait for every
@@ -106,7 +126,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     const T* __restrict__ ft, const uint8_t* __restrict__ cls,
     const double* in, double* out,
     int ldk, int out_classes, int zero_rest, double* __restrict__ scratch, int64_t scratch_stride,
-    const int32_t* __restrict__ active) {
+    const int32_t* __restrict__ active, int phase, double* __restrict__ sep, int64_t sep_q) {
   static_assert(32 * KC == 256, "reduction threads = the first 256, w threads = the last 128");
   static_assert(KC == 8, "the register reduce-scatter splits 8 columns over 4 tile groups");
   static_assert(SOLVE_THREADS / 16 == SOLVE_TILES, "one tile group of 16 threads per tile of a set");
@@ -117,11 +137,15 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   const int x = blockIdx.x;
   const int xcd = x & 7, rest = x >> 3;
   const int chunk = rest % n_chunk;
-  const int box = (rest / n_chunk) * 8 + xcd;
+  const int nun = (phase == 1 || phase == 3) ? 2 : 1;
+  const int unit = (rest / n_chunk) * 8 + xcd;
+  const int box = unit / nun, chain = unit - box * nun;
   if (box >= n_box) return;
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
-  BandView v = band_view(bm, kind);
+  const bool split = bm.nd[kind] != 0;
+  if ((phase == 2 && !split) || (chain == 1 && !split)) return;
+  BandView v = band_view(bm, kind, phase == 2 ? 2 : chain);
   const uint8_t* cl = cls + bm.dof_off;
   const int tid = threadIdx.x;
   const int h = tid & 1, rq = (tid >> 1) & 7, sg = tid >> 4;  // item of the thread
@@ -135,8 +159,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   const bool wthr = tid >= SOLVE_THREADS - 128;               // forms w = D^{-1} y
   const double* vin = in + bm.dof_off * ldk;
   double* vout = out + bm.dof_off * ldk;
-  double* w = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
-  const int BT = v.BT, NT = v.NT;
+  double* sb = split ? sep + ((int64_t)box * n_chunk + chunk) * 4 * sep_q : nullptr;
+  double* w = phase == 2 ? sb + 2 * sep_q : scratch + ((int64_t)(2 * box + chain) * n_chunk + chunk) * scratch_stride;
+  const int BT = v.BT, NT = v.NT, NF = v.NTf;
+  const bool do_fwd = phase <= 2, do_bwd = phase != 1;
   const int nthr = solve_nthr(BT);
   const int nsets = NS == 1 ? 1 : solve_sets(BT);
   const int tc = nthr ? min(tid, nthr - 1) : 0;
@@ -248,6 +274,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   };
 
   // ---- forward: Lu y = f
+  if (do_fwd) {
   if (wave_tiles) frag_load<T>(slot(Ffw, 0, 0), nthr, -1, f);
   for (int I = 0; I < NT; ++I) {
     const int smax = min(BT - 1, I);
@@ -283,8 +310,16 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
       Dl[(e + 1) >> 5][(e + 1) & 31] = da.y;
       Dl[(e + 2) >> 5][(e + 2) & 31] = db.x;
       Dl[(e + 3) >> 5][(e + 3) & 31] = db.y;
-      const bool fok = (dof >= 0) & colok & dof_active(kind, cb);
-      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = (fok ? fraw : 0.0) - part_sum();
+      // a chain's separator rows (I >= NF) collect t_c = -Lu_sc y_c; S adds both
+      const bool fok = (dof >= 0) & colok & dof_active(kind, cb) & (I < NF);
+      double rhs = fok ? fraw : 0.0;
+      if (phase == 2) {
+        const int64_t o = (int64_t)(I * 32 + rr) * KC + cc;
+        rhs += sb[o] + sb[sep_q + o];
+      }
+      const double yv = rhs - part_sum();
+      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = yv;
+      if (phase == 1 && I >= NF) sb[chain * sep_q + (int64_t)((I - NF) * 32 + rr) * KC + cc] = yv;
     }
     lds_barrier();
   }
@@ -292,10 +327,19 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   lds_barrier();
   w[(int64_t)((NT - 1) * 32 + rr) * KC + cc] = Wl[t8];
   __syncthreads();
+  }
+  if (!do_bwd) return;
 
-  // ---- backward: Lu^T x = w
-  if (wave_tiles) frag_load<T>(slot(Fbw, NT - 1, 0), nthr, +1, f);
-  for (int I = NT - 1; I >= 0; --I) {
+  // ---- backward: Lu^T x = w, from the last own row (a chain: with x_s of
+  // the separator rows in the ring)
+  if (phase == 3 && split) {
+    if (red)
+      for (int i = 0; i < NT - NF; ++i)
+        ring[(int64_t)((NF + i) % BT) * 32 * KC + rr * KC + cc] = sb[3 * sep_q + (int64_t)(i * 32 + rr) * KC + cc];
+    __syncthreads();
+  }
+  if (wave_tiles) frag_load<T>(slot(Fbw, NF - 1, 0), nthr, +1, f);
+  for (int I = NF - 1; I >= 0; --I) {
     const int smax = min(BT - 1, NT - 1 - I);
     const int row = I * 32 + rr;
     const double fv = w[(int64_t)row * KC + cc];
@@ -320,13 +364,14 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     if (red) {
       xv = fv - part_sum();
       ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = xv;
+      if (phase == 2) sb[3 * sep_q + (int64_t)(I * 32 + rr) * KC + cc] = xv;
     }
     // the solution goes to `out` where it belongs, else to the spare row
     const bool wr = red & (dof >= 0) & colok & dof_active(kind, cb) & (((out_classes >> cb) & 1) != 0);
     *(wr ? vout + (int64_t)dof * ldk + col : w + (int64_t)(NT * 32 + rr) * KC + cc) = xv;
     lds_barrier();
   }
-  if (zero_rest && colok && red) {
+  if (zero_rest && colok && red && (phase == 0 || (phase == 3 && chain == 0))) {
     // zero the DoFs of this box (this chunk's columns) that were not written
     for (int d = rr; d < bm.n_dof; d += 32) {
       uint8_t k = cl[d];
@@ -339,7 +384,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
 #define SOLVE_INST(NS, T)                                                                                     \
   template __global__ void k_band_solve<8, NS, T>(const BoxMeta*, int, int, int, const T*, const uint8_t*,   \
                                                   const double*, double*, int, int, int, double*, int64_t,     \
-                                                  const int32_t*);
+                                                  const int32_t*, int, double*, int64_t);
 SOLVE_INST(1, double)
 SOLVE_INST(2, double)
 SOLVE_INST(1, float)
@@ -366,29 +411,38 @@ SOLVE_INST(2, float)
 // the current ones are used.  The ring is cleared before each sweep, so rows outside
 // the matrix read zeros.  Scratch as for k_band_solve.
 // grid.x = 8 * n_chunk * ceil(n_box/8), 512 threads; dynamic LDS = BT*32*KC doubles.
-template <int NSLOT, typename T>
+template <bool WIDE> struct McAcc;
+template <> struct McAcc<false> { double a[2][2]; };   // 4x4x4: (row half, column half)
+template <> struct McAcc<true> { dbl4 a[2]; };         // 16x16x4: row half
+template <int NSLOT, bool WIDE, typename T>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
     const BoxMeta* __restrict__ meta, int n_box, int n_chunk, int kind,
     const T* __restrict__ ft, const uint8_t* __restrict__ cls,
     const double* in, double* out,
     int ldk, int out_classes, int zero_rest, double* __restrict__ scratch, int64_t scratch_stride,
-    const int32_t* __restrict__ active) {
-  constexpr int KC = 8;
+    const int32_t* __restrict__ active, int phase, double* __restrict__ sep, int64_t sep_q) {
+  constexpr int KC = WIDE ? 16 : 8;
   static_assert(SOLVE_THREADS == 512, "8 wavefronts: tiles 1 + w + 8u");
+  static_assert(32 * KC <= SOLVE_THREADS, "one reduction thread per entry of a 32 x KC step");
   extern __shared__ double ring[];   // [BT][32][KC]
   __shared__ double part[SOLVE_WAVES][32][KC + 1];
   const int x = blockIdx.x;
   const int xcd = x & 7, rest = x >> 3;
   const int chunk = rest % n_chunk;
-  const int box = (rest / n_chunk) * 8 + xcd;
+  const int nun = (phase == 1 || phase == 3) ? 2 : 1;
+  const int unit = (rest / n_chunk) * 8 + xcd;
+  const int box = unit / nun, chain = unit - box * nun;
   if (box >= n_box) return;
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
-  BandView v = band_view(bm, kind);
+  const bool split = bm.nd[kind] != 0;
+  if ((phase == 2 && !split) || (chain == 1 && !split)) return;
+  BandView v = band_view(bm, kind, phase == 2 ? 2 : chain);
   const uint8_t* cl = cls + bm.dof_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int kk = lane >> 4, ob = (lane >> 2) & 3, jl = lane & 3;   // operand roles of the lane
+  const int kk = lane >> 4, ob = (lane >> 2) & 3, jl = lane & 3;   // operand roles of the lane (4x4x4)
   const int oi = lane >> 4;                                        // accumulator row i of the lane
+  const int li = lane & 15;                                        // 16x16x4: row / column, inner index kk
   const bool red = tid < 32 * KC;
   const int t8 = tid & (32 * KC - 1);
   const int rr = t8 / KC, cc = t8 % KC;
@@ -397,8 +451,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
   const int colc = colok ? col : ldk - 1;
   const double* vin = in + bm.dof_off * ldk;
   double* vout = out + bm.dof_off * ldk;
-  double* w = scratch + (int64_t)(box * n_chunk + chunk) * scratch_stride;
-  const int BT = v.BT, NT = v.NT;
+  double* sb = split ? sep + ((int64_t)box * n_chunk + chunk) * 4 * sep_q : nullptr;
+  double* w = phase == 2 ? sb + 2 * sep_q : scratch + ((int64_t)(2 * box + chain) * n_chunk + chunk) * scratch_stride;
+  const int BT = v.BT, NT = v.NT, NF = v.NTf;
+  const bool do_fwd = phase <= 2, do_bwd = phase != 1;
   const int S = solve4_slots(BT);
   typedef typename vec2_of<T>::type V2;
   // piece pair pp of slot `sl` of row I, this lane
@@ -418,23 +474,31 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
       a[2 * pp + 1] = (double)t.y;
     }
   };
-  // acc += the tile's 32x8 product with the ring row yp; the next row's
-  // pieces of the slot are requested as the current ones are used.  Per inner
-  // step ss the two ring values of the lane feed both row halves, so the four
-  // accumulators are updated in turn (independent MFMA chains).
-  auto tile_step = [&](double (&a)[16], const double* yp, double (&acc)[2][2], const T* base, int In, int sl) {
+  // acc += the tile's 32 x KC product with the ring row yp; the next row's
+  // pieces of the slot are requested as the current ones are used.  4x4x4:
+  // per inner step ss the two ring values of the lane feed both row halves,
+  // so the four accumulators are updated in turn (independent MFMA chains);
+  // 16x16x4: one ring value per step feeds both row halves (two chains).
+  auto tile_step = [&](double (&a)[16], const double* yp, McAcc<WIDE>& acc, const T* base, int In, int sl) {
 #pragma unroll
     for (int ss2 = 0; ss2 < 4; ++ss2) {
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int ss = 2 * ss2 + e;
-        const double b0 = yp[(4 * ss + kk) * KC + jl];
-        const double b1 = yp[(4 * ss + kk) * KC + 4 + jl];
+        if constexpr (WIDE) {
+          const double bv = yp[(4 * ss + kk) * KC + li];
 #pragma unroll
-        for (int rh = 0; rh < 2; ++rh) {
-          const double av = a[2 * (4 * rh + ss2) + e];
-          acc[rh][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b0, acc[rh][0], 0, 0, 0);
-          acc[rh][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b1, acc[rh][1], 0, 0, 0);
+          for (int rh = 0; rh < 2; ++rh)
+            acc.a[rh] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2 * (4 * rh + ss2) + e], bv, acc.a[rh], 0, 0, 0);
+        } else {
+          const double b0 = yp[(4 * ss + kk) * KC + jl];
+          const double b1 = yp[(4 * ss + kk) * KC + 4 + jl];
+#pragma unroll
+          for (int rh = 0; rh < 2; ++rh) {
+            const double av = a[2 * (4 * rh + ss2) + e];
+            acc.a[rh][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b0, acc.a[rh][0], 0, 0, 0);
+            acc.a[rh][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b1, acc.a[rh][1], 0, 0, 0);
+          }
         }
       }
 #pragma unroll
@@ -446,11 +510,26 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
       }
     }
   };
-  auto store_part = [&](const double (&acc)[2][2]) {
+  auto zero_acc = [&](McAcc<WIDE>& acc) {
+    if constexpr (WIDE) {
+      acc.a[0] = dbl4{0.0, 0.0, 0.0, 0.0};
+      acc.a[1] = dbl4{0.0, 0.0, 0.0, 0.0};
+    } else {
+      acc.a[0][0] = acc.a[0][1] = acc.a[1][0] = acc.a[1][1] = 0.0;
+    }
+  };
+  auto store_part = [&](const McAcc<WIDE>& acc) {
+    if constexpr (WIDE) {
 #pragma unroll
-    for (int rh = 0; rh < 2; ++rh)
+      for (int rh = 0; rh < 2; ++rh)
 #pragma unroll
-      for (int ch = 0; ch < 2; ++ch) part[wave][16 * rh + 4 * ob + oi][4 * ch + jl] = acc[rh][ch];
+        for (int v4 = 0; v4 < 4; ++v4) part[wave][16 * rh + kk + 4 * v4][li] = acc.a[rh][v4];
+    } else {
+#pragma unroll
+      for (int rh = 0; rh < 2; ++rh)
+#pragma unroll
+        for (int ch = 0; ch < 2; ++ch) part[wave][16 * rh + 4 * ob + oi][4 * ch + jl] = acc.a[rh][ch];
+    }
   };
   auto part_sum = [&]() {
     double a0 = 0.0, a1 = 0.0;
@@ -466,27 +545,43 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
   };
   // w_J = D^{-1}_J y_J by wavefront 7 into row `dst` of the scratch (the spare row NT when J < 0)
   auto form_w = [&](int J, int dst) {
-    double accw[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
     const double* yp = ring + (int64_t)((J < 0 ? 0 : J) % BT) * 32 * KC;
+    if constexpr (WIDE) {
+      dbl4 accw[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
-    for (int ss = 0; ss < 8; ++ss) {
-      const double b0 = yp[(4 * ss + kk) * KC + jl];
-      const double b1 = yp[(4 * ss + kk) * KC + 4 + jl];
+      for (int ss = 0; ss < 8; ++ss) {
+        const double bv = yp[(4 * ss + kk) * KC + li];
 #pragma unroll
-      for (int rh = 0; rh < 2; ++rh) {
-        const double av = Aw[2 * (4 * rh + (ss >> 1)) + (ss & 1)];
-        accw[rh][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b0, accw[rh][0], 0, 0, 0);
-        accw[rh][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b1, accw[rh][1], 0, 0, 0);
+        for (int rh = 0; rh < 2; ++rh)
+          accw[rh] = __builtin_amdgcn_mfma_f64_16x16x4f64(Aw[2 * (4 * rh + (ss >> 1)) + (ss & 1)], bv, accw[rh], 0, 0, 0);
       }
+#pragma unroll
+      for (int rh = 0; rh < 2; ++rh)
+#pragma unroll
+        for (int v4 = 0; v4 < 4; ++v4) w[(int64_t)(dst * 32 + 16 * rh + kk + 4 * v4) * KC + li] = accw[rh][v4];
+    } else {
+      double accw[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+      for (int ss = 0; ss < 8; ++ss) {
+        const double b0 = yp[(4 * ss + kk) * KC + jl];
+        const double b1 = yp[(4 * ss + kk) * KC + 4 + jl];
+#pragma unroll
+        for (int rh = 0; rh < 2; ++rh) {
+          const double av = Aw[2 * (4 * rh + (ss >> 1)) + (ss & 1)];
+          accw[rh][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b0, accw[rh][0], 0, 0, 0);
+          accw[rh][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b1, accw[rh][1], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int rh = 0; rh < 2; ++rh)
+#pragma unroll
+        for (int ch = 0; ch < 2; ++ch)
+          w[(int64_t)(dst * 32 + 16 * rh + 4 * ob + oi) * KC + 4 * ch + jl] = accw[rh][ch];
     }
-#pragma unroll
-    for (int rh = 0; rh < 2; ++rh)
-#pragma unroll
-      for (int ch = 0; ch < 2; ++ch)
-        w[(int64_t)(dst * 32 + 16 * rh + 4 * ob + oi) * KC + 4 * ch + jl] = accw[rh][ch];
   };
 
   // ---- forward: Lu y = f
+  if (do_fwd) {
   clear_ring();
 #pragma unroll
   for (int u = 0; u < NSLOT; ++u)
@@ -499,7 +594,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
     const double fraw = vin[(int64_t)dofc * ldk + colc];
     const uint8_t cb = cl[dofc];
     const int In = min(I + 1, NT - 1);
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    McAcc<WIDE> acc;
+    zero_acc(acc);
 #pragma unroll
     for (int u = 0; u < NSLOT; ++u) {
       const int s = 1 + wave + 8 * u;
@@ -515,27 +611,45 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
     }
     lds_barrier();
     if (red) {
-      const bool fok = (dof >= 0) & colok & dof_active(kind, cb);
-      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = (fok ? fraw : 0.0) - part_sum();
+      // a chain's separator rows (I >= NF) collect t_c = -Lu_sc y_c; S adds both
+      const bool fok = (dof >= 0) & colok & dof_active(kind, cb) & (I < NF);
+      double rhs = fok ? fraw : 0.0;
+      if (phase == 2) {
+        const int64_t o = (int64_t)(I * 32 + rr) * KC + cc;
+        rhs += sb[o] + sb[sep_q + o];
+      }
+      const double yv = rhs - part_sum();
+      ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = yv;
+      if (phase == 1 && I >= NF) sb[chain * sep_q + (int64_t)((I - NF) * 32 + rr) * KC + cc] = yv;
     }
     lds_barrier();
   }
   if (wforms) form_w(NT - 1, NT - 1);
   __syncthreads();
+  }
+  if (!do_bwd) return;
   clear_ring();
 
-  // ---- backward: Lu^T x = w
+  // ---- backward: Lu^T x = w, from the last own row (a chain: with x_s of
+  // the separator rows in the ring)
+  __syncthreads();
+  if (phase == 3 && split) {
+    if (red)
+      for (int i = 0; i < NT - NF; ++i)
+        ring[(int64_t)((NF + i) % BT) * 32 * KC + rr * KC + cc] = sb[3 * sep_q + (int64_t)(i * 32 + rr) * KC + cc];
+  }
 #pragma unroll
   for (int u = 0; u < NSLOT; ++u)
-    if (1 + wave + 8 * u <= BT - 1) load_slot(A[u], Fbw, NT - 1, 1 + wave + 8 * u);
+    if (1 + wave + 8 * u <= BT - 1) load_slot(A[u], Fbw, NF - 1, 1 + wave + 8 * u);
   __syncthreads();
-  for (int I = NT - 1; I >= 0; --I) {
+  for (int I = NF - 1; I >= 0; --I) {
     const int row = I * 32 + rr;
     const double fv = w[(int64_t)row * KC + cc];
     const int dof = band_to_dof(v, bm, row);
     const uint8_t cb = cl[dof >= 0 ? dof : 0];
     const int In = max(I - 1, 0);
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    McAcc<WIDE> acc;
+    zero_acc(acc);
 #pragma unroll
     for (int u = 0; u < NSLOT; ++u) {
       const int s = 1 + wave + 8 * u;
@@ -548,12 +662,13 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
     if (red) {
       xv = fv - part_sum();
       ring[(int64_t)(I % BT) * 32 * KC + rr * KC + cc] = xv;
+      if (phase == 2) sb[3 * sep_q + (int64_t)(I * 32 + rr) * KC + cc] = xv;
     }
     const bool wr = red & (dof >= 0) & colok & dof_active(kind, cb) & (((out_classes >> cb) & 1) != 0);
     *(wr ? vout + (int64_t)dof * ldk + col : w + (int64_t)(NT * 32 + rr) * KC + cc) = xv;
     lds_barrier();
   }
-  if (zero_rest && colok && red) {
+  if (zero_rest && colok && red && (phase == 0 || (phase == 3 && chain == 0))) {
     for (int d = rr; d < bm.n_dof; d += 32) {
       uint8_t k = cl[d];
       bool written = dof_active(kind, k) && ((out_classes >> k) & 1);
@@ -562,17 +677,14 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
   }
 }
 
-#define SOLVE4_INST(NSL, T)                                                                                     \
-  template __global__ void k_band_solve4<NSL, T>(const BoxMeta*, int, int, int, const T*, const uint8_t*,      \
-                                                 const double*, double*, int, int, int, double*, int64_t,       \
-                                                 const int32_t*);
-SOLVE4_INST(1, double)
-SOLVE4_INST(2, double)
-SOLVE4_INST(3, double)
-SOLVE4_INST(4, double)
-SOLVE4_INST(1, float)
-SOLVE4_INST(2, float)
-SOLVE4_INST(3, float)
-SOLVE4_INST(4, float)
+#define SOLVE4_INST(NSL, W, T)                                                                                  \
+  template __global__ void k_band_solve4<NSL, W, T>(const BoxMeta*, int, int, int, const T*, const uint8_t*,   \
+                                                    const double*, double*, int, int, int, double*, int64_t,    \
+                                                    const int32_t*, int, double*, int64_t);
+#define SOLVE4_INST_ALL(W, T) SOLVE4_INST(1, W, T) SOLVE4_INST(2, W, T) SOLVE4_INST(3, W, T) SOLVE4_INST(4, W, T)
+SOLVE4_INST_ALL(false, double)
+SOLVE4_INST_ALL(false, float)
+SOLVE4_INST_ALL(true, double)
+SOLVE4_INST_ALL(true, float)
 
 }  // namespace msg

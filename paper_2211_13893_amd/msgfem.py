@@ -66,9 +66,11 @@ class msgfem_kernel_stat(ctypes.Structure):
 
 # plan option keys (msgfem.h)
 OPT_GRAPH = 1
+OPT_SPLIT = 2
 INFO_GRAPH_LAUNCHES = 100
 INFO_GRAPH_ITERS = 101
 INFO_GRAPHS_CACHED = 102
+INFO_SPLIT_BOXES = 103
 
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -183,7 +185,7 @@ class LocalStage:
     def __init__(self, problem, batch: Optional[Sequence[int]] = None,
                  n_ev: Optional[Sequence[int]] = None, device: str = "cuda:0", shift: float = 1.0,
                  tol: float = 1e-6, maxit: int = 200, block: int = 0, seed: int = 1234,
-                 geneo: bool = False, precision: int = 0, graph: bool = False):
+                 geneo: bool = False, precision: int = 0, graph: bool = False, split: Optional[bool] = None):
         import torch
         self.torch = torch
         lib = load()
@@ -217,6 +219,9 @@ class LocalStage:
                                     int(self.batch.size), ctypes.byref(opts))
         self.plan = plan
         _check(rc, plan, "msgfem_plan_create")
+        if split is not None:
+            # the factor layout: before the sizes are read and buffers allocated
+            _check(lib.msgfem_plan_set_option(plan, OPT_SPLIT, 1 if split else 0), plan, "msgfem_plan_set_option")
         s = msgfem_sizes()
         _check(lib.msgfem_plan_sizes(plan, ctypes.byref(s)), plan, "msgfem_plan_sizes")
         self.sizes = s
