@@ -177,17 +177,32 @@ int msgfem_plan_box(const msgfem_plan *plan, int32_t b, msgfem_box_info *out);
  *     before msgfem_plan_sizes and msgfem_assemble_local (ops_bytes and
  *     work_bytes change).  A coarse store (msgfem_coarse_create) takes the
  *     plans of the default layout.
+ *   MSGFEM_OPT_SOLVE: the block-solve family (for both matrices): 0 (default)
+ *     = the widest that fits, 1 = vector FMA (bands up to 65 tiles), 2 =
+ *     matrix cores, 8 columns per workgroup (v_mfma_f64_4x4x4f64, bands up to
+ *     33 tiles), 3 = matrix cores, 16 columns per workgroup
+ *     (v_mfma_f64_16x16x4f64, bands up to 31 tiles); a family the bands do not
+ *     fit falls back to the next one down.  It fixes the layout of the factor
+ *     copies, so set it before msgfem_assemble_local.  Results agree up to
+ *     rounding.
  * msgfem_plan_set_option returns MSGFEM_EARG for an unknown key or value.
  * msgfem_plan_get_option reads an option or one of the counters of the last
  * msgfem_local_eigs call: MSGFEM_INFO_GRAPH_LAUNCHES (graph launches),
  * MSGFEM_INFO_GRAPH_ITERS (iterations they ran), MSGFEM_INFO_GRAPHS_CACHED;
- * MSGFEM_INFO_SPLIT_BOXES: sum over the batch of 1 (A11 split) + 2 (Ahat split). */
+ * MSGFEM_INFO_SPLIT_BOXES: sum over the batch of 1 (A11 split) + 2 (Ahat split);
+ * MSGFEM_INFO_SOLVE_FAMILY: the families in use, A11 + 4 Ahat (1 vector, 2
+ * matrix cores 8 columns, 3 matrix cores 16 columns); MSGFEM_INFO_MAX_BT_A11,
+ * MSGFEM_INFO_MAX_BT_AHAT: the widest band (tiles) of each matrix in the plan. */
 #define MSGFEM_OPT_GRAPH 1
 #define MSGFEM_OPT_SPLIT 2
+#define MSGFEM_OPT_SOLVE 3
 #define MSGFEM_INFO_GRAPH_LAUNCHES 100
 #define MSGFEM_INFO_GRAPH_ITERS 101
 #define MSGFEM_INFO_GRAPHS_CACHED 102
 #define MSGFEM_INFO_SPLIT_BOXES 103
+#define MSGFEM_INFO_SOLVE_FAMILY 104
+#define MSGFEM_INFO_MAX_BT_A11 105
+#define MSGFEM_INFO_MAX_BT_AHAT 106
 int msgfem_plan_set_option(msgfem_plan *plan, int32_t key, int64_t value);
 int msgfem_plan_get_option(const msgfem_plan *plan, int32_t key, int64_t *value);
 

@@ -32,10 +32,10 @@ __global__ void k_band_relayout(const BoxMeta*, int, double*);
 __global__ void k_band_relayout4(const BoxMeta*, int, double*, int);
 template <int KC, int NS, typename T>
 __global__ void k_band_solve(const BoxMeta*, int, int, int, const T*, const uint8_t*, const double*, double*, int,
-                             int, int, double*, int64_t, const int32_t*, int, double*, int64_t);
+                             int, int, double*, int64_t, const int32_t*, int, double*, int64_t, const int32_t*);
 template <int NSLOT, bool WIDE, typename T>
 __global__ void k_band_solve4(const BoxMeta*, int, int, int, const T*, const uint8_t*, const double*, double*, int,
-                              int, int, double*, int64_t, const int32_t*, int, double*, int64_t);
+                              int, int, double*, int64_t, const int32_t*, int, double*, int64_t, const int32_t*);
 __global__ void k_sep_syrk(const SepDesc*, double*);
 
 template <bool TWO, int CW, typename ST>
@@ -165,11 +165,14 @@ struct msgfem_plan {
   int64_t max_fac_tiles = 0;
   // nested dissection of the box matrices (MSGFEM_OPT_SPLIT)
   int split = 1;
+  int solve_pref = 0;            // MSGFEM_OPT_SOLVE
   bool any_split[2] = {false, false};
   int max_nts = 0;               // separator tile rows
   int n_chain_mats = 0;          // mats[0 .. n_chain_mats): whole bands and chains; then the separator blocks
   std::vector<SepDesc> seps;
   int64_t o_seps = 0, w_sep = 0, sep_q = 0;
+  std::vector<int32_t> order;    // [kind][nb]: batch boxes by decreasing block-solve sweep length
+  int64_t o_order = 0;
   int n_gchunk = 0;
   // work layout (bytes)
   int64_t w_vec = 0, w_part = 0, w_G = 0, w_L = 0, w_Y = 0, w_Yp = 0, w_nu = 0, w_rho = 0,
@@ -441,12 +444,28 @@ static int plan_layout(msgfem_plan* p, int nsd, int n_mat) {
       p->seps.push_back(SepDesc{q->NT, c0->BT, c0->NTf, c1->NTf, c0->off, c1->off, q->off});
     }
   p->fac_total = fac_off;
+  // block-solve dispatch order: longest sweep (tile rows x band tiles of the
+  // longest part) first
+  p->order.assign((size_t)2 * nb, 0);
+  for (int kind = 0; kind < 2; ++kind) {
+    std::vector<std::pair<int64_t, int>> w(nb);
+    for (int b = 0; b < nb; ++b) {
+      const BoxMeta& m = p->meta[b];
+      int64_t c = 0;
+      for (int pi = 0; pi < (m.nd[kind] ? 2 : 1); ++pi)
+        c = std::max(c, (int64_t)m.part[kind][pi].NT * m.part[kind][pi].BT);
+      w[b] = {-c, b};
+    }
+    std::stable_sort(w.begin(), w.end());
+    for (int b = 0; b < nb; ++b) p->order[(size_t)kind * nb + b] = w[b].second;
+  }
   const msgfem_eig_opts& o = p->opts;
   // ops layout
   int64_t off = 0;
   p->o_meta = off; off = align256(off + (int64_t)nb * sizeof(BoxMeta));
   p->o_mats = off; off = align256(off + (int64_t)p->mats.size() * sizeof(MatDesc));
   p->o_seps = off; off = align256(off + (int64_t)std::max<size_t>(p->seps.size(), 1) * sizeof(SepDesc));
+  p->o_order = off; off = align256(off + (int64_t)2 * nb * 4);
   p->o_omega = off; off = align256(off + (int64_t)nsd * 6 * 4);
   p->o_ctab = off; off = align256(off + (int64_t)n_mat * 36 * 8);
   p->o_wtot = off; off = align256(off + p->n_nodes_global * 4);
@@ -678,6 +697,7 @@ struct OpsView {
   const BoxMeta* meta;
   MatDesc* mats;
   SepDesc* seps;
+  int32_t* order;
   int32_t* omega;
   double* ctab;
   int32_t* wtot;
@@ -695,6 +715,7 @@ static OpsView ops_view(const msgfem_plan* p, const void* ops) {
   v.meta = (const BoxMeta*)(b + p->o_meta);
   v.mats = (MatDesc*)(b + p->o_mats);
   v.seps = (SepDesc*)(b + p->o_seps);
+  v.order = (int32_t*)(b + p->o_order);
   v.omega = (int32_t*)(b + p->o_omega);
   v.ctab = (double*)(b + p->o_ctab);
   v.wtot = (int32_t*)(b + p->o_wtot);
@@ -710,13 +731,15 @@ static OpsView ops_view(const msgfem_plan* p, const void* ops) {
 static void lds_attributes();
 
 // the matrix-core block solve serves a matrix kind whose bands all fit its slots
+// block-solve family of a matrix kind (MSGFEM_OPT_SOLVE: 0 widest that fits,
+// 1 vector FMA, 2 matrix cores with 8 columns, 3 matrix cores with 16 columns)
 static bool solve4_kind(const msgfem_plan* p, int kind) {
-  return p->max_bt_kind[kind] - 1 <= 8 * SOLVE4_MAX_SLOTS;
+  return p->solve_pref != 1 && p->max_bt_kind[kind] - 1 <= 8 * SOLVE4_MAX_SLOTS;
 }
 
 // the wide (16-column) matrix-core solve for this matrix kind
 static bool wide_kind(const msgfem_plan* p, int kind) {
-  return solve4_kind(p, kind) && p->max_bt_kind[kind] <= WIDE_MAX_BT;
+  return solve4_kind(p, kind) && p->solve_pref != 2 && p->max_bt_kind[kind] <= WIDE_MAX_BT;
 }
 
 static int set_device(msgfem_plan* p) {
@@ -779,6 +802,7 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
                            hipMemcpyHostToDevice, s));
   if (!p->seps.empty())
     HIPCHK(p, hipMemcpyAsync(v.seps, p->seps.data(), p->seps.size() * sizeof(SepDesc), hipMemcpyHostToDevice, s));
+  HIPCHK(p, hipMemcpyAsync(v.order, p->order.data(), p->order.size() * 4, hipMemcpyHostToDevice, s));
   // the host copies must stay alive until the copies complete
   HIPCHK(p, hipStreamSynchronize(s));
   k_fill_i32<<<(nb + 255) / 256, 256, 0, s>>>(status, nb, 0);
@@ -1056,7 +1080,8 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
       const int nun = (ph == 1 || ph == 3) ? 2 * c.nb : c.nb;
       dim3 grid(8 * nchunk * ((nun + 7) / 8));
       kern<<<grid, 512, lds, c.s>>>(c.v.meta, c.nb, nchunk, kind, ft, c.v.cls, in, out, kk, out_classes, zero_rest,
-                                    c.w.scr, scr_stride, active, ph, c.w.sep, sep_q);
+                                    c.w.scr, scr_stride, active, ph, c.w.sep, sep_q,
+                                    c.v.order + (size_t)kind * c.nb);
     }
   };
   if (solve4_kind(c.p, kind)) {
@@ -1673,6 +1698,13 @@ extern "C" int msgfem_plan_set_option(msgfem_plan* p, int32_t key, int64_t value
       p->graphs.clear();
       return plan_layout(p, p->nsd, p->mesh.n_mat);
     }
+    case MSGFEM_OPT_SOLVE:
+      if (value < 0 || value > 3) return fail(p, MSGFEM_EARG, "MSGFEM_OPT_SOLVE takes 0 .. 3, not %lld",
+                                             (long long)value);
+      p->solve_pref = (int)value;
+      for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+      p->graphs.clear();
+      return MSGFEM_OK;
     default:
       return fail(p, MSGFEM_EARG, "unknown plan option %d", key);
   }
@@ -1683,6 +1715,12 @@ extern "C" int msgfem_plan_get_option(const msgfem_plan* p, int32_t key, int64_t
   switch (key) {
     case MSGFEM_OPT_GRAPH: *value = p->graph_mode; return MSGFEM_OK;
     case MSGFEM_OPT_SPLIT: *value = p->split; return MSGFEM_OK;
+    case MSGFEM_OPT_SOLVE: *value = p->solve_pref; return MSGFEM_OK;
+    case MSGFEM_INFO_MAX_BT_A11: *value = p->max_bt_kind[0]; return MSGFEM_OK;
+    case MSGFEM_INFO_MAX_BT_AHAT: *value = p->max_bt_kind[1]; return MSGFEM_OK;
+    case MSGFEM_INFO_SOLVE_FAMILY:
+      *value = (solve4_kind(p, 0) ? (wide_kind(p, 0) ? 3 : 2) : 1) + 4 * (solve4_kind(p, 1) ? (wide_kind(p, 1) ? 3 : 2) : 1);
+      return MSGFEM_OK;
     case MSGFEM_INFO_SPLIT_BOXES: {
       int64_t n = 0;
       for (auto& m : p->meta) n += m.nd[0] + 2 * m.nd[1];
@@ -2622,7 +2660,7 @@ static int solve_f32(hipStream_t s, const BoxMeta* meta, int nb, int max_bt, boo
       const int nun = (ph == 1 || ph == 3) ? 2 * nb : nb;
       dim3 grid(8 * nchunk * ((nun + 7) / 8));
       kern<<<grid, 512, lds, s>>>(meta, nb, nchunk, kind, ft, cls, in, out, kk, out_classes, zero_rest, scr,
-                                  scr_stride, nullptr, ph, sep, sep_q);
+                                  scr_stride, nullptr, ph, sep, sep_q, nullptr);
     }
   };
   if (use4 && wide) {

@@ -51,7 +51,10 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // when no box of the plan is split).
 //
 // The column chunks of one box share an XCD (block id mod 8) so the factor
-// they stream is read from HBM once and then hit in that XCD's L2.
+// they stream is read from HBM once and then hit in that XCD's L2.  With an
+// order array (box indices by decreasing sweep length) the longest sweeps are
+// dispatched first, so on a batch of unequal boxes that needs more than one
+// wave of workgroups the largest boxes do not start last.
 // grid.x = 8 * n_chunk * ceil(n_unit/8) (n_unit = 2 n_box in phases 1 and 3,
 // n_box otherwise), 512 threads; dynamic LDS = BT*32*KC doubles.  Scratch:
 // w of unit (box, chain) at (2 box + chain) * n_chunk + chunk; the separator
@@ -126,7 +129,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
     const T* __restrict__ ft, const uint8_t* __restrict__ cls,
     const double* in, double* out,
     int ldk, int out_classes, int zero_rest, double* __restrict__ scratch, int64_t scratch_stride,
-    const int32_t* __restrict__ active, int phase, double* __restrict__ sep, int64_t sep_q) {
+    const int32_t* __restrict__ active, int phase, double* __restrict__ sep, int64_t sep_q,
+    const int32_t* __restrict__ order) {
   static_assert(32 * KC == 256, "reduction threads = the first 256, w threads = the last 128");
   static_assert(KC == 8, "the register reduce-scatter splits 8 columns over 4 tile groups");
   static_assert(SOLVE_THREADS / 16 == SOLVE_TILES, "one tile group of 16 threads per tile of a set");
@@ -139,8 +143,9 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
   const int chunk = rest % n_chunk;
   const int nun = (phase == 1 || phase == 3) ? 2 : 1;
   const int unit = (rest / n_chunk) * 8 + xcd;
-  const int box = unit / nun, chain = unit - box * nun;
-  if (box >= n_box) return;
+  const int bslot = unit / nun, chain = unit - bslot * nun;
+  if (bslot >= n_box) return;
+  const int box = order ? order[bslot] : bslot;   // boxes with the longest sweeps first
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
   const bool split = bm.nd[kind] != 0;
@@ -384,7 +389,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(
 #define SOLVE_INST(NS, T)                                                                                     \
   template __global__ void k_band_solve<8, NS, T>(const BoxMeta*, int, int, int, const T*, const uint8_t*,   \
                                                   const double*, double*, int, int, int, double*, int64_t,     \
-                                                  const int32_t*, int, double*, int64_t);
+                                                  const int32_t*, int, double*, int64_t, const int32_t*);
 SOLVE_INST(1, double)
 SOLVE_INST(2, double)
 SOLVE_INST(1, float)
@@ -420,7 +425,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
     const T* __restrict__ ft, const uint8_t* __restrict__ cls,
     const double* in, double* out,
     int ldk, int out_classes, int zero_rest, double* __restrict__ scratch, int64_t scratch_stride,
-    const int32_t* __restrict__ active, int phase, double* __restrict__ sep, int64_t sep_q) {
+    const int32_t* __restrict__ active, int phase, double* __restrict__ sep, int64_t sep_q,
+    const int32_t* __restrict__ order) {
   constexpr int KC = WIDE ? 16 : 8;
   static_assert(SOLVE_THREADS == 512, "8 wavefronts: tiles 1 + w + 8u");
   static_assert(32 * KC <= SOLVE_THREADS, "one reduction thread per entry of a 32 x KC step");
@@ -431,8 +437,9 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
   const int chunk = rest % n_chunk;
   const int nun = (phase == 1 || phase == 3) ? 2 : 1;
   const int unit = (rest / n_chunk) * 8 + xcd;
-  const int box = unit / nun, chain = unit - box * nun;
-  if (box >= n_box) return;
+  const int bslot = unit / nun, chain = unit - bslot * nun;
+  if (bslot >= n_box) return;
+  const int box = order ? order[bslot] : bslot;   // boxes with the longest sweeps first
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
   const bool split = bm.nd[kind] != 0;
@@ -680,7 +687,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
 #define SOLVE4_INST(NSL, W, T)                                                                                  \
   template __global__ void k_band_solve4<NSL, W, T>(const BoxMeta*, int, int, int, const T*, const uint8_t*,   \
                                                     const double*, double*, int, int, int, double*, int64_t,    \
-                                                    const int32_t*, int, double*, int64_t);
+                                                    const int32_t*, int, double*, int64_t, const int32_t*);
 #define SOLVE4_INST_ALL(W, T) SOLVE4_INST(1, W, T) SOLVE4_INST(2, W, T) SOLVE4_INST(3, W, T) SOLVE4_INST(4, W, T)
 SOLVE4_INST_ALL(false, double)
 SOLVE4_INST_ALL(false, float)

@@ -67,10 +67,14 @@ class msgfem_kernel_stat(ctypes.Structure):
 # plan option keys (msgfem.h)
 OPT_GRAPH = 1
 OPT_SPLIT = 2
+OPT_SOLVE = 3
 INFO_GRAPH_LAUNCHES = 100
 INFO_GRAPH_ITERS = 101
 INFO_GRAPHS_CACHED = 102
 INFO_SPLIT_BOXES = 103
+INFO_SOLVE_FAMILY = 104
+INFO_MAX_BT_A11 = 105
+INFO_MAX_BT_AHAT = 106
 
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -185,7 +189,8 @@ class LocalStage:
     def __init__(self, problem, batch: Optional[Sequence[int]] = None,
                  n_ev: Optional[Sequence[int]] = None, device: str = "cuda:0", shift: float = 1.0,
                  tol: float = 1e-6, maxit: int = 200, block: int = 0, seed: int = 1234,
-                 geneo: bool = False, precision: int = 0, graph: bool = False, split: Optional[bool] = None):
+                 geneo: bool = False, precision: int = 0, graph: Optional[bool] = None,
+                 split: Optional[bool] = None, solve: Optional[int] = None, tuned: bool = False):
         import torch
         self.torch = torch
         lib = load()
@@ -219,9 +224,25 @@ class LocalStage:
                                     int(self.batch.size), ctypes.byref(opts))
         self.plan = plan
         _check(rc, plan, "msgfem_plan_create")
-        if split is not None:
-            # the factor layout: before the sizes are read and buffers allocated
-            _check(lib.msgfem_plan_set_option(plan, OPT_SPLIT, 1 if split else 0), plan, "msgfem_plan_set_option")
+        # plan options: the measured table for the plan's size class (tuned),
+        # then explicit arguments; the factor layout (split, solve family) is
+        # fixed before the sizes are read and buffers allocated
+        opts_set = {}
+        if tuned:
+            from . import tuning
+            s0 = msgfem_sizes()
+            _check(lib.msgfem_plan_sizes(plan, ctypes.byref(s0)), plan, "msgfem_plan_sizes")
+            bt = ctypes.c_int64()
+            _check(lib.msgfem_plan_get_option(plan, INFO_MAX_BT_AHAT, ctypes.byref(bt)), plan, "msgfem_plan_get_option")
+            self.size_class = tuning.size_class(int(bt.value), int(s0.n_box), int(s0.block))
+            opts_set.update(tuning.options_for(self.size_class) or {})
+        for key, val in (("split", split), ("solve", solve), ("graph", graph)):
+            if val is not None:
+                opts_set[key] = int(val)
+        self.plan_options = dict(opts_set)
+        for key, code in (("split", OPT_SPLIT), ("solve", OPT_SOLVE), ("graph", OPT_GRAPH)):
+            if key in opts_set:
+                _check(lib.msgfem_plan_set_option(plan, code, int(opts_set[key])), plan, "msgfem_plan_set_option")
         s = msgfem_sizes()
         _check(lib.msgfem_plan_sizes(plan, ctypes.byref(s)), plan, "msgfem_plan_sizes")
         self.sizes = s
@@ -233,8 +254,6 @@ class LocalStage:
             self.boxes.append(bi)
         self.ops = None
         self.work = None
-        if graph:
-            self.set_option(OPT_GRAPH, 1)
 
     def set_option(self, key: int, value: int):
         """msgfem_plan_set_option"""
