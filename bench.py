@@ -60,6 +60,91 @@ def cpu_baseline(prob, n_sample: int):
                       f"assembly + Schur reduction + scipy eigh, {dt:.1f} s"}
 
 
+def roofline(stats, profile_name):
+    """Roofline of the dominant kernel of a profiled run: algorithmic bytes
+    (or flops) per launch over the average launch duration (HIP events on the
+    launch stream); a block solve's launch is one solve operation (its three
+    phase kernels when the matrices are split).  traffic: FETCH_SIZE +
+    WRITE_SIZE per launch from the committed profile, while its sources are
+    unchanged."""
+    from paper_2211_13893_amd import profiling
+    dom = max(stats, key=lambda n: stats[n]["ms"])
+    d = stats[dom]
+    avg_s = d["ms"] / d["launches"] / 1e3
+    per_launch_bytes = d["bytes"] / d["launches"]
+    per_launch_flops = d["flops"] / d["launches"]
+    ai = per_launch_flops / per_launch_bytes if per_launch_bytes else float("inf")
+    if ai > PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
+        achieved = per_launch_flops / avg_s / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
+    else:
+        achieved = per_launch_bytes / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    roof.update(kernel=dom, avg_launch_ms=avg_s * 1e3, algorithmic_bytes_per_launch=per_launch_bytes,
+                algorithmic_flops_per_launch=per_launch_flops,
+                fp64_tflops=per_launch_flops / avg_s / 1e12)
+    lib_kernel = {"band_solve": "k_band_solve", "spmm": "k_spmm"}.get(dom)
+    if lib_kernel and profile_name:
+        t = profiling.recorded_traffic(os.path.join(ROOT, "profiles", profile_name), lib_kernel)
+        roof["traffic"] = t
+        if t:
+            roof["traffic_vs_algorithmic"] = t / per_launch_bytes
+    return roof
+
+
+def kernel_table(stats, steps):
+    tot_ms = sum(v["ms"] for v in stats.values()) or 1.0
+    out = {}
+    for n, v in stats.items():
+        sec = v["ms"] / 1e3
+        out[n] = {"launches": v["launches"], "ms_per_step": v["ms"] / steps, "share": v["ms"] / tot_ms,
+                  "GB/s": (v["bytes"] / sec / 1e9) if sec > 0 else None,
+                  "TFLOP/s": (v["flops"] / sec / 1e12) if sec > 0 else None}
+    return out
+
+
+def c3_leg(run, args):
+    """The uneven batch (168 boxes of 4.6k-25k DoF, one plan) with the plan
+    options of its size class: FP64, and the mixed path (FP32 copy of the
+    preconditioner's factor; SpMM, interior solves, Gram, FP64 Rayleigh-Ritz
+    and residuals in FP64) with LOBPCG iterations replayed from HIP graphs
+    against the eager loop (both without per-kernel events), and a profiled
+    run of the mixed path for its roofline."""
+    import numpy as np
+    from paper_2211_13893_amd import synth
+    up = synth.uneven_laminate()
+    steps = max(5, args.steps)
+    fp = run(0, problem=up, steps=steps, warmup=1)
+    mixed = run(1, problem=up, steps=steps, warmup=1)
+    graph = run(1, problem=up, steps=steps, warmup=1, profile=False, graph=True)
+    eager = run(1, problem=up, steps=steps, warmup=1, profile=False, graph=False)
+    dofs = [b.n_dof for b in fp["stage"].boxes]
+    dnu = np.abs(1.0 / (mixed["nu"] + 1.0) - 1.0 / (fp["nu"] + 1.0)) * (fp["nu"] + 1.0)
+    out = {"workload": "uneven_laminate",
+           "description": "all 168 oversampled boxes of a wrinkled 256x32x24-element laminate (24 plies of "
+                          "random angle) cut at random tensor positions (6-16 elements), overlap 1, "
+                          "oversampling 1-3, n_ev 8-32, rho <= 1e-6, one plan",
+           "box_dof": [int(min(dofs)), int(max(dofs))], "block": int(fp["stage"].k), "steps": steps, "warmup": 1,
+           "size_class": fp["size_class"], "plan_options": fp["plan_options"],
+           "fp64": {"value": fp["value"], "unit": "GEVP/s", "ms_per_step": fp["ms_step"],
+                    "converged": f"{fp['conv']}/{len(dofs)}", "lobpcg_iters_mean": float(fp["iters"].mean()),
+                    "roofline": roofline(fp["stats"], None), "kernels": kernel_table(fp["stats"], steps)},
+           "mixed_fp32_preconditioner": {
+               "value": mixed["value"], "unit": "GEVP/s", "ms_per_step": mixed["ms_step"],
+               "converged": f"{mixed['conv']}/{len(dofs)}", "lobpcg_iters_mean": float(mixed["iters"].mean()),
+               "max_nu_rel_diff_vs_fp64_path": float(dnu.max()),
+               "roofline": roofline(mixed["stats"], None), "kernels": kernel_table(mixed["stats"], steps)},
+           "graph_vs_eager": {"graph": {"value": graph["value"], "ms_per_step": graph["ms_step"],
+                                        "graph_launches_last_step": graph["graph_launches"]},
+                              "eager": {"value": eager["value"], "ms_per_step": eager["ms_step"]},
+                              "ratio": graph["value"] / eager["value"] if eager["value"] > 0 else None,
+                              "path": "mixed (FP32 preconditioner factor), no per-kernel events"}}
+    del fp, mixed, graph, eager
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,10 +170,14 @@ def main():
 
     prob = synth.uniform_batch(n_boxes=args.boxes)
 
-    def run(precision: int, net=None, G=None, problem=None, steps=None, warmup=None):
-        """Time `steps` full local stages (assembly + factorisation + LOBPCG;
-        with a warm-start network also its features, inference and start block)."""
-        stage = msgfem.LocalStage(problem or prob, tol=1e-6, precision=precision, block=args.block)
+    def run(precision: int, net=None, G=None, problem=None, steps=None, warmup=None, profile=True, **stage_kw):
+        """Time `steps` full local stages (assembly + factorisation + LOBPCG; with
+        a warm-start network also its features, inference and start block).
+        With profile, HIP events bracket every kernel launch in the timed
+        region (the per-kernel times and the roofline come from them; the
+        LOBPCG iterations are then launched eagerly, not from graphs)."""
+        stage_kw.setdefault("tuned", True)
+        stage = msgfem.LocalStage(problem or prob, tol=1e-6, precision=precision, block=args.block, **stage_kw)
         steps = args.steps if steps is None else steps
         warmup = args.warmup if warmup is None else warmup
 
@@ -100,15 +189,18 @@ def main():
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
-        stage.msgfem_profile(True)
+        if profile:
+            stage.msgfem_profile(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             out = step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        stage.msgfem_profile(False)
-        stats = stage.msgfem_profile_stats()
+        stats = {}
+        if profile:
+            stage.msgfem_profile(False)
+            stats = stage.msgfem_profile_stats()
         ms_step = (t1 - t0) / steps * 1e3
         status = out["status"].cpu().numpy()
         iters = out["iters"].cpu().numpy()
@@ -117,7 +209,10 @@ def main():
             r = stage.resid(out, b).cpu().numpy()
             conv += int(np.all(r <= 1e-6) and status[b] == 0)
         res = {"stage": stage, "stats": stats, "ms_step": ms_step, "conv": conv, "iters": iters,
-               "value": conv / (ms_step / 1e3), "nu": out["evals"].cpu().numpy()}
+               "value": conv / (ms_step / 1e3), "nu": out["evals"].cpu().numpy(),
+               "graph_launches": stage.get_option(msgfem.INFO_GRAPH_LAUNCHES),
+               "plan_options": dict(getattr(stage, "plan_options", {})),
+               "size_class": getattr(stage, "size_class", None)}
         return res
 
     fp = run(0)
@@ -144,18 +239,7 @@ def main():
             del mx
     uneven = None
     if not args.no_uneven:
-        up = synth.uneven_laminate()
-        ur = run(0, problem=up, steps=1, warmup=1)
-        dofs = [b.n_dof for b in ur["stage"].boxes]
-        uneven = {"workload": "uneven_laminate",
-                  "description": "all 168 oversampled boxes of a wrinkled 256x32x24-element laminate "
-                                 "(24 plies of random angle) cut at random tensor positions (6-16 "
-                                 "elements), overlap 1, oversampling 1-3, n_ev 8-32, rho <= 1e-6, FP64 path",
-                  "value": ur["value"], "unit": "GEVP/s", "ms_per_step": ur["ms_step"], "steps": 1, "warmup": 1,
-                  "converged": f"{ur['conv']}/{len(dofs)}", "box_dof": [int(min(dofs)), int(max(dofs))],
-                  "block": int(ur["stage"].k), "lobpcg_iters_mean": float(ur["iters"].mean()),
-                  "kernels_ms_per_step": {n: v["ms"] for n, v in ur["stats"].items()}}
-        del ur
+        uneven = c3_leg(run, args)
     warm_res = None
     if not args.no_warm:
         from paper_2211_13893_amd import warm
@@ -179,36 +263,8 @@ def main():
 
     # dominant kernel and its roofline
     tot_ms = sum(v["ms"] for v in stats.values()) or 1.0
-    dom = max(stats, key=lambda n: stats[n]["ms"])
-    d = stats[dom]
-    avg_s = d["ms"] / d["launches"] / 1e3
-    per_launch_bytes = d["bytes"] / d["launches"]
-    per_launch_flops = d["flops"] / d["launches"]
-    ai = per_launch_flops / per_launch_bytes if per_launch_bytes else float("inf")
-    if ai > PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
-        achieved = per_launch_flops / avg_s / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom,
-                "avg_launch_ms": avg_s * 1e3}
-    else:
-        achieved = per_launch_bytes / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
-                "avg_launch_ms": avg_s * 1e3}
-    from paper_2211_13893_amd import profiling
-    lib_kernel = {"band_solve": "k_band_solve", "spmm": "k_spmm"}.get(dom)
-    if lib_kernel:
-        t = profiling.recorded_traffic(os.path.join(ROOT, "profiles", PROFILE), lib_kernel)
-        roof["traffic"] = t
-        if t:
-            roof["traffic_vs_algorithmic"] = t / per_launch_bytes
-    kernels = {}
-    for n, v in stats.items():
-        sec = v["ms"] / 1e3
-        kernels[n] = {"launches": v["launches"], "ms_per_step": v["ms"] / args.steps,
-                      "share": v["ms"] / tot_ms,
-                      "GB/s": (v["bytes"] / sec / 1e9) if sec > 0 else None,
-                      "TFLOP/s": (v["flops"] / sec / 1e12) if sec > 0 else None}
+    roof = roofline(stats, PROFILE)
+    kernels = kernel_table(stats, args.steps)
     spmm = stats.get("spmm")
     line = {
         "metric": METRIC,
@@ -228,7 +284,9 @@ def main():
                                   "(10125 DoF), 0.25 mm plies / 0.05 mm resin, core 8^3, overlap 1, "
                                   f"oversampling 2, n_ev 16, LOBPCG block {int(stage.k)}, rho <= 1e-6, FP64 path",
                    "boxes": args.boxes, "n_ev": 16, "block": int(stage.k), "tol": 1e-6,
-                   "path": "fp64", "parallelism": "subdomain batch on one GPU"},
+                   "path": "fp64", "parallelism": "subdomain batch on one GPU",
+                   "size_class": fp["size_class"], "plan_options": fp["plan_options"],
+                   "lobpcg_launch": "eager (per-kernel HIP events in the timed region)"},
         "converged": f"{conv}/{len(stage.batch)}",
         "lobpcg_iters_mean": float(iters.mean()),
         "spmm_hbm_GBs": (spmm["bytes"] / (spmm["ms"] / 1e3) / 1e9) if spmm else None,

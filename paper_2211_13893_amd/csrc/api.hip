@@ -1167,7 +1167,17 @@ static int gram(Ctx& c, int nblk, double* const* Zb, double* const* AZb, double*
   const int k = c.k, m = nblk * k;
   if (gram_only(c, nblk, Zb, AZb, BZb, act)) return MSGFEM_EHIP;
   size_t lds_rr = ((size_t)2 * m * (m + 1) + 4 * m + 256) * 8 + ((size_t)5 * m + 1) * 4;
-  ProfScope ps2(c.p, PK_RR, c.s, 0.0, 0.0);
+  // per box: the two m x m Gram matrices in, the k-column coefficient blocks
+  // of X and P and k Ritz values out; flops a nominal 50 m^3 (the Cholesky
+  // reduction C = L^{-1} G_M L^{-T}, about 4 m^3, and some six two-sided
+  // Jacobi sweeps of about 7 m^3 each)
+  double by_rr = 0.0, fl_rr = 0.0;
+  for (int b = 0; b < c.nb; ++b) {
+    if (!c.counts(b, act)) continue;
+    by_rr += 8.0 * (2.0 * m * m + 2.0 * m * k + k);
+    fl_rr += 50.0 * m * (double)m * m;
+  }
+  ProfScope ps2(c.p, PK_RR, c.s, by_rr, fl_rr);
   k_rayleigh_ritz<<<c.nb, 1024, lds_rr, c.s>>>(m, k, 1, c.p->opts.shift, c.w.G, c.w.L, c.w.Y, c.w.Yp,
                                                c.w.nu, act);
   LAUNCHCHK(c.p);

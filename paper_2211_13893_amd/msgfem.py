@@ -235,7 +235,11 @@ class LocalStage:
             bt = ctypes.c_int64()
             _check(lib.msgfem_plan_get_option(plan, INFO_MAX_BT_AHAT, ctypes.byref(bt)), plan, "msgfem_plan_get_option")
             self.size_class = tuning.size_class(int(bt.value), int(s0.n_box), int(s0.block))
-            opts_set.update(tuning.options_for(self.size_class) or {})
+            table = tuning.options_for(self.size_class) or {}
+            if geneo:
+                # a GenEO coarse store fixes the interior band layout (default split and family)
+                table = {key: v for key, v in table.items() if key == "graph"}
+            opts_set.update(table)
         for key, val in (("split", split), ("solve", solve), ("graph", graph)):
             if val is not None:
                 opts_set[key] = int(val)

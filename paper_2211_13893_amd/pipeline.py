@@ -91,7 +91,8 @@ def local_stage_streamed(problem, store: "msgfem.CoarseStore", chunks: List[List
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for ci, chunk in enumerate(chunks):
-        st = msgfem.LocalStage(problem, batch=chunk, tol=tol, geneo=geneo, precision=precision, device=device)
+        st = msgfem.LocalStage(problem, batch=chunk, tol=tol, geneo=geneo, precision=precision, device=device,
+                               tuned=True)
         st.msgfem_assemble_local()
         out = st.msgfem_local_eigs()
         store.add(st, out)
