@@ -114,19 +114,32 @@ def c3_leg(run, args):
     run of the mixed path for its roofline."""
     import numpy as np
     from paper_2211_13893_amd import synth
+    import gc
+    import torch
     up = synth.uneven_laminate()
     steps = max(5, args.steps)
-    fp = run(0, problem=up, steps=steps, warmup=1)
-    mixed = run(1, problem=up, steps=steps, warmup=1)
-    graph = run(1, problem=up, steps=steps, warmup=1, profile=False, graph=True)
-    eager = run(1, problem=up, steps=steps, warmup=1, profile=False, graph=False)
-    dofs = [b.n_dof for b in fp["stage"].boxes]
+
+    def one(*a, **kw):
+        # each plan of this batch holds about 100 GB: release it before the next
+        r = run(*a, **kw)
+        r["dofs"] = [b.n_dof for b in r["stage"].boxes]
+        r["k"] = int(r["stage"].k)
+        del r["stage"]
+        gc.collect()
+        torch.cuda.empty_cache()
+        return r
+
+    fp = one(0, problem=up, steps=steps, warmup=1)
+    mixed = one(1, problem=up, steps=steps, warmup=1)
+    graph = one(1, problem=up, steps=steps, warmup=1, profile=False, graph=True)
+    eager = one(1, problem=up, steps=steps, warmup=1, profile=False, graph=False)
+    dofs = fp["dofs"]
     dnu = np.abs(1.0 / (mixed["nu"] + 1.0) - 1.0 / (fp["nu"] + 1.0)) * (fp["nu"] + 1.0)
     out = {"workload": "uneven_laminate",
            "description": "all 168 oversampled boxes of a wrinkled 256x32x24-element laminate (24 plies of "
                           "random angle) cut at random tensor positions (6-16 elements), overlap 1, "
                           "oversampling 1-3, n_ev 8-32, rho <= 1e-6, one plan",
-           "box_dof": [int(min(dofs)), int(max(dofs))], "block": int(fp["stage"].k), "steps": steps, "warmup": 1,
+           "box_dof": [int(min(dofs)), int(max(dofs))], "block": fp["k"], "steps": steps, "warmup": 1,
            "size_class": fp["size_class"], "plan_options": fp["plan_options"],
            "fp64": {"value": fp["value"], "unit": "GEVP/s", "ms_per_step": fp["ms_step"],
                     "converged": f"{fp['conv']}/{len(dofs)}", "lobpcg_iters_mean": float(fp["iters"].mean()),

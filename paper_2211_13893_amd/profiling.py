@@ -1,15 +1,21 @@
 """Kernel-time and HBM-traffic summaries of the local stage from rocprofv3 output.
 
-    python -m paper_2211_13893_amd.profiling run [--boxes 64] [--steps 1]
+    python -m paper_2211_13893_amd.profiling run [--boxes 64] [--steps 1] [--workload uniform|uneven]
+                                                 [--precision 0|1]
         the profiled workload: one 256 MiB device-to-device copy (the
-        calibration of the traffic counters), then `steps` FP64 local stages
-        (assembly + factorisation + LOBPCG) of the uniform batch;
+        calibration of the traffic counters), then `steps` local stages
+        (assembly + factorisation + LOBPCG) of the uniform batch or the
+        uneven batch, with the plan options of their size class (as bench.py);
     python -m paper_2211_13893_amd.profiling summarize --trace D --fetch D --write D --out F.md
         a markdown summary of the kernel statistics of a `--kernel-trace
         --stats` run (directory D) and, per kernel, the HBM bytes per launch
         from a `--pmc FETCH_SIZE` and a `--pmc WRITE_SIZE` run of the same
         workload.  Each counter is scaled by the factor that makes it read
         256 MiB for the calibration copy (read 256 MiB, written 256 MiB).
+        --solve-phases P: the block solve of a split plan is P dispatches
+        (chains forward, separators, chains backward) per solve operation;
+        its time and traffic are also given per operation, the unit of the
+        roofline in bench.py.
 
 The summary records a SHA-256 of the kernel sources; bench.py reports the
 measured traffic only while those sources are unchanged.
@@ -92,7 +98,7 @@ def traffic_per_launch(fetch_dir: str, write_dir: str):
     return {n: (a[0], a[1] / a[0], a[2] / a[0]) for n, a in acc.items() if a[0]}, cf, cw
 
 
-def summarize(trace: str, fetch: str, write: str, out: str, title: str, commands: str):
+def summarize(trace: str, fetch: str, write: str, out: str, title: str, commands: str, solve_phases: int = 1):
     stats = _csv(trace, "kernel_stats.csv")
     tot = sum(float(r["TotalDurationNs"]) for r in stats)
     rows = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))
@@ -105,6 +111,13 @@ def summarize(trace: str, fetch: str, write: str, out: str, title: str, commands
         lines.append(f"| {short_name(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                      f"{float(r['MaxNs']) / 1e3:.1f} | {100 * float(r['TotalDurationNs']) / tot:.2f} |")
+    solve = [r for r in stats if short_name(r["Name"]).startswith("k_band_solve")]
+    if solve:
+        calls = sum(int(r["Calls"]) for r in solve)
+        tns = sum(float(r["TotalDurationNs"]) for r in solve)
+        ops = calls / solve_phases
+        lines += ["", f"Block solve per operation ({solve_phases} dispatch(es) per solve): {ops:.0f} operations, "
+                      f"{tns / ops / 1e3:.1f} us per operation."]
     if traffic:
         lines += ["", "## HBM traffic per launch (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`)", "",
                   f"Calibration on the 256 MiB copy: bytes = FETCH_SIZE x {cf / 1024:.3f} KiB, "
@@ -118,7 +131,8 @@ def summarize(trace: str, fetch: str, write: str, out: str, title: str, commands
             if not hit:
                 continue
             c = sum(v[0] for _, v in hit)
-            b = sum(v[0] * (v[1] + v[2]) for _, v in hit) / c
+            per = solve_phases if kern == "k_band_solve" else 1
+            b = sum(v[0] * (v[1] + v[2]) for _, v in hit) / (c / per)
             lines.append(f"    traffic_bytes_per_launch {kern} {b:.0f} sources_sha256 {sources_sha256(kern)}")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -139,7 +153,7 @@ def recorded_traffic(md_path: str, kernel: str):
     return None
 
 
-def run_workload(boxes: int, steps: int):
+def run_workload(boxes: int, steps: int, workload: str = "uniform", precision: int = 0):
     import torch
     sys.path.insert(0, os.path.dirname(HERE))
     from paper_2211_13893_amd import msgfem, synth
@@ -149,7 +163,9 @@ def run_workload(boxes: int, steps: int):
     torch.cuda.synchronize()
     print("calibration copy done", flush=True)
     del a, b
-    st = msgfem.LocalStage(synth.uniform_batch(n_boxes=boxes), tol=1e-6)
+    prob = synth.uniform_batch(n_boxes=boxes) if workload == "uniform" else synth.uneven_laminate()
+    st = msgfem.LocalStage(prob, tol=1e-6, precision=precision, tuned=True)
+    print(f"plan options {st.plan_options} (class {st.size_class})", flush=True)
     for i in range(steps):
         st.msgfem_assemble_local()
         out = st.msgfem_local_eigs()
@@ -235,6 +251,8 @@ def main(argv=None):
     r = sub.add_parser("run")
     r.add_argument("--boxes", type=int, default=64)
     r.add_argument("--steps", type=int, default=1)
+    r.add_argument("--workload", choices=["uniform", "uneven"], default="uniform")
+    r.add_argument("--precision", type=int, default=0)
     u = sub.add_parser("reuse")
     u.add_argument("--boxes", type=int, default=64)
     u.add_argument("--changed", type=int, default=8)
@@ -246,13 +264,14 @@ def main(argv=None):
     s.add_argument("--out", required=True)
     s.add_argument("--title", default="Kernel trace")
     s.add_argument("--commands", default="")
+    s.add_argument("--solve-phases", type=int, default=1)
     a = ap.parse_args(argv)
     if a.cmd == "run":
-        run_workload(a.boxes, a.steps)
+        run_workload(a.boxes, a.steps, a.workload, a.precision)
     elif a.cmd == "reuse":
         run_reuse(a.boxes, a.changed, a.layout)
     else:
-        summarize(a.trace, a.fetch, a.write, a.out, a.title, a.commands)
+        summarize(a.trace, a.fetch, a.write, a.out, a.title, a.commands, a.solve_phases)
 
 
 if __name__ == "__main__":
