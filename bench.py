@@ -38,6 +38,8 @@ PEAK_FP64_TFLOPS = 78.6
 # rocprofv3 summary of the FP64 path on this workload (kernel times and the
 # FETCH_SIZE / WRITE_SIZE traffic of its kernels)
 PROFILE = "local_stage_uniform_batch64_fp64.md"
+# the same for the mixed path on the uneven batch
+PROFILE_C3 = "local_stage_uneven_batch168_mixed.md"
 
 
 def cpu_baseline(prob, n_sample: int):
@@ -148,7 +150,7 @@ def c3_leg(run, args):
                "value": mixed["value"], "unit": "GEVP/s", "ms_per_step": mixed["ms_step"],
                "converged": f"{mixed['conv']}/{len(dofs)}", "lobpcg_iters_mean": float(mixed["iters"].mean()),
                "max_nu_rel_diff_vs_fp64_path": float(dnu.max()),
-               "roofline": roofline(mixed["stats"], None), "kernels": kernel_table(mixed["stats"], steps)},
+               "roofline": roofline(mixed["stats"], PROFILE_C3), "kernels": kernel_table(mixed["stats"], steps)},
            "graph_vs_eager": {"graph": {"value": graph["value"], "ms_per_step": graph["ms_step"],
                                         "graph_launches_last_step": graph["graph_launches"]},
                               "eager": {"value": eager["value"], "ms_per_step": eager["ms_step"]},

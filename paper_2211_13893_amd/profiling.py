@@ -5,7 +5,8 @@
         the profiled workload: one 256 MiB device-to-device copy (the
         calibration of the traffic counters), then `steps` local stages
         (assembly + factorisation + LOBPCG) of the uniform batch or the
-        uneven batch, with the plan options of their size class (as bench.py);
+        uneven batch, with the plan options of their size class and eager
+        LOBPCG launches (as the timed steps of bench.py);
     python -m paper_2211_13893_amd.profiling summarize --trace D --fetch D --write D --out F.md
         a markdown summary of the kernel statistics of a `--kernel-trace
         --stats` run (directory D) and, per kernel, the HBM bytes per launch
@@ -164,7 +165,10 @@ def run_workload(boxes: int, steps: int, workload: str = "uniform", precision: i
     print("calibration copy done", flush=True)
     del a, b
     prob = synth.uniform_batch(n_boxes=boxes) if workload == "uniform" else synth.uneven_laminate()
-    st = msgfem.LocalStage(prob, tol=1e-6, precision=precision, tuned=True)
+    # eager LOBPCG launches, as in the timed steps of bench.py (which bracket
+    # every launch with HIP events): graph replays would add the empty
+    # iterations of a replay after convergence to the dispatch counts
+    st = msgfem.LocalStage(prob, tol=1e-6, precision=precision, tuned=True, graph=False)
     print(f"plan options {st.plan_options} (class {st.size_class})", flush=True)
     for i in range(steps):
         st.msgfem_assemble_local()
