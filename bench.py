@@ -160,6 +160,73 @@ def c3_leg(run, args):
     return out
 
 
+def c4_leg(n_train_seeds=79, n_held_seeds=16, n_boxes=256, steps=2000):
+    """The learned warm start at scale: a 48-mode basis (the 48 lowest
+    A-harmonic modes of the homogeneous reference box, two deflated rounds),
+    labels from the FP64 path on n_train_seeds x n_boxes training boxes
+    (seeds 0 ..), Adam on 64-box minibatches, then LOBPCG iterations and time
+    from the random and the learned start on n_held_seeds x n_boxes held-out
+    boxes (seeds 10^6 ..).  The best start each basis span allows (the label
+    projector's leading vectors, so the network's ceiling) is measured for
+    the 32- and 48-mode bases on the first held-out batch."""
+    import gc
+    import numpy as np
+    import torch
+    from paper_2211_13893_amd import msgfem, synth, warm
+    t0 = time.perf_counter()
+    G48, st_ref, _ = warm.reference_basis(ng=48)
+    del st_ref
+    G32, st_ref, _ = warm.reference_basis(ng=32)
+    del st_ref
+    _log("[C4] reference bases of 48 and 32 modes done")
+    feats, labels = warm.dataset(G48, range(n_train_seeds), n_boxes=n_boxes, log=_log)
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, losses = warm.fit_dataset(G48, feats, labels, steps=steps, log=_log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n_train = sum(f.shape[0] for f in feats)
+    del feats, labels
+    gc.collect()
+    torch.cuda.empty_cache()
+    held = [10**6 + i for i in range(n_held_seeds)]
+    ev = warm.evaluate(net, G48, held, n_boxes=n_boxes, log=_log)
+    _log("[C4] basis ceilings")
+    # ceilings of the two bases on the first held-out batch
+    p = synth.warm_start_batch(n_boxes=n_boxes, seed=held[0])
+    st = msgfem.LocalStage(p, tuned=True)
+    st.msgfem_assemble_local()
+    out = st.msgfem_local_eigs()
+    ceil = {}
+    for name, G in (("basis32", G32), ("basis48", G48)):
+        P = st.msgfem_warm_labels(out, G, 16).double().cpu().numpy()
+        _, V = np.linalg.eigh(P)
+        coef = torch.as_tensor(np.ascontiguousarray(V[:, :, -16:]).reshape(P.shape[0], -1), dtype=torch.float32,
+                               device="cuda:0")
+        o2 = st.msgfem_local_eigs(x0=st.msgfem_warm_start(coef, G, 16, 0))
+        ceil[name] = float(o2["iters"].float().mean().item())
+    it_rand_first = float(out["iters"].float().mean().item())
+    del st, out
+    gc.collect()
+    torch.cuda.empty_cache()
+    ir, iw = ev["iters_random"], ev["iters_warm"]
+    return {"workload": "warm_start_batch",
+            "description": "14^3-element boxes of wrinkled ply/resin laminates (wrinkle amplitude U[0, 0.8] ply, "
+                           "layer moduli log-U scaled by 1/1.2 .. 1.2), n_ev 16, FP64 path, rho <= 1e-6",
+            "training_boxes": int(n_train), "held_out_boxes": int(ir.size), "basis_modes": 48,
+            "adam_steps": steps, "minibatch": 64, "final_loss": float(np.mean(losses[-50:])),
+            "data_seconds": t_data, "train_seconds": t_train,
+            "iters_mean_random": float(ir.mean()), "iters_mean_learned": float(iw.mean()),
+            "iteration_reduction": float(1.0 - iw.mean() / ir.mean()),
+            "seconds_per_box_random": float(ev["seconds_random"].sum() / ir.size),
+            "seconds_per_box_learned": float(ev["seconds_warm"].sum() / iw.size),
+            "time_reduction": float(1.0 - ev["seconds_warm"].sum() / ev["seconds_random"].sum()),
+            "max_nu_rel_diff": ev["max_nu_rel_diff"], "all_converged": ev["all_converged"],
+            "ceiling_first_held_batch": {"iters_random": it_rand_first, **{f"iters_{k}": v for k, v in ceil.items()}},
+            "network": "4 conv3d 3^3 (6->32->32->32->32, strides 1,1,2,2, ReLU), mean pool, affine 32 -> 48*16; "
+                       "BF16 storage, FP32 sums (vector FMA kernels)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +241,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="LOBPCG block width (0: the library's rule)")
     ap.add_argument("--no-c5", action="store_true", help="skip the full-laminate pipeline")
     ap.add_argument("--no-f1", action="store_true", help="skip the GenEO vs MS-GFEM comparison")
+    ap.add_argument("--no-c4", action="store_true", help="skip the learned warm start at scale")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the local GEVPs of a batch "
@@ -323,6 +391,10 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_f1:
         line["geneo_vs_msgfem"] = f1_leg()
+        gc.collect()
+        torch.cuda.empty_cache()
+    if not args.no_c4:
+        line["learned_warm_start_at_scale"] = c4_leg()
         gc.collect()
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline and args.cpu_sample > 0:

@@ -551,7 +551,8 @@ int msgfem_warm_labels(msgfem_plan *plan, const void *ops, const double *evecs, 
  * first ne columns, Gaussian columns from (seed, box, DoF, column)
  * otherwise, 0 off B2.  coef: device float[n_box][ng][ne] (network output).
  * A predicted column that is zero or not finite is replaced by a Gaussian
- * column (the fallback to the random start).  0 <= ne <= k. */
+ * column (the fallback to the random start).  0 <= ne <= k, ng ne <= 12288
+ * (the coefficients of a box are staged in LDS); MSGFEM_EARG otherwise. */
 int msgfem_warm_start(msgfem_plan *plan, const void *ops, const float *coef, const double *G,
                       int32_t n_dof_g, int32_t ng, int32_t ne, uint64_t seed, double *x0, void *stream);
 

@@ -2957,11 +2957,12 @@ extern "C" int msgfem_warm_start(msgfem_plan* p, const void* ops, const float* c
   if (!same_boxes(p) || p->meta[0].n_dof != n_dof_g)
     return fail(p, MSGFEM_EARG, "every box must have the %d DoFs of the basis", n_dof_g);
   if (ng < 1 || ne < 0 || ne > p->k) return fail(p, MSGFEM_EARG, "need ng >= 1 and 0 <= ne <= block %d", p->k);
+  if ((int64_t)ng * ne > 12288) return fail(p, MSGFEM_EARG, "ng x ne = %d exceeds 12288", ng * ne);
   if (set_device(p)) return MSGFEM_EHIP;
   OpsView v = ops_view(p, ops);
-  const int64_t n = (int64_t)n_dof_g * p->k;
-  k_warm_start<<<dim3((unsigned)((n + 255) / 256), (unsigned)p->meta.size()), 256, 0, (hipStream_t)stream>>>(
-      v.meta, v.cls, coef, G, ng, ne, p->k, seed, x0);
+  const size_t lds = ((size_t)ng * ne + ne) * 4;
+  k_warm_start<<<dim3((unsigned)((n_dof_g + 255) / 256), (unsigned)p->meta.size()), 256, lds,
+                 (hipStream_t)stream>>>(v.meta, v.cls, coef, G, ng, ne, p->k, seed, x0);
   LAUNCHCHK(p);
   return MSGFEM_OK;
 }

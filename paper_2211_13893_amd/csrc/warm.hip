@@ -81,6 +81,112 @@ __global__ void k_conv_fwd(const T* __restrict__ x, const T* __restrict__ w, con
   }
 }
 
+// The same layer for BF16 storage on the matrix cores, as an implicit GEMM
+//     Y[co][v] = sum_k W[co][k] X[k][v],
+// X[k][v] the input value of channel ci(k) under tap tap(k) of output voxel v
+// (zero outside the grid), with v_mfma_f32_16x16x16bf16_1k: BF16 products,
+// FP32 sums.  The K order is ci-major (k = 27 ci + tap) in general and
+// tap-major (k = ci_n tap + ci) when ci_n is a multiple of 16, so that a
+// chunk of 16 k shares one tap and its bounds test.  W comes packed in that
+// order by k_pack_conv_w: 32 rows (zero past co_n) of kp = 27 ci_n rounded up
+// to 16 (zero past 27 ci_n).  A wavefront owns 16 output voxels of one sample
+// and every output channel (co_n <= 32, two 16-row blocks).
+// Lane layout (l = lane): A operand A[l&15][4(l>>4) + e], B operand
+// B[4(l>>4) + e][l&15], accumulator item e = D[4(l>>4) + e][l&15], e < 4.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void k_pack_conv_w(const float* __restrict__ w, uint16_t* __restrict__ wp, int ci_n, int co_n, int kp,
+                              int tap_major) {
+  const int K = 27 * ci_n;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 32 * kp; t += gridDim.x * blockDim.x) {
+    const int co = t / kp, k = t % kp;
+    float v = 0.0f;
+    if (co < co_n && k < K) {
+      const int ci = tap_major ? k % ci_n : k / 27, tap = tap_major ? k / ci_n : k % 27;
+      v = w[((int64_t)co * ci_n + ci) * 27 + tap];
+    }
+    wp[t] = f2bf(v);
+  }
+}
+
+template <bool TAP_MAJOR>
+__global__ __launch_bounds__(256) void k_conv_fwd_mfma(const uint16_t* __restrict__ x,
+                                                       const uint16_t* __restrict__ wp,
+                                                       const float* __restrict__ bias, uint16_t* __restrict__ y,
+                                                       int B, int ci_n, int co_n, int kp, int d, int s) {
+  const int od = cnn_out(d, s), ov = od * od * od, iv = d * d * d;
+  const int nt = (ov + 15) / 16;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wave >= (int64_t)B * nt) return;
+  const int b = (int)(wave / nt), o = (int)(wave % nt) * 16 + (lane & 15), g = lane >> 4;
+  const bool vox = o < ov;
+  const int oc = vox ? o : 0;
+  const int i = oc / (od * od), j = (oc / od) % od, k = oc % od;
+  const int z0 = s * i - 1, y0 = s * j - 1, x0 = s * k - 1;
+  const int K = 27 * ci_n;
+  const uint16_t* xb = x + (int64_t)b * ci_n * iv;
+  const uint16_t* w0p = wp + (int64_t)(lane & 15) * kp + 4 * g;
+  const uint16_t* w1p = w0p + (int64_t)16 * kp;
+  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  // ci-major order: (ci, tap) of this lane's 4 k values in the current chunk
+  int ci[4], tap[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    ci[e] = (4 * g + e) / 27;
+    tap[e] = (4 * g + e) % 27;
+  }
+  const int nblk_ci = ci_n / 16;
+  for (int kc = 0, c = 0; kc < K; kc += 16, ++c) {
+    bf16x4 bv;
+    if (TAP_MAJOR) {
+      const int t = c / nblk_ci, cb = c % nblk_ci;
+      const int zi = z0 + t / 9, zj = y0 + (t / 3) % 3, zk = x0 + t % 3;
+      const bool in = vox && zi >= 0 && zi < d && zj >= 0 && zj < d && zk >= 0 && zk < d;
+      const uint16_t* xp = xb + (int64_t)(cb * 16 + 4 * g) * iv + (in ? (zi * d + zj) * d + zk : 0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bv[e] = in ? (short)xp[(int64_t)e * iv] : (short)0;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        uint16_t xv = 0;
+        if (kc + 4 * g + e < K) {
+          const int zi = z0 + tap[e] / 9, zj = y0 + (tap[e] / 3) % 3, zk = x0 + tap[e] % 3;
+          if (vox && zi >= 0 && zi < d && zj >= 0 && zj < d && zk >= 0 && zk < d)
+            xv = xb[(int64_t)ci[e] * iv + (zi * d + zj) * d + zk];
+        }
+        bv[e] = (short)xv;
+        tap[e] += 16;
+        if (tap[e] >= 27) {
+          tap[e] -= 27;
+          ++ci[e];
+        }
+      }
+    }
+    const bf16x4 a0 = *(const bf16x4*)(w0p + kc);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, bv, acc0, 0, 0, 0);
+    if (co_n > 16) {
+      const bf16x4 a1 = *(const bf16x4*)(w1p + kc);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, bv, acc1, 0, 0, 0);
+    }
+  }
+  if (!vox) return;
+  uint16_t* yb = y + (int64_t)b * co_n * ov;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int c0 = 4 * g + e, c1 = 16 + 4 * g + e;
+    if (c0 < co_n) {
+      const float v = acc0[e] + bias[c0];
+      stv(yb, (int64_t)c0 * ov + o, v > 0.0f ? v : 0.0f);
+    }
+    if (c1 < co_n) {
+      const float v = acc1[e] + bias[c1];
+      stv(yb, (int64_t)c1 * ov + o, v > 0.0f ? v : 0.0f);
+    }
+  }
+}
+
 // g[b][c] = mean over the grid of a[b][c]
 template <typename T>
 __global__ void k_pool_fwd(const T* __restrict__ a, float* __restrict__ g, int B, int C, int vol) {
@@ -440,30 +546,54 @@ __device__ inline double warm_gauss(uint64_t seed, uint64_t a, uint64_t b, uint6
 
 // x0 of every box on B2: column e < ne = G C[:, e], the other columns seeded
 // Gaussian; 0 off B2.  A predicted column that is not finite or is zero falls
-// back to a Gaussian column too.  Box block layout [n_dof][k].
-__global__ void k_warm_start(const BoxMeta* __restrict__ meta, const uint8_t* __restrict__ cls,
-                             const float* __restrict__ coef, const double* __restrict__ G, int ng, int ne,
-                             int k, uint64_t seed, double* __restrict__ x0) {
-  const BoxMeta& bm = meta[blockIdx.y];
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)bm.n_dof * k) return;
-  const int d = (int)(t / k), e = (int)(t % k);
-  double v = 0.0;
-  if (cls[bm.dof_off + d] == 2) {
-    bool rnd = e >= ne;
-    if (!rnd) {
-      const float* cb = coef + (int64_t)blockIdx.y * ng * ne;
-      double nrm = 0.0;
-      for (int g = 0; g < ng; ++g) {
-        const double cg = (double)cb[g * ne + e];
-        v += G[(int64_t)d * ng + g] * cg;
-        nrm += cg * cg;
-      }
-      rnd = !(nrm > 0.0) || !isfinite(nrm);
+// back to a Gaussian column too.  Box block layout [n_dof][k].  One thread
+// per DoF row: the box's C and its column checks sit in LDS, the row's G
+// entries are read once per 8 columns, and the row of x0 is written whole.
+__global__ __launch_bounds__(256) void k_warm_start(const BoxMeta* __restrict__ meta,
+                                                    const uint8_t* __restrict__ cls,
+                                                    const float* __restrict__ coef, const double* __restrict__ G,
+                                                    int ng, int ne, int k, uint64_t seed, double* __restrict__ x0) {
+  extern __shared__ float wsh[];          // C of this box [ng][ne], then one flag per column
+  int* okc = (int*)(wsh + ng * ne);
+  const int box = blockIdx.y;
+  const BoxMeta& bm = meta[box];
+  const float* cb = coef + (int64_t)box * ng * ne;
+  for (int i = threadIdx.x; i < ng * ne; i += blockDim.x) wsh[i] = cb[i];
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    double nrm = 0.0;
+    for (int g = 0; g < ng; ++g) {
+      const double cg = (double)cb[g * ne + e];
+      nrm += cg * cg;
     }
-    if (rnd) v = warm_gauss(seed, blockIdx.y, d, e);
+    okc[e] = (nrm > 0.0 && isfinite(nrm)) ? 1 : 0;
   }
-  x0[bm.dof_off * k + t] = v;
+  __syncthreads();
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= bm.n_dof) return;
+  double* xr = x0 + ((int64_t)bm.dof_off + d) * k;
+  if (cls[bm.dof_off + d] != 2) {
+    for (int e = 0; e < k; ++e) xr[e] = 0.0;
+    return;
+  }
+  const double* gr = G + (int64_t)d * ng;
+  for (int e0 = 0; e0 < ne; e0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+    for (int g = 0; g < ng; ++g) {
+      const double gv = gr[g];
+      const float* cr = wsh + g * ne + e0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (e0 + j < ne) acc[j] += gv * (double)cr[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = e0 + j;
+      if (e < ne) xr[e] = okc[e] ? acc[j] : warm_gauss(seed, box, d, e);
+    }
+  }
+  for (int e = ne; e < k; ++e) xr[e] = warm_gauss(seed, box, d, e);
 }
 
 // ------------------------------------------------------------- C ABI
@@ -471,6 +601,8 @@ namespace {
 struct CnnDims {
   int cin, width, n_out, d0, d[5];
   int64_t woff[4], boff[4], wl, bl, n_params;
+  int kp[4];                 // packed K per layer (27 ci_n rounded up to 16)
+  int64_t wpoff[4], n_wp;    // packed BF16 weights of the matrix-core layers: 32 x kp each
 };
 CnnDims cnn_dims(int cin, int width, int n_out, int d0) {
   CnnDims c;
@@ -493,12 +625,19 @@ CnnDims cnn_dims(int cin, int width, int n_out, int d0) {
   c.bl = off;
   off += n_out;
   c.n_params = off;
+  c.n_wp = 0;
+  for (int l = 0; l < 4; ++l) {
+    c.kp[l] = (27 * (l == 0 ? cin : width) + 15) / 16 * 16;
+    c.wpoff[l] = c.n_wp;
+    c.n_wp += 32 * (int64_t)c.kp[l];
+  }
   return c;
 }
 struct CnnWork {
   char* act;        // storage-type activations: x, a1..a4
   int64_t aoff[5];
   char* wT;         // storage-type conv weights
+  uint16_t* wP;     // packed BF16 conv weights (matrix-core layers)
   float* g;         // pooled [B][width]
   float* gg;        // [B][width]
   float* gA;        // gradient ping-pong buffers
@@ -521,6 +660,8 @@ CnnWork cnn_work(const CnnDims& c, int B, int esz, void* base) {
   w.act = b;
   w.wT = b + off;
   off = al(off + c.n_params * esz);
+  w.wP = (uint16_t*)(b + off);
+  off = al(off + c.n_wp * 2);
   w.g = (float*)(b + off);
   off = al(off + (int64_t)B * c.width * 4);
   w.gg = (float*)(b + off);
@@ -546,8 +687,26 @@ int cnn_forward_t(const CnnDims& c, const float* params, int B, const float* x, 
   for (int l = 0; l < 4; ++l) {
     const int ci = l == 0 ? c.cin : c.width;
     const int64_t n = (int64_t)B * c.width * c.d[l + 1] * c.d[l + 1] * c.d[l + 1];
-    k_conv_fwd<T><<<nblk(n), 256, 0, s>>>((const T*)(w.act + w.aoff[l]), wT + c.woff[l], params + c.boff[l],
-                                           (T*)(w.act + w.aoff[l + 1]), B, ci, c.width, c.d[l], st[l]);
+    if (sizeof(T) == 2 && c.width <= 32) {
+      const int ov = c.d[l + 1] * c.d[l + 1] * c.d[l + 1];
+      const int64_t waves = (int64_t)B * ((ov + 15) / 16);
+      const bool tap_major = ci % 16 == 0;
+      uint16_t* wp = w.wP + c.wpoff[l];
+      k_pack_conv_w<<<nblk(32 * (int64_t)c.kp[l]), 256, 0, s>>>(params + c.woff[l], wp, ci, c.width, c.kp[l],
+                                                                tap_major ? 1 : 0);
+      const unsigned grid = (unsigned)((waves + 3) / 4);
+      const uint16_t* xin = (const uint16_t*)(w.act + w.aoff[l]);
+      uint16_t* yout = (uint16_t*)(w.act + w.aoff[l + 1]);
+      if (tap_major)
+        k_conv_fwd_mfma<true><<<grid, 256, 0, s>>>(xin, wp, params + c.boff[l], yout, B, ci, c.width, c.kp[l],
+                                                   c.d[l], st[l]);
+      else
+        k_conv_fwd_mfma<false><<<grid, 256, 0, s>>>(xin, wp, params + c.boff[l], yout, B, ci, c.width, c.kp[l],
+                                                    c.d[l], st[l]);
+    } else {
+      k_conv_fwd<T><<<nblk(n), 256, 0, s>>>((const T*)(w.act + w.aoff[l]), wT + c.woff[l], params + c.boff[l],
+                                             (T*)(w.act + w.aoff[l + 1]), B, ci, c.width, c.d[l], st[l]);
+    }
   }
   const int vol = c.d[4] * c.d[4] * c.d[4];
   k_pool_fwd<T><<<B * c.width, 256, 0, s>>>((const T*)(w.act + w.aoff[4]), w.g, B, c.width, vol);

@@ -259,6 +259,31 @@ class LocalStage:
         self.ops = None
         self.work = None
 
+    def load_mesh(self, problem):
+        """Copy the mesh arrays (node coordinates, element materials, material
+        table, Dirichlet flags) of `problem` into this stage's device arrays,
+        which the plan reads at every msgfem_assemble_local.  The problem must
+        have this plan's geometry: mesh size, material count, decomposition and
+        batch (only the values change, e.g. another wrinkle or layup), so the
+        plan, its ops and work buffers are reused as they are."""
+        torch = self.torch
+        p, q = problem, self.problem
+        same = ((p.nx, p.ny, p.nz, p.materials.shape[0], p.overlap) == (q.nx, q.ny, q.nz, q.materials.shape[0],
+                                                                      q.overlap)
+                and np.array_equal(p.cores, q.cores) and np.array_equal(p.ovs, q.ovs)
+                and np.array_equal(np.asarray(p.batch), np.asarray(q.batch))
+                and np.array_equal(np.asarray(p.n_ev), np.asarray(q.n_ev)))
+        if not same:
+            raise MsgfemError("load_mesh needs a problem with this plan's mesh size, materials count, "
+                              "decomposition and batch")
+        for dst, src, dt in ((self._xyz, p.xyz, np.float64), (self._emat, p.elem_mat, np.int32),
+                             (self._mats, p.materials, np.float64), (self._dir, p.dirichlet, np.uint8)):
+            a = torch.as_tensor(np.ascontiguousarray(src, dtype=dt))
+            if a.numel() != dst.numel():
+                raise MsgfemError("load_mesh: array sizes differ")
+            dst.copy_(a.view(dst.shape))
+        self.problem = p
+
     def set_option(self, key: int, value: int):
         """msgfem_plan_set_option"""
         _check(self.lib.msgfem_plan_set_option(self.plan, int(key), int(value)), self.plan, "msgfem_plan_set_option")

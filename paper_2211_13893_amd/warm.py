@@ -135,3 +135,93 @@ def fit(G, seeds=range(4), steps: int = 300, lr: float = 2e-3, ne: int = 16, bf1
     for i, b in enumerate(order):
         losses.append(net.train_step(*data[int(b)], lr=lr if i < 0.7 * steps else lr / 4))
     return net, losses
+
+
+def dataset(G, seeds, ne: int = 16, n_boxes: int = 256, device: str = "cuda:0", log=None):
+    """Features and labels (FP64 path) of the warm-start batches of `seeds`,
+    n_boxes boxes each.  The batches share their geometry, so one plan is
+    reused and only the mesh arrays change between them (LocalStage.load_mesh)."""
+    import torch
+    feats, labels = [], []
+    st = None
+    for i, s in enumerate(seeds):
+        if log and i % 8 == 0:
+            log(f"  warm-start data: batch {i + 1}/{len(seeds)} (seed {s})")
+        p = synth.warm_start_batch(n_boxes=n_boxes, seed=int(s))
+        if st is None:
+            st = msgfem.LocalStage(p, device=device, tuned=True)
+        else:
+            st.load_mesh(p)
+        st.msgfem_assemble_local()
+        out = st.msgfem_local_eigs()
+        feats.append(st.msgfem_warm_features())
+        labels.append(st.msgfem_warm_labels(out, G, ne))
+        del out
+    del st
+    torch.cuda.empty_cache()
+    return feats, labels
+
+
+def fit_dataset(G, feats, labels, steps: int = 2000, lr: float = 2e-3, ne: int = 16, bf16: bool = True,
+                net_seed: int = 1, minibatch: int = 64, device: str = "cuda:0", log=None):
+    """Adam on minibatches of `minibatch` boxes drawn (seeded) from the whole
+    data set; lr dropped 4x for the last 30%.  Returns (net, losses)."""
+    net = WarmStartNet(ng=G.shape[1], ne=ne, bf16=bf16, seed=net_seed, device=device)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([23, net_seed])))
+    losses = []
+    for i in range(steps):
+        j = int(rng.integers(len(feats)))
+        nb = feats[j].shape[0]
+        o = int(rng.integers(max(1, nb // minibatch))) * minibatch
+        f, p = feats[j][o:o + minibatch], labels[j][o:o + minibatch]
+        losses.append(net.train_step(f, p, lr=lr if i < 0.7 * steps else lr / 4))
+        if log and (i + 1) % 250 == 0:
+            log(f"  warm-start training: step {i + 1}/{steps}, loss {np.mean(losses[-50:]):.3f}")
+    return net, losses
+
+
+def evaluate(net, G, seeds, ne: int = 16, n_boxes: int = 256, device: str = "cuda:0", log=None):
+    """On the held-out batches of `seeds`: LOBPCG iterations and seconds per
+    batch from the random start and from the network's start (its features,
+    inference and start block inside the timed region), and the largest
+    relative difference of nu between the two.  Returns a dict of arrays."""
+    import time
+    import torch
+    it_r, it_w, t_r, t_w, dnu, ok = [], [], [], [], [], True
+    st = None
+    for i, s in enumerate(seeds):
+        if log:
+            log(f"  warm-start held-out batch {i + 1}/{len(seeds)} (seed {s})")
+        p = synth.warm_start_batch(n_boxes=n_boxes, seed=int(s))
+        if st is None:
+            st = msgfem.LocalStage(p, device=device, tuned=True)
+            st.msgfem_assemble_local()
+            st.msgfem_local_eigs()          # first calls: buffers allocated outside the timings
+            net.start_block(st, G)
+        else:
+            st.load_mesh(p)
+        st.msgfem_assemble_local()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out_r = st.msgfem_local_eigs()
+        torch.cuda.synchronize()
+        t_r.append(time.perf_counter() - t0)
+        it_r.append(out_r["iters"].cpu().numpy())
+        lam_r = out_r["evals"].cpu().numpy()
+        ok &= bool(np.all(out_r["status"].cpu().numpy() == 0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out_w = st.msgfem_local_eigs(x0=net.start_block(st, G))
+        torch.cuda.synchronize()
+        t_w.append(time.perf_counter() - t0)
+        it_w.append(out_w["iters"].cpu().numpy())
+        lam_w = out_w["evals"].cpu().numpy()
+        ok &= bool(np.all(out_w["status"].cpu().numpy() == 0))
+        nu_r, nu_w = 1.0 / (lam_r + 1.0), 1.0 / (lam_w + 1.0)
+        dnu.append(float(np.abs(nu_w - nu_r).max() / nu_r.max()))
+        del out_r, out_w
+    del st
+    torch.cuda.empty_cache()
+    return {"iters_random": np.concatenate(it_r), "iters_warm": np.concatenate(it_w),
+            "seconds_random": np.array(t_r), "seconds_warm": np.array(t_w), "max_nu_rel_diff": max(dnu),
+            "all_converged": ok}
