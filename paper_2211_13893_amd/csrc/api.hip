@@ -41,6 +41,16 @@ __global__ void k_sep_syrk(const SepDesc*, double*);
 template <bool TWO, int CW, typename ST>
 __global__ void k_spmm(const BoxMeta*, int, int, const ST*, const uint8_t*, const double*, const double*,
                        double*, double*, int, int, double, const int32_t*);
+template <bool TWO, typename ST>
+__global__ void k_spmm_planes(const BoxMeta*, int, int, int, const ST*, const uint8_t*, const double*,
+                              const double*, double*, double*, int, int, double, const int32_t*);
+#define SP_PLANE 240   // nodes of a staged plane tile (k_spmm_planes)
+static int sp_tile_x_host(int mx, int my) {
+  if (mx * my <= SP_PLANE) return mx;
+  const int t = SP_PLANE / my - 2;
+  return t >= 1 ? t : 0;
+}
+static size_t sp_lds(bool two) { return (size_t)3 * 3 * SP_PLANE * 4 * 16 + (two ? (size_t)3 * 3 * SP_PLANE * 8 : 0); }
 __global__ void k_mixed_copies(const BoxMeta*, int, const double*, float*, const double*, float*);
 __global__ void k_mask_b3(const uint8_t*, const double*, int, int64_t, double*);
 __global__ void k_keep_classes(const uint8_t*, int, int, int64_t, double*);
@@ -1007,6 +1017,9 @@ static void lds_attributes() {
   for (const void* f : solves4) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_update<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
+  const void* spp[] = {(const void*)k_spmm_planes<false, double>, (const void*)k_spmm_planes<true, double>,
+                       (const void*)k_spmm_planes<false, float>, (const void*)k_spmm_planes<true, float>};
+  for (const void* f : spp) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_update<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_gram_partial<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1033,6 +1046,37 @@ static int spmm(Ctx& c, const double* X, double* Y, double* Y2, int kk, int ycla
     fl += 2.0 * 243 * m.n_nodes * kk * (Y2 ? 2 : 1);
   }
   ProfScope ps(c.p, PK_SPMM, c.s, by, fl, !c.no_alloc);
+  // a batch of boxes and a block of whole 8-column groups: the LDS-staged
+  // plane sweep (every box's plane tile must fit)
+  int max_tiles = 0;
+  if (kk % 8 == 0 && c.nb >= 16) {
+    for (int b = 0; b < c.nb; ++b) {
+      const BoxMeta& m = c.p->meta[b];
+      const int tx = sp_tile_x_host(m.mx, m.my);
+      if (tx == 0) {
+        max_tiles = 0;
+        break;
+      }
+      max_tiles = std::max(max_tiles, (m.mx + tx - 1) / tx);
+    }
+  }
+  if (max_tiles > 0) {
+    const int ng = kk / 8;
+    const int64_t units = (int64_t)c.nb * max_tiles;
+    const dim3 pg((unsigned)(8 * ng * ((units + 7) / 8)));
+    auto launch_p = [&](auto st) {
+      if (Y2)
+        k_spmm_planes<true><<<pg, 1024, sp_lds(true), c.s>>>(c.v.meta, c.nb, max_tiles, ng, st, c.v.cls, c.v.mu1,
+                                                            X, Y, Y2, kk, yclasses, scale, active);
+      else
+        k_spmm_planes<false><<<pg, 1024, sp_lds(false), c.s>>>(c.v.meta, c.nb, max_tiles, ng, st, c.v.cls,
+                                                              c.v.mu1, X, Y, Y2, kk, yclasses, scale, active);
+    };
+    if (c.use32) launch_p((const float*)c.v.stencil32);
+    else launch_p((const double*)c.v.stencil);
+    LAUNCHCHK(c.p);
+    return 0;
+  }
   auto launch = [&](auto st) {
     if (Y2)
       k_spmm<true, 4><<<grid, 256, 0, c.s>>>(c.v.meta, c.nb, bpb, st, c.v.cls, c.v.mu1, X, Y, Y2, kk, yclasses,

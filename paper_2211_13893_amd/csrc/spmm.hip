@@ -151,6 +151,245 @@ template __global__ void k_spmm<true, 4, float>(const BoxMeta*, int, int, const 
                                                    const double*, const double*, double*, double*, int, int, double,
                                                    const int32_t*);
 
+// The same products for a batch of boxes and a block of width k (a multiple
+// of 8), staged through LDS.  A workgroup takes 8 columns of one box (or of
+// an x-tile of it when a node plane holds more than SP_PLANE nodes) and
+// marches through the box's node planes (z, the slowest node index): the
+// rows of X (and mu) of planes z-1, z, z+1 sit in LDS and the 27 neighbours
+// of a node are read there, so the stencil is the only stream (read once
+// per node and column group, 16 nodes per load).  Four threads per node,
+// two columns each (16 wavefronts per CU hide the stencil's latency).  Plane
+// z+2 is requested into registers while plane z is computed and stored into
+// the slot plane z-1 leaves.  The 8-column groups of a box run on one XCD
+// (block x on XCD x mod 8), so the box's stencil is read from HBM about
+// once.  LDS: 3 slots of [3 DoFs][SP_PLANE nodes][4 column pairs] double2
+// (the 4 threads of a node read consecutive 16-byte pieces), plus [3][SP_PLANE]
+// mu with the second product.
+// grid.x = 8 * n_group * ceil(n_unit / 8), units = n_box * max_tiles
+// (unit = box * max_tiles + tile); 1024 threads.
+#define SP_PLANE 240
+#define SP_THREADS 1024
+
+// x-tile width of a box: the whole plane when it fits, else the widest tile
+// whose plane with one halo column on each side fits (0: does not fit)
+__host__ __device__ inline int sp_tile_x(int mx, int my) {
+  if (mx * my <= SP_PLANE) return mx;
+  const int t = SP_PLANE / my - 2;
+  return t >= 1 ? t : 0;
+}
+
+// value of lane (lane & ~3) + o of the quad (DPP quad_perm broadcast, o a constant)
+__device__ inline double quad_bcast(double v, int o) {
+  const int ctrl = o == 0 ? 0x00 : o == 1 ? 0x55 : o == 2 ? 0xAA : 0xFF;
+  int lo, hi;
+  switch (ctrl) {
+    case 0x00:
+      lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x00, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x00, 0xF, 0xF, false);
+      break;
+    case 0x55:
+      lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x55, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x55, 0xF, 0xF, false);
+      break;
+    case 0xAA:
+      lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xAA, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xAA, 0xF, 0xF, false);
+      break;
+    default:
+      lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xFF, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xFF, 0xF, 0xF, false);
+      break;
+  }
+  return __hiloint2double(hi, lo);
+}
+
+template <bool TWO, typename ST>
+__global__ __launch_bounds__(SP_THREADS) void k_spmm_planes(const BoxMeta* __restrict__ meta, int n_box,
+                                                            int max_tiles, int n_group,
+                                                            const ST* __restrict__ stencil,
+                                                            const uint8_t* __restrict__ cls,
+                                                            const double* __restrict__ mu1,
+                                                            const double* __restrict__ X, double* Y, double* Y2,
+                                                            int k, int y_classes, double scale,
+                                                            const int32_t* __restrict__ active) {
+  extern __shared__ double2 spl[];   // [3 slots][3 DoFs][SP_PLANE][4] double2, then (TWO) [3][3][SP_PLANE] double
+  double* smu = (double*)(spl + 3 * 3 * SP_PLANE * 4);
+  const int xb = blockIdx.x, xcd = xb & 7, rest = xb >> 3;
+  const int g = rest % n_group;
+  const int unit = (rest / n_group) * 8 + xcd;
+  const int box = unit / max_tiles, tile = unit - box * max_tiles;
+  if (box >= n_box) return;
+  if (active && !active[box]) return;
+  const BoxMeta& bm = meta[box];
+  const int mx = bm.mx, my = bm.my, mz = bm.mz;
+  const int TX = sp_tile_x(mx, my);
+  const int x0 = tile * TX;
+  if (TX == 0 || x0 >= mx) return;
+  const int xs = max(x0 - 1, 0), xe = min(x0 + TX + 1, mx), TXh = xe - xs;   // staged columns
+  const int TXa = min(TX, mx - x0);                                           // own columns
+  const int tid = threadIdx.x, tn = tid >> 2, q = tid & 3;
+  const bool own = tn < TXa * my;
+  const int ly = own ? tn / TXa : 0, lx = own ? tn - ly * TXa : 0;
+  const int nx = x0 + lx;
+  const int c0 = 8 * g;
+  const double* x = X + bm.dof_off * k + c0;
+  const uint8_t* cl = cls + bm.dof_off;
+  const double* m1 = mu1 + bm.dof_off;
+  const int nunits = TXh * my * 12;   // double2 pieces of a staged plane
+  constexpr int MAXU = (SP_PLANE * 12 + SP_THREADS - 1) / SP_THREADS;
+  constexpr int MAXM = (SP_PLANE * 3 + SP_THREADS - 1) / SP_THREADS;
+  double2 buf[MAXU];
+  double bmu[MAXM];
+  // plane z into registers: piece u = (staged node h, DoF c, column pair pc)
+  auto fetch = [&](int z) {
+#pragma unroll
+    for (int r = 0; r < MAXU; ++r) {
+      const int u = tid + SP_THREADS * r;
+      buf[r] = double2{0.0, 0.0};
+      if (u < nunits) {
+        const int h = u / 12, e = u - 12 * h;
+        const int hy = h / TXh, hx = h - hy * TXh;
+        const int node = (xs + hx) + mx * (hy + my * z);
+        buf[r] = *(const double2*)(x + (int64_t)(3 * node + (e >> 2)) * k + 2 * (e & 3));
+      }
+    }
+    if (TWO) {
+#pragma unroll
+      for (int r = 0; r < MAXM; ++r) {
+        const int u = tid + SP_THREADS * r;
+        bmu[r] = 0.0;
+        if (u < TXh * my * 3) {
+          const int h = u / 3, c = u - 3 * h;
+          const int hy = h / TXh, hx = h - hy * TXh;
+          bmu[r] = m1[3 * ((xs + hx) + mx * (hy + my * z)) + c];
+        }
+      }
+    }
+  };
+  auto stash = [&](int slot) {
+#pragma unroll
+    for (int r = 0; r < MAXU; ++r) {
+      const int u = tid + SP_THREADS * r;
+      if (u < nunits) {
+        const int h = u / 12, e = u - 12 * h;
+        spl[((slot * 3 + (e >> 2)) * SP_PLANE + h) * 4 + (e & 3)] = buf[r];
+      }
+    }
+    if (TWO) {
+#pragma unroll
+      for (int r = 0; r < MAXM; ++r) {
+        const int u = tid + SP_THREADS * r;
+        if (u < TXh * my * 3) {
+          const int h = u / 3, c = u - 3 * h;
+          smu[(slot * 3 + c) * SP_PLANE + h] = bmu[r];
+        }
+      }
+    }
+  };
+  fetch(0);
+  stash(0);
+  if (mz > 1) {
+    fetch(1);
+    stash(1);
+  }
+  __syncthreads();
+  if (mz > 2) fetch(2);
+  const ST* stb = stencil + bm.node_off * 243;
+  double* y = Y ? Y + bm.dof_off * k + c0 + 2 * q : nullptr;
+  double* y2 = TWO ? Y2 + bm.dof_off * k + c0 + 2 * q : nullptr;
+  for (int z = 0; z < mz; ++z) {
+    if (own) {
+      const int node = nx + mx * (ly + my * z);
+      const ST* st = stb + node;
+      double acc[3][2], acc2[3][2];
+#pragma unroll
+      for (int cr = 0; cr < 3; ++cr) {
+        acc[cr][0] = acc[cr][1] = 0.0;
+        acc2[cr][0] = acc2[cr][1] = 0.0;
+      }
+      // neighbours outside the box have zero stencil blocks: their index is
+      // clamped into the box (the staged tile includes the clamped node).
+      // Per layer dz, the 4 threads of the node split the 81 coefficients of
+      // its 9 neighbours (coefficient v = 9 nbl + e to lane v % 4), request
+      // them together, and pass each one round the quad.
+#pragma unroll 1
+      for (int dz = -1; dz <= 1; ++dz) {
+        const int zz = min(max(z + dz, 0), mz - 1);
+        const int slot = zz % 3;
+        // coefficient v of the layer is stencil row 81 (dz + 1) + v of the node
+        // (nb * 9 + e with nb = nbl + 9 (dz + 1)); lane v % 4 reads it.  With
+        // the second product the layer goes in two parts (neighbours 0-4,
+        // 5-8) to hold fewer coefficients at a time.
+        constexpr int NH = TWO ? 2 : 1;
+        constexpr int NR = TWO ? 12 : 21;
+#pragma unroll
+        for (int hh = 0; hh < NH; ++hh) {
+          asm volatile("" ::: "memory");   // each part's loads after the previous part
+          const int vlo = hh == 0 ? 0 : 45, vhi = NH == 1 ? 81 : (hh == 0 ? 45 : 81);
+          const int qq = (q - vlo) & 3;   // this lane's first coefficient: vlo + qq
+          double sv[NR];
+          const ST* sq = st + (int64_t)(81 * (dz + 1) + vlo + qq) * bm.n_nodes;
+          const int64_t s4 = 4 * (int64_t)bm.n_nodes;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) sv[r] = (vlo + qq + 4 * r < vhi) ? (double)sq[r * s4] : 0.0;
+#pragma unroll
+          for (int nbl = 0; nbl < 9; ++nbl) {
+            if (9 * nbl < vlo || 9 * nbl >= vhi) continue;
+            asm volatile("" ::: "memory");   // one neighbour's LDS reads at a time (register pressure)
+            const int dy = nbl / 3 - 1, dx = nbl % 3 - 1;
+            const int yy = min(max(ly + dy, 0), my - 1);
+            const int xx = min(max(nx + dx, 0), mx - 1);
+            const int h = (xx - xs) + TXh * yy;
+            double2 xv[3];
+            double mu[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+              xv[cc] = spl[((slot * 3 + cc) * SP_PLANE + h) * 4 + q];
+              mu[cc] = TWO ? smu[(slot * 3 + cc) * SP_PLANE + h] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < 9; ++e) {
+              const int v = 9 * nbl + e, cr = e / 3, cc = e % 3;
+              const double a = quad_bcast(sv[(v - vlo) >> 2], v & 3);
+              acc[cr][0] += a * xv[cc].x;
+              acc[cr][1] += a * xv[cc].y;
+              if (TWO) {
+                const double am = a * mu[cc];
+                acc2[cr][0] += am * xv[cc].x;
+                acc2[cr][1] += am * xv[cc].y;
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int cr = 0; cr < 3; ++cr) {
+        const int d = 3 * node + cr;
+        const bool w = (y_classes >> cl[d]) & 1;
+        if (y) *(double2*)(y + (int64_t)d * k) = w ? double2{scale * acc[cr][0], scale * acc[cr][1]} : double2{0.0, 0.0};
+        if (TWO) {
+          const double mo = m1[d];
+          *(double2*)(y2 + (int64_t)d * k) = double2{mo * acc2[cr][0], mo * acc2[cr][1]};
+        }
+      }
+    }
+    // slot (z+2) % 3 held plane z-1, which no thread reads any more
+    __syncthreads();
+    if (z + 2 < mz) stash((z + 2) % 3);
+    __syncthreads();
+    if (z + 3 < mz) fetch(z + 3);
+  }
+}
+
+#define SPP_INST(TW, ST)                                                                                        \
+  template __global__ void k_spmm_planes<TW, ST>(const BoxMeta*, int, int, int, const ST*, const uint8_t*,      \
+                                                 const double*, const double*, double*, double*, int, int, double, \
+                                                 const int32_t*);
+SPP_INST(false, double)
+SPP_INST(true, double)
+SPP_INST(false, float)
+SPP_INST(true, float)
+
 // out = X with the rows of B3 DoFs cleared (flat over all boxes' [n_dof][k] blocks)
 __global__ void k_mask_b3(const uint8_t* __restrict__ cls, const double* __restrict__ X, int k, int64_t n,
                           double* __restrict__ out) {

@@ -117,6 +117,87 @@ def test_apply_parity_small_bands(torch, n, core, overlap, ovs):
     _apply_check(torch, prob, list(prob.batch)[:8])
 
 
+# Batches of 16 boxes or more take the LDS-staged plane sweep of the stencil
+# products: 16 boxes of 9^3 nodes (whole planes in LDS) against the dense
+# oracle, every operator.
+def test_apply_parity_plane_sweep(torch):
+    say("[apply plane sweep] 16 boxes of 9^3 nodes")
+    prob = synth.uniform_batch(n_boxes=16, core=4, overlap=1, ovs=1, n_ev=4)
+    _apply_check(torch, prob, list(prob.batch)[:16])
+
+
+def _oracle_rows(prob, j, kec, nodes, xb, mu1, keep):
+    """Rows (3 per node) of A x~ and of D A D x~ for the sampled nodes of box
+    Omega*_j, from the element matrices of the elements around each node
+    (x~ = x with the B3 rows cleared; D = diag(mu on B1))."""
+    elo, ehi = prob.omega_star_box(j)
+    mx, my = int(ehi[0] - elo[0]) + 1, int(ehi[1] - elo[1]) + 1
+    xt = xb * keep[:, None]
+    y0 = np.zeros((len(nodes), 3, xb.shape[1]))
+    y1 = np.zeros_like(y0)
+    for r, node in enumerate(nodes):
+        li, lj, lk = node % mx, (node // mx) % my, node // (mx * my)
+        for ek in (lk - 1, lk):
+            for ej in (lj - 1, lj):
+                for ei in (li - 1, li):
+                    gi, gj, gk = elo[0] + ei, elo[1] + ej, elo[2] + ek
+                    if not (elo[0] <= gi < ehi[0] and elo[1] <= gj < ehi[1] and elo[2] <= gk < ehi[2]):
+                        continue
+                    Ke = kec(int(gi), int(gj), int(gk))
+                    loc = []
+                    for a in range(8):
+                        n2 = (ei + (a & 1)) + mx * ((ej + ((a >> 1) & 1)) + my * (ek + ((a >> 2) & 1)))
+                        loc.extend([3 * n2, 3 * n2 + 1, 3 * n2 + 2])
+                    loc = np.array(loc)
+                    a_me = (li - ei) + 2 * (lj - ej) + 4 * (lk - ek)
+                    rows = Ke[3 * a_me:3 * a_me + 3]
+                    y0[r] += rows @ xt[loc]
+                    y1[r] += rows @ (mu1[loc][:, None] * xt[loc])
+        dof = 3 * node + np.arange(3)
+        y0[r] *= keep[dof][:, None]
+        y1[r] *= mu1[dof][:, None]
+    return y0, y1
+
+
+# Planes of 19 x 19 nodes exceed one LDS tile: the sweep splits them into
+# x-tiles of 10 and 9 node columns with a halo column each side.  Sampled
+# rows (corners, faces, both sides of the tile seam, random nodes) against
+# the oracle's element matrices.
+def test_stencil_rows_tiled_planes(torch):
+    from paper_2211_13893_amd import msgfem
+    say("[apply plane sweep, x-tiles] 16 boxes of 19^3 nodes, sampled rows")
+    prob = synth.uniform_batch(n_boxes=16, core=12, overlap=1, ovs=2, n_ev=4)
+    st = _stage(torch, prob)
+    st.msgfem_assemble_local()
+    x = st.new_block()
+    x.normal_(generator=torch.Generator(device="cuda:0").manual_seed(21))
+    y0 = st.msgfem_local_apply(0, x)
+    y1 = st.msgfem_local_apply(1, x)
+    torch.cuda.synchronize()
+    kec = fem.KeCache(prob)
+    rng = np.random.default_rng(3)
+    for b in (0, 5, 15):
+        j = int(prob.batch[b])
+        bi = st.boxes[b]
+        mx, my, mz = bi.mx, bi.my, bi.mz
+        assert mx * my > 240
+        pick = [(0, 0, 0), (mx - 1, my - 1, mz - 1), (mx - 1, 0, mz // 2)]
+        for sx in (9, 10, 11):   # the seam between the x-tiles
+            pick += [(sx, int(rng.integers(my)), int(rng.integers(mz))) for _ in range(3)]
+        pick += [tuple(int(rng.integers(n)) for n in (mx, my, mz)) for _ in range(12)]
+        nodes = [i + mx * (jj + my * kk) for i, jj, kk in pick]
+        cls = decomp.dof_classes(prob, j)
+        mu1 = decomp.pou_dofs(prob, j) * (cls == 1)
+        xb = st.box_vector(x, b).cpu().numpy()
+        r0, r1 = _oracle_rows(prob, j, kec, nodes, xb, mu1, cls != 3)
+        g0 = st.box_vector(y0, b).cpu().numpy().reshape(-1, 3, st.k)[nodes]
+        g1 = st.box_vector(y1, b).cpu().numpy().reshape(-1, 3, st.k)[nodes]
+        e0 = np.abs(g0 - r0).max() / np.abs(r0).max()
+        e1 = np.abs(g1 - r1).max() / max(np.abs(r1).max(), 1e-300)
+        say(f"  box {b} ({mx}x{my}x{mz} nodes): {len(nodes)} nodes, A x rel err {e0:.2e}, DAD x rel err {e1:.2e}")
+        assert e0 <= 1e-12 and e1 <= 1e-12
+
+
 # Bands of 10-17 and 26-33 tiles (2 and 4 tile slots per wavefront of the
 # matrix-core solve) on boxes too large for dense oracle solves: the solves
 # are checked through the stencil products, themselves checked against the
