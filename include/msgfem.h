@@ -180,11 +180,20 @@ int msgfem_plan_box(const msgfem_plan *plan, int32_t b, msgfem_box_info *out);
  *   MSGFEM_OPT_SOLVE: the block-solve family (for both matrices): 0 (default)
  *     = the widest that fits, 1 = vector FMA (bands up to 65 tiles), 2 =
  *     matrix cores, 8 columns per workgroup (v_mfma_f64_4x4x4f64, bands up to
- *     33 tiles), 3 = matrix cores, 16 columns per workgroup
+ *     41 tiles), 3 = matrix cores, 16 columns per workgroup
  *     (v_mfma_f64_16x16x4f64, bands up to 31 tiles); a family the bands do not
  *     fit falls back to the next one down.  It fixes the layout of the factor
  *     copies, so set it before msgfem_assemble_local.  Results agree up to
  *     rounding.
+ *   MSGFEM_OPT_SPMM: the kernel of the stencil products A X and D A D X on
+ *     blocks of whole 8-column groups: 0 (default) = the LDS-staged plane
+ *     sweep (a workgroup per box and 8 columns marches through the box's
+ *     node planes with three planes of X in LDS) when the batch has at least
+ *     256 such workgroups and every node plane fits one LDS tile of 240
+ *     nodes, else one thread per node and 8 columns reading X through the
+ *     caches; 1 = always the latter; 2 = the plane sweep wherever it applies,
+ *     wider planes split into x-tiles.
+ *     Results agree up to rounding; it can change between calls.
  * msgfem_plan_set_option returns MSGFEM_EARG for an unknown key or value.
  * msgfem_plan_get_option reads an option or one of the counters of the last
  * msgfem_local_eigs call: MSGFEM_INFO_GRAPH_LAUNCHES (graph launches),
@@ -196,6 +205,7 @@ int msgfem_plan_box(const msgfem_plan *plan, int32_t b, msgfem_box_info *out);
 #define MSGFEM_OPT_GRAPH 1
 #define MSGFEM_OPT_SPLIT 2
 #define MSGFEM_OPT_SOLVE 3
+#define MSGFEM_OPT_SPMM 4
 #define MSGFEM_INFO_GRAPH_LAUNCHES 100
 #define MSGFEM_INFO_GRAPH_ITERS 101
 #define MSGFEM_INFO_GRAPHS_CACHED 102

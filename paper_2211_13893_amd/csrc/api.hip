@@ -176,6 +176,7 @@ struct msgfem_plan {
   // nested dissection of the box matrices (MSGFEM_OPT_SPLIT)
   int split = 1;
   int solve_pref = 0;            // MSGFEM_OPT_SOLVE
+  int spmm_pref = 0;             // MSGFEM_OPT_SPMM
   bool any_split[2] = {false, false};
   int max_nts = 0;               // separator tile rows
   int n_chain_mats = 0;          // mats[0 .. n_chain_mats): whole bands and chains; then the separator blocks
@@ -1015,6 +1016,10 @@ static void lds_attributes() {
       (const void*)k_band_solve4<1, true, float>,   (const void*)k_band_solve4<2, true, float>,
       (const void*)k_band_solve4<3, true, float>,   (const void*)k_band_solve4<4, true, float>};
   for (const void* f : solves4) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_band_solve4<5, false, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_band_solve4<5, false, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_update<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   const void* spp[] = {(const void*)k_spmm_planes<false, double>, (const void*)k_spmm_planes<true, double>,
@@ -1046,10 +1051,13 @@ static int spmm(Ctx& c, const double* X, double* Y, double* Y2, int kk, int ycla
     fl += 2.0 * 243 * m.n_nodes * kk * (Y2 ? 2 : 1);
   }
   ProfScope ps(c.p, PK_SPMM, c.s, by, fl, !c.no_alloc);
-  // a batch of boxes and a block of whole 8-column groups: the LDS-staged
-  // plane sweep (every box's plane tile must fit)
+  // blocks of whole 8-column groups: the LDS-staged plane sweep, by default
+  // (MSGFEM_OPT_SPMM 0) when the batch gives every CU a workgroup (boxes x
+  // column groups >= 256) and each node plane fits one LDS tile, on request
+  // (2) wherever it applies, with x-tiles for wider planes
   int max_tiles = 0;
-  if (kk % 8 == 0 && c.nb >= 16) {
+  const int pref = c.p->spmm_pref;
+  if (kk % 8 == 0 && pref != 1 && (pref == 2 || (int64_t)c.nb * (kk / 8) >= 256)) {
     for (int b = 0; b < c.nb; ++b) {
       const BoxMeta& m = c.p->meta[b];
       const int tx = sp_tile_x_host(m.mx, m.my);
@@ -1059,6 +1067,7 @@ static int spmm(Ctx& c, const double* X, double* Y, double* Y2, int kk, int ycla
       }
       max_tiles = std::max(max_tiles, (m.mx + tx - 1) / tx);
     }
+    if (pref == 0 && max_tiles > 1) max_tiles = 0;
   }
   if (max_tiles > 0) {
     const int ng = kk / 8;
@@ -1129,7 +1138,8 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
     }
   };
   if (solve4_kind(c.p, kind)) {
-    // bands of at most 33 tiles: the matrix-core solve, 1..4 tile slots per wavefront
+    // bands of at most 41 tiles: the matrix-core solve, 1..5 tile slots per
+    // wavefront (5 with 8 columns only: the 16-column solve takes <= 31 tiles)
     const int ns = solve4_nslot(c.p->max_bt_kind[kind]);
     auto pick = [&](auto wide_tag, auto ft) {
       constexpr bool W = decltype(wide_tag)::value;
@@ -1137,7 +1147,8 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
       if (ns <= 1) launch(k_band_solve4<1, W, FT>, ft);
       else if (ns == 2) launch(k_band_solve4<2, W, FT>, ft);
       else if (ns == 3) launch(k_band_solve4<3, W, FT>, ft);
-      else launch(k_band_solve4<4, W, FT>, ft);
+      else if (ns == 4 || W) launch(k_band_solve4<4, W, FT>, ft);
+      else if constexpr (!W) launch(k_band_solve4<5, false, FT>, ft);
     };
     if (f32) {
       const float* f = (const float*)c.v.fac32;
@@ -1759,6 +1770,13 @@ extern "C" int msgfem_plan_set_option(msgfem_plan* p, int32_t key, int64_t value
       for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
       p->graphs.clear();
       return MSGFEM_OK;
+    case MSGFEM_OPT_SPMM:
+      if (value < 0 || value > 2) return fail(p, MSGFEM_EARG, "MSGFEM_OPT_SPMM takes 0 .. 2, not %lld",
+                                             (long long)value);
+      p->spmm_pref = (int)value;
+      for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+      p->graphs.clear();
+      return MSGFEM_OK;
     default:
       return fail(p, MSGFEM_EARG, "unknown plan option %d", key);
   }
@@ -1770,6 +1788,7 @@ extern "C" int msgfem_plan_get_option(const msgfem_plan* p, int32_t key, int64_t
     case MSGFEM_OPT_GRAPH: *value = p->graph_mode; return MSGFEM_OK;
     case MSGFEM_OPT_SPLIT: *value = p->split; return MSGFEM_OK;
     case MSGFEM_OPT_SOLVE: *value = p->solve_pref; return MSGFEM_OK;
+    case MSGFEM_OPT_SPMM: *value = p->spmm_pref; return MSGFEM_OK;
     case MSGFEM_INFO_MAX_BT_A11: *value = p->max_bt_kind[0]; return MSGFEM_OK;
     case MSGFEM_INFO_MAX_BT_AHAT: *value = p->max_bt_kind[1]; return MSGFEM_OK;
     case MSGFEM_INFO_SOLVE_FAMILY:
@@ -2728,7 +2747,8 @@ static int solve_f32(hipStream_t s, const BoxMeta* meta, int nb, int max_bt, boo
     if (ns <= 1) launch(k_band_solve4<1, false, float>);
     else if (ns == 2) launch(k_band_solve4<2, false, float>);
     else if (ns == 3) launch(k_band_solve4<3, false, float>);
-    else launch(k_band_solve4<4, false, float>);
+    else if (ns == 4) launch(k_band_solve4<4, false, float>);
+    else launch(k_band_solve4<5, false, float>);
   } else if (max_bt - 1 > SOLVE_TILES) {
     launch(k_band_solve<KC, 2, float>);
   } else {

@@ -691,6 +691,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
 #define SOLVE4_INST_ALL(W, T) SOLVE4_INST(1, W, T) SOLVE4_INST(2, W, T) SOLVE4_INST(3, W, T) SOLVE4_INST(4, W, T)
 SOLVE4_INST_ALL(false, double)
 SOLVE4_INST_ALL(false, float)
+SOLVE4_INST(5, false, double)
+SOLVE4_INST(5, false, float)
 SOLVE4_INST_ALL(true, double)
 SOLVE4_INST_ALL(true, float)
 

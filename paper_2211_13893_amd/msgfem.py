@@ -68,6 +68,8 @@ class msgfem_kernel_stat(ctypes.Structure):
 OPT_GRAPH = 1
 OPT_SPLIT = 2
 OPT_SOLVE = 3
+OPT_SPMM = 4
+SPMM_AUTO, SPMM_NODES, SPMM_PLANES = 0, 1, 2   # values of OPT_SPMM
 INFO_GRAPH_LAUNCHES = 100
 INFO_GRAPH_ITERS = 101
 INFO_GRAPHS_CACHED = 102
@@ -190,7 +192,8 @@ class LocalStage:
                  n_ev: Optional[Sequence[int]] = None, device: str = "cuda:0", shift: float = 1.0,
                  tol: float = 1e-6, maxit: int = 200, block: int = 0, seed: int = 1234,
                  geneo: bool = False, precision: int = 0, graph: Optional[bool] = None,
-                 split: Optional[bool] = None, solve: Optional[int] = None, tuned: bool = False):
+                 split: Optional[bool] = None, solve: Optional[int] = None, tuned: bool = False,
+                 spmm: Optional[int] = None):
         import torch
         self.torch = torch
         lib = load()
@@ -240,11 +243,11 @@ class LocalStage:
                 # a GenEO coarse store fixes the interior band layout (default split and family)
                 table = {key: v for key, v in table.items() if key == "graph"}
             opts_set.update(table)
-        for key, val in (("split", split), ("solve", solve), ("graph", graph)):
+        for key, val in (("split", split), ("solve", solve), ("graph", graph), ("spmm", spmm)):
             if val is not None:
                 opts_set[key] = int(val)
         self.plan_options = dict(opts_set)
-        for key, code in (("split", OPT_SPLIT), ("solve", OPT_SOLVE), ("graph", OPT_GRAPH)):
+        for key, code in (("split", OPT_SPLIT), ("solve", OPT_SOLVE), ("graph", OPT_GRAPH), ("spmm", OPT_SPMM)):
             if key in opts_set:
                 _check(lib.msgfem_plan_set_option(plan, code, int(opts_set[key])), plan, "msgfem_plan_set_option")
         s = msgfem_sizes()

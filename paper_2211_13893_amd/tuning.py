@@ -4,7 +4,7 @@ A plan's block-solve work is set by the width of its widest band and by how
 many work units (boxes x 8-column chunks of the LOBPCG block) it spreads over
 the 256 CUs.  The size class buckets both:
 
-    widest Ahat band (tiles): <= 20, <= 24, <= 31, <= 33, <= 65
+    widest Ahat band (tiles): <= 20, <= 24, <= 31, <= 41, <= 65
     work units:               < 64, < 256, < 1024, >= 1024
 
 For each class the table (tuning.json, written by autotune.py from timed runs
@@ -24,7 +24,7 @@ import os
 from typing import Dict, Optional
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
-BT_EDGES = (20, 24, 31, 33, 65)
+BT_EDGES = (20, 24, 31, 41, 65)
 UNIT_EDGES = (64, 256, 1024)
 KEYS = ("split", "solve", "graph")
 

@@ -117,13 +117,13 @@ def test_apply_parity_small_bands(torch, n, core, overlap, ovs):
     _apply_check(torch, prob, list(prob.batch)[:8])
 
 
-# Batches of 16 boxes or more take the LDS-staged plane sweep of the stencil
-# products: 16 boxes of 9^3 nodes (whole planes in LDS) against the dense
-# oracle, every operator.
+# The LDS-staged plane sweep of the stencil products (MSGFEM_OPT_SPMM 2; the
+# default takes it on batches of 64+ boxes): 16 boxes of 9^3 nodes (whole
+# planes in LDS) against the dense oracle, every operator.
 def test_apply_parity_plane_sweep(torch):
     say("[apply plane sweep] 16 boxes of 9^3 nodes")
     prob = synth.uniform_batch(n_boxes=16, core=4, overlap=1, ovs=1, n_ev=4)
-    _apply_check(torch, prob, list(prob.batch)[:16])
+    _apply_check(torch, prob, list(prob.batch)[:16], spmm=2)
 
 
 def _oracle_rows(prob, j, kec, nodes, xb, mu1, keep):
@@ -159,15 +159,17 @@ def _oracle_rows(prob, j, kec, nodes, xb, mu1, keep):
     return y0, y1
 
 
-# Planes of 19 x 19 nodes exceed one LDS tile: the sweep splits them into
-# x-tiles of 10 and 9 node columns with a halo column each side.  Sampled
+# Planes of 19 x 19 nodes exceed one LDS tile: with MSGFEM_OPT_SPMM 2 the
+# sweep splits them into x-tiles of 10 and 9 node columns with a halo column
+# each side (by default such boxes take the per-node kernel).  Sampled
 # rows (corners, faces, both sides of the tile seam, random nodes) against
 # the oracle's element matrices.
 def test_stencil_rows_tiled_planes(torch):
     from paper_2211_13893_amd import msgfem
     say("[apply plane sweep, x-tiles] 16 boxes of 19^3 nodes, sampled rows")
     prob = synth.uniform_batch(n_boxes=16, core=12, overlap=1, ovs=2, n_ev=4)
-    st = _stage(torch, prob)
+    st = _stage(torch, prob, spmm=msgfem.SPMM_PLANES)
+    assert st.get_option(msgfem.OPT_SPMM) == 2
     st.msgfem_assemble_local()
     x = st.new_block()
     x.normal_(generator=torch.Generator(device="cuda:0").manual_seed(21))
@@ -198,11 +200,12 @@ def test_stencil_rows_tiled_planes(torch):
         assert e0 <= 1e-12 and e1 <= 1e-12
 
 
-# Bands of 10-17 and 26-33 tiles (2 and 4 tile slots per wavefront of the
-# matrix-core solve) on boxes too large for dense oracle solves: the solves
-# are checked through the stencil products, themselves checked against the
-# oracle above: (A + s D A D) y = x on B1 u B2 for op 3, (A y)_1 = x_1 for op 2.
-@pytest.mark.parametrize("core,ovs", [(6, 1), (10, 2)])
+# Bands of 10-17, 26-33 and 34-41 tiles (2, 4 and 5 tile slots per wavefront
+# of the matrix-core solve; 37-tile Ahat bands for core 12) on boxes too large
+# for dense oracle solves: the solves are checked through the stencil
+# products, themselves checked against the oracle above: (A + s D A D) y = x
+# on B1 u B2 for op 3, (A y)_1 = x_1 for op 2.
+@pytest.mark.parametrize("core,ovs", [(6, 1), (10, 2), (12, 2)])
 def test_solve_residual_wide_boxes(torch, core, ovs):
     say(f"[solve residual] core {core} ovs {ovs}")
     prob = synth.uniform_batch(n_boxes=2, core=core, overlap=1, ovs=ovs, n_ev=8)
@@ -232,8 +235,11 @@ def test_solve_residual_wide_boxes(torch, core, ovs):
         assert np.all(y2b[cls != 1] == 0.0)
 
 
-def _apply_check(torch, prob, batch):
-    st = _stage(torch, prob, batch=batch)
+def _apply_check(torch, prob, batch, **kw):
+    st = _stage(torch, prob, batch=batch, **kw)
+    if "spmm" in kw:
+        from paper_2211_13893_amd import msgfem
+        assert st.get_option(msgfem.OPT_SPMM) == kw["spmm"]
     st.msgfem_assemble_local()
     k = st.k
     rng = np.random.default_rng(5)

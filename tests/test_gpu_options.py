@@ -121,3 +121,31 @@ def test_eigs_tuned(torch, beam):
     st = msgfem.LocalStage(prob, tuned=True, tol=1e-9, maxit=400)
     say(f"[options] beam eigs, tuned: class {st.size_class}, options {st.plan_options}")
     _eigs(torch, st, dense, 10)
+
+
+def test_spmm_kernels_agree(torch):
+    """MSGFEM_OPT_SPMM: the per-node kernel (1, and 0 on a batch of 16
+    boxes) and the LDS-staged plane sweep (2) give the same stencil products
+    (relative 1e-13: FP64 sums in another order); the plane sweep itself is
+    checked against the oracle in test_gpu_local."""
+    from paper_2211_13893_amd import msgfem
+    say("[options] spmm kernels, 16 boxes of 9^3 nodes")
+    prob = synth.uniform_batch(n_boxes=16, core=4, overlap=1, ovs=1, n_ev=4)
+    st = msgfem.LocalStage(prob)
+    assert st.get_option(msgfem.OPT_SPMM) == 0
+    st.msgfem_assemble_local()
+    x = st.new_block()
+    x.normal_(generator=torch.Generator(device="cuda:0").manual_seed(4))
+    out = {}
+    for pref in (1, 2, 0):
+        st.set_option(msgfem.OPT_SPMM, pref)
+        out[pref] = [st.msgfem_local_apply(op, x).clone() for op in (0, 1)]
+    torch.cuda.synchronize()
+    for pref in (2, 0):
+        for op in (0, 1):
+            ref = out[1][op]
+            e = float((out[pref][op] - ref).abs().max() / ref.abs().max())
+            say(f"  spmm {pref} vs 1, op {op}: rel {e:.2e}")
+            assert e <= 1e-13
+    with pytest.raises(msgfem.MsgfemError):
+        st.set_option(msgfem.OPT_SPMM, 3)
