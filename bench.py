@@ -224,7 +224,8 @@ def c4_leg(n_train_seeds=79, n_held_seeds=16, n_boxes=256, steps=2000):
             "max_nu_rel_diff": ev["max_nu_rel_diff"], "all_converged": ev["all_converged"],
             "ceiling_first_held_batch": {"iters_random": it_rand_first, **{f"iters_{k}": v for k, v in ceil.items()}},
             "network": "4 conv3d 3^3 (6->32->32->32->32, strides 1,1,2,2, ReLU), mean pool, affine 32 -> 48*16; "
-                       "BF16 storage, FP32 sums (vector FMA kernels)"}
+                       "BF16 storage, FP32 sums; forward convolutions on the BF16 matrix cores, backward on "
+                       "FP32 FMA kernels"}
 
 
 def main():
