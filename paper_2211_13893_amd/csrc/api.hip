@@ -25,7 +25,9 @@ __global__ void k_band_build(const BoxMeta*, int, const double*, const uint8_t*,
                              double*);
 __global__ void k_chol_update(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_panel(const MatDesc*, int, double*);
+template <int P>
 __global__ void k_chol_step(const MatDesc*, int, double*, int32_t*);
+#define CHOL_PANEL 4   // panel columns of the tile Cholesky (k_chol_step<P>)
 __global__ void k_chol_unit(const MatDesc*, double*);
 __global__ void k_band_unit_relayout4(const BoxMeta*, int, double*, int);
 __global__ void k_band_relayout(const BoxMeta*, int, double*);
@@ -795,7 +797,7 @@ static int tile_trsv(const double* T, int NT, int NH, const double* b, double* y
 static int band_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int last_J, int max_nt, int max_bt,
                          double* fac, int32_t* status, bool unit, hipStream_t s) {
   for (int J = -1; J <= last_J; ++J)
-    k_chol_step<<<dim3(nmat, (max_bt + 1 + 3) / 4), 256, 0, s>>>(mats, J, fac, status);
+    k_chol_step<CHOL_PANEL><<<dim3(nmat, (chol_jobs(CHOL_PANEL, max_bt) + 3) / 4), 256, 0, s>>>(mats, J, fac, status);
   if (unit) k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
   LAUNCHCHK(p);
   return 0;

@@ -477,11 +477,30 @@ __device__ int factor_tile32(const double* __restrict__ C, double* __restrict__ 
   return bad;
 }
 
-// grid (n_mat, ceil((max BT + 1) / 4)), 256 threads: job = 4 blockIdx.y +
+// One step J of the left-looking tile Cholesky, with the products that read
+// only final tiles gathered into panels of P columns.  Step J completes
+// column J (L(I,J) for the band rows I > J) and factors the diagonal tile
+// J+1.  At a panel step (J + 1 divisible by P, J = -1 included) the products
+// L(I,K) L(c,K)^T with K <= J-1 are subtracted from the next P columns
+// c = J+1 .. J+P in one pass over the band window (each tile L(I,K) read
+// once for P columns): for the diagonal tiles J+2 .. J+P+1 and for the rows'
+// tiles (I, c), c < I.  The products with K between the last panel step and
+// J-1 (at most P) are taken where column J or the diagonal tile J+1 is
+// formed.  Jobs (one wavefront each): 0, the chain of the step (X^T of
+// L(J+1,J), its triangular solve, the diagonal tile J+1's remaining products
+// and its one-wavefront Cholesky and inverse); 1 .. P, the panel products of
+// the diagonal tiles; then per band row I = J + s (s >= 2) and pair g of
+// panel columns, the triangular solve for L(I,J) (g = 0) and the panel
+// products of columns J+1+2g, J+2+2g.
+// grid (n_mat, ceil(chol_jobs / 4)), 256 threads: job = 4 blockIdx.y +
 // wavefront; blockIdx.x is the matrix, so the step's chain (job 0) of every
 // matrix and the longest rows are dispatched first.
+
+template <int P>
 __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict__ mats, int J,
                                                       double* __restrict__ fac, int32_t* __restrict__ status) {
+  static_assert(P >= 2 && P % 2 == 0, "panel columns come in pairs");
+  constexpr int G = P / 2;
   __shared__ __align__(16) double X[32 * CH_LD];
   __shared__ __align__(16) double Y[32 * CH_LD];
   __shared__ double dinv[32], vec[32];
@@ -497,39 +516,44 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
   auto tile = [&](int I, int K) { return L + ((int64_t)I * BT + (I - K)) * MSG_TILE2; };
   const double* LinvJ = fac + v.ioff + (int64_t)(J < 0 ? 0 : J) * MSG_TILE2;
   const dbl4 zero = {0.0, 0.0, 0.0, 0.0};
-  const bool pair = (J & 1) != 0;
+  const bool panel = ((J + 1) % P) == 0;
+  // the last panel step before J (its products reached column J)
+  const int Jb = J >= 0 ? (J / P) * P - 1 : -1;
   dbl4 acc[2][2], xt[2][2], lt[2][2];
+  auto zero4 = [&](dbl4 (&a)[2][2]) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) a[bi][bj] = zero;
+  };
+  // X^T = A(I,J)^T - sum_{K = max(Jb, kb) .. J-1} L(J,K) L(I,K)^T, then
+  // L(I,J) = X L_JJ^{-T} stored, L(I,J)^T returned in lt
+  auto column_tile = [&](int I, int kb) {
+    zero4(xt);
+    for (int K = max(Jb, kb); K <= J - 1; ++K) {
+      TileOps a, b;
+      tops_load(tile(J, K), lane, a);
+      tops_load(tile(I, K), lane, b);
+      tops_abt(a, b, xt);
+    }
+    double* T = tile(I, J);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) xt[bi][bj] = quadT_get(T, bi, bj, lane) - xt[bi][bj];
+    trsm_from_xt(LinvJ, xt, T, lt, lane);
+  };
 
   if (job == 0) {
     const int R = J + 1;
     if (R > NT - 1) return;
     const bool diag = R < NF;                // the diagonal tile R is factored here
-    const bool has_x = J >= 0 && BT >= 2;    // tile (R, J) exists
-    const bool has_k = J >= 1 && BT >= 3;    // tiles (R, J-1), (J, J-1) exist
-    // first K of the diagonal tile's remaining products
-    const int kd = max(max(0, R - (BT - 1)), pair ? J - 2 : J - 1);
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = zero;
+    const int kbR = max(0, R - (BT - 1));
+    const bool has_x = J >= 0 && BT >= 2;   // tile (R, J) exists
+    if (has_x) column_tile(R, kbR);
+    if (!diag) return;
+    zero4(acc);
     if (has_x) {
-      // X^T = A(R,J)^T - L(J,J-1) L(R,J-1)^T
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) xt[bi][bj] = zero;
-      if (has_k) {
-        TileOps a, b;
-        tops_load(tile(J, J - 1), lane, a);
-        tops_load(tile(R, J - 1), lane, b);
-        tops_abt(a, b, xt);
-      }
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) xt[bi][bj] = quadT_get(tile(R, J), bi, bj, lane) - xt[bi][bj];
-      trsm_from_xt(LinvJ, xt, tile(R, J), lt, lane);
-      if (!diag) return;
       // + L(R,J) L(R,J)^T: the accumulators of L^T serve as both operands
 #pragma unroll
       for (int bk = 0; bk < 2; ++bk)
@@ -541,8 +565,8 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
             for (int bj = 0; bj < 2; ++bj)
               acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(lt[bk][bi][w], lt[bk][bj][w], acc[bi][bj], 0, 0, 0);
     }
-    if (!diag) return;
-    for (int K = kd; K <= J - 1; ++K) {
+    // the diagonal tile R received the products K <= Jb - 1 at step Jb
+    for (int K = max(kbR, Jb); K <= J - 1; ++K) {
       TileOps a;
       tops_load(tile(R, K), lane, a);
       tops_abt<true>(a, a, acc);
@@ -558,15 +582,13 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
     if (lane == 0 && bad) atomicOr(&status[v.status_idx], 4);
     return;
   }
-  if (job <= 2) {
+  if (job <= P) {
+    // panel products of the diagonal tiles J+2 .. J+P+1
     const int R = J + 1 + job;
-    if (!pair || R > NT - 1 || R >= NF) return;
+    if (!panel || R > NT - 1 || R >= NF) return;
     const int k0 = max(0, R - (BT - 1)), k1 = J - 1;
     if (k0 > k1) return;
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = zero;
+    zero4(acc);
     for (int K = k1; K >= k0; --K) {
       TileOps a;
       tops_load(tile(R, K), lane, a);
@@ -580,68 +602,50 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
         if (bi >= bj) quad_put(T, 32, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - acc[bi][bj]);
     return;
   }
-  const int s = job - 1, I = J + s;
+  const int r = job - 1 - P;
+  const int s = 2 + r / G, g = r % G, I = J + s;
   if (J < 0 || s > BT - 1 || I > NT - 1) return;
-  const int k1 = J - 1, kb = max(0, I - (BT - 1));   // K range of row I's final tiles: [kb, J-1]
-  // L(I,J) from X^T = A(I,J)^T - L(J,J-1) L(I,J-1)^T
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) xt[bi][bj] = zero;
-  if (kb <= k1) {
-    TileOps a, b;
-    tops_load(tile(J, J - 1), lane, a);
-    tops_load(tile(I, J - 1), lane, b);
-    tops_abt(a, b, xt);
-  }
-  {
-    double* T = tile(I, J);
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) xt[bi][bj] = quadT_get(T, bi, bj, lane) - xt[bi][bj];
-    trsm_from_xt(LinvJ, xt, T, lt, lane);
-  }
-  if (kb > k1 || J + 1 >= NF) return;
-  // the next column(s): odd J all final products, even J the one with K = J-1
-  const int k0 = pair ? kb : k1;
-  const bool two = pair && s >= 3 && J + 2 < NF;
+  const int kb = max(0, I - (BT - 1));   // K range of row I's band tiles: [kb, I]
+  if (g == 0) column_tile(I, kb);
+  if (!panel) return;
+  // panel products of columns c0 = J+1+2g and c0+1 (those before row I)
+  const int c0 = J + 1 + 2 * g;
+  const int k1 = J - 1;
+  if (kb > k1 || c0 >= NF || c0 >= I) return;
+  const bool two = c0 + 1 < NF && c0 + 1 < I;
   dbl4 acc2[2][2];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      acc[bi][bj] = zero;
-      acc2[bi][bj] = zero;
-    }
+  zero4(acc);
+  zero4(acc2);
   if (two) {
-    for (int K = k1; K >= k0; --K) {
+    for (int K = k1; K >= kb; --K) {
       TileOps a, b, c;
       tops_load(tile(I, K), lane, a);
-      tops_load(tile(J + 1, K), lane, b);
-      tops_load(tile(J + 2, K), lane, c);
+      tops_load(tile(c0, K), lane, b);
+      tops_load(tile(c0 + 1, K), lane, c);
       tops_abt(a, b, acc);
       tops_abt(a, c, acc2);
     }
-    double* T2 = tile(I, J + 2);
+    double* T2 = tile(I, c0 + 1);
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) quad_put(T2, 32, bi, bj, lane, quad_get(T2, 32, bi, bj, lane) - acc2[bi][bj]);
   } else {
-    for (int K = k1; K >= k0; --K) {
+    for (int K = k1; K >= kb; --K) {
       TileOps a, b;
       tops_load(tile(I, K), lane, a);
-      tops_load(tile(J + 1, K), lane, b);
+      tops_load(tile(c0, K), lane, b);
       tops_abt(a, b, acc);
     }
   }
-  double* T1 = tile(I, J + 1);
+  double* T1 = tile(I, c0);
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) quad_put(T1, 32, bi, bj, lane, quad_get(T1, 32, bi, bj, lane) - acc[bi][bj]);
 }
+template __global__ void k_chol_step<2>(const MatDesc*, int, double*, int32_t*);
+template __global__ void k_chol_step<4>(const MatDesc*, int, double*, int32_t*);
 
 // The separator's Schur complement of a split matrix, once both chains are
 // factored on their own columns:
