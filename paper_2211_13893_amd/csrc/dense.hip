@@ -28,7 +28,7 @@ struct Blk3 {
 };
 
 #define GR_ROWS 32
-#define UPD_DEPTH 4    // MFMA steps (4 inner indices each) whose A operands are requested ahead
+#define UPD_DEPTH 2    // MFMA step pairs (8 inner indices each) whose A operands are requested ahead
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -547,9 +547,15 @@ struct Out4 {
 // Z = [Z_0 .. Z_{nblk-1}] of m = nblk*k columns, Y and Yp m x k per box.
 // FP64 matrix cores (16x16x4): a wavefront takes 16 rows at a time (4 blocks
 // of 16 rows per wavefront, UPD_ROWS rows per workgroup); the inner index
-// runs over the m columns of Z in steps of 4, the output columns in CB blocks
-// of 16 (k <= 16 CB: 2 for the LOBPCG block, 6 for a coarse basis of up to
-// 96 columns); Y and Yp are staged in LDS once per workgroup.
+// runs over the m columns of Z, 8 per pair of MFMA steps: lane (row li,
+// lk) loads Z[row][8t + 2lk .. +1] as one 16-byte piece and uses its halves
+// in steps 2t and 2t+1 (inner index 8t + 2lk + e), and the B operand is
+// read to match.  Output columns in CB blocks of 16 (k <= 16 CB: 2 for the
+// LOBPCG block, 6 for a coarse basis of up to 96 columns); Y and Yp are
+// staged in LDS once per workgroup, for k = 32 with the two 16-column halves
+// of a row swapped on every other pair of rows (element (i, c) at column
+// c ^ 16 when bit 1 of i is set), so the four inner-index lanes groups of a
+// read fall on two bank halves, not one.
 // grid (ceil(max n_dof / UPD_ROWS), n_box, kinds); dynamic LDS = 2*m*k doubles
 template <int CB>
 __global__ __launch_bounds__(UPD_THREADS, CB == 2 ? 3 : 1) void k_update(const BoxMeta* __restrict__ meta, int nblk, int k,
@@ -565,17 +571,20 @@ __global__ __launch_bounds__(UPD_THREADS, CB == 2 ? 3 : 1) void k_update(const B
   const int r_wg = blockIdx.x * UPD_ROWS;
   if (r_wg >= bm.n_dof) return;
   const int m = nblk * k;
+  const int swz = k == 32 ? 16 : 0;
+  auto yix = [&](int i, int c) { return i * k + (c ^ (((i >> 1) & 1) ? swz : 0)); };
   double* ys = sm;
   double* yps = sm + m * k;
   const bool wantP = OP.p[kind] != nullptr;
   for (int t = threadIdx.x; t < m * k; t += UPD_THREADS) {
-    ys[t] = Y[(int64_t)box * m * k + t];
-    yps[t] = wantP ? Yp[(int64_t)box * m * k + t] : 0.0;
+    const int i = t / k, c = t - i * k;
+    ys[yix(i, c)] = Y[(int64_t)box * m * k + t];
+    yps[yix(i, c)] = wantP ? Yp[(int64_t)box * m * k + t] : 0.0;
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int nsteps = (m + 3) >> 2;
+  const int npairs = (m + 7) >> 3;
   const int64_t base = bm.dof_off * k;
   for (int rb = 0; rb < 4; ++rb) {
     const int r0 = r_wg + (wave * 4 + rb) * 16;
@@ -588,42 +597,46 @@ __global__ __launch_bounds__(UPD_THREADS, CB == 2 ? 3 : 1) void k_update(const B
       ax[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
       ap[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
     }
-    // A operand of step st (inner index i = 4 st + lk: block i / k, column
-    // i % k; k is a multiple of 8).  Two register sets of UPD_DEPTH steps: the
+    // A operands of step pair t (inner indices 8t + 2lk, +1: one block, k
+    // being a multiple of 8).  Two register sets of UPD_DEPTH pairs: the
     // next set is requested before the current one is multiplied.
-    auto load_a = [&](int st) {
-      const int i = 4 * st + lk;
-      double a = 0.0;
-      if (st < nsteps && rok && i < m) {
+    auto load_a = [&](int t) {
+      const int i = 8 * t + 2 * lk;
+      double2 a = double2{0.0, 0.0};
+      if (t < npairs && rok && i < m) {
         const int b = i / k;
-        a = Z.p[kind][b][base + (int64_t)row * k + (i - b * k)];
+        a = *(const double2*)(Z.p[kind][b] + base + (int64_t)row * k + (i - b * k));
       }
       return a;
     };
-    auto mma = [&](int st, double a) {
-      if (st < nsteps) {
-        const int i = 4 * st + lk;
+    auto mma = [&](int t, double2 a) {
+      if (t < npairs) {
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          const int col = 16 * cb + li;
-          const bool ok = i < m && col < k;
-          ax[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ok ? ys[i * k + col] : 0.0, ax[cb], 0, 0, 0);
-          if (wantP) ap[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ok ? yps[i * k + col] : 0.0, ap[cb], 0, 0, 0);
+        for (int e = 0; e < 2; ++e) {
+          const int i = 8 * t + 2 * lk + e;
+          const double av = e ? a.y : a.x;
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            const int col = 16 * cb + li;
+            const bool ok = i < m && col < k;
+            ax[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ok ? ys[yix(i, col)] : 0.0, ax[cb], 0, 0, 0);
+            if (wantP) ap[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ok ? yps[yix(i, col)] : 0.0, ap[cb], 0, 0, 0);
+          }
         }
       }
     };
-    double pa[UPD_DEPTH], pb[UPD_DEPTH];
+    double2 pa[UPD_DEPTH], pb[UPD_DEPTH];
 #pragma unroll
     for (int j = 0; j < UPD_DEPTH; ++j) pa[j] = load_a(j);
-    for (int st = 0; st < nsteps; st += 2 * UPD_DEPTH) {
+    for (int t = 0; t < npairs; t += 2 * UPD_DEPTH) {
 #pragma unroll
-      for (int j = 0; j < UPD_DEPTH; ++j) pb[j] = load_a(st + UPD_DEPTH + j);
+      for (int j = 0; j < UPD_DEPTH; ++j) pb[j] = load_a(t + UPD_DEPTH + j);
 #pragma unroll
-      for (int j = 0; j < UPD_DEPTH; ++j) mma(st + j, pa[j]);
+      for (int j = 0; j < UPD_DEPTH; ++j) mma(t + j, pa[j]);
 #pragma unroll
-      for (int j = 0; j < UPD_DEPTH; ++j) pa[j] = load_a(st + 2 * UPD_DEPTH + j);
+      for (int j = 0; j < UPD_DEPTH; ++j) pa[j] = load_a(t + 2 * UPD_DEPTH + j);
 #pragma unroll
-      for (int j = 0; j < UPD_DEPTH; ++j) mma(st + UPD_DEPTH + j, pb[j]);
+      for (int j = 0; j < UPD_DEPTH; ++j) mma(t + UPD_DEPTH + j, pb[j]);
     }
     // accumulator item v of lane l: row r0 + (l >> 4) + 4 v, column 16 cb + (l & 15)
     double* ox = OX.p[kind] + base;
