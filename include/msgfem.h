@@ -180,7 +180,7 @@ int msgfem_plan_box(const msgfem_plan *plan, int32_t b, msgfem_box_info *out);
  *   MSGFEM_OPT_SOLVE: the block-solve family (for both matrices): 0 (default)
  *     = the widest that fits, 1 = vector FMA (bands up to 65 tiles), 2 =
  *     matrix cores, 8 columns per workgroup (v_mfma_f64_4x4x4f64, bands up to
- *     41 tiles), 3 = matrix cores, 16 columns per workgroup
+ *     65 tiles), 3 = matrix cores, 16 columns per workgroup
  *     (v_mfma_f64_16x16x4f64, bands up to 31 tiles); a family the bands do not
  *     fit falls back to the next one down.  It fixes the layout of the factor
  *     copies, so set it before msgfem_assemble_local.  Results agree up to

@@ -1022,6 +1022,10 @@ static void lds_attributes() {
                             160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_band_solve4<5, false, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_band_solve4<8, false, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_band_solve4<8, false, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_update<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   const void* spp[] = {(const void*)k_spmm_planes<false, double>, (const void*)k_spmm_planes<true, double>,
@@ -1140,8 +1144,9 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
     }
   };
   if (solve4_kind(c.p, kind)) {
-    // bands of at most 41 tiles: the matrix-core solve, 1..5 tile slots per
-    // wavefront (5 with 8 columns only: the 16-column solve takes <= 31 tiles)
+    // bands of at most 65 tiles: the matrix-core solve, 1..5 tile slots per
+    // wavefront, 6..8 as two sets of four (8 columns only beyond 4 slots:
+    // the 16-column solve takes <= 31 tiles)
     const int ns = solve4_nslot(c.p->max_bt_kind[kind]);
     auto pick = [&](auto wide_tag, auto ft) {
       constexpr bool W = decltype(wide_tag)::value;
@@ -1150,7 +1155,10 @@ static int solve(Ctx& c, int kind, const double* in, double* out, int kk, int ou
       else if (ns == 2) launch(k_band_solve4<2, W, FT>, ft);
       else if (ns == 3) launch(k_band_solve4<3, W, FT>, ft);
       else if (ns == 4 || W) launch(k_band_solve4<4, W, FT>, ft);
-      else if constexpr (!W) launch(k_band_solve4<5, false, FT>, ft);
+      else if constexpr (!W) {
+        if (ns == 5) launch(k_band_solve4<5, false, FT>, ft);
+        else launch(k_band_solve4<8, false, FT>, ft);
+      }
     };
     if (f32) {
       const float* f = (const float*)c.v.fac32;
@@ -2750,7 +2758,8 @@ static int solve_f32(hipStream_t s, const BoxMeta* meta, int nb, int max_bt, boo
     else if (ns == 2) launch(k_band_solve4<2, false, float>);
     else if (ns == 3) launch(k_band_solve4<3, false, float>);
     else if (ns == 4) launch(k_band_solve4<4, false, float>);
-    else launch(k_band_solve4<5, false, float>);
+    else if (ns == 5) launch(k_band_solve4<5, false, float>);
+    else launch(k_band_solve4<8, false, float>);
   } else if (max_bt - 1 > SOLVE_TILES) {
     launch(k_band_solve<KC, 2, float>);
   } else {

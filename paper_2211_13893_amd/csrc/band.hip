@@ -793,7 +793,7 @@ __device__ inline void solve_piece_entry(int wide, int pp, int l, int* row, int*
 }
 
 // Copies of the unit-lower band in the operand order of the matrix-core block
-// solves (k_band_solve4; bands of at most 41 tiles).  Tile row I has 1 + 8
+// solves (k_band_solve4; bands of at most 65 tiles).  Tile row I has 1 + 8
 // nslot slots of 8 KB: slot 0 of the forward copy is D^{-1}_I, slot s >= 1 the
 // tile (I, I-s) (forward) or (I+s, I)^T (backward); tiles outside the matrix
 // or the band are zero.  Inside a slot, double2 pp (0..7) of lane l = 16 kk +

@@ -12,9 +12,9 @@
 //     the inverses of the diagonal tiles follow in a separate NT*1024 array;
 //   * after factorisation the unit-lower band (Lu, D^{-1}) of every box matrix
 //     is written twice more, once per sweep direction of the block solve, in
-//     the order the solve reads it (for bands of at most 41 tiles straight
+//     the order the solve reads it (for bands of at most 65 tiles straight
 //     from L, the band then keeping L off the diagonal and D^{-1} on it), so that a wavefront's load instruction reads 1 KB of
-//     consecutive memory.  Bands of at most 41 tiles (matrix-core solve):
+//     consecutive memory.  Matrix-core solve (bands of at most 65 tiles):
 //     1 + 8 nslot slots of 8 KB per tile row (slot 0 = D^{-1} in the forward
 //     copy, slot s = tile s), double2 pp of lane l at ((I*S + slot)*8 + pp)*64
 //     + l (see k_band_relayout4).  Wider bands (vector-FMA solve): fragment
@@ -101,10 +101,10 @@ __host__ __device__ inline int solve_sets(int BT) { return BT - 1 > SOLVE_TILES 
 __host__ __device__ inline int chol_jobs(int P, int max_bt) { return 1 + P + (max_bt > 2 ? max_bt - 2 : 0) * (P / 2); }
 
 // the matrix-core block solve (k_band_solve4) takes bands of at most
-// 1 + 8 * SOLVE4_MAX_SLOTS tiles (5 slots with 8 columns per workgroup; the
-// 16-column solve's LDS ring limits it to 31 tiles, 4 slots); its copies hold
-// 1 + 8 nslot tiles per row
-#define SOLVE4_MAX_SLOTS 5
+// 1 + 8 * SOLVE4_MAX_SLOTS tiles with 8 columns per workgroup (up to 5 slots
+// in registers, 6-8 as two sets of four); the 16-column solve's LDS ring
+// limits it to 31 tiles, 4 slots.  Its copies hold 1 + 8 nslot tiles per row
+#define SOLVE4_MAX_SLOTS 8
 __host__ __device__ inline int solve4_nslot(int BT) { return (BT - 1 + 7) / 8; }
 __host__ __device__ inline int solve4_slots(int BT) { return 1 + 8 * solve4_nslot(BT); }
 // doubles of one solve-ordered copy of a band (room for either layout)

@@ -397,7 +397,9 @@ SOLVE_INST(2, float)
 
 
 // The same block solve on the FP64 matrix cores, for bands of at most
-// 1 + 8 NSLOT tiles (k_band_relayout4 writes the operand copies).  One step
+// 1 + 8 NSLOT tiles (NSLOT = 8: two sets of four slots, each wavefront
+// streaming the second set's pieces of a row while it multiplies the first
+// set, and the first set's pieces of the next row during the second) (k_band_relayout4 writes the operand copies).  One step
 // y_I = f_I - sum_s Lu(I,I-s) y_{I-s} (backward: x_I = w_I - sum_s
 // Lu(I+s,I)^T x_{I+s}) is a 32 x 8 block product per tile, done as
 // v_mfma_f64_4x4x4f64: lane l = 16 kk + 4 o + i supplies A[16 rh + 4 o + i][4 ss + kk]
@@ -428,6 +430,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
     const int32_t* __restrict__ active, int phase, double* __restrict__ sep, int64_t sep_q,
     const int32_t* __restrict__ order) {
   constexpr int KC = WIDE ? 16 : 8;
+  // NSLOT 8: two sets of four register slots (tiles 1 + w + 8u, then 33 + w + 8u)
+  constexpr bool TWOSET = NSLOT > 5;
+  constexpr int NR = TWOSET ? 4 : NSLOT;
+  static_assert(!TWOSET || (NSLOT == 8 && !WIDE), "two sets: 8 slots, 8 columns (the LDS ring of 65 rows)");
   static_assert(SOLVE_THREADS == 512, "8 wavefronts: tiles 1 + w + 8u");
   static_assert(32 * KC <= SOLVE_THREADS, "one reduction thread per entry of a 32 x KC step");
   extern __shared__ double ring[];   // [BT][32][KC]
@@ -472,7 +478,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
   const T* Fbw = ft + v.bw;
   const bool wforms = wave == SOLVE_WAVES - 1;
   // factor pieces of this wavefront's slots (and of D^{-1} for wavefront 7)
-  double A[NSLOT][16], Aw[16];
+  double A[NR][16], Aw[16];
   auto load_slot = [&](double (&a)[16], const T* base, int I, int sl) {
 #pragma unroll
     for (int pp = 0; pp < 8; ++pp) {
@@ -591,7 +597,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
   if (do_fwd) {
   clear_ring();
 #pragma unroll
-  for (int u = 0; u < NSLOT; ++u)
+  for (int u = 0; u < NR; ++u)
     if (1 + wave + 8 * u <= BT - 1) load_slot(A[u], Ffw, 0, 1 + wave + 8 * u);
   if (wforms) load_slot(Aw, Ffw, 0, 0);
   lds_barrier();
@@ -604,11 +610,24 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
     McAcc<WIDE> acc;
     zero_acc(acc);
 #pragma unroll
-    for (int u = 0; u < NSLOT; ++u) {
+    for (int u = 0; u < NR; ++u) {
       const int s = 1 + wave + 8 * u;
       // row I-s (zero before row 0); tiles past the band are skipped (wave-uniform)
       const double* yp = ring + (int64_t)(((I - s) % BT + BT) % BT) * 32 * KC;
-      if (s <= BT - 1) tile_step(A[u], yp, acc, Ffw, In, s);
+      if (s <= BT - 1) {
+        // two sets: the first streams the second set's pieces of row I (when
+        // the wavefront has that slot), the second the first set's of row In
+        const bool has1 = TWOSET && s + 32 <= BT - 1;
+        tile_step(A[u], yp, acc, Ffw, has1 ? I : In, has1 ? s + 32 : s);
+      }
+    }
+    if constexpr (TWOSET) {
+#pragma unroll
+      for (int u = 0; u < NR; ++u) {
+        const int s = 33 + wave + 8 * u;
+        const double* yp = ring + (int64_t)(((I - s) % BT + BT) % BT) * 32 * KC;
+        if (s <= BT - 1) tile_step(A[u], yp, acc, Ffw, In, s - 32);
+      }
     }
     store_part(acc);
     // w_{I-1} (its ring row was completed last step); D^{-1} of row I next
@@ -646,7 +665,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
         ring[(int64_t)((NF + i) % BT) * 32 * KC + rr * KC + cc] = sb[3 * sep_q + (int64_t)(i * 32 + rr) * KC + cc];
   }
 #pragma unroll
-  for (int u = 0; u < NSLOT; ++u)
+  for (int u = 0; u < NR; ++u)
     if (1 + wave + 8 * u <= BT - 1) load_slot(A[u], Fbw, NF - 1, 1 + wave + 8 * u);
   __syncthreads();
   for (int I = NF - 1; I >= 0; --I) {
@@ -658,10 +677,21 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve4(
     McAcc<WIDE> acc;
     zero_acc(acc);
 #pragma unroll
-    for (int u = 0; u < NSLOT; ++u) {
+    for (int u = 0; u < NR; ++u) {
       const int s = 1 + wave + 8 * u;
       const double* yp = ring + (int64_t)((I + s) % BT) * 32 * KC;   // zero beyond row NT-1
-      if (s <= BT - 1) tile_step(A[u], yp, acc, Fbw, In, s);
+      if (s <= BT - 1) {
+        const bool has1 = TWOSET && s + 32 <= BT - 1;
+        tile_step(A[u], yp, acc, Fbw, has1 ? I : In, has1 ? s + 32 : s);
+      }
+    }
+    if constexpr (TWOSET) {
+#pragma unroll
+      for (int u = 0; u < NR; ++u) {
+        const int s = 33 + wave + 8 * u;
+        const double* yp = ring + (int64_t)((I + s) % BT) * 32 * KC;
+        if (s <= BT - 1) tile_step(A[u], yp, acc, Fbw, In, s - 32);
+      }
     }
     store_part(acc);
     lds_barrier();
@@ -693,6 +723,8 @@ SOLVE4_INST_ALL(false, double)
 SOLVE4_INST_ALL(false, float)
 SOLVE4_INST(5, false, double)
 SOLVE4_INST(5, false, float)
+SOLVE4_INST(8, false, double)
+SOLVE4_INST(8, false, float)
 SOLVE4_INST_ALL(true, double)
 SOLVE4_INST_ALL(true, float)
 

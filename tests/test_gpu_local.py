@@ -200,12 +200,13 @@ def test_stencil_rows_tiled_planes(torch):
         assert e0 <= 1e-12 and e1 <= 1e-12
 
 
-# Bands of 10-17, 26-33 and 34-41 tiles (2, 4 and 5 tile slots per wavefront
-# of the matrix-core solve; 37-tile Ahat bands for core 12) on boxes too large
-# for dense oracle solves: the solves are checked through the stencil
+# Bands of 10-17, 26-33, 34-41 and 42-65 tiles (2, 4 and 5 tile slots per
+# wavefront of the matrix-core solve, then two sets of four; 37-tile Ahat
+# bands for core 12, about 50 for core 14 with oversampling 3) on boxes too
+# large for dense oracle solves: the solves are checked through the stencil
 # products, themselves checked against the oracle above: (A + s D A D) y = x
 # on B1 u B2 for op 3, (A y)_1 = x_1 for op 2.
-@pytest.mark.parametrize("core,ovs", [(6, 1), (10, 2), (12, 2)])
+@pytest.mark.parametrize("core,ovs", [(6, 1), (10, 2), (12, 2), (14, 3)])
 def test_solve_residual_wide_boxes(torch, core, ovs):
     say(f"[solve residual] core {core} ovs {ovs}")
     prob = synth.uniform_batch(n_boxes=2, core=core, overlap=1, ovs=ovs, n_ev=8)
@@ -311,8 +312,8 @@ def _check_eigs(torch, prob, batch, n_ev, tol_nu=1e-8):
 
 def test_eigs_parity_wide_band(torch):
     # boxes of 22 x 22 x 4 elements: the banded matrix of B1 u B2 spans
-    # 3 (23*23 + 23 + 1) + 2 = 1661 rows, more than 33 tiles of 32, so the
-    # block solve walks two tile sets per step
+    # 3 (23*23 + 23 + 1) + 2 = 1661 rows, more than 41 tiles of 32, so the
+    # block solve walks two sets of tile slots per step
     say("[eigs] wide-band slab, 4 boxes of 23 x 23 x 5 nodes, n_ev 8")
     prob = synth.slab()
     _check_eigs(torch, prob, [0, 1, 2, 3], 8)

@@ -85,9 +85,9 @@ def test_streamed_coarse_matches_single_plan_beam(torch):
 
 @pytest.mark.parametrize("case", ["beam", "cube", "slab"])
 def test_store_geneo_pcg(torch, case):
-    """beam and cube: interior bands of at most 33 tiles (matrix-core solve
-    layout, D^{-1} in the forward copy); slab: 45-tile bands (vector-FMA
-    layout, D^{-1} from the store's compact tiles)."""
+    """beam and cube: interior bands of at most 33 tiles; slab: 45-tile bands
+    (the two-set matrix-core solve); all in the matrix-core layout, D^{-1} in
+    the forward copy."""
     from paper_2211_13893_amd import msgfem
     if case == "beam":
         prob = synth.laminated_beam(n_ev=8)
