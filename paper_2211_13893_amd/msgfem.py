@@ -151,6 +151,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2211_13893_amd.build`")
+    # torch first: the library must bind to the HIP runtime torch loads (a
+    # second runtime loaded on the library's own dependency finds no device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
