@@ -109,9 +109,14 @@ def local_stage_streamed(problem, store: "msgfem.CoarseStore", chunks: List[List
         if log:
             log(f"  chunk {ci + 1}/{len(chunks)}: {len(chunk)} boxes, iterations {it.min()}-{it.max()}, "
                 f"status {sorted(set(stat.tolist()))}")
+        # the chunks' plans have nearly the same sizes (boxes dealt round-robin
+        # by size), so the caching allocator serves each plan from the blocks
+        # the previous one freed; returning them to the driver made every
+        # chunk's first solve map its buffers afresh (about 4 s per chunk of
+        # the full laminate).  An allocation that does not fit makes torch
+        # release the cache and retry by itself.
         del st, out
         torch.cuda.synchronize()
-        torch.cuda.empty_cache()
     torch.cuda.synchronize()
     return LocalResult(iters, status, max_rho, evals, kept, chunks, time.perf_counter() - t0)
 
