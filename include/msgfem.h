@@ -27,6 +27,10 @@
  *     written to the caller's device `status` array (bit flags, below) and are
  *     valid after the stream is synchronised.
  *   - Inputs are never modified.  No exceptions cross the ABI.
+ *   - Threads: different plans (and coarse stores) may be used from different
+ *     host threads at the same time, each on its own stream; the library's
+ *     one-time set-up runs once, whichever thread calls first.  Calls on
+ *     one plan must not overlap.
  *
  * Return codes: MSGFEM_OK (0), MSGFEM_EARG (-1) bad argument,
  * MSGFEM_EHIP (-2) HIP error, MSGFEM_ESIZE (-3) unsupported size.

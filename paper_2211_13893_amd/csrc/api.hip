@@ -998,11 +998,15 @@ struct Ctx {
   bool counts(int b, const int32_t* act) const { return !act || act_h.empty() || act_h[b]; }
 };
 
-// Kernels whose dynamic LDS may exceed 64 KiB declare it once per process.
+// Kernels whose dynamic LDS may exceed 64 KiB declare it once per process
+// (plans may be driven from several host threads: the first caller sets the
+// attributes, the others wait until it has).
+static void lds_attributes_once();
 static void lds_attributes() {
-  static bool done = false;
-  if (done) return;
-  done = true;
+  static std::once_flag once;
+  std::call_once(once, lds_attributes_once);
+}
+static void lds_attributes_once() {
   (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   const void* solves[4] = {(const void*)k_band_solve<KC, 1, double>, (const void*)k_band_solve<KC, 2, double>,
