@@ -602,7 +602,8 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
         if (bi >= bj) quad_put(T, 32, bi, bj, lane, quad_get(T, 32, bi, bj, lane) - acc[bi][bj]);
     return;
   }
-  const int r = job - 1 - P;
+  if (job < CHOL_ROW0(P)) return;   // padding of the diagonal jobs
+  const int r = job - CHOL_ROW0(P);
   const int s = 2 + r / G, g = r % G, I = J + s;
   if (J < 0 || s > BT - 1 || I > NT - 1) return;
   const int kb = max(0, I - (BT - 1));   // K range of row I's band tiles: [kb, I]

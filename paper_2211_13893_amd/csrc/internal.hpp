@@ -97,8 +97,13 @@ __host__ __device__ inline int solve_nthr(int BT) {
 #define SOLVE_MAX_BT (2 * SOLVE_TILES + 1)
 __host__ __device__ inline int solve_sets(int BT) { return BT - 1 > SOLVE_TILES ? 2 : 1; }
 // jobs (wavefronts) of one step of the tile Cholesky with panels of P
-// columns: the step's chain, P diagonal tiles, (BT - 2) rows x P / 2 column pairs
-__host__ __device__ inline int chol_jobs(int P, int max_bt) { return 1 + P + (max_bt > 2 ? max_bt - 2 : 0) * (P / 2); }
+// columns: the step's chain and P diagonal tiles, padded to whole workgroups
+// of four (so that a workgroup holds whole rows), then (BT - 2) rows x P / 2
+// column pairs
+#define CHOL_ROW0(P) ((((P) + 1) + 3) / 4 * 4)
+__host__ __device__ inline int chol_jobs(int P, int max_bt) {
+  return CHOL_ROW0(P) + (max_bt > 2 ? max_bt - 2 : 0) * (P / 2);
+}
 
 // the matrix-core block solve (k_band_solve4) takes bands of at most
 // 1 + 8 * SOLVE4_MAX_SLOTS tiles with 8 columns per workgroup (up to 5 slots
