@@ -152,6 +152,20 @@ static const int MAX_NEV = 48;
 static const int ROUND_PAIRS = 24; // pairs per deflated round (block 32, 8 guard columns)
 static const int GRAM_ROWS = 1024; // rows per Gram / residual chunk
 
+// the Gram partials of every (row chunk, box): 64 threads per 16-column
+// block of the m columns (m <= 96), both products from one workgroup
+static void gram_partials(int m, int n_chunk, int nb, hipStream_t s, const BoxMeta* meta, int nblk, Blk3 Z,
+                          Blk3 A, Blk3 B, int k, double* part, const int32_t* act) {
+  const int nb16 = (m + 15) / 16;
+  const dim3 grid(n_chunk, nb);
+  if (nb16 <= 2)
+    k_gram_partial<2><<<grid, 128, 0, s>>>(meta, nblk, Z, A, B, k, GRAM_ROWS, n_chunk, part, act);
+  else if (nb16 <= 4)
+    k_gram_partial<4><<<grid, 256, 0, s>>>(meta, nblk, Z, A, B, k, GRAM_ROWS, n_chunk, part, act);
+  else
+    k_gram_partial<6><<<grid, 384, 0, s>>>(meta, nblk, Z, A, B, k, GRAM_ROWS, n_chunk, part, act);
+}
+
 static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
 struct msgfem_plan {
@@ -1037,12 +1051,6 @@ static void lds_attributes_once() {
   for (const void* f : spp) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipFuncSetAttribute((const void*)k_update<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
-  (void)hipFuncSetAttribute((const void*)k_gram_partial<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-  (void)hipFuncSetAttribute((const void*)k_gram_partial<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-  (void)hipFuncSetAttribute((const void*)k_gram_partial<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
   (void)hipGetLastError();
 }
 
@@ -1210,8 +1218,6 @@ static int gram_only(Ctx& c, int nblk, double* const* Zb, double* const* AZb, do
     A.p[i] = i < nblk ? AZb[i] : nullptr;
     B.p[i] = i < nblk ? BZb[i] : nullptr;
   }
-  dim3 grid(c.p->n_gchunk, c.nb, 2);
-  size_t lds = (size_t)m * m * 8;
   double by = 0, fl = 0;
   for (int b = 0; b < c.nb; ++b) {
     if (!c.counts(b, act)) continue;
@@ -1220,10 +1226,7 @@ static int gram_only(Ctx& c, int nblk, double* const* Zb, double* const* AZb, do
     fl += 2 * 2.0 * mt.n_dof * m * m;
   }
   ProfScope ps(c.p, PK_GRAM, c.s, by, fl);
-  // 16x16 blocks of the m x m result per side: 2, 4 or 6
-  const int nb16 = (m + 15) / 16;
-  auto kern = nb16 <= 2 ? k_gram_partial<2> : (nb16 <= 4 ? k_gram_partial<4> : k_gram_partial<6>);
-  kern<<<grid, 256, lds, c.s>>>(c.v.meta, nblk, Z, A, B, k, GRAM_ROWS, c.p->n_gchunk, c.w.part, act);
+  gram_partials(m, c.p->n_gchunk, c.nb, c.s, c.v.meta, nblk, Z, A, B, k, c.w.part, act);
   LAUNCHCHK(c.p);
   dim3 g2((2 * m * m + 255) / 256, c.nb);
   k_gram_reduce<<<g2, 256, 0, c.s>>>(m, c.p->n_gchunk, c.w.part, c.w.G, act);
@@ -2100,10 +2103,7 @@ extern "C" int msgfem_coarse_assemble(msgfem_plan* p, const void* ops, void* wor
     Z.p[0] = A.p[0] = B.p[0] = V;
     Z.p[1] = Z.p[2] = A.p[1] = A.p[2] = B.p[1] = B.p[2] = nullptr;
     (void)Zb;
-    auto kern = k <= 32 ? k_gram_partial<2> : (k <= 64 ? k_gram_partial<4> : k_gram_partial<6>);
-    kern<<<dim3(p->n_gchunk, nb, 2), 256, (size_t)k * k * 8, s>>>(v.meta, 1, Z, A, B, k, GRAM_ROWS,
-                                                                            p->n_gchunk,
-                                                            c.w.part, nullptr);
+    gram_partials(k, p->n_gchunk, nb, s, v.meta, 1, Z, A, B, k, c.w.part, nullptr);
     k_gram_reduce<<<dim3((2 * k * k + 255) / 256, nb), 256, 0, s>>>(k, p->n_gchunk, c.w.part, c.w.G, nullptr);
     k_cholqr_coef<<<nb, 256, (size_t)(k * (k + 1) + k) * 8, s>>>(k, c.w.G, c.w.Y);
     Blk4x3 Zu;
@@ -2624,9 +2624,7 @@ extern "C" int msgfem_coarse_add(msgfem_coarse* c, msgfem_plan* p, const void* o
     Blk3 Z, A, B;
     Z.p[0] = A.p[0] = B.p[0] = V;
     Z.p[1] = Z.p[2] = A.p[1] = A.p[2] = B.p[1] = B.p[2] = nullptr;
-    auto kern = k <= 32 ? k_gram_partial<2> : (k <= 64 ? k_gram_partial<4> : k_gram_partial<6>);
-    kern<<<dim3(p->n_gchunk, nb, 2), 256, (size_t)k * k * 8, s>>>(x.v.meta, 1, Z, A, B, k, GRAM_ROWS, p->n_gchunk,
-                                                                  x.w.part, nullptr);
+    gram_partials(k, p->n_gchunk, nb, s, x.v.meta, 1, Z, A, B, k, x.w.part, nullptr);
     k_gram_reduce<<<dim3((2 * k * k + 255) / 256, nb), 256, 0, s>>>(k, p->n_gchunk, x.w.part, x.w.G, nullptr);
     k_cholqr_coef<<<nb, 256, (size_t)(k * (k + 1) + k) * 8, s>>>(k, x.w.G, x.w.Y);
     Blk4x3 Zu;

@@ -34,99 +34,135 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // Partial Gram matrices of one row chunk of one box:
 //   part[box][chunk][0] = Z^T (A Z),  part[box][chunk][1] = Z^T (B Z)
-// (upper 16x16 blocks only; blockIdx.z selects the product), Z = [Z_0 .. Z_{nblk-1}]
-// of m = nblk*k columns.  Each wave takes every fourth group of 4 rows and
-// accumulates all upper blocks of the m x m result with the FP64 matrix cores
-// (16x16x4: one group of 4 rows is one inner step), two groups per iteration
-// so that the next rows are in flight during the products.  The four waves'
-// sums are added in a fixed order through LDS (dynamic LDS: m*m doubles).
+// (upper 16x16 blocks only), Z = [Z_0 .. Z_{nblk-1}] of m = nblk*k <= 16 NB
+// columns, with the FP64 matrix cores (16x16x4: one group of 4 rows is one
+// inner step).  The workgroup stages the chunk GRAM_SLAB rows at a time: the
+// rows of Z, A Z and B Z with 16-byte loads into LDS (two buffers; the next
+// slab is requested while this one is used), laid out so that the operand of
+// one (16-column slice, group of 4 rows) is 64 consecutive doubles in lane
+// order.  Wavefront w of the NB takes product p = w / (NB/2) and the block
+// rows a = w % (NB/2) and NB-1-a: NB+1 blocks for every wavefront, each a sum
+// over the chunk's rows in order.  The chunks are added by k_gram_reduce.
+#define GRAM_SLAB 16
+#define GRAM_PIECES 6   // 16-byte pieces per thread and slab: 3 * GRAM_SLAB * m/2 <= 6 * 64 NB
+
+template <int NB, int A>
+__device__ __forceinline__ void gram_chunk(double* __restrict__ sh, int m, int k, int64_t base, int r_begin,
+                                           int r_end, int which, const Blk3& Z, const Blk3& AZ, const Blk3& BZ,
+                                           double* __restrict__ out) {
+  constexpr int R0 = A, R1 = NB - 1 - A;   // the two block rows
+  constexpr int NW = NB - A;               // product slices A .. NB-1
+  constexpr int N1 = A + 1;                // blocks of row R1: columns R1 .. NB-1
+  constexpr int KIND = 4 * NB * 64;        // doubles of one kind in a buffer
+  constexpr int BUF = 3 * KIND;
+  const int t = threadIdx.x, lane = t & 63;
+  // this thread's pieces: kind, slab row, column pair -> source and LDS slot
+  const int half = m / 2, per_kind = GRAM_SLAB * half;
+  const double* src[GRAM_PIECES];
+  int dst[GRAM_PIECES], prow[GRAM_PIECES];
+#pragma unroll
+  for (int i = 0; i < GRAM_PIECES; ++i) {
+    const int e = t + i * 64 * NB;
+    prow[i] = -1;
+    src[i] = nullptr;
+    dst[i] = 0;
+    if (e < 3 * per_kind) {
+      const int kq = e / per_kind, rem = e - kq * per_kind;
+      const int rr = rem / half, c = 2 * (rem - rr * half);
+      const Blk3& X = kq == 0 ? Z : (kq == 1 ? AZ : BZ);
+      const int cb = c / k;
+      const double* x = cb == 0 ? X.p[0] : (cb == 1 ? X.p[1] : X.p[2]);
+      src[i] = x + base + (c - cb * k);
+      prow[i] = rr;
+      dst[i] = kq * KIND + ((rr >> 2) * NB + (c >> 4)) * 64 + (rr & 3) * 16 + (c & 15);
+    }
+  }
+  const int n_slab = (r_end - r_begin + GRAM_SLAB - 1) / GRAM_SLAB;
+  double2 v[GRAM_PIECES];
+  auto fetch = [&](int slab) {
+#pragma unroll
+    for (int i = 0; i < GRAM_PIECES; ++i) {
+      const int row = r_begin + slab * GRAM_SLAB + prow[i];
+      v[i] = (prow[i] >= 0 && row < r_end) ? *reinterpret_cast<const double2*>(src[i] + (int64_t)row * k)
+                                           : make_double2(0.0, 0.0);
+    }
+  };
+  // slots of columns past m are never staged: zero both buffers once
+  for (int e = t; e < 2 * BUF; e += 64 * NB) sh[e] = 0.0;
+  dbl4 acc0[NW], acc1[N1];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) acc0[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < N1; ++j) acc1[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  __syncthreads();
+  if (n_slab > 0) fetch(0);
+  for (int slab = 0; slab < n_slab; ++slab) {
+    double* B = sh + (slab & 1) * BUF;
+#pragma unroll
+    for (int i = 0; i < GRAM_PIECES; ++i)
+      if (prow[i] >= 0) *reinterpret_cast<double2*>(B + dst[i]) = v[i];
+    // one barrier per slab: a buffer is rewritten two slabs later, after
+    // every wavefront has passed the barrier that follows its last reads
+    __syncthreads();
+    if (slab + 1 < n_slab) fetch(slab + 1);
+    const double* Zs = B;
+    const double* Ws = B + (1 + which) * KIND;
+#pragma unroll
+    for (int g = 0; g < GRAM_SLAB / 4; ++g) {
+      const double z0 = Zs[(g * NB + R0) * 64 + lane], z1 = Zs[(g * NB + R1) * 64 + lane];
+      double w[NW];
+#pragma unroll
+      for (int j = 0; j < NW; ++j) w[j] = Ws[(g * NB + A + j) * 64 + lane];
+#pragma unroll
+      for (int j = 0; j < NW; ++j) acc0[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(z0, w[j], acc0[j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < N1; ++j)
+        acc1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(z1, w[R1 - A + j], acc1[j], 0, 0, 0);
+    }
+  }
+  // item q of lane l is entry (16 bi + (l>>4) + 4q, 16 bj + (l&15)) of the block
+  const int lc = lane & 15, lr = lane >> 4;
+#pragma unroll
+  for (int j = 0; j < NW; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * R0 + lr + 4 * q, c = 16 * (A + j) + lc;
+      if (i < m && c < m) out[i * m + c] = acc0[j][q];
+    }
+#pragma unroll
+  for (int j = 0; j < N1; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * R1 + lr + 4 * q, c = 16 * (R1 + j) + lc;
+      if (i < m && c < m) out[i * m + c] = acc1[j][q];
+    }
+}
+
 template <int NB>
-__global__ __launch_bounds__(256) void k_gram_partial(const BoxMeta* __restrict__ meta, int nblk,
-                                                      Blk3 Z, Blk3 AZ, Blk3 BZ, int k,
-                                                      int rows_per_chunk, int n_chunk,
-                                                      double* __restrict__ part,
-                                                      const int32_t* __restrict__ active) {
-  extern __shared__ double gsum[];   // [m][m]
-  const int box = blockIdx.y, chunk = blockIdx.x, which = blockIdx.z;
+__global__ __launch_bounds__(64 * NB) void k_gram_partial(const BoxMeta* __restrict__ meta, int nblk,
+                                                          Blk3 Z, Blk3 AZ, Blk3 BZ, int k,
+                                                          int rows_per_chunk, int n_chunk,
+                                                          double* __restrict__ part,
+                                                          const int32_t* __restrict__ active) {
+  static_assert(NB == 2 || NB == 4 || NB == 6, "2, 4 or 6 blocks of 16 columns");
+  __shared__ __align__(16) double sh[2 * 3 * 4 * NB * 64];
+  const int box = blockIdx.y, chunk = blockIdx.x;
   if (active && !active[box]) return;
   const BoxMeta& bm = meta[box];
   const int m = nblk * k;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int which = wave / (NB / 2), a = wave % (NB / 2);
   const int r_begin = chunk * rows_per_chunk;
   const int r_end = min(bm.n_dof, r_begin + rows_per_chunk);
-  const int lc = lane & 15, lr = lane >> 4;
   const int64_t base = bm.dof_off * k;
-  // per-lane column pointers of every 16-block (block of the basis selected
-  // from the kernel arguments without indexing them); columns past m read
-  // nothing and give zeros
-  const double* zp[NB];
-  const double* wp[NB];
-  bool cok[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int c = 16 * b + lc;
-    cok[b] = c < m;
-    const int cb = cok[b] ? c / k : 0, cc = cok[b] ? c % k : 0;
-    const double* z = cb == 0 ? Z.p[0] : (cb == 1 ? Z.p[1] : Z.p[2]);
-    const double* wa = cb == 0 ? AZ.p[0] : (cb == 1 ? AZ.p[1] : AZ.p[2]);
-    const double* wb = cb == 0 ? BZ.p[0] : (cb == 1 ? BZ.p[1] : BZ.p[2]);
-    zp[b] = z + base + cc;
-    wp[b] = (which ? wb : wa) + base + cc;
+  double* out = part + (((int64_t)box * n_chunk + chunk) * 2 + which) * m * m;
+  // every wavefront passes the same barriers whichever block rows it holds
+  if (a == 0) gram_chunk<NB, 0>(sh, m, k, base, r_begin, r_end, which, Z, AZ, BZ, out);
+  if constexpr (NB >= 4) {
+    if (a == 1) gram_chunk<NB, 1>(sh, m, k, base, r_begin, r_end, which, Z, AZ, BZ, out);
   }
-  dbl4 acc[NB][NB];
-#pragma unroll
-  for (int bi = 0; bi < NB; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < NB; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
-  auto load = [&](int row, double (&zf)[6], double (&wf)[6]) {
-    const bool rok = row < r_end;
-    const int64_t o = (int64_t)(rok ? row : r_begin) * k;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      // every lane loads (a valid address), then drops what is outside
-      const bool ok = rok && cok[b];
-      const double zv = zp[b][o], wv = wp[b][o];
-      zf[b] = ok ? zv : 0.0;
-      wf[b] = ok ? wv : 0.0;
-    }
-  };
-  auto mma = [&](const double (&zf)[6], const double (&wf)[6]) {
-#pragma unroll
-    for (int bi = 0; bi < NB; ++bi)
-#pragma unroll
-      for (int bj = bi; bj < NB; ++bj)
-        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(zf[bi], wf[bj], acc[bi][bj], 0, 0, 0);
-  };
-  // row groups g = wave, wave + 4, ... (4 rows each), two per iteration
-  const int n_groups = (r_end - r_begin + 3) >> 2;
-  for (int g0 = wave; g0 < n_groups; g0 += 8) {
-    double z0[6], w0[6], z1[6], w1[6];
-    load(r_begin + 4 * g0 + lr, z0, w0);
-    load(r_begin + 4 * (g0 + 4) + lr, z1, w1);   // beyond r_end: zeros
-    mma(z0, w0);
-    mma(z1, w1);
-  }
-  // fixed-order sum of the four waves' blocks
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int bi = 0; bi < NB; ++bi)
-#pragma unroll
-        for (int bj = bi; bj < NB; ++bj) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = 16 * bi + lr + 4 * v, j = 16 * bj + lc;
-            if (i < m && j < m) gsum[i * m + j] = (w == 0 ? 0.0 : gsum[i * m + j]) + acc[bi][bj][v];
-          }
-        }
-    }
-    __syncthreads();
-  }
-  const int mm = m * m;
-  double* out = part + ((int64_t)box * n_chunk + chunk) * 2 * mm + (int64_t)which * mm;
-  for (int e = threadIdx.x; e < mm; e += 256) {
-    const int i = e / m, j = e % m;
-    if ((i >> 4) <= (j >> 4)) out[e] = gsum[e];
+  if constexpr (NB >= 6) {
+    if (a == 2) gram_chunk<NB, 2>(sh, m, k, base, r_begin, r_end, which, Z, AZ, BZ, out);
   }
 }
 
