@@ -26,7 +26,7 @@ __global__ void k_band_build(const BoxMeta*, int, const double*, const uint8_t*,
 __global__ void k_chol_update(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_panel(const MatDesc*, int, double*);
 template <int P>
-__global__ void k_chol_step(const MatDesc*, int, double*, int32_t*);
+__global__ void k_chol_step(const MatDesc*, int, int, int, int, double*, int32_t*);
 #define CHOL_PANEL 4   // panel columns of the tile Cholesky (k_chol_step<P>)
 __global__ void k_chol_unit(const MatDesc*, double*);
 __global__ void k_band_unit_relayout4(const BoxMeta*, int, double*, int);
@@ -810,8 +810,14 @@ static int tile_trsv(const double* T, int NT, int NH, const double* b, double* y
 // NTf - 1 for a chain, whose last step gives its separator rows' L tiles)
 static int band_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int last_J, int max_nt, int max_bt,
                          double* fac, int32_t* status, bool unit, hipStream_t s) {
+  // row workgroups in groups of 8 matrices for bands wider than 24 tiles
+  // (a matrix's rows then share its tiles in L2: uneven batch, 41-tile bands,
+  // 146 -> 140 ms per factor pass), else the longest rows of every matrix
+  // first (uniform batch, 24-tile bands: groups of 8 take 36.5 ms, not 35.0)
+  const int group = max_bt > 24 ? 8 : (nmat + 7) / 8 * 8;
   for (int J = -1; J <= last_J; ++J)
-    k_chol_step<CHOL_PANEL><<<dim3(nmat, (chol_jobs(CHOL_PANEL, max_bt) + 3) / 4), 256, 0, s>>>(mats, J, fac, status);
+    k_chol_step<CHOL_PANEL><<<chol_grid(CHOL_PANEL, nmat, max_bt), 256, 0, s>>>(mats, nmat, max_bt, group, J, fac,
+                                                                                  status);
   if (unit) k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
   LAUNCHCHK(p);
   return 0;

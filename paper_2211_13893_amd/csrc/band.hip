@@ -492,21 +492,39 @@ __device__ int factor_tile32(const double* __restrict__ C, double* __restrict__ 
 // the diagonal tiles; then per band row I = J + s (s >= 2) and pair g of
 // panel columns, the triangular solve for L(I,J) (g = 0) and the panel
 // products of columns J+1+2g, J+2+2g.
-// grid (n_mat, ceil(chol_jobs / 4)), 256 threads: job = 4 blockIdx.y +
-// wavefront; blockIdx.x is the matrix, so the step's chain (job 0) of every
-// matrix and the longest rows are dispatched first.
+// grid chol_grid(P, n_mat, max BT), 256 threads: workgroup y of a matrix
+// holds jobs 4y .. 4y+3 (one per wavefront); the order in which the
+// (matrix, y) workgroups are dispatched is set by `group` (below).
 
 template <int P>
-__global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict__ mats, int J,
+__global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict__ mats, int nmat, int max_bt, int group, int J,
                                                       double* __restrict__ fac, int32_t* __restrict__ status) {
   static_assert(P >= 2 && P % 2 == 0, "panel columns come in pairs");
   constexpr int G = P / 2;
   __shared__ __align__(16) double X[32 * CH_LD];
   __shared__ __align__(16) double Y[32 * CH_LD];
   __shared__ double dinv[32], vec[32];
-  const MatDesc v = mats[blockIdx.x];
+  // dispatch order (block id): the diagonal workgroups of every matrix first
+  // (each step's chain starts at once), then the row workgroups, row group
+  // by row group within groups of `group` matrices (a multiple of 8; all
+  // matrices: the longest rows of every matrix first; 8: matrix by matrix,
+  // so that a matrix's rows read the tiles they share while they are in L2).
+  // Matrix m always runs on XCD m mod 8 (block id mod 8).
+  const int nyb = (chol_jobs(P, max_bt) + 3) / 4, ndb = CHOL_ROW0(P) / 4, nrb = nyb - ndb;
+  const int nm8 = (nmat + 7) / 8 * 8, L8 = (int)blockIdx.x;
+  int mat, yb;
+  if (L8 < ndb * nm8) {
+    yb = L8 / nm8;
+    mat = L8 - yb * nm8;
+  } else {
+    const int R = L8 - ndb * nm8, grp = R / (group * nrb), r8 = R - grp * group * nrb;
+    mat = grp * group + r8 % group;
+    yb = ndb + r8 / group;
+  }
+  if (mat >= nmat) return;
+  const MatDesc v = mats[mat];
   const int lane = threadIdx.x & 63;
-  const int job = (int)blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int job = yb * 4 + (threadIdx.x >> 6);
   const int BT = v.BT, NT = v.NT;
   // a chain of a split matrix factors its first NF columns only: its
   // separator rows get L(I, J) for J < NF, no tile of a column >= NF changes
@@ -645,8 +663,8 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) quad_put(T1, 32, bi, bj, lane, quad_get(T1, 32, bi, bj, lane) - acc[bi][bj]);
 }
-template __global__ void k_chol_step<2>(const MatDesc*, int, double*, int32_t*);
-template __global__ void k_chol_step<4>(const MatDesc*, int, double*, int32_t*);
+template __global__ void k_chol_step<2>(const MatDesc*, int, int, int, int, double*, int32_t*);
+template __global__ void k_chol_step<4>(const MatDesc*, int, int, int, int, double*, int32_t*);
 
 // The separator's Schur complement of a split matrix, once both chains are
 // factored on their own columns:

@@ -104,6 +104,11 @@ __host__ __device__ inline int solve_sets(int BT) { return BT - 1 > SOLVE_TILES 
 __host__ __device__ inline int chol_jobs(int P, int max_bt) {
   return CHOL_ROW0(P) + (max_bt > 2 ? max_bt - 2 : 0) * (P / 2);
 }
+// workgroups of one step: the diagonal and row workgroups of every matrix,
+// the matrix count padded to a multiple of 8 (one XCD per matrix)
+__host__ __device__ inline int chol_grid(int P, int nmat, int max_bt) {
+  return (chol_jobs(P, max_bt) + 3) / 4 * ((nmat + 7) / 8 * 8);
+}
 
 // the matrix-core block solve (k_band_solve4) takes bands of at most
 // 1 + 8 * SOLVE4_MAX_SLOTS tiles with 8 columns per workgroup (up to 5 slots
