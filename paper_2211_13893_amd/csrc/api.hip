@@ -167,6 +167,9 @@ static void gram_partials(int m, int n_chunk, int nb, hipStream_t s, const BoxMe
 }
 
 static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+// dynamic LDS of k_update<cb> for an m x k coefficient pair staged in
+// operand order (groups of 64 doubles per 4 inner indices and 16 columns)
+static size_t upd_lds(int m, int cb) { return (size_t)2 * ((m + 7) / 8) * 2 * cb * 64 * 8; }
 
 struct msgfem_plan {
   int device = 0;
@@ -1329,7 +1332,7 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
       OX.p[kind] = B[kind][3];
       OP.p[kind] = nullptr;
     }
-    k_update<2><<<ugrid, UPD_THREADS, (size_t)2 * k * k * 8, c.s>>>(c.v.meta, 1, k, Z, OX, OP, c.w.Y, c.w.Yp, a_);
+    k_update<2><<<ugrid, UPD_THREADS, upd_lds(k, 2), c.s>>>(c.v.meta, 1, k, Z, OX, OP, c.w.Y, c.w.Yp, a_);
     LAUNCHCHK(p);
     for (int kind = 0; kind < 4; ++kind) std::swap(B[kind][0], B[kind][3]);
     return 0;
@@ -1353,7 +1356,7 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
         OX.p[kind] = B[kind][3];
         OP.p[kind] = nullptr;
       }
-      k_update<2><<<ugrid, UPD_THREADS, (size_t)2 * 2 * k * k * 8, c.s>>>(c.v.meta, 2, k, Z, OX, OP, c.w.Y, c.w.Yp,
+      k_update<2><<<ugrid, UPD_THREADS, upd_lds(2 * k, 2), c.s>>>(c.v.meta, 2, k, Z, OX, OP, c.w.Y, c.w.Yp,
                                                                          a_);
       LAUNCHCHK(p);
       for (int kind = 0; kind < 4; ++kind) std::swap(B[kind][sl], B[kind][3]);
@@ -1476,7 +1479,7 @@ static int local_eigs_impl(msgfem_plan* p, const void* ops, void* work, const do
         fl += 4 * 2 * 2.0 * mt.n_dof * (nblk * k) * k;
       }
       ProfScope ps(p, PK_UPDATE, c.s, by, fl);
-      k_update<2><<<ugrid, UPD_THREADS, (size_t)2 * nblk * k * k * 8, c.s>>>(c.v.meta, nblk, k, Z, OX, OP, c.w.Y,
+      k_update<2><<<ugrid, UPD_THREADS, upd_lds(nblk * k, 2), c.s>>>(c.v.meta, nblk, k, Z, OX, OP, c.w.Y,
                                                                             c.w.Yp, act);
       LAUNCHCHK(p);
       for (int kind = 0; kind < 4; ++kind) {
@@ -2121,7 +2124,7 @@ extern "C" int msgfem_coarse_assemble(msgfem_plan* p, const void* ops, void* wor
     Zu.p[0][0] = V;
     OX.p[0] = Vn;
     auto upd = k <= 32 ? k_update<2> : k_update<6>;
-    upd<<<dim3((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, 1), UPD_THREADS, (size_t)2 * k * k * 8, s>>>(
+    upd<<<dim3((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, 1), UPD_THREADS, upd_lds(k, k <= 32 ? 2 : 6), s>>>(
         v.meta, 1, k, Zu, OX, OP, c.w.Y, c.w.Yp, nullptr);
     LAUNCHCHK(p);
     std::swap(V, Vn);
@@ -2642,7 +2645,7 @@ extern "C" int msgfem_coarse_add(msgfem_coarse* c, msgfem_plan* p, const void* o
     Zu.p[0][0] = V;
     OX.p[0] = Vn;
     auto upd = k <= 32 ? k_update<2> : k_update<6>;
-    upd<<<dim3((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, 1), UPD_THREADS, (size_t)2 * k * k * 8, s>>>(
+    upd<<<dim3((unsigned)((p->max_dof + UPD_ROWS - 1) / UPD_ROWS), nb, 1), UPD_THREADS, upd_lds(k, k <= 32 ? 2 : 6), s>>>(
         x.v.meta, 1, k, Zu, OX, OP, x.w.Y, x.w.Yp, nullptr);
     CLAUNCHCHK(c);
     std::swap(V, Vn);

@@ -588,11 +588,12 @@ struct Out4 {
 // in steps 2t and 2t+1 (inner index 8t + 2lk + e), and the B operand is
 // read to match.  Output columns in CB blocks of 16 (k <= 16 CB: 2 for the
 // LOBPCG block, 6 for a coarse basis of up to 96 columns); Y and Yp are
-// staged in LDS once per workgroup, for k = 32 with the two 16-column halves
-// of a row swapped on every other pair of rows (element (i, c) at column
-// c ^ 16 when bit 1 of i is set), so the four inner-index lanes groups of a
-// read fall on two bank halves, not one.
-// grid (ceil(max n_dof / UPD_ROWS), n_box, kinds); dynamic LDS = 2*m*k doubles
+// staged in LDS once per workgroup in operand order: the B operand of step
+// 2t + e and column block cb is 64 consecutive doubles in lane order (lane
+// (lk, li) holds Y[8t + 2lk + e][16 cb + li], zero outside m x k), so every
+// operand read is one conflict-free ds_read_b64 with a constant offset.
+// grid (ceil(max n_dof / UPD_ROWS), n_box, kinds);
+// dynamic LDS = 2 * ceil(m/8) * 2 * CB * 64 doubles
 template <int CB>
 __global__ __launch_bounds__(UPD_THREADS, CB == 2 ? 3 : 1) void k_update(const BoxMeta* __restrict__ meta, int nblk, int k,
                                                 Blk4x3 Z, Out4 OX, Out4 OP,
@@ -607,20 +608,24 @@ __global__ __launch_bounds__(UPD_THREADS, CB == 2 ? 3 : 1) void k_update(const B
   const int r_wg = blockIdx.x * UPD_ROWS;
   if (r_wg >= bm.n_dof) return;
   const int m = nblk * k;
-  const int swz = k == 32 ? 16 : 0;
-  auto yix = [&](int i, int c) { return i * k + (c ^ (((i >> 1) & 1) ? swz : 0)); };
+  const int npairs = (m + 7) >> 3;
+  const int ystride = npairs * 2 * CB * 64;   // doubles of one staged matrix
   double* ys = sm;
-  double* yps = sm + m * k;
+  double* yps = sm + ystride;
   const bool wantP = OP.p[kind] != nullptr;
-  for (int t = threadIdx.x; t < m * k; t += UPD_THREADS) {
-    const int i = t / k, c = t - i * k;
-    ys[yix(i, c)] = Y[(int64_t)box * m * k + t];
-    yps[yix(i, c)] = wantP ? Yp[(int64_t)box * m * k + t] : 0.0;
+  for (int t = threadIdx.x; t < ystride; t += UPD_THREADS) {
+    // slot t: operand group g = (2 tp + e) CB + cb, lane l
+    const int l = t & 63, g = t >> 6;
+    const int cb = g % CB, te = g / CB, tp = te >> 1, e = te & 1;
+    const int i = 8 * tp + 2 * (l >> 4) + e, c = 16 * cb + (l & 15);
+    const bool ok = i < m && c < k;
+    const int64_t src = (int64_t)box * m * k + (ok ? i * k + c : 0);
+    ys[t] = ok ? Y[src] : 0.0;
+    yps[t] = (ok && wantP) ? Yp[src] : 0.0;
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int npairs = (m + 7) >> 3;
   const int64_t base = bm.dof_off * k;
   for (int rb = 0; rb < 4; ++rb) {
     const int r0 = r_wg + (wave * 4 + rb) * 16;
@@ -649,14 +654,12 @@ __global__ __launch_bounds__(UPD_THREADS, CB == 2 ? 3 : 1) void k_update(const B
       if (t < npairs) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-          const int i = 8 * t + 2 * lk + e;
           const double av = e ? a.y : a.x;
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
-            const int col = 16 * cb + li;
-            const bool ok = i < m && col < k;
-            ax[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ok ? ys[yix(i, col)] : 0.0, ax[cb], 0, 0, 0);
-            if (wantP) ap[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ok ? yps[yix(i, col)] : 0.0, ap[cb], 0, 0, 0);
+            const int o = ((2 * t + e) * CB + cb) * 64 + lane;
+            ax[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ys[o], ax[cb], 0, 0, 0);
+            if (wantP) ap[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, yps[o], ap[cb], 0, 0, 0);
           }
         }
       }
