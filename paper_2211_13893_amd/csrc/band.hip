@@ -63,13 +63,15 @@ __global__ void k_band_build(const BoxMeta* __restrict__ meta, int kind,
         } else {
           const int cnode = cq / 3, cc = cq - 3 * cnode;
           const int ci = cnode % v.sx, cj = (cnode / v.sx) % v.sy, ck = cnode / sxy;
-          const int dc = 3 * (v.base + ci * v.st0 + cj * v.st1 + ck * v.st2) + cc;
-          const bool ac = dof_active(kind, cl[dc]);
-          if (!ar || !ac) {
-            x = (row == col) ? 1.0 : 0.0;
-          } else {
-            const int di = ci - ri, dj = cj - rj, dk = ck - rk;
-            if (di >= -1 && di <= 1 && dj >= -1 && dj <= 1 && dk >= -1 && dk <= 1) {
+          const int di = ci - ri, dj = cj - rj, dk = ck - rk;
+          // outside the 27-point neighbourhood the entry is zero whatever the
+          // classes (the diagonal is inside): the class byte is read only there
+          if (di >= -1 && di <= 1 && dj >= -1 && dj <= 1 && dk >= -1 && dk <= 1) {
+            const int dc = 3 * (v.base + ci * v.st0 + cj * v.st1 + ck * v.st2) + cc;
+            const bool ac = dof_active(kind, cl[dc]);
+            if (!ar || !ac) {
+              x = (row == col) ? 1.0 : 0.0;
+            } else {
               const int nr = dr / 3;
               const int nbi = 13 + di * v.w0 + dj * v.w1 + dk * v.w2;   // 27-point index of the box offset
               const double a = st[(int64_t)(nbi * 9 + 3 * rc + cc) * bm.n_nodes + nr];
