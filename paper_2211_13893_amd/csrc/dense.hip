@@ -27,7 +27,6 @@ struct Blk3 {
   const double* p[3];
 };
 
-#define GR_ROWS 32
 #define UPD_DEPTH 2    // MFMA step pairs (8 inner indices each) whose A operands are requested ahead
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
