@@ -38,7 +38,7 @@ __global__ void k_band_solve(const BoxMeta*, int, int, int, const T*, const uint
 template <int NSLOT, bool WIDE, typename T>
 __global__ void k_band_solve4(const BoxMeta*, int, int, int, const T*, const uint8_t*, const double*, double*, int,
                               int, int, double*, int64_t, const int32_t*, int, double*, int64_t, const int32_t*);
-__global__ void k_sep_syrk(const SepDesc*, double*);
+__global__ void k_sep_syrk(const SepDesc*, int, int, double*);
 
 template <bool TWO, int CW, typename ST>
 __global__ void k_spmm(const BoxMeta*, int, int, const ST*, const uint8_t*, const double*, const double*,
@@ -917,7 +917,8 @@ extern "C" int msgfem_assemble_local(msgfem_plan* p, void* ops, int32_t* status,
       return MSGFEM_EHIP;
     if (nsep) {
       const int nts = p->max_nts;
-      k_sep_syrk<<<dim3((nts * (nts + 1) / 2 + 3) / 4, nsep), 256, 0, s>>>(v.seps, v.fac);
+      const int ntg = (nts * (nts + 1) / 2 + 3) / 4;
+      k_sep_syrk<<<8 * ntg * ((nsep + 7) / 8), 256, 0, s>>>(v.seps, nsep, ntg, v.fac);
       LAUNCHCHK(p);
       if (!fused_unit) {
         k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), p->n_chain_mats), 256, 0, s>>>(v.mats,

@@ -673,12 +673,18 @@ template __global__ void k_chol_step<4>(const MatDesc*, int, int, int, int, doub
 //   S(I,J) -= sum_{c = 0,1} sum_K Lc(NFc + I, K) Lc(NFc + J, K)^T,  I >= J,
 // K over chain c's columns in band of row NFc + I (the chain's separator
 // rows hold L_sc = A_sc L_cc^{-T}).  S then holds A_ss - sum_c L_sc L_sc^T
-// and is factored as a dense band.  One target tile per wavefront;
-// grid (ceil(max NTs (NTs + 1) / 2 / 4), n_sep), 256 threads.
-__global__ __launch_bounds__(256) void k_sep_syrk(const SepDesc* __restrict__ seps, double* __restrict__ fac) {
-  const SepDesc d = seps[blockIdx.y];
+// and is factored as a dense band.  One target tile per wavefront, ntg
+// workgroups of four per separator.  The workgroups of separator n run one
+// after another on XCD n mod 8 (block id mod 8), so the separator rows that
+// all its target tiles read are fetched from HBM about once;
+// grid 8 * ntg * ceil(n_sep / 8), 256 threads.
+__global__ __launch_bounds__(256) void k_sep_syrk(const SepDesc* __restrict__ seps, int n_sep, int ntg,
+                                                  double* __restrict__ fac) {
+  const int L8 = (int)blockIdx.x, sep = (L8 / (8 * ntg)) * 8 + (L8 & 7), tg = (L8 >> 3) % ntg;
+  if (sep >= n_sep) return;
+  const SepDesc d = seps[sep];
   const int lane = threadIdx.x & 63;
-  const int t = (int)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int t = tg * 4 + (threadIdx.x >> 6);
   const int NTs = d.NTs;
   if (t >= NTs * (NTs + 1) / 2) return;
   int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
