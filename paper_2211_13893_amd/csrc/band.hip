@@ -491,9 +491,10 @@ __device__ int factor_tile32(const double* __restrict__ C, double* __restrict__ 
 // formed.  Jobs (one wavefront each): 0, the chain of the step (X^T of
 // L(J+1,J), its triangular solve, the diagonal tile J+1's remaining products
 // and its one-wavefront Cholesky and inverse); 1 .. P, the panel products of
-// the diagonal tiles; then per band row I = J + s (s >= 2) and pair g of
-// panel columns, the triangular solve for L(I,J) (g = 0) and the panel
-// products of columns J+1+2g, J+2+2g.
+// the diagonal tiles (then empty jobs up to the next multiple of four, so
+// that a workgroup holds whole rows); then per band row I = J + s (s >= 2)
+// and pair g of panel columns, the triangular solve for L(I,J) (g = 0) and
+// the panel products of columns J+1+2g, J+2+2g.
 // grid chol_grid(P, n_mat, max BT), 256 threads: workgroup y of a matrix
 // holds jobs 4y .. 4y+3 (one per wavefront); the order in which the
 // (matrix, y) workgroups are dispatched is set by `group` (below).
@@ -508,9 +509,11 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
   __shared__ double dinv[32], vec[32];
   // dispatch order (block id): the diagonal workgroups of every matrix first
   // (each step's chain starts at once), then the row workgroups, row group
-  // by row group within groups of `group` matrices (a multiple of 8; all
-  // matrices: the longest rows of every matrix first; 8: matrix by matrix,
-  // so that a matrix's rows read the tiles they share while they are in L2).
+  // by row group within groups of `group` matrices (a multiple of 8 that
+  // divides the matrix count padded to a multiple of 8, so that the grid
+  // covers every (matrix, y); the padded count: the longest rows of every
+  // matrix first; 8: matrix by matrix, so that a matrix's rows read the
+  // tiles they share while they are in L2).
   // Matrix m always runs on XCD m mod 8 (block id mod 8).
   const int nyb = (chol_jobs(P, max_bt) + 3) / 4, ndb = CHOL_ROW0(P) / 4, nrb = nyb - ndb;
   const int nm8 = (nmat + 7) / 8 * 8, L8 = (int)blockIdx.x;
