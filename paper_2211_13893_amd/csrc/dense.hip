@@ -451,8 +451,8 @@ __global__ __launch_bounds__(1024) void k_rayleigh_ritz(int m, int k, int nblk_x
       tots += red[16 + w];
     }
     __syncthreads();
-    // relative off-diagonal norm 1e-13: Ritz values then carry errors ~1e-26
-    if (offs <= 1e-26 * tots || tots == 0.0) break;
+    // relative off-diagonal norm 1e-12: Ritz values then carry errors ~1e-24
+    if (offs <= 1e-24 * tots || tots == 0.0) break;
     for (int i = tid; i < h; i += RR_THREADS) rotation(0, 0, i);
     __syncthreads();
     for (int r = 0; r < m1; ++r) {
