@@ -279,24 +279,14 @@ __global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* __restrict__ 
 }
 
 // Left-looking tile Cholesky of banded matrices, one launch per step J
-// (J = -1 .. NT-2), with the products that read only final tiles taken two
-// columns at a time, so that each band tile is read once per column pair.
-// Invariant before step J: every tile of the columns K <= J-1 is final; the
-// diagonal tile J is factored and its inverse stored; the tiles (I, J),
-// I > J, hold A minus the products with K <= J-2.  Step J computes, on
-// disjoint tiles, one job per wavefront:
-//   job 0 (the step's chain): L(J+1,J) = (A(J+1,J) - L(J+1,J-1) L(J,J-1)^T) L_JJ^{-T},
-//          then C = A(J+1,J+1) minus its remaining products (K from J-1 for
-//          even J, from J-2 for odd J, up to J), L_{J+1,J+1} = chol(C) and
-//          its inverse;
-//   jobs 1, 2 (odd J only): the diagonal tiles J+2, J+3 lose their products
-//          with K <= J-1;
-//   job s+1, s = 2 .. BT-1, row I = J+s:
-//          L(I,J) = (A(I,J) - L(I,J-1) L(J,J-1)^T) L_JJ^{-T}; then for odd J
-//          the tiles (I,J+1) and (I,J+2) (if s >= 3) lose their products with
-//          K <= J-1, for even J the tile (I,J+1) loses L(I,J-1) L(J+1,J-1)^T.
-// So the diagonal factor of a column is computed by the launch before the
-// one that needs it, next to the bulk of the tile products.  A wavefront
+// (J = -1 .. NT-2).  Invariant before step J: every tile of the columns
+// K <= J-1 is final; the diagonal tile J is factored and its inverse stored;
+// the tiles (I, J), I > J, hold A minus the products that earlier steps took.
+// Step J completes column J (L(I,J) = X L_JJ^{-T} from the remaining products
+// of row I) and factors the diagonal tile J+1 (its chain job), so the
+// diagonal factor of a column is computed by the launch before the one that
+// needs it, next to the bulk of the tile products; the products that read
+// only final tiles are gathered into panels (k_chol_step below).  A wavefront
 // owns whole 32x32 target tiles (each loaded operand feeds two or four
 // MFMAs) on the FP64 matrix cores; no job shares data with another wavefront.
 #define CH_LD 34   // LDS row stride (doubles) of staged tiles
@@ -668,7 +658,6 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) quad_put(T1, 32, bi, bj, lane, quad_get(T1, 32, bi, bj, lane) - acc[bi][bj]);
 }
-template __global__ void k_chol_step<2>(const MatDesc*, int, int, int, int, double*, int32_t*);
 template __global__ void k_chol_step<4>(const MatDesc*, int, int, int, int, double*, int32_t*);
 
 // The separator's Schur complement of a split matrix, once both chains are
