@@ -198,6 +198,13 @@ int msgfem_plan_box(const msgfem_plan *plan, int32_t b, msgfem_box_info *out);
  *     caches; 1 = always the latter; 2 = the plane sweep wherever it applies,
  *     wider planes split into x-tiles.
  *     Results agree up to rounding; it can change between calls.
+ *   MSGFEM_OPT_CHOL: how the tile Cholesky of msgfem_assemble_local is
+ *     launched: 0 (default) = one workgroup per matrix for all steps when the
+ *     matrices of a factorisation number between 3/4 of the device's compute
+ *     units and all of them and their bands are at most 24 tiles wide, else a
+ *     launch per step; 1 = always a launch per step; 2 = always one
+ *     workgroup per matrix.  The factors are bitwise the same; it can change
+ *     between calls.
  * msgfem_plan_set_option returns MSGFEM_EARG for an unknown key or value.
  * msgfem_plan_get_option reads an option or one of the counters of the last
  * msgfem_local_eigs call: MSGFEM_INFO_GRAPH_LAUNCHES (graph launches),
@@ -210,6 +217,7 @@ int msgfem_plan_box(const msgfem_plan *plan, int32_t b, msgfem_box_info *out);
 #define MSGFEM_OPT_SPLIT 2
 #define MSGFEM_OPT_SOLVE 3
 #define MSGFEM_OPT_SPMM 4
+#define MSGFEM_OPT_CHOL 5
 #define MSGFEM_INFO_GRAPH_LAUNCHES 100
 #define MSGFEM_INFO_GRAPH_ITERS 101
 #define MSGFEM_INFO_GRAPHS_CACHED 102

@@ -27,6 +27,8 @@ __global__ void k_chol_update(const MatDesc*, int, double*, int32_t*);
 __global__ void k_chol_panel(const MatDesc*, int, double*);
 template <int P>
 __global__ void k_chol_step(const MatDesc*, int, int, int, int, double*, int32_t*);
+template <int P>
+__global__ void k_chol_matrix(const MatDesc*, int, double*, int32_t*);
 #define CHOL_PANEL 4   // panel columns of the tile Cholesky (k_chol_step<P>)
 __global__ void k_chol_unit(const MatDesc*, double*);
 __global__ void k_band_unit_relayout4(const BoxMeta*, int, double*, int);
@@ -196,6 +198,8 @@ struct msgfem_plan {
   int split = 1;
   int solve_pref = 0;            // MSGFEM_OPT_SOLVE
   int spmm_pref = 0;             // MSGFEM_OPT_SPMM
+  int chol_pref = 0;             // MSGFEM_OPT_CHOL
+  int n_cu = 0;                  // compute units of the device (read at the first factorisation; -1: unknown)
   bool any_split[2] = {false, false};
   int max_nts = 0;               // separator tile rows
   int n_chain_mats = 0;          // mats[0 .. n_chain_mats): whole bands and chains; then the separator blocks
@@ -813,14 +817,29 @@ static int tile_trsv(const double* T, int NT, int NH, const double* b, double* y
 // NTf - 1 for a chain, whose last step gives its separator rows' L tiles)
 static int band_cholesky(msgfem_plan* p, const MatDesc* mats, int nmat, int last_J, int max_nt, int max_bt,
                          double* fac, int32_t* status, bool unit, hipStream_t s) {
-  // row workgroups in groups of 8 matrices for bands wider than 24 tiles
-  // (a matrix's rows then share its tiles in L2: uneven batch, 41-tile bands,
-  // 146 -> 140 ms per factor pass), else the longest rows of every matrix
-  // first (uniform batch, 24-tile bands: groups of 8 take 36.5 ms, not 35.0)
-  const int group = max_bt > 24 ? 8 : (nmat + 7) / 8 * 8;
-  for (int J = -1; J <= last_J; ++J)
-    k_chol_step<CHOL_PANEL><<<chol_grid(CHOL_PANEL, nmat, max_bt), 256, 0, s>>>(mats, nmat, max_bt, group, J, fac,
-                                                                                  status);
+  // one workgroup per matrix for all steps (MSGFEM_OPT_CHOL 2, or by default
+  // when the matrices fill the CUs about once and the bands are narrow, so
+  // that a step's jobs suit 8 wavefronts: uniform batch, 256 matrices of
+  // 24-tile bands, 35.0 -> 33.7 ms per factor pass), else a launch per step
+  bool per_matrix = p->chol_pref == 2;
+  if (p->chol_pref == 0) {
+    if (p->n_cu == 0 && hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+      p->n_cu = -1;
+    per_matrix = p->n_cu > 0 && nmat <= p->n_cu && 4 * nmat >= 3 * p->n_cu && max_bt <= 24;
+  }
+  if (per_matrix) {
+    k_chol_matrix<CHOL_PANEL><<<nmat, 512, 0, s>>>(mats, last_J, fac, status);
+  } else {
+    // row workgroups in groups of 8 matrices for bands wider than 24 tiles
+    // (a matrix's rows then share its tiles in L2: uneven batch, 41-tile
+    // bands, 146 -> 140 ms per factor pass), else the longest rows of every
+    // matrix first (uniform batch, 24-tile bands: groups of 8 take 36.5 ms,
+    // not 35.0)
+    const int group = max_bt > 24 ? 8 : (nmat + 7) / 8 * 8;
+    for (int J = -1; J <= last_J; ++J)
+      k_chol_step<CHOL_PANEL><<<chol_grid(CHOL_PANEL, nmat, max_bt), 256, 0, s>>>(mats, nmat, max_bt, group, J, fac,
+                                                                                    status);
+  }
   if (unit) k_chol_unit<<<dim3((unsigned)(((int64_t)max_nt * max_bt + 3) / 4), nmat), 256, 0, s>>>(mats, fac);
   LAUNCHCHK(p);
   return 0;
@@ -1804,6 +1823,11 @@ extern "C" int msgfem_plan_set_option(msgfem_plan* p, int32_t key, int64_t value
       for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
       p->graphs.clear();
       return MSGFEM_OK;
+    case MSGFEM_OPT_CHOL:
+      if (value < 0 || value > 2) return fail(p, MSGFEM_EARG, "MSGFEM_OPT_CHOL takes 0 .. 2, not %lld",
+                                             (long long)value);
+      p->chol_pref = (int)value;
+      return MSGFEM_OK;
     default:
       return fail(p, MSGFEM_EARG, "unknown plan option %d", key);
   }
@@ -1816,6 +1840,7 @@ extern "C" int msgfem_plan_get_option(const msgfem_plan* p, int32_t key, int64_t
     case MSGFEM_OPT_SPLIT: *value = p->split; return MSGFEM_OK;
     case MSGFEM_OPT_SOLVE: *value = p->solve_pref; return MSGFEM_OK;
     case MSGFEM_OPT_SPMM: *value = p->spmm_pref; return MSGFEM_OK;
+    case MSGFEM_OPT_CHOL: *value = p->chol_pref; return MSGFEM_OK;
     case MSGFEM_INFO_MAX_BT_A11: *value = p->max_bt_kind[0]; return MSGFEM_OK;
     case MSGFEM_INFO_MAX_BT_AHAT: *value = p->max_bt_kind[1]; return MSGFEM_OK;
     case MSGFEM_INFO_SOLVE_FAMILY:

@@ -489,37 +489,18 @@ __device__ int factor_tile32(const double* __restrict__ C, double* __restrict__ 
 // holds jobs 4y .. 4y+3 (one per wavefront); the order in which the
 // (matrix, y) workgroups are dispatched is set by `group` (below).
 
+// One job of step J on matrix *mat, run by one wavefront (job 0 uses the LDS
+// scratch X, Y (32 x CH_LD each), dinv and vec).  The descriptor is read here,
+// so that a loop over jobs keeps nothing of it live between them.
 template <int P>
-__global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict__ mats, int nmat, int max_bt, int group, int J,
-                                                      double* __restrict__ fac, int32_t* __restrict__ status) {
+__device__ __forceinline__ void chol_job(const MatDesc* __restrict__ mat, int J, int job, double* __restrict__ fac,
+                                         int32_t* __restrict__ status, double* __restrict__ X,
+                                         double* __restrict__ Y, double* __restrict__ dinv,
+                                         double* __restrict__ vec) {
   static_assert(P >= 2 && P % 2 == 0, "panel columns come in pairs");
   constexpr int G = P / 2;
-  __shared__ __align__(16) double X[32 * CH_LD];
-  __shared__ __align__(16) double Y[32 * CH_LD];
-  __shared__ double dinv[32], vec[32];
-  // dispatch order (block id): the diagonal workgroups of every matrix first
-  // (each step's chain starts at once), then the row workgroups, row group
-  // by row group within groups of `group` matrices (a multiple of 8 that
-  // divides the matrix count padded to a multiple of 8, so that the grid
-  // covers every (matrix, y); the padded count: the longest rows of every
-  // matrix first; 8: matrix by matrix, so that a matrix's rows read the
-  // tiles they share while they are in L2).
-  // Matrix m always runs on XCD m mod 8 (block id mod 8).
-  const int nyb = (chol_jobs(P, max_bt) + 3) / 4, ndb = CHOL_ROW0(P) / 4, nrb = nyb - ndb;
-  const int nm8 = (nmat + 7) / 8 * 8, L8 = (int)blockIdx.x;
-  int mat, yb;
-  if (L8 < ndb * nm8) {
-    yb = L8 / nm8;
-    mat = L8 - yb * nm8;
-  } else {
-    const int R = L8 - ndb * nm8, grp = R / (group * nrb), r8 = R - grp * group * nrb;
-    mat = grp * group + r8 % group;
-    yb = ndb + r8 / group;
-  }
-  if (mat >= nmat) return;
-  const MatDesc v = mats[mat];
+  const MatDesc v = *mat;
   const int lane = threadIdx.x & 63;
-  const int job = yb * 4 + (threadIdx.x >> 6);
   const int BT = v.BT, NT = v.NT;
   // a chain of a split matrix factors its first NF columns only: its
   // separator rows get L(I, J) for J < NF, no tile of a column >= NF changes
@@ -658,7 +639,75 @@ __global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict_
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) quad_put(T1, 32, bi, bj, lane, quad_get(T1, 32, bi, bj, lane) - acc[bi][bj]);
 }
+
+template <int P>
+__global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict__ mats, int nmat, int max_bt, int group, int J,
+                                                      double* __restrict__ fac, int32_t* __restrict__ status) {
+  __shared__ __align__(16) double X[32 * CH_LD];
+  __shared__ __align__(16) double Y[32 * CH_LD];
+  __shared__ double dinv[32], vec[32];
+  // dispatch order (block id): the diagonal workgroups of every matrix first
+  // (each step's chain starts at once), then the row workgroups, row group
+  // by row group within groups of `group` matrices (a multiple of 8 that
+  // divides the matrix count padded to a multiple of 8, so that the grid
+  // covers every (matrix, y); the padded count: the longest rows of every
+  // matrix first; 8: matrix by matrix, so that a matrix's rows read the
+  // tiles they share while they are in L2).
+  // Matrix m always runs on XCD m mod 8 (block id mod 8).
+  const int nyb = (chol_jobs(P, max_bt) + 3) / 4, ndb = CHOL_ROW0(P) / 4, nrb = nyb - ndb;
+  const int nm8 = (nmat + 7) / 8 * 8, L8 = (int)blockIdx.x;
+  int mat, yb;
+  if (L8 < ndb * nm8) {
+    yb = L8 / nm8;
+    mat = L8 - yb * nm8;
+  } else {
+    const int R = L8 - ndb * nm8, grp = R / (group * nrb), r8 = R - grp * group * nrb;
+    mat = grp * group + r8 % group;
+    yb = ndb + r8 / group;
+  }
+  if (mat >= nmat) return;
+  chol_job<P>(mats + mat, J, yb * 4 + (threadIdx.x >> 6), fac, status, X, Y, dinv, vec);
+}
 template __global__ void k_chol_step<4>(const MatDesc*, int, int, int, int, double*, int32_t*);
+
+// The steps J = -1 .. last_J of one matrix per workgroup of 8 wavefronts: the
+// jobs of k_chol_step, taken by the wavefronts in job order from a counter in
+// LDS, with a workgroup barrier between steps in place of a launch per step
+// (the step's global writes are visible to the whole workgroup after it).
+// Matrices proceed independently, each on one CU, so one matrix's chain
+// overlaps the products of others and a matrix's tiles are read on one CU.
+// Pays when the matrices fill the chip about once and their bands are narrow
+// (few jobs per step).  grid (n_mat), 512 threads.
+template <int P>
+__global__ __launch_bounds__(512) void k_chol_matrix(const MatDesc* __restrict__ mats, int last_J,
+                                                     double* __restrict__ fac, int32_t* __restrict__ status) {
+  __shared__ __align__(16) double X[32 * CH_LD];
+  __shared__ __align__(16) double Y[32 * CH_LD];
+  __shared__ double dinv[32], vec[32];
+  __shared__ int next[2];   // job counters of even and odd steps
+  constexpr int W = 8;      // wavefronts
+  const MatDesc* mat = mats + blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int NF = mat->NTf > 0 ? mat->NTf : mat->NT;
+  const int lastJ = min(last_J, NF - 1);
+  const int njobs = chol_jobs(P, mat->BT);
+  if (threadIdx.x == 0) next[0] = W;
+  for (int J = -1; J <= lastJ; ++J) {
+    __syncthreads();
+    // every wavefront has left step J-1, whose counter is readied here for
+    // step J+1 (published by the next barrier); wavefront w starts with job w
+    // (job 0, the chain, on wavefront 0: the only user of X, Y, dinv, vec)
+    if (threadIdx.x == 0) next[(J + 2) & 1] = W;
+    int job = __builtin_amdgcn_readfirstlane(wave);
+    while (job < njobs) {
+      chol_job<P>(mat, J, job, fac, status, X, Y, dinv, vec);
+      int nj = 0;
+      if (lane == 0) nj = atomicAdd(&next[(J + 1) & 1], 1);
+      job = __builtin_amdgcn_readfirstlane(nj);
+    }
+  }
+}
+template __global__ void k_chol_matrix<4>(const MatDesc*, int, double*, int32_t*);
 
 // The separator's Schur complement of a split matrix, once both chains are
 // factored on their own columns:

@@ -70,6 +70,8 @@ OPT_SPLIT = 2
 OPT_SOLVE = 3
 OPT_SPMM = 4
 SPMM_AUTO, SPMM_NODES, SPMM_PLANES = 0, 1, 2   # values of OPT_SPMM
+OPT_CHOL = 5
+CHOL_AUTO, CHOL_STEPS, CHOL_PER_MATRIX = 0, 1, 2   # values of OPT_CHOL
 INFO_GRAPH_LAUNCHES = 100
 INFO_GRAPH_ITERS = 101
 INFO_GRAPHS_CACHED = 102
@@ -196,7 +198,7 @@ class LocalStage:
                  tol: float = 1e-6, maxit: int = 200, block: int = 0, seed: int = 1234,
                  geneo: bool = False, precision: int = 0, graph: Optional[bool] = None,
                  split: Optional[bool] = None, solve: Optional[int] = None, tuned: bool = False,
-                 spmm: Optional[int] = None):
+                 spmm: Optional[int] = None, chol: Optional[int] = None):
         import torch
         self.torch = torch
         lib = load()
@@ -246,11 +248,12 @@ class LocalStage:
                 # a GenEO coarse store fixes the interior band layout (default split and family)
                 table = {key: v for key, v in table.items() if key == "graph"}
             opts_set.update(table)
-        for key, val in (("split", split), ("solve", solve), ("graph", graph), ("spmm", spmm)):
+        for key, val in (("split", split), ("solve", solve), ("graph", graph), ("spmm", spmm), ("chol", chol)):
             if val is not None:
                 opts_set[key] = int(val)
         self.plan_options = dict(opts_set)
-        for key, code in (("split", OPT_SPLIT), ("solve", OPT_SOLVE), ("graph", OPT_GRAPH), ("spmm", OPT_SPMM)):
+        for key, code in (("split", OPT_SPLIT), ("solve", OPT_SOLVE), ("graph", OPT_GRAPH), ("spmm", OPT_SPMM),
+                          ("chol", OPT_CHOL)):
             if key in opts_set:
                 _check(lib.msgfem_plan_set_option(plan, code, int(opts_set[key])), plan, "msgfem_plan_set_option")
         s = msgfem_sizes()

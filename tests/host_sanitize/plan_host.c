@@ -75,6 +75,10 @@ static void check_plan(const char *name, msgfem_mesh *mesh, msgfem_decomp *dec, 
   EXPECT(msgfem_plan_get_option(p, MSGFEM_OPT_SPMM, &v) == MSGFEM_OK && v == 2, "spmm option read");
   EXPECT(msgfem_plan_set_option(p, MSGFEM_OPT_SPMM, 3) == MSGFEM_EARG, "spmm option range");
   EXPECT(msgfem_plan_set_option(p, MSGFEM_OPT_SPMM, 0) == MSGFEM_OK, "spmm default");
+  for (int f = 0; f <= 2; ++f) EXPECT(msgfem_plan_set_option(p, MSGFEM_OPT_CHOL, f) == MSGFEM_OK, "chol option");
+  EXPECT(msgfem_plan_get_option(p, MSGFEM_OPT_CHOL, &v) == MSGFEM_OK && v == 2, "chol option read");
+  EXPECT(msgfem_plan_set_option(p, MSGFEM_OPT_CHOL, 3) == MSGFEM_EARG, "chol option range");
+  EXPECT(msgfem_plan_set_option(p, MSGFEM_OPT_CHOL, 0) == MSGFEM_OK, "chol default");
   EXPECT(msgfem_plan_set_option(p, MSGFEM_OPT_GRAPH, 1) == MSGFEM_OK, "graph on");
   EXPECT(msgfem_plan_set_option(p, MSGFEM_OPT_GRAPH, 2) == MSGFEM_EARG, "graph range");
   EXPECT(msgfem_plan_set_option(p, MSGFEM_OPT_GRAPH, 0) == MSGFEM_OK, "graph off");

@@ -149,3 +149,36 @@ def test_spmm_kernels_agree(torch):
             assert e <= 1e-13
     with pytest.raises(msgfem.MsgfemError):
         st.set_option(msgfem.OPT_SPMM, 3)
+
+
+@pytest.mark.parametrize("name", ["beam", "uniform_16"])
+def test_chol_launches_agree(torch, name):
+    """MSGFEM_OPT_CHOL: the tile Cholesky launched per step (1) and as one
+    workgroup per matrix for all steps (2) run the same jobs with the same
+    arithmetic, so the factors, and with them the interior solves (op 2:
+    A11^{-1}, op 3: Ahat^{-1}) and the eigenpairs, are bitwise the same; the
+    factor is checked against the oracle's solves in test_apply_options."""
+    from paper_2211_13893_amd import msgfem
+    prob = synth.laminated_beam() if name == "beam" else synth.uniform_batch(n_boxes=16)
+    say(f"[options] Cholesky launches, {name}")
+    res = {}
+    for pref in (msgfem.CHOL_STEPS, msgfem.CHOL_PER_MATRIX):
+        st = msgfem.LocalStage(prob, chol=pref)
+        assert st.get_option(msgfem.OPT_CHOL) == pref
+        st.msgfem_assemble_local()
+        x = st.new_block()
+        x.normal_(generator=torch.Generator(device="cuda:0").manual_seed(5))
+        apply = [st.msgfem_local_apply(op, x).clone() for op in (2, 3)]
+        out = st.msgfem_local_eigs()
+        torch.cuda.synchronize()
+        assert int(out["status"].abs().sum()) == 0
+        res[pref] = (apply, out["evals"].clone(), out["iters"].clone())
+        del st
+    a, b = res[msgfem.CHOL_STEPS], res[msgfem.CHOL_PER_MATRIX]
+    for op in (0, 1):
+        assert torch.equal(a[0][op], b[0][op]), f"solve op {op + 2} differs"
+    assert torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+    st = msgfem.LocalStage(prob)
+    assert st.get_option(msgfem.OPT_CHOL) == msgfem.CHOL_AUTO
+    with pytest.raises(msgfem.MsgfemError):
+        st.set_option(msgfem.OPT_CHOL, 3)
