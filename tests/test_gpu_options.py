@@ -151,8 +151,8 @@ def test_spmm_kernels_agree(torch):
         st.set_option(msgfem.OPT_SPMM, 3)
 
 
-@pytest.mark.parametrize("name", ["beam", "uniform_16"])
-def test_chol_launches_agree(torch, name):
+@pytest.mark.parametrize("name,split", [("beam", 1), ("beam", 0), ("uniform_16", 1)])
+def test_chol_launches_agree(torch, name, split):
     """MSGFEM_OPT_CHOL: the tile Cholesky launched per step (1) and as one
     workgroup per matrix for all steps (2) run the same jobs with the same
     arithmetic, so the factors, and with them the interior solves (op 2:
@@ -160,10 +160,10 @@ def test_chol_launches_agree(torch, name):
     factor is checked against the oracle's solves in test_apply_options."""
     from paper_2211_13893_amd import msgfem
     prob = synth.laminated_beam() if name == "beam" else synth.uniform_batch(n_boxes=16)
-    say(f"[options] Cholesky launches, {name}")
+    say(f"[options] Cholesky launches, {name}, split {split}")
     res = {}
     for pref in (msgfem.CHOL_STEPS, msgfem.CHOL_PER_MATRIX):
-        st = msgfem.LocalStage(prob, chol=pref)
+        st = msgfem.LocalStage(prob, chol=pref, split=bool(split))
         assert st.get_option(msgfem.OPT_CHOL) == pref
         st.msgfem_assemble_local()
         x = st.new_block()
