@@ -32,6 +32,16 @@ def test_library_exports_every_declared_symbol():
     assert set(msgfem.SIGNATURES) == set(names)
 
 
+def test_binding_option_codes_match_header():
+    """Every plan option and counter code of the binding is the header's
+    value, and the header has no option or counter the binding lacks."""
+    hdr = open(os.path.join(ROOT, "include", "msgfem.h")).read()
+    codes = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define MSGFEM_((?:OPT|INFO)_[A-Z0-9_]+) (\d+)", hdr)}
+    assert "OPT_CHOL" in codes and "INFO_MAX_BT_AHAT" in codes
+    ours = {n: getattr(msgfem, n) for n in dir(msgfem) if re.fullmatch(r"(OPT|INFO)_[A-Z0-9_]+", n)}
+    assert ours == codes
+
+
 def _plan(prob, batch=None, n_ev=None, **kw):
     lib = _lib()
     mesh = msgfem.msgfem_mesh(prob.nx, prob.ny, prob.nz, prob.materials.shape[0], 1, 1, 1, 1)
