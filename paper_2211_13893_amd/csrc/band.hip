@@ -641,7 +641,7 @@ __device__ __forceinline__ void chol_job(const MatDesc* __restrict__ mat, int J,
 }
 
 template <int P>
-__global__ __launch_bounds__(256, 4) void k_chol_step(const MatDesc* __restrict__ mats, int nmat, int max_bt, int group, int J,
+__global__ __launch_bounds__(256, 3) void k_chol_step(const MatDesc* __restrict__ mats, int nmat, int max_bt, int group, int J,
                                                       double* __restrict__ fac, int32_t* __restrict__ status) {
   __shared__ __align__(16) double X[32 * CH_LD];
   __shared__ __align__(16) double Y[32 * CH_LD];
